@@ -1,0 +1,294 @@
+"""Dense brute-force checkers for tiny QRAM instances (n <= 3).
+
+TEST INFRASTRUCTURE.  This is a second, independent rendering of the same
+circuit with a different state representation: every register digit of the
+whole machine (address bits, bus bits, every tree site) is an axis of a dense
+numpy array, each gate is a permutation of the full basis built by vectorised
+digit arithmetic, and noise is either a forced joint Kraus outcome K_J
+(Eq. layerkraus) applied to a state vector, or the full amplitude-damping
+channel (Eq. kraus, Eq. kraus-tri) applied site by site to a density matrix,
+as in the circuit-level cross-check of App. C.
+
+Register digits, in order: address bit t (t = 0 is the root's bit, the most
+significant bit of i), bus bit b, then tree sites q = 2v (router) and
+q = 2v+1 (data slot).  Qubit sites have 2 levels; a qutrit router has 3
+(W, L, R = 0, 1, 2).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+QUTRIT, QUBIT = 0, 1
+
+
+class Machine:
+    def __init__(self, n: int, k: int, enc: int, mem):
+        self.n, self.k, self.enc = n, k, enc
+        self.T = 6 * n + 2 * k
+        self.M = 2 * ((1 << n) - 1)
+        self.mem = [int(m) & ((1 << k) - 1) for m in mem]
+        radix = [2] * (n + k)
+        for q in range(self.M):
+            radix.append(3 if (enc == QUTRIT and q % 2 == 0) else 2)
+        self.radix = np.array(radix, dtype=np.int64)
+        self.ndig = len(radix)
+        self.N = int(np.prod(self.radix))
+        # place values, last digit fastest
+        pv = np.ones(self.ndig, dtype=np.int64)
+        for d in range(self.ndig - 2, -1, -1):
+            pv[d] = pv[d + 1] * self.radix[d + 1]
+        self.pv = pv
+        idx = np.arange(self.N, dtype=np.int64)
+        self.digits = (idx[:, None] // pv[None, :]) % self.radix[None, :]
+        self._slice_perm = {}
+
+    # digit positions
+    def A(self, t):
+        return t
+
+    def B(self, b):
+        return self.n + b
+
+    def S(self, q):
+        return self.n + self.k + q
+
+    def index(self, dig):
+        return dig @ self.pv
+
+    # ---- gates of App. A/C as maps on the digit table ----
+    def events(self, s):
+        n, k, T = self.n, self.k, self.T
+        ev = set()
+        for t in range(n):
+            if s in (2 * t + 1, T - 2 * t - 1):
+                ev.add(("copy", t))
+            for l in range(t):
+                if s in (2 * t + 2 + l, T - 2 * t - 2 - l):
+                    ev.add(("cswap", l))
+            if s in (3 * t + 2, T - 3 * t - 2):
+                ev.add(("store", t))
+        for b in range(k):
+            if s in (2 * n + 2 * b + 1, 4 * n + 2 * b + 1):
+                ev.add(("bus", b))
+            for l in range(n - 1):
+                if s in (2 * n + 2 * b + 2 + l, 4 * n + 2 * b - l):
+                    ev.add(("cswap", l))
+            if s == 3 * n + 2 * b + 1:
+                ev.add(("fetch", b))
+        return sorted(ev)
+
+    def _apply(self, dig, ph, name, arg):
+        d = dig.copy()
+        n = self.n
+        if name == "copy":
+            d[:, self.S(1)] ^= dig[:, self.A(arg)]
+        elif name == "bus":
+            d[:, self.B(arg)] = dig[:, self.S(1)]
+            d[:, self.S(1)] = dig[:, self.B(arg)]
+        elif name == "store":
+            for v in range(2 ** arg - 1, 2 ** (arg + 1) - 1):
+                r, x = dig[:, self.S(2 * v)], dig[:, self.S(2 * v + 1)]
+                if self.enc == QUBIT:
+                    d[:, self.S(2 * v)], d[:, self.S(2 * v + 1)] = x, r
+                else:
+                    if v == 0:
+                        g = np.ones(len(dig), dtype=bool)
+                    else:
+                        p = (v - 1) // 2
+                        want = 1 if v % 2 == 1 else 2
+                        g = dig[:, self.S(2 * p)] == want
+                    # (W,0)<->(L,0) and (W,1)<->(R,0)
+                    m1 = g & (r == 0)
+                    m2 = g & (r != 0) & (x == 0)
+                    nr = r.copy()
+                    nx = x.copy()
+                    nr[m1] = np.where(x[m1] == 1, 2, 1)
+                    nx[m1] = 0
+                    nr[m2] = 0
+                    nx[m2] = np.where(r[m2] == 2, 1, 0)
+                    d[:, self.S(2 * v)], d[:, self.S(2 * v + 1)] = nr, nx
+        elif name == "cswap":
+            for v in range(2 ** arg - 1, 2 ** (arg + 1) - 1):
+                r = dig[:, self.S(2 * v)]
+                dv = dig[:, self.S(2 * v + 1)]
+                dl = dig[:, self.S(2 * (2 * v + 1) + 1)]
+                dr = dig[:, self.S(2 * (2 * v + 2) + 1)]
+                if self.enc == QUBIT:
+                    left, right = r == 0, r == 1
+                else:
+                    left, right = r == 1, r == 2
+                d[:, self.S(2 * v + 1)] = np.where(left, dl, np.where(right, dr, dv))
+                d[:, self.S(2 * (2 * v + 1) + 1)] = np.where(left, dv, dl)
+                d[:, self.S(2 * (2 * v + 2) + 1)] = np.where(right, dv, dr)
+        elif name == "fetch":
+            b = arg
+            l = n - 1
+            for v in range(2 ** l - 1, 2 ** (l + 1) - 1):
+                p = v - (2 ** l - 1)
+                r = dig[:, self.S(2 * v)]
+                x = dig[:, self.S(2 * v + 1)]
+                m0 = (self.mem[2 * p] >> b) & 1
+                m1 = (self.mem[2 * p + 1] >> b) & 1
+                if self.enc == QUBIT:
+                    bitv = np.where(r == 1, m1, m0)
+                    ph = ph * np.where((x == 1) & (bitv == 1), -1.0, 1.0)
+                else:
+                    bitv = np.where(r == 2, m1, m0)
+                    bitv = np.where(r == 0, 0, bitv)
+                    d[:, self.S(2 * v + 1)] = x ^ bitv
+        return d, ph
+
+    def slice_perm(self, s):
+        """(dest index, phase) of every basis state under the gates of slice s.
+        Within a slice the operations touch disjoint digits, so they are
+        applied one after the other on the original table."""
+        if s not in self._slice_perm:
+            dig = self.digits
+            ph = np.ones(self.N)
+            for name, arg in self.events(s):
+                dig, ph = self._apply(dig, ph, name, arg)
+            dest = self.index(dig)
+            assert len(np.unique(dest)) == self.N, "gates must be a permutation"
+            self._slice_perm[s] = (dest, ph)
+        return self._slice_perm[s]
+
+    def gates(self, psi, s):
+        dest, ph = self.slice_perm(s)
+        out = np.zeros_like(psi)
+        out[dest] = ph * psi
+        return out
+
+    def gates_rho(self, rho, s):
+        dest, ph = self.slice_perm(s)
+        out = np.zeros_like(rho)
+        out[np.ix_(dest, dest)] = (ph[:, None] * ph[None, :]) * rho
+        return out
+
+    def wall(self, psi):
+        """Hadamard on every bus qubit (qubit encoding only)."""
+        shape = tuple(int(r) for r in self.radix)
+        x = psi.reshape(shape)
+        H = np.array([[1.0, 1.0], [1.0, -1.0]]) / np.sqrt(2.0)
+        for b in range(self.k):
+            ax = self.B(b)
+            x = np.moveaxis(np.tensordot(H, x, axes=([1], [ax])), 0, ax)
+        return x.reshape(self.N)
+
+    def wall_rho(self, rho):
+        rho = np.apply_along_axis(self.wall, 0, rho)
+        rho = np.apply_along_axis(self.wall, 1, rho.conj()).conj()
+        return rho
+
+    # ---- states ----
+    def input_state(self):
+        psi = np.zeros(self.N, dtype=complex)
+        for i in range(1 << self.n):
+            dig = np.zeros(self.ndig, dtype=np.int64)
+            for t in range(self.n):
+                dig[self.A(t)] = (i >> (self.n - 1 - t)) & 1
+            psi[self.index(dig)] = 1.0 / np.sqrt(1 << self.n)
+        return psi
+
+    def ideal_state(self):
+        psi = np.zeros(self.N, dtype=complex)
+        for i in range(1 << self.n):
+            dig = np.zeros(self.ndig, dtype=np.int64)
+            for t in range(self.n):
+                dig[self.A(t)] = (i >> (self.n - 1 - t)) & 1
+            for b in range(self.k):
+                dig[self.B(b)] = (self.mem[i] >> b) & 1
+            psi[self.index(dig)] = 1.0 / np.sqrt(1 << self.n)
+        return psi
+
+    def excited(self):
+        """Boolean table: tree site q excited in basis state x."""
+        return self.digits[:, self.n + self.k:] != 0
+
+    # ---- noise ----
+    def kraus_J(self, psi, J, gamma):
+        """Apply K_J (Eq. layerkraus) for the joint outcome J = {(site, level)}."""
+        a = np.sqrt(1.0 - gamma)
+        tree = self.digits[:, self.n + self.k:]
+        nexc = (tree != 0).sum(axis=1)
+        ok = np.ones(self.N, dtype=bool)
+        dig = self.digits.copy()
+        for q, lev in J:
+            ok &= tree[:, q] == lev
+            dig[:, self.S(q)] = 0
+        fac = np.sqrt(gamma) ** len(J) * a ** (nexc - len(J))
+        out = np.zeros_like(psi)
+        src = np.nonzero(ok)[0]
+        out[self.index(dig[src])] = fac[src] * psi[src]
+        return out
+
+    def damp_rho(self, rho, gamma):
+        """Amplitude damping on every tree site (Eq. kraus / kraus-tri)."""
+        a = np.sqrt(1.0 - gamma)
+        for q in range(self.M):
+            col = self.digits[:, self.S(q)]
+            k0 = np.where(col != 0, a, 1.0)
+            new = (k0[:, None] * k0[None, :]) * rho
+            for lev in (1, 2):
+                if lev == 2 and not (self.enc == QUTRIT and q % 2 == 0):
+                    continue
+                src = np.nonzero(col == lev)[0]
+                if len(src) == 0:
+                    continue
+                dig = self.digits[src].copy()
+                dig[:, self.S(q)] = 0
+                dst = self.index(dig)
+                new[np.ix_(dst, dst)] += gamma * rho[np.ix_(src, src)]
+            rho = new
+        return rho
+
+
+def density_fidelity(n, k, enc, mem, gamma):
+    """F_rho = <psi_id| rho |psi_id> of the whole query under damping."""
+    m = Machine(n, k, enc, mem)
+    psi = m.input_state()
+    if enc == QUBIT:
+        psi = m.wall(psi)
+    rho = np.outer(psi, psi.conj())
+    for s in range(1, m.T):
+        rho = m.gates_rho(rho, s)
+        rho = m.damp_rho(rho, gamma)
+    if enc == QUBIT:
+        rho = m.wall_rho(rho)
+    pid = m.ideal_state()
+    return float(np.real(pid.conj() @ rho @ pid)), float(np.real(np.trace(rho)))
+
+
+def forced_evolution(n, k, enc, mem, gamma, jumps, stop_before_wall=True, machine=None):
+    """State vector under a forced sequence of joint outcomes.
+
+    jumps: list of (slice, site, level).  Every other layer applies K_empty.
+    Returns the final state (before the second wall unless told otherwise)."""
+    m = machine if machine is not None else Machine(n, k, enc, mem)
+    psi = m.input_state()
+    if enc == QUBIT:
+        psi = m.wall(psi)
+    byslice = {}
+    for s, q, lev in jumps:
+        byslice.setdefault(s, []).append((q, lev))
+    for s in range(1, m.T):
+        psi = m.gates(psi, s)
+        psi = m.kraus_J(psi, byslice.get(s, []), gamma)
+    if enc == QUBIT and not stop_before_wall:
+        psi = m.wall(psi)
+    return m, psi
+
+
+def layer_state(n, k, enc, mem, gamma, jumps, s):
+    """State after the damping layers of slices 1..s-1 and the gates of s."""
+    m = Machine(n, k, enc, mem)
+    psi = m.input_state()
+    if enc == QUBIT:
+        psi = m.wall(psi)
+    byslice = {}
+    for ss, q, lev in jumps:
+        byslice.setdefault(ss, []).append((q, lev))
+    for ss in range(1, s + 1):
+        psi = m.gates(psi, ss)
+        if ss < s:
+            psi = m.kraus_J(psi, byslice.get(ss, []), gamma)
+    return m, psi

@@ -1,0 +1,1034 @@
+/*
+ * qram_oracle.c -- plain CPU oracle for amplitude-damped bucket-brigade QRAM
+ * trajectories (full, unpruned evolution of every branch).
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the package's smoke check and the
+ * benchmark's cpu_baseline leg may load this library.  It shares no code,
+ * header, table or constant generator with the HIP library: every quantity
+ * below (random numbers, thresholds, schedule, gates, Kraus layers, fidelity)
+ * is computed here from the paper's definitions, on its own.
+ *
+ * What it computes, per trajectory (paper: Sec. II A-B, Sec. IV D, App. A,
+ * App. C):
+ *   1. The damping candidate history: every (slice, tree site) pair is a
+ *      candidate with probability gamma, drawn in advance and state
+ *      independently (Sec. IV D, first step of the joint sampler).
+ *   2. The brute-force bad-address set of the marking rule: Eq. (subtree)
+ *      for the qutrit encoding, Eq. (badrange) for the qubit encoding.
+ *   3. The full sparse evolution of the data-loading input
+ *      sum_i c_i |i>|0>_bus|ground>_tree: each time slice applies its gates
+ *      (bucket-brigade schedule with T = 6n+2k), then one joint damping layer
+ *      over all M = 2(2^n-1) tree sites (Eq. layerkraus, Theorem 4):
+ *      one auxiliary draw of a component x with probability |c_x|^2,
+ *      J = C_s intersect X(x), then K_J applied to every component.
+ *   4. The end of the query: the second Hadamard wall (qubit encoding), the
+ *      tree measurement, and the fidelity of the post-measurement state with
+ *      the ideal output sum_i c_i |i>|d_i>|ground> (Eq. nk-qram, App. C).
+ *
+ * Conventions fixed here where the paper is silent (they are restated in the
+ * design notes):
+ *   - Address bit t (t = 0 .. n-1) is the bit routed at tree layer t, the
+ *     most significant bit at the root: i_t = (i >> (n-1-t)) & 1.
+ *   - Node v has children 2v+1 (left: router 0 / L) and 2v+2 (right: 1 / R).
+ *     Site q = 2v is the router (qubit a_v, qutrit r_v), q = 2v+1 the data
+ *     slot d_v.
+ *   - Qutrit circuit: router qutrit {W,L,R} plus a data-slot qubit.  STORE on
+ *     layer t acts on the node its parent routes into (the root for t = 0)
+ *     and exchanges (W,b) <-> (L if b = 0 else R, 0).  A W router blocks the
+ *     controlled swap.  FETCH is d_v ^= bit_b(m[2p + (r_v == R)]) when
+ *     r_v != W.  No walls.
+ *   - Random numbers: Philox4x32-10 keyed by the 64-bit seed; counters
+ *     (block, draw, trajectory, 1) for candidates, (slice, 0, trajectory, 2)
+ *     for the auxiliary draw of a damping layer, (0, 0, trajectory, 3) for the
+ *     final tree measurement.  u64 = w0 | w1 << 32, u = (u64 >> 11) 2^-53.
+ *   - The candidate set is sampled as i.i.d. Bernoulli(gamma) over the linear
+ *     index L = (s-1) M + q by a geometric walk in 64-site blocks, whose gap
+ *     thresholds are G[o] = floor(2^64 (1 - (1-gamma)^(o+1))) (saturated),
+ *     with (1-gamma)^(o+1) formed by o+1 successive double multiplications.
+ *   - Order of the auxiliary draw: all components whose mask C_s cap X(x) is
+ *     empty come first as one block, then the remaining components in the
+ *     order of their initial label (address, then bus word).  The same rule
+ *     orders the final tree measurement: the ground-configuration block
+ *     first.  Any fixed order samples the distribution of Theorem 4.
+ *   - Amplitudes are kept unnormalised; draws use ratios (Sec. II B).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_QUTRIT 0
+#define ORC_QUBIT 1
+
+#define ORC_TAG_FAULT 1u
+#define ORC_TAG_AUX 2u
+#define ORC_TAG_FINAL 3u
+
+/* qutrit router levels; a qubit site uses 0/1 */
+#define LV_W 0
+#define LV_L 1
+#define LV_R 2
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of the   */
+/* Philox S-box on a 4x32-bit counter, key bumped by the Weyl constants     */
+/* between rounds.                                                          */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
+                       uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+    uint32_t y1 = (uint32_t)p1;
+    uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    uint32_t y3 = (uint32_t)p0;
+    x0 = y0;
+    x1 = y1;
+    x2 = y2;
+    x3 = y3;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+static uint64_t draw_u64(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t traj,
+                         uint32_t tag) {
+  uint32_t ctr[4] = {c0, c1, traj, tag};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  return (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+}
+
+static double u53(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
+
+double orc_uniform(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t traj,
+                   uint32_t tag) {
+  return u53(draw_u64(seed, c0, c1, traj, tag));
+}
+
+/* Gap thresholds of the geometric candidate walk. */
+void orc_thresholds(double gamma, uint64_t G[64]) {
+  double q = 1.0 - gamma;
+  double qp = 1.0;
+  for (int o = 0; o < 64; ++o) {
+    qp = qp * q;
+    double x = ldexp(1.0 - qp, 64);
+    if (x >= 18446744073709551616.0)
+      G[o] = UINT64_MAX;
+    else
+      G[o] = (uint64_t)x;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Configuration and schedule (Sec. II A Eq. schedule; App. C).             */
+/* ------------------------------------------------------------------------ */
+enum { EV_COPY = 1, EV_STORE = 2, EV_CSWAP = 3, EV_BUS = 4, EV_FETCH = 5 };
+
+#define ORC_MAXEV 64
+
+typedef struct {
+  int n, k, enc;
+  int T, M, D, K2, E;
+  double gamma, a, sg;
+  const uint32_t *mem;
+  uint64_t G[64];
+  int nev[512];
+  int ev_type[512][ORC_MAXEV];
+  int ev_arg[512][ORC_MAXEV];
+} orc_cfg;
+
+static void add_event(orc_cfg *c, int s, int type, int arg) {
+  /* a layer's controlled swap fires once per slice, whoever lists it */
+  for (int e = 0; e < c->nev[s]; ++e)
+    if (c->ev_type[s][e] == type && c->ev_arg[s][e] == arg)
+      return;
+  c->ev_type[s][c->nev[s]] = type;
+  c->ev_arg[s][c->nev[s]] = arg;
+  c->nev[s]++;
+}
+
+/* Events of the bucket-brigade query.  Address bit t is copied into the root
+ * data slot at 2t+1, moves down one layer per slice and is stored into the
+ * router of layer t at 3t+2; data bit b enters at tau_in = 2n+2b+1, reaches
+ * the leaf layer for the fetch at tau_fetch = 3n+2b+1 and leaves at
+ * tau_out = 4n+2b+1 (Eq. schedule).  Every event at slice s has its mirror
+ * at T-s. */
+static void build_schedule(orc_cfg *c) {
+  int n = c->n, k = c->k, T = c->T;
+  memset(c->nev, 0, sizeof(c->nev));
+  for (int t = 0; t < n; ++t) {
+    add_event(c, 2 * t + 1, EV_COPY, t);
+    add_event(c, T - 2 * t - 1, EV_COPY, t);
+    for (int l = 0; l < t; ++l) {
+      add_event(c, 2 * t + 2 + l, EV_CSWAP, l);
+      add_event(c, T - 2 * t - 2 - l, EV_CSWAP, l);
+    }
+    add_event(c, 3 * t + 2, EV_STORE, t);
+    add_event(c, T - 3 * t - 2, EV_STORE, t);
+  }
+  for (int b = 0; b < k; ++b) {
+    add_event(c, 2 * n + 2 * b + 1, EV_BUS, b);
+    add_event(c, 4 * n + 2 * b + 1, EV_BUS, b);
+    for (int l = 0; l + 1 < n; ++l) {
+      add_event(c, 2 * n + 2 * b + 2 + l, EV_CSWAP, l);
+      add_event(c, 4 * n + 2 * b - l, EV_CSWAP, l);
+    }
+    add_event(c, 3 * n + 2 * b + 1, EV_FETCH, b);
+  }
+}
+
+static int cfg_init(orc_cfg *c, int n, int k, int enc, double gamma,
+                    const uint32_t *mem) {
+  if (n < 1 || n > 15 || k < 1 || k > 8 || k > n)
+    return -4;
+  if (enc != ORC_QUBIT && enc != ORC_QUTRIT)
+    return -1;
+  if (!(gamma >= 0.0 && gamma < 1.0))
+    return -1;
+  c->n = n;
+  c->k = k;
+  c->enc = enc;
+  c->T = 6 * n + 2 * k;
+  c->M = 2 * ((1 << n) - 1);
+  c->D = 1 << n;
+  c->K2 = 1 << k;
+  c->E = enc == ORC_QUBIT ? c->D * c->K2 : c->D;
+  c->gamma = gamma;
+  c->a = sqrt(1.0 - gamma);
+  c->sg = sqrt(gamma);
+  c->mem = mem;
+  orc_thresholds(gamma, c->G);
+  build_schedule(c);
+  return 0;
+}
+
+/* Export the event list of slice s (for schedule tests). */
+int orc_schedule(int n, int k, int s, int *types, int *args) {
+  static const uint32_t zero_mem[1] = {0};
+  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  int rc = cfg_init(c, n, k, ORC_QUBIT, 0.0, zero_mem);
+  if (rc) {
+    free(c);
+    return rc;
+  }
+  int m = 0;
+  if (s >= 1 && s < c->T) {
+    m = c->nev[s];
+    for (int e = 0; e < m; ++e) {
+      types[e] = c->ev_type[s][e];
+      args[e] = c->ev_arg[s][e];
+    }
+  }
+  free(c);
+  return m;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Candidate history (Sec. IV D step 1; Alg. 1 step 1).                      */
+/* ------------------------------------------------------------------------ */
+static int sample_candidates(const orc_cfg *c, uint64_t seed, uint32_t traj,
+                             uint32_t *L, int cap) {
+  uint64_t S = (uint64_t)(c->T - 1) * (uint64_t)c->M;
+  uint64_t nb = (S + 63) / 64;
+  int cnt = 0;
+  for (uint64_t b = 0; b < nb; ++b) {
+    uint64_t len = S - 64 * b < 64 ? S - 64 * b : 64;
+    uint64_t pos = 0;
+    for (uint32_t j = 0;; ++j) {
+      uint64_t u = draw_u64(seed, (uint32_t)b, j, traj, ORC_TAG_FAULT);
+      int o = 0;
+      while (o < 64 && !(u < c->G[o]))
+        ++o;
+      if (o == 64 || pos + (uint64_t)o >= len)
+        break;
+      if (cnt < cap && L)
+        L[cnt] = (uint32_t)(64 * b + pos + (uint64_t)o);
+      ++cnt;
+      pos += (uint64_t)o + 1;
+    }
+  }
+  return cnt;
+}
+
+int orc_sample(int n, int k, double gamma, uint64_t seed, uint32_t traj,
+               uint32_t *L, int cap) {
+  static const uint32_t zero_mem[1] = {0};
+  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  int rc = cfg_init(c, n, k, ORC_QUBIT, gamma, zero_mem);
+  if (rc) {
+    free(c);
+    return rc;
+  }
+  int cnt = sample_candidates(c, seed, traj, L, cap);
+  free(c);
+  return cnt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Marking rule (Eq. subtree, Eq. badrange; Alg. 1 steps 1-2).              */
+/* ------------------------------------------------------------------------ */
+/* The node whose subtree is the bad range of a fault at node v. */
+static uint32_t range_node(int enc, uint32_t v) {
+  if (enc == ORC_QUTRIT)
+    return v; /* Eq. subtree */
+  /* Eq. badrange: a right child or a child of the root marks its own
+   * subtree, a left child inherits the range of its parent, the root marks
+   * everything. */
+  for (;;) {
+    if (v == 0)
+      return 0;
+    if (v <= 2)
+      return v;
+    if ((v & 1u) == 0)
+      return v;
+    v = (v - 1) >> 1;
+  }
+}
+
+/* bad[i] = 1 if address i lies in the bad range of some candidate. */
+static int classify(const orc_cfg *c, const uint32_t *L, int ncand,
+                    uint8_t *bad) {
+  int n = c->n;
+  uint32_t nodes = (uint32_t)c->D - 1;
+  uint8_t *mark = (uint8_t *)calloc(nodes, 1);
+  for (int j = 0; j < ncand; ++j) {
+    uint32_t q = L[j] % (uint32_t)c->M;
+    mark[range_node(c->enc, q >> 1)] = 1;
+  }
+  int nbad = 0;
+  for (uint32_t i = 0; i < (uint32_t)c->D; ++i) {
+    int b = 0;
+    for (int l = 0; l < n && !b; ++l) {
+      uint32_t v = ((uint32_t)1 << l) - 1 + (i >> (n - l));
+      if (mark[v])
+        b = 1;
+    }
+    bad[i] = (uint8_t)b;
+    nbad += b;
+  }
+  free(mark);
+  return nbad;
+}
+
+int orc_classify(int n, int k, int enc, const uint32_t *L, int ncand,
+                 uint8_t *bad) {
+  static const uint32_t zero_mem[1] = {0};
+  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  int rc = cfg_init(c, n, k, enc, 0.0, zero_mem);
+  if (rc) {
+    free(c);
+    return rc;
+  }
+  int nb = classify(c, L, ncand, bad);
+  free(c);
+  return nb;
+}
+
+/* Range node of a site's fault, exported for the marking-rule tests. */
+int orc_range_node(int enc, uint32_t v) { return (int)range_node(enc, v); }
+
+/* ------------------------------------------------------------------------ */
+/* Sparse state: one entry per component (address, bus word, tree levels).  */
+/* Gates are permutations of basis labels, so components never split; the  */
+/* state is kept as an array in initial-label order.                        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int E, M;
+  uint32_t *addr;
+  uint32_t *bus;
+  uint8_t *alive;
+  int *nexc; /* number of excited tree sites */
+  double complex *amp;
+  uint8_t *tree; /* E x M levels */
+} orc_state;
+
+static int state_alloc(orc_state *st, int E, int M) {
+  st->E = E;
+  st->M = M;
+  st->addr = (uint32_t *)malloc(sizeof(uint32_t) * E);
+  st->bus = (uint32_t *)malloc(sizeof(uint32_t) * E);
+  st->alive = (uint8_t *)malloc(E);
+  st->nexc = (int *)malloc(sizeof(int) * E);
+  st->amp = (double complex *)malloc(sizeof(double complex) * E);
+  st->tree = (uint8_t *)malloc((size_t)E * (size_t)M);
+  return st->addr && st->bus && st->alive && st->nexc && st->amp && st->tree
+             ? 0
+             : -2;
+}
+
+static void state_free(orc_state *st) {
+  free(st->addr);
+  free(st->bus);
+  free(st->alive);
+  free(st->nexc);
+  free(st->amp);
+  free(st->tree);
+}
+
+/* The data-loading input with uniform address amplitudes and bus word 0.
+ * For the qubit encoding the first Hadamard wall acts on the noiseless bus
+ * before any tree gate touches it, so it is applied here. */
+static void state_init(const orc_cfg *c, orc_state *st) {
+  double ci = 1.0 / sqrt((double)c->D);
+  double wall = c->enc == ORC_QUBIT ? 1.0 / sqrt((double)c->K2) : 1.0;
+  for (int x = 0; x < c->E; ++x) {
+    uint32_t i = c->enc == ORC_QUBIT ? (uint32_t)x >> c->k : (uint32_t)x;
+    uint32_t beta = c->enc == ORC_QUBIT ? (uint32_t)x & (uint32_t)(c->K2 - 1) : 0;
+    st->addr[x] = i;
+    st->bus[x] = beta;
+    st->alive[x] = 1;
+    st->nexc[x] = 0;
+    st->amp[x] = ci * wall;
+    memset(st->tree + (size_t)x * c->M, 0, c->M);
+  }
+}
+
+static void swap_u8(uint8_t *a, uint8_t *b) {
+  uint8_t t = *a;
+  *a = *b;
+  *b = t;
+}
+
+/* Apply one scheduled event to component x. */
+static void apply_event(const orc_cfg *c, orc_state *st, int x, int type,
+                        int arg) {
+  uint8_t *tr = st->tree + (size_t)x * c->M;
+  int n = c->n;
+  switch (type) {
+  case EV_COPY: { /* CNOT from address bit t into the root data slot */
+    uint32_t bit = (st->addr[x] >> (n - 1 - arg)) & 1u;
+    if (bit) {
+      tr[1] ^= 1;
+      st->nexc[x] += tr[1] ? 1 : -1;
+    }
+    break;
+  }
+  case EV_STORE: {
+    int l = arg;
+    uint32_t v0 = ((uint32_t)1 << l) - 1, v1 = ((uint32_t)2 << l) - 1;
+    for (uint32_t v = v0; v < v1; ++v) {
+      uint8_t *r = &tr[2 * v], *d = &tr[2 * v + 1];
+      if (c->enc == ORC_QUBIT) {
+        swap_u8(r, d); /* SWAP(a_v, d_v) */
+      } else {
+        int gated;
+        if (v == 0) {
+          gated = 1;
+        } else {
+          uint32_t p = (v - 1) >> 1;
+          gated = (v & 1u) ? tr[2 * p] == LV_L : tr[2 * p] == LV_R;
+        }
+        if (!gated)
+          continue;
+        /* (W,0)<->(L,0), (W,1)<->(R,0); (L,1),(R,1) unchanged */
+        if (*r == LV_W) {
+          uint8_t b = *d;
+          *r = b ? LV_R : LV_L;
+          *d = 0;
+          if (!b)
+            st->nexc[x] += 1;
+        } else if (*d == 0) {
+          uint8_t b = *r == LV_R ? 1 : 0;
+          *r = LV_W;
+          *d = b;
+          if (!b)
+            st->nexc[x] -= 1;
+        }
+      }
+    }
+    break;
+  }
+  case EV_CSWAP: {
+    int l = arg;
+    uint32_t v0 = ((uint32_t)1 << l) - 1, v1 = ((uint32_t)2 << l) - 1;
+    for (uint32_t v = v0; v < v1; ++v) {
+      uint8_t r = tr[2 * v];
+      uint32_t ch;
+      if (c->enc == ORC_QUBIT) {
+        ch = r ? 2 * v + 2 : 2 * v + 1;
+      } else {
+        if (r == LV_W)
+          continue; /* the wait state blocks routing */
+        ch = r == LV_L ? 2 * v + 1 : 2 * v + 2;
+      }
+      swap_u8(&tr[2 * v + 1], &tr[2 * ch + 1]);
+    }
+    break;
+  }
+  case EV_BUS: { /* SWAP(bus_b, d_0) */
+    uint32_t bb = (st->bus[x] >> arg) & 1u;
+    uint8_t d = tr[1];
+    tr[1] = (uint8_t)bb;
+    st->bus[x] = (st->bus[x] & ~(1u << arg)) | ((uint32_t)d << arg);
+    st->nexc[x] += (int)bb - (int)d;
+    break;
+  }
+  case EV_FETCH: {
+    int l = n - 1;
+    uint32_t v0 = ((uint32_t)1 << l) - 1, v1 = ((uint32_t)2 << l) - 1;
+    for (uint32_t v = v0; v < v1; ++v) {
+      uint32_t p = v - v0;
+      uint8_t r = tr[2 * v];
+      if (c->enc == ORC_QUBIT) {
+        /* CZ phase kickback: -1 on d_v = 1 when the routed cell holds 1 */
+        if (tr[2 * v + 1]) {
+          uint32_t cell = 2 * p + (r ? 1u : 0u);
+          if ((c->mem[cell] >> arg) & 1u)
+            st->amp[x] = -st->amp[x];
+        }
+      } else {
+        /* computational-basis CNOT from the routed cell */
+        if (r == LV_W)
+          continue;
+        uint32_t cell = 2 * p + (r == LV_R ? 1u : 0u);
+        if ((c->mem[cell] >> arg) & 1u) {
+          tr[2 * v + 1] ^= 1;
+          st->nexc[x] += tr[2 * v + 1] ? 1 : -1;
+        }
+      }
+    }
+    break;
+  }
+  default:
+    break;
+  }
+}
+
+/* Neumaier compensated sum. */
+typedef struct {
+  double s, c;
+} nsum;
+static void nadd(nsum *a, double v) {
+  double t = a->s + v;
+  if (fabs(a->s) >= fabs(v))
+    a->c += (a->s - t) + v;
+  else
+    a->c += (v - t) + a->s;
+  a->s = t;
+}
+static double nval(const nsum *a) { return a->s + a->c; }
+
+static double abs2(double complex z) {
+  return creal(z) * creal(z) + cimag(z) * cimag(z);
+}
+
+typedef struct {
+  /* per-trajectory results */
+  double fid, fid_pre;
+  double w_ground, w_total;
+  int ncand, nbad, ref, nexplicit;
+  int njumps, first_jump;
+  int ref_survived, q_ground;
+  int max_exc;
+} orc_result;
+
+#define ORC_JLOG_MAX 4096
+
+typedef struct {
+  int n;                     /* entries used */
+  int slice[ORC_JLOG_MAX];   /* slice of the jump */
+  int site[ORC_JLOG_MAX];    /* tree site */
+  int level[ORC_JLOG_MAX];   /* 1 = qubit/L/data, 2 = R */
+} orc_jlog;
+
+/* One joint damping layer (Eq. layerkraus, Theorem 4, Eq. maskweight). */
+static int damping_layer(const orc_cfg *c, orc_state *st, int s,
+                         const int *cq, int nc, double uaux, orc_jlog *jl,
+                         int *jsite, int *jlev) {
+  int nJ = 0;
+  if (nc > 0) {
+    int any = 0;
+    for (int x = 0; x < st->E && !any; ++x) {
+      if (!st->alive[x])
+        continue;
+      const uint8_t *tr = st->tree + (size_t)x * c->M;
+      for (int j = 0; j < nc; ++j)
+        if (tr[cq[j]]) {
+          any = 1;
+          break;
+        }
+    }
+    if (any) {
+      nsum we = {0, 0}, wn = {0, 0};
+      for (int x = 0; x < st->E; ++x) {
+        if (!st->alive[x])
+          continue;
+        const uint8_t *tr = st->tree + (size_t)x * c->M;
+        int hit = 0;
+        for (int j = 0; j < nc; ++j)
+          if (tr[cq[j]])
+            hit = 1;
+        if (hit)
+          nadd(&wn, abs2(st->amp[x]));
+        else
+          nadd(&we, abs2(st->amp[x]));
+      }
+      double w_empty = nval(&we), w_ne = nval(&wn);
+      double r = uaux * (w_empty + w_ne);
+      if (!(r < w_empty)) {
+        double r2 = r - w_empty, cum = 0.0;
+        int pick = -1, last = -1;
+        for (int x = 0; x < st->E; ++x) {
+          if (!st->alive[x])
+            continue;
+          const uint8_t *tr = st->tree + (size_t)x * c->M;
+          int hit = 0;
+          for (int j = 0; j < nc; ++j)
+            if (tr[cq[j]])
+              hit = 1;
+          if (!hit)
+            continue;
+          last = x;
+          cum += abs2(st->amp[x]);
+          if (cum > r2) {
+            pick = x;
+            break;
+          }
+        }
+        if (pick < 0)
+          pick = last;
+        const uint8_t *tr = st->tree + (size_t)pick * c->M;
+        for (int j = 0; j < nc; ++j)
+          if (tr[cq[j]]) {
+            jsite[nJ] = cq[j];
+            jlev[nJ] = tr[cq[j]];
+            ++nJ;
+          }
+      }
+    }
+  }
+  /* K_J = prod_{q in J} K1_q prod_{q not in J} K0_q on every component */
+  for (int x = 0; x < st->E; ++x) {
+    if (!st->alive[x])
+      continue;
+    uint8_t *tr = st->tree + (size_t)x * c->M;
+    int ok = 1;
+    for (int j = 0; j < nJ; ++j)
+      if (tr[jsite[j]] != jlev[j])
+        ok = 0;
+    if (!ok) {
+      st->alive[x] = 0;
+      continue;
+    }
+    double complex f = 1.0;
+    for (int j = 0; j < nJ; ++j)
+      f *= c->sg;
+    for (int e = 0; e < st->nexc[x] - nJ; ++e)
+      f *= c->a;
+    st->amp[x] *= f;
+    for (int j = 0; j < nJ; ++j)
+      tr[jsite[j]] = 0;
+    st->nexc[x] -= nJ;
+  }
+  if (jl)
+    for (int j = 0; j < nJ && jl->n < ORC_JLOG_MAX; ++j) {
+      jl->slice[jl->n] = s;
+      jl->site[jl->n] = jsite[j];
+      jl->level[jl->n] = jlev[j];
+      jl->n++;
+    }
+  return nJ;
+}
+
+static int count_exc(const orc_cfg *c, const orc_state *st, int x) {
+  const uint8_t *tr = st->tree + (size_t)x * c->M;
+  int m = 0;
+  for (int q = 0; q < c->M; ++q)
+    m += tr[q] != 0;
+  return m;
+}
+
+/* History source: sampled from the seed, or forced by the caller. */
+typedef struct {
+  const uint32_t *L; /* forced candidates (ascending), or NULL */
+  int ncand;
+  const double *uaux; /* forced auxiliary uniforms indexed by slice, or NULL */
+  double ufin;        /* forced final uniform if >= 0 */
+} orc_forced;
+
+/* Evolve one trajectory; optionally stop after the gates of slice
+ * stop_slice (> 0) and leave the state in st. */
+static int run_traj(const orc_cfg *c, uint64_t seed, uint32_t traj,
+                    const orc_forced *fh, int check_counts, orc_state *st,
+                    orc_result *res, orc_jlog *jl) {
+  int T = c->T, M = c->M;
+  uint32_t *L = NULL;
+  int ncand;
+  if (fh && fh->L) {
+    ncand = fh->ncand;
+    L = (uint32_t *)malloc(sizeof(uint32_t) * (ncand > 0 ? ncand : 1));
+    memcpy(L, fh->L, sizeof(uint32_t) * ncand);
+  } else {
+    ncand = sample_candidates(c, seed, traj, NULL, 0);
+    L = (uint32_t *)malloc(sizeof(uint32_t) * (ncand > 0 ? ncand : 1));
+    sample_candidates(c, seed, traj, L, ncand);
+  }
+  uint8_t *bad = (uint8_t *)malloc(c->D);
+  int nbad = classify(c, L, ncand, bad);
+  int ref = -1;
+  for (int i = 0; i < c->D; ++i)
+    if (!bad[i]) {
+      ref = i;
+      break;
+    }
+  state_init(c, st);
+  if (jl)
+    jl->n = 0;
+  int *cq = (int *)malloc(sizeof(int) * (ncand > 0 ? ncand : 1));
+  int *jsite = (int *)malloc(sizeof(int) * (ncand > 0 ? ncand : 1));
+  int *jlev = (int *)malloc(sizeof(int) * (ncand > 0 ? ncand : 1));
+  int cpos = 0, njumps = 0, first_jump = 0, max_exc = 0;
+  for (int s = 1; s < T; ++s) {
+    for (int x = 0; x < c->E; ++x) {
+      if (!st->alive[x])
+        continue;
+      for (int e = 0; e < c->nev[s]; ++e)
+        apply_event(c, st, x, c->ev_type[s][e], c->ev_arg[s][e]);
+      if (st->nexc[x] > max_exc)
+        max_exc = st->nexc[x];
+      if (check_counts && count_exc(c, st, x) != st->nexc[x])
+        max_exc = 1 << 30; /* flags a bookkeeping error to the tests */
+    }
+    int nc = 0;
+    while (cpos < ncand && (int)(L[cpos] / (uint32_t)M) + 1 == s)
+      cq[nc++] = (int)(L[cpos++] % (uint32_t)M);
+    double ua = (fh && fh->uaux) ? fh->uaux[s]
+                                 : u53(draw_u64(seed, (uint32_t)s, 0, traj,
+                                                ORC_TAG_AUX));
+    int nJ = damping_layer(c, st, s, cq, nc, ua, jl, jsite, jlev);
+    if (nJ > 0) {
+      ++njumps;
+      if (!first_jump)
+        first_jump = s;
+    }
+  }
+  free(cq);
+  free(jsite);
+  free(jlev);
+
+  /* End of the query: wall 2 (qubit), tree measurement, fidelity. */
+  double ci = 1.0 / sqrt((double)c->D);
+  double complex overlap = 0.0;
+  nsum wg = {0, 0}, wt = {0, 0};
+  if (c->enc == ORC_QUBIT) {
+    int K2 = c->K2;
+    double complex *grp = (double complex *)malloc(sizeof(double complex) * K2);
+    double h = 1.0 / sqrt((double)K2);
+    for (int i = 0; i < c->D; ++i) {
+      /* components of address i with the ground tree: Hadamard wall over
+       * the bus word within the group */
+      int any = 0;
+      for (int beta = 0; beta < K2; ++beta)
+        grp[beta] = 0.0;
+      for (int x = i * K2; x < (i + 1) * K2; ++x) {
+        if (!st->alive[x] || st->nexc[x] != 0)
+          continue;
+        grp[st->bus[x]] += st->amp[x];
+        any = 1;
+      }
+      if (!any)
+        continue;
+      for (int cw = 0; cw < K2; ++cw) {
+        double complex v = 0.0;
+        for (int beta = 0; beta < K2; ++beta)
+          v += (__builtin_popcount((unsigned)(beta & cw)) & 1) ? -grp[beta]
+                                                               : grp[beta];
+        v *= h;
+        nadd(&wg, abs2(v));
+        if ((uint32_t)cw == (c->mem[i] & (uint32_t)(K2 - 1)))
+          overlap += ci * v; /* conj(c_i) = c_i, real input */
+      }
+    }
+    free(grp);
+    /* groups with an excited tree: the wall is orthogonal on each group */
+    for (int x = 0; x < c->E; ++x)
+      if (st->alive[x] && st->nexc[x] != 0)
+        nadd(&wt, abs2(st->amp[x]));
+  } else {
+    for (int x = 0; x < c->E; ++x) {
+      if (!st->alive[x])
+        continue;
+      if (st->nexc[x] == 0) {
+        nadd(&wg, abs2(st->amp[x]));
+        if (st->bus[x] == (c->mem[st->addr[x]] & (uint32_t)(c->K2 - 1)))
+          overlap += ci * st->amp[x];
+      } else {
+        nadd(&wt, abs2(st->amp[x]));
+      }
+    }
+  }
+  double w_ground = nval(&wg);
+  double w_total = w_ground + nval(&wt);
+  double uf = (fh && fh->ufin >= 0.0)
+                  ? fh->ufin
+                  : u53(draw_u64(seed, 0, 0, traj, ORC_TAG_FINAL));
+  double r = uf * w_total;
+  int q_ground = r < w_ground;
+  double ov2 = abs2(overlap);
+  res->fid = (q_ground && w_ground > 0.0) ? ov2 / w_ground : 0.0;
+  res->fid_pre = w_total > 0.0 ? ov2 / w_total : 0.0;
+  res->w_ground = w_ground;
+  res->w_total = w_total;
+  res->ncand = ncand;
+  res->nbad = nbad;
+  res->ref = ref;
+  res->nexplicit = c->E;
+  res->njumps = njumps;
+  res->first_jump = first_jump;
+  res->q_ground = q_ground;
+  res->max_exc = max_exc;
+  int rs = 0;
+  if (ref >= 0)
+    for (int x = 0; x < c->E; ++x)
+      if (st->alive[x] && st->addr[x] == (uint32_t)ref)
+        rs = 1;
+  res->ref_survived = rs;
+  free(bad);
+  free(L);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exported entry points (ctypes).                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Result layout of orc_run_traj's double and int outputs. */
+#define ORC_NRD 4
+#define ORC_NRI 10
+
+static void pack_result(const orc_result *r, double *rd, int *ri) {
+  if (rd) {
+    rd[0] = r->fid;
+    rd[1] = r->fid_pre;
+    rd[2] = r->w_ground;
+    rd[3] = r->w_total;
+  }
+  if (ri) {
+    ri[0] = r->ncand;
+    ri[1] = r->nbad;
+    ri[2] = r->ref;
+    ri[3] = r->nexplicit;
+    ri[4] = r->njumps;
+    ri[5] = r->first_jump;
+    ri[6] = r->ref_survived;
+    ri[7] = r->q_ground;
+    ri[8] = r->max_exc;
+    ri[9] = 0;
+  }
+}
+
+/*
+ * One trajectory.  forced_L/forced_ncand override the sampled candidates
+ * when forced_L != NULL; forced_uaux (T entries, index = slice) overrides the
+ * auxiliary uniforms; forced_ufin >= 0 overrides the final uniform.
+ * Outputs: rd[ORC_NRD], ri[ORC_NRI]; optional jump log (jslice, jsite,
+ * jlevel, capacity jcap, count in *njl); optional export of the final
+ * pre-wall components (exp_cap entries): address, bus word, excitation count,
+ * amplitude (re, im), and the sites/levels of each (M bytes per component in
+ * exp_tree).  Returns the number of exported components, or < 0 on error.
+ */
+int orc_run_traj(int n, int k, int enc, double gamma, const uint32_t *mem,
+                 uint64_t seed, uint32_t traj, const uint32_t *forced_L,
+                 int forced_ncand, const double *forced_uaux,
+                 double forced_ufin, int check_counts, double *rd, int *ri,
+                 int *jslice, int *jsite, int *jlevel, int jcap, int *njl,
+                 uint32_t *exp_addr, uint32_t *exp_bus, double *exp_amp,
+                 uint8_t *exp_tree, int exp_cap) {
+  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  int rc = cfg_init(c, n, k, enc, gamma, mem);
+  if (rc) {
+    free(c);
+    return rc;
+  }
+  orc_state st;
+  if (state_alloc(&st, c->E, c->M)) {
+    state_free(&st);
+    free(c);
+    return -2;
+  }
+  orc_forced fh = {forced_L, forced_ncand, forced_uaux, forced_ufin};
+  orc_jlog *jl = (orc_jlog *)malloc(sizeof(orc_jlog));
+  orc_result res;
+  run_traj(c, seed, traj, &fh, check_counts, &st, &res, jl);
+  pack_result(&res, rd, ri);
+  if (njl) {
+    int m = jl->n < jcap ? jl->n : jcap;
+    for (int j = 0; j < m; ++j) {
+      jslice[j] = jl->slice[j];
+      jsite[j] = jl->site[j];
+      jlevel[j] = jl->level[j];
+    }
+    *njl = jl->n;
+  }
+  int ne = 0;
+  if (exp_cap > 0) {
+    for (int x = 0; x < c->E; ++x) {
+      if (!st.alive[x])
+        continue;
+      if (ne < exp_cap) {
+        exp_addr[ne] = st.addr[x];
+        exp_bus[ne] = st.bus[x];
+        exp_amp[2 * ne] = creal(st.amp[x]);
+        exp_amp[2 * ne + 1] = cimag(st.amp[x]);
+        memcpy(exp_tree + (size_t)ne * c->M, st.tree + (size_t)x * c->M, c->M);
+      }
+      ++ne;
+    }
+  }
+  free(jl);
+  state_free(&st);
+  free(c);
+  return ne;
+}
+
+/*
+ * Mask weights of one damping layer: evolve the forced history through the
+ * damping layers of slices 1..s-1 and the gates of slice s, then return, for
+ * the candidate sites cand[0..nc-1] of slice s, every distinct nonempty mask
+ * J = C cap X(x) with its weight w(J) (Eq. maskweight) and w(empty).
+ * Masks are returned as nc levels per entry (0 = not in J).
+ */
+int orc_layer_masks(int n, int k, int enc, double gamma, const uint32_t *mem,
+                    const uint32_t *forced_L, int forced_ncand,
+                    const double *forced_uaux, int s, const int *cand, int nc,
+                    uint8_t *masks, double *weights, int cap, double *w_empty) {
+  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  int rc = cfg_init(c, n, k, enc, gamma, mem);
+  if (rc) {
+    free(c);
+    return rc;
+  }
+  orc_state st;
+  state_alloc(&st, c->E, c->M);
+  state_init(c, &st);
+  int ncand = forced_ncand;
+  int *cq = (int *)malloc(sizeof(int) * (ncand + 1));
+  int *js = (int *)malloc(sizeof(int) * (ncand + 1));
+  int *jv = (int *)malloc(sizeof(int) * (ncand + 1));
+  int cpos = 0;
+  for (int ss = 1; ss <= s; ++ss) {
+    for (int x = 0; x < c->E; ++x) {
+      if (!st.alive[x])
+        continue;
+      for (int e = 0; e < c->nev[ss]; ++e)
+        apply_event(c, &st, x, c->ev_type[ss][e], c->ev_arg[ss][e]);
+    }
+    if (ss == s)
+      break;
+    int ncs = 0;
+    while (cpos < ncand && (int)(forced_L[cpos] / (uint32_t)c->M) + 1 == ss)
+      cq[ncs++] = (int)(forced_L[cpos++] % (uint32_t)c->M);
+    damping_layer(c, &st, ss, cq, ncs, forced_uaux ? forced_uaux[ss] : 0.5,
+                  NULL, js, jv);
+  }
+  int nm = 0;
+  nsum we = {0, 0};
+  uint8_t *cur = (uint8_t *)malloc(nc > 0 ? nc : 1);
+  for (int x = 0; x < c->E; ++x) {
+    if (!st.alive[x])
+      continue;
+    const uint8_t *tr = st.tree + (size_t)x * c->M;
+    int hit = 0;
+    for (int j = 0; j < nc; ++j) {
+      cur[j] = tr[cand[j]];
+      if (cur[j])
+        hit = 1;
+    }
+    double w = abs2(st.amp[x]);
+    if (!hit) {
+      nadd(&we, w);
+      continue;
+    }
+    int m;
+    for (m = 0; m < nm; ++m)
+      if (memcmp(masks + (size_t)m * nc, cur, nc) == 0)
+        break;
+    if (m == nm) {
+      if (nm >= cap)
+        continue;
+      memcpy(masks + (size_t)m * nc, cur, nc);
+      weights[m] = 0.0;
+      ++nm;
+    }
+    weights[m] += w;
+  }
+  *w_empty = nval(&we);
+  free(cur);
+  free(cq);
+  free(js);
+  free(jv);
+  state_free(&st);
+  free(c);
+  return nm;
+}
+
+/*
+ * Batch of trajectories traj0 .. traj0+ntraj-1 with OpenMP over
+ * trajectories.  fid[ntraj], fid_pre[ntraj] (or NULL), ri[ntraj*ORC_NRI]
+ * (or NULL).  nthreads <= 0 uses the OpenMP default.  Returns the number of
+ * threads used.
+ */
+int orc_run_batch(int n, int k, int enc, double gamma, const uint32_t *mem,
+                  uint64_t seed, uint32_t traj0, int ntraj, int nthreads,
+                  double *fid, double *fid_pre, int *ri) {
+  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  int rc = cfg_init(c, n, k, enc, gamma, mem);
+  if (rc) {
+    free(c);
+    return rc;
+  }
+  int used = 1;
+#ifdef _OPENMP
+  if (nthreads > 0)
+    omp_set_num_threads(nthreads);
+#pragma omp parallel
+  {
+#pragma omp single
+    used = omp_get_num_threads();
+    orc_state st;
+    state_alloc(&st, c->E, c->M);
+#pragma omp for schedule(dynamic, 1)
+    for (int t = 0; t < ntraj; ++t) {
+      orc_result res;
+      run_traj(c, seed, traj0 + (uint32_t)t, NULL, 0, &st, &res, NULL);
+      fid[t] = res.fid;
+      if (fid_pre)
+        fid_pre[t] = res.fid_pre;
+      if (ri)
+        pack_result(&res, NULL, ri + (size_t)t * ORC_NRI);
+    }
+    state_free(&st);
+  }
+#else
+  (void)nthreads;
+  orc_state st;
+  state_alloc(&st, c->E, c->M);
+  for (int t = 0; t < ntraj; ++t) {
+    orc_result res;
+    run_traj(c, seed, traj0 + (uint32_t)t, NULL, 0, &st, &res, NULL);
+    fid[t] = res.fid;
+    if (fid_pre)
+      fid_pre[t] = res.fid_pre;
+    if (ri)
+      pack_result(&res, NULL, ri + (size_t)t * ORC_NRI);
+  }
+  state_free(&st);
+#endif
+  free(c);
+  return used;
+}
