@@ -1,0 +1,199 @@
+/*
+ * qram.h -- C ABI of the MI355X trajectory simulator for amplitude-damped
+ * bucket-brigade QRAM queries (qubit and qutrit encodings).
+ *
+ * A query of an (n,k)-QRAM maps sum_i c_i |i>|0>_bus to sum_i c_i |i>|d_i>
+ * (Eq. nk-qram).  Each time slice of the T = 6n+2k slice schedule applies its
+ * gates and then one joint amplitude-damping layer over the M = 2(2^n - 1)
+ * tree sites (Sec. II B, Eq. kraus / kraus-tri, Eq. layerkraus).  One
+ * trajectory samples the candidate history in advance, resolves every layer
+ * with one auxiliary draw (Theorem 4), measures the tree at the end and
+ * returns the fidelity of the normalised post-measurement state with the ideal
+ * output, whose tree is in the ground state (App. C).  The "pruned" mode
+ * evolves only the bad branches plus one reference branch and predicts the
+ * others in closed form (Alg. 1, Proposition 1, Theorems 2-3); the "full"
+ * mode evolves every branch.  Both give the same fidelity up to rounding.
+ *
+ * Input class: the data-loading input with uniform address amplitudes
+ * c_i = 2^{-n/2} and bus word 0 (Sec. V, App. D).
+ *
+ * Random numbers (fixed contract, identical for every mode and launch shape):
+ * Philox4x32-10 keyed by the 64-bit seed.  Candidate history: the tree site q
+ * of slice s is linear index L = (s-1) M + q, candidates are i.i.d.
+ * Bernoulli(gamma) drawn by a geometric walk in 64-site blocks with counters
+ * (block, draw, trajectory, 1); the auxiliary uniform of slice s uses
+ * (s, 0, trajectory, 2); the final tree measurement (0, 0, trajectory, 3).
+ * Trajectory indices are global within a seed: a run over [traj0, traj0+a+b)
+ * equals the runs over [traj0, traj0+a) and [traj0+a, traj0+a+b) entry by
+ * entry.  traj0 + ntraj must not exceed 2^32.
+ *
+ * Ownership: the caller owns every buffer it passes; the library never frees
+ * caller memory.  A context owns the device memory it allocates (tables and
+ * work buffers) until qram_destroy.  A context is not thread-safe; use one
+ * context per host thread or lock around calls.
+ *
+ * Errors: every call returns a qram_status.  Nothing throws across the ABI.
+ * After an error the context stays usable and qram_last_error describes it.
+ */
+#ifndef QRAM_H
+#define QRAM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qram_ctx qram_ctx;
+
+typedef enum { QRAM_QUTRIT = 0, QRAM_QUBIT = 1 } qram_encoding;
+
+typedef enum {
+  QRAM_OK = 0,
+  QRAM_E_INVAL = -1,    /* null pointer, gamma outside [0,1), bad enum/mode */
+  QRAM_E_NOMEM = -2,    /* device or host allocation failed */
+  QRAM_E_DEVICE = -3,   /* a HIP call failed */
+  QRAM_E_RANGE = -4,    /* n or k outside the supported range */
+  QRAM_E_CAPACITY = -5  /* an output or work buffer is too small */
+} qram_status;
+
+typedef enum { QRAM_MODE_FULL = 0, QRAM_MODE_PRUNED = 1 } qram_mode;
+
+/* Per-trajectory statistics (32 bytes, naturally aligned). */
+typedef struct {
+  uint32_t n_cand;           /* candidates drawn over slices 1..T-1 */
+  uint32_t n_bad;            /* bad addresses under the marking rule */
+  uint32_t ref_addr;         /* reference address (smallest good), UINT32_MAX if none */
+  uint32_t n_explicit;       /* components evolved explicitly */
+  uint16_t n_jumps;          /* damping layers whose joint outcome J was nonempty */
+  uint16_t first_jump_slice; /* slice of the first nonempty J, 0 if none */
+  uint8_t ref_survived;      /* 1 if the reference branch was never annihilated */
+  uint8_t q_ground;          /* 1 if the tree measurement gave the ground state */
+  uint8_t flags;             /* bit 0: candidate buffer overflow, bit 1: list overflow */
+  uint8_t pad;
+  double fid_pre;            /* |<psi_id|psi>|^2 / <psi|psi> before the tree measurement */
+} qram_traj_stats;
+
+/*
+ * Create a context for an (n,k)-QRAM in the given encoding with damping
+ * strength gamma (Sec. II B; Theorem 4 needs gamma < 1).
+ *   n_addr      1..15 (qubit), 1..14 (qutrit); k_data 1..8 with k <= n.
+ *   memory_bits host array of 2^n words; bit b of word i is d_i^(b); only the
+ *               low k bits are used.  Copied: the caller may free it after the
+ *               call returns.
+ *   out         receives the context.
+ * The current HIP device at the time of the call is used for every later call.
+ * Returns QRAM_E_RANGE when gamma is so large that the damping weights of the
+ * deepest orbit underflow double precision.
+ */
+qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
+                        const uint32_t *memory_bits, qram_ctx **out);
+
+/* Release a context and all device memory it owns.  NULL is allowed. */
+void qram_destroy(qram_ctx *ctx);
+
+/* Message for the last failing call on ctx (or for qram_create when ctx is
+ * NULL); valid until the next call on the same context. */
+const char *qram_last_error(const qram_ctx *ctx);
+
+/*
+ * Candidate histories and branch classification (Alg. 1 steps 1-2) of
+ * trajectories traj0 .. traj0+ntraj-1, synchronously, into host buffers.
+ *   n_cand      [ntraj] number of candidates of each trajectory.
+ *   cand_digest [ntraj] FNV-1a 64 of the ascending candidate indices L, each
+ *               folded as 4 little-endian bytes (offset basis
+ *               0xcbf29ce484222325, prime 0x100000001b3).  May be NULL.
+ *   n_bad       [ntraj] number of bad addresses.  May be NULL.
+ *   bad_bits    [ntraj * ceil(2^n / 64)] bitmap of bad addresses (bit i%64 of
+ *               word i/64).  May be NULL.
+ *   cand_L      optional dump of all candidate lists, concatenated in
+ *               trajectory order; cand_cap entries available.  If the total
+ *               exceeds cand_cap the dump is skipped and QRAM_E_CAPACITY is
+ *               returned after every other output has been written.
+ */
+qram_status qram_sample_faults(qram_ctx *ctx, uint64_t seed, uint64_t traj0,
+                               uint32_t ntraj, uint32_t *n_cand,
+                               uint64_t *cand_digest, uint32_t *n_bad,
+                               uint64_t *bad_bits, uint32_t *cand_L,
+                               uint64_t cand_cap);
+
+/*
+ * Full evolution of every branch (the comparator mode), synchronously.
+ *   fid [ntraj] post-measurement fidelity of each trajectory.
+ *   st  [ntraj] statistics, or NULL.
+ */
+qram_status qram_run_full(qram_ctx *ctx, uint64_t seed, uint64_t traj0,
+                          uint32_t ntraj, double *fid, qram_traj_stats *st);
+
+/*
+ * Pruned evolution (Alg. 1): bad branches plus one reference branch evolve
+ * explicitly; good branches are predicted (Proposition 1 for the qutrit
+ * encoding, Theorem 3 and the XOR mirror for the qubit encoding) and enter
+ * every joint damping draw through their closed-form weights (Eq. maskweight).
+ * Same arguments as qram_run_full; same results up to rounding.
+ */
+qram_status qram_run_pruned(qram_ctx *ctx, uint64_t seed, uint64_t traj0,
+                            uint32_t ntraj, double *fid, qram_traj_stats *st);
+
+/*
+ * Device-buffer variants: d_fid [ntraj] and d_st [ntraj] (or NULL) are device
+ * pointers; the work is enqueued on stream (a hipStream_t, NULL = the null
+ * stream) and the call returns without waiting.  The outputs are valid once
+ * the stream has reached this point.  Work buffers stay owned by the context;
+ * a later call on the same context may reuse them only after this one is
+ * ordered before it on the stream (same stream, or caller-side sync).
+ */
+qram_status qram_run_full_async(qram_ctx *ctx, uint64_t seed, uint64_t traj0,
+                                uint32_t ntraj, double *d_fid,
+                                qram_traj_stats *d_st, void *stream);
+qram_status qram_run_pruned_async(qram_ctx *ctx, uint64_t seed, uint64_t traj0,
+                                  uint32_t ntraj, double *d_fid,
+                                  qram_traj_stats *d_st, void *stream);
+
+/* Mean and standard error of the mean of fid[0..ntraj-1] (host arrays). */
+qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,
+                          double *sem);
+
+/*
+ * Launch shape of a mode: threads per trajectory (64, 128, 256, 512 or 1024),
+ * schedule 0 = one workgroup per trajectory in index order, 1 = persistent
+ * workgroups taking trajectories from a device queue in descending order of
+ * explicit work (longest first).  threads = 0 restores the automatic choice.
+ * The shape changes only the speed: results are identical across shapes up to
+ * the rounding of the per-slice weight sums.
+ */
+qram_status qram_set_launch(qram_ctx *ctx, qram_mode mode, int threads,
+                            int schedule);
+qram_status qram_get_launch(const qram_ctx *ctx, qram_mode mode, int *threads,
+                            int *schedule);
+
+/*
+ * Measure every launch shape of a mode on trajectories [traj0, traj0+ntraj)
+ * of seed and keep the fastest (the autotuner).  best_ms receives its time.
+ */
+qram_status qram_autotune(qram_ctx *ctx, qram_mode mode, uint64_t seed,
+                          uint64_t traj0, uint32_t ntraj, double *best_ms);
+
+/*
+ * Device time of the last synchronous run's kernels (milliseconds): sampling,
+ * classification and evolution, measured with HIP events on the context's
+ * stream.  times[3].
+ */
+qram_status qram_last_kernel_ms(const qram_ctx *ctx, double *times);
+
+/*
+ * Test entry: one trajectory under a forced history instead of the random
+ * draws.  cand_L [ncand] ascending linear indices; u_aux [T] auxiliary
+ * uniforms indexed by slice (entry 0 unused); u_fin the final uniform.
+ * Runs the given mode; returns the fidelity and statistics.
+ */
+qram_status qram_run_forced(qram_ctx *ctx, qram_mode mode,
+                            const uint32_t *cand_L, uint32_t ncand,
+                            const double *u_aux, double u_fin, double *fid,
+                            qram_traj_stats *st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QRAM_H */

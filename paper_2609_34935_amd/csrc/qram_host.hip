@@ -1,0 +1,807 @@
+// Host side of the HIP library: contexts, schedule tables, work buffers,
+// launch sequence, autotuner and the C ABI declared in include/qram.h.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qram_internal.h"
+
+using namespace qr;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct qram_ctx {
+  int n = 0, k = 0, enc = 0;
+  double gamma = 0.0;
+  int T = 0, M = 0, D = 0, K2 = 1, Emax = 0, lmax = 0, emax = 0, rec = 0;
+  int device = 0, num_cu = 0;
+  size_t lds_max = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  Tables htab{};
+  Tables *dtab = nullptr;
+  uint32_t *dmem = nullptr;
+  double *dwpow = nullptr, *dapow = nullptr;
+  std::vector<uint32_t> mem;
+  std::string err;
+  // work buffers (grown on demand)
+  uint32_t batch_cap = 0;   // trajectories per batch the buffers hold
+  uint32_t cand_cap = 0;    // candidate slots per trajectory
+  uint32_t grid_cap = 0;    // evolution workgroups the per-workgroup buffers hold
+  uint32_t ecap_cap = 0;    // tier-1 words per workgroup in gstate
+  uint32_t *cand = nullptr, *ncand = nullptr, *nbad = nullptr, *ref = nullptr;
+  uint32_t *nexpl = nullptr, *order = nullptr, *counter = nullptr, *errw = nullptr;
+  uint64_t *badbits = nullptr, *digest = nullptr;
+  uint16_t *xlist = nullptr, *pool = nullptr;
+  uint32_t *gstate = nullptr;
+  double *fid_tmp = nullptr, *uaux = nullptr;
+  qram_traj_stats *st_tmp = nullptr;
+  uint32_t out_cap = 0;
+  // launch shape per mode
+  int threads[2] = {0, 0};
+  int schedule[2] = {1, 1};
+  bool user_shape[2] = {false, false};
+  double last_ms[3] = {0, 0, 0};
+};
+
+namespace {
+
+qram_status fail(qram_ctx *c, qram_status st, const std::string &msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_create_error = msg;
+  return st;
+}
+
+#define HIPCHK(c, expr)                                                       \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      return fail((c), QRAM_E_DEVICE,                                         \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+template <typename T>
+qram_status dev_alloc(qram_ctx *c, T **p, size_t count) {
+  if (*p) {
+    (void)hipFree(*p);
+    *p = nullptr;
+  }
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(c, QRAM_E_NOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  return QRAM_OK;
+}
+
+template <typename T>
+void dev_free(T **p) {
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// Schedule tables.  Events follow the bucket-brigade query of Sec. II A:
+// address bit t is copied into the root data slot at 2t+1, moves down one
+// layer per slice and is stored into the router of layer t at 3t+2; data bit
+// b enters at 2n+2b+1, is fetched at 3n+2b+1 and leaves at 4n+2b+1; every
+// event has its mirror at T-s.  Token positions are then obtained by moving
+// each token of one generic root-to-leaf path through these events.
+// ---------------------------------------------------------------------------
+bool build_tables(qram_ctx *c, std::string &why) {
+  Tables &t = c->htab;
+  std::memset(&t, 0, sizeof(t));
+  const int n = c->n, k = c->k, T = c->T;
+  t.n = n;
+  t.k = k;
+  t.enc = c->enc;
+  t.T = T;
+  t.M = c->M;
+  t.D = c->D;
+  t.K2 = c->K2;
+  t.lmax = c->lmax;
+  t.emax = c->emax;
+  t.rec = c->rec;
+  // geometric-walk thresholds: G[o] = floor(2^64 (1 - (1-gamma)^(o+1)))
+  {
+    const double q = 1.0 - c->gamma;
+    double qp = 1.0;
+    for (int o = 0; o < 64; ++o) {
+      qp = qp * q;
+      const double x = std::ldexp(1.0 - qp, 64);
+      t.G[o] = x >= 18446744073709551616.0 ? UINT64_MAX : (uint64_t)x;
+    }
+  }
+  for (int s = 0; s < MAXT; ++s) {
+    t.copy_t[s] = t.store_l[s] = t.bus_b[s] = t.fetch_b[s] = -1;
+    t.cswap[s] = 0;
+  }
+  auto set1 = [&](int8_t *arr, int s, int v) -> bool {
+    if (arr[s] != -1 && arr[s] != v) return false;
+    arr[s] = (int8_t)v;
+    return true;
+  };
+  bool ok = true;
+  for (int a = 0; a < n; ++a) {
+    ok &= set1(t.copy_t, 2 * a + 1, a);
+    ok &= set1(t.copy_t, T - 2 * a - 1, a);
+    ok &= set1(t.store_l, 3 * a + 2, a);
+    ok &= set1(t.store_l, T - 3 * a - 2, a);
+    for (int l = 0; l < a; ++l) {
+      t.cswap[2 * a + 2 + l] |= 1u << l;
+      t.cswap[T - 2 * a - 2 - l] |= 1u << l;
+    }
+  }
+  for (int b = 0; b < k; ++b) {
+    ok &= set1(t.bus_b, 2 * n + 2 * b + 1, b);
+    ok &= set1(t.bus_b, 4 * n + 2 * b + 1, b);
+    ok &= set1(t.fetch_b, 3 * n + 2 * b + 1, b);
+    for (int l = 0; l + 1 < n; ++l) {
+      t.cswap[2 * n + 2 * b + 2 + l] |= 1u << l;
+      t.cswap[4 * n + 2 * b - l] |= 1u << l;
+    }
+  }
+  if (!ok) {
+    why = "schedule events collide";
+    return false;
+  }
+  const int ntok = n + k;
+  std::vector<int> pos(ntok, -1);  // layer << 1 | slot, -1 outside
+  std::vector<int> entered(ntok, 0);
+  for (int s = 1; s < T; ++s) {
+    if (t.copy_t[s] >= 0) {
+      const int a = t.copy_t[s];
+      if (pos[a] < 0 && !entered[a]) {
+        pos[a] = 1;  // root data slot
+        entered[a] = 1;
+      } else if (pos[a] == 1) {
+        pos[a] = -1;
+      } else {
+        why = "address token not at the root when uncopied";
+        return false;
+      }
+    }
+    if (t.store_l[s] >= 0) {
+      const int l = t.store_l[s];
+      for (int x = 0; x < ntok; ++x)
+        if (pos[x] >= 0 && (pos[x] >> 1) == l) pos[x] ^= 1;
+    }
+    if (t.cswap[s]) {
+      for (int x = 0; x < ntok; ++x) {
+        if (pos[x] < 0 || !(pos[x] & 1)) continue;
+        const int l = pos[x] >> 1;
+        if ((t.cswap[s] >> l) & 1u)
+          pos[x] = ((l + 1) << 1) | 1;
+        else if (l >= 1 && ((t.cswap[s] >> (l - 1)) & 1u))
+          pos[x] = ((l - 1) << 1) | 1;
+      }
+    }
+    if (t.bus_b[s] >= 0) {
+      const int x = n + t.bus_b[s];
+      if (pos[x] < 0 && !entered[x]) {
+        pos[x] = 1;
+        entered[x] = 1;
+      } else if (pos[x] == 1) {
+        pos[x] = -1;
+      } else {
+        why = "data token not at the root when it leaves";
+        return false;
+      }
+    }
+    for (int l = 0; l < MAXN; ++l) t.tok[s][l][0] = t.tok[s][l][1] = NONE;
+    uint32_t am = 0, dm = 0;
+    int nr = 0;
+    for (int x = 0; x < ntok; ++x) {
+      t.pos[s][x] = pos[x] < 0 ? NONE : (uint8_t)pos[x];
+      if (pos[x] < 0) continue;
+      const int l = pos[x] >> 1, slot = pos[x] & 1;
+      if (l >= n) {
+        why = "token below the leaf layer";
+        return false;
+      }
+      if (t.tok[s][l][slot] != NONE) {
+        why = "two tokens share a site of the path";
+        return false;
+      }
+      t.tok[s][l][slot] = (uint8_t)x;
+      if (x < n) {
+        if (c->enc == QUBIT || slot == 1) am |= 1u << (n - 1 - x);
+        if (c->enc == QUTRIT && slot == 0) ++nr;
+      } else {
+        const int b = x - n;
+        if (c->enc == QUBIT || s >= 3 * n + 2 * b + 1) dm |= 1u << b;
+      }
+    }
+    t.amask[s] = am;
+    t.dmask[s] = dm;
+    t.nrouter[s] = (uint8_t)nr;
+    for (int a = 0; a < n; ++a)
+      t.cntA[s][a] = (uint16_t)(t.cntA[s - 1][a] + ((am >> (n - 1 - a)) & 1u));
+    for (int b = 0; b < k; ++b)
+      t.cntD[s][b] = (uint16_t)(t.cntD[s - 1][b] + ((dm >> b) & 1u));
+  }
+  for (int x = 0; x < ntok; ++x)
+    if (pos[x] >= 0) {
+      why = "a token is still in the tree after the last slice";
+      return false;
+    }
+  for (int s = T; s < MAXT; ++s) {
+    for (int a = 0; a < n; ++a) t.cntA[s][a] = t.cntA[T - 1][a];
+    for (int b = 0; b < k; ++b) t.cntD[s][b] = t.cntD[T - 1][b];
+  }
+  return true;
+}
+
+uint32_t cand_capacity(const qram_ctx *c) {
+  const double S = (double)(c->T - 1) * (double)c->M;
+  const double mean = S * c->gamma;
+  const double sd = std::sqrt(S * c->gamma * (1.0 - c->gamma));
+  double cap = mean + 10.0 * sd + 32.0;
+  if (cap > S) cap = S;
+  uint32_t r = (uint32_t)std::ceil(cap);
+  return std::max<uint32_t>(r, 32u);
+}
+
+int default_threads(const qram_ctx *c, int mode) {
+  // explicit components per trajectory: all of them in full mode; the
+  // expected bad count plus one in pruned mode (Eq. eb) -- a rough guess
+  // that the autotuner replaces
+  const double E = (double)c->Emax;
+  double e = E;
+  if (mode == 1) {
+    const double pbad = std::min(1.0, 2.0 * (c->T - 1) * c->gamma * (c->n + 0.25 * (c->n - 1) * (c->n - 2)));
+    e = std::max(1.0, pbad * E + (c->enc == QUBIT ? c->K2 : 1));
+  }
+  if (e <= 256) return 64;
+  if (e <= 2048) return 128;
+  return 256;
+}
+
+struct Shape {
+  int threads;
+  bool state_lds;
+  uint32_t e_cap;
+  uint32_t lds;
+  uint32_t grid;
+  bool persistent;
+};
+
+Shape make_shape(qram_ctx *c, int mode, uint32_t ntraj) {
+  Shape sh;
+  sh.threads = c->threads[mode] ? c->threads[mode] : default_threads(c, mode);
+  const uint32_t spt = (c->Emax + sh.threads - 1) / sh.threads;
+  sh.e_cap = spt * sh.threads;
+  const uint32_t fixed = evolve_lds_bytes(c->n, c->T, c->M, sh.threads, 0, false);
+  sh.state_lds = fixed + sh.e_cap * 4u <= 80u * 1024u && fixed + sh.e_cap * 4u <= c->lds_max;
+  sh.lds = evolve_lds_bytes(c->n, c->T, c->M, sh.threads, sh.e_cap, sh.state_lds);
+  int occ = evolve_occupancy(c->enc, sh.state_lds, sh.threads, sh.lds);
+  if (occ < 1) occ = 1;
+  uint32_t g = (uint32_t)(c->num_cu * occ);
+  sh.grid = std::max<uint32_t>(1u, std::min<uint32_t>(g, ntraj));
+  sh.persistent = c->schedule[mode] == 1;
+  return sh;
+}
+
+// Grow the per-trajectory buffers to hold `nb` trajectories and the
+// per-workgroup buffers to hold `grid` workgroups.
+qram_status ensure_buffers(qram_ctx *c, uint32_t nb, uint32_t grid, uint32_t e_cap) {
+  qram_status st;
+  if (nb > c->batch_cap || c->cand_cap == 0) {
+    c->cand_cap = cand_capacity(c);
+    if ((st = dev_alloc(c, &c->cand, (size_t)nb * c->cand_cap))) return st;
+    if ((st = dev_alloc(c, &c->ncand, nb))) return st;
+    if ((st = dev_alloc(c, &c->nbad, nb))) return st;
+    if ((st = dev_alloc(c, &c->ref, nb))) return st;
+    if ((st = dev_alloc(c, &c->nexpl, nb))) return st;
+    if ((st = dev_alloc(c, &c->order, nb))) return st;
+    if ((st = dev_alloc(c, &c->digest, nb))) return st;
+    if ((st = dev_alloc(c, &c->badbits, (size_t)nb * ((c->D + 63) / 64)))) return st;
+    if ((st = dev_alloc(c, &c->xlist, (size_t)nb * c->D))) return st;
+    c->batch_cap = nb;
+  }
+  if (!c->counter) {
+    if ((st = dev_alloc(c, &c->counter, 4))) return st;
+    if ((st = dev_alloc(c, &c->errw, 4))) return st;
+    HIPCHK(c, hipMemset(c->errw, 0, 16));
+  }
+  if (grid > c->grid_cap || e_cap > c->ecap_cap) {
+    const uint32_t g = std::max(grid, c->grid_cap);
+    const uint32_t ec = std::max(e_cap, c->ecap_cap);
+    if ((st = dev_alloc(c, &c->gstate, (size_t)g * ec))) return st;
+    if ((st = dev_alloc(c, &c->pool, (size_t)g * c->Emax * c->rec))) return st;
+    c->grid_cap = g;
+    c->ecap_cap = ec;
+  }
+  return QRAM_OK;
+}
+
+uint32_t batch_size(const qram_ctx *c, uint32_t ntraj) {
+  // keep the per-trajectory buffers within about 2 GiB
+  const double per = (double)cand_capacity(c) * 4.0 + (double)c->D * 2.0 +
+                     (double)((c->D + 63) / 64) * 8.0 + 64.0;
+  double nb = (2.0 * 1024 * 1024 * 1024) / per;
+  nb = std::max(256.0, std::min(nb, 262144.0));
+  return std::min<uint32_t>(ntraj, (uint32_t)nb);
+}
+
+Run base_run(qram_ctx *c, int mode, uint64_t seed, const Shape &sh) {
+  Run r{};
+  r.seed = seed;
+  r.mode = mode;
+  r.cand_cap = c->cand_cap;
+  r.e_cap = sh.e_cap;
+  r.grid = sh.grid;
+  r.persistent = sh.persistent ? 1u : 0u;
+  r.state_lds = sh.state_lds ? 1u : 0u;
+  r.lds_bytes = sh.lds;
+  r.cand = c->cand;
+  r.ncand = c->ncand;
+  r.digest = c->digest;
+  r.badbits = c->badbits;
+  r.nbad = c->nbad;
+  r.ref = c->ref;
+  r.xlist = c->xlist;
+  r.nexpl = c->nexpl;
+  r.order = c->order;
+  r.counter = c->counter;
+  r.gstate = c->gstate;
+  r.pool = c->pool;
+  r.err = c->errw;
+  return r;
+}
+
+uint32_t sample_grid(const qram_ctx *c, uint32_t ntraj) {
+  return std::max<uint32_t>(1u, std::min<uint32_t>(ntraj, (uint32_t)c->num_cu * 8u));
+}
+
+// Enqueue sampling (unless forced), classification and evolution of one
+// batch on stream s.  With `timed`, events bracket the three stages.
+qram_status enqueue_batch(qram_ctx *c, int mode, const Shape &sh, Run r,
+                          hipStream_t s, bool timed, bool skip_sample) {
+  const uint32_t nt = r.ntraj;
+  if (timed) HIPCHK(c, hipEventRecord(c->ev[0], s));
+  if (!skip_sample) HIPCHK(c, launch_sample(c->dtab, r, nt, sample_grid(c, nt), s));
+  if (timed) HIPCHK(c, hipEventRecord(c->ev[1], s));
+  HIPCHK(c, launch_classify(c->dtab, r, nt, sample_grid(c, nt), c->D, s));
+  if (sh.persistent) HIPCHK(c, launch_order(c->dtab, r, nt, s));
+  if (timed) HIPCHK(c, hipEventRecord(c->ev[2], s));
+  HIPCHK(c, launch_evolve(c->dtab, r, c->enc, sh.grid, sh.threads, sh.lds, sh.state_lds, s));
+  if (timed) HIPCHK(c, hipEventRecord(c->ev[3], s));
+  (void)mode;
+  return QRAM_OK;
+}
+
+qram_status check_err(qram_ctx *c) {
+  uint32_t e = 0;
+  HIPCHK(c, hipMemcpy(&e, c->errw, 4, hipMemcpyDeviceToHost));
+  if (e) {
+    HIPCHK(c, hipMemset(c->errw, 0, 4));
+    if (e & ERR_CAND) return fail(c, QRAM_E_CAPACITY, "candidate buffer overflow");
+    if (e & ERR_LIST) return fail(c, QRAM_E_CAPACITY, "explicit site list overflow");
+  }
+  return QRAM_OK;
+}
+
+qram_status check_args(qram_ctx *c, uint64_t traj0, uint32_t ntraj) {
+  if (!c) return fail(nullptr, QRAM_E_INVAL, "null context");
+  if (traj0 + (uint64_t)ntraj > (1ull << 32))
+    return fail(c, QRAM_E_RANGE, "traj0 + ntraj exceeds 2^32");
+  HIPCHK(c, hipSetDevice(c->device));
+  return QRAM_OK;
+}
+
+qram_status ensure_out(qram_ctx *c, uint32_t nb) {
+  if (nb > c->out_cap) {
+    qram_status st;
+    if ((st = dev_alloc(c, &c->fid_tmp, nb))) return st;
+    if ((st = dev_alloc(c, &c->st_tmp, nb))) return st;
+    c->out_cap = nb;
+  }
+  return QRAM_OK;
+}
+
+// Runs trajectories [traj0, traj0+ntraj) in batches.  Outputs go to device
+// arrays d_fid/d_st (async) or through the context's staging buffers to host
+// arrays h_fid/h_st (sync).
+qram_status run_mode(qram_ctx *c, int mode, uint64_t seed, uint64_t traj0,
+                     uint32_t ntraj, double *d_fid, qram_traj_stats *d_st,
+                     double *h_fid, qram_traj_stats *h_st, hipStream_t s,
+                     bool sync) {
+  qram_status st = check_args(c, traj0, ntraj);
+  if (st) return st;
+  if (ntraj == 0) return QRAM_OK;
+  const uint32_t nb = batch_size(c, ntraj);
+  const Shape sh = make_shape(c, mode, nb);
+  if ((st = ensure_buffers(c, nb, sh.grid, sh.e_cap))) return st;
+  if (sync && (st = ensure_out(c, nb))) return st;
+  const bool timed = sync && ntraj <= nb;
+  for (uint32_t b0 = 0; b0 < ntraj; b0 += nb) {
+    const uint32_t cnt = std::min(nb, ntraj - b0);
+    Run r = base_run(c, mode, seed, sh);
+    r.traj0 = (uint32_t)(traj0 + b0);
+    r.ntraj = cnt;
+    r.fid = sync ? c->fid_tmp : d_fid + b0;
+    r.st = sync ? (h_st ? c->st_tmp : nullptr) : (d_st ? d_st + b0 : nullptr);
+    if ((st = enqueue_batch(c, mode, sh, r, s, timed, false))) return st;
+    if (sync) {
+      HIPCHK(c, hipMemcpyAsync(h_fid + b0, c->fid_tmp, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+      if (h_st)
+        HIPCHK(c, hipMemcpyAsync(h_st + b0, c->st_tmp, cnt * sizeof(qram_traj_stats), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+    }
+  }
+  if (sync) {
+    if (timed) {
+      float ms;
+      for (int i = 0; i < 3; ++i) {
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+        c->last_ms[i] = ms;
+      }
+    }
+    return check_err(c);
+  }
+  return QRAM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
+                        const uint32_t *memory_bits, qram_ctx **out) {
+  if (!out || !memory_bits) return fail(nullptr, QRAM_E_INVAL, "null argument");
+  *out = nullptr;
+  if (enc != QRAM_QUBIT && enc != QRAM_QUTRIT) return fail(nullptr, QRAM_E_INVAL, "unknown encoding");
+  if (!(gamma >= 0.0 && gamma < 1.0)) return fail(nullptr, QRAM_E_INVAL, "gamma must lie in [0, 1)");
+  const int nmax = enc == QRAM_QUTRIT ? 14 : 15;
+  if (n_addr < 1 || n_addr > nmax) return fail(nullptr, QRAM_E_RANGE, "n_addr out of range");
+  if (k_data < 1 || k_data > 8 || k_data > n_addr) return fail(nullptr, QRAM_E_RANGE, "k_data out of range (1..8, k <= n)");
+  qram_ctx *c = new (std::nothrow) qram_ctx();
+  if (!c) return fail(nullptr, QRAM_E_NOMEM, "host allocation failed");
+  c->n = n_addr;
+  c->k = k_data;
+  c->enc = enc == QRAM_QUBIT ? QUBIT : QUTRIT;
+  c->gamma = gamma;
+  c->T = 6 * n_addr + 2 * k_data;
+  c->M = 2 * ((1 << n_addr) - 1);
+  c->D = 1 << n_addr;
+  c->K2 = c->enc == QUBIT ? (1 << k_data) : 1;
+  c->Emax = c->D * c->K2;
+  // excitations per component: the CNOT copies are the only gates that
+  // create them in the qubit circuit (<= 2n, plus k bus bits); the qutrit
+  // circuit adds at most one router per store/unstore and one per fetch
+  c->lmax = c->enc == QUBIT ? 2 * n_addr + k_data : 4 * n_addr + k_data;
+  c->emax = (c->T - 1) * c->lmax;
+  c->rec = c->lmax + 2;
+  const double lw = c->emax * std::log(1.0 - gamma);
+  if (lw < -690.0) {
+    delete c;
+    return fail(nullptr, QRAM_E_RANGE, "gamma too large: damping weights underflow double precision");
+  }
+  c->mem.assign(memory_bits, memory_bits + c->D);
+  for (auto &m : c->mem) m &= (1u << k_data) - 1u;
+  std::string why;
+  if (!build_tables(c, why)) {
+    delete c;
+    return fail(nullptr, QRAM_E_INVAL, "schedule: " + why);
+  }
+  auto bail = [&](qram_status st) {
+    std::string m = c->err;
+    qram_destroy(c);
+    return fail(nullptr, st, m);
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(c, QRAM_E_DEVICE, "no HIP device"));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return bail(fail(c, QRAM_E_DEVICE, "hipGetDeviceProperties failed"));
+  c->num_cu = prop.multiProcessorCount;
+  c->lds_max = prop.sharedMemPerBlock;
+  if (evolve_prepare((int)c->lds_max) != hipSuccess) {
+    (void)hipGetLastError();
+    c->lds_max = std::min<size_t>(c->lds_max, 64 * 1024);
+  }
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return bail(fail(c, QRAM_E_DEVICE, "stream creation failed"));
+  for (auto &e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) return bail(fail(c, QRAM_E_DEVICE, "event creation failed"));
+  qram_status st;
+  if ((st = dev_alloc(c, &c->dmem, c->D))) return bail(st);
+  std::vector<double> wp(2 * c->emax + 1), ap(2 * c->emax + 1);
+  const double a = std::sqrt(1.0 - gamma);
+  for (int m = 0; m <= 2 * c->emax; ++m) {
+    wp[m] = std::pow(1.0 - gamma, (double)(m - c->emax));
+    ap[m] = std::pow(a, (double)(m - c->emax));
+  }
+  if ((st = dev_alloc(c, &c->dwpow, wp.size()))) return bail(st);
+  if ((st = dev_alloc(c, &c->dapow, ap.size()))) return bail(st);
+  if ((st = dev_alloc(c, &c->dtab, 1))) return bail(st);
+  c->htab.mem = c->dmem;
+  c->htab.wpow = c->dwpow;
+  c->htab.apow = c->dapow;
+  if (hipMemcpy(c->dmem, c->mem.data(), c->D * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->dwpow, wp.data(), wp.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->dapow, ap.data(), ap.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->dtab, &c->htab, sizeof(Tables), hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(c, QRAM_E_DEVICE, "table upload failed"));
+  *out = c;
+  return QRAM_OK;
+}
+
+void qram_destroy(qram_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  dev_free(&c->dtab);
+  dev_free(&c->dmem);
+  dev_free(&c->dwpow);
+  dev_free(&c->dapow);
+  dev_free(&c->cand);
+  dev_free(&c->ncand);
+  dev_free(&c->nbad);
+  dev_free(&c->ref);
+  dev_free(&c->nexpl);
+  dev_free(&c->order);
+  dev_free(&c->counter);
+  dev_free(&c->errw);
+  dev_free(&c->badbits);
+  dev_free(&c->digest);
+  dev_free(&c->xlist);
+  dev_free(&c->pool);
+  dev_free(&c->gstate);
+  dev_free(&c->fid_tmp);
+  dev_free(&c->st_tmp);
+  dev_free(&c->uaux);
+  for (auto &e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char *qram_last_error(const qram_ctx *c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+qram_status qram_sample_faults(qram_ctx *c, uint64_t seed, uint64_t traj0,
+                               uint32_t ntraj, uint32_t *n_cand,
+                               uint64_t *cand_digest, uint32_t *n_bad,
+                               uint64_t *bad_bits, uint32_t *cand_L,
+                               uint64_t cand_cap) {
+  qram_status st = check_args(c, traj0, ntraj);
+  if (st) return st;
+  if (!n_cand) return fail(c, QRAM_E_INVAL, "n_cand is required");
+  if (ntraj == 0) return QRAM_OK;
+  const uint32_t nb = batch_size(c, ntraj);
+  const Shape sh = make_shape(c, 0, nb);
+  if ((st = ensure_buffers(c, nb, sh.grid, sh.e_cap))) return st;
+  const int w64 = (c->D + 63) / 64;
+  uint64_t written = 0;
+  bool overflow = false;
+  std::vector<uint32_t> hc;
+  for (uint32_t b0 = 0; b0 < ntraj; b0 += nb) {
+    const uint32_t cnt = std::min(nb, ntraj - b0);
+    Run r = base_run(c, 0, seed, sh);
+    r.traj0 = (uint32_t)(traj0 + b0);
+    r.ntraj = cnt;
+    HIPCHK(c, launch_sample(c->dtab, r, cnt, sample_grid(c, cnt), c->stream));
+    HIPCHK(c, launch_classify(c->dtab, r, cnt, sample_grid(c, cnt), c->D, c->stream));
+    HIPCHK(c, launch_digest(r, cnt, c->stream));
+    HIPCHK(c, hipMemcpyAsync(n_cand + b0, c->ncand, cnt * 4, hipMemcpyDeviceToHost, c->stream));
+    if (cand_digest) HIPCHK(c, hipMemcpyAsync(cand_digest + b0, c->digest, cnt * 8, hipMemcpyDeviceToHost, c->stream));
+    if (n_bad) HIPCHK(c, hipMemcpyAsync(n_bad + b0, c->nbad, cnt * 4, hipMemcpyDeviceToHost, c->stream));
+    if (bad_bits)
+      HIPCHK(c, hipMemcpyAsync(bad_bits + (size_t)b0 * w64, c->badbits, (size_t)cnt * w64 * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (cand_L && !overflow) {
+      uint64_t need = written;
+      for (uint32_t t = 0; t < cnt; ++t) need += std::min(n_cand[b0 + t], c->cand_cap);
+      if (need > cand_cap) {
+        overflow = true;
+      } else {
+        hc.resize((size_t)cnt * c->cand_cap);
+        HIPCHK(c, hipMemcpy(hc.data(), c->cand, hc.size() * 4, hipMemcpyDeviceToHost));
+        for (uint32_t t = 0; t < cnt; ++t) {
+          const uint32_t m = std::min(n_cand[b0 + t], c->cand_cap);
+          std::memcpy(cand_L + written, hc.data() + (size_t)t * c->cand_cap, m * 4);
+          written += m;
+        }
+      }
+    }
+  }
+  if ((st = check_err(c))) return st;
+  if (overflow) return fail(c, QRAM_E_CAPACITY, "cand_L too small for the candidate dump");
+  return QRAM_OK;
+}
+
+qram_status qram_run_full(qram_ctx *c, uint64_t seed, uint64_t traj0,
+                          uint32_t ntraj, double *fid, qram_traj_stats *st) {
+  if (!fid) return fail(c, QRAM_E_INVAL, "fid is required");
+  return run_mode(c, 0, seed, traj0, ntraj, nullptr, nullptr, fid, st, c ? c->stream : nullptr, true);
+}
+
+qram_status qram_run_pruned(qram_ctx *c, uint64_t seed, uint64_t traj0,
+                            uint32_t ntraj, double *fid, qram_traj_stats *st) {
+  if (!fid) return fail(c, QRAM_E_INVAL, "fid is required");
+  return run_mode(c, 1, seed, traj0, ntraj, nullptr, nullptr, fid, st, c ? c->stream : nullptr, true);
+}
+
+qram_status qram_run_full_async(qram_ctx *c, uint64_t seed, uint64_t traj0,
+                                uint32_t ntraj, double *d_fid,
+                                qram_traj_stats *d_st, void *stream) {
+  if (!d_fid) return fail(c, QRAM_E_INVAL, "d_fid is required");
+  return run_mode(c, 0, seed, traj0, ntraj, d_fid, d_st, nullptr, nullptr, (hipStream_t)stream, false);
+}
+
+qram_status qram_run_pruned_async(qram_ctx *c, uint64_t seed, uint64_t traj0,
+                                  uint32_t ntraj, double *d_fid,
+                                  qram_traj_stats *d_st, void *stream) {
+  if (!d_fid) return fail(c, QRAM_E_INVAL, "d_fid is required");
+  return run_mode(c, 1, seed, traj0, ntraj, d_fid, d_st, nullptr, nullptr, (hipStream_t)stream, false);
+}
+
+qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,
+                          double *sem) {
+  if (!fid || !mean) return QRAM_E_INVAL;
+  if (ntraj == 0) {
+    *mean = 0.0;
+    if (sem) *sem = 0.0;
+    return QRAM_OK;
+  }
+  double m = 0.0;
+  for (uint32_t i = 0; i < ntraj; ++i) m += fid[i];
+  m /= ntraj;
+  double v = 0.0;
+  for (uint32_t i = 0; i < ntraj; ++i) v += (fid[i] - m) * (fid[i] - m);
+  *mean = m;
+  if (sem) *sem = ntraj > 1 ? std::sqrt(v / (ntraj - 1) / ntraj) : 0.0;
+  return QRAM_OK;
+}
+
+qram_status qram_set_launch(qram_ctx *c, qram_mode mode, int threads,
+                            int schedule) {
+  if (!c) return QRAM_E_INVAL;
+  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return fail(c, QRAM_E_INVAL, "bad mode");
+  if (threads != 0 && threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
+    return fail(c, QRAM_E_INVAL, "threads must be 64, 128, 256, 512 or 1024");
+  if (schedule != 0 && schedule != 1) return fail(c, QRAM_E_INVAL, "schedule must be 0 or 1");
+  c->threads[mode] = threads;
+  c->schedule[mode] = schedule;
+  c->user_shape[mode] = threads != 0;
+  return QRAM_OK;
+}
+
+qram_status qram_get_launch(const qram_ctx *c, qram_mode mode, int *threads,
+                            int *schedule) {
+  if (!c || !threads || !schedule) return QRAM_E_INVAL;
+  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return QRAM_E_INVAL;
+  *threads = c->threads[mode] ? c->threads[mode] : default_threads(c, mode);
+  *schedule = c->schedule[mode];
+  return QRAM_OK;
+}
+
+qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
+                          uint64_t traj0, uint32_t ntraj, double *best_ms) {
+  qram_status st = check_args(c, traj0, ntraj);
+  if (st) return st;
+  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return fail(c, QRAM_E_INVAL, "bad mode");
+  if (ntraj == 0) return fail(c, QRAM_E_INVAL, "ntraj must be positive");
+  const uint32_t nt = std::min(ntraj, batch_size(c, ntraj));
+  if ((st = ensure_out(c, nt))) return st;
+  const int cand_threads[5] = {64, 128, 256, 512, 1024};
+  double best = 1e300;
+  int bt = 0, bs = 1;
+  const int save_t = c->threads[mode], save_s = c->schedule[mode];
+  bool sampled = false;
+  for (int sched = 0; sched < 2; ++sched) {
+    for (int ti = 0; ti < 5; ++ti) {
+      c->threads[mode] = cand_threads[ti];
+      c->schedule[mode] = sched;
+      const Shape sh = make_shape(c, mode, nt);
+      if (sh.lds > c->lds_max) continue;
+      if ((st = ensure_buffers(c, nt, sh.grid, sh.e_cap))) return st;
+      Run r = base_run(c, mode, seed, sh);
+      r.traj0 = (uint32_t)traj0;
+      r.ntraj = nt;
+      r.fid = c->fid_tmp;
+      r.st = nullptr;
+      if (!sampled) {
+        HIPCHK(c, launch_sample(c->dtab, r, nt, sample_grid(c, nt), c->stream));
+        sampled = true;
+      }
+      double t_best = 1e300;
+      for (int rep = 0; rep < 2; ++rep) {
+        HIPCHK(c, launch_classify(c->dtab, r, nt, sample_grid(c, nt), c->D, c->stream));
+        if (sh.persistent) HIPCHK(c, launch_order(c->dtab, r, nt, c->stream));
+        HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+        HIPCHK(c, launch_evolve(c->dtab, r, c->enc, sh.grid, sh.threads, sh.lds, sh.state_lds, c->stream));
+        HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+        HIPCHK(c, hipEventSynchronize(c->ev[1]));
+        float ms;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+        t_best = std::min(t_best, (double)ms);
+      }
+      if (t_best < best) {
+        best = t_best;
+        bt = cand_threads[ti];
+        bs = sched;
+      }
+    }
+  }
+  (void)save_t;
+  (void)save_s;
+  c->threads[mode] = bt;
+  c->schedule[mode] = bs;
+  c->user_shape[mode] = true;
+  if (best_ms) *best_ms = best;
+  return check_err(c);
+}
+
+qram_status qram_last_kernel_ms(const qram_ctx *c, double *times) {
+  if (!c || !times) return QRAM_E_INVAL;
+  for (int i = 0; i < 3; ++i) times[i] = c->last_ms[i];
+  return QRAM_OK;
+}
+
+qram_status qram_run_forced(qram_ctx *c, qram_mode mode, const uint32_t *cand_L,
+                            uint32_t ncand, const double *u_aux, double u_fin,
+                            double *fid, qram_traj_stats *stt) {
+  qram_status st = check_args(c, 0, 1);
+  if (st) return st;
+  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return fail(c, QRAM_E_INVAL, "bad mode");
+  if (!fid || !u_aux || (ncand && !cand_L)) return fail(c, QRAM_E_INVAL, "null argument");
+  const uint64_t S = (uint64_t)(c->T - 1) * c->M;
+  for (uint32_t j = 0; j < ncand; ++j) {
+    if (cand_L[j] >= S) return fail(c, QRAM_E_INVAL, "candidate index out of range");
+    if (j && cand_L[j] <= cand_L[j - 1]) return fail(c, QRAM_E_INVAL, "candidates must be strictly ascending");
+  }
+  const Shape sh0 = make_shape(c, mode, 1);
+  if ((st = ensure_buffers(c, 1, sh0.grid, sh0.e_cap))) return st;
+  if (ncand > c->cand_cap) {
+    c->batch_cap = 0;  // regrow with a larger candidate capacity
+    const uint32_t need = ncand;
+    if ((st = dev_alloc(c, &c->cand, need))) return st;
+    c->cand_cap = need;
+    c->batch_cap = 1;
+  }
+  if ((st = ensure_out(c, 1))) return st;
+  if (!c->uaux)
+    if ((st = dev_alloc(c, &c->uaux, MAXT))) return st;
+  std::vector<double> ua(MAXT, 0.0);
+  for (int s = 0; s < c->T; ++s) ua[s] = u_aux[s];
+  HIPCHK(c, hipMemcpy(c->uaux, ua.data(), MAXT * 8, hipMemcpyHostToDevice));
+  if (ncand) HIPCHK(c, hipMemcpy(c->cand, cand_L, ncand * 4, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->ncand, &ncand, 4, hipMemcpyHostToDevice));
+  Shape sh = sh0;
+  Run r = base_run(c, mode, 0, sh);
+  r.traj0 = 0;
+  r.ntraj = 1;
+  r.forced = 1;
+  r.uaux = c->uaux;
+  r.ufin = u_fin;
+  r.fid = c->fid_tmp;
+  r.st = c->st_tmp;
+  if ((st = enqueue_batch(c, mode, sh, r, c->stream, false, true))) return st;
+  HIPCHK(c, hipMemcpyAsync(fid, c->fid_tmp, 8, hipMemcpyDeviceToHost, c->stream));
+  if (stt) HIPCHK(c, hipMemcpyAsync(stt, c->st_tmp, sizeof(qram_traj_stats), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return check_err(c);
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Internal declarations shared by the host code and the kernels of the HIP
+// library.  Nothing here is visible through the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/qram.h"
+
+namespace qr {
+
+constexpr int MAXN = 15;
+constexpr int MAXK = 8;
+constexpr int MAXT = 6 * MAXN + 2 * MAXK + 1;  // slices 0..T
+constexpr uint8_t NONE = 0xFF;
+constexpr int NCS = 16;    // a slice with at most NCS candidates is scanned as a list
+constexpr int JMAX = 64;   // joint outcome capacity (|J| <= excitations of one component)
+constexpr int QUTRIT = 0;
+constexpr int QUBIT = 1;
+
+// Tier-1 state word of an explicit component (address and initial bus word
+// are implied by its slot):
+//   bits  0..15 exposure e (excited sites summed over slices, K0 factors)
+//   bits 16..23 live data tokens (qubit: bus bits still carried; qutrit:
+//               data bits not yet lost)
+//   bit 24 sign, bit 25 alive, bit 26 deviated (site list in the pool)
+constexpr uint32_t W_E = 0xFFFFu;
+constexpr int W_LIVE_SH = 16;
+constexpr uint32_t W_SIGN = 1u << 24;
+constexpr uint32_t W_ALIVE = 1u << 25;
+constexpr uint32_t W_DEV = 1u << 26;
+
+// Tier-2 record in the pool: [0] count, [1] bus word, [2..] excited sites.
+// Qutrit router sites carry their level in bit 15 (set: R, clear: L).
+constexpr uint16_t LV_R_BIT = 0x8000u;
+
+struct Tables {
+  int n, k, enc, T, M, D, K2, lmax, emax, rec;  // rec = pool record length
+  uint64_t G[64];                 // geometric-walk thresholds
+  const uint32_t *mem;            // [D] memory words
+  const double *wpow;             // [2 emax + 1] (1-gamma)^(m - emax)
+  const double *apow;             // [2 emax + 1] a^(m - emax)
+  uint32_t amask[MAXT];  // address tokens excitable after the gates of s (bit n-1-t)
+  uint32_t dmask[MAXT];  // data tokens excitable after the gates of s (bit b)
+  uint32_t cswap[MAXT];  // layers whose controlled swap fires at s
+  uint8_t nrouter[MAXT]; // qutrit: stored routers at s (always excited)
+  int8_t copy_t[MAXT], store_l[MAXT], bus_b[MAXT], fetch_b[MAXT];
+  uint8_t tok[MAXT][MAXN][2];      // token at (layer, slot) of the path at s
+  uint8_t pos[MAXT][MAXN + MAXK];  // layer << 1 | slot of each token at s
+  uint16_t cntA[MAXT][MAXN];       // exposure of address token t through s
+  uint16_t cntD[MAXT][MAXK];       // exposure of data token b through s
+};
+
+struct Run {
+  uint64_t seed;
+  uint32_t traj0, ntraj;
+  int mode;              // 0 full, 1 pruned
+  uint32_t cand_cap;     // candidate slots per trajectory
+  uint32_t e_cap;        // explicit component slots per trajectory
+  uint32_t grid;         // workgroups of the evolution launch
+  uint32_t persistent;   // 1: dynamic queue over `order`
+  uint32_t state_lds;    // 1: tier-1 words live in LDS
+  uint32_t lds_bytes;    // dynamic LDS of the evolution kernel
+  uint32_t forced;       // 1: forced history (single trajectory)
+  uint32_t *cand;        // [ntraj * cand_cap] ascending L
+  uint32_t *ncand;       // [ntraj]
+  uint64_t *digest;      // [ntraj]
+  uint64_t *badbits;     // [ntraj * words64]
+  uint32_t *nbad;        // [ntraj]
+  uint32_t *ref;         // [ntraj]
+  uint16_t *xlist;       // [ntraj * D] explicit addresses (pruned)
+  uint32_t *nexpl;       // [ntraj] explicit components
+  uint32_t *order;       // [ntraj] processing order
+  uint32_t *counter;     // [4] queue head and scratch
+  uint32_t *gstate;      // [grid * e_cap] tier-1 words when not in LDS
+  uint16_t *pool;        // [grid * e_cap * rec] tier-2 records
+  double *fid;           // [ntraj]
+  qram_traj_stats *st;   // [ntraj] or null
+  uint32_t *err;         // [1] error bits
+  const double *uaux;    // forced auxiliary uniforms [T]
+  double ufin;           // forced final uniform
+};
+
+constexpr uint32_t ERR_CAND = 1u;
+constexpr uint32_t ERR_LIST = 2u;
+
+// Kernel launchers (qram_kernels.hip).
+hipError_t launch_sample(const Tables *tb, const Run &rp, uint32_t ntraj,
+                         uint32_t grid, hipStream_t s);
+hipError_t launch_classify(const Tables *tb, const Run &rp, uint32_t ntraj,
+                           uint32_t grid, int D, hipStream_t s);
+hipError_t launch_order(const Tables *tb, const Run &rp, uint32_t ntraj,
+                        hipStream_t s);
+hipError_t launch_evolve(const Tables *tb, const Run &rp, int enc,
+                         uint32_t grid, int threads, uint32_t lds_bytes,
+                         bool state_lds, hipStream_t s);
+hipError_t launch_digest(const Run &rp, uint32_t ntraj, hipStream_t s);
+
+uint32_t evolve_lds_bytes(int n, int T, int M, int threads, uint32_t e_cap,
+                          bool state_lds);
+int evolve_occupancy(int enc, bool state_lds, int threads, uint32_t lds_bytes);
+hipError_t evolve_prepare(int lds_max);
+
+}  // namespace qr

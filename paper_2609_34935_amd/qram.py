@@ -1,0 +1,219 @@
+"""Python binding of the C ABI in include/qram.h (argument marshalling only).
+
+Every step of a trajectory runs in the HIP library ``libqram_hip.so``; this
+module loads it with ctypes and fails loudly when it is missing.  PyTorch is
+used only for device buffers and streams in the ``*_async`` calls.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqram_hip.so")
+
+QRAM_QUTRIT, QRAM_QUBIT = 0, 1
+QRAM_MODE_FULL, QRAM_MODE_PRUNED = 0, 1
+STATUS = {0: "QRAM_OK", -1: "QRAM_E_INVAL", -2: "QRAM_E_NOMEM", -3: "QRAM_E_DEVICE",
+          -4: "QRAM_E_RANGE", -5: "QRAM_E_CAPACITY"}
+
+STATS_DTYPE = np.dtype([
+    ("n_cand", "<u4"), ("n_bad", "<u4"), ("ref_addr", "<u4"), ("n_explicit", "<u4"),
+    ("n_jumps", "<u2"), ("first_jump_slice", "<u2"), ("ref_survived", "u1"),
+    ("q_ground", "u1"), ("flags", "u1"), ("pad", "u1"), ("fid_pre", "<f8")])
+assert STATS_DTYPE.itemsize == 32
+
+# Every entry point declared in include/qram.h.
+EXPORTS = [
+    "qram_create", "qram_destroy", "qram_last_error", "qram_sample_faults",
+    "qram_run_full", "qram_run_pruned", "qram_run_full_async", "qram_run_pruned_async",
+    "qram_fidelity", "qram_set_launch", "qram_get_launch", "qram_autotune",
+    "qram_last_kernel_ms", "qram_run_forced",
+]
+
+
+class QramError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"HIP library not found at {path}; build it with "
+            "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(path)
+    vp, u32, u64, f64 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_double
+    p = C.POINTER
+    L.qram_create.argtypes = [C.c_int, C.c_int, C.c_int, f64, p(u32), p(vp)]
+    L.qram_create.restype = C.c_int
+    L.qram_destroy.argtypes = [vp]
+    L.qram_destroy.restype = None
+    L.qram_last_error.argtypes = [vp]
+    L.qram_last_error.restype = C.c_char_p
+    L.qram_sample_faults.argtypes = [vp, u64, u64, u32, p(u32), p(u64), p(u32), p(u64), p(u32), u64]
+    for f in (L.qram_run_full, L.qram_run_pruned):
+        f.argtypes = [vp, u64, u64, u32, p(f64), vp]
+    for f in (L.qram_run_full_async, L.qram_run_pruned_async):
+        f.argtypes = [vp, u64, u64, u32, vp, vp, vp]
+    L.qram_fidelity.argtypes = [p(f64), u32, p(f64), p(f64)]
+    L.qram_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+    L.qram_get_launch.argtypes = [vp, C.c_int, p(C.c_int), p(C.c_int)]
+    L.qram_autotune.argtypes = [vp, C.c_int, u64, u64, u32, p(f64)]
+    L.qram_last_kernel_ms.argtypes = [vp, p(f64)]
+    L.qram_run_forced.argtypes = [vp, C.c_int, p(u32), u32, p(f64), f64, p(f64), vp]
+    for name in EXPORTS:
+        if name not in ("qram_destroy", "qram_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _ptr(a, ct):
+    return None if a is None else a.ctypes.data_as(C.POINTER(ct))
+
+
+def qram_fidelity(fid):
+    """Mean and standard error of the mean of per-trajectory fidelities."""
+    L = load_library()
+    f = np.ascontiguousarray(fid, dtype=np.float64)
+    m, s = C.c_double(), C.c_double()
+    st = L.qram_fidelity(_ptr(f, C.c_double), len(f), C.byref(m), C.byref(s))
+    if st:
+        raise QramError(st, "qram_fidelity")
+    return m.value, s.value
+
+
+class QramContext:
+    """One (n, k, encoding, gamma, memory) simulator context on the current
+    HIP device (``qram_create`` ... ``qram_destroy``)."""
+
+    def __init__(self, n_addr, k_data, encoding, gamma, memory_bits):
+        L = load_library()
+        self.n, self.k, self.enc, self.gamma = int(n_addr), int(k_data), int(encoding), float(gamma)
+        self.T = 6 * self.n + 2 * self.k
+        self.M = 2 * ((1 << self.n) - 1)
+        self.D = 1 << self.n
+        mem = np.ascontiguousarray(memory_bits, dtype=np.uint32)
+        if mem.shape != (self.D,):
+            raise ValueError(f"memory_bits must hold 2^n = {self.D} words")
+        h = C.c_void_p()
+        st = L.qram_create(self.n, self.k, self.enc, self.gamma, _ptr(mem, C.c_uint32), C.byref(h))
+        if st:
+            raise QramError(st, L.qram_last_error(None).decode())
+        self._h = h
+        self._L = L
+
+    def _check(self, st, what):
+        if st:
+            raise QramError(st, f"{what}: {self._L.qram_last_error(self._h).decode()}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.qram_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---- entry points -------------------------------------------------
+    def sample_faults(self, seed, traj0, ntraj, dump=False, dump_cap=None):
+        w64 = (self.D + 63) // 64
+        n_cand = np.zeros(ntraj, dtype=np.uint32)
+        dig = np.zeros(ntraj, dtype=np.uint64)
+        n_bad = np.zeros(ntraj, dtype=np.uint32)
+        bits = np.zeros(ntraj * w64, dtype=np.uint64)
+        cap = 0
+        buf = None
+        if dump:
+            cap = dump_cap if dump_cap is not None else max(1, int(ntraj * (self.M * (self.T - 1) * self.gamma + 64 + 10 * np.sqrt(self.M * self.T * self.gamma + 1))))
+            buf = np.zeros(cap, dtype=np.uint32)
+        st = self._L.qram_sample_faults(
+            self._h, seed, traj0, ntraj, _ptr(n_cand, C.c_uint32), _ptr(dig, C.c_uint64),
+            _ptr(n_bad, C.c_uint32), _ptr(bits, C.c_uint64), _ptr(buf, C.c_uint32), cap)
+        self._check(st, "qram_sample_faults")
+        out = dict(n_cand=n_cand, digest=dig, n_bad=n_bad, bad_bits=bits.reshape(ntraj, w64))
+        if dump:
+            offs = np.concatenate([[0], np.cumsum(n_cand.astype(np.int64))])
+            out["cand_L"] = [buf[offs[t]:offs[t + 1]].copy() for t in range(ntraj)]
+        return out
+
+    def _run(self, fn, seed, traj0, ntraj, stats):
+        fid = np.zeros(ntraj, dtype=np.float64)
+        st_arr = np.zeros(ntraj, dtype=STATS_DTYPE) if stats else None
+        st = fn(self._h, seed, traj0, ntraj, _ptr(fid, C.c_double),
+                None if st_arr is None else st_arr.ctypes.data_as(C.c_void_p))
+        self._check(st, fn.__name__)
+        return (fid, st_arr) if stats else fid
+
+    def run_full(self, seed, traj0, ntraj, stats=True):
+        return self._run(self._L.qram_run_full, seed, traj0, ntraj, stats)
+
+    def run_pruned(self, seed, traj0, ntraj, stats=True):
+        return self._run(self._L.qram_run_pruned, seed, traj0, ntraj, stats)
+
+    def _run_async(self, fn, seed, traj0, ntraj, d_fid, d_st, stream):
+        """d_fid: device tensor of ntraj float64; d_st: device uint8 tensor of
+        ntraj*32 bytes or None; stream: torch.cuda.Stream, raw handle or None."""
+        if hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
+        st = fn(self._h, seed, traj0, ntraj, C.c_void_p(d_fid.data_ptr()),
+                None if d_st is None else C.c_void_p(d_st.data_ptr()),
+                None if stream is None else C.c_void_p(int(stream)))
+        self._check(st, fn.__name__)
+
+    def run_full_async(self, seed, traj0, ntraj, d_fid, d_st=None, stream=None):
+        self._run_async(self._L.qram_run_full_async, seed, traj0, ntraj, d_fid, d_st, stream)
+
+    def run_pruned_async(self, seed, traj0, ntraj, d_fid, d_st=None, stream=None):
+        self._run_async(self._L.qram_run_pruned_async, seed, traj0, ntraj, d_fid, d_st, stream)
+
+    def run_forced(self, mode, cand_L, u_aux, u_fin):
+        L = np.ascontiguousarray(cand_L, dtype=np.uint32)
+        ua = np.ascontiguousarray(u_aux, dtype=np.float64)
+        if len(ua) < self.T:
+            raise ValueError("u_aux needs T entries (index = slice)")
+        fid = C.c_double()
+        st_arr = np.zeros(1, dtype=STATS_DTYPE)
+        st = self._L.qram_run_forced(self._h, mode, _ptr(L, C.c_uint32) if len(L) else None, len(L),
+                                     _ptr(ua, C.c_double), float(u_fin), C.byref(fid),
+                                     st_arr.ctypes.data_as(C.c_void_p))
+        self._check(st, "qram_run_forced")
+        return fid.value, st_arr[0]
+
+    def set_launch(self, mode, threads, schedule):
+        self._check(self._L.qram_set_launch(self._h, mode, threads, schedule), "qram_set_launch")
+
+    def get_launch(self, mode):
+        t, s = C.c_int(), C.c_int()
+        self._check(self._L.qram_get_launch(self._h, mode, C.byref(t), C.byref(s)), "qram_get_launch")
+        return t.value, s.value
+
+    def autotune(self, mode, seed, traj0, ntraj):
+        ms = C.c_double()
+        self._check(self._L.qram_autotune(self._h, mode, seed, traj0, ntraj, C.byref(ms)), "qram_autotune")
+        return ms.value
+
+    def last_kernel_ms(self):
+        t = np.zeros(3)
+        self._check(self._L.qram_last_kernel_ms(self._h, _ptr(t, C.c_double)), "qram_last_kernel_ms")
+        return t

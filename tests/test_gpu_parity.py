@@ -1,0 +1,276 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: candidate histories and branch classification bit-exact; fidelity within
+1e-12 relative per trajectory (absolute 1e-15 when F < 1e-3, the value 0 after
+a non-ground tree measurement included); integer statistics identical."""
+import numpy as np
+import pytest
+
+from paper_2609_34935_amd.inputs import memory_words
+
+pytestmark = pytest.mark.gpu
+
+QUTRIT, QUBIT = 0, 1
+FULL, PRUNED = 0, 1
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_34935_amd as P
+    P.load_library()
+    return P
+
+
+def fid_close(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b) <= 1e-12 * np.maximum(np.abs(b), 1e-3)
+
+
+def oracle_ref(ri):
+    r = ri[:, 2].astype(np.int64)
+    return np.where(r < 0, 0xFFFFFFFF, r).astype(np.uint32)
+
+
+def compare_runs(P, orc, n, k, enc, gamma, mem, seed, traj0, ntraj, threads=None):
+    fo, fpo, so, _ = orc.run_batch(n, k, enc, gamma, mem, seed, traj0, ntraj)
+    with P.QramContext(n, k, enc, gamma, mem) as ctx:
+        out = {}
+        for mode, fn in ((FULL, ctx.run_full), (PRUNED, ctx.run_pruned)):
+            if threads:
+                ctx.set_launch(mode, threads[0], threads[1])
+            f, st = fn(seed, traj0, ntraj)
+            bad = np.nonzero(~fid_close(f, fo))[0]
+            assert len(bad) == 0, (mode, bad[:5], f[bad[:5]], fo[bad[:5]], st[bad[:5]])
+            assert np.all(fid_close(st["fid_pre"], fpo)), mode
+            assert np.array_equal(st["n_cand"], so[:, 0].astype(np.uint32))
+            assert np.array_equal(st["n_bad"], so[:, 1].astype(np.uint32))
+            assert np.array_equal(st["ref_addr"], oracle_ref(so))
+            assert np.array_equal(st["n_jumps"], so[:, 4].astype(np.uint16))
+            assert np.array_equal(st["first_jump_slice"], so[:, 5].astype(np.uint16))
+            assert np.array_equal(st["ref_survived"], so[:, 6].astype(np.uint8))
+            assert np.array_equal(st["q_ground"], so[:, 7].astype(np.uint8))
+            out[mode] = (f, st)
+    ff, fp = out[FULL][0], out[PRUNED][0]
+    assert np.all(fid_close(fp, ff))
+    return out, (fo, fpo, so)
+
+
+# ---------------------------------------------------------------------------
+# candidate histories and classification: bit-exact
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,k,enc,gamma,ntraj", [
+    (3, 1, QUTRIT, 1e-3, 300), (3, 1, QUBIT, 0.05, 300), (6, 1, QUBIT, 1e-2, 200),
+    (10, 4, QUBIT, 1e-3, 64), (10, 4, QUTRIT, 1e-3, 64), (5, 2, QUTRIT, 0.2, 50), (1, 1, QUBIT, 0.3, 100)])
+def test_sampler_and_classifier_bit_exact(lib, orc, n, k, enc, gamma, ntraj):
+    mem = memory_words(n, k, 1000 + n)
+    seed = 880000 + n
+    with lib.QramContext(n, k, enc, gamma, mem) as ctx:
+        out = ctx.sample_faults(seed, 5, ntraj, dump=True)
+    for t in range(ntraj):
+        L = orc.sample(n, k, gamma, seed, 5 + t)
+        assert out["n_cand"][t] == len(L)
+        assert np.array_equal(out["cand_L"][t], L), t
+        h = 0xcbf29ce484222325
+        for x in L.tolist():
+            for b in range(4):
+                h ^= (x >> (8 * b)) & 0xFF
+                h = (h * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+        assert int(out["digest"][t]) == h
+        bad = orc.classify(n, k, enc, L)
+        bits = np.unpackbits(out["bad_bits"][t].view(np.uint8), bitorder="little")[: 1 << n]
+        assert np.array_equal(bits, bad), t
+        assert out["n_bad"][t] == bad.sum()
+
+
+def test_sampler_large_history_bit_exact(lib, orc):
+    """n = 14 qutrit at gamma = 1e-2: ~27.9k candidates per trajectory."""
+    n, k, enc, gamma = 14, 1, QUTRIT, 1e-2
+    mem = memory_words(n, k, 1005)
+    with lib.QramContext(n, k, enc, gamma, mem) as ctx:
+        out = ctx.sample_faults(880005, 1000, 4, dump=True)
+    for t in range(4):
+        L = orc.sample(n, k, gamma, 880005, 1000 + t)
+        assert np.array_equal(out["cand_L"][t], L)
+        bits = np.unpackbits(out["bad_bits"][t].view(np.uint8), bitorder="little")[: 1 << n]
+        assert np.array_equal(bits, orc.classify(n, k, enc, L))
+
+
+# ---------------------------------------------------------------------------
+# trajectories: fidelity and statistics against the oracle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,k,enc,gamma,ntraj", [
+    (2, 1, QUBIT, 0.2, 400), (2, 1, QUTRIT, 0.2, 400), (3, 2, QUBIT, 0.08, 300),
+    (3, 1, QUTRIT, 0.08, 300), (3, 3, QUBIT, 0.05, 200), (4, 2, QUTRIT, 0.05, 200),
+    (1, 1, QUBIT, 0.3, 200), (1, 1, QUTRIT, 0.3, 200), (4, 4, QUBIT, 0.03, 100)])
+def test_small_high_gamma(lib, orc, n, k, enc, gamma, ntraj):
+    """Small trees with strong damping: many jumps, deviated routing."""
+    mem = memory_words(n, k, 77 + n)
+    out, (fo, _, so) = compare_runs(lib, orc, n, k, enc, gamma, mem, 12345, 0, ntraj)
+    assert so[:, 4].sum() > 0  # jumps happened
+
+
+def test_config1_qutrit_all_trajectories(lib, orc):
+    """Qutrit n = 3, k = 1, gamma = 1e-3, 1000 trajectories, both modes."""
+    mem = memory_words(3, 1, 1001)
+    compare_runs(lib, orc, 3, 1, QUTRIT, 1e-3, mem, 880001, 0, 1000)
+
+
+@pytest.mark.parametrize("gamma", [1e-4, 1e-3, 1e-2])
+def test_config2_qubit_sample(lib, orc, gamma):
+    """Qubit n = 6, k = 1: 400 trajectories per gamma against the oracle."""
+    mem = memory_words(6, 1, 1002)
+    compare_runs(lib, orc, 6, 1, QUBIT, gamma, mem, 880002, 0, 400)
+
+
+@pytest.mark.parametrize("threads,sched", [(64, 0), (128, 1), (256, 0), (512, 1), (1024, 1)])
+def test_launch_shapes(lib, orc, threads, sched):
+    mem = memory_words(5, 3, 55)
+    compare_runs(lib, orc, 5, 3, QUBIT, 0.01, mem, 99, 0, 120, threads=(threads, sched))
+
+
+# ---------------------------------------------------------------------------
+# forced histories
+# ---------------------------------------------------------------------------
+def forced_case(lib, orc, n, k, enc, gamma, mem, L, ua, uf):
+    fo = orc.run_traj(n, k, enc, gamma, mem, forced_L=L, forced_uaux=ua, forced_ufin=uf)
+    with lib.QramContext(n, k, enc, gamma, mem) as ctx:
+        for mode in (FULL, PRUNED):
+            f, st = ctx.run_forced(mode, L, ua, uf)
+            assert fid_close(f, fo["fid"]), (mode, f, fo["fid"])
+            assert fid_close(st["fid_pre"], fo["fid_pre"])
+            assert st["n_jumps"] == fo["njumps"] and st["first_jump_slice"] == fo["first_jump"]
+            assert st["q_ground"] == fo["q_ground"]
+    return fo
+
+
+@pytest.mark.parametrize("enc", [QUBIT, QUTRIT])
+def test_forced_no_jump(lib, orc, enc):
+    n, k = 5, 2
+    T = 6 * n + 2 * k
+    mem = memory_words(n, k, 3)
+    fo = forced_case(lib, orc, n, k, enc, 1e-2, mem, [], np.full(T, 0.5), 0.3)
+    assert fo["njumps"] == 0
+
+
+@pytest.mark.parametrize("enc", [QUBIT, QUTRIT])
+def test_forced_reference_annihilated(lib, orc, enc):
+    """A jump on the root router kills every good branch, the reference
+    included (Sec. V A: the annihilation propagates to the predicted groups)."""
+    n, k = 4, 2
+    T, M = 6 * n + 2 * k, 2 * (2**n - 1)
+    mem = memory_words(n, k, 4)
+    # router of node 2 (range: its own subtree) at slice 8, a second candidate
+    L = [(8 - 1) * M + 4, (9 - 1) * M + 5]
+    ua = np.full(T, 0.999999)
+    fo = forced_case(lib, orc, n, k, enc, 0.02, mem, L, ua, 0.1)
+    assert fo["ref"] == 0 and fo["njumps"] >= 1 and fo["ref_survived"] == 0
+
+
+def test_forced_data_slot_jump_qubit(lib, orc):
+    """A jump on the root data slot while bus bit 0 passes (slice 2n+1)."""
+    n, k = 4, 2
+    T, M = 6 * n + 2 * k, 2 * (2**n - 1)
+    mem = memory_words(n, k, 5)
+    L = [(2 * n + 1 - 1) * M + 1]
+    fo = forced_case(lib, orc, n, k, QUBIT, 0.02, mem, L, np.full(T, 0.9999), 0.2)
+    assert fo["njumps"] == 1
+
+
+def test_forced_router_jump_qutrit(lib, orc):
+    """A qutrit router jump (K1 or K2 by level) below the root."""
+    n, k = 4, 1
+    T, M = 6 * n + 2 * k, 2 * (2**n - 1)
+    mem = memory_words(n, k, 6)
+    for site in (2, 4, 6):  # routers of nodes 1, 2, 3
+        L = [(12 - 1) * M + site]
+        forced_case(lib, orc, n, k, QUTRIT, 0.05, mem, L, np.full(T, 0.99999), 0.5)
+
+
+@pytest.mark.parametrize("enc", [QUBIT, QUTRIT])
+def test_forced_idle_sites(lib, orc, enc):
+    """Candidates on sites no component excites never fire."""
+    n, k = 4, 1
+    T, M = 6 * n + 2 * k, 2 * (2**n - 1)
+    mem = memory_words(n, k, 7)
+    # slice 1 excites only the root data slot, slice 2 only the root router,
+    # and after the last uncopy (slice T-1) the tree is empty
+    L = [0 * M + 5, 0 * M + 29, 1 * M + 7, (T - 2) * M + 0, (T - 2) * M + 1]
+    fo = forced_case(lib, orc, n, k, enc, 0.05, mem, L, np.full(T, 0.99999), 0.5)
+    assert fo["njumps"] == 0
+
+
+@pytest.mark.parametrize("enc", [QUBIT, QUTRIT])
+def test_forced_many_candidates_one_slice(lib, orc, enc):
+    """More candidates in one slice than the list scan holds (bitmap path)."""
+    n, k = 5, 2
+    T, M = 6 * n + 2 * k, 2 * (2**n - 1)
+    mem = memory_words(n, k, 8)
+    rng = np.random.default_rng(enc)
+    for trial in range(6):
+        s = int(rng.integers(1, T))
+        qs = np.sort(rng.choice(M, size=24, replace=False))
+        extra = np.sort(rng.choice((T - 1) * M, size=5, replace=False))
+        L = np.unique(np.concatenate([(s - 1) * M + qs, extra])).astype(np.uint32)
+        ua = rng.uniform(0, 1, size=T)
+        ua[s] = rng.uniform(0.5, 1.0)
+        forced_case(lib, orc, n, k, enc, 0.05, mem, L, ua, float(rng.uniform()))
+
+
+@pytest.mark.parametrize("enc", [QUBIT, QUTRIT])
+def test_forced_random_histories(lib, orc, enc):
+    n, k = 3, 2
+    T, M = 6 * n + 2 * k, 2 * (2**n - 1)
+    mem = memory_words(n, k, 9)
+    rng = np.random.default_rng(100 + enc)
+    for trial in range(40):
+        L = np.sort(rng.choice((T - 1) * M, size=int(rng.integers(0, 12)), replace=False)).astype(np.uint32)
+        ua = rng.uniform(0, 1, size=T)
+        forced_case(lib, orc, n, k, enc, 0.1, mem, L, ua, float(rng.uniform()))
+
+
+# ---------------------------------------------------------------------------
+# determinism, ranges, gamma = 0, async
+# ---------------------------------------------------------------------------
+def test_deterministic_and_range_split(lib):
+    n, k = 6, 2
+    mem = memory_words(n, k, 10)
+    with lib.QramContext(n, k, QUBIT, 3e-3, mem) as ctx:
+        for fn in (ctx.run_full, ctx.run_pruned):
+            a, sa = fn(5, 100, 500)
+            b, sb = fn(5, 100, 500)
+            assert np.array_equal(a, b) and np.array_equal(sa, sb)
+            c1, _ = fn(5, 100, 123)
+            c2, _ = fn(5, 223, 377)
+            assert np.array_equal(np.concatenate([c1, c2]), a)
+
+
+@pytest.mark.parametrize("enc", [QUBIT, QUTRIT])
+def test_gamma_zero(lib, enc):
+    n, k = 8, 2
+    mem = memory_words(n, k, 11)
+    with lib.QramContext(n, k, enc, 0.0, mem) as ctx:
+        f, st = ctx.run_pruned(1, 0, 50)
+        assert np.allclose(f, 1.0, atol=1e-13)
+        assert np.all(st["n_cand"] == 0) and np.all(st["n_bad"] == 0)
+        assert np.all(st["n_explicit"] == (2**k if enc == QUBIT else 1))
+        f2, _ = ctx.run_full(1, 0, 50)
+        assert np.allclose(f2, 1.0, atol=1e-13)
+
+
+def test_async_device_buffers(lib):
+    import torch
+    n, k = 6, 1
+    mem = memory_words(n, k, 12)
+    with lib.QramContext(n, k, QUBIT, 1e-3, mem) as ctx:
+        ref_f, ref_s = ctx.run_pruned(42, 0, 1000)
+        d_f = torch.empty(1000, dtype=torch.float64, device="cuda")
+        d_s = torch.empty(1000 * 32, dtype=torch.uint8, device="cuda")
+        s = torch.cuda.Stream()
+        ctx.run_pruned_async(42, 0, 1000, d_f, d_s, stream=s)
+        s.synchronize()
+        assert np.array_equal(d_f.cpu().numpy(), ref_f)
+        st = np.frombuffer(d_s.cpu().numpy().tobytes(), dtype=lib.STATS_DTYPE)
+        assert np.array_equal(st, ref_s)
