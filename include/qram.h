@@ -77,7 +77,9 @@ typedef struct {
 /*
  * Create a context for an (n,k)-QRAM in the given encoding with damping
  * strength gamma (Sec. II B; Theorem 4 needs gamma < 1).
- *   n_addr      1..15 (qubit), 1..14 (qutrit); k_data 1..8 with k <= n.
+ *   n_addr      1..15 (qubit), 1..14 (qutrit); k_data 1..8 with k <= n; the
+ *               qubit encoding also needs k <= 6 and n + k <= 16 (at most
+ *               65536 components per trajectory).
  *   memory_bits host array of 2^n words; bit b of word i is d_i^(b); only the
  *               low k bits are used.  Copied: the caller may free it after the
  *               call returns.
@@ -155,17 +157,27 @@ qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,
                           double *sem);
 
 /*
- * Launch shape of a mode: threads per trajectory (64, 128, 256, 512 or 1024),
- * schedule 0 = one workgroup per trajectory in index order, 1 = persistent
- * workgroups taking trajectories from a device queue in descending order of
- * explicit work (longest first).  threads = 0 restores the automatic choice.
+ * Launch shape of a mode.  Trajectories are grouped by their number of
+ * explicitly evolved components; each group runs as its own launch whose
+ * workgroups hold about slots_per_thread components per thread (4, 8, 16, 32
+ * or 64; 0 restores the automatic choice).  schedule 0 hands trajectories to
+ * workgroups round robin, 1 takes them from a device queue, longest first.
  * The shape changes only the speed: results are identical across shapes up to
  * the rounding of the per-slice weight sums.
  */
-qram_status qram_set_launch(qram_ctx *ctx, qram_mode mode, int threads,
+qram_status qram_set_launch(qram_ctx *ctx, qram_mode mode, int slots_per_thread,
                             int schedule);
-qram_status qram_get_launch(const qram_ctx *ctx, qram_mode mode, int *threads,
-                            int *schedule);
+qram_status qram_get_launch(const qram_ctx *ctx, qram_mode mode,
+                            int *slots_per_thread, int *schedule);
+
+/*
+ * Options.  QRAM_OPT_TIER2_GLOBAL (value 0/1): keep every explicit site list
+ * of a component whose routing a jump changed in global memory instead of
+ * registers (same results; for testing the two list paths against each
+ * other).
+ */
+enum { QRAM_OPT_TIER2_GLOBAL = 1 };
+qram_status qram_set_option(qram_ctx *ctx, int option, int value);
 
 /*
  * Measure every launch shape of a mode on trajectories [traj0, traj0+ntraj)
@@ -180,6 +192,17 @@ qram_status qram_autotune(qram_ctx *ctx, qram_mode mode, uint64_t seed,
  * stream.  times[3].
  */
 qram_status qram_last_kernel_ms(const qram_ctx *ctx, double *times);
+
+/*
+ * Stage timing of the device-buffer variants.  With timing on, every batch a
+ * *_async call enqueues records HIP events on the caller's stream around
+ * sampling, classification (with ordering) and evolution.  qram_stage_times
+ * waits for the recorded events, returns the summed milliseconds of the three
+ * stages since timing was switched on or last read (ms[3]) and the number of
+ * batches (nbatches, may be NULL), and starts a new accumulation.
+ */
+qram_status qram_set_timing(qram_ctx *ctx, int on);
+qram_status qram_stage_times(qram_ctx *ctx, double *ms, uint32_t *nbatches);
 
 /*
  * Test entry: one trajectory under a forced history instead of the random

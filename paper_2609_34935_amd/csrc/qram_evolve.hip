@@ -1,0 +1,1209 @@
+// Trajectory evolution kernel (gfx950): one workgroup per trajectory carries
+// every explicit component through the T-1 slices of the schedule with one
+// joint damping layer per slice (Eq. layerkraus, Theorem 4, Eq. maskweight),
+// predicts the good branches in pruned mode (Proposition 1, Theorem 3), and
+// reduces the post-measurement fidelity (Alg. 1 steps 3-6).
+//
+// Components never split between the walls: every gate permutes basis labels
+// and K_J maps survivors one to one.  A component therefore keeps its slot,
+// which encodes its initial label (address, bus word), and is one of
+//   tier 1: no jump has touched its routing.  Its excited sites are the
+//           schedule positions of its live tokens on its own path, so its
+//           state changes only at slices whose joint outcome J is nonempty
+//           (a lost data token).  Its exposure, sign and weight follow from
+//           prefix tables of the schedule.
+//   tier 2: a jump removed an address token or a router.  The component
+//           carries an explicit site list in a per-workgroup pool and follows
+//           the gates literally; lists up to REG_CAP - 6 entries are processed
+//           in registers, longer ones in global memory.
+// Amplitudes are c_i * sign * gamma^{|J|/2} * a^e.  gamma^{|J|/2} is the same
+// for every survivor and cancels in every ratio, so a draw uses the weights
+// (1-gamma)^e.  Per slice the kernel tests the slice's candidates against
+// every component; weights are formed only when some component is hit.
+#include "qram_device.h"
+
+namespace qr {
+
+namespace {
+
+constexpr uint32_t EMPTY = 0xFFFFu;
+
+// ---------------------------------------------------------------------------
+// tier 1
+// ---------------------------------------------------------------------------
+
+// Level of site q (0 ground; 1 excited / L; 2 R) of a tier-1 component of
+// address a with live data tokens `live` after the gates of slice s.
+template <int ENC>
+__device__ __forceinline__ int t1_level(const Tables *__restrict__ tb, int s,
+                                        uint32_t a, uint32_t live, uint32_t memw,
+                                        uint32_t q) {
+  const int n = tb->n;
+  const uint32_t v = q >> 1, slot = q & 1u;
+  const int l = layer_of(v);
+  if ((a >> (n - l)) != v + 1 - (1u << l)) return 0;
+  const uint32_t tk = tb->tok[s][l][slot];
+  if (tk == NONE) return 0;
+  if (tk < (uint32_t)n) {
+    const uint32_t bit = (a >> (n - 1 - tk)) & 1u;
+    if (ENC == QUBIT) return (int)bit;
+    return slot == 0 ? (bit ? 2 : 1) : (int)bit;
+  }
+  const int b = (int)tk - n;
+  if (ENC == QUBIT) return (int)((live >> b) & 1u);
+  return (int)(((tb->dmask[s] & memw & live) >> b) & 1u);
+}
+
+// Site of token tk (address token t < n, data token n + b) of address a
+// after the gates of slice s, or -1 outside the tree.
+__device__ __forceinline__ int t1_site(const Tables *__restrict__ tb, int s,
+                                       uint32_t a, int tk) {
+  const uint8_t ps = tb->pos[s][tk];
+  if (ps == NONE) return -1;
+  const int l = ps >> 1, slot = ps & 1;
+  const uint32_t v = (1u << l) - 1u + (a >> (tb->n - l));
+  return (int)(2 * v + slot);
+}
+
+__device__ __forceinline__ bool cand_bm(const uint32_t *cbm, uint32_t q) {
+  return (cbm[q >> 5] >> (q & 31)) & 1u;
+}
+
+__device__ __forceinline__ bool cand_list(const uint32_t *cdec, int nc,
+                                          uint32_t q) {
+  for (int j = 0; j < nc; ++j)
+    if ((cdec[j] & 0xFFFFu) == q) return true;
+  return false;
+}
+
+// Candidates of slice s on the path of address a: `ah` when a candidate sits
+// on a site every tier-1 component of a excites (an address token of a), `dh`
+// the data tokens sitting on candidate sites.
+template <int ENC>
+__device__ __forceinline__ void t1_addr_hits(const Tables *__restrict__ tb,
+                                             int s, uint32_t a, bool big,
+                                             int nc, const uint32_t *cdec,
+                                             const uint32_t *cbm, bool &ah,
+                                             uint32_t &dh) {
+  const int n = tb->n;
+  ah = false;
+  dh = 0;
+  if (!big) {
+    for (int j = 0; j < nc; ++j) {
+      const uint32_t c = cdec[j];
+      const uint32_t tk = (c >> 20) & 0xFFu;
+      if (tk == NONE) continue;
+      const int l = (c >> 16) & 15;
+      const uint32_t q = c & 0xFFFFu;
+      if ((a >> (n - l)) != (q >> 1) + 1 - (1u << l)) continue;
+      if (tk < (uint32_t)n) {
+        if ((ENC == QUTRIT && (q & 1u) == 0) || ((a >> (n - 1 - tk)) & 1u)) ah = true;
+      } else {
+        dh |= 1u << (tk - n);
+      }
+    }
+    return;
+  }
+  for (int t = 0; t < n; ++t) {
+    const uint8_t ps = tb->pos[s][t];
+    if (ps == NONE) continue;
+    const bool abit = (a >> (n - 1 - t)) & 1u;
+    if (!(abit || (ENC == QUTRIT && (ps & 1) == 0))) continue;
+    if (cand_bm(cbm, (uint32_t)t1_site(tb, s, a, t))) ah = true;
+  }
+  for (int b = 0; b < tb->k; ++b) {
+    const int q = t1_site(tb, s, a, n + b);
+    if (q >= 0 && cand_bm(cbm, (uint32_t)q)) dh |= 1u << b;
+  }
+}
+
+// Integer exposure through slice s of a tier-1 component (excited sites
+// summed over slices 1..s).
+template <int ENC>
+__device__ __forceinline__ uint32_t t1_exposure(const Tables *__restrict__ tb,
+                                                int s, uint32_t a,
+                                                uint32_t dv, uint32_t ek) {
+  const int n = tb->n;
+  uint32_t e = ek;
+  for (int t = 0; t < n; ++t)
+    if ((a >> (n - 1 - t)) & 1u) e += tb->cntA[s][t];
+  for (int b = 0; b < tb->k; ++b)
+    if ((dv >> b) & 1u) e += tb->cntD[s][b];
+  if (ENC == QUTRIT) e += tb->cntR[s];
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// tier 2, global-memory list (any length)
+// ---------------------------------------------------------------------------
+template <int ENC>
+struct Rec {
+  uint16_t *r;
+  static constexpr uint32_t SM = ENC == QUTRIT ? 0x7FFFu : 0xFFFFu;
+  __device__ __forceinline__ int cnt() const { return r[0]; }
+  __device__ __forceinline__ uint32_t raw(int j) const { return r[2 + j]; }
+  __device__ __forceinline__ uint32_t site(int j) const { return r[2 + j] & SM; }
+  __device__ __forceinline__ int find_site(uint32_t q) const {
+    const int c = r[0];
+    for (int j = 0; j < c; ++j)
+      if ((r[2 + j] & SM) == q) return j;
+    return -1;
+  }
+  __device__ __forceinline__ int find_raw(uint32_t x) const {
+    const int c = r[0];
+    for (int j = 0; j < c; ++j)
+      if (r[2 + j] == x) return j;
+    return -1;
+  }
+  __device__ __forceinline__ void remove(int j) {
+    const int c = r[0] - 1;
+    r[2 + j] = r[2 + c];
+    r[0] = (uint16_t)c;
+  }
+  __device__ __forceinline__ bool add(uint32_t x, int lmax) {
+    const int c = r[0];
+    if (c >= lmax) return false;
+    r[2 + c] = (uint16_t)x;
+    r[0] = (uint16_t)(c + 1);
+    return true;
+  }
+  // routing direction of node v: qubit 0/1; qutrit -1 (W), 0 (L), 1 (R)
+  __device__ __forceinline__ int dir(uint32_t v) const {
+    const int j = find_site(2 * v);
+    if (ENC == QUBIT) return j >= 0 ? 1 : 0;
+    if (j < 0) return -1;
+    return (r[2 + j] & LV_R_BIT) ? 1 : 0;
+  }
+};
+
+// Gates of slice s on a global-memory list (schedule of Sec. II A, gate set
+// of App. C; qutrit stores gated by the parent's router).
+template <int ENC>
+__device__ __attribute__((noinline)) void t2_gates_mem(const Tables *__restrict__ tb, int s, Rec<ENC> R,
+                             uint32_t a, uint32_t &word, uint32_t *err) {
+  const int n = tb->n, lmax = tb->lmax;
+  const int ct = tb->copy_t[s];
+  if (ct >= 0 && ((a >> (n - 1 - ct)) & 1u)) {
+    const int j = R.find_site(1);
+    if (j >= 0)
+      R.remove(j);
+    else if (!R.add(1, lmax))
+      atomicOr(err, ERR_LIST);
+  }
+  const int sl = tb->store_l[s];
+  if (sl >= 0) {
+    if (ENC == QUBIT) {
+      for (int j = 0; j < R.cnt(); ++j) {
+        const uint32_t q = R.site(j);
+        if (layer_of(q >> 1) == sl) R.r[2 + j] = (uint16_t)(q ^ 1u);
+      }
+    } else {
+      uint32_t g0 = 0, g1 = 0, g2 = 0, g3 = 0;
+      int ng = 0;
+      if (sl == 0) {
+        ng = 1;
+      } else {
+        for (int j = 0; j < R.cnt(); ++j) {
+          const uint32_t x = R.raw(j), q = x & Rec<ENC>::SM;
+          if (q & 1u) continue;
+          const uint32_t v = q >> 1;
+          if (layer_of(v) != sl - 1) continue;
+          const uint32_t c = 2 * v + 1 + ((x & LV_R_BIT) ? 1u : 0u);
+          if (ng == 0) g0 = c;
+          else if (ng == 1) g1 = c;
+          else if (ng == 2) g2 = c;
+          else if (ng == 3) g3 = c;
+          else atomicOr(err, ERR_LIST);
+          ++ng;
+        }
+      }
+      for (int g = 0; g < ng && g < 4; ++g) {
+        const uint32_t v = g == 0 ? g0 : g == 1 ? g1 : g == 2 ? g2 : g3;
+        const int jr = R.find_site(2 * v);
+        const int jd = R.find_site(2 * v + 1);
+        if (jr < 0) {
+          if (jd >= 0) {
+            R.remove(jd);
+            R.add(2 * v | LV_R_BIT, lmax);
+          } else if (!R.add(2 * v, lmax)) {
+            atomicOr(err, ERR_LIST);
+          }
+        } else if (jd < 0) {
+          const bool isR = (R.raw(jr) & LV_R_BIT) != 0;
+          R.remove(jr);
+          if (isR) R.add(2 * v + 1, lmax);
+        }
+      }
+    }
+  }
+  const uint32_t cm = tb->cswap[s];
+  if (cm) {
+    for (int j = 0; j < R.cnt(); ++j) {
+      const uint32_t q = R.site(j);
+      if (!(q & 1u)) continue;
+      const uint32_t v = q >> 1;
+      const int l = layer_of(v);
+      if ((cm >> l) & 1u) {
+        const int d = R.dir(v);
+        if (d >= 0) R.r[2 + j] = (uint16_t)(2 * (2 * v + 1 + d) + 1);
+      } else if (l >= 1 && ((cm >> (l - 1)) & 1u)) {
+        const uint32_t p = (v - 1) >> 1;
+        const int d = R.dir(p);
+        if (d >= 0 && v == 2 * p + 1 + (uint32_t)d) R.r[2 + j] = (uint16_t)(2 * p + 1);
+      }
+    }
+  }
+  const int bb = tb->bus_b[s];
+  if (bb >= 0) {
+    const int j = R.find_site(1);
+    const uint32_t bus = R.r[1];
+    const bool bbit = (bus >> bb) & 1u;
+    if (j >= 0 && !bbit) {
+      R.remove(j);
+      R.r[1] = (uint16_t)(bus | (1u << bb));
+    } else if (j < 0 && bbit) {
+      if (!R.add(1, lmax)) atomicOr(err, ERR_LIST);
+      R.r[1] = (uint16_t)(bus & ~(1u << bb));
+    }
+  }
+  const int fb = tb->fetch_b[s];
+  if (fb >= 0) {
+    const uint32_t v0 = (1u << (n - 1)) - 1u;
+    if (ENC == QUBIT) {
+      for (int j = 0; j < R.cnt(); ++j) {
+        const uint32_t q = R.site(j);
+        if (!(q & 1u) || (q >> 1) < v0) continue;
+        const uint32_t v = q >> 1, p = v - v0;
+        const uint32_t cell = 2 * p + (uint32_t)R.dir(v);
+        if ((tb->mem[cell] >> fb) & 1u) word ^= W_SIGN;
+      }
+    } else {
+      uint32_t c0 = 0, c1 = 0;  // cells' d-site targets of the leaf routers
+      int nl = 0;
+      for (int j = 0; j < R.cnt(); ++j) {
+        const uint32_t x = R.raw(j), q = x & Rec<ENC>::SM;
+        if ((q & 1u) || (q >> 1) < v0) continue;
+        const uint32_t v = q >> 1;
+        const uint32_t cell = 2 * (v - v0) + ((x & LV_R_BIT) ? 1u : 0u);
+        const uint32_t tgt = ((tb->mem[cell] >> fb) & 1u) ? 2 * v + 1 : 0xFFFFFFFFu;
+        if (nl == 0) c0 = tgt;
+        else if (nl == 1) c1 = tgt;
+        else atomicOr(err, ERR_LIST);
+        ++nl;
+      }
+      for (int g = 0; g < nl && g < 2; ++g) {
+        const uint32_t tgt = g == 0 ? c0 : c1;
+        if (tgt != 0xFFFFFFFFu) {
+          const uint32_t v = tgt >> 1;
+          const int jd = R.find_site(2 * v + 1);
+          if (jd >= 0)
+            R.remove(jd);
+          else if (!R.add(2 * v + 1, lmax))
+            atomicOr(err, ERR_LIST);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tier 2, register list (fixed capacity, empty slots marked)
+// ---------------------------------------------------------------------------
+template <int ENC>
+struct RList {
+  // REG_CAP 16-bit entries, two per register; EMPTY marks a free entry
+  uint32_t p[REG_CAP / 2];
+  uint32_t bus;
+  static constexpr uint32_t SM = ENC == QUTRIT ? 0x7FFFu : 0xFFFFu;
+
+  __device__ __forceinline__ uint32_t get(int j) const {
+    return (p[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu;
+  }
+  __device__ __forceinline__ void set(int j, uint32_t x) {
+    const int sh = (j & 1) * 16;
+    p[j >> 1] = (p[j >> 1] & ~(0xFFFFu << sh)) | (x << sh);
+  }
+  __device__ __forceinline__ void load(const uint16_t *rec, uint32_t cnt) {
+    const uint32_t *r32 = reinterpret_cast<const uint32_t *>(rec);
+    bus = r32[0] >> 16;
+#pragma unroll
+    for (int j = 0; j < REG_CAP; j += 2) {
+      const uint32_t w = (uint32_t)j < cnt ? r32[1 + j / 2] : 0xFFFFFFFFu;
+      const uint32_t lo = (uint32_t)j < cnt ? (w & 0xFFFFu) : EMPTY;
+      const uint32_t hi = (uint32_t)(j + 1) < cnt ? (w >> 16) : EMPTY;
+      p[j >> 1] = lo | (hi << 16);
+    }
+  }
+  __device__ __forceinline__ uint32_t store(uint16_t *rec) const {
+    uint32_t pos = 0;
+#pragma unroll
+    for (int j = 0; j < REG_CAP; ++j) {
+      const uint32_t x = get(j);
+      if (x != EMPTY) {
+        rec[2 + pos] = (uint16_t)x;
+        ++pos;
+      }
+    }
+    rec[0] = (uint16_t)pos;
+    rec[1] = (uint16_t)bus;
+    return pos;
+  }
+  __device__ __forceinline__ bool has(uint32_t q) const {
+    bool f = false;
+#pragma unroll
+    for (int j = 0; j < REG_CAP; ++j) {
+      const uint32_t x = get(j);
+      f |= x != EMPTY && (x & SM) == q;
+    }
+    return f;
+  }
+  __device__ __forceinline__ void remove_site(uint32_t q) {
+#pragma unroll
+    for (int j = 0; j < REG_CAP; ++j) {
+      const uint32_t x = get(j);
+      if (x != EMPTY && (x & SM) == q) set(j, EMPTY);
+    }
+  }
+  __device__ __forceinline__ bool add(uint32_t x) {
+    bool placed = false;
+#pragma unroll
+    for (int j = 0; j < REG_CAP; ++j)
+      if (!placed && get(j) == EMPTY) {
+        set(j, x);
+        placed = true;
+      }
+    return placed;
+  }
+  __device__ __forceinline__ void toggle(uint32_t q, bool &ovf) {
+    if (has(q))
+      remove_site(q);
+    else
+      ovf |= !add(q);
+  }
+  // routing direction of node v: qubit 0/1; qutrit -1 (W), 0 (L), 1 (R)
+  __device__ __forceinline__ int dir(uint32_t v) const {
+    int d = ENC == QUBIT ? 0 : -1;
+#pragma unroll
+    for (int j = 0; j < REG_CAP; ++j) {
+      const uint32_t x = get(j);
+      if (x != EMPTY && (x & SM) == 2 * v) d = ENC == QUBIT ? 1 : ((x & LV_R_BIT) ? 1 : 0);
+    }
+    return d;
+  }
+};
+
+template <int ENC>
+__device__ __attribute__((noinline)) void t2_gates_reg(const Tables *__restrict__ tb, int s, RList<ENC> &L,
+                             uint32_t a, uint32_t &word, uint32_t *err) {
+  const int n = tb->n;
+  constexpr uint32_t SM = RList<ENC>::SM;
+  bool ovf = false;
+  const int ct = tb->copy_t[s];
+  if (ct >= 0 && ((a >> (n - 1 - ct)) & 1u)) L.toggle(1, ovf);
+  const int sl = tb->store_l[s];
+  if (sl >= 0) {
+    if (ENC == QUBIT) {
+#pragma unroll
+      for (int j = 0; j < REG_CAP; ++j) {
+        const uint32_t x = L.get(j);
+        if (x != EMPTY && layer_of(x >> 1) == sl) L.set(j, x ^ 1u);
+      }
+    } else {
+      uint32_t g0 = 0, g1 = 0, g2 = 0, g3 = 0;
+      int ng = 0;
+      if (sl == 0) {
+        ng = 1;
+      } else {
+#pragma unroll
+        for (int j = 0; j < REG_CAP; ++j) {
+          const uint32_t x = L.get(j);
+          if (x == EMPTY || (x & 1u)) continue;
+          const uint32_t v = (x & SM) >> 1;
+          if (layer_of(v) != sl - 1) continue;
+          const uint32_t c = 2 * v + 1 + ((x & LV_R_BIT) ? 1u : 0u);
+          if (ng == 0) g0 = c;
+          else if (ng == 1) g1 = c;
+          else if (ng == 2) g2 = c;
+          else if (ng == 3) g3 = c;
+          else ovf = true;
+          ++ng;
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        if (g >= ng) break;
+        const uint32_t v = g == 0 ? g0 : g == 1 ? g1 : g == 2 ? g2 : g3;
+        const int d = L.dir(v);  // -1: W
+        const bool dd = L.has(2 * v + 1);
+        if (d < 0) {
+          if (dd) {
+            L.remove_site(2 * v + 1);
+            ovf |= !L.add(2 * v | LV_R_BIT);
+          } else {
+            ovf |= !L.add(2 * v);
+          }
+        } else if (!dd) {
+          L.remove_site(2 * v);
+          if (d == 1) ovf |= !L.add(2 * v + 1);
+        }
+      }
+    }
+  }
+  const uint32_t cm = tb->cswap[s];
+  if (cm) {
+#pragma unroll
+    for (int j = 0; j < REG_CAP; ++j) {
+      const uint32_t x = L.get(j);
+      if (x == EMPTY || !(x & 1u)) continue;
+      const uint32_t v = (x & SM) >> 1;
+      const int l = layer_of(v);
+      if ((cm >> l) & 1u) {
+        const int d = L.dir(v);
+        if (d >= 0) L.set(j, 2 * (2 * v + 1 + (uint32_t)d) + 1);
+      } else if (l >= 1 && ((cm >> (l - 1)) & 1u)) {
+        const uint32_t p = (v - 1) >> 1;
+        const int d = L.dir(p);
+        if (d >= 0 && v == 2 * p + 1 + (uint32_t)d) L.set(j, 2 * p + 1);
+      }
+    }
+  }
+  const int bb = tb->bus_b[s];
+  if (bb >= 0) {
+    const bool d0 = L.has(1);
+    const bool bbit = (L.bus >> bb) & 1u;
+    if (d0 && !bbit) {
+      L.remove_site(1);
+      L.bus |= 1u << bb;
+    } else if (!d0 && bbit) {
+      ovf |= !L.add(1);
+      L.bus &= ~(1u << bb);
+    }
+  }
+  const int fb = tb->fetch_b[s];
+  if (fb >= 0) {
+    const uint32_t v0 = (1u << (n - 1)) - 1u;
+    if (ENC == QUBIT) {
+#pragma unroll
+      for (int j = 0; j < REG_CAP; ++j) {
+        const uint32_t x = L.get(j);
+        if (x == EMPTY || !(x & 1u) || (x >> 1) < v0) continue;
+        const uint32_t v = x >> 1, p = v - v0;
+        if ((tb->mem[2 * p + (uint32_t)L.dir(v)] >> fb) & 1u) word ^= W_SIGN;
+      }
+    } else {
+      uint32_t c0 = 0, c1 = 0;
+      int nl = 0;
+#pragma unroll
+      for (int j = 0; j < REG_CAP; ++j) {
+        const uint32_t x = L.get(j);
+        if (x == EMPTY || (x & 1u) || ((x & SM) >> 1) < v0) continue;
+        const uint32_t v = (x & SM) >> 1;
+        const uint32_t cell = 2 * (v - v0) + ((x & LV_R_BIT) ? 1u : 0u);
+        const uint32_t target = (tb->mem[cell] >> fb) & 1u ? 2 * v + 1 : EMPTY;
+        if (nl == 0) c0 = target;
+        else if (nl == 1) c1 = target;
+        else ovf = true;
+        ++nl;
+      }
+      if (nl > 0 && c0 != EMPTY) L.toggle(c0, ovf);
+      if (nl > 1 && c1 != EMPTY) L.toggle(c1, ovf);
+    }
+  }
+  if (ovf) atomicOr(err, ERR_LIST);
+}
+
+// ---------------------------------------------------------------------------
+// shared memory layout
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint32_t al16(uint32_t x) { return (x + 15u) & ~15u; }
+
+struct Sm {
+  double *red;      // [2 * nw * 8]
+  double *scanb;    // [nw]
+  double *fw;       // factor tables (1-gamma)^m: A chunks [3*32], data [256], lost [256]
+  double *fa;       // the same with a^m (final)
+  double *fmisc;    // [4]
+  uint32_t *cstart; // [MAXT + 1]
+  uint32_t *cdec;   // [NCS]
+  uint32_t *Jb;     // [JMAX]
+  int *misc;        // [8]
+  uint32_t *cbm;    // [(M + 31) / 32]
+  uint32_t *badl;   // [(D + 31) / 32]
+  uint32_t *st;     // [e_cap] when the state lives in LDS
+};
+
+constexpr int F_A = 0, F_D = 96, F_K = 96 + 256, F_N = 96 + 256 + 256;
+
+__host__ __device__ inline uint32_t fixed_bytes(int M, int D, int threads) {
+  const int nw = threads >> 6;
+  uint32_t b = 0;
+  b += al16(2 * nw * 8 * 8);
+  b += al16(nw * 8);
+  b += al16(F_N * 8) * 2;
+  b += al16(4 * 8);
+  b += al16((MAXT + 1) * 4);
+  b += al16(NCS * 4);
+  b += al16(JMAX * 4);
+  b += al16(8 * 4);
+  b += al16(((M + 31) / 32) * 4);
+  b += al16(((D + 31) / 32) * 4);
+  return b;
+}
+
+__device__ inline Sm carve(unsigned char *base, int M, int D, int threads) {
+  const int nw = threads >> 6;
+  Sm m;
+  unsigned char *p = base;
+  m.red = reinterpret_cast<double *>(p);
+  p += al16(2 * nw * 8 * 8);
+  m.scanb = reinterpret_cast<double *>(p);
+  p += al16(nw * 8);
+  m.fw = reinterpret_cast<double *>(p);
+  p += al16(F_N * 8);
+  m.fa = reinterpret_cast<double *>(p);
+  p += al16(F_N * 8);
+  m.fmisc = reinterpret_cast<double *>(p);
+  p += al16(4 * 8);
+  m.cstart = reinterpret_cast<uint32_t *>(p);
+  p += al16((MAXT + 1) * 4);
+  m.cdec = reinterpret_cast<uint32_t *>(p);
+  p += al16(NCS * 4);
+  m.Jb = reinterpret_cast<uint32_t *>(p);
+  p += al16(JMAX * 4);
+  m.misc = reinterpret_cast<int *>(p);
+  p += al16(8 * 4);
+  m.cbm = reinterpret_cast<uint32_t *>(p);
+  p += al16(((M + 31) / 32) * 4);
+  m.badl = reinterpret_cast<uint32_t *>(p);
+  p += al16(((D + 31) / 32) * 4);
+  m.st = reinterpret_cast<uint32_t *>(p);
+  return m;
+}
+
+// Factor tables for exposure through slice s: chunk c of the address bits
+// (bits 5c..5c+4 of i, where bit n-1-t is address token t), data-token sets
+// and lost-token exposure.  pw points at the centre of a power table.
+template <int ENC>
+__device__ void build_factors(const Tables *__restrict__ tb, int s,
+                              const double *__restrict__ pw, double *f,
+                              double *fmisc, bool with_lost) {
+  const int n = tb->n, k = tb->k;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  for (int x = tid; x < 96; x += nthr) {
+    const int c = x >> 5, v = x & 31;
+    int e = 0;
+    for (int b = 0; b < 5; ++b) {
+      const int pbit = 5 * c + b;
+      if (pbit < n && ((v >> b) & 1)) e += tb->cntA[s][n - 1 - pbit];
+    }
+    f[F_A + x] = pw[e];
+  }
+  for (int v = tid; v < (1 << k); v += nthr) {
+    int e = 0;
+    for (int b = 0; b < k; ++b)
+      if ((v >> b) & 1) e += tb->cntD[s][b];
+    f[F_D + v] = pw[e];
+  }
+  if (with_lost) {
+    const int kmax = min(255, tb->emax);
+    for (int m = tid; m <= kmax; m += nthr) f[F_K + m] = pw[m];
+  }
+  if (tid == 0) fmisc[0] = ENC == QUTRIT ? pw[tb->cntR[s]] : 1.0;
+}
+
+__device__ __forceinline__ double fA(const double *f, uint32_t a) {
+  return f[F_A + (a & 31u)] * f[F_A + 32 + ((a >> 5) & 31u)] * f[F_A + 64 + ((a >> 10) & 31u)];
+}
+
+// ---------------------------------------------------------------------------
+// the kernel
+// ---------------------------------------------------------------------------
+template <int ENC, bool SL>
+__global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
+                                                 const Run R_) {
+  const Run *rp = &R_;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int n = tb->n, T = tb->T, M = tb->M, D = tb->D, emax = tb->emax;
+  const int K2 = ENC == QUBIT ? tb->K2 : 1;
+  const int kb = ENC == QUBIT ? tb->k : 0;
+  const uint32_t kmask = (1u << tb->k) - 1u;
+  const double *__restrict__ wpow = tb->wpow + emax;
+  const double *__restrict__ apow = tb->apow + emax;
+  const uint32_t *__restrict__ mem = tb->mem;
+  Sm sm = carve(smem, M, D, nthr);
+  uint32_t *st = SL ? sm.st : rp->gstate + (size_t)blockIdx.x * rp->e_cap;
+  const int rec = tb->rec;
+  uint16_t *pool = rp->pool + (size_t)blockIdx.x * rp->pool_slots * rec;
+  const bool pruned = rp->mode == 1;
+  const uint32_t ccap = rp->cand_cap;
+  const uint32_t apt = rp->apt;
+  const uint32_t bkt = rp->bucket;
+  const bool slow_all = rp->tier2_slow != 0;
+  int big_prev_s = 0, big_prev_cb = 0, big_prev_nc = 0;
+  // the constant lost-token factors, and a clean candidate bitmap
+  build_factors<ENC>(tb, 0, wpow, sm.fw, sm.fmisc, true);
+  build_factors<ENC>(tb, 0, apow, sm.fa, sm.fmisc + 1, true);
+  for (int w = tid; w < (M + 31) / 32; w += nthr) sm.cbm[w] = 0u;
+
+  const uint32_t seg0 = rp->bucket_base[bkt];
+  const uint32_t segn = rp->bucket_base[bkt + 1] - seg0;
+  for (uint32_t iter = 0;; ++iter) {
+    __syncthreads();
+    uint32_t qslot;
+    if (rp->persistent) {
+      if (tid == 0) sm.misc[0] = (int)atomicAdd(&rp->counter[bkt], 1u);
+      __syncthreads();
+      qslot = (uint32_t)sm.misc[0];
+    } else {
+      qslot = blockIdx.x + iter * gridDim.x;
+    }
+    if (qslot >= segn) break;
+    const uint32_t tj = rp->order[seg0 + qslot];
+    const uint32_t traj = rp->traj0 + tj;
+    const uint32_t E = rp->nexpl[tj];
+    const uint32_t A = E >> kb;  // explicit addresses
+    const uint32_t nct = min(rp->ncand[tj], ccap);
+    const uint32_t *__restrict__ cand = rp->cand + (size_t)tj * ccap;
+    const uint16_t *__restrict__ xl = pruned ? rp->xlist + (size_t)tj * D : nullptr;
+    const uint32_t ref = rp->ref[tj];
+    const uint64_t *__restrict__ badg = rp->badbits + (size_t)tj * ((D + 63) >> 6);
+
+    for (uint32_t j = tid; j <= nct; j += nthr) {  // slice boundaries
+      const int sj = j < nct ? (int)(cand[j] / (uint32_t)M) + 1 : T;
+      const int sp = j > 0 ? (int)(cand[j - 1] / (uint32_t)M) + 1 : 0;
+      for (int ss = sp + 1; ss <= sj; ++ss) sm.cstart[ss] = j;
+    }
+    if (pruned)
+      for (int w = tid; w < (D + 31) / 32; w += nthr)
+        sm.badl[w] = (uint32_t)(badg[w >> 1] >> (32 * (w & 1)));
+    // initial components: data-loading input after the first wall; the sign
+    // already holds every fetch phase its live tokens will pick up
+    for (uint32_t al = 0; al < apt; ++al) {
+      const uint32_t g = tid * apt + al;
+      if (g >= A) break;
+      const uint32_t a = xl ? xl[g] : g;
+      for (int b = 0; b < K2; ++b) {
+        const uint32_t live = ENC == QUBIT ? (uint32_t)b : kmask;
+        const bool sg = ENC == QUBIT && (__popc(live & mem[a] & kmask) & 1);
+        st[(al * K2 + b) * nthr + tid] = W_ALIVE | (live << W_LIVE_SH) | (sg ? W_SIGN : 0u);
+      }
+    }
+    __syncthreads();
+
+    bool ref_alive = pruned && ref != 0xFFFFFFFFu;
+    bool dev_any = false;    // uniform: some component of the block is tier 2
+    bool has_dev = false;    // this thread owns a tier-2 component
+    int njumps = 0, first_jump = 0;
+
+    for (int s = 1; s < T; ++s) {
+      const uint32_t cb = sm.cstart[s];
+      const int nc = (int)(sm.cstart[s + 1] - cb);
+      if (nc == 0 && !dev_any) continue;
+      const bool big = nc > NCS;
+      if (nc > 0) {
+        if (big) {
+          if (big_prev_nc > 0) {
+            for (int j = tid; j < big_prev_nc; j += nthr) {
+              const uint32_t q = cand[big_prev_cb + j] - (uint32_t)(big_prev_s - 1) * M;
+              sm.cbm[q >> 5] = 0;
+            }
+            __syncthreads();
+          }
+          for (int j = tid; j < nc; j += nthr) {
+            const uint32_t q = cand[cb + j] - (uint32_t)(s - 1) * M;
+            atomicOr(&sm.cbm[q >> 5], 1u << (q & 31));
+          }
+          big_prev_s = s;
+          big_prev_cb = (int)cb;
+          big_prev_nc = nc;
+        } else {
+          for (int j = tid; j < nc; j += nthr) {
+            const uint32_t q = cand[cb + j] - (uint32_t)(s - 1) * M;
+            const uint32_t v = q >> 1;
+            const int l = layer_of(v);
+            const uint32_t tk = tb->tok[s][l][q & 1u];
+            sm.cdec[j] = q | ((uint32_t)l << 16) | (tk << 20);
+          }
+        }
+        __syncthreads();
+      }
+
+      // pass H: tier-2 gates; which components does a candidate hit?
+      uint64_t hmask = 0;
+      double t2w[2] = {0.0, 0.0};  // tier-2 weights before this slice: empty, hit
+      if (nc > 0 || has_dev) {
+        for (uint32_t al = 0; al < apt; ++al) {
+          const uint32_t g = tid * apt + al;
+          if (g >= A) break;
+          const uint32_t a = xl ? xl[g] : g;
+          const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
+          bool ah = false, addr_done = false;
+          uint32_t dh = 0;
+          for (int b = 0; b < K2; ++b) {
+            const uint32_t j = al * K2 + b;
+            uint32_t w = st[j * nthr + tid];
+            if (!(w & W_ALIVE)) continue;
+            if (!(w & W_DEV)) {
+              if (nc == 0) continue;
+              if (!addr_done) {
+                t1_addr_hits<ENC>(tb, s, a, big, nc, sm.cdec, sm.cbm, ah, dh);
+                addr_done = true;
+              }
+              const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
+              const uint32_t df = ENC == QUBIT ? live : (live & memw & tb->dmask[s]);
+              if (ah || (df & dh)) hmask |= 1ull << j;
+              continue;
+            }
+            // tier 2: follow the gates of slice s literally
+            uint16_t *recp = pool + (size_t)(g * K2 + b) * rec;
+            const uint32_t cnt0 = recp[0];
+            const uint32_t e0 = w & W_E;
+            bool hit = false;
+            uint32_t cnt;
+            if (slow_all || cnt0 + 6 > (uint32_t)REG_CAP) {
+              Rec<ENC> R{recp};
+              t2_gates_mem<ENC>(tb, s, R, a, w, rp->err);
+              cnt = R.cnt();
+              if (nc > 0)
+                for (int q = 0; q < R.cnt() && !hit; ++q)
+                  hit = big ? cand_bm(sm.cbm, R.site(q)) : cand_list(sm.cdec, nc, R.site(q));
+            } else {
+              RList<ENC> L;
+              L.load(recp, cnt0);
+              t2_gates_reg<ENC>(tb, s, L, a, w, rp->err);
+              if (nc > 0) {
+#pragma unroll
+                for (int q = 0; q < REG_CAP; ++q) {
+                  const uint32_t x = L.get(q);
+                  if (x == EMPTY) continue;
+                  const uint32_t site = x & RList<ENC>::SM;
+                  hit |= big ? cand_bm(sm.cbm, site) : cand_list(sm.cdec, nc, site);
+                }
+              }
+              cnt = L.store(recp);
+            }
+            if (nc > 0) {
+              if (hit) {
+                hmask |= 1ull << j;
+                t2w[1] += wpow[e0];
+              } else {
+                t2w[0] += wpow[e0];
+              }
+            }
+            st[j * nthr + tid] = (w & ~W_E) | (e0 + cnt);  // K0 exposure as if J were empty
+          }
+        }
+      }
+      if (nc == 0) continue;
+      if (!__syncthreads_or(hmask != 0ull)) continue;  // J is empty
+
+      // a draw slice: weights of every component before this slice's layer
+      build_factors<ENC>(tb, s - 1, wpow, sm.fw, sm.fmisc, false);
+      if (tid == 0 && ENC == QUBIT) {
+        double sd = 0.0;
+        for (int b = 0; b < K2; ++b) sd += sm.fw[F_D + b];
+        sm.fmisc[2] = sd;
+      }
+      __syncthreads();
+      const double wr = sm.fmisc[0];
+      double acc[3] = {t2w[0], t2w[1], 0.0};  // w_empty, w_hit, good branches
+      for (uint32_t al = 0; al < apt; ++al) {
+        const uint32_t g = tid * apt + al;
+        if (g >= A) break;
+        const uint32_t a = xl ? xl[g] : g;
+        const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
+        const double wa = fA(sm.fw, a) * wr;
+        for (int b = 0; b < K2; ++b) {
+          const uint32_t j = al * K2 + b;
+          const uint32_t w = st[j * nthr + tid];
+          if (!(w & W_ALIVE) || (w & W_DEV)) continue;
+          const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
+          const uint32_t dv = ENC == QUBIT ? live : (live & memw);
+          const double wt = wa * sm.fw[F_D + dv] * sm.fw[F_K + (w & W_EK)];
+          if ((hmask >> j) & 1ull)
+            acc[1] += wt;
+          else
+            acc[0] += wt;
+        }
+      }
+      const double my_hit_w = acc[1];
+      if (ref_alive) {
+        // good branches other than the reference, on their no-jump orbits
+        for (int i = tid; i < D; i += nthr) {
+          if ((uint32_t)i == ref || ((sm.badl[i >> 5] >> (i & 31)) & 1u)) continue;
+          double x = fA(sm.fw, (uint32_t)i);
+          if (ENC == QUTRIT) x *= sm.fw[F_D + (mem[i] & kmask)];
+          acc[2] += x;
+        }
+      }
+      double *rbuf = sm.red + (s & 1) * (nthr >> 6) * 8;
+      block_sum<3>(acc, rbuf);
+      const double wgood = ref_alive ? acc[2] * (ENC == QUBIT ? sm.fmisc[2] : wr) : 0.0;
+      const double u = rp->forced ? rp->uaux[s] : uniform53(rp->seed, (uint32_t)s, 0, traj, 2u);
+      const double w0 = acc[0] + wgood;
+      const double r = u * (w0 + acc[1]);
+      if (r < w0) continue;  // J empty: K0 already accounted
+      const double r2 = r - w0;
+
+      // auxiliary component x*: the empty-mask block first, then the other
+      // components in slot order (initial-label order)
+      const double excl = block_excl_scan(my_hit_w, sm.scanb);
+      if (tid == 0) {
+        sm.misc[1] = -1;
+        sm.misc[2] = 0;
+      }
+      __syncthreads();
+      if (my_hit_w > 0.0 && excl <= r2) atomicMax(&sm.misc[1], tid);
+      __syncthreads();
+      if (sm.misc[1] == tid) {
+        double cum = excl;
+        int pick = -1, last = -1;
+        for (uint32_t al = 0; al < apt && pick < 0; ++al) {
+          const uint32_t g = tid * apt + al;
+          if (g >= A) break;
+          const uint32_t a = xl ? xl[g] : g;
+          const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
+          for (int b = 0; b < K2; ++b) {
+            const uint32_t j = al * K2 + b;
+            if (!((hmask >> j) & 1ull)) continue;
+            const uint32_t w = st[j * nthr + tid];
+            double wt;
+            if (!(w & W_DEV)) {
+              const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
+              const uint32_t dv = ENC == QUBIT ? live : (live & memw);
+              wt = fA(sm.fw, a) * wr * sm.fw[F_D + dv] * sm.fw[F_K + (w & W_EK)];
+            } else {
+              const uint32_t cnt = pool[(size_t)(g * K2 + b) * rec];
+              wt = wpow[(w & W_E) - cnt];
+            }
+            last = (int)j;
+            cum += wt;
+            if (cum > r2) {
+              pick = (int)j;
+              break;
+            }
+          }
+        }
+        if (pick < 0) pick = last;
+        // J = the slice's candidates among x*'s excited sites, with levels
+        int nJ = 0;
+        const uint32_t al = (uint32_t)pick / K2, b = (uint32_t)pick % K2;
+        const uint32_t g = tid * apt + al;
+        const uint32_t a = xl ? xl[g] : g;
+        const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
+        const uint32_t w = st[pick * nthr + tid];
+        if (!(w & W_DEV)) {
+          const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
+          if (!big) {
+            for (int c = 0; c < nc; ++c) {
+              const uint32_t q = sm.cdec[c] & 0xFFFFu;
+              const int lev = t1_level<ENC>(tb, s, a, live, memw, q);
+              if (lev && nJ < JMAX) sm.Jb[nJ++] = q | ((uint32_t)lev << 16);
+            }
+          } else {
+            for (int tk = 0; tk < n + tb->k; ++tk) {
+              const int q = t1_site(tb, s, a, tk);
+              if (q < 0 || !cand_bm(sm.cbm, (uint32_t)q)) continue;
+              const int lev = t1_level<ENC>(tb, s, a, live, memw, (uint32_t)q);
+              if (lev && nJ < JMAX) sm.Jb[nJ++] = (uint32_t)q | ((uint32_t)lev << 16);
+            }
+          }
+        } else {
+          Rec<ENC> R{pool + (size_t)(g * K2 + b) * rec};
+          for (int c = 0; c < R.cnt(); ++c) {
+            const uint32_t x = R.raw(c), q = x & Rec<ENC>::SM;
+            const bool isc = big ? cand_bm(sm.cbm, q) : cand_list(sm.cdec, nc, q);
+            if (!isc) continue;
+            const uint32_t lev = (ENC == QUTRIT && (x & LV_R_BIT)) ? 2u : 1u;
+            if (nJ < JMAX) sm.Jb[nJ++] = q | (lev << 16);
+          }
+        }
+        sm.misc[2] = nJ;
+      }
+      __syncthreads();
+      const int nJ = sm.misc[2];
+      if (nJ == 0) continue;
+
+      // K_J on every component: survivors carry every site of J
+      for (uint32_t al = 0; al < apt; ++al) {
+        const uint32_t g = tid * apt + al;
+        if (g >= A) break;
+        const uint32_t a = xl ? xl[g] : g;
+        const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
+        for (int b = 0; b < K2; ++b) {
+          const uint32_t j = al * K2 + b;
+          uint32_t w = st[j * nthr + tid];
+          if (!(w & W_ALIVE)) continue;
+          uint16_t *recp = pool + (size_t)(g * K2 + b) * rec;
+          if (!(w & W_DEV)) {
+            uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
+            bool ok = true, dev = false;
+            for (int c = 0; c < nJ && ok; ++c) {
+              const uint32_t x = sm.Jb[c], q = x & 0xFFFFu;
+              ok = t1_level<ENC>(tb, s, a, live, memw, q) == (int)(x >> 16);
+            }
+            if (!ok) {
+              st[j * nthr + tid] = 0u;
+              continue;
+            }
+            uint32_t kill = 0;
+            for (int c = 0; c < nJ; ++c) {
+              const uint32_t q = sm.Jb[c] & 0xFFFFu;
+              const uint32_t tk = tb->tok[s][layer_of(q >> 1)][q & 1u];
+              if (tk < (uint32_t)n)
+                dev = true;
+              else
+                kill |= 1u << (tk - (uint32_t)n);
+            }
+            if (dev) {
+              // exposure through slice s and the phases fetched so far
+              const uint32_t dv = ENC == QUBIT ? live : (live & memw);
+              const uint32_t e = t1_exposure<ENC>(tb, s, a, dv, w & W_EK) - (uint32_t)nJ;
+              uint32_t sign = w & W_SIGN;
+              if (ENC == QUBIT) {
+                uint32_t future = 0;
+                for (int bb = 0; bb < tb->k; ++bb)
+                  if (3 * n + 2 * bb + 1 > s) future |= 1u << bb;
+                if (__popc(live & mem[a] & future) & 1) sign ^= W_SIGN;
+              }
+              Rec<ENC> R{recp};
+              R.r[0] = 0;
+              uint32_t bus = 0;
+              for (int t = 0; t < n; ++t) {
+                const bool abit = (a >> (n - 1 - t)) & 1u;
+                const int q = t1_site(tb, s, a, t);
+                if (q < 0) continue;
+                if (ENC == QUTRIT && (q & 1) == 0) {
+                  if (!R.add((uint32_t)q | (abit ? LV_R_BIT : 0u), tb->lmax)) atomicOr(rp->err, ERR_LIST);
+                } else if (abit) {
+                  if (!R.add((uint32_t)q, tb->lmax)) atomicOr(rp->err, ERR_LIST);
+                }
+              }
+              for (int bb = 0; bb < tb->k; ++bb) {
+                const int q = t1_site(tb, s, a, n + bb);
+                if (ENC == QUBIT) {
+                  const bool lb = (live >> bb) & 1u;
+                  if (q >= 0) {
+                    if (lb && !R.add((uint32_t)q, tb->lmax)) atomicOr(rp->err, ERR_LIST);
+                  } else if (lb) {
+                    bus |= 1u << bb;  // not yet in, or already back on the bus
+                  }
+                } else {
+                  const bool vb = ((memw & live) >> bb) & 1u;
+                  if (q >= 0) {
+                    if (((tb->dmask[s] >> bb) & 1u) && vb && !R.add((uint32_t)q, tb->lmax))
+                      atomicOr(rp->err, ERR_LIST);
+                  } else if (s >= 4 * n + 2 * bb + 1 && vb) {
+                    bus |= 1u << bb;  // fetched value already on the bus
+                  }
+                }
+              }
+              R.r[1] = (uint16_t)bus;
+              for (int c = 0; c < nJ; ++c) {
+                const uint32_t x = sm.Jb[c], q = x & 0xFFFFu;
+                const uint32_t raw = (ENC == QUTRIT && (x >> 16) == 2u) ? (q | LV_R_BIT) : q;
+                const int jj = R.find_raw(raw);
+                if (jj >= 0) R.remove(jj);
+              }
+              w = (W_ALIVE | W_DEV | sign) | e;
+              has_dev = true;
+            } else {
+              uint32_t ek = w & W_EK;
+              uint32_t sign = w & W_SIGN;
+              for (int bb = 0; bb < tb->k; ++bb) {
+                if (!((kill >> bb) & 1u)) continue;
+                ek += tb->cntD[s - 1][bb];
+                // a token lost before its fetch never picks up the phase
+                if (ENC == QUBIT && s < 3 * n + 2 * bb + 1 && ((mem[a] >> bb) & 1u)) sign ^= W_SIGN;
+              }
+              live &= ~kill;
+              w = W_ALIVE | sign | (live << W_LIVE_SH) | ek;
+            }
+            st[j * nthr + tid] = w;
+          } else {
+            Rec<ENC> R{recp};
+            bool ok = true;
+            for (int c = 0; c < nJ && ok; ++c) {
+              const uint32_t x = sm.Jb[c], q = x & 0xFFFFu;
+              const uint32_t raw = (ENC == QUTRIT && (x >> 16) == 2u) ? (q | LV_R_BIT) : q;
+              const int jj = R.find_raw(raw);
+              if (jj < 0)
+                ok = false;
+              else
+                R.remove(jj);
+            }
+            if (!ok) {
+              st[j * nthr + tid] = 0u;
+              continue;
+            }
+            st[j * nthr + tid] = (w & ~W_E) | ((w & W_E) - (uint32_t)nJ);
+          }
+        }
+      }
+      ref_alive = false;  // a good branch never carries a candidate site
+      ++njumps;
+      if (!first_jump) first_jump = s;
+      dev_any = __syncthreads_or(has_dev) != 0;
+    }
+
+    if (big_prev_nc > 0) {  // leave the candidate bitmap clean
+      __syncthreads();
+      for (int j = tid; j < big_prev_nc; j += nthr) {
+        const uint32_t q = cand[big_prev_cb + j] - (uint32_t)(big_prev_s - 1) * M;
+        sm.cbm[q >> 5] = 0;
+      }
+      big_prev_nc = 0;
+    }
+
+    // second wall, tree measurement and fidelity (Alg. 1 steps 4-6)
+    __syncthreads();
+    build_factors<ENC>(tb, T - 1, wpow, sm.fw, sm.fmisc, false);
+    build_factors<ENC>(tb, T - 1, apow, sm.fa, sm.fmisc + 1, false);
+    if (tid == 0 && ENC == QUBIT) {
+      double sw = 0.0, sa = 0.0;
+      for (int b = 0; b < K2; ++b) {
+        sw += sm.fw[F_D + b];
+        sa += sm.fa[F_D + b];
+      }
+      sm.fmisc[2] = sw;
+      sm.fmisc[3] = sa;
+    }
+    __syncthreads();
+    const double wr = sm.fmisc[0], ar = sm.fmisc[1];
+    double fin[5] = {0, 0, 0, 0, 0};  // overlap, w_ground, w_total, good a-sum, good w-sum
+    for (uint32_t al = 0; al < apt; ++al) {
+      const uint32_t g = tid * apt + al;
+      if (g >= A) break;
+      const uint32_t a = xl ? xl[g] : g;
+      const uint32_t memw = mem[a] & kmask;
+      for (int b = 0; b < K2; ++b) {
+        const uint32_t j = al * K2 + b;
+        const uint32_t w = st[j * nthr + tid];
+        if (!(w & W_ALIVE)) continue;
+        double wt, at;
+        bool ground;
+        uint32_t bus;
+        if (!(w & W_DEV)) {
+          const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
+          const uint32_t dv = ENC == QUBIT ? live : (live & memw);
+          wt = fA(sm.fw, a) * wr * sm.fw[F_D + dv] * sm.fw[F_K + (w & W_EK)];
+          at = fA(sm.fa, a) * ar * sm.fa[F_D + dv] * sm.fa[F_K + (w & W_EK)];
+          ground = true;
+          bus = dv;
+        } else {
+          const uint16_t *recp = pool + (size_t)(g * K2 + b) * rec;
+          wt = wpow[w & W_E];
+          at = apow[w & W_E];
+          ground = recp[0] == 0;
+          bus = recp[1];
+        }
+        fin[2] += wt;
+        if (!ground) continue;
+        fin[1] += wt;
+        if (ENC == QUBIT) {
+          const bool neg = ((w & W_SIGN) != 0) ^ (bool)(__popc(bus & memw) & 1);
+          fin[0] += neg ? -at : at;
+        } else if (bus == memw) {
+          fin[0] += at;
+        }
+      }
+    }
+    if (ref_alive) {
+      for (int i = tid; i < D; i += nthr) {
+        if ((uint32_t)i == ref || ((sm.badl[i >> 5] >> (i & 31)) & 1u)) continue;
+        double xa = fA(sm.fa, (uint32_t)i), xw = fA(sm.fw, (uint32_t)i);
+        if (ENC == QUTRIT) {
+          xa *= sm.fa[F_D + (mem[i] & kmask)];
+          xw *= sm.fw[F_D + (mem[i] & kmask)];
+        }
+        fin[3] += xa;
+        fin[4] += xw;
+      }
+    }
+    block_sum<5>(fin, sm.red);
+    if (tid == 0) {
+      double ov = fin[0], wg = fin[1], wt = fin[2];
+      if (ref_alive) {  // the predicted good groups (Theorem 3 / Proposition 1)
+        const double sa = ENC == QUBIT ? sm.fmisc[3] : ar;
+        const double sw = ENC == QUBIT ? sm.fmisc[2] : wr;
+        ov += fin[3] * sa;
+        wg += fin[4] * sw;
+        wt += fin[4] * sw;
+      }
+      const double uf = rp->forced ? rp->ufin : uniform53(rp->seed, 0, 0, traj, 3u);
+      const bool qg = uf * wt < wg;
+      const double norm = 1.0 / ((double)D * (double)K2);
+      rp->fid[tj] = (qg && wg > 0.0) ? ov * ov / wg * norm : 0.0;
+      if (rp->st) {
+        qram_traj_stats o;
+        o.n_cand = rp->ncand[tj];
+        o.n_bad = rp->nbad[tj];
+        o.ref_addr = ref;
+        o.n_explicit = E;
+        o.n_jumps = (uint16_t)njumps;
+        o.first_jump_slice = (uint16_t)first_jump;
+        o.ref_survived = (uint8_t)(ref != 0xFFFFFFFFu && njumps == 0);
+        o.q_ground = (uint8_t)qg;
+        o.flags = (uint8_t)((rp->ncand[tj] > ccap ? 1 : 0));
+        o.pad = 0;
+        o.fid_pre = wt > 0.0 ? ov * ov / wt * norm : 0.0;
+        rp->st[tj] = o;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+uint32_t evolve_lds_bytes(int n, int k, int M, int D, int threads,
+                          uint32_t e_cap, bool state_lds) {
+  (void)n;
+  (void)k;
+  return fixed_bytes(M, D, threads) + (state_lds ? e_cap * 4u : 0u);
+}
+
+int evolve_occupancy(int enc, bool state_lds, int threads, uint32_t lds_bytes) {
+  int blocks = 0;
+  hipError_t e;
+  if (enc == QUBIT)
+    e = state_lds ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_evolve<QUBIT, true>, threads, lds_bytes)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_evolve<QUBIT, false>, threads, lds_bytes);
+  else
+    e = state_lds ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_evolve<QUTRIT, true>, threads, lds_bytes)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_evolve<QUTRIT, false>, threads, lds_bytes);
+  if (e != hipSuccess) return 0;
+  return blocks;
+}
+
+hipError_t evolve_prepare(int lds_max) {
+  hipError_t e = hipSuccess;
+  const void *fns[4] = {reinterpret_cast<const void *>(&k_evolve<QUBIT, true>),
+                        reinterpret_cast<const void *>(&k_evolve<QUBIT, false>),
+                        reinterpret_cast<const void *>(&k_evolve<QUTRIT, true>),
+                        reinterpret_cast<const void *>(&k_evolve<QUTRIT, false>)};
+  for (const void *f : fns) {
+    const hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    if (r != hipSuccess) e = r;
+  }
+  return e;
+}
+
+hipError_t launch_evolve(const Tables *tb, const Run &rp, int enc,
+                         uint32_t grid, int threads, uint32_t lds_bytes,
+                         bool state_lds, hipStream_t s) {
+  if (enc == QUBIT) {
+    if (state_lds)
+      hipLaunchKernelGGL((k_evolve<QUBIT, true>), dim3(grid), dim3(threads), lds_bytes, s, tb, rp);
+    else
+      hipLaunchKernelGGL((k_evolve<QUBIT, false>), dim3(grid), dim3(threads), lds_bytes, s, tb, rp);
+  } else {
+    if (state_lds)
+      hipLaunchKernelGGL((k_evolve<QUTRIT, true>), dim3(grid), dim3(threads), lds_bytes, s, tb, rp);
+    else
+      hipLaunchKernelGGL((k_evolve<QUTRIT, false>), dim3(grid), dim3(threads), lds_bytes, s, tb, rp);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace qr

@@ -1,7 +1,6 @@
 // Host side of the HIP library: contexts, schedule tables, work buffers,
-// launch sequence, autotuner and the C ABI declared in include/qram.h.
+// launch plans, autotuner and the C ABI declared in include/qram.h.
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -13,15 +12,30 @@
 using namespace qr;
 
 namespace {
-
 thread_local std::string g_create_error;
+}  // namespace
 
-struct DevBuf {
-  void *p = nullptr;
-  size_t bytes = 0;
+// One bucket of the evolution: trajectories with at most `emax` explicit
+// components, run by `grid` persistent workgroups of `threads` threads, each
+// thread holding `apt` addresses (apt * K2 component slots).
+struct BucketShape {
+  uint32_t emax = 0;
+  int threads = 64;
+  uint32_t apt = 1;
+  uint32_t e_cap = 0;
+  bool state_lds = false;
+  uint32_t lds = 0;
+  uint32_t grid = 1;
 };
 
-}  // namespace
+struct Plan {
+  int nb = 0;
+  BucketShape b[MAXB];
+  bool persistent = true;
+  uint32_t pool_slots = 0;  // max emax over buckets
+  uint32_t grid_max = 0;
+  uint32_t ecap_max = 0;
+};
 
 struct qram_ctx {
   int n = 0, k = 0, enc = 0;
@@ -40,21 +54,26 @@ struct qram_ctx {
   // work buffers (grown on demand)
   uint32_t batch_cap = 0;   // trajectories per batch the buffers hold
   uint32_t cand_cap = 0;    // candidate slots per trajectory
-  uint32_t grid_cap = 0;    // evolution workgroups the per-workgroup buffers hold
-  uint32_t ecap_cap = 0;    // tier-1 words per workgroup in gstate
+  size_t gstate_cap = 0;    // tier-1 words in gstate
+  size_t pool_cap = 0;      // uint16 words in pool
   uint32_t *cand = nullptr, *ncand = nullptr, *nbad = nullptr, *ref = nullptr;
   uint32_t *nexpl = nullptr, *order = nullptr, *counter = nullptr, *errw = nullptr;
+  uint32_t *bucket_base = nullptr;
   uint64_t *badbits = nullptr, *digest = nullptr;
   uint16_t *xlist = nullptr, *pool = nullptr;
   uint32_t *gstate = nullptr;
   double *fid_tmp = nullptr, *uaux = nullptr;
   qram_traj_stats *st_tmp = nullptr;
   uint32_t out_cap = 0;
-  // launch shape per mode
-  int threads[2] = {0, 0};
+  // launch choice per mode: slots per thread (0 = automatic), schedule
+  int spt[2] = {0, 0};
   int schedule[2] = {1, 1};
-  bool user_shape[2] = {false, false};
+  bool tier2_global = false;
   double last_ms[3] = {0, 0, 0};
+  // stage timing of asynchronous runs: four events per batch
+  bool timing = false;
+  std::vector<hipEvent_t> tev;
+  size_t tev_used = 0;
 };
 
 namespace {
@@ -236,6 +255,7 @@ bool build_tables(qram_ctx *c, std::string &why) {
       t.cntA[s][a] = (uint16_t)(t.cntA[s - 1][a] + ((am >> (n - 1 - a)) & 1u));
     for (int b = 0; b < k; ++b)
       t.cntD[s][b] = (uint16_t)(t.cntD[s - 1][b] + ((dm >> b) & 1u));
+    t.cntR[s] = (uint16_t)(t.cntR[s - 1] + nr);
   }
   for (int x = 0; x < ntok; ++x)
     if (pos[x] >= 0) {
@@ -245,6 +265,7 @@ bool build_tables(qram_ctx *c, std::string &why) {
   for (int s = T; s < MAXT; ++s) {
     for (int a = 0; a < n; ++a) t.cntA[s][a] = t.cntA[T - 1][a];
     for (int b = 0; b < k; ++b) t.cntD[s][b] = t.cntD[T - 1][b];
+    t.cntR[s] = t.cntR[T - 1];
   }
   return true;
 }
@@ -259,49 +280,62 @@ uint32_t cand_capacity(const qram_ctx *c) {
   return std::max<uint32_t>(r, 32u);
 }
 
-int default_threads(const qram_ctx *c, int mode) {
-  // explicit components per trajectory: all of them in full mode; the
-  // expected bad count plus one in pruned mode (Eq. eb) -- a rough guess
-  // that the autotuner replaces
-  const double E = (double)c->Emax;
-  double e = E;
-  if (mode == 1) {
-    const double pbad = std::min(1.0, 2.0 * (c->T - 1) * c->gamma * (c->n + 0.25 * (c->n - 1) * (c->n - 2)));
-    e = std::max(1.0, pbad * E + (c->enc == QUBIT ? c->K2 : 1));
+uint32_t pow2ceil(uint32_t x) {
+  uint32_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Launch plan of a mode.  The full mode evolves every address, so it has one
+// bucket.  The pruned mode's explicit work varies per trajectory (bad
+// addresses plus the reference), so trajectories are grouped by it, each
+// group with a workgroup size and LDS footprint sized for its largest member.
+qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
+  const int spt_target = c->spt[mode] ? c->spt[mode] : 16;
+  std::vector<uint32_t> ems;
+  if (mode == 0) {
+    ems.push_back((uint32_t)c->Emax);
+  } else {
+    for (uint32_t addrs = 64; ems.empty() || ems.back() < (uint32_t)c->Emax; addrs *= 4)
+      ems.push_back(std::min<uint32_t>((uint32_t)c->Emax, addrs * (uint32_t)c->K2));
+    while ((int)ems.size() > MAXB) ems.erase(ems.begin());
   }
-  if (e <= 256) return 64;
-  if (e <= 2048) return 128;
-  return 256;
+  pl = Plan{};
+  pl.nb = (int)ems.size();
+  pl.persistent = c->schedule[mode] == 1;
+  for (int i = 0; i < pl.nb; ++i) {
+    BucketShape &b = pl.b[i];
+    b.emax = ems[i];
+    const uint32_t addrs = b.emax / (uint32_t)c->K2;
+    uint32_t thr = pow2ceil((b.emax + spt_target - 1) / spt_target);
+    thr = std::max<uint32_t>(64u, std::min<uint32_t>(1024u, thr));
+    uint32_t apt = (addrs + thr - 1) / thr;
+    while (apt * (uint32_t)c->K2 > (uint32_t)MAXSPT && thr < 1024) {
+      thr *= 2;
+      apt = (addrs + thr - 1) / thr;
+    }
+    if (apt * (uint32_t)c->K2 > (uint32_t)MAXSPT)
+      return fail(c, QRAM_E_RANGE, "too many components per trajectory for one workgroup");
+    b.threads = (int)thr;
+    b.apt = apt;
+    b.e_cap = apt * (uint32_t)c->K2 * thr;
+    const uint32_t fixed = evolve_lds_bytes(c->n, c->k, c->M, c->D, b.threads, 0, false);
+    b.state_lds = fixed + b.e_cap * 4u <= std::min<size_t>(c->lds_max, 96u * 1024u);
+    b.lds = evolve_lds_bytes(c->n, c->k, c->M, c->D, b.threads, b.e_cap, b.state_lds);
+    if (b.lds > c->lds_max) return fail(c, QRAM_E_RANGE, "workgroup shared memory exceeds the device limit");
+    int occ = evolve_occupancy(c->enc, b.state_lds, b.threads, b.lds);
+    if (occ < 1) occ = 1;
+    b.grid = std::max<uint32_t>(1u, std::min<uint32_t>((uint32_t)(c->num_cu * occ), ntraj));
+    pl.pool_slots = std::max(pl.pool_slots, b.emax);
+    pl.grid_max = std::max(pl.grid_max, b.grid);
+    pl.ecap_max = std::max(pl.ecap_max, b.state_lds ? 0u : b.e_cap);
+  }
+  return QRAM_OK;
 }
 
-struct Shape {
-  int threads;
-  bool state_lds;
-  uint32_t e_cap;
-  uint32_t lds;
-  uint32_t grid;
-  bool persistent;
-};
-
-Shape make_shape(qram_ctx *c, int mode, uint32_t ntraj) {
-  Shape sh;
-  sh.threads = c->threads[mode] ? c->threads[mode] : default_threads(c, mode);
-  const uint32_t spt = (c->Emax + sh.threads - 1) / sh.threads;
-  sh.e_cap = spt * sh.threads;
-  const uint32_t fixed = evolve_lds_bytes(c->n, c->T, c->M, sh.threads, 0, false);
-  sh.state_lds = fixed + sh.e_cap * 4u <= 80u * 1024u && fixed + sh.e_cap * 4u <= c->lds_max;
-  sh.lds = evolve_lds_bytes(c->n, c->T, c->M, sh.threads, sh.e_cap, sh.state_lds);
-  int occ = evolve_occupancy(c->enc, sh.state_lds, sh.threads, sh.lds);
-  if (occ < 1) occ = 1;
-  uint32_t g = (uint32_t)(c->num_cu * occ);
-  sh.grid = std::max<uint32_t>(1u, std::min<uint32_t>(g, ntraj));
-  sh.persistent = c->schedule[mode] == 1;
-  return sh;
-}
-
-// Grow the per-trajectory buffers to hold `nb` trajectories and the
-// per-workgroup buffers to hold `grid` workgroups.
-qram_status ensure_buffers(qram_ctx *c, uint32_t nb, uint32_t grid, uint32_t e_cap) {
+// Grow the per-trajectory buffers to `nb` trajectories and the per-workgroup
+// buffers to the plan.
+qram_status ensure_buffers(qram_ctx *c, uint32_t nb, const Plan *pl) {
   qram_status st;
   if (nb > c->batch_cap || c->cand_cap == 0) {
     c->cand_cap = cand_capacity(c);
@@ -317,17 +351,24 @@ qram_status ensure_buffers(qram_ctx *c, uint32_t nb, uint32_t grid, uint32_t e_c
     c->batch_cap = nb;
   }
   if (!c->counter) {
-    if ((st = dev_alloc(c, &c->counter, 4))) return st;
+    if ((st = dev_alloc(c, &c->counter, MAXB))) return st;
+    if ((st = dev_alloc(c, &c->bucket_base, MAXB + 1))) return st;
     if ((st = dev_alloc(c, &c->errw, 4))) return st;
     HIPCHK(c, hipMemset(c->errw, 0, 16));
   }
-  if (grid > c->grid_cap || e_cap > c->ecap_cap) {
-    const uint32_t g = std::max(grid, c->grid_cap);
-    const uint32_t ec = std::max(e_cap, c->ecap_cap);
-    if ((st = dev_alloc(c, &c->gstate, (size_t)g * ec))) return st;
-    if ((st = dev_alloc(c, &c->pool, (size_t)g * c->Emax * c->rec))) return st;
-    c->grid_cap = g;
-    c->ecap_cap = ec;
+  if (pl) {
+    const size_t gs = (size_t)pl->grid_max * pl->ecap_max;
+    if (gs > c->gstate_cap) {
+      if ((st = dev_alloc(c, &c->gstate, gs))) return st;
+      c->gstate_cap = gs;
+    }
+    size_t ps = 0;
+    for (int i = 0; i < pl->nb; ++i)
+      ps = std::max(ps, (size_t)pl->b[i].grid * pl->pool_slots * c->rec);
+    if (ps > c->pool_cap) {
+      if ((st = dev_alloc(c, &c->pool, ps))) return st;
+      c->pool_cap = ps;
+    }
   }
   return QRAM_OK;
 }
@@ -341,16 +382,18 @@ uint32_t batch_size(const qram_ctx *c, uint32_t ntraj) {
   return std::min<uint32_t>(ntraj, (uint32_t)nb);
 }
 
-Run base_run(qram_ctx *c, int mode, uint64_t seed, const Shape &sh) {
+Run base_run(qram_ctx *c, int mode, uint64_t seed, const Plan *pl) {
   Run r{};
   r.seed = seed;
   r.mode = mode;
   r.cand_cap = c->cand_cap;
-  r.e_cap = sh.e_cap;
-  r.grid = sh.grid;
-  r.persistent = sh.persistent ? 1u : 0u;
-  r.state_lds = sh.state_lds ? 1u : 0u;
-  r.lds_bytes = sh.lds;
+  r.tier2_slow = c->tier2_global ? 1u : 0u;
+  if (pl) {
+    r.nbkt = (uint32_t)pl->nb;
+    for (int i = 0; i < pl->nb; ++i) r.bkt_emax[i] = pl->b[i].emax;
+    r.pool_slots = pl->pool_slots;
+    r.persistent = pl->persistent ? 1u : 0u;
+  }
   r.cand = c->cand;
   r.ncand = c->ncand;
   r.digest = c->digest;
@@ -360,6 +403,7 @@ Run base_run(qram_ctx *c, int mode, uint64_t seed, const Shape &sh) {
   r.xlist = c->xlist;
   r.nexpl = c->nexpl;
   r.order = c->order;
+  r.bucket_base = c->bucket_base;
   r.counter = c->counter;
   r.gstate = c->gstate;
   r.pool = c->pool;
@@ -371,20 +415,42 @@ uint32_t sample_grid(const qram_ctx *c, uint32_t ntraj) {
   return std::max<uint32_t>(1u, std::min<uint32_t>(ntraj, (uint32_t)c->num_cu * 8u));
 }
 
-// Enqueue sampling (unless forced), classification and evolution of one
-// batch on stream s.  With `timed`, events bracket the three stages.
-qram_status enqueue_batch(qram_ctx *c, int mode, const Shape &sh, Run r,
-                          hipStream_t s, bool timed, bool skip_sample) {
+qram_status launch_buckets(qram_ctx *c, const Plan &pl, Run r, hipStream_t s) {
+  for (int i = 0; i < pl.nb; ++i) {
+    const BucketShape &b = pl.b[i];
+    r.bucket = (uint32_t)i;
+    r.apt = b.apt;
+    r.e_cap = b.e_cap;
+    HIPCHK(c, launch_evolve(c->dtab, r, c->enc, b.grid, b.threads, b.lds, b.state_lds, s));
+  }
+  return QRAM_OK;
+}
+
+// Enqueue sampling (unless forced), classification, bucketing and evolution
+// of one batch on stream s.  With `timed`, events bracket the three stages.
+qram_status enqueue_batch(qram_ctx *c, const Plan &pl, Run r, hipStream_t s,
+                          bool timed, bool skip_sample) {
   const uint32_t nt = r.ntraj;
-  if (timed) HIPCHK(c, hipEventRecord(c->ev[0], s));
+  hipEvent_t e[4] = {c->ev[0], c->ev[1], c->ev[2], c->ev[3]};
+  if (!timed && c->timing) {  // async stage timing: four pooled events
+    while (c->tev.size() < c->tev_used + 4) {
+      hipEvent_t x;
+      HIPCHK(c, hipEventCreate(&x));
+      c->tev.push_back(x);
+    }
+    for (int i = 0; i < 4; ++i) e[i] = c->tev[c->tev_used + i];
+    c->tev_used += 4;
+    timed = true;
+  }
+  if (timed) HIPCHK(c, hipEventRecord(e[0], s));
   if (!skip_sample) HIPCHK(c, launch_sample(c->dtab, r, nt, sample_grid(c, nt), s));
-  if (timed) HIPCHK(c, hipEventRecord(c->ev[1], s));
+  if (timed) HIPCHK(c, hipEventRecord(e[1], s));
   HIPCHK(c, launch_classify(c->dtab, r, nt, sample_grid(c, nt), c->D, s));
-  if (sh.persistent) HIPCHK(c, launch_order(c->dtab, r, nt, s));
-  if (timed) HIPCHK(c, hipEventRecord(c->ev[2], s));
-  HIPCHK(c, launch_evolve(c->dtab, r, c->enc, sh.grid, sh.threads, sh.lds, sh.state_lds, s));
-  if (timed) HIPCHK(c, hipEventRecord(c->ev[3], s));
-  (void)mode;
+  HIPCHK(c, launch_order(c->dtab, r, s));
+  if (timed) HIPCHK(c, hipEventRecord(e[2], s));
+  qram_status st = launch_buckets(c, pl, r, s);
+  if (st) return st;
+  if (timed) HIPCHK(c, hipEventRecord(e[3], s));
   return QRAM_OK;
 }
 
@@ -428,18 +494,19 @@ qram_status run_mode(qram_ctx *c, int mode, uint64_t seed, uint64_t traj0,
   if (st) return st;
   if (ntraj == 0) return QRAM_OK;
   const uint32_t nb = batch_size(c, ntraj);
-  const Shape sh = make_shape(c, mode, nb);
-  if ((st = ensure_buffers(c, nb, sh.grid, sh.e_cap))) return st;
+  Plan pl;
+  if ((st = make_plan(c, mode, nb, pl))) return st;
+  if ((st = ensure_buffers(c, nb, &pl))) return st;
   if (sync && (st = ensure_out(c, nb))) return st;
   const bool timed = sync && ntraj <= nb;
   for (uint32_t b0 = 0; b0 < ntraj; b0 += nb) {
     const uint32_t cnt = std::min(nb, ntraj - b0);
-    Run r = base_run(c, mode, seed, sh);
+    Run r = base_run(c, mode, seed, &pl);
     r.traj0 = (uint32_t)(traj0 + b0);
     r.ntraj = cnt;
     r.fid = sync ? c->fid_tmp : d_fid + b0;
     r.st = sync ? (h_st ? c->st_tmp : nullptr) : (d_st ? d_st + b0 : nullptr);
-    if ((st = enqueue_batch(c, mode, sh, r, s, timed, false))) return st;
+    if ((st = enqueue_batch(c, pl, r, s, timed, false))) return st;
     if (sync) {
       HIPCHK(c, hipMemcpyAsync(h_fid + b0, c->fid_tmp, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
       if (h_st)
@@ -476,6 +543,8 @@ qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
   const int nmax = enc == QRAM_QUTRIT ? 14 : 15;
   if (n_addr < 1 || n_addr > nmax) return fail(nullptr, QRAM_E_RANGE, "n_addr out of range");
   if (k_data < 1 || k_data > 8 || k_data > n_addr) return fail(nullptr, QRAM_E_RANGE, "k_data out of range (1..8, k <= n)");
+  if (enc == QRAM_QUBIT && (k_data > 6 || n_addr + k_data > 16))
+    return fail(nullptr, QRAM_E_RANGE, "qubit encoding needs k <= 6 and n + k <= 16");
   qram_ctx *c = new (std::nothrow) qram_ctx();
   if (!c) return fail(nullptr, QRAM_E_NOMEM, "host allocation failed");
   c->n = n_addr;
@@ -492,7 +561,7 @@ qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
   // circuit adds at most one router per store/unstore and one per fetch
   c->lmax = c->enc == QUBIT ? 2 * n_addr + k_data : 4 * n_addr + k_data;
   c->emax = (c->T - 1) * c->lmax;
-  c->rec = c->lmax + 2;
+  c->rec = (c->lmax + 2 + 1) & ~1;
   const double lw = c->emax * std::log(1.0 - gamma);
   if (lw < -690.0) {
     delete c;
@@ -560,6 +629,7 @@ void qram_destroy(qram_ctx *c) {
   dev_free(&c->nexpl);
   dev_free(&c->order);
   dev_free(&c->counter);
+  dev_free(&c->bucket_base);
   dev_free(&c->errw);
   dev_free(&c->badbits);
   dev_free(&c->digest);
@@ -571,6 +641,7 @@ void qram_destroy(qram_ctx *c) {
   dev_free(&c->uaux);
   for (auto &e : c->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto &e : c->tev) (void)hipEventDestroy(e);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -589,15 +660,14 @@ qram_status qram_sample_faults(qram_ctx *c, uint64_t seed, uint64_t traj0,
   if (!n_cand) return fail(c, QRAM_E_INVAL, "n_cand is required");
   if (ntraj == 0) return QRAM_OK;
   const uint32_t nb = batch_size(c, ntraj);
-  const Shape sh = make_shape(c, 0, nb);
-  if ((st = ensure_buffers(c, nb, sh.grid, sh.e_cap))) return st;
+  if ((st = ensure_buffers(c, nb, nullptr))) return st;
   const int w64 = (c->D + 63) / 64;
   uint64_t written = 0;
   bool overflow = false;
   std::vector<uint32_t> hc;
   for (uint32_t b0 = 0; b0 < ntraj; b0 += nb) {
     const uint32_t cnt = std::min(nb, ntraj - b0);
-    Run r = base_run(c, 0, seed, sh);
+    Run r = base_run(c, 0, seed, nullptr);
     r.traj0 = (uint32_t)(traj0 + b0);
     r.ntraj = cnt;
     HIPCHK(c, launch_sample(c->dtab, r, cnt, sample_grid(c, cnt), c->stream));
@@ -674,26 +744,35 @@ qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,
   return QRAM_OK;
 }
 
-qram_status qram_set_launch(qram_ctx *c, qram_mode mode, int threads,
+qram_status qram_set_launch(qram_ctx *c, qram_mode mode, int slots_per_thread,
                             int schedule) {
   if (!c) return QRAM_E_INVAL;
   if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return fail(c, QRAM_E_INVAL, "bad mode");
-  if (threads != 0 && threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
-    return fail(c, QRAM_E_INVAL, "threads must be 64, 128, 256, 512 or 1024");
+  if (slots_per_thread != 0 && slots_per_thread != 4 && slots_per_thread != 8 && slots_per_thread != 16 &&
+      slots_per_thread != 32 && slots_per_thread != 64)
+    return fail(c, QRAM_E_INVAL, "slots_per_thread must be 0, 4, 8, 16, 32 or 64");
   if (schedule != 0 && schedule != 1) return fail(c, QRAM_E_INVAL, "schedule must be 0 or 1");
-  c->threads[mode] = threads;
+  c->spt[mode] = slots_per_thread;
   c->schedule[mode] = schedule;
-  c->user_shape[mode] = threads != 0;
   return QRAM_OK;
 }
 
-qram_status qram_get_launch(const qram_ctx *c, qram_mode mode, int *threads,
-                            int *schedule) {
-  if (!c || !threads || !schedule) return QRAM_E_INVAL;
+qram_status qram_get_launch(const qram_ctx *c, qram_mode mode,
+                            int *slots_per_thread, int *schedule) {
+  if (!c || !slots_per_thread || !schedule) return QRAM_E_INVAL;
   if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return QRAM_E_INVAL;
-  *threads = c->threads[mode] ? c->threads[mode] : default_threads(c, mode);
+  *slots_per_thread = c->spt[mode] ? c->spt[mode] : 16;
   *schedule = c->schedule[mode];
   return QRAM_OK;
+}
+
+qram_status qram_set_option(qram_ctx *c, int option, int value) {
+  if (!c) return QRAM_E_INVAL;
+  if (option == QRAM_OPT_TIER2_GLOBAL) {
+    c->tier2_global = value != 0;
+    return QRAM_OK;
+  }
+  return fail(c, QRAM_E_INVAL, "unknown option");
 }
 
 qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
@@ -704,19 +783,18 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
   if (ntraj == 0) return fail(c, QRAM_E_INVAL, "ntraj must be positive");
   const uint32_t nt = std::min(ntraj, batch_size(c, ntraj));
   if ((st = ensure_out(c, nt))) return st;
-  const int cand_threads[5] = {64, 128, 256, 512, 1024};
+  const int cands[5] = {4, 8, 16, 32, 64};
   double best = 1e300;
-  int bt = 0, bs = 1;
-  const int save_t = c->threads[mode], save_s = c->schedule[mode];
+  int bs = 16, bsched = 1;
   bool sampled = false;
   for (int sched = 0; sched < 2; ++sched) {
-    for (int ti = 0; ti < 5; ++ti) {
-      c->threads[mode] = cand_threads[ti];
+    for (int ci = 0; ci < 5; ++ci) {
+      c->spt[mode] = cands[ci];
       c->schedule[mode] = sched;
-      const Shape sh = make_shape(c, mode, nt);
-      if (sh.lds > c->lds_max) continue;
-      if ((st = ensure_buffers(c, nt, sh.grid, sh.e_cap))) return st;
-      Run r = base_run(c, mode, seed, sh);
+      Plan pl;
+      if (make_plan(c, mode, nt, pl) != QRAM_OK) continue;
+      if ((st = ensure_buffers(c, nt, &pl))) return st;
+      Run r = base_run(c, mode, seed, &pl);
       r.traj0 = (uint32_t)traj0;
       r.ntraj = nt;
       r.fid = c->fid_tmp;
@@ -728,9 +806,9 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
       double t_best = 1e300;
       for (int rep = 0; rep < 2; ++rep) {
         HIPCHK(c, launch_classify(c->dtab, r, nt, sample_grid(c, nt), c->D, c->stream));
-        if (sh.persistent) HIPCHK(c, launch_order(c->dtab, r, nt, c->stream));
+        HIPCHK(c, launch_order(c->dtab, r, c->stream));
         HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
-        HIPCHK(c, launch_evolve(c->dtab, r, c->enc, sh.grid, sh.threads, sh.lds, sh.state_lds, c->stream));
+        if ((st = launch_buckets(c, pl, r, c->stream))) return st;
         HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
         HIPCHK(c, hipEventSynchronize(c->ev[1]));
         float ms;
@@ -739,16 +817,13 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
       }
       if (t_best < best) {
         best = t_best;
-        bt = cand_threads[ti];
-        bs = sched;
+        bs = cands[ci];
+        bsched = sched;
       }
     }
   }
-  (void)save_t;
-  (void)save_s;
-  c->threads[mode] = bt;
-  c->schedule[mode] = bs;
-  c->user_shape[mode] = true;
+  c->spt[mode] = bs;
+  c->schedule[mode] = bsched;
   if (best_ms) *best_ms = best;
   return check_err(c);
 }
@@ -756,6 +831,31 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
 qram_status qram_last_kernel_ms(const qram_ctx *c, double *times) {
   if (!c || !times) return QRAM_E_INVAL;
   for (int i = 0; i < 3; ++i) times[i] = c->last_ms[i];
+  return QRAM_OK;
+}
+
+qram_status qram_set_timing(qram_ctx *c, int on) {
+  if (!c) return QRAM_E_INVAL;
+  c->timing = on != 0;
+  c->tev_used = 0;
+  return QRAM_OK;
+}
+
+qram_status qram_stage_times(qram_ctx *c, double *ms, uint32_t *nbatches) {
+  if (!c || !ms) return QRAM_E_INVAL;
+  HIPCHK(c, hipSetDevice(c->device));
+  ms[0] = ms[1] = ms[2] = 0.0;
+  const size_t nb = c->tev_used / 4;
+  for (size_t b = 0; b < nb; ++b) {
+    HIPCHK(c, hipEventSynchronize(c->tev[4 * b + 3]));
+    for (int i = 0; i < 3; ++i) {
+      float t;
+      HIPCHK(c, hipEventElapsedTime(&t, c->tev[4 * b + i], c->tev[4 * b + i + 1]));
+      ms[i] += t;
+    }
+  }
+  if (nbatches) *nbatches = (uint32_t)nb;
+  c->tev_used = 0;
   return QRAM_OK;
 }
 
@@ -771,13 +871,12 @@ qram_status qram_run_forced(qram_ctx *c, qram_mode mode, const uint32_t *cand_L,
     if (cand_L[j] >= S) return fail(c, QRAM_E_INVAL, "candidate index out of range");
     if (j && cand_L[j] <= cand_L[j - 1]) return fail(c, QRAM_E_INVAL, "candidates must be strictly ascending");
   }
-  const Shape sh0 = make_shape(c, mode, 1);
-  if ((st = ensure_buffers(c, 1, sh0.grid, sh0.e_cap))) return st;
+  Plan pl;
+  if ((st = make_plan(c, mode, 1, pl))) return st;
+  if ((st = ensure_buffers(c, 1, &pl))) return st;
   if (ncand > c->cand_cap) {
-    c->batch_cap = 0;  // regrow with a larger candidate capacity
-    const uint32_t need = ncand;
-    if ((st = dev_alloc(c, &c->cand, need))) return st;
-    c->cand_cap = need;
+    if ((st = dev_alloc(c, &c->cand, ncand))) return st;
+    c->cand_cap = ncand;
     c->batch_cap = 1;
   }
   if ((st = ensure_out(c, 1))) return st;
@@ -788,8 +887,7 @@ qram_status qram_run_forced(qram_ctx *c, qram_mode mode, const uint32_t *cand_L,
   HIPCHK(c, hipMemcpy(c->uaux, ua.data(), MAXT * 8, hipMemcpyHostToDevice));
   if (ncand) HIPCHK(c, hipMemcpy(c->cand, cand_L, ncand * 4, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->ncand, &ncand, 4, hipMemcpyHostToDevice));
-  Shape sh = sh0;
-  Run r = base_run(c, mode, 0, sh);
+  Run r = base_run(c, mode, 0, &pl);
   r.traj0 = 0;
   r.ntraj = 1;
   r.forced = 1;
@@ -797,7 +895,7 @@ qram_status qram_run_forced(qram_ctx *c, qram_mode mode, const uint32_t *cand_L,
   r.ufin = u_fin;
   r.fid = c->fid_tmp;
   r.st = c->st_tmp;
-  if ((st = enqueue_batch(c, mode, sh, r, c->stream, false, true))) return st;
+  if ((st = enqueue_batch(c, pl, r, c->stream, false, true))) return st;
   HIPCHK(c, hipMemcpyAsync(fid, c->fid_tmp, 8, hipMemcpyDeviceToHost, c->stream));
   if (stt) HIPCHK(c, hipMemcpyAsync(stt, c->st_tmp, sizeof(qram_traj_stats), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -16,27 +16,35 @@ constexpr int MAXT = 6 * MAXN + 2 * MAXK + 1;  // slices 0..T
 constexpr uint8_t NONE = 0xFF;
 constexpr int NCS = 16;    // a slice with at most NCS candidates is scanned as a list
 constexpr int JMAX = 64;   // joint outcome capacity (|J| <= excitations of one component)
+constexpr int MAXB = 6;    // work buckets of the evolution launches
+constexpr int MAXSPT = 64; // component slots per thread (one bit each in a mask)
 constexpr int QUTRIT = 0;
 constexpr int QUBIT = 1;
 
-// Tier-1 state word of an explicit component (address and initial bus word
-// are implied by its slot):
-//   bits  0..15 exposure e (excited sites summed over slices, K0 factors)
-//   bits 16..23 live data tokens (qubit: bus bits still carried; qutrit:
+// State word of an explicit component.  Its slot fixes its initial label
+// (address, bus word).  Tier 1 (no jump has touched its routing):
+//   bits  0..7  exposure carried by data tokens it lost
+//   bits  8..15 live data tokens (qubit: bus bits still carried; qutrit:
 //               data bits not yet lost)
-//   bit 24 sign, bit 25 alive, bit 26 deviated (site list in the pool)
+// Tier 2 (explicit site list in the pool):
+//   bits  0..15 exposure e (K0 factors so far)
+// Both: bit 24 sign, bit 25 alive, bit 26 tier 2, bit 27 slow list path.
+constexpr uint32_t W_EK = 0xFFu;
+constexpr int W_LIVE_SH = 8;
 constexpr uint32_t W_E = 0xFFFFu;
-constexpr int W_LIVE_SH = 16;
 constexpr uint32_t W_SIGN = 1u << 24;
 constexpr uint32_t W_ALIVE = 1u << 25;
 constexpr uint32_t W_DEV = 1u << 26;
+constexpr uint32_t W_SLOW = 1u << 27;
 
-// Tier-2 record in the pool: [0] count, [1] bus word, [2..] excited sites.
-// Qutrit router sites carry their level in bit 15 (set: R, clear: L).
+// Tier-2 record in the pool (uint16 words): [0] count, [1] bus word,
+// [2..] excited sites.  Qutrit router sites carry their level in bit 15
+// (set: R, clear: L).
 constexpr uint16_t LV_R_BIT = 0x8000u;
+constexpr int REG_CAP = 32;  // list entries held in registers
 
 struct Tables {
-  int n, k, enc, T, M, D, K2, lmax, emax, rec;  // rec = pool record length
+  int n, k, enc, T, M, D, K2, lmax, emax, rec;  // rec = pool record length (even)
   uint64_t G[64];                 // geometric-walk thresholds
   const uint32_t *mem;            // [D] memory words
   const double *wpow;             // [2 emax + 1] (1-gamma)^(m - emax)
@@ -50,6 +58,7 @@ struct Tables {
   uint8_t pos[MAXT][MAXN + MAXK];  // layer << 1 | slot of each token at s
   uint16_t cntA[MAXT][MAXN];       // exposure of address token t through s
   uint16_t cntD[MAXT][MAXK];       // exposure of data token b through s
+  uint16_t cntR[MAXT];             // qutrit: router exposure through s
 };
 
 struct Run {
@@ -57,12 +66,16 @@ struct Run {
   uint32_t traj0, ntraj;
   int mode;              // 0 full, 1 pruned
   uint32_t cand_cap;     // candidate slots per trajectory
-  uint32_t e_cap;        // explicit component slots per trajectory
-  uint32_t grid;         // workgroups of the evolution launch
-  uint32_t persistent;   // 1: dynamic queue over `order`
-  uint32_t state_lds;    // 1: tier-1 words live in LDS
-  uint32_t lds_bytes;    // dynamic LDS of the evolution kernel
   uint32_t forced;       // 1: forced history (single trajectory)
+  uint32_t tier2_slow;   // 1: every tier-2 list takes the global-memory path
+  // bucket of this evolution launch
+  uint32_t bucket;       // index of the bucket this launch serves
+  uint32_t apt;          // explicit addresses per thread
+  uint32_t e_cap;        // tier-1 words per workgroup (spt * threads)
+  uint32_t pool_slots;   // tier-2 records per workgroup
+  uint32_t persistent;   // 1: dynamic queue, 0: static round robin
+  uint32_t nbkt;         // buckets in use
+  uint32_t bkt_emax[MAXB];  // explicit components admitted by each bucket
   uint32_t *cand;        // [ntraj * cand_cap] ascending L
   uint32_t *ncand;       // [ntraj]
   uint64_t *digest;      // [ntraj]
@@ -71,10 +84,11 @@ struct Run {
   uint32_t *ref;         // [ntraj]
   uint16_t *xlist;       // [ntraj * D] explicit addresses (pruned)
   uint32_t *nexpl;       // [ntraj] explicit components
-  uint32_t *order;       // [ntraj] processing order
-  uint32_t *counter;     // [4] queue head and scratch
+  uint32_t *order;       // [ntraj] trajectories grouped by bucket
+  uint32_t *bucket_base; // [MAXB + 1]
+  uint32_t *counter;     // [MAXB] queue heads
   uint32_t *gstate;      // [grid * e_cap] tier-1 words when not in LDS
-  uint16_t *pool;        // [grid * e_cap * rec] tier-2 records
+  uint16_t *pool;        // [grid * pool_slots * rec] tier-2 records
   double *fid;           // [ntraj]
   qram_traj_stats *st;   // [ntraj] or null
   uint32_t *err;         // [1] error bits
@@ -85,20 +99,19 @@ struct Run {
 constexpr uint32_t ERR_CAND = 1u;
 constexpr uint32_t ERR_LIST = 2u;
 
-// Kernel launchers (qram_kernels.hip).
+// Kernel launchers.
 hipError_t launch_sample(const Tables *tb, const Run &rp, uint32_t ntraj,
                          uint32_t grid, hipStream_t s);
 hipError_t launch_classify(const Tables *tb, const Run &rp, uint32_t ntraj,
                            uint32_t grid, int D, hipStream_t s);
-hipError_t launch_order(const Tables *tb, const Run &rp, uint32_t ntraj,
-                        hipStream_t s);
+hipError_t launch_order(const Tables *tb, const Run &rp, hipStream_t s);
 hipError_t launch_evolve(const Tables *tb, const Run &rp, int enc,
                          uint32_t grid, int threads, uint32_t lds_bytes,
                          bool state_lds, hipStream_t s);
 hipError_t launch_digest(const Run &rp, uint32_t ntraj, hipStream_t s);
 
-uint32_t evolve_lds_bytes(int n, int T, int M, int threads, uint32_t e_cap,
-                          bool state_lds);
+uint32_t evolve_lds_bytes(int n, int k, int M, int D, int threads,
+                          uint32_t e_cap, bool state_lds);
 int evolve_occupancy(int enc, bool state_lds, int threads, uint32_t lds_bytes);
 hipError_t evolve_prepare(int lds_max);
 

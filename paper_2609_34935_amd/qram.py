@@ -30,8 +30,10 @@ EXPORTS = [
     "qram_create", "qram_destroy", "qram_last_error", "qram_sample_faults",
     "qram_run_full", "qram_run_pruned", "qram_run_full_async", "qram_run_pruned_async",
     "qram_fidelity", "qram_set_launch", "qram_get_launch", "qram_autotune",
-    "qram_last_kernel_ms", "qram_run_forced",
+    "qram_last_kernel_ms", "qram_set_timing", "qram_stage_times", "qram_set_option",
+    "qram_run_forced",
 ]
+QRAM_OPT_TIER2_GLOBAL = 1
 
 
 class QramError(RuntimeError):
@@ -72,6 +74,9 @@ def load_library(path: str = LIB_PATH):
     L.qram_autotune.argtypes = [vp, C.c_int, u64, u64, u32, p(f64)]
     L.qram_last_kernel_ms.argtypes = [vp, p(f64)]
     L.qram_run_forced.argtypes = [vp, C.c_int, p(u32), u32, p(f64), f64, p(f64), vp]
+    L.qram_set_timing.argtypes = [vp, C.c_int]
+    L.qram_stage_times.argtypes = [vp, p(f64), p(u32)]
+    L.qram_set_option.argtypes = [vp, C.c_int, C.c_int]
     for name in EXPORTS:
         if name not in ("qram_destroy", "qram_last_error"):
             getattr(L, name).restype = C.c_int
@@ -200,8 +205,11 @@ class QramContext:
         self._check(st, "qram_run_forced")
         return fid.value, st_arr[0]
 
-    def set_launch(self, mode, threads, schedule):
-        self._check(self._L.qram_set_launch(self._h, mode, threads, schedule), "qram_set_launch")
+    def set_launch(self, mode, slots_per_thread, schedule):
+        self._check(self._L.qram_set_launch(self._h, mode, slots_per_thread, schedule), "qram_set_launch")
+
+    def set_option(self, option, value):
+        self._check(self._L.qram_set_option(self._h, option, int(value)), "qram_set_option")
 
     def get_launch(self, mode):
         t, s = C.c_int(), C.c_int()
@@ -212,6 +220,16 @@ class QramContext:
         ms = C.c_double()
         self._check(self._L.qram_autotune(self._h, mode, seed, traj0, ntraj, C.byref(ms)), "qram_autotune")
         return ms.value
+
+    def set_timing(self, on=True):
+        self._check(self._L.qram_set_timing(self._h, 1 if on else 0), "qram_set_timing")
+
+    def stage_times(self):
+        """(ms of sampling, classification, evolution summed over batches, batches)."""
+        t = np.zeros(3)
+        nb = C.c_uint32()
+        self._check(self._L.qram_stage_times(self._h, _ptr(t, C.c_double), C.byref(nb)), "qram_stage_times")
+        return t, nb.value
 
     def last_kernel_ms(self):
         t = np.zeros(3)

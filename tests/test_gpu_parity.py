@@ -34,9 +34,11 @@ def oracle_ref(ri):
     return np.where(r < 0, 0xFFFFFFFF, r).astype(np.uint32)
 
 
-def compare_runs(P, orc, n, k, enc, gamma, mem, seed, traj0, ntraj, threads=None):
+def compare_runs(P, orc, n, k, enc, gamma, mem, seed, traj0, ntraj, threads=None, tier2_global=False):
     fo, fpo, so, _ = orc.run_batch(n, k, enc, gamma, mem, seed, traj0, ntraj)
     with P.QramContext(n, k, enc, gamma, mem) as ctx:
+        if tier2_global:
+            ctx.set_option(P.qram.QRAM_OPT_TIER2_GLOBAL, 1)
         out = {}
         for mode, fn in ((FULL, ctx.run_full), (PRUNED, ctx.run_pruned)):
             if threads:
@@ -112,6 +114,14 @@ def test_small_high_gamma(lib, orc, n, k, enc, gamma, ntraj):
     assert so[:, 4].sum() > 0  # jumps happened
 
 
+@pytest.mark.parametrize("n,k,enc,gamma,ntraj", [
+    (3, 2, QUBIT, 0.08, 300), (3, 1, QUTRIT, 0.08, 300), (4, 2, QUTRIT, 0.05, 200), (4, 4, QUBIT, 0.03, 100)])
+def test_small_high_gamma_global_lists(lib, orc, n, k, enc, gamma, ntraj):
+    """The same trajectories with every explicit site list in global memory."""
+    mem = memory_words(n, k, 77 + n)
+    compare_runs(lib, orc, n, k, enc, gamma, mem, 12345, 0, ntraj, tier2_global=True)
+
+
 def test_config1_qutrit_all_trajectories(lib, orc):
     """Qutrit n = 3, k = 1, gamma = 1e-3, 1000 trajectories, both modes."""
     mem = memory_words(3, 1, 1001)
@@ -125,10 +135,10 @@ def test_config2_qubit_sample(lib, orc, gamma):
     compare_runs(lib, orc, 6, 1, QUBIT, gamma, mem, 880002, 0, 400)
 
 
-@pytest.mark.parametrize("threads,sched", [(64, 0), (128, 1), (256, 0), (512, 1), (1024, 1)])
-def test_launch_shapes(lib, orc, threads, sched):
+@pytest.mark.parametrize("spt,sched", [(4, 0), (8, 1), (16, 0), (32, 1), (64, 1)])
+def test_launch_shapes(lib, orc, spt, sched):
     mem = memory_words(5, 3, 55)
-    compare_runs(lib, orc, 5, 3, QUBIT, 0.01, mem, 99, 0, 120, threads=(threads, sched))
+    compare_runs(lib, orc, 5, 3, QUBIT, 0.01, mem, 99, 0, 120, threads=(spt, sched))
 
 
 # ---------------------------------------------------------------------------
