@@ -12,6 +12,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed fp32 instructions in any generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the register-held site lists index their entries with unrolled loops
+    # only; a partial unroll would move them to scratch memory
+    "-mllvm", "-pragma-unroll-threshold=200000",
 ]
 
 

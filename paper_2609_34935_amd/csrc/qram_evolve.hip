@@ -24,6 +24,33 @@
 
 namespace qr {
 
+// Optional phase timers (build with -DQR_PHASE_TIMERS): wave 0 of every
+// workgroup adds the shader-clock cycles spent in each phase of the kernel.
+#ifdef QR_PHASE_TIMERS
+__device__ unsigned long long qr_phase_cycles[16];
+#define QR_TINIT unsigned long long qr_ph[8] = {0, 0, 0, 0, 0, 0, 0, 0}, qr_pn[8] = {0, 0, 0, 0, 0, 0, 0, 0}; \
+  unsigned long long qr_t = clock64();
+#define QR_TM(i)                               \
+  do {                                         \
+    const unsigned long long qr_n = clock64(); \
+    qr_ph[i] += qr_n - qr_t;                   \
+    qr_pn[i] += 1;                             \
+    qr_t = qr_n;                               \
+  } while (0)
+#define QR_TFLUSH                                                   \
+  if (threadIdx.x == 0)                                             \
+    for (int i = 0; i < 8; ++i) {                                   \
+      atomicAdd(&qr_phase_cycles[i], qr_ph[i]);                     \
+      atomicAdd(&qr_phase_cycles[8 + i], qr_pn[i]);                 \
+    }
+#else
+#define QR_TINIT
+#define QR_TM(i) \
+  do {           \
+  } while (0)
+#define QR_TFLUSH
+#endif
+
 namespace {
 
 constexpr uint32_t EMPTY = 0xFFFFu;
@@ -177,10 +204,12 @@ struct Rec {
 };
 
 // Gates of slice s on a global-memory list (schedule of Sec. II A, gate set
-// of App. C; qutrit stores gated by the parent's router).
+// of App. C; qutrit stores gated by the parent's router).  Returns the sign
+// picked up by the qubit fetch.
 template <int ENC>
-__device__ __attribute__((noinline)) void t2_gates_mem(const Tables *__restrict__ tb, int s, Rec<ENC> R,
-                             uint32_t a, uint32_t &word, uint32_t *err) {
+__device__ __attribute__((noinline)) uint32_t t2_gates_mem(const Tables *__restrict__ tb, int s,
+                                                           Rec<ENC> R, uint32_t a, uint32_t *err) {
+  uint32_t flip = 0;
   const int n = tb->n, lmax = tb->lmax;
   const int ct = tb->copy_t[s];
   if (ct >= 0 && ((a >> (n - 1 - ct)) & 1u)) {
@@ -275,7 +304,7 @@ __device__ __attribute__((noinline)) void t2_gates_mem(const Tables *__restrict_
         if (!(q & 1u) || (q >> 1) < v0) continue;
         const uint32_t v = q >> 1, p = v - v0;
         const uint32_t cell = 2 * p + (uint32_t)R.dir(v);
-        if ((tb->mem[cell] >> fb) & 1u) word ^= W_SIGN;
+        if ((tb->mem[cell] >> fb) & 1u) flip ^= W_SIGN;
       }
     } else {
       uint32_t c0 = 0, c1 = 0;  // cells' d-site targets of the leaf routers
@@ -304,15 +333,16 @@ __device__ __attribute__((noinline)) void t2_gates_mem(const Tables *__restrict_
       }
     }
   }
+  return flip;
 }
 
 // ---------------------------------------------------------------------------
-// tier 2, register list (fixed capacity, empty slots marked)
+// tier 2, register list (C entries, empty slots marked)
 // ---------------------------------------------------------------------------
-template <int ENC>
+template <int ENC, int C>
 struct RList {
-  // REG_CAP 16-bit entries, two per register; EMPTY marks a free entry
-  uint32_t p[REG_CAP / 2];
+  // C 16-bit entries, two per register; EMPTY marks a free entry
+  uint32_t p[C / 2];
   uint32_t bus;
   static constexpr uint32_t SM = ENC == QUTRIT ? 0x7FFFu : 0xFFFFu;
 
@@ -327,7 +357,7 @@ struct RList {
     const uint32_t *r32 = reinterpret_cast<const uint32_t *>(rec);
     bus = r32[0] >> 16;
 #pragma unroll
-    for (int j = 0; j < REG_CAP; j += 2) {
+    for (int j = 0; j < C; j += 2) {
       const uint32_t w = (uint32_t)j < cnt ? r32[1 + j / 2] : 0xFFFFFFFFu;
       const uint32_t lo = (uint32_t)j < cnt ? (w & 0xFFFFu) : EMPTY;
       const uint32_t hi = (uint32_t)(j + 1) < cnt ? (w >> 16) : EMPTY;
@@ -337,7 +367,7 @@ struct RList {
   __device__ __forceinline__ uint32_t store(uint16_t *rec) const {
     uint32_t pos = 0;
 #pragma unroll
-    for (int j = 0; j < REG_CAP; ++j) {
+    for (int j = 0; j < C; ++j) {
       const uint32_t x = get(j);
       if (x != EMPTY) {
         rec[2 + pos] = (uint16_t)x;
@@ -351,7 +381,7 @@ struct RList {
   __device__ __forceinline__ bool has(uint32_t q) const {
     bool f = false;
 #pragma unroll
-    for (int j = 0; j < REG_CAP; ++j) {
+    for (int j = 0; j < C; ++j) {
       const uint32_t x = get(j);
       f |= x != EMPTY && (x & SM) == q;
     }
@@ -359,7 +389,7 @@ struct RList {
   }
   __device__ __forceinline__ void remove_site(uint32_t q) {
 #pragma unroll
-    for (int j = 0; j < REG_CAP; ++j) {
+    for (int j = 0; j < C; ++j) {
       const uint32_t x = get(j);
       if (x != EMPTY && (x & SM) == q) set(j, EMPTY);
     }
@@ -367,7 +397,7 @@ struct RList {
   __device__ __forceinline__ bool add(uint32_t x) {
     bool placed = false;
 #pragma unroll
-    for (int j = 0; j < REG_CAP; ++j)
+    for (int j = 0; j < C; ++j)
       if (!placed && get(j) == EMPTY) {
         set(j, x);
         placed = true;
@@ -384,27 +414,42 @@ struct RList {
   __device__ __forceinline__ int dir(uint32_t v) const {
     int d = ENC == QUBIT ? 0 : -1;
 #pragma unroll
-    for (int j = 0; j < REG_CAP; ++j) {
+    for (int j = 0; j < C; ++j) {
       const uint32_t x = get(j);
       if (x != EMPTY && (x & SM) == 2 * v) d = ENC == QUBIT ? 1 : ((x & LV_R_BIT) ? 1 : 0);
     }
     return d;
   }
+  // does a candidate of the slice sit on one of the sites?
+  __device__ __forceinline__ bool hit(bool big, int nc, const uint32_t *cdec,
+                                      const uint32_t *cbm) const {
+    bool h = false;
+    if (big) {
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const uint32_t x = get(j);
+        if (x != EMPTY) h |= cand_bm(cbm, x & SM);
+      }
+    } else {
+      for (int c = 0; c < nc; ++c) h |= has(cdec[c] & 0xFFFFu);
+    }
+    return h;
+  }
 };
 
-template <int ENC>
-__device__ __attribute__((noinline)) void t2_gates_reg(const Tables *__restrict__ tb, int s, RList<ENC> &L,
-                             uint32_t a, uint32_t &word, uint32_t *err) {
+template <int ENC, int C>
+__device__ __forceinline__ void t2_gates_reg(const Tables *__restrict__ tb, int s,
+                                             RList<ENC, C> &L, uint32_t a,
+                                             uint32_t &word, bool &ovf) {
   const int n = tb->n;
-  constexpr uint32_t SM = RList<ENC>::SM;
-  bool ovf = false;
+  constexpr uint32_t SM = RList<ENC, C>::SM;
   const int ct = tb->copy_t[s];
   if (ct >= 0 && ((a >> (n - 1 - ct)) & 1u)) L.toggle(1, ovf);
   const int sl = tb->store_l[s];
   if (sl >= 0) {
     if (ENC == QUBIT) {
 #pragma unroll
-      for (int j = 0; j < REG_CAP; ++j) {
+      for (int j = 0; j < C; ++j) {
         const uint32_t x = L.get(j);
         if (x != EMPTY && layer_of(x >> 1) == sl) L.set(j, x ^ 1u);
       }
@@ -415,7 +460,7 @@ __device__ __attribute__((noinline)) void t2_gates_reg(const Tables *__restrict_
         ng = 1;
       } else {
 #pragma unroll
-        for (int j = 0; j < REG_CAP; ++j) {
+        for (int j = 0; j < C; ++j) {
           const uint32_t x = L.get(j);
           if (x == EMPTY || (x & 1u)) continue;
           const uint32_t v = (x & SM) >> 1;
@@ -429,7 +474,6 @@ __device__ __attribute__((noinline)) void t2_gates_reg(const Tables *__restrict_
           ++ng;
         }
       }
-#pragma unroll
       for (int g = 0; g < 4; ++g) {
         if (g >= ng) break;
         const uint32_t v = g == 0 ? g0 : g == 1 ? g1 : g == 2 ? g2 : g3;
@@ -452,7 +496,7 @@ __device__ __attribute__((noinline)) void t2_gates_reg(const Tables *__restrict_
   const uint32_t cm = tb->cswap[s];
   if (cm) {
 #pragma unroll
-    for (int j = 0; j < REG_CAP; ++j) {
+    for (int j = 0; j < C; ++j) {
       const uint32_t x = L.get(j);
       if (x == EMPTY || !(x & 1u)) continue;
       const uint32_t v = (x & SM) >> 1;
@@ -484,7 +528,7 @@ __device__ __attribute__((noinline)) void t2_gates_reg(const Tables *__restrict_
     const uint32_t v0 = (1u << (n - 1)) - 1u;
     if (ENC == QUBIT) {
 #pragma unroll
-      for (int j = 0; j < REG_CAP; ++j) {
+      for (int j = 0; j < C; ++j) {
         const uint32_t x = L.get(j);
         if (x == EMPTY || !(x & 1u) || (x >> 1) < v0) continue;
         const uint32_t v = x >> 1, p = v - v0;
@@ -494,7 +538,7 @@ __device__ __attribute__((noinline)) void t2_gates_reg(const Tables *__restrict_
       uint32_t c0 = 0, c1 = 0;
       int nl = 0;
 #pragma unroll
-      for (int j = 0; j < REG_CAP; ++j) {
+      for (int j = 0; j < C; ++j) {
         const uint32_t x = L.get(j);
         if (x == EMPTY || (x & 1u) || ((x & SM) >> 1) < v0) continue;
         const uint32_t v = (x & SM) >> 1;
@@ -509,7 +553,47 @@ __device__ __attribute__((noinline)) void t2_gates_reg(const Tables *__restrict_
       if (nl > 1 && c1 != EMPTY) L.toggle(c1, ovf);
     }
   }
+}
+
+// Gates of slice s on one tier-2 component whose record holds cnt0 entries;
+// returns the new count and whether a candidate of the slice sits on one of
+// its sites.  Short lists run in registers, long ones in global memory.
+template <int ENC>
+__device__ __forceinline__ uint32_t t2_step(const Tables *__restrict__ tb,
+                                            int s, uint16_t *recp,
+                                            uint32_t cnt0, uint32_t a,
+                                            uint32_t &word, bool slow, bool big,
+                                            int nc, const uint32_t *cdec,
+                                            const uint32_t *cbm, bool &hit,
+                                            uint32_t *err) {
+  // register capacities; the gates of one slice add at most `grow` entries
+  constexpr uint32_t C1 = ENC == QUBIT ? 16 : 24, C2 = ENC == QUBIT ? 24 : 32;
+  constexpr uint32_t grow = ENC == QUBIT ? 2 : 8;
+  bool ovf = false;
+  uint32_t cnt;
+  hit = false;
+  if (!slow && cnt0 + grow <= C1) {
+    RList<ENC, C1> L;
+    L.load(recp, cnt0);
+    t2_gates_reg<ENC, C1>(tb, s, L, a, word, ovf);
+    if (nc > 0) hit = L.hit(big, nc, cdec, cbm);
+    cnt = L.store(recp);
+  } else if (!slow && cnt0 + grow <= C2) {
+    RList<ENC, C2> L;
+    L.load(recp, cnt0);
+    t2_gates_reg<ENC, C2>(tb, s, L, a, word, ovf);
+    if (nc > 0) hit = L.hit(big, nc, cdec, cbm);
+    cnt = L.store(recp);
+  } else {
+    Rec<ENC> R{recp};
+    word ^= t2_gates_mem<ENC>(tb, s, R, a, err);
+    cnt = R.cnt();
+    if (nc > 0)
+      for (uint32_t q = 0; q < cnt && !hit; ++q)
+        hit = big ? cand_bm(cbm, R.site(q)) : cand_list(cdec, nc, R.site(q));
+  }
   if (ovf) atomicOr(err, ERR_LIST);
+  return cnt;
 }
 
 // ---------------------------------------------------------------------------
@@ -619,7 +703,7 @@ __device__ __forceinline__ double fA(const double *f, uint32_t a) {
 // the kernel
 // ---------------------------------------------------------------------------
 template <int ENC, bool SL>
-__global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
+__global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tables *__restrict__ tb,
                                                  const Run R_) {
   const Run *rp = &R_;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -635,6 +719,7 @@ __global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
   uint32_t *st = SL ? sm.st : rp->gstate + (size_t)blockIdx.x * rp->e_cap;
   const int rec = tb->rec;
   uint16_t *pool = rp->pool + (size_t)blockIdx.x * rp->pool_slots * rec;
+  uint16_t *devl = rp->devl + (size_t)blockIdx.x * rp->pool_slots;
   const bool pruned = rp->mode == 1;
   const uint32_t ccap = rp->cand_cap;
   const uint32_t apt = rp->apt;
@@ -646,6 +731,7 @@ __global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
   build_factors<ENC>(tb, 0, apow, sm.fa, sm.fmisc + 1, true);
   for (int w = tid; w < (M + 31) / 32; w += nthr) sm.cbm[w] = 0u;
 
+  QR_TINIT
   const uint32_t seg0 = rp->bucket_base[bkt];
   const uint32_t segn = rp->bucket_base[bkt + 1] - seg0;
   for (uint32_t iter = 0;; ++iter) {
@@ -690,16 +776,16 @@ __global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
       }
     }
     __syncthreads();
+    QR_TM(0);
 
     bool ref_alive = pruned && ref != 0xFFFFFFFFu;
-    bool dev_any = false;    // uniform: some component of the block is tier 2
-    bool has_dev = false;    // this thread owns a tier-2 component
+    uint32_t ndev = 0;  // tier-2 components of the block (listed in devl)
     int njumps = 0, first_jump = 0;
 
     for (int s = 1; s < T; ++s) {
       const uint32_t cb = sm.cstart[s];
       const int nc = (int)(sm.cstart[s + 1] - cb);
-      if (nc == 0 && !dev_any) continue;
+      if (nc == 0 && ndev == 0) continue;
       const bool big = nc > NCS;
       if (nc > 0) {
         if (big) {
@@ -728,86 +814,63 @@ __global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
         }
         __syncthreads();
       }
+      QR_TM(1);
 
-      // pass H: tier-2 gates; which components does a candidate hit?
+      // tier-2 pass: the listed components follow the gates of slice s
+      // literally, spread over all threads of the block
+      for (uint32_t i = tid; i < ndev; i += nthr) {
+        const uint32_t c = devl[i];
+        const uint32_t g = c >> kb, b = c & (uint32_t)(K2 - 1);
+        const uint32_t ow = g / apt, al = g - ow * apt;
+        const uint32_t widx = (al * K2 + b) * nthr + ow;
+        const uint32_t a = xl ? xl[g] : g;
+        uint32_t w = st[widx];
+        const uint32_t cnt0 = (w & W_CNT) >> W_CNT_SH;
+        const uint32_t e = (w & W_E) + cnt0;  // exposure through slice s-1
+        bool hit;
+        const uint32_t cnt = t2_step<ENC>(tb, s, pool + (size_t)c * rec, cnt0, a, w, slow_all, big, nc,
+                                          sm.cdec, sm.cbm, hit, rp->err);
+        st[widx] = (w & (W_SIGN | W_ALIVE | W_DEV)) | e | (cnt << W_CNT_SH) | (hit ? W_HIT : 0u);
+      }
+      QR_TM(2);
+      if (nc == 0) continue;
+      if (ndev > 0) __syncthreads();
+
+      // owner pass: which of my components does a candidate hit?
       uint64_t hmask = 0;
-      double t2w[2] = {0.0, 0.0};  // tier-2 weights before this slice: empty, hit
-      if (nc > 0 || has_dev) {
-        for (uint32_t al = 0; al < apt; ++al) {
-          const uint32_t g = tid * apt + al;
-          if (g >= A) break;
-          const uint32_t a = xl ? xl[g] : g;
-          const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
-          bool ah = false, addr_done = false;
-          uint32_t dh = 0;
-          for (int b = 0; b < K2; ++b) {
-            const uint32_t j = al * K2 + b;
-            uint32_t w = st[j * nthr + tid];
-            if (!(w & W_ALIVE)) continue;
-            if (!(w & W_DEV)) {
-              if (nc == 0) continue;
-              if (!addr_done) {
-                t1_addr_hits<ENC>(tb, s, a, big, nc, sm.cdec, sm.cbm, ah, dh);
-                addr_done = true;
-              }
-              const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
-              const uint32_t df = ENC == QUBIT ? live : (live & memw & tb->dmask[s]);
-              if (ah || (df & dh)) hmask |= 1ull << j;
-              continue;
-            }
-            // tier 2: follow the gates of slice s literally
-            uint16_t *recp = pool + (size_t)(g * K2 + b) * rec;
-            const uint32_t cnt0 = recp[0];
-            const uint32_t e0 = w & W_E;
-            bool hit = false;
-            uint32_t cnt;
-            if (slow_all || cnt0 + 6 > (uint32_t)REG_CAP) {
-              Rec<ENC> R{recp};
-              t2_gates_mem<ENC>(tb, s, R, a, w, rp->err);
-              cnt = R.cnt();
-              if (nc > 0)
-                for (int q = 0; q < R.cnt() && !hit; ++q)
-                  hit = big ? cand_bm(sm.cbm, R.site(q)) : cand_list(sm.cdec, nc, R.site(q));
-            } else {
-              RList<ENC> L;
-              L.load(recp, cnt0);
-              t2_gates_reg<ENC>(tb, s, L, a, w, rp->err);
-              if (nc > 0) {
-#pragma unroll
-                for (int q = 0; q < REG_CAP; ++q) {
-                  const uint32_t x = L.get(q);
-                  if (x == EMPTY) continue;
-                  const uint32_t site = x & RList<ENC>::SM;
-                  hit |= big ? cand_bm(sm.cbm, site) : cand_list(sm.cdec, nc, site);
-                }
-              }
-              cnt = L.store(recp);
-            }
-            if (nc > 0) {
-              if (hit) {
-                hmask |= 1ull << j;
-                t2w[1] += wpow[e0];
-              } else {
-                t2w[0] += wpow[e0];
-              }
-            }
-            st[j * nthr + tid] = (w & ~W_E) | (e0 + cnt);  // K0 exposure as if J were empty
+      for (uint32_t al = 0; al < apt; ++al) {
+        const uint32_t g = tid * apt + al;
+        if (g >= A) break;
+        const uint32_t a = xl ? xl[g] : g;
+        const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
+        bool ah = false, addr_done = false;
+        uint32_t dh = 0;
+        for (int b = 0; b < K2; ++b) {
+          const uint32_t j = al * K2 + b;
+          const uint32_t w = st[j * nthr + tid];
+          if (!(w & W_ALIVE)) continue;
+          if (w & W_DEV) {
+            if (w & W_HIT) hmask |= 1ull << j;
+            continue;
           }
+          if (!addr_done) {
+            t1_addr_hits<ENC>(tb, s, a, big, nc, sm.cdec, sm.cbm, ah, dh);
+            addr_done = true;
+          }
+          const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
+          const uint32_t df = ENC == QUBIT ? live : (live & memw & tb->dmask[s]);
+          if (ah || (df & dh)) hmask |= 1ull << j;
         }
       }
-      if (nc == 0) continue;
-      if (!__syncthreads_or(hmask != 0ull)) continue;  // J is empty
+      const bool any_hit = __syncthreads_or(hmask != 0ull);
+      QR_TM(2);
+      if (!any_hit) continue;  // J is empty
 
       // a draw slice: weights of every component before this slice's layer
       build_factors<ENC>(tb, s - 1, wpow, sm.fw, sm.fmisc, false);
-      if (tid == 0 && ENC == QUBIT) {
-        double sd = 0.0;
-        for (int b = 0; b < K2; ++b) sd += sm.fw[F_D + b];
-        sm.fmisc[2] = sd;
-      }
       __syncthreads();
       const double wr = sm.fmisc[0];
-      double acc[3] = {t2w[0], t2w[1], 0.0};  // w_empty, w_hit, good branches
+      double acc[3] = {0.0, 0.0, 0.0};  // w_empty, w_hit, good branches
       for (uint32_t al = 0; al < apt; ++al) {
         const uint32_t g = tid * apt + al;
         if (g >= A) break;
@@ -817,10 +880,15 @@ __global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
         for (int b = 0; b < K2; ++b) {
           const uint32_t j = al * K2 + b;
           const uint32_t w = st[j * nthr + tid];
-          if (!(w & W_ALIVE) || (w & W_DEV)) continue;
-          const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
-          const uint32_t dv = ENC == QUBIT ? live : (live & memw);
-          const double wt = wa * sm.fw[F_D + dv] * sm.fw[F_K + (w & W_EK)];
+          if (!(w & W_ALIVE)) continue;
+          double wt;
+          if (w & W_DEV) {
+            wt = wpow[w & W_E];
+          } else {
+            const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
+            const uint32_t dv = ENC == QUBIT ? live : (live & memw);
+            wt = wa * sm.fw[F_D + dv] * sm.fw[F_K + (w & W_EK)];
+          }
           if ((hmask >> j) & 1ull)
             acc[1] += wt;
           else
@@ -839,7 +907,13 @@ __global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
       }
       double *rbuf = sm.red + (s & 1) * (nthr >> 6) * 8;
       block_sum<3>(acc, rbuf);
-      const double wgood = ref_alive ? acc[2] * (ENC == QUBIT ? sm.fmisc[2] : wr) : 0.0;
+      QR_TM(3);
+      double sd = wr;  // qutrit: the router factor; qubit: the bus-word sum
+      if (ENC == QUBIT) {
+        sd = 0.0;
+        for (int b = 0; b < K2; ++b) sd += sm.fw[F_D + b];
+      }
+      const double wgood = ref_alive ? acc[2] * sd : 0.0;
       const double u = rp->forced ? rp->uaux[s] : uniform53(rp->seed, (uint32_t)s, 0, traj, 2u);
       const double w0 = acc[0] + wgood;
       const double r = u * (w0 + acc[1]);
@@ -874,8 +948,7 @@ __global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
               const uint32_t dv = ENC == QUBIT ? live : (live & memw);
               wt = fA(sm.fw, a) * wr * sm.fw[F_D + dv] * sm.fw[F_K + (w & W_EK)];
             } else {
-              const uint32_t cnt = pool[(size_t)(g * K2 + b) * rec];
-              wt = wpow[(w & W_E) - cnt];
+              wt = wpow[w & W_E];
             }
             last = (int)j;
             cum += wt;
@@ -923,9 +996,11 @@ __global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
       }
       __syncthreads();
       const int nJ = sm.misc[2];
+      QR_TM(4);
       if (nJ == 0) continue;
 
       // K_J on every component: survivors carry every site of J
+      uint32_t mydev = 0;
       for (uint32_t al = 0; al < apt; ++al) {
         const uint32_t g = tid * apt + al;
         if (g >= A) break;
@@ -1006,8 +1081,8 @@ __global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
                 const int jj = R.find_raw(raw);
                 if (jj >= 0) R.remove(jj);
               }
-              w = (W_ALIVE | W_DEV | sign) | e;
-              has_dev = true;
+              const uint32_t cnt = (uint32_t)R.cnt();
+              w = (W_ALIVE | W_DEV | sign) | (e - cnt) | (cnt << W_CNT_SH);
             } else {
               uint32_t ek = w & W_EK;
               uint32_t sign = w & W_SIGN;
@@ -1020,7 +1095,6 @@ __global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
               live &= ~kill;
               w = W_ALIVE | sign | (live << W_LIVE_SH) | ek;
             }
-            st[j * nthr + tid] = w;
           } else {
             Rec<ENC> R{recp};
             bool ok = true;
@@ -1037,14 +1111,32 @@ __global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
               st[j * nthr + tid] = 0u;
               continue;
             }
-            st[j * nthr + tid] = (w & ~W_E) | ((w & W_E) - (uint32_t)nJ);
+            const uint32_t cnt = ((w & W_CNT) >> W_CNT_SH) - (uint32_t)nJ;
+            w = (w & (W_SIGN | W_ALIVE | W_DEV | W_E)) | (cnt << W_CNT_SH);
           }
+          st[j * nthr + tid] = w;
+          if (w & W_DEV) ++mydev;
         }
       }
       ref_alive = false;  // a good branch never carries a candidate site
       ++njumps;
       if (!first_jump) first_jump = s;
-      dev_any = __syncthreads_or(has_dev) != 0;
+      // rebuild the tier-2 work list in slot order
+      {
+        uint32_t tot;
+        uint32_t pos = block_excl_scan_u32(mydev, reinterpret_cast<uint32_t *>(sm.scanb), &tot);
+        for (uint32_t al = 0; al < apt && mydev > 0; ++al) {
+          const uint32_t g = tid * apt + al;
+          if (g >= A) break;
+          for (int b = 0; b < K2; ++b) {
+            const uint32_t w = st[(al * K2 + b) * nthr + tid];
+            if ((w & (W_ALIVE | W_DEV)) == (W_ALIVE | W_DEV)) devl[pos++] = (uint16_t)(g * K2 + b);
+          }
+        }
+        ndev = tot;
+        __syncthreads();
+      }
+      QR_TM(5);
     }
 
     if (big_prev_nc > 0) {  // leave the candidate bitmap clean
@@ -1060,15 +1152,6 @@ __global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
     __syncthreads();
     build_factors<ENC>(tb, T - 1, wpow, sm.fw, sm.fmisc, false);
     build_factors<ENC>(tb, T - 1, apow, sm.fa, sm.fmisc + 1, false);
-    if (tid == 0 && ENC == QUBIT) {
-      double sw = 0.0, sa = 0.0;
-      for (int b = 0; b < K2; ++b) {
-        sw += sm.fw[F_D + b];
-        sa += sm.fa[F_D + b];
-      }
-      sm.fmisc[2] = sw;
-      sm.fmisc[3] = sa;
-    }
     __syncthreads();
     const double wr = sm.fmisc[0], ar = sm.fmisc[1];
     double fin[5] = {0, 0, 0, 0, 0};  // overlap, w_ground, w_total, good a-sum, good w-sum
@@ -1092,11 +1175,12 @@ __global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
           ground = true;
           bus = dv;
         } else {
-          const uint16_t *recp = pool + (size_t)(g * K2 + b) * rec;
-          wt = wpow[w & W_E];
-          at = apow[w & W_E];
-          ground = recp[0] == 0;
-          bus = recp[1];
+          const uint32_t cnt = (w & W_CNT) >> W_CNT_SH;
+          const uint32_t e = (w & W_E) + cnt;
+          wt = wpow[e];
+          at = apow[e];
+          ground = cnt == 0;
+          bus = pool[(size_t)(g * K2 + b) * rec + 1];
         }
         fin[2] += wt;
         if (!ground) continue;
@@ -1125,8 +1209,14 @@ __global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
     if (tid == 0) {
       double ov = fin[0], wg = fin[1], wt = fin[2];
       if (ref_alive) {  // the predicted good groups (Theorem 3 / Proposition 1)
-        const double sa = ENC == QUBIT ? sm.fmisc[3] : ar;
-        const double sw = ENC == QUBIT ? sm.fmisc[2] : wr;
+        double sa = ar, sw = wr;
+        if (ENC == QUBIT) {
+          sa = sw = 0.0;
+          for (int b = 0; b < K2; ++b) {
+            sw += sm.fw[F_D + b];
+            sa += sm.fa[F_D + b];
+          }
+        }
         ov += fin[3] * sa;
         wg += fin[4] * sw;
         wt += fin[4] * sw;
@@ -1151,7 +1241,9 @@ __global__ void __launch_bounds__(1024) k_evolve(const Tables *__restrict__ tb,
         rp->st[tj] = o;
       }
     }
+    QR_TM(6);
   }
+  QR_TFLUSH
 }
 
 }  // namespace
@@ -1175,6 +1267,17 @@ int evolve_occupancy(int enc, bool state_lds, int threads, uint32_t lds_bytes) {
   if (e != hipSuccess) return 0;
   return blocks;
 }
+
+#ifdef QR_PHASE_TIMERS
+extern "C" int qram_probe_phase_cycles(unsigned long long *out, int reset) {
+  hipError_t e = hipMemcpyFromSymbol(out, HIP_SYMBOL(qr_phase_cycles), sizeof(unsigned long long) * 16);
+  if (reset) {
+    unsigned long long z[16] = {};
+    e = hipMemcpyToSymbol(HIP_SYMBOL(qr_phase_cycles), z, sizeof(z));
+  }
+  return (int)e;
+}
+#endif
 
 hipError_t evolve_prepare(int lds_max) {
   hipError_t e = hipSuccess;

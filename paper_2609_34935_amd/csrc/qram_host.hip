@@ -56,11 +56,12 @@ struct qram_ctx {
   uint32_t cand_cap = 0;    // candidate slots per trajectory
   size_t gstate_cap = 0;    // tier-1 words in gstate
   size_t pool_cap = 0;      // uint16 words in pool
+  size_t devl_cap = 0;      // uint16 words in devl
   uint32_t *cand = nullptr, *ncand = nullptr, *nbad = nullptr, *ref = nullptr;
   uint32_t *nexpl = nullptr, *order = nullptr, *counter = nullptr, *errw = nullptr;
   uint32_t *bucket_base = nullptr;
   uint64_t *badbits = nullptr, *digest = nullptr;
-  uint16_t *xlist = nullptr, *pool = nullptr;
+  uint16_t *xlist = nullptr, *pool = nullptr, *devl = nullptr;
   uint32_t *gstate = nullptr;
   double *fid_tmp = nullptr, *uaux = nullptr;
   qram_traj_stats *st_tmp = nullptr;
@@ -307,10 +308,11 @@ qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
     BucketShape &b = pl.b[i];
     b.emax = ems[i];
     const uint32_t addrs = b.emax / (uint32_t)c->K2;
+    const uint32_t tmax = (uint32_t)EVOLVE_MAX_THREADS[c->enc];
     uint32_t thr = pow2ceil((b.emax + spt_target - 1) / spt_target);
-    thr = std::max<uint32_t>(64u, std::min<uint32_t>(1024u, thr));
+    thr = std::max<uint32_t>(64u, std::min<uint32_t>(tmax, thr));
     uint32_t apt = (addrs + thr - 1) / thr;
-    while (apt * (uint32_t)c->K2 > (uint32_t)MAXSPT && thr < 1024) {
+    while (apt * (uint32_t)c->K2 > (uint32_t)MAXSPT && thr < tmax) {
       thr *= 2;
       apt = (addrs + thr - 1) / thr;
     }
@@ -369,6 +371,12 @@ qram_status ensure_buffers(qram_ctx *c, uint32_t nb, const Plan *pl) {
       if ((st = dev_alloc(c, &c->pool, ps))) return st;
       c->pool_cap = ps;
     }
+    size_t ds = 0;
+    for (int i = 0; i < pl->nb; ++i) ds = std::max(ds, (size_t)pl->b[i].grid * pl->pool_slots);
+    if (ds > c->devl_cap) {
+      if ((st = dev_alloc(c, &c->devl, ds))) return st;
+      c->devl_cap = ds;
+    }
   }
   return QRAM_OK;
 }
@@ -407,6 +415,7 @@ Run base_run(qram_ctx *c, int mode, uint64_t seed, const Plan *pl) {
   r.counter = c->counter;
   r.gstate = c->gstate;
   r.pool = c->pool;
+  r.devl = c->devl;
   r.err = c->errw;
   return r;
 }
@@ -635,6 +644,7 @@ void qram_destroy(qram_ctx *c) {
   dev_free(&c->digest);
   dev_free(&c->xlist);
   dev_free(&c->pool);
+  dev_free(&c->devl);
   dev_free(&c->gstate);
   dev_free(&c->fid_tmp);
   dev_free(&c->st_tmp);

@@ -27,21 +27,26 @@ constexpr int QUBIT = 1;
 //   bits  8..15 live data tokens (qubit: bus bits still carried; qutrit:
 //               data bits not yet lost)
 // Tier 2 (explicit site list in the pool):
-//   bits  0..15 exposure e (K0 factors so far)
-// Both: bit 24 sign, bit 25 alive, bit 26 tier 2, bit 27 slow list path.
+//   bits  0..15 exposure through the previous slice
+//   bits 16..23 excited sites now (the record's count)
+//   bit  28     a candidate of this slice sits on one of its sites
+// Both: bit 24 sign, bit 25 alive, bit 26 tier 2.
 constexpr uint32_t W_EK = 0xFFu;
 constexpr int W_LIVE_SH = 8;
 constexpr uint32_t W_E = 0xFFFFu;
+constexpr int W_CNT_SH = 16;
+constexpr uint32_t W_CNT = 0xFFu << W_CNT_SH;
 constexpr uint32_t W_SIGN = 1u << 24;
 constexpr uint32_t W_ALIVE = 1u << 25;
 constexpr uint32_t W_DEV = 1u << 26;
-constexpr uint32_t W_SLOW = 1u << 27;
+constexpr uint32_t W_HIT = 1u << 28;
 
 // Tier-2 record in the pool (uint16 words): [0] count, [1] bus word,
 // [2..] excited sites.  Qutrit router sites carry their level in bit 15
 // (set: R, clear: L).
 constexpr uint16_t LV_R_BIT = 0x8000u;
-constexpr int REG_CAP = 32;  // list entries held in registers
+// Largest evolution workgroup of each encoding.
+constexpr int EVOLVE_MAX_THREADS[2] = {512, 1024};
 
 struct Tables {
   int n, k, enc, T, M, D, K2, lmax, emax, rec;  // rec = pool record length (even)
@@ -89,6 +94,7 @@ struct Run {
   uint32_t *counter;     // [MAXB] queue heads
   uint32_t *gstate;      // [grid * e_cap] tier-1 words when not in LDS
   uint16_t *pool;        // [grid * pool_slots * rec] tier-2 records
+  uint16_t *devl;        // [grid * pool_slots] tier-2 work list
   double *fid;           // [ntraj]
   qram_traj_stats *st;   // [ntraj] or null
   uint32_t *err;         // [1] error bits
