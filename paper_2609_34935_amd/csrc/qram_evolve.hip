@@ -92,6 +92,14 @@ __device__ __forceinline__ int t1_site(const Tables *__restrict__ tb, int s,
   return (int)(2 * v + slot);
 }
 
+// Bit b set for every b that is a subset of c (c below 2^k).
+__device__ __forceinline__ uint64_t subsets_of(uint32_t c, int k) {
+  uint64_t m = 1;
+  for (int i = 0; i < k; ++i)
+    if ((c >> i) & 1u) m |= m << (1u << i);
+  return m;
+}
+
 __device__ __forceinline__ bool cand_bm(const uint32_t *cbm, uint32_t q) {
   return (cbm[q >> 5] >> (q & 31)) & 1u;
 }
@@ -712,6 +720,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
   const int K2 = ENC == QUBIT ? tb->K2 : 1;
   const int kb = ENC == QUBIT ? tb->k : 0;
   const uint32_t kmask = (1u << tb->k) - 1u;
+  const uint64_t kfull = K2 >= 64 ? ~0ull : ((1ull << K2) - 1ull);
   const double *__restrict__ wpow = tb->wpow + emax;
   const double *__restrict__ apow = tb->apow + emax;
   const uint32_t *__restrict__ mem = tb->mem;
@@ -832,12 +841,31 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
                                           sm.cdec, sm.cbm, hit, rp->err);
         st[widx] = (w & (W_SIGN | W_ALIVE | W_DEV)) | e | (cnt << W_CNT_SH) | (hit ? W_HIT : 0u);
       }
-      QR_TM(2);
+      QR_TM(7);
       if (nc == 0) continue;
       if (ndev > 0) __syncthreads();
 
       // owner pass: which of my components does a candidate hit?
       uint64_t hmask = 0;
+      if (njumps == 0) {
+        // no jump so far: every component still has its initial label, so
+        // the hits follow from the address alone (qubit: bus word b is hit
+        // when it shares a live token with a hit data site)
+        for (uint32_t al = 0; al < apt; ++al) {
+          const uint32_t g = tid * apt + al;
+          if (g >= A) break;
+          const uint32_t a = xl ? xl[g] : g;
+          bool ah;
+          uint32_t dh;
+          t1_addr_hits<ENC>(tb, s, a, big, nc, sm.cdec, sm.cbm, ah, dh);
+          uint64_t m;
+          if (ENC == QUBIT)
+            m = ah ? kfull : (kfull & ~subsets_of(~dh & kmask, tb->k));
+          else
+            m = (ah || (mem[a] & kmask & tb->dmask[s] & dh)) ? 1ull : 0ull;
+          hmask |= m << (al * K2);
+        }
+      } else
       for (uint32_t al = 0; al < apt; ++al) {
         const uint32_t g = tid * apt + al;
         if (g >= A) break;
@@ -877,6 +905,16 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
         const uint32_t a = xl ? xl[g] : g;
         const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
         const double wa = fA(sm.fw, a) * wr;
+        if (njumps == 0) {  // initial labels: live tokens = bus word (qubit), every bit (qutrit)
+          for (int b = 0; b < K2; ++b) {
+            const double wt = wa * sm.fw[F_D + (ENC == QUBIT ? (uint32_t)b : (kmask & memw))];
+            if ((hmask >> (al * K2 + b)) & 1ull)
+              acc[1] += wt;
+            else
+              acc[0] += wt;
+          }
+          continue;
+        }
         for (int b = 0; b < K2; ++b) {
           const uint32_t j = al * K2 + b;
           const uint32_t w = st[j * nthr + tid];
