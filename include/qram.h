@@ -171,12 +171,18 @@ qram_status qram_get_launch(const qram_ctx *ctx, qram_mode mode,
                             int *slots_per_thread, int *schedule);
 
 /*
- * Options.  QRAM_OPT_TIER2_GLOBAL (value 0/1): keep every explicit site list
- * of a component whose routing a jump changed in global memory instead of
- * registers (same results; for testing the two list paths against each
- * other).
+ * Options (value 0/1; both default to 0).
+ *   QRAM_OPT_TIER2_GLOBAL: keep every explicit site list of a component whose
+ *     routing a jump changed in global memory instead of registers (same
+ *     results; for testing the two list paths against each other).
+ *   QRAM_OPT_GRAPH: run each batch (sampling, classification, bucketing and
+ *     every bucket's persistent evolution launch) as one HIP graph.  The
+ *     graph is captured on the context's stream, instantiated once and then
+ *     updated in place for the next batch, and launched on the caller's
+ *     stream.  Results are identical to the eager path.  Stage timing then
+ *     reports the whole batch as the evolution stage.
  */
-enum { QRAM_OPT_TIER2_GLOBAL = 1 };
+enum { QRAM_OPT_TIER2_GLOBAL = 1, QRAM_OPT_GRAPH = 2 };
 qram_status qram_set_option(qram_ctx *ctx, int option, int value);
 
 /*

@@ -70,6 +70,10 @@ struct qram_ctx {
   int spt[2] = {0, 0};
   int schedule[2] = {1, 1};
   bool tier2_global = false;
+  // graph mode: every batch is captured once into a graph and replayed;
+  // the executable graph is updated in place for the next batch
+  bool use_graph = false;
+  hipGraphExec_t gexec = nullptr;
   double last_ms[3] = {0, 0, 0};
   // stage timing of asynchronous runs: four events per batch
   bool timing = false;
@@ -438,10 +442,11 @@ qram_status launch_buckets(qram_ctx *c, const Plan &pl, Run r, hipStream_t s) {
 // Enqueue sampling (unless forced), classification, bucketing and evolution
 // of one batch on stream s.  With `timed`, events bracket the three stages.
 qram_status enqueue_batch(qram_ctx *c, const Plan &pl, Run r, hipStream_t s,
-                          bool timed, bool skip_sample) {
+                          bool timed, bool skip_sample, bool capture = false) {
   const uint32_t nt = r.ntraj;
   hipEvent_t e[4] = {c->ev[0], c->ev[1], c->ev[2], c->ev[3]};
-  if (!timed && c->timing) {  // async stage timing: four pooled events
+  if (capture) timed = false;
+  if (!timed && !capture && c->timing) {  // async stage timing: four pooled events
     while (c->tev.size() < c->tev_used + 4) {
       hipEvent_t x;
       HIPCHK(c, hipEventCreate(&x));
@@ -460,6 +465,44 @@ qram_status enqueue_batch(qram_ctx *c, const Plan &pl, Run r, hipStream_t s,
   qram_status st = launch_buckets(c, pl, r, s);
   if (st) return st;
   if (timed) HIPCHK(c, hipEventRecord(e[3], s));
+  return QRAM_OK;
+}
+
+// The batch as one graph: captured on the context's stream, instantiated
+// once (or updated in place when the executable graph exists) and launched
+// on stream s.  The captured work holds no memset node.
+qram_status launch_batch_graph(qram_ctx *c, const Plan &pl, const Run &r,
+                               hipStream_t s) {
+  hipGraph_t g = nullptr;
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  qram_status st = enqueue_batch(c, pl, r, c->stream, false, false, true);
+  const hipError_t ec = hipStreamEndCapture(c->stream, &g);
+  if (st) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  HIPCHK(c, ec);
+  bool ok = false;
+  if (c->gexec) {
+    hipGraphNode_t bad = nullptr;
+    hipGraphExecUpdateResult res;
+    ok = hipGraphExecUpdate(c->gexec, g, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(c->gexec);
+      c->gexec = nullptr;
+    }
+  }
+  if (!ok) {
+    const hipError_t ei = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      c->gexec = nullptr;
+      (void)hipGraphDestroy(g);
+      HIPCHK(c, ei);
+    }
+  }
+  (void)hipGraphDestroy(g);
+  HIPCHK(c, hipGraphLaunch(c->gexec, s));
   return QRAM_OK;
 }
 
@@ -515,7 +558,13 @@ qram_status run_mode(qram_ctx *c, int mode, uint64_t seed, uint64_t traj0,
     r.ntraj = cnt;
     r.fid = sync ? c->fid_tmp : d_fid + b0;
     r.st = sync ? (h_st ? c->st_tmp : nullptr) : (d_st ? d_st + b0 : nullptr);
-    if ((st = enqueue_batch(c, pl, r, s, timed, false))) return st;
+    if (c->use_graph) {
+      if (timed) HIPCHK(c, hipEventRecord(c->ev[0], s));
+      if ((st = launch_batch_graph(c, pl, r, s))) return st;
+      if (timed) HIPCHK(c, hipEventRecord(c->ev[3], s));
+    } else if ((st = enqueue_batch(c, pl, r, s, timed, false))) {
+      return st;
+    }
     if (sync) {
       HIPCHK(c, hipMemcpyAsync(h_fid + b0, c->fid_tmp, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
       if (h_st)
@@ -524,7 +573,12 @@ qram_status run_mode(qram_ctx *c, int mode, uint64_t seed, uint64_t traj0,
     }
   }
   if (sync) {
-    if (timed) {
+    if (timed && c->use_graph) {  // one graph: the whole batch counts as evolution
+      float ms;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[3]));
+      c->last_ms[0] = c->last_ms[1] = 0.0;
+      c->last_ms[2] = ms;
+    } else if (timed) {
       float ms;
       for (int i = 0; i < 3; ++i) {
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
@@ -652,6 +706,7 @@ void qram_destroy(qram_ctx *c) {
   for (auto &e : c->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto &e : c->tev) (void)hipEventDestroy(e);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -780,6 +835,10 @@ qram_status qram_set_option(qram_ctx *c, int option, int value) {
   if (!c) return QRAM_E_INVAL;
   if (option == QRAM_OPT_TIER2_GLOBAL) {
     c->tier2_global = value != 0;
+    return QRAM_OK;
+  }
+  if (option == QRAM_OPT_GRAPH) {
+    c->use_graph = value != 0;
     return QRAM_OK;
   }
   return fail(c, QRAM_E_INVAL, "unknown option");

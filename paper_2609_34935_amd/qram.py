@@ -34,6 +34,7 @@ EXPORTS = [
     "qram_run_forced",
 ]
 QRAM_OPT_TIER2_GLOBAL = 1
+QRAM_OPT_GRAPH = 2
 
 
 class QramError(RuntimeError):

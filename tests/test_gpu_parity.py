@@ -284,3 +284,40 @@ def test_async_device_buffers(lib):
         assert np.array_equal(d_f.cpu().numpy(), ref_f)
         st = np.frombuffer(d_s.cpu().numpy().tobytes(), dtype=lib.STATS_DTYPE)
         assert np.array_equal(st, ref_s)
+
+
+# ---------------------------------------------------------------------------
+# graph mode: each batch captured once, updated in place and replayed
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("enc", [QUBIT, QUTRIT])
+def test_graph_replays_match_eager(lib, enc):
+    import torch
+    n, k, gamma = 8, 2, 3e-3
+    mem = memory_words(n, k, 13)
+    calls = [(7, 0, 600), (7, 600, 600), (8, 0, 600), (7, 0, 600), (9, 17, 250), (9, 17, 250)]
+    with lib.QramContext(n, k, enc, gamma, mem) as eager, lib.QramContext(n, k, enc, gamma, mem) as g:
+        g.set_option(lib.qram.QRAM_OPT_GRAPH, 1)
+        for mode in (FULL, PRUNED):
+            for seed, traj0, nt in calls:
+                fe, se = (eager.run_pruned if mode else eager.run_full)(seed, traj0, nt)
+                # unrelated device work between replays
+                x = torch.randn(1 << 16, device="cuda", dtype=torch.float64)
+                torch.cuda.synchronize()
+                fg, sg = (g.run_pruned if mode else g.run_full)(seed, traj0, nt)
+                assert float((x * x).sum()) > 0
+                assert np.array_equal(fg, fe), (mode, seed, traj0, nt)
+                assert np.array_equal(sg, se), (mode, seed, traj0, nt)
+
+
+def test_graph_async_streams(lib):
+    import torch
+    n, k = 6, 1
+    mem = memory_words(n, k, 14)
+    with lib.QramContext(n, k, QUBIT, 1e-3, mem) as ctx:
+        ref_f, _ = ctx.run_pruned(42, 0, 1000)
+        ctx.set_option(lib.qram.QRAM_OPT_GRAPH, 1)
+        for stream in (torch.cuda.Stream(), None, torch.cuda.Stream()):
+            d_f = torch.full((1000,), -1.0, dtype=torch.float64, device="cuda")
+            ctx.run_pruned_async(42, 0, 1000, d_f, None, stream=stream)
+            torch.cuda.synchronize()
+            assert np.array_equal(d_f.cpu().numpy(), ref_f)
