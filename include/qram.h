@@ -221,6 +221,75 @@ qram_status qram_run_forced(qram_ctx *ctx, qram_mode mode,
                             const double *u_aux, double u_fin, double *fid,
                             qram_traj_stats *st);
 
+/*
+ * Device memory.  qram_footprint: bytes of device memory the context holds
+ * for runs of `mode` with up to ntraj trajectories per call (its tables plus
+ * the work buffers of one batch; the caller's output arrays not included).
+ * Allocates nothing.  qram_reserve: allocate those buffers now, so that such
+ * runs allocate nothing later.  qram_errors: after the caller has waited for
+ * its stream, report (QRAM_E_CAPACITY) and clear a capacity overflow that a
+ * *_async run flagged on the device.
+ */
+qram_status qram_footprint(qram_ctx *ctx, qram_mode mode, uint32_t ntraj,
+                           uint64_t *bytes);
+qram_status qram_reserve(qram_ctx *ctx, qram_mode mode, uint32_t ntraj);
+qram_status qram_errors(qram_ctx *ctx);
+
+/*
+ * Request server: continuous batching of simulation requests on the current
+ * device.  A host thread owns one context per admitted request.  Requests
+ * are admitted in arrival order as soon as an execution slot is free
+ * (max_active slots, one HIP stream each) and their footprint fits the
+ * budget: qram_footprint for chunks of `chunk` trajectories plus 8 bytes per
+ * shot for the device-resident results.  An admitted request runs `chunk`
+ * trajectories per launch on its slot's stream, so chunks of different
+ * requests overlap on the device.  A request's results are those of
+ * qram_run_{full,pruned}(seed, traj0, shots) on its own context, whatever
+ * else is in flight.  The server copies memory_bits at submission and owns
+ * all memory it allocates; a request larger than the budget fails with
+ * QRAM_E_CAPACITY.  The functions are thread-safe.
+ */
+typedef struct qram_server qram_server;
+
+typedef struct {
+  int n_addr, k_data;
+  qram_encoding enc;
+  double gamma;
+  const uint32_t *memory_bits; /* host, 2^n words; copied */
+  uint64_t seed, traj0;
+  uint32_t shots;              /* trajectories */
+  qram_mode mode;
+} qram_request;
+
+typedef struct {
+  uint64_t ticket;
+  int state;                /* 0 waiting, 1 running, 2 done, 3 failed */
+  qram_status status;       /* failure reason when state is 3 */
+  double mean, sem;         /* fidelity estimate when state is 2 */
+  uint32_t shots;
+  uint64_t footprint_bytes; /* admission footprint */
+  double queue_ms;          /* submission to admission */
+  double latency_ms;        /* submission to results on the host */
+} qram_result;
+
+qram_status qram_server_create(uint64_t hbm_budget_bytes, int max_active,
+                               uint32_t chunk, qram_server **out);
+qram_status qram_server_submit(qram_server *srv, const qram_request *req,
+                               uint64_t *ticket);
+/* Current state of a request (does not wait). */
+qram_status qram_server_poll(qram_server *srv, uint64_t ticket,
+                             qram_result *res);
+/* Wait until the request is done or failed, or timeout_ms (<0: no limit). */
+qram_status qram_server_wait(qram_server *srv, uint64_t ticket,
+                             double timeout_ms, qram_result *res);
+/* Per-trajectory fidelities of a finished request (fid[n], n >= shots). */
+qram_status qram_server_fidelities(qram_server *srv, uint64_t ticket,
+                                   double *fid, uint32_t n);
+/* Forget a finished request. */
+qram_status qram_server_release(qram_server *srv, uint64_t ticket);
+/* Finish every submitted request, then stop the thread and free all. */
+void qram_server_destroy(qram_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

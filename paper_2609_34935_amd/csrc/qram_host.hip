@@ -385,6 +385,28 @@ qram_status ensure_buffers(qram_ctx *c, uint32_t nb, const Plan *pl) {
   return QRAM_OK;
 }
 
+// Device bytes of the work buffers that batches of nb trajectories need
+// under plan pl (what ensure_buffers allocates), and of the context's tables.
+size_t buffers_bytes(const qram_ctx *c, uint32_t nb, const Plan &pl) {
+  const size_t n = nb;
+  size_t b = n * cand_capacity(c) * 4 + n * 5 * 4 + n * 8 + n * ((c->D + 63) / 64) * 8 + n * c->D * 2;
+  b += (2 * MAXB + 1 + 4) * 4;
+  b += (size_t)pl.grid_max * pl.ecap_max * 4;
+  size_t ps = 0, ds = 0;
+  for (int i = 0; i < pl.nb; ++i) {
+    ps = std::max(ps, (size_t)pl.b[i].grid * pl.pool_slots * c->rec);
+    ds = std::max(ds, (size_t)pl.b[i].grid * pl.pool_slots);
+  }
+  return b + ps * 2 + ds * 2;
+}
+
+size_t table_bytes(const qram_ctx *c) {
+  return (size_t)c->D * 4 + (size_t)(2 * c->emax + 1) * 8 * 2 + sizeof(Tables) + (size_t)(MAXT + 1) * 8;
+}
+
+uint32_t batch_size(const qram_ctx *c, uint32_t ntraj);
+qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl);
+
 uint32_t batch_size(const qram_ctx *c, uint32_t ntraj) {
   // keep the per-trajectory buffers within about 2 GiB
   const double per = (double)cand_capacity(c) * 4.0 + (double)c->D * 2.0 +
@@ -789,6 +811,37 @@ qram_status qram_run_pruned_async(qram_ctx *c, uint64_t seed, uint64_t traj0,
                                   qram_traj_stats *d_st, void *stream) {
   if (!d_fid) return fail(c, QRAM_E_INVAL, "d_fid is required");
   return run_mode(c, 1, seed, traj0, ntraj, d_fid, d_st, nullptr, nullptr, (hipStream_t)stream, false);
+}
+
+qram_status qram_footprint(qram_ctx *c, qram_mode mode, uint32_t ntraj,
+                           uint64_t *bytes) {
+  if (!c || !bytes) return fail(c, QRAM_E_INVAL, "null argument");
+  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return fail(c, QRAM_E_INVAL, "bad mode");
+  HIPCHK(c, hipSetDevice(c->device));
+  const uint32_t nb = batch_size(c, std::max<uint32_t>(ntraj, 1u));
+  Plan pl;
+  qram_status st = make_plan(c, mode, nb, pl);
+  if (st) return st;
+  *bytes = (uint64_t)(table_bytes(c) + buffers_bytes(c, nb, pl));
+  return QRAM_OK;
+}
+
+qram_status qram_reserve(qram_ctx *c, qram_mode mode, uint32_t ntraj) {
+  if (!c) return QRAM_E_INVAL;
+  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return fail(c, QRAM_E_INVAL, "bad mode");
+  HIPCHK(c, hipSetDevice(c->device));
+  const uint32_t nb = batch_size(c, std::max<uint32_t>(ntraj, 1u));
+  Plan pl;
+  qram_status st = make_plan(c, mode, nb, pl);
+  if (st) return st;
+  return ensure_buffers(c, nb, &pl);
+}
+
+qram_status qram_errors(qram_ctx *c) {
+  if (!c) return QRAM_E_INVAL;
+  HIPCHK(c, hipSetDevice(c->device));
+  if (!c->errw) return QRAM_OK;
+  return check_err(c);
 }
 
 qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,

@@ -25,13 +25,27 @@ STATS_DTYPE = np.dtype([
     ("q_ground", "u1"), ("flags", "u1"), ("pad", "u1"), ("fid_pre", "<f8")])
 assert STATS_DTYPE.itemsize == 32
 
+
+class QramRequest(C.Structure):
+    _fields_ = [("n_addr", C.c_int), ("k_data", C.c_int), ("enc", C.c_int), ("gamma", C.c_double),
+                ("memory_bits", C.POINTER(C.c_uint32)), ("seed", C.c_uint64), ("traj0", C.c_uint64),
+                ("shots", C.c_uint32), ("mode", C.c_int)]
+
+
+class QramResult(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("state", C.c_int), ("status", C.c_int), ("mean", C.c_double),
+                ("sem", C.c_double), ("shots", C.c_uint32), ("footprint_bytes", C.c_uint64),
+                ("queue_ms", C.c_double), ("latency_ms", C.c_double)]
+
 # Every entry point declared in include/qram.h.
 EXPORTS = [
     "qram_create", "qram_destroy", "qram_last_error", "qram_sample_faults",
     "qram_run_full", "qram_run_pruned", "qram_run_full_async", "qram_run_pruned_async",
     "qram_fidelity", "qram_set_launch", "qram_get_launch", "qram_autotune",
     "qram_last_kernel_ms", "qram_set_timing", "qram_stage_times", "qram_set_option",
-    "qram_run_forced",
+    "qram_run_forced", "qram_footprint", "qram_reserve", "qram_errors",
+    "qram_server_create", "qram_server_submit", "qram_server_poll", "qram_server_wait",
+    "qram_server_fidelities", "qram_server_release", "qram_server_destroy",
 ]
 QRAM_OPT_TIER2_GLOBAL = 1
 QRAM_OPT_GRAPH = 2
@@ -62,6 +76,7 @@ def load_library(path: str = LIB_PATH):
     L.qram_create.restype = C.c_int
     L.qram_destroy.argtypes = [vp]
     L.qram_destroy.restype = None
+    L.qram_server_destroy.restype = None
     L.qram_last_error.argtypes = [vp]
     L.qram_last_error.restype = C.c_char_p
     L.qram_sample_faults.argtypes = [vp, u64, u64, u32, p(u32), p(u64), p(u32), p(u64), p(u32), u64]
@@ -78,8 +93,18 @@ def load_library(path: str = LIB_PATH):
     L.qram_set_timing.argtypes = [vp, C.c_int]
     L.qram_stage_times.argtypes = [vp, p(f64), p(u32)]
     L.qram_set_option.argtypes = [vp, C.c_int, C.c_int]
+    L.qram_footprint.argtypes = [vp, C.c_int, u32, p(u64)]
+    L.qram_reserve.argtypes = [vp, C.c_int, u32]
+    L.qram_errors.argtypes = [vp]
+    L.qram_server_create.argtypes = [u64, C.c_int, u32, p(vp)]
+    L.qram_server_submit.argtypes = [vp, p(QramRequest), p(u64)]
+    L.qram_server_poll.argtypes = [vp, u64, p(QramResult)]
+    L.qram_server_wait.argtypes = [vp, u64, f64, p(QramResult)]
+    L.qram_server_fidelities.argtypes = [vp, u64, p(f64), u32]
+    L.qram_server_release.argtypes = [vp, u64]
+    L.qram_server_destroy.argtypes = [vp]
     for name in EXPORTS:
-        if name not in ("qram_destroy", "qram_last_error"):
+        if name not in ("qram_destroy", "qram_last_error", "qram_server_destroy"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -232,7 +257,98 @@ class QramContext:
         self._check(self._L.qram_stage_times(self._h, _ptr(t, C.c_double), C.byref(nb)), "qram_stage_times")
         return t, nb.value
 
+    def footprint(self, mode, ntraj):
+        """Device bytes held for runs of up to ntraj trajectories per call."""
+        b = C.c_uint64()
+        self._check(self._L.qram_footprint(self._h, mode, ntraj, C.byref(b)), "qram_footprint")
+        return b.value
+
+    def reserve(self, mode, ntraj):
+        self._check(self._L.qram_reserve(self._h, mode, ntraj), "qram_reserve")
+
+    def errors(self):
+        """Raise if an asynchronous run flagged a capacity overflow."""
+        self._check(self._L.qram_errors(self._h), "qram_errors")
+
     def last_kernel_ms(self):
         t = np.zeros(3)
         self._check(self._L.qram_last_kernel_ms(self._h, _ptr(t, C.c_double)), "qram_last_kernel_ms")
         return t
+
+
+RESULT_STATE = {0: "waiting", 1: "running", 2: "done", 3: "failed"}
+
+
+class QramServer:
+    """Continuous-batching request server (``qram_server_*``) on the current
+    HIP device: admission by device footprint, ``max_active`` overlapping
+    execution slots, ``chunk`` trajectories per launch."""
+
+    def __init__(self, hbm_budget_bytes, max_active=8, chunk=8192):
+        L = load_library()
+        h = C.c_void_p()
+        st = L.qram_server_create(int(hbm_budget_bytes), int(max_active), int(chunk), C.byref(h))
+        if st:
+            raise QramError(st, "qram_server_create")
+        self._h, self._L = h, L
+        self._keep = {}
+
+    def submit(self, n, k, enc, gamma, memory_bits, seed, shots, mode=QRAM_MODE_PRUNED, traj0=0):
+        mem = np.ascontiguousarray(memory_bits, dtype=np.uint32)
+        if mem.shape != (1 << n,):
+            raise ValueError("memory_bits must hold 2^n words")
+        req = QramRequest(n, k, enc, float(gamma), _ptr(mem, C.c_uint32), int(seed), int(traj0), int(shots), int(mode))
+        t = C.c_uint64()
+        st = self._L.qram_server_submit(self._h, C.byref(req), C.byref(t))
+        if st:
+            raise QramError(st, "qram_server_submit")
+        return t.value
+
+    @staticmethod
+    def _as_dict(r):
+        return dict(ticket=r.ticket, state=RESULT_STATE.get(r.state, r.state), status=STATUS.get(r.status, r.status),
+                    mean=r.mean, sem=r.sem, shots=r.shots, footprint_bytes=r.footprint_bytes,
+                    queue_ms=r.queue_ms, latency_ms=r.latency_ms)
+
+    def poll(self, ticket):
+        r = QramResult()
+        st = self._L.qram_server_poll(self._h, ticket, C.byref(r))
+        if st:
+            raise QramError(st, "qram_server_poll")
+        return self._as_dict(r)
+
+    def wait(self, ticket, timeout_ms=-1.0):
+        r = QramResult()
+        st = self._L.qram_server_wait(self._h, ticket, float(timeout_ms), C.byref(r))
+        if st:
+            raise QramError(st, "qram_server_wait")
+        return self._as_dict(r)
+
+    def fidelities(self, ticket, shots):
+        f = np.zeros(shots, dtype=np.float64)
+        st = self._L.qram_server_fidelities(self._h, ticket, _ptr(f, C.c_double), shots)
+        if st:
+            raise QramError(st, "qram_server_fidelities")
+        return f
+
+    def release(self, ticket):
+        st = self._L.qram_server_release(self._h, ticket)
+        if st:
+            raise QramError(st, "qram_server_release")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.qram_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
