@@ -209,6 +209,10 @@ qram_status qram_last_kernel_ms(const qram_ctx *ctx, double *times);
  */
 qram_status qram_set_timing(qram_ctx *ctx, int on);
 qram_status qram_stage_times(qram_ctx *ctx, double *ms, uint32_t *nbatches);
+/* Evolution kernel launches (one per work bucket and batch) inside the
+ * batches the current accumulation timed; read it before qram_stage_times,
+ * which starts a new accumulation. */
+qram_status qram_stage_launches(const qram_ctx *ctx, uint32_t *evolve_launches);
 
 /*
  * Test entry: one trajectory under a forced history instead of the random

@@ -79,6 +79,7 @@ struct qram_ctx {
   bool timing = false;
   std::vector<hipEvent_t> tev;
   size_t tev_used = 0;
+  uint32_t tev_launches = 0;  // evolution launches inside the timed batches
 };
 
 namespace {
@@ -476,6 +477,7 @@ qram_status enqueue_batch(qram_ctx *c, const Plan &pl, Run r, hipStream_t s,
     }
     for (int i = 0; i < 4; ++i) e[i] = c->tev[c->tev_used + i];
     c->tev_used += 4;
+    c->tev_launches += (uint32_t)pl.nb;
     timed = true;
   }
   if (timed) HIPCHK(c, hipEventRecord(e[0], s));
@@ -960,6 +962,13 @@ qram_status qram_set_timing(qram_ctx *c, int on) {
   if (!c) return QRAM_E_INVAL;
   c->timing = on != 0;
   c->tev_used = 0;
+  c->tev_launches = 0;
+  return QRAM_OK;
+}
+
+qram_status qram_stage_launches(const qram_ctx *c, uint32_t *evolve_launches) {
+  if (!c || !evolve_launches) return QRAM_E_INVAL;
+  *evolve_launches = c->tev_launches;
   return QRAM_OK;
 }
 
@@ -978,6 +987,7 @@ qram_status qram_stage_times(qram_ctx *c, double *ms, uint32_t *nbatches) {
   }
   if (nbatches) *nbatches = (uint32_t)nb;
   c->tev_used = 0;
+  c->tev_launches = 0;
   return QRAM_OK;
 }
 

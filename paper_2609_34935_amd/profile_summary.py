@@ -1,0 +1,133 @@
+"""Short text summaries of rocprofv3 CSV output (kernel trace, counters).
+
+    python -m paper_2609_34935_amd.profile_summary trace KERNEL_TRACE.csv OUT.txt --command "..."
+    python -m paper_2609_34935_amd.profile_summary counters --fetch F.csv --write W.csv [--sq S.csv] \\
+        --kernel 'k_evolve<1,' OUT.json --command "..." [--command "..."]
+
+The counter summary scales FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by
+what the same counters read for the largest plain device copy of the run
+(a 256 MiB copy: 268435456 bytes read and written) and reports HBM bytes per
+launch of the named kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+from collections import OrderedDict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SRCS = [os.path.join(HERE, "csrc", f) for f in ("qram_evolve.hip", "qram_device.h", "qram_internal.h")]
+COPY_BYTES = 268435456
+
+
+def kernel_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def short_name(name):
+    for cut in ("(qr::", "(unsigned", "(void"):
+        i = name.find(cut)
+        if i > 0:
+            name = name[:i]
+    return name.replace("void ", "").replace("qr::(anonymous namespace)::", "").replace("qr::", "").strip()
+
+
+def trace_summary(path, out, commands):
+    rows = list(csv.DictReader(open(path)))
+    agg = OrderedDict()
+    for r in rows:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+        name = short_name(r["Kernel_Name"])
+        key = (name, r.get("Workgroup_Size_X", r.get("Workgroup_Size", "")))
+        a = agg.setdefault(key, [0, 0.0, 1e30, 0.0])
+        a[0] += 1
+        a[1] += d
+        a[2] = min(a[2], d)
+        a[3] = max(a[3], d)
+    total = sum(v[1] for v in agg.values())
+    lines = ["rocprofv3 kernel trace summary", ""]
+    lines += [f"command: {c}" for c in commands]
+    lines += ["", f"{'kernel':<44} {'wg':>5} {'calls':>6} {'total ms':>10} {'avg ms':>9} {'min ms':>9} {'max ms':>9} {'%':>6}"]
+    for (name, wg), (n, t, lo, hi) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"{name[:44]:<44} {wg:>5} {n:>6} {t:>10.3f} {t / n:>9.3f} {lo:>9.3f} {hi:>9.3f} {100 * t / total:>6.2f}")
+    byname = OrderedDict()
+    for (name, _), (n, t, lo, hi) in agg.items():
+        a = byname.setdefault(name, [0, 0.0])
+        a[0] += n
+        a[1] += t
+    lines += ["", "all workgroup sizes together:", f"{'kernel':<44} {'calls':>6} {'total ms':>10} {'avg ms':>9}"]
+    for name, (n, t) in sorted(byname.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"{name[:44]:<44} {n:>6} {t:>10.3f} {t / n:>9.3f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def _per_dispatch(path):
+    d = OrderedDict()
+    for r in csv.DictReader(open(path)):
+        key = int(r["Dispatch_Id"])
+        e = d.setdefault(key, {"name": r["Kernel_Name"], "grid": r.get("Grid_Size"), "wg": r.get("Workgroup_Size")})
+        e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return d
+
+
+def counter_summary(fetch, write, sq, kernel, out, commands):
+    res = {"kernel": kernel, "kernel_sha256": kernel_sha256(), "commands": commands}
+    for path, ctr, tag in ((fetch, "FETCH_SIZE", "fetch"), (write, "WRITE_SIZE", "write")):
+        d = _per_dispatch(path)
+        copies = [v[ctr] for v in d.values() if "copyBuffer" in v["name"] and ctr in v]
+        if not copies:
+            raise SystemExit(f"no calibration copy in {path}")
+        cal_kib = max(copies)
+        factor = COPY_BYTES / (cal_kib * 1024.0)
+        ks = [v[ctr] for v in d.values() if kernel in v["name"] and ctr in v]
+        if not ks:
+            raise SystemExit(f"no dispatch of {kernel} in {path}")
+        res[f"copy_{tag}_kib"] = cal_kib
+        res[f"copy_factor_{tag}"] = round(factor, 4)
+        res[f"launches_{tag}"] = len(ks)
+        res[f"{tag}_bytes_per_launch"] = round(sum(ks) * 1024.0 * factor / len(ks), 1)
+    res["hbm_bytes_per_launch"] = round(res["fetch_bytes_per_launch"] + res["write_bytes_per_launch"], 1)
+    if sq:
+        d = _per_dispatch(sq)
+        ks = [v for v in d.values() if kernel in v["name"]]
+        for c in sorted({c for v in ks for c in v if c.startswith("SQ_")}):
+            res[f"{c}_per_launch"] = round(sum(v.get(c, 0.0) for v in ks) / len(ks), 1)
+    json.dump(res, open(out, "w"), indent=1)
+    txt = os.path.splitext(out)[0] + ".txt"
+    lines = ["rocprofv3 counter summary (per launch of the kernel below)", ""]
+    lines += [f"command: {c}" for c in commands]
+    lines += [""] + [f"{k}: {v}" for k, v in res.items() if k != "commands"]
+    open(txt, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("csv")
+    t.add_argument("out")
+    t.add_argument("--command", action="append", default=[])
+    c = sub.add_parser("counters")
+    c.add_argument("--fetch", required=True)
+    c.add_argument("--write", required=True)
+    c.add_argument("--sq", default=None)
+    c.add_argument("--kernel", required=True)
+    c.add_argument("out")
+    c.add_argument("--command", action="append", default=[])
+    a = ap.parse_args()
+    if a.what == "trace":
+        trace_summary(a.csv, a.out, a.command)
+    else:
+        counter_summary(a.fetch, a.write, a.sq, a.kernel, a.out, a.command)
+
+
+if __name__ == "__main__":
+    main()

@@ -42,7 +42,7 @@ EXPORTS = [
     "qram_create", "qram_destroy", "qram_last_error", "qram_sample_faults",
     "qram_run_full", "qram_run_pruned", "qram_run_full_async", "qram_run_pruned_async",
     "qram_fidelity", "qram_set_launch", "qram_get_launch", "qram_autotune",
-    "qram_last_kernel_ms", "qram_set_timing", "qram_stage_times", "qram_set_option",
+    "qram_last_kernel_ms", "qram_set_timing", "qram_stage_times", "qram_stage_launches", "qram_set_option",
     "qram_run_forced", "qram_footprint", "qram_reserve", "qram_errors",
     "qram_server_create", "qram_server_submit", "qram_server_poll", "qram_server_wait",
     "qram_server_fidelities", "qram_server_release", "qram_server_destroy",
@@ -92,6 +92,7 @@ def load_library(path: str = LIB_PATH):
     L.qram_run_forced.argtypes = [vp, C.c_int, p(u32), u32, p(f64), f64, p(f64), vp]
     L.qram_set_timing.argtypes = [vp, C.c_int]
     L.qram_stage_times.argtypes = [vp, p(f64), p(u32)]
+    L.qram_stage_launches.argtypes = [vp, p(u32)]
     L.qram_set_option.argtypes = [vp, C.c_int, C.c_int]
     L.qram_footprint.argtypes = [vp, C.c_int, u32, p(u64)]
     L.qram_reserve.argtypes = [vp, C.c_int, u32]
@@ -249,6 +250,12 @@ class QramContext:
 
     def set_timing(self, on=True):
         self._check(self._L.qram_set_timing(self._h, 1 if on else 0), "qram_set_timing")
+
+    def stage_launches(self):
+        """Evolution launches inside the batches timed since the last read."""
+        n = C.c_uint32()
+        self._check(self._L.qram_stage_launches(self._h, C.byref(n)), "qram_stage_launches")
+        return n.value
 
     def stage_times(self):
         """(ms of sampling, classification, evolution summed over batches, batches)."""
