@@ -22,6 +22,8 @@
 // every component; weights are formed only when some component is hit.
 #include "qram_device.h"
 
+#include <algorithm>
+
 namespace qr {
 
 // Optional phase timers (build with -DQR_PHASE_TIMERS): wave 0 of every
@@ -1317,16 +1319,22 @@ extern "C" int qram_probe_phase_cycles(unsigned long long *out, int reset) {
 }
 #endif
 
-hipError_t evolve_prepare(int lds_max) {
+hipError_t evolve_prepare(int lds_max, int *dyn_max) {
   hipError_t e = hipSuccess;
   const void *fns[4] = {reinterpret_cast<const void *>(&k_evolve<QUBIT, true>),
                         reinterpret_cast<const void *>(&k_evolve<QUBIT, false>),
                         reinterpret_cast<const void *>(&k_evolve<QUTRIT, true>),
                         reinterpret_cast<const void *>(&k_evolve<QUTRIT, false>)};
+  int dyn = lds_max;
+  for (const void *f : fns) {  // the compiler's own shared memory comes first
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, f) == hipSuccess) dyn = std::min(dyn, lds_max - (int)fa.sharedSizeBytes);
+  }
   for (const void *f : fns) {
-    const hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    const hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     if (r != hipSuccess) e = r;
   }
+  *dyn_max = dyn;
   return e;
 }
 

@@ -670,10 +670,12 @@ qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return bail(fail(c, QRAM_E_DEVICE, "hipGetDeviceProperties failed"));
   c->num_cu = prop.multiProcessorCount;
-  c->lds_max = prop.sharedMemPerBlock;
-  if (evolve_prepare((int)c->lds_max) != hipSuccess) {
+  int dyn = 0;
+  if (evolve_prepare((int)prop.sharedMemPerBlock, &dyn) == hipSuccess) {
+    c->lds_max = (size_t)dyn;  // dynamic shared memory an evolution launch may take
+  } else {
     (void)hipGetLastError();
-    c->lds_max = std::min<size_t>(c->lds_max, 64 * 1024);
+    c->lds_max = std::min<size_t>(prop.sharedMemPerBlock, 64 * 1024) - 1024;
   }
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return bail(fail(c, QRAM_E_DEVICE, "stream creation failed"));
   for (auto &e : c->ev)

@@ -119,6 +119,6 @@ hipError_t launch_digest(const Run &rp, uint32_t ntraj, hipStream_t s);
 uint32_t evolve_lds_bytes(int n, int k, int M, int D, int threads,
                           uint32_t e_cap, bool state_lds);
 int evolve_occupancy(int enc, bool state_lds, int threads, uint32_t lds_bytes);
-hipError_t evolve_prepare(int lds_max);
+hipError_t evolve_prepare(int lds_max, int *dyn_max);
 
 }  // namespace qr
