@@ -1,0 +1,104 @@
+"""Parity at the benchmark's full sizes, in the benchmark's launch
+configuration: every trajectory of the run checked for properties that hold
+at any size (pruned equals full, integer statistics agree across modes, the
+candidate count follows its binomial law), and sampled trajectories checked
+one by one against the oracle (fidelities within 1e-12 relative, candidate
+lists and statistics bit-exact)."""
+import json
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from paper_2609_34935_amd.inputs import memory_words
+
+pytestmark = pytest.mark.gpu
+
+QUTRIT, QUBIT = 0, 1
+FULL, PRUNED = 0, 1
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TUNED = os.path.join(ROOT, "paper_2609_34935_amd", "tuned", "launch_n10k4_gamma1e-3.json")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_34935_amd as P
+    P.load_library()
+    return P
+
+
+def fid_close(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b) <= 1e-12 * np.maximum(np.abs(b), 1e-3)
+
+
+def oracle_at(orc, n, k, enc, gamma, mem, seed, idx):
+    def one(i):
+        f, fp, ri, _ = orc.run_batch(n, k, enc, gamma, mem, seed, int(i), 1, nthreads=1)
+        return f[0], fp[0], ri[0]
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(one, idx))
+
+
+def check_run(lib, orc, n, k, enc, gamma, mem, seed, nt, idx, launch=None):
+    with lib.QramContext(n, k, enc, gamma, mem) as ctx:
+        if launch:
+            for mode in (FULL, PRUNED):
+                ctx.set_launch(mode, *launch[f"{enc}:{mode}"])
+        fp, sp = ctx.run_pruned(seed, 0, nt)
+        ff, sf = ctx.run_full(seed, 0, nt)
+        dump = {int(i): ctx.sample_faults(seed, int(i), 1, dump=True) for i in idx}
+    # every trajectory: pruned equals full, statistics agree across modes
+    assert np.all(fid_close(fp, ff))
+    assert np.all(fid_close(sp["fid_pre"], sf["fid_pre"]))
+    for f in ("n_cand", "n_bad", "ref_addr", "n_jumps", "first_jump_slice", "ref_survived", "q_ground"):
+        assert np.array_equal(sp[f], sf[f]), f
+    assert np.all(sf["n_explicit"] == (2**n) * (2**k if enc == QUBIT else 1))
+    assert np.all(sp["n_explicit"] <= sf["n_explicit"])
+    assert np.all((sp["flags"] & 1) == 0)  # no candidate overflow
+    # candidate counts: Binomial(S, gamma) over all trajectories
+    S = (6 * n + 2 * k - 1) * 2 * (2**n - 1)
+    m = sp["n_cand"].astype(np.float64)
+    assert abs(m.mean() - S * gamma) < 6 * np.sqrt(S * gamma * (1 - gamma) / nt)
+    # sampled trajectories against the oracle
+    ref = oracle_at(orc, n, k, enc, gamma, mem, seed, idx)
+    for i, (fo, fpo, ri) in zip(idx, ref):
+        assert fid_close(fp[i], fo) and fid_close(ff[i], fo), (i, fp[i], ff[i], fo)
+        assert fid_close(sp["fid_pre"][i], fpo), i
+        assert sp["n_cand"][i] == ri[0] and sp["n_bad"][i] == ri[1], i
+        assert sp["n_jumps"][i] == ri[4] and sp["first_jump_slice"][i] == ri[5], i
+        assert sp["ref_survived"][i] == ri[6] and sp["q_ground"][i] == ri[7], i
+        L = orc.sample(n, k, gamma, seed, int(i))
+        assert np.array_equal(dump[int(i)]["cand_L"][0], L), i
+    return fp, sp
+
+
+@pytest.mark.parametrize("enc", [QUBIT, QUTRIT])
+def test_c3_full_size_sampled(lib, orc, enc):
+    n, k, gamma, nt = 10, 4, 1e-3, 100000
+    mem = memory_words(n, k, 1003)
+    launch = json.load(open(TUNED))
+    rng = np.random.default_rng(31 + enc)
+    idx = sorted(set([0, 1, 2, nt - 1] + rng.choice(nt, 24, replace=False).tolist()))
+    fp, sp = check_run(lib, orc, n, k, enc, gamma, mem, 880003, nt, idx, launch)
+    # the no-jump trajectories of the qubit encoding hit the closed form
+    if enc == QUBIT:
+        a = np.sqrt(1 - gamma)
+        g = lambda u: (1 + u) ** 2 / (2 * (1 + u * u))
+        T = 6 * n + 2 * k
+        F0 = np.prod([g(a ** (T - 4 * t - 2)) for t in range(n)]) * g(a ** (2 * n)) ** k
+        sel = sp["n_jumps"] == 0
+        assert sel.sum() > nt // 2
+        assert np.all(np.abs(sp["fid_pre"][sel] - F0) <= 1e-12)
+
+
+def test_c5_qutrit_n14_sampled(lib, orc):
+    n, k, gamma, nt = 14, 1, 1e-2, 4096
+    mem = memory_words(n, k, 1005)
+    idx = [0, 1, 2, 1000, 2047, nt - 1]
+    fp, sp = check_run(lib, orc, n, k, QUTRIT, gamma, mem, 880005, nt, idx)
+    assert np.all(sp["n_bad"] == 2**n)  # every branch bad at this noise level
