@@ -618,7 +618,7 @@ struct Sm {
   double *fa;       // the same with a^m (final)
   double *fmisc;    // [4]
   uint32_t *cstart; // [MAXT + 1]
-  uint32_t *cdec;   // [NCS]
+  uint32_t *cdec;   // [cdec_cap]: the slice's decoded candidates, or all of them
   uint32_t *Jb;     // [JMAX]
   int *misc;        // [8]
   uint32_t *cbm;    // [(M + 31) / 32]
@@ -628,7 +628,7 @@ struct Sm {
 
 constexpr int F_A = 0, F_D = 96, F_K = 96 + 256, F_N = 96 + 256 + 256;
 
-__host__ __device__ inline uint32_t fixed_bytes(int M, int D, int threads) {
+__host__ __device__ inline uint32_t fixed_bytes(int M, int D, int threads, uint32_t cdec_cap) {
   const int nw = threads >> 6;
   uint32_t b = 0;
   b += al16(2 * nw * 8 * 8);
@@ -636,7 +636,7 @@ __host__ __device__ inline uint32_t fixed_bytes(int M, int D, int threads) {
   b += al16(F_N * 8) * 2;
   b += al16(4 * 8);
   b += al16((MAXT + 1) * 4);
-  b += al16(NCS * 4);
+  b += al16(cdec_cap * 4);
   b += al16(JMAX * 4);
   b += al16(8 * 4);
   b += al16(((M + 31) / 32) * 4);
@@ -644,7 +644,7 @@ __host__ __device__ inline uint32_t fixed_bytes(int M, int D, int threads) {
   return b;
 }
 
-__device__ inline Sm carve(unsigned char *base, int M, int D, int threads) {
+__device__ inline Sm carve(unsigned char *base, int M, int D, int threads, uint32_t cdec_cap) {
   const int nw = threads >> 6;
   Sm m;
   unsigned char *p = base;
@@ -661,7 +661,7 @@ __device__ inline Sm carve(unsigned char *base, int M, int D, int threads) {
   m.cstart = reinterpret_cast<uint32_t *>(p);
   p += al16((MAXT + 1) * 4);
   m.cdec = reinterpret_cast<uint32_t *>(p);
-  p += al16(NCS * 4);
+  p += al16(cdec_cap * 4);
   m.Jb = reinterpret_cast<uint32_t *>(p);
   p += al16(JMAX * 4);
   m.misc = reinterpret_cast<int *>(p);
@@ -674,35 +674,25 @@ __device__ inline Sm carve(unsigned char *base, int M, int D, int threads) {
   return m;
 }
 
-// Factor tables for exposure through slice s: chunk c of the address bits
-// (bits 5c..5c+4 of i, where bit n-1-t is address token t), data-token sets
-// and lost-token exposure.  pw points at the centre of a power table.
+// Factor tables of slice s into shared memory: (1-gamma)^e or a^e of the
+// exposure through slice s for the three 5-bit chunks of the address bits
+// (bit n-1-t is address token t), for every data-token set, and the router
+// factor (qutrit).  The host precomputes them per slice.
 template <int ENC>
-__device__ void build_factors(const Tables *__restrict__ tb, int s,
-                              const double *__restrict__ pw, double *f,
-                              double *fmisc, bool with_lost) {
-  const int n = tb->n, k = tb->k;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  for (int x = tid; x < 96; x += nthr) {
-    const int c = x >> 5, v = x & 31;
-    int e = 0;
-    for (int b = 0; b < 5; ++b) {
-      const int pbit = 5 * c + b;
-      if (pbit < n && ((v >> b) & 1)) e += tb->cntA[s][n - 1 - pbit];
-    }
-    f[F_A + x] = pw[e];
-  }
-  for (int v = tid; v < (1 << k); v += nthr) {
-    int e = 0;
-    for (int b = 0; b < k; ++b)
-      if ((v >> b) & 1) e += tb->cntD[s][b];
-    f[F_D + v] = pw[e];
-  }
-  if (with_lost) {
-    const int kmax = min(255, tb->emax);
-    for (int m = tid; m <= kmax; m += nthr) f[F_K + m] = pw[m];
-  }
-  if (tid == 0) fmisc[0] = ENC == QUTRIT ? pw[tb->cntR[s]] : 1.0;
+__device__ __forceinline__ void load_factors(const Tables *__restrict__ tb, int s,
+                                             const double *__restrict__ ftab, double *f,
+                                             double *fmisc) {
+  const int nd = 1 << tb->k, nfs = tb->nfs;
+  const double *__restrict__ src = ftab + (size_t)s * nfs;
+  for (int x = threadIdx.x; x < F_D + nd; x += blockDim.x) f[x] = src[x];  // F_A = 0, F_D = 96
+  if (threadIdx.x == 0) *fmisc = ENC == QUTRIT ? src[F_D + nd] : 1.0;
+}
+
+// Exposure factors of data tokens lost to jumps (index = exposure).
+__device__ __forceinline__ void load_lost(const Tables *__restrict__ tb,
+                                          const double *__restrict__ pw, double *f) {
+  const int kmax = min(255, tb->emax);
+  for (int m = threadIdx.x; m <= kmax; m += blockDim.x) f[F_K + m] = pw[m];
 }
 
 __device__ __forceinline__ double fA(const double *f, uint32_t a) {
@@ -726,7 +716,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
   const double *__restrict__ wpow = tb->wpow + emax;
   const double *__restrict__ apow = tb->apow + emax;
   const uint32_t *__restrict__ mem = tb->mem;
-  Sm sm = carve(smem, M, D, nthr);
+  Sm sm = carve(smem, M, D, nthr, rp->cdec_all ? rp->cand_cap : (uint32_t)NCS);
   uint32_t *st = SL ? sm.st : rp->gstate + (size_t)blockIdx.x * rp->e_cap;
   const int rec = tb->rec;
   uint16_t *pool = rp->pool + (size_t)blockIdx.x * rp->pool_slots * rec;
@@ -736,10 +726,11 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
   const uint32_t apt = rp->apt;
   const uint32_t bkt = rp->bucket;
   const bool slow_all = rp->tier2_slow != 0;
+  const bool pre = rp->cdec_all != 0;  // every candidate decoded into shared memory up front
   int big_prev_s = 0, big_prev_cb = 0, big_prev_nc = 0;
   // the constant lost-token factors, and a clean candidate bitmap
-  build_factors<ENC>(tb, 0, wpow, sm.fw, sm.fmisc, true);
-  build_factors<ENC>(tb, 0, apow, sm.fa, sm.fmisc + 1, true);
+  load_lost(tb, wpow, sm.fw);
+  load_lost(tb, apow, sm.fa);
   for (int w = tid; w < (M + 31) / 32; w += nthr) sm.cbm[w] = 0u;
 
   QR_TINIT
@@ -767,15 +758,22 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
     const uint64_t *__restrict__ badg = rp->badbits + (size_t)tj * ((D + 63) >> 6);
 
     for (uint32_t j = tid; j <= nct; j += nthr) {  // slice boundaries
-      const int sj = j < nct ? (int)(cand[j] / (uint32_t)M) + 1 : T;
+      const uint32_t cj = j < nct ? cand[j] : 0u;
+      const int sj = j < nct ? (int)(cj / (uint32_t)M) + 1 : T;
       const int sp = j > 0 ? (int)(cand[j - 1] / (uint32_t)M) + 1 : 0;
       for (int ss = sp + 1; ss <= sj; ++ss) sm.cstart[ss] = j;
+      if (pre && j < nct) {  // site, layer and schedule token of every candidate
+        const uint32_t q = cj - (uint32_t)(sj - 1) * M;
+        const int l = layer_of(q >> 1);
+        sm.cdec[j] = q | ((uint32_t)l << 16) | ((uint32_t)tb->tok[sj][l][q & 1u] << 20);
+      }
     }
     if (pruned)
       for (int w = tid; w < (D + 31) / 32; w += nthr)
         sm.badl[w] = (uint32_t)(badg[w >> 1] >> (32 * (w & 1)));
     // initial components: data-loading input after the first wall; the sign
     // already holds every fetch phase its live tokens will pick up
+    uint64_t alive = 0, devm = 0;  // this thread's live and tier-2 slots (bit j)
     for (uint32_t al = 0; al < apt; ++al) {
       const uint32_t g = tid * apt + al;
       if (g >= A) break;
@@ -785,6 +783,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
         const bool sg = ENC == QUBIT && (__popc(live & mem[a] & kmask) & 1);
         st[(al * K2 + b) * nthr + tid] = W_ALIVE | (live << W_LIVE_SH) | (sg ? W_SIGN : 0u);
       }
+      alive |= kfull << (al * K2);
     }
     __syncthreads();
     QR_TM(0);
@@ -798,17 +797,19 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
       const int nc = (int)(sm.cstart[s + 1] - cb);
       if (nc == 0 && ndev == 0) continue;
       const bool big = nc > NCS;
-      if (nc > 0) {
+      const uint32_t *cd = pre ? sm.cdec + cb : sm.cdec;  // the slice's decoded candidates
+      if (nc > 0 && (big || !pre)) {
         if (big) {
           if (big_prev_nc > 0) {
             for (int j = tid; j < big_prev_nc; j += nthr) {
-              const uint32_t q = cand[big_prev_cb + j] - (uint32_t)(big_prev_s - 1) * M;
+              const uint32_t q = pre ? (sm.cdec[big_prev_cb + j] & 0xFFFFu)
+                                     : cand[big_prev_cb + j] - (uint32_t)(big_prev_s - 1) * M;
               sm.cbm[q >> 5] = 0;
             }
             __syncthreads();
           }
           for (int j = tid; j < nc; j += nthr) {
-            const uint32_t q = cand[cb + j] - (uint32_t)(s - 1) * M;
+            const uint32_t q = pre ? (sm.cdec[cb + j] & 0xFFFFu) : cand[cb + j] - (uint32_t)(s - 1) * M;
             atomicOr(&sm.cbm[q >> 5], 1u << (q & 31));
           }
           big_prev_s = s;
@@ -840,7 +841,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
         const uint32_t e = (w & W_E) + cnt0;  // exposure through slice s-1
         bool hit;
         const uint32_t cnt = t2_step<ENC>(tb, s, pool + (size_t)c * rec, cnt0, a, w, slow_all, big, nc,
-                                          sm.cdec, sm.cbm, hit, rp->err);
+                                          cd, sm.cbm, hit, rp->err);
         st[widx] = (w & (W_SIGN | W_ALIVE | W_DEV)) | e | (cnt << W_CNT_SH) | (hit ? W_HIT : 0u);
       }
       QR_TM(7);
@@ -859,7 +860,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
           const uint32_t a = xl ? xl[g] : g;
           bool ah;
           uint32_t dh;
-          t1_addr_hits<ENC>(tb, s, a, big, nc, sm.cdec, sm.cbm, ah, dh);
+          t1_addr_hits<ENC>(tb, s, a, big, nc, cd, sm.cbm, ah, dh);
           uint64_t m;
           if (ENC == QUBIT)
             m = ah ? kfull : (kfull & ~subsets_of(~dh & kmask, tb->k));
@@ -867,26 +868,25 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
             m = (ah || (mem[a] & kmask & tb->dmask[s] & dh)) ? 1ull : 0ull;
           hmask |= m << (al * K2);
         }
-      } else
-      for (uint32_t al = 0; al < apt; ++al) {
-        const uint32_t g = tid * apt + al;
-        if (g >= A) break;
-        const uint32_t a = xl ? xl[g] : g;
-        const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
-        bool ah = false, addr_done = false;
-        uint32_t dh = 0;
-        for (int b = 0; b < K2; ++b) {
-          const uint32_t j = al * K2 + b;
+      } else {
+        for (uint64_t m = devm; m; m &= m - 1) {  // tier 2: hit flags from the tier-2 pass
+          const int j = __ffsll((unsigned long long)m) - 1;
+          if (st[j * nthr + tid] & W_HIT) hmask |= 1ull << j;
+        }
+        int cur = -1;
+        uint32_t memw = 0, dh = 0;
+        bool ah = false;
+        for (uint64_t m = alive & ~devm; m; m &= m - 1) {  // tier 1
+          const int j = __ffsll((unsigned long long)m) - 1;
+          const int al = j >> kb;
+          if (al != cur) {
+            cur = al;
+            const uint32_t g = tid * apt + (uint32_t)al;
+            const uint32_t a = xl ? xl[g] : g;
+            memw = ENC == QUTRIT ? mem[a] : 0u;
+            t1_addr_hits<ENC>(tb, s, a, big, nc, cd, sm.cbm, ah, dh);
+          }
           const uint32_t w = st[j * nthr + tid];
-          if (!(w & W_ALIVE)) continue;
-          if (w & W_DEV) {
-            if (w & W_HIT) hmask |= 1ull << j;
-            continue;
-          }
-          if (!addr_done) {
-            t1_addr_hits<ENC>(tb, s, a, big, nc, sm.cdec, sm.cbm, ah, dh);
-            addr_done = true;
-          }
           const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
           const uint32_t df = ENC == QUBIT ? live : (live & memw & tb->dmask[s]);
           if (ah || (df & dh)) hmask |= 1ull << j;
@@ -897,17 +897,17 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
       if (!any_hit) continue;  // J is empty
 
       // a draw slice: weights of every component before this slice's layer
-      build_factors<ENC>(tb, s - 1, wpow, sm.fw, sm.fmisc, false);
+      load_factors<ENC>(tb, s - 1, tb->ftab_w, sm.fw, sm.fmisc);
       __syncthreads();
       const double wr = sm.fmisc[0];
       double acc[3] = {0.0, 0.0, 0.0};  // w_empty, w_hit, good branches
-      for (uint32_t al = 0; al < apt; ++al) {
-        const uint32_t g = tid * apt + al;
-        if (g >= A) break;
-        const uint32_t a = xl ? xl[g] : g;
-        const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
-        const double wa = fA(sm.fw, a) * wr;
-        if (njumps == 0) {  // initial labels: live tokens = bus word (qubit), every bit (qutrit)
+      if (njumps == 0) {  // initial labels: live tokens = bus word (qubit), every bit (qutrit)
+        for (uint32_t al = 0; al < apt; ++al) {
+          const uint32_t g = tid * apt + al;
+          if (g >= A) break;
+          const uint32_t a = xl ? xl[g] : g;
+          const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
+          const double wa = fA(sm.fw, a) * wr;
           for (int b = 0; b < K2; ++b) {
             const double wt = wa * sm.fw[F_D + (ENC == QUBIT ? (uint32_t)b : (kmask & memw))];
             if ((hmask >> (al * K2 + b)) & 1ull)
@@ -915,16 +915,26 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
             else
               acc[0] += wt;
           }
-          continue;
         }
-        for (int b = 0; b < K2; ++b) {
-          const uint32_t j = al * K2 + b;
+      } else {
+        int cur = -1;
+        uint32_t memw = 0;
+        double wa = 0.0;
+        for (uint64_t m = alive; m; m &= m - 1) {
+          const int j = __ffsll((unsigned long long)m) - 1;
           const uint32_t w = st[j * nthr + tid];
-          if (!(w & W_ALIVE)) continue;
           double wt;
           if (w & W_DEV) {
             wt = wpow[w & W_E];
           } else {
+            const int al = j >> kb;
+            if (al != cur) {
+              cur = al;
+              const uint32_t g = tid * apt + (uint32_t)al;
+              const uint32_t a = xl ? xl[g] : g;
+              memw = ENC == QUTRIT ? mem[a] : 0u;
+              wa = fA(sm.fw, a) * wr;
+            }
             const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
             const uint32_t dv = ENC == QUBIT ? live : (live & memw);
             wt = wa * sm.fw[F_D + dv] * sm.fw[F_K + (w & W_EK)];
@@ -1010,7 +1020,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
           const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
           if (!big) {
             for (int c = 0; c < nc; ++c) {
-              const uint32_t q = sm.cdec[c] & 0xFFFFu;
+              const uint32_t q = cd[c] & 0xFFFFu;
               const int lev = t1_level<ENC>(tb, s, a, live, memw, q);
               if (lev && nJ < JMAX) sm.Jb[nJ++] = q | ((uint32_t)lev << 16);
             }
@@ -1026,7 +1036,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
           Rec<ENC> R{pool + (size_t)(g * K2 + b) * rec};
           for (int c = 0; c < R.cnt(); ++c) {
             const uint32_t x = R.raw(c), q = x & Rec<ENC>::SM;
-            const bool isc = big ? cand_bm(sm.cbm, q) : cand_list(sm.cdec, nc, q);
+            const bool isc = big ? cand_bm(sm.cbm, q) : cand_list(cd, nc, q);
             if (!isc) continue;
             const uint32_t lev = (ENC == QUTRIT && (x & LV_R_BIT)) ? 2u : 1u;
             if (nJ < JMAX) sm.Jb[nJ++] = q | (lev << 16);
@@ -1060,6 +1070,8 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
             }
             if (!ok) {
               st[j * nthr + tid] = 0u;
+              alive &= ~(1ull << j);
+              devm &= ~(1ull << j);
               continue;
             }
             uint32_t kill = 0;
@@ -1149,13 +1161,18 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
             }
             if (!ok) {
               st[j * nthr + tid] = 0u;
+              alive &= ~(1ull << j);
+              devm &= ~(1ull << j);
               continue;
             }
             const uint32_t cnt = ((w & W_CNT) >> W_CNT_SH) - (uint32_t)nJ;
             w = (w & (W_SIGN | W_ALIVE | W_DEV | W_E)) | (cnt << W_CNT_SH);
           }
           st[j * nthr + tid] = w;
-          if (w & W_DEV) ++mydev;
+          if (w & W_DEV) {
+            ++mydev;
+            devm |= 1ull << j;
+          }
         }
       }
       ref_alive = false;  // a good branch never carries a candidate site
@@ -1165,13 +1182,9 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
       {
         uint32_t tot;
         uint32_t pos = block_excl_scan_u32(mydev, reinterpret_cast<uint32_t *>(sm.scanb), &tot);
-        for (uint32_t al = 0; al < apt && mydev > 0; ++al) {
-          const uint32_t g = tid * apt + al;
-          if (g >= A) break;
-          for (int b = 0; b < K2; ++b) {
-            const uint32_t w = st[(al * K2 + b) * nthr + tid];
-            if ((w & (W_ALIVE | W_DEV)) == (W_ALIVE | W_DEV)) devl[pos++] = (uint16_t)(g * K2 + b);
-          }
+        for (uint64_t m = devm; m; m &= m - 1) {
+          const uint32_t j = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+          devl[pos++] = (uint16_t)((tid * apt + (j >> kb)) * K2 + (j & (uint32_t)(K2 - 1)));
         }
         ndev = tot;
         __syncthreads();
@@ -1182,7 +1195,8 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
     if (big_prev_nc > 0) {  // leave the candidate bitmap clean
       __syncthreads();
       for (int j = tid; j < big_prev_nc; j += nthr) {
-        const uint32_t q = cand[big_prev_cb + j] - (uint32_t)(big_prev_s - 1) * M;
+        const uint32_t q = pre ? (sm.cdec[big_prev_cb + j] & 0xFFFFu)
+                               : cand[big_prev_cb + j] - (uint32_t)(big_prev_s - 1) * M;
         sm.cbm[q >> 5] = 0;
       }
       big_prev_nc = 0;
@@ -1190,28 +1204,35 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
 
     // second wall, tree measurement and fidelity (Alg. 1 steps 4-6)
     __syncthreads();
-    build_factors<ENC>(tb, T - 1, wpow, sm.fw, sm.fmisc, false);
-    build_factors<ENC>(tb, T - 1, apow, sm.fa, sm.fmisc + 1, false);
+    load_factors<ENC>(tb, T - 1, tb->ftab_w, sm.fw, sm.fmisc);
+    load_factors<ENC>(tb, T - 1, tb->ftab_a, sm.fa, sm.fmisc + 1);
     __syncthreads();
     const double wr = sm.fmisc[0], ar = sm.fmisc[1];
     double fin[5] = {0, 0, 0, 0, 0};  // overlap, w_ground, w_total, good a-sum, good w-sum
-    for (uint32_t al = 0; al < apt; ++al) {
-      const uint32_t g = tid * apt + al;
-      if (g >= A) break;
-      const uint32_t a = xl ? xl[g] : g;
-      const uint32_t memw = mem[a] & kmask;
-      for (int b = 0; b < K2; ++b) {
-        const uint32_t j = al * K2 + b;
+    {
+      int cur = -1;
+      uint32_t memw = 0, g = 0;
+      double wa = 0.0, aa = 0.0;
+      for (uint64_t m = alive; m; m &= m - 1) {
+        const int j = __ffsll((unsigned long long)m) - 1;
+        const int al = j >> kb, b = j & (K2 - 1);
+        if (al != cur) {
+          cur = al;
+          g = tid * apt + (uint32_t)al;
+          const uint32_t a = xl ? xl[g] : g;
+          memw = mem[a] & kmask;
+          wa = fA(sm.fw, a) * wr;
+          aa = fA(sm.fa, a) * ar;
+        }
         const uint32_t w = st[j * nthr + tid];
-        if (!(w & W_ALIVE)) continue;
         double wt, at;
         bool ground;
         uint32_t bus;
         if (!(w & W_DEV)) {
           const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
           const uint32_t dv = ENC == QUBIT ? live : (live & memw);
-          wt = fA(sm.fw, a) * wr * sm.fw[F_D + dv] * sm.fw[F_K + (w & W_EK)];
-          at = fA(sm.fa, a) * ar * sm.fa[F_D + dv] * sm.fa[F_K + (w & W_EK)];
+          wt = wa * sm.fw[F_D + dv] * sm.fw[F_K + (w & W_EK)];
+          at = aa * sm.fa[F_D + dv] * sm.fa[F_K + (w & W_EK)];
           ground = true;
           bus = dv;
         } else {
@@ -1288,11 +1309,9 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
 
 }  // namespace
 
-uint32_t evolve_lds_bytes(int n, int k, int M, int D, int threads,
+uint32_t evolve_lds_bytes(int M, int D, int threads, uint32_t cdec_cap,
                           uint32_t e_cap, bool state_lds) {
-  (void)n;
-  (void)k;
-  return fixed_bytes(M, D, threads) + (state_lds ? e_cap * 4u : 0u);
+  return fixed_bytes(M, D, threads, cdec_cap) + (state_lds ? e_cap * 4u : 0u);
 }
 
 int evolve_occupancy(int enc, bool state_lds, int threads, uint32_t lds_bytes) {

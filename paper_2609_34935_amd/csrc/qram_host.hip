@@ -33,6 +33,8 @@ struct Plan {
   BucketShape b[MAXB];
   bool persistent = true;
   uint32_t pool_slots = 0;  // max emax over buckets
+  bool cdec_all = false;    // all candidates decoded into shared memory
+  uint32_t cdec_cap = 0;    // decoded-candidate entries in shared memory
   uint32_t grid_max = 0;
   uint32_t ecap_max = 0;
 };
@@ -48,7 +50,7 @@ struct qram_ctx {
   Tables htab{};
   Tables *dtab = nullptr;
   uint32_t *dmem = nullptr;
-  double *dwpow = nullptr, *dapow = nullptr;
+  double *dwpow = nullptr, *dapow = nullptr, *dftab = nullptr;
   std::vector<uint32_t> mem;
   std::string err;
   // work buffers (grown on demand)
@@ -308,6 +310,11 @@ qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
   }
   pl = Plan{};
   pl.nb = (int)ems.size();
+  // decode every candidate of a trajectory into shared memory when the
+  // candidate buffer is small; otherwise one slice at a time
+  const uint32_t ccap = cand_capacity(c);
+  pl.cdec_all = ccap <= 4096u;
+  pl.cdec_cap = pl.cdec_all ? ccap : (uint32_t)NCS;
   pl.persistent = c->schedule[mode] == 1;
   for (int i = 0; i < pl.nb; ++i) {
     BucketShape &b = pl.b[i];
@@ -326,9 +333,9 @@ qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
     b.threads = (int)thr;
     b.apt = apt;
     b.e_cap = apt * (uint32_t)c->K2 * thr;
-    const uint32_t fixed = evolve_lds_bytes(c->n, c->k, c->M, c->D, b.threads, 0, false);
+    const uint32_t fixed = evolve_lds_bytes(c->M, c->D, b.threads, pl.cdec_cap, 0, false);
     b.state_lds = fixed + b.e_cap * 4u <= std::min<size_t>(c->lds_max, 96u * 1024u);
-    b.lds = evolve_lds_bytes(c->n, c->k, c->M, c->D, b.threads, b.e_cap, b.state_lds);
+    b.lds = evolve_lds_bytes(c->M, c->D, b.threads, pl.cdec_cap, b.e_cap, b.state_lds);
     if (b.lds > c->lds_max) return fail(c, QRAM_E_RANGE, "workgroup shared memory exceeds the device limit");
     int occ = evolve_occupancy(c->enc, b.state_lds, b.threads, b.lds);
     if (occ < 1) occ = 1;
@@ -402,7 +409,8 @@ size_t buffers_bytes(const qram_ctx *c, uint32_t nb, const Plan &pl) {
 }
 
 size_t table_bytes(const qram_ctx *c) {
-  return (size_t)c->D * 4 + (size_t)(2 * c->emax + 1) * 8 * 2 + sizeof(Tables) + (size_t)(MAXT + 1) * 8;
+  return (size_t)c->D * 4 + (size_t)(2 * c->emax + 1) * 8 * 2 + sizeof(Tables) + (size_t)(MAXT + 1) * 8 +
+         (size_t)2 * c->T * (97 + (1 << c->k)) * 8;
 }
 
 uint32_t batch_size(const qram_ctx *c, uint32_t ntraj);
@@ -423,6 +431,7 @@ Run base_run(qram_ctx *c, int mode, uint64_t seed, const Plan *pl) {
   r.mode = mode;
   r.cand_cap = c->cand_cap;
   r.tier2_slow = c->tier2_global ? 1u : 0u;
+  if (pl) r.cdec_all = pl->cdec_all ? 1u : 0u;
   if (pl) {
     r.nbkt = (uint32_t)pl->nb;
     for (int i = 0; i < pl->nb; ++i) r.bkt_emax[i] = pl->b[i].emax;
@@ -691,12 +700,43 @@ qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
   if ((st = dev_alloc(c, &c->dwpow, wp.size()))) return bail(st);
   if ((st = dev_alloc(c, &c->dapow, ap.size()))) return bail(st);
   if ((st = dev_alloc(c, &c->dtab, 1))) return bail(st);
+  // per-slice factor tables: exposure through slice s of each 5-bit chunk
+  // of the address bits, of each data-token set, and of the routers
+  const int nd = 1 << c->k, nfs = 96 + nd + 1;
+  std::vector<double> ft((size_t)2 * c->T * nfs);
+  for (int which = 0; which < 2; ++which) {
+    const std::vector<double> &pw = which ? ap : wp;
+    for (int sl = 0; sl < c->T; ++sl) {
+      double *row = ft.data() + ((size_t)which * c->T + sl) * nfs;
+      for (int x = 0; x < 96; ++x) {
+        const int ch = x >> 5, v = x & 31;
+        int e = 0;
+        for (int b = 0; b < 5; ++b) {
+          const int pbit = 5 * ch + b;
+          if (pbit < c->n && ((v >> b) & 1)) e += c->htab.cntA[sl][c->n - 1 - pbit];
+        }
+        row[x] = pw[c->emax + e];
+      }
+      for (int v = 0; v < nd; ++v) {
+        int e = 0;
+        for (int b = 0; b < c->k; ++b)
+          if ((v >> b) & 1) e += c->htab.cntD[sl][b];
+        row[96 + v] = pw[c->emax + e];
+      }
+      row[96 + nd] = pw[c->emax + c->htab.cntR[sl]];
+    }
+  }
+  if ((st = dev_alloc(c, &c->dftab, ft.size()))) return bail(st);
   c->htab.mem = c->dmem;
   c->htab.wpow = c->dwpow;
   c->htab.apow = c->dapow;
+  c->htab.ftab_w = c->dftab;
+  c->htab.ftab_a = c->dftab + (size_t)c->T * nfs;
+  c->htab.nfs = nfs;
   if (hipMemcpy(c->dmem, c->mem.data(), c->D * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->dwpow, wp.data(), wp.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->dapow, ap.data(), ap.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->dftab, ft.data(), ft.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->dtab, &c->htab, sizeof(Tables), hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(c, QRAM_E_DEVICE, "table upload failed"));
   *out = c;
@@ -711,6 +751,7 @@ void qram_destroy(qram_ctx *c) {
   dev_free(&c->dmem);
   dev_free(&c->dwpow);
   dev_free(&c->dapow);
+  dev_free(&c->dftab);
   dev_free(&c->cand);
   dev_free(&c->ncand);
   dev_free(&c->nbad);

@@ -54,6 +54,9 @@ struct Tables {
   const uint32_t *mem;            // [D] memory words
   const double *wpow;             // [2 emax + 1] (1-gamma)^(m - emax)
   const double *apow;             // [2 emax + 1] a^(m - emax)
+  const double *ftab_w;           // [(T + 1) * nfs] per-slice factor tables, (1-gamma)^e
+  const double *ftab_a;           // the same with a^e
+  int nfs;                        // entries per slice: 96 address-chunk, 2^k data, 1 router
   uint32_t amask[MAXT];  // address tokens excitable after the gates of s (bit n-1-t)
   uint32_t dmask[MAXT];  // data tokens excitable after the gates of s (bit b)
   uint32_t cswap[MAXT];  // layers whose controlled swap fires at s
@@ -73,6 +76,7 @@ struct Run {
   uint32_t cand_cap;     // candidate slots per trajectory
   uint32_t forced;       // 1: forced history (single trajectory)
   uint32_t tier2_slow;   // 1: every tier-2 list takes the global-memory path
+  uint32_t cdec_all;     // 1: all candidates of a trajectory fit shared memory
   // bucket of this evolution launch
   uint32_t bucket;       // index of the bucket this launch serves
   uint32_t apt;          // explicit addresses per thread
@@ -116,7 +120,7 @@ hipError_t launch_evolve(const Tables *tb, const Run &rp, int enc,
                          bool state_lds, hipStream_t s);
 hipError_t launch_digest(const Run &rp, uint32_t ntraj, hipStream_t s);
 
-uint32_t evolve_lds_bytes(int n, int k, int M, int D, int threads,
+uint32_t evolve_lds_bytes(int M, int D, int threads, uint32_t cdec_cap,
                           uint32_t e_cap, bool state_lds);
 int evolve_occupancy(int enc, bool state_lds, int threads, uint32_t lds_bytes);
 hipError_t evolve_prepare(int lds_max, int *dyn_max);
