@@ -846,6 +846,13 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
       }
       QR_TM(7);
       if (nc == 0) continue;
+      if (ndev == 0 && !big) {
+        // a tier-1 component is excited only where the schedule puts one of
+        // its tokens: candidates on token-free sites hit nothing
+        bool maybe = false;
+        for (int c = 0; c < nc; ++c) maybe |= ((cd[c] >> 20) & 0xFFu) != NONE;
+        if (!maybe) continue;
+      }
       if (ndev > 0) __syncthreads();
 
       // owner pass: which of my components does a candidate hit?
@@ -901,19 +908,20 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
       __syncthreads();
       const double wr = sm.fmisc[0];
       double acc[3] = {0.0, 0.0, 0.0};  // w_empty, w_hit, good branches
-      if (njumps == 0) {  // initial labels: live tokens = bus word (qubit), every bit (qutrit)
+      if (njumps == 0) {
+        // initial labels: live tokens = bus word (qubit), every bit (qutrit).
+        // Only the hit components are summed; every address, explicit or
+        // good, is still on its no-jump orbit, so the total weight is the
+        // slice's closed-form sum over all addresses.
         for (uint32_t al = 0; al < apt; ++al) {
+          const uint64_t hm = (hmask >> (al * K2)) & kfull;
+          if (!hm) continue;
           const uint32_t g = tid * apt + al;
-          if (g >= A) break;
           const uint32_t a = xl ? xl[g] : g;
-          const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
           const double wa = fA(sm.fw, a) * wr;
-          for (int b = 0; b < K2; ++b) {
-            const double wt = wa * sm.fw[F_D + (ENC == QUBIT ? (uint32_t)b : (kmask & memw))];
-            if ((hmask >> (al * K2 + b)) & 1ull)
-              acc[1] += wt;
-            else
-              acc[0] += wt;
+          for (uint64_t m = hm; m; m &= m - 1) {
+            const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+            acc[1] += wa * sm.fw[F_D + (ENC == QUBIT ? b : (kmask & mem[a]))];
           }
         }
       } else {
@@ -946,7 +954,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
         }
       }
       const double my_hit_w = acc[1];
-      if (ref_alive) {
+      if (ref_alive && njumps > 0) {
         // good branches other than the reference, on their no-jump orbits
         for (int i = tid; i < D; i += nthr) {
           if ((uint32_t)i == ref || ((sm.badl[i >> 5] >> (i & 31)) & 1u)) continue;
@@ -965,8 +973,9 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
       }
       const double wgood = ref_alive ? acc[2] * sd : 0.0;
       const double u = rp->forced ? rp->uaux[s] : uniform53(rp->seed, (uint32_t)s, 0, traj, 2u);
-      const double w0 = acc[0] + wgood;
-      const double r = u * (w0 + acc[1]);
+      const double wall = njumps == 0 ? tb->ctot[s - 1] : acc[0] + wgood + acc[1];
+      const double w0 = njumps == 0 ? wall - acc[1] : acc[0] + wgood;
+      const double r = u * wall;
       if (r < w0) continue;  // J empty: K0 already accounted
       const double r2 = r - w0;
 
@@ -1204,6 +1213,34 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
 
     // second wall, tree measurement and fidelity (Alg. 1 steps 4-6)
     __syncthreads();
+    if (njumps == 0) {
+      // no jump: every branch ends on its no-jump orbit in the ground
+      // configuration, so the sums are the context's closed-form constants
+      if (tid == 0) {
+        const double ov = tb->ov_nojump, wt = tb->w_nojump;
+        const double norm = 1.0 / ((double)D * (double)K2);
+        const double uf = rp->forced ? rp->ufin : uniform53(rp->seed, 0, 0, traj, 3u);
+        const bool qg = uf * wt < wt;
+        rp->fid[tj] = (qg && wt > 0.0) ? ov * ov / wt * norm : 0.0;
+        if (rp->st) {
+          qram_traj_stats o;
+          o.n_cand = rp->ncand[tj];
+          o.n_bad = rp->nbad[tj];
+          o.ref_addr = ref;
+          o.n_explicit = E;
+          o.n_jumps = 0;
+          o.first_jump_slice = 0;
+          o.ref_survived = (uint8_t)(ref != 0xFFFFFFFFu);
+          o.q_ground = (uint8_t)qg;
+          o.flags = (uint8_t)((rp->ncand[tj] > ccap ? 1 : 0));
+          o.pad = 0;
+          o.fid_pre = wt > 0.0 ? ov * ov / wt * norm : 0.0;
+          rp->st[tj] = o;
+        }
+      }
+      QR_TM(6);
+      continue;
+    }
     load_factors<ENC>(tb, T - 1, tb->ftab_w, sm.fw, sm.fmisc);
     load_factors<ENC>(tb, T - 1, tb->ftab_a, sm.fa, sm.fmisc + 1);
     __syncthreads();

@@ -50,7 +50,7 @@ struct qram_ctx {
   Tables htab{};
   Tables *dtab = nullptr;
   uint32_t *dmem = nullptr;
-  double *dwpow = nullptr, *dapow = nullptr, *dftab = nullptr;
+  double *dwpow = nullptr, *dapow = nullptr, *dftab = nullptr, *dctot = nullptr;
   std::vector<uint32_t> mem;
   std::string err;
   // work buffers (grown on demand)
@@ -726,6 +726,29 @@ qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
       row[96 + nd] = pw[c->emax + c->htab.cntR[sl]];
     }
   }
+  // no-jump sums over all addresses (every branch on its no-jump orbit):
+  // the total weight through each slice, and the final overlap and weight
+  std::vector<double> ctot(c->T);
+  auto nojump_sum = [&](int which, int sl) {
+    const double *row = ft.data() + ((size_t)which * c->T + sl) * nfs;
+    double sum = 0.0, comp = 0.0;  // Neumaier
+    for (int a = 0; a < c->D; ++a) {
+      double g = 0.0;
+      if (c->enc == QUBIT)
+        for (int b = 0; b < nd; ++b) g += row[96 + b];
+      else
+        g = row[96 + (c->mem[a] & (uint32_t)(nd - 1))];
+      const double x = row[a & 31] * row[32 + ((a >> 5) & 31)] * row[64 + ((a >> 10) & 31)] * row[96 + nd] * g;
+      const double t = sum + x;
+      comp += std::fabs(sum) >= std::fabs(x) ? (sum - t) + x : (x - t) + sum;
+      sum = t;
+    }
+    return sum + comp;
+  };
+  for (int sl = 0; sl < c->T; ++sl) ctot[sl] = nojump_sum(0, sl);
+  c->htab.w_nojump = ctot[c->T - 1];
+  c->htab.ov_nojump = nojump_sum(1, c->T - 1);
+  if ((st = dev_alloc(c, &c->dctot, ctot.size()))) return bail(st);
   if ((st = dev_alloc(c, &c->dftab, ft.size()))) return bail(st);
   c->htab.mem = c->dmem;
   c->htab.wpow = c->dwpow;
@@ -733,10 +756,12 @@ qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
   c->htab.ftab_w = c->dftab;
   c->htab.ftab_a = c->dftab + (size_t)c->T * nfs;
   c->htab.nfs = nfs;
+  c->htab.ctot = c->dctot;
   if (hipMemcpy(c->dmem, c->mem.data(), c->D * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->dwpow, wp.data(), wp.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->dapow, ap.data(), ap.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->dftab, ft.data(), ft.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->dctot, ctot.data(), ctot.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->dtab, &c->htab, sizeof(Tables), hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(c, QRAM_E_DEVICE, "table upload failed"));
   *out = c;
@@ -752,6 +777,7 @@ void qram_destroy(qram_ctx *c) {
   dev_free(&c->dwpow);
   dev_free(&c->dapow);
   dev_free(&c->dftab);
+  dev_free(&c->dctot);
   dev_free(&c->cand);
   dev_free(&c->ncand);
   dev_free(&c->nbad);

@@ -57,6 +57,8 @@ struct Tables {
   const double *ftab_w;           // [(T + 1) * nfs] per-slice factor tables, (1-gamma)^e
   const double *ftab_a;           // the same with a^e
   int nfs;                        // entries per slice: 96 address-chunk, 2^k data, 1 router
+  const double *ctot;             // [T] total no-jump weight of all addresses through slice s
+  double ov_nojump, w_nojump;     // final overlap and weight when no jump occurred
   uint32_t amask[MAXT];  // address tokens excitable after the gates of s (bit n-1-t)
   uint32_t dmask[MAXT];  // data tokens excitable after the gates of s (bit b)
   uint32_t cswap[MAXT];  // layers whose controlled swap fires at s
