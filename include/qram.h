@@ -160,10 +160,13 @@ qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,
  * Launch shape of a mode.  Trajectories are grouped by their number of
  * explicitly evolved components; each group runs as its own launch whose
  * workgroups hold about slots_per_thread components per thread (4, 8, 16, 32
- * or 64; 0 restores the automatic choice).  schedule 0 hands trajectories to
- * workgroups round robin, 1 takes them from a device queue, longest first.
- * The shape changes only the speed: results are identical across shapes up to
- * the rounding of the per-slice weight sums.
+ * or 64; 0 restores the automatic choice).  schedule bit 0: 0 hands
+ * trajectories to workgroups round robin, 1 takes them from a device queue,
+ * longest first; bit 1: keep the component state words in device memory
+ * instead of workgroup shared memory (smaller workgroups per compute unit
+ * footprint, more trajectories in flight).  The shape changes only the speed:
+ * results are identical across shapes up to the rounding of the per-slice
+ * weight sums.
  */
 qram_status qram_set_launch(qram_ctx *ctx, qram_mode mode, int slots_per_thread,
                             int schedule);

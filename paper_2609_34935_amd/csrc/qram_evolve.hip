@@ -94,6 +94,16 @@ __device__ __forceinline__ int t1_site(const Tables *__restrict__ tb, int s,
   return (int)(2 * v + slot);
 }
 
+// Initial state word of the component (address a, bus word b): live tokens =
+// the bus word (qubit) or every data bit (qutrit); the qubit sign already
+// holds every fetch phase its live tokens will pick up.
+template <int ENC>
+__device__ __forceinline__ uint32_t init_word(uint32_t memw_a, uint32_t b, uint32_t kmask) {
+  const uint32_t live = ENC == QUBIT ? b : kmask;
+  const bool sg = ENC == QUBIT && (__popc(live & memw_a & kmask) & 1);
+  return W_ALIVE | (live << W_LIVE_SH) | (sg ? W_SIGN : 0u);
+}
+
 // Bit b set for every b that is a subset of c (c below 2^k).
 __device__ __forceinline__ uint64_t subsets_of(uint32_t c, int k) {
   uint64_t m = 1;
@@ -773,16 +783,11 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
         sm.badl[w] = (uint32_t)(badg[w >> 1] >> (32 * (w & 1)));
     // initial components: data-loading input after the first wall; the sign
     // already holds every fetch phase its live tokens will pick up
+    // initial components: data-loading input after the first wall.  Their
+    // state words (init_word) are written only at the trajectory's first jump.
     uint64_t alive = 0, devm = 0;  // this thread's live and tier-2 slots (bit j)
     for (uint32_t al = 0; al < apt; ++al) {
-      const uint32_t g = tid * apt + al;
-      if (g >= A) break;
-      const uint32_t a = xl ? xl[g] : g;
-      for (int b = 0; b < K2; ++b) {
-        const uint32_t live = ENC == QUBIT ? (uint32_t)b : kmask;
-        const bool sg = ENC == QUBIT && (__popc(live & mem[a] & kmask) & 1);
-        st[(al * K2 + b) * nthr + tid] = W_ALIVE | (live << W_LIVE_SH) | (sg ? W_SIGN : 0u);
-      }
+      if (tid * apt + al >= A) break;
       alive |= kfull << (al * K2);
     }
     __syncthreads();
@@ -1000,7 +1005,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
           for (int b = 0; b < K2; ++b) {
             const uint32_t j = al * K2 + b;
             if (!((hmask >> j) & 1ull)) continue;
-            const uint32_t w = st[j * nthr + tid];
+            const uint32_t w = njumps == 0 ? init_word<ENC>(mem[a], (uint32_t)b, kmask) : st[j * nthr + tid];
             double wt;
             if (!(w & W_DEV)) {
               const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
@@ -1024,7 +1029,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
         const uint32_t g = tid * apt + al;
         const uint32_t a = xl ? xl[g] : g;
         const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
-        const uint32_t w = st[pick * nthr + tid];
+        const uint32_t w = njumps == 0 ? init_word<ENC>(mem[a], b, kmask) : st[pick * nthr + tid];
         if (!(w & W_DEV)) {
           const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
           if (!big) {
@@ -1067,7 +1072,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
         const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
         for (int b = 0; b < K2; ++b) {
           const uint32_t j = al * K2 + b;
-          uint32_t w = st[j * nthr + tid];
+          uint32_t w = njumps == 0 ? init_word<ENC>(mem[a], (uint32_t)b, kmask) : st[j * nthr + tid];
           if (!(w & W_ALIVE)) continue;
           uint16_t *recp = pool + (size_t)(g * K2 + b) * rec;
           if (!(w & W_DEV)) {

@@ -315,7 +315,8 @@ qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
   const uint32_t ccap = cand_capacity(c);
   pl.cdec_all = ccap <= 4096u;
   pl.cdec_cap = pl.cdec_all ? ccap : (uint32_t)NCS;
-  pl.persistent = c->schedule[mode] == 1;
+  pl.persistent = (c->schedule[mode] & 1) != 0;
+  const bool state_global = (c->schedule[mode] & 2) != 0;
   for (int i = 0; i < pl.nb; ++i) {
     BucketShape &b = pl.b[i];
     b.emax = ems[i];
@@ -334,7 +335,7 @@ qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
     b.apt = apt;
     b.e_cap = apt * (uint32_t)c->K2 * thr;
     const uint32_t fixed = evolve_lds_bytes(c->M, c->D, b.threads, pl.cdec_cap, 0, false);
-    b.state_lds = fixed + b.e_cap * 4u <= std::min<size_t>(c->lds_max, 96u * 1024u);
+    b.state_lds = !state_global && fixed + b.e_cap * 4u <= std::min<size_t>(c->lds_max, 96u * 1024u);
     b.lds = evolve_lds_bytes(c->M, c->D, b.threads, pl.cdec_cap, b.e_cap, b.state_lds);
     if (b.lds > c->lds_max) return fail(c, QRAM_E_RANGE, "workgroup shared memory exceeds the device limit");
     int occ = evolve_occupancy(c->enc, b.state_lds, b.threads, b.lds);
@@ -940,7 +941,7 @@ qram_status qram_set_launch(qram_ctx *c, qram_mode mode, int slots_per_thread,
   if (slots_per_thread != 0 && slots_per_thread != 4 && slots_per_thread != 8 && slots_per_thread != 16 &&
       slots_per_thread != 32 && slots_per_thread != 64)
     return fail(c, QRAM_E_INVAL, "slots_per_thread must be 0, 4, 8, 16, 32 or 64");
-  if (schedule != 0 && schedule != 1) return fail(c, QRAM_E_INVAL, "schedule must be 0 or 1");
+  if (schedule < 0 || schedule > 3) return fail(c, QRAM_E_INVAL, "schedule must be 0, 1, 2 or 3");
   c->spt[mode] = slots_per_thread;
   c->schedule[mode] = schedule;
   return QRAM_OK;
@@ -980,7 +981,7 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
   double best = 1e300;
   int bs = 16, bsched = 1;
   bool sampled = false;
-  for (int sched = 0; sched < 2; ++sched) {
+  for (int sched = 0; sched < 4; ++sched) {
     for (int ci = 0; ci < 5; ++ci) {
       c->spt[mode] = cands[ci];
       c->schedule[mode] = sched;

@@ -135,7 +135,7 @@ def test_config2_qubit_sample(lib, orc, gamma):
     compare_runs(lib, orc, 6, 1, QUBIT, gamma, mem, 880002, 0, 400)
 
 
-@pytest.mark.parametrize("spt,sched", [(4, 0), (8, 1), (16, 0), (32, 1), (64, 1)])
+@pytest.mark.parametrize("spt,sched", [(4, 0), (8, 1), (16, 0), (32, 1), (64, 1), (8, 2), (32, 3), (64, 3)])
 def test_launch_shapes(lib, orc, spt, sched):
     mem = memory_words(5, 3, 55)
     compare_runs(lib, orc, 5, 3, QUBIT, 0.01, mem, 99, 0, 120, threads=(spt, sched))
