@@ -627,7 +627,8 @@ struct Sm {
   double *fw;       // factor tables (1-gamma)^m: A chunks [3*32], data [256], lost [256]
   double *fa;       // the same with a^m (final)
   double *fmisc;    // [4]
-  uint32_t *cstart; // [MAXT + 1]
+  uint32_t *cstart; // [MAXT + 1] first candidate of each slice
+  uint8_t *nxt;     // [MAXT + 1] first slice >= s holding a candidate (T: none)
   uint32_t *cdec;   // [cdec_cap]: the slice's decoded candidates, or all of them
   uint32_t *Jb;     // [JMAX]
   int *misc;        // [8]
@@ -646,6 +647,7 @@ __host__ __device__ inline uint32_t fixed_bytes(int M, int D, int threads, uint3
   b += al16(F_N * 8) * 2;
   b += al16(4 * 8);
   b += al16((MAXT + 1) * 4);
+  b += al16(MAXT + 1);
   b += al16(cdec_cap * 4);
   b += al16(JMAX * 4);
   b += al16(8 * 4);
@@ -670,6 +672,8 @@ __device__ inline Sm carve(unsigned char *base, int M, int D, int threads, uint3
   p += al16(4 * 8);
   m.cstart = reinterpret_cast<uint32_t *>(p);
   p += al16((MAXT + 1) * 4);
+  m.nxt = reinterpret_cast<uint8_t *>(p);
+  p += al16(MAXT + 1);
   m.cdec = reinterpret_cast<uint32_t *>(p);
   p += al16(cdec_cap * 4);
   m.Jb = reinterpret_cast<uint32_t *>(p);
@@ -746,13 +750,17 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
   QR_TINIT
   const uint32_t seg0 = rp->bucket_base[bkt];
   const uint32_t segn = rp->bucket_base[bkt + 1] - seg0;
+  // queue slot of the next trajectory: taken one trajectory ahead, so the
+  // atomic's round trip overlaps the current trajectory's work
+  uint32_t next_slot = 0;
+  if (rp->persistent && tid == 0) next_slot = atomicAdd(&rp->counter[bkt], 1u);
   for (uint32_t iter = 0;; ++iter) {
+    if (rp->persistent && tid == 0) sm.misc[0] = (int)next_slot;
     __syncthreads();
     uint32_t qslot;
     if (rp->persistent) {
-      if (tid == 0) sm.misc[0] = (int)atomicAdd(&rp->counter[bkt], 1u);
-      __syncthreads();
       qslot = (uint32_t)sm.misc[0];
+      if (qslot < segn && tid == 0) next_slot = atomicAdd(&rp->counter[bkt], 1u);
     } else {
       qslot = blockIdx.x + iter * gridDim.x;
     }
@@ -771,7 +779,10 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
       const uint32_t cj = j < nct ? cand[j] : 0u;
       const int sj = j < nct ? (int)(cj / (uint32_t)M) + 1 : T;
       const int sp = j > 0 ? (int)(cand[j - 1] / (uint32_t)M) + 1 : 0;
-      for (int ss = sp + 1; ss <= sj; ++ss) sm.cstart[ss] = j;
+      for (int ss = sp + 1; ss <= sj; ++ss) {
+        sm.cstart[ss] = j;
+        sm.nxt[ss] = (uint8_t)sj;
+      }
       if (pre && j < nct) {  // site, layer and schedule token of every candidate
         const uint32_t q = cj - (uint32_t)(sj - 1) * M;
         const int l = layer_of(q >> 1);
@@ -798,6 +809,10 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) k_evolve(const Tabl
     int njumps = 0, first_jump = 0;
 
     for (int s = 1; s < T; ++s) {
+      if (ndev == 0) {  // without tier-2 components only slices with candidates matter
+        s = sm.nxt[s];
+        if (s >= T) break;
+      }
       const uint32_t cb = sm.cstart[s];
       const int nc = (int)(sm.cstart[s + 1] - cb);
       if (nc == 0 && ndev == 0) continue;
