@@ -129,18 +129,16 @@ def serving_leg(P, nreq, seed, chunk, max_active, budget_gib):
     mu = nreq / sat["wall_s"]
     out["saturated"] = dict(sat, capacity_req_per_s=round(mu, 2))
     for frac, key in ((0.5, "load_0.5"), (0.8, "load_0.8")):
-        rq = request_mix(nreq, seed + int(frac * 10))
-        mm = [memory_words(r["n"], r["k"], r["mem_seed"]) for r in rq]
         rng = np.random.default_rng(seed + 100 + int(frac * 10))
         arrivals = np.cumsum(rng.exponential(1.0 / (frac * mu), size=nreq))
-        out[key] = dict(_serve_once(P, rq, mm, arrivals, chunk, max_active, budget_gib, key),
+        out[key] = dict(_serve_once(P, reqs, mems, arrivals, chunk, max_active, budget_gib, key),
                         arrival_rate_per_s=round(frac * mu, 2))
     head = out["load_0.8"]
     return {"p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "at": "Poisson arrivals at 0.8 x measured capacity",
             "aggregate_traj_per_s": out["saturated"]["aggregate_traj_per_s"], **out,
             "mix": "n~U{4..12}, k~U{1,2,4}, encoding~U, gamma log-uniform [1e-5,1e-2], "
                    "shots log-uniform [1e3,1e5], seeded Bernoulli(0.5) memory, pruned mode, master seed "
-                   f"{seed} (+5, +8 for the two loads)",
+                   f"{seed}; the same requests in every phase, arrival times seeded {seed + 105} and {seed + 108}",
             "server": {"max_active": max_active, "chunk": chunk, "hbm_budget_gib": budget_gib}}
 
 
