@@ -364,6 +364,7 @@ struct RList {
   // C 16-bit entries, two per register; EMPTY marks a free entry
   uint32_t p[C / 2];
   uint32_t bus;
+  bool dirty;  // changed since load: the record needs writing back
   static constexpr uint32_t SM = ENC == QUTRIT ? 0x7FFFu : 0xFFFFu;
 
   __device__ __forceinline__ uint32_t get(int j) const {
@@ -372,10 +373,12 @@ struct RList {
   __device__ __forceinline__ void set(int j, uint32_t x) {
     const int sh = (j & 1) * 16;
     p[j >> 1] = (p[j >> 1] & ~(0xFFFFu << sh)) | (x << sh);
+    dirty = true;
   }
   __device__ __forceinline__ void load(const uint16_t *rec, uint32_t cnt) {
     const uint32_t *r32 = reinterpret_cast<const uint32_t *>(rec);
     bus = r32[0] >> 16;
+    dirty = false;
 #pragma unroll
     for (int j = 0; j < C; j += 2) {
       const uint32_t w = (uint32_t)j < cnt ? r32[1 + j / 2] : 0xFFFFFFFFu;
@@ -538,9 +541,11 @@ __device__ __forceinline__ void t2_gates_reg(const Tables *__restrict__ tb, int 
     if (d0 && !bbit) {
       L.remove_site(1);
       L.bus |= 1u << bb;
+      L.dirty = true;
     } else if (!d0 && bbit) {
       ovf |= !L.add(1);
       L.bus &= ~(1u << bb);
+      L.dirty = true;
     }
   }
   const int fb = tb->fetch_b[s];
@@ -597,13 +602,13 @@ __device__ __forceinline__ uint32_t t2_step(const Tables *__restrict__ tb,
     L.load(recp, cnt0);
     t2_gates_reg<ENC, C1>(tb, s, L, a, word, ovf);
     if (nc > 0) hit = L.hit(big, nc, cdec, cbm);
-    cnt = L.store(recp);
+    cnt = L.dirty ? L.store(recp) : cnt0;
   } else if (!slow && cnt0 + grow <= C2) {
     RList<ENC, C2> L;
     L.load(recp, cnt0);
     t2_gates_reg<ENC, C2>(tb, s, L, a, word, ovf);
     if (nc > 0) hit = L.hit(big, nc, cdec, cbm);
-    cnt = L.store(recp);
+    cnt = L.dirty ? L.store(recp) : cnt0;
   } else {
     Rec<ENC> R{recp};
     word ^= t2_gates_mem<ENC>(tb, s, R, a, err);
