@@ -102,3 +102,14 @@ def test_c5_qutrit_n14_sampled(lib, orc):
     idx = [0, 1, 2, 1000, 2047, nt - 1]
     fp, sp = check_run(lib, orc, n, k, QUTRIT, gamma, mem, 880005, nt, idx)
     assert np.all(sp["n_bad"] == 2**n)  # every branch bad at this noise level
+
+
+@pytest.mark.parametrize("n,k,enc,gamma,nsample", [
+    (15, 1, QUBIT, 1e-5, 3),    # largest qubit tree (n + k = 16)
+    (14, 8, QUTRIT, 1e-5, 4),   # largest qutrit tree and data word
+    (10, 6, QUBIT, 1e-4, 6),    # largest qubit data word
+    (12, 4, QUBIT, 2e-4, 4)])   # the serving mix's largest request shape
+def test_maximum_sizes(lib, orc, n, k, enc, gamma, nsample):
+    mem = memory_words(n, k, 4000 + n + k)
+    idx = list(range(nsample))
+    check_run(lib, orc, n, k, enc, gamma, mem, 990000 + n, 256, idx)
