@@ -401,21 +401,18 @@ struct RList {
     rec[1] = (uint16_t)bus;
     return pos;
   }
+  // (EMPTY & SM is above every site of a tree with n <= 15 (qubit) or
+  // n <= 14 (qutrit), so an empty entry never matches a site)
   __device__ __forceinline__ bool has(uint32_t q) const {
     bool f = false;
 #pragma unroll
-    for (int j = 0; j < C; ++j) {
-      const uint32_t x = get(j);
-      f |= x != EMPTY && (x & SM) == q;
-    }
+    for (int j = 0; j < C; ++j) f |= (get(j) & SM) == q;
     return f;
   }
   __device__ __forceinline__ void remove_site(uint32_t q) {
 #pragma unroll
-    for (int j = 0; j < C; ++j) {
-      const uint32_t x = get(j);
-      if (x != EMPTY && (x & SM) == q) set(j, EMPTY);
-    }
+    for (int j = 0; j < C; ++j)
+      if ((get(j) & SM) == q) set(j, EMPTY);
   }
   __device__ __forceinline__ bool add(uint32_t x) {
     bool placed = false;
@@ -439,7 +436,7 @@ struct RList {
 #pragma unroll
     for (int j = 0; j < C; ++j) {
       const uint32_t x = get(j);
-      if (x != EMPTY && (x & SM) == 2 * v) d = ENC == QUBIT ? 1 : ((x & LV_R_BIT) ? 1 : 0);
+      if ((x & SM) == 2 * v) d = ENC == QUBIT ? 1 : ((x & LV_R_BIT) ? 1 : 0);
     }
     return d;
   }
