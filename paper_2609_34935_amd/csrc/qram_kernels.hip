@@ -17,13 +17,17 @@ namespace qr {
 // ---------------------------------------------------------------------------
 // k_sample
 // ---------------------------------------------------------------------------
-template <bool WRITE>
+// MODE 0 counts the candidates of block b, 1 also writes them to out[base..]
+// (below cap), 2 keeps the first four of the thread in buf (cnt counts on
+// from its value on entry).
+template <int MODE>
 __device__ __forceinline__ uint32_t walk_block(uint32_t b, uint32_t len,
                                                uint32_t traj, uint32_t k0,
                                                uint32_t k1, const uint64_t *G,
                                                uint32_t *out, uint32_t base,
-                                               uint32_t cap) {
-  uint32_t pos = 0, cnt = 0;
+                                               uint32_t cap, uint32_t (&buf)[4],
+                                               uint32_t cnt = 0) {
+  uint32_t pos = 0;
   for (uint32_t j = 0;; ++j) {
     const uint4 w = philox10(make_uint4(b, j, traj, 1u), k0, k1);
     const uint64_t u = (uint64_t)w.x | ((uint64_t)w.y << 32);
@@ -38,7 +42,14 @@ __device__ __forceinline__ uint32_t walk_block(uint32_t b, uint32_t len,
       else
         lo = mid + 1;
     }
-    if (WRITE && base + cnt < cap) out[base + cnt] = 64u * b + pos + lo;
+    const uint32_t L = 64u * b + pos + lo;
+    if (MODE == 1 && base + cnt < cap) out[base + cnt] = L;
+    if (MODE == 2) {
+      buf[0] = cnt == 0 ? L : buf[0];
+      buf[1] = cnt == 1 ? L : buf[1];
+      buf[2] = cnt == 2 ? L : buf[2];
+      buf[3] = cnt == 3 ? L : buf[3];
+    }
     ++cnt;
     pos += lo + 1;
     if (pos >= len) break;
@@ -63,20 +74,28 @@ __global__ void __launch_bounds__(256) k_sample(const Tables *__restrict__ tb,
   const uint32_t cap = rp->cand_cap;
   for (uint32_t tj = blockIdx.x; tj < rp->ntraj; tj += gridDim.x) {
     const uint32_t traj = rp->traj0 + tj;
-    uint32_t cnt = 0;
+    // one walk keeps each thread's first four candidates in registers; a
+    // second walk writes them only when some thread of the block had more
+    uint32_t cnt = 0, buf[4] = {0, 0, 0, 0};
     for (uint32_t b = b0; b < b1; ++b) {
       const uint32_t len = (uint32_t)min((uint64_t)64, S - 64ull * b);
-      cnt += walk_block<false>(b, len, traj, k0, k1, G, nullptr, 0, 0);
+      cnt = walk_block<2>(b, len, traj, k0, k1, G, nullptr, 0, 0, buf, cnt);
     }
     uint32_t total;
     const uint32_t off = block_excl_scan_u32(cnt, sbuf, &total);
     uint32_t *out = rp->cand + (size_t)tj * cap;
-    if (cnt) {
-      uint32_t o = off;
-      for (uint32_t b = b0; b < b1; ++b) {
-        const uint32_t len = (uint32_t)min((uint64_t)64, S - 64ull * b);
-        o += walk_block<true>(b, len, traj, k0, k1, G, out, o, cap);
+    if (__syncthreads_or(cnt > 4u)) {
+      if (cnt) {
+        uint32_t o = off;
+        for (uint32_t b = b0; b < b1; ++b) {
+          const uint32_t len = (uint32_t)min((uint64_t)64, S - 64ull * b);
+          o += walk_block<1>(b, len, traj, k0, k1, G, out, o, cap, buf);
+        }
       }
+    } else {
+#pragma unroll
+      for (uint32_t i = 0; i < 4; ++i)
+        if (i < cnt && off + i < cap) out[off + i] = buf[i];
     }
     if (tid == 0) {
       rp->ncand[tj] = total;
