@@ -587,7 +587,7 @@ __device__ __forceinline__ uint32_t t2_step(const Tables *__restrict__ tb,
                                             uint32_t &word, bool slow, bool big,
                                             int nc, const uint32_t *cdec,
                                             const uint32_t *cbm, bool &hit,
-                                            uint32_t *err) {
+                                            uint32_t &bus, uint32_t *err) {
   // register capacities; the gates of one slice add at most `grow` entries
   constexpr uint32_t C1 = ENC == QUBIT ? 16 : 24, C2 = ENC == QUBIT ? 24 : 32;
   constexpr uint32_t grow = ENC == QUBIT ? 2 : 8;
@@ -600,16 +600,19 @@ __device__ __forceinline__ uint32_t t2_step(const Tables *__restrict__ tb,
     t2_gates_reg<ENC, C1>(tb, s, L, a, word, ovf);
     if (nc > 0) hit = L.hit(big, nc, cdec, cbm);
     cnt = L.dirty ? L.store(recp) : cnt0;
+    bus = L.bus;
   } else if (!slow && cnt0 + grow <= C2) {
     RList<ENC, C2> L;
     L.load(recp, cnt0);
     t2_gates_reg<ENC, C2>(tb, s, L, a, word, ovf);
     if (nc > 0) hit = L.hit(big, nc, cdec, cbm);
     cnt = L.dirty ? L.store(recp) : cnt0;
+    bus = L.bus;
   } else {
     Rec<ENC> R{recp};
     word ^= t2_gates_mem<ENC>(tb, s, R, a, err);
     cnt = R.cnt();
+    bus = R.r[1];
     if (nc > 0)
       for (uint32_t q = 0; q < cnt && !hit; ++q)
         hit = big ? cand_bm(cbm, R.site(q)) : cand_list(cdec, nc, R.site(q));
@@ -636,12 +639,14 @@ struct Sm {
   int *misc;        // [8]
   uint32_t *cbm;    // [(M + 31) / 32]
   uint32_t *badl;   // [(D + 31) / 32]
+  uint8_t *wc;      // [T * (n + k)] exposure counts of each token through each slice
   uint32_t *st;     // [e_cap] when the state lives in LDS
 };
 
 constexpr int F_A = 0, F_D = 96, F_K = 96 + 256, F_N = 96 + 256 + 256;
 
-__host__ __device__ inline uint32_t fixed_bytes(int M, int D, int threads, uint32_t cdec_cap) {
+__host__ __device__ inline uint32_t fixed_bytes(int M, int D, int threads, uint32_t cdec_cap,
+                                                uint32_t walk_bytes) {
   const int nw = threads >> 6;
   uint32_t b = 0;
   b += al16(2 * nw * 8 * 8);
@@ -655,10 +660,12 @@ __host__ __device__ inline uint32_t fixed_bytes(int M, int D, int threads, uint3
   b += al16(8 * 4);
   b += al16(((M + 31) / 32) * 4);
   b += al16(((D + 31) / 32) * 4);
+  b += al16(walk_bytes);
   return b;
 }
 
-__device__ inline Sm carve(unsigned char *base, int M, int D, int threads, uint32_t cdec_cap) {
+__device__ inline Sm carve(unsigned char *base, int M, int D, int threads, uint32_t cdec_cap,
+                           uint32_t walk_bytes) {
   const int nw = threads >> 6;
   Sm m;
   unsigned char *p = base;
@@ -686,6 +693,8 @@ __device__ inline Sm carve(unsigned char *base, int M, int D, int threads, uint3
   p += al16(((M + 31) / 32) * 4);
   m.badl = reinterpret_cast<uint32_t *>(p);
   p += al16(((D + 31) / 32) * 4);
+  m.wc = reinterpret_cast<uint8_t *>(p);
+  p += al16(walk_bytes);
   m.st = reinterpret_cast<uint32_t *>(p);
   return m;
 }
@@ -716,6 +725,197 @@ __device__ __forceinline__ double fA(const double *f, uint32_t a) {
 }
 
 // ---------------------------------------------------------------------------
+// qubit: slices before the first jump, one wave
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+constexpr int WALK_MAXC = 6;     // token candidates per slice the walk combines
+constexpr int WALK_MAXA = 2048;  // qutrit: addresses per slice the walk sums over
+
+// Until the first jump every component keeps its initial label: address a
+// and bus word b (qubit) or the fetched data bits (qutrit).  A candidate on
+// a token site then hits the components whose address lies below its node
+// (fixed leading address bits) and whose token there is excited: one more
+// address bit set, or, for a data token, one bus bit set (qubit) or that
+// memory bit fetched (qutrit).  Good branches are never hit, so the sum of
+// the weights of the hit components over every address equals the sum over
+// the explicit ones, and with the slice's closed-form total it decides the
+// slice's draw (Eq. maskweight) as the block does, without a pass over the
+// components.
+//   qubit: the weight before the layer of slice s factorises over the
+//     tokens, the product of f_p = (1-gamma)^e over the set address bits p
+//     and of g_c over the set bus bits c (e: that token's exposure through
+//     slice s-1).  An intersection of hit sets fixes some address and bus
+//     bits, so its weight is a product, and the weight of the union follows
+//     by inclusion-exclusion with one subset of candidates per lane.
+//   qutrit: the data factor depends on the memory word, so the lanes sum the
+//     weights of the hit addresses over the union of the candidates'
+//     subtrees (nested subtrees taken once).
+//
+// Called by the 64 lanes of wave 0 at a slice s holding candidates; returns
+// the first slice from s on that the block must evolve: a slice whose draw
+// picks a nonempty J, one with too many candidates or addresses to sum, or T.
+template <int ENC>
+__device__ __forceinline__ int nojump_walk(const Tables *__restrict__ tb, const Run *rp,
+                                           const Sm &sm, const uint32_t *__restrict__ cand,
+                                           bool pre, int s, uint32_t traj) {
+  const int n = tb->n, k = tb->k, T = tb->T, nb = n + k;
+  const uint32_t M = (uint32_t)tb->M;
+  const uint32_t kmask = (1u << k) - 1u;
+  const int lane = threadIdx.x & 63;
+  while (s < T) {
+    const uint32_t cb = sm.cstart[s];
+    const int nc = (int)(sm.cstart[s + 1] - cb);
+    if (nc > NCS) return s;
+    uint32_t x = 0;
+    if (lane < nc) {
+      if (pre) {
+        x = sm.cdec[cb + lane];
+      } else {
+        const uint32_t q = cand[cb + lane] - (uint32_t)(s - 1) * M;
+        const int l = layer_of(q >> 1);
+        x = q | ((uint32_t)l << 16) | ((uint32_t)tb->tok[s][l][q & 1u] << 20);
+      }
+    }
+    const uint32_t tk = (x >> 20) & 0xFFu;
+    const int l = (int)((x >> 16) & 15u);
+    const uint32_t idx = ((x & 0xFFFFu) >> 1) + 1u - (1u << l);  // node's index in its layer
+    // lane p < n: f_p; lane n + c: g_c (slice s-1)
+    double f = 1.0;
+    if (lane < nb) f = sm.fw[F_K + sm.wc[(s - 1) * nb + lane]];
+    double H = 0.0;
+    if (ENC == QUBIT) {
+      const bool tokc = lane < nc && tk != NONE;
+      const uint64_t bal = __ballot(tokc);
+      const int m = __popcll(bal);
+      if (m > WALK_MAXC) return s;
+      if (m > 0) {
+        // this lane's candidate: address bits forced to 1 / to 0, bus bits forced to 1
+        uint32_t A1 = 0, A0 = 0, B1 = 0;
+        if (tokc) {
+          A1 = idx << (n - l);
+          A0 = (((1u << l) - 1u) << (n - l)) & ~A1;
+          if (tk < (uint32_t)n)
+            A1 |= 1u << (n - 1 - (int)tk);
+          else
+            B1 = 1u << (tk - (uint32_t)n);
+        }
+        // subset `lane` of the token candidates (bit i: the i-th of them)
+        uint32_t a1 = 0, a0 = 0, b1 = 0;
+        uint64_t rest = bal;
+        for (int i = 0; i < m; ++i) {
+          const int src = __ffsll((unsigned long long)rest) - 1;
+          rest &= rest - 1;
+          const uint32_t y1 = (uint32_t)__builtin_amdgcn_readlane((int)A1, src);
+          const uint32_t y0 = (uint32_t)__builtin_amdgcn_readlane((int)A0, src);
+          const uint32_t z1 = (uint32_t)__builtin_amdgcn_readlane((int)B1, src);
+          if ((lane >> i) & 1) {
+            a1 |= y1;
+            a0 |= y0;
+            b1 |= z1;
+          }
+        }
+        const bool term = lane >= 1 && lane < (1 << m) && !(a1 & a0);
+        double w = 1.0;
+        for (int p = 0; p < nb; ++p) {
+          const double fp = readlane_f64(f, p);
+          const bool one = p < n ? ((a1 >> p) & 1u) : ((b1 >> (p - n)) & 1u);
+          const bool zero = p < n && ((a0 >> p) & 1u);
+          w *= one ? fp : (zero ? 1.0 : 1.0 + fp);
+        }
+        w = term ? ((__popc((uint32_t)lane) & 1) ? w : -w) : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+        H = readlane_f64(w, 0);
+      }
+    } else {
+      // this lane's candidate: subtree [lo, lo + len) and what it needs to be
+      // excited there: 1 always (a stored router), 2 address bit cbit set,
+      // 3 memory bit cbit fetched
+      uint32_t lo = 0, len = 0, cond = 0, cbit = 0;
+      if (lane < nc && tk != NONE) {
+        lo = idx << (n - l);
+        len = 1u << (n - l);
+        if (tk < (uint32_t)n) {
+          cond = (x & 1u) ? 2u : 1u;
+          cbit = (uint32_t)(n - 1) - tk;
+        } else {
+          cbit = tk - (uint32_t)n;
+          cond = ((tb->dmask[s] >> cbit) & 1u) ? 3u : 0u;
+        }
+      }
+      const uint64_t hb = __ballot(cond != 0u);
+      const int m = __popcll(hb);
+      if (m > WALK_MAXC) return s;
+      if (m > 0) {
+        // subtrees to sum over: those inside no other one (equal ones: the first)
+        bool inner = false;
+        for (uint64_t r = hb; r; r &= r - 1) {
+          const int src = __ffsll((unsigned long long)r) - 1;
+          const uint32_t lo2 = (uint32_t)__builtin_amdgcn_readlane((int)lo, src);
+          const uint32_t len2 = (uint32_t)__builtin_amdgcn_readlane((int)len, src);
+          if (src != lane && lo >= lo2 && lo + len <= lo2 + len2 && (len < len2 || lo != lo2 || src < lane))
+            inner = true;
+        }
+        const uint64_t eb = __ballot(cond != 0u && !inner);
+        uint32_t tot = 0;
+        for (uint64_t r = eb; r; r &= r - 1)
+          tot += (uint32_t)__builtin_amdgcn_readlane((int)len, __ffsll((unsigned long long)r) - 1);
+        if (tot > (uint32_t)WALK_MAXA) return s;
+        const double wr = tb->ftab_w[(size_t)(s - 1) * tb->nfs + F_D + (1 << k)];  // router factor
+        double h = 0.0;
+        for (uint64_t r = eb; r; r &= r - 1) {
+          const int src = __ffsll((unsigned long long)r) - 1;
+          const uint32_t lo2 = (uint32_t)__builtin_amdgcn_readlane((int)lo, src);
+          const uint32_t len2 = (uint32_t)__builtin_amdgcn_readlane((int)len, src);
+          for (uint32_t o = (uint32_t)lane; o < len2; o += 64) {
+            const uint32_t a = lo2 + o;
+            const uint32_t memw = tb->mem[a];
+            bool hit = false;
+            for (uint64_t r2 = hb; r2; r2 &= r2 - 1) {
+              const int c = __ffsll((unsigned long long)r2) - 1;
+              const uint32_t clo = (uint32_t)__builtin_amdgcn_readlane((int)lo, c);
+              const uint32_t clen = (uint32_t)__builtin_amdgcn_readlane((int)len, c);
+              const uint32_t cc = (uint32_t)__builtin_amdgcn_readlane((int)cond, c);
+              const uint32_t cbt = (uint32_t)__builtin_amdgcn_readlane((int)cbit, c);
+              const bool ok = cc == 1u || (cc == 2u && ((a >> cbt) & 1u)) || (cc == 3u && ((memw >> cbt) & 1u));
+              hit |= (a - clo) < clen && ok;
+            }
+            if (!hit) continue;
+            double w = wr;
+            for (int p = 0; p < n; ++p) {
+              const double fp = readlane_f64(f, p);
+              if ((a >> p) & 1u) w *= fp;
+            }
+            const uint32_t dv = memw & kmask;
+            for (int c = 0; c < k; ++c) {
+              const double gc = readlane_f64(f, n + c);
+              if ((dv >> c) & 1u) w *= gc;
+            }
+            h += w;
+          }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) h += __shfl_xor(h, off, 64);
+        H = readlane_f64(h, 0);
+      }
+    }
+    if (H > 0.0) {
+      const double u = rp->forced ? rp->uaux[s] : uniform53(rp->seed, (uint32_t)s, 0, traj, 2u);
+      const double wall = tb->ctot[s - 1];
+      if (!(u * wall < wall - H)) return s;
+    }
+    s = sm.nxt[s + 1];
+  }
+  return T;
+}
+
+// ---------------------------------------------------------------------------
 // the kernel
 // ---------------------------------------------------------------------------
 template <int ENC, bool SL>
@@ -732,11 +932,12 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
   const double *__restrict__ wpow = tb->wpow + emax;
   const double *__restrict__ apow = tb->apow + emax;
   const uint32_t *__restrict__ mem = tb->mem;
-  Sm sm = carve(smem, M, D, nthr, rp->cdec_all ? rp->cand_cap : (uint32_t)NCS);
+  Sm sm = carve(smem, M, D, nthr, rp->cdec_all ? rp->cand_cap : (uint32_t)NCS,
+                walk_table_bytes(T, n, tb->k));
   uint32_t *st = SL ? sm.st : rp->gstate + (size_t)blockIdx.x * rp->e_cap;
   const int rec = tb->rec;
   uint16_t *pool = rp->pool + (size_t)blockIdx.x * rp->pool_slots * rec;
-  uint16_t *devl = rp->devl + (size_t)blockIdx.x * rp->pool_slots;
+  uint32_t *devl = rp->devl + (size_t)blockIdx.x * rp->pool_slots;
   const bool pruned = rp->mode == 1;
   const uint32_t ccap = rp->cand_cap;
   const uint32_t apt = rp->apt;
@@ -748,6 +949,13 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
   load_lost(tb, wpow, sm.fw);
   load_lost(tb, apow, sm.fa);
   for (int w = tid; w < (M + 31) / 32; w += nthr) sm.cbm[w] = 0u;
+  {  // exposure counts of the walk, address bit p = token n-1-p
+    const int nb = n + tb->k;
+    for (int i = tid; i < T * nb; i += nthr) {
+      const int sl = i / nb, j = i - sl * nb;
+      sm.wc[i] = (uint8_t)(j < n ? tb->cntA[sl][n - 1 - j] : tb->cntD[sl][j - n]);
+    }
+  }
 
   QR_TINIT
   const uint32_t seg0 = rp->bucket_base[bkt];
@@ -815,6 +1023,17 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
         s = sm.nxt[s];
         if (s >= T) break;
       }
+      if (njumps == 0) {
+        // before the first jump, wave 0 decides the draws from the initial
+        // labels and stops at the first slice the block has to evolve
+        if (tid < 64) {
+          const int sw = nojump_walk<ENC>(tb, rp, sm, cand, pre, s, traj);
+          if (tid == 0) sm.misc[3] = sw;
+        }
+        __syncthreads();
+        s = sm.misc[3];
+        if (s >= T) break;
+      }
       const uint32_t cb = sm.cstart[s];
       const int nc = (int)(sm.cstart[s + 1] - cb);
       if (nc == 0 && ndev == 0) continue;
@@ -852,19 +1071,25 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
 
       // tier-2 pass: the listed components follow the gates of slice s
       // literally, spread over all threads of the block
+      // (each thread's next entry is fetched one iteration ahead)
+      uint32_t dnext = tid < ndev ? devl[tid] : 0u;
       for (uint32_t i = tid; i < ndev; i += nthr) {
-        const uint32_t c = devl[i];
+        const uint32_t d = dnext;
+        if (i + nthr < ndev) dnext = devl[i + nthr];
+        const uint32_t c = d & 0xFFFFu, a = d >> 16;
         const uint32_t g = c >> kb, b = c & (uint32_t)(K2 - 1);
         const uint32_t ow = g / apt, al = g - ow * apt;
         const uint32_t widx = (al * K2 + b) * nthr + ow;
-        const uint32_t a = xl ? xl[g] : g;
         uint32_t w = st[widx];
         const uint32_t cnt0 = (w & W_CNT) >> W_CNT_SH;
         const uint32_t e = (w & W_E) + cnt0;  // exposure through slice s-1
         bool hit;
+        uint32_t bus;
         const uint32_t cnt = t2_step<ENC>(tb, s, pool + (size_t)c * rec, cnt0, a, w, slow_all, big, nc,
-                                          cd, sm.cbm, hit, rp->err);
-        st[widx] = (w & (W_SIGN | W_ALIVE | W_DEV)) | e | (cnt << W_CNT_SH) | (hit ? W_HIT : 0u);
+                                          cd, sm.cbm, hit, bus, rp->err);
+        // after the last slice a ground list keeps its bus word in the count field
+        const uint32_t cf = (s == T - 1 && cnt == 0) ? (W_FBUS | (bus << W_CNT_SH)) : (cnt << W_CNT_SH);
+        st[widx] = (w & (W_SIGN | W_ALIVE | W_DEV)) | e | cf | (hit ? W_HIT : 0u);
       }
       QR_TM(7);
       if (nc == 0) continue;
@@ -1125,47 +1350,52 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
                   if (3 * n + 2 * bb + 1 > s) future |= 1u << bb;
                 if (__popc(live & mem[a] & future) & 1) sign ^= W_SIGN;
               }
-              Rec<ENC> R{recp};
-              R.r[0] = 0;
-              uint32_t bus = 0;
+              // the record: every excited site but J's (lost), written once
+              uint32_t cnt = 0, bus = 0;
+              bool ovf = false;
+              auto put = [&](uint32_t raw) {
+                for (int c = 0; c < nJ; ++c) {
+                  const uint32_t xj = sm.Jb[c], qj = xj & 0xFFFFu;
+                  if (raw == ((ENC == QUTRIT && (xj >> 16) == 2u) ? (qj | LV_R_BIT) : qj)) return;
+                }
+                if (cnt < (uint32_t)tb->lmax)
+                  recp[2 + cnt++] = (uint16_t)raw;
+                else
+                  ovf = true;
+              };
               for (int t = 0; t < n; ++t) {
                 const bool abit = (a >> (n - 1 - t)) & 1u;
                 const int q = t1_site(tb, s, a, t);
                 if (q < 0) continue;
-                if (ENC == QUTRIT && (q & 1) == 0) {
-                  if (!R.add((uint32_t)q | (abit ? LV_R_BIT : 0u), tb->lmax)) atomicOr(rp->err, ERR_LIST);
-                } else if (abit) {
-                  if (!R.add((uint32_t)q, tb->lmax)) atomicOr(rp->err, ERR_LIST);
-                }
+                if (ENC == QUTRIT && (q & 1) == 0)
+                  put((uint32_t)q | (abit ? LV_R_BIT : 0u));
+                else if (abit)
+                  put((uint32_t)q);
               }
               for (int bb = 0; bb < tb->k; ++bb) {
                 const int q = t1_site(tb, s, a, n + bb);
                 if (ENC == QUBIT) {
                   const bool lb = (live >> bb) & 1u;
                   if (q >= 0) {
-                    if (lb && !R.add((uint32_t)q, tb->lmax)) atomicOr(rp->err, ERR_LIST);
+                    if (lb) put((uint32_t)q);
                   } else if (lb) {
                     bus |= 1u << bb;  // not yet in, or already back on the bus
                   }
                 } else {
                   const bool vb = ((memw & live) >> bb) & 1u;
                   if (q >= 0) {
-                    if (((tb->dmask[s] >> bb) & 1u) && vb && !R.add((uint32_t)q, tb->lmax))
-                      atomicOr(rp->err, ERR_LIST);
+                    if (((tb->dmask[s] >> bb) & 1u) && vb) put((uint32_t)q);
                   } else if (s >= 4 * n + 2 * bb + 1 && vb) {
                     bus |= 1u << bb;  // fetched value already on the bus
                   }
                 }
               }
-              R.r[1] = (uint16_t)bus;
-              for (int c = 0; c < nJ; ++c) {
-                const uint32_t x = sm.Jb[c], q = x & 0xFFFFu;
-                const uint32_t raw = (ENC == QUTRIT && (x >> 16) == 2u) ? (q | LV_R_BIT) : q;
-                const int jj = R.find_raw(raw);
-                if (jj >= 0) R.remove(jj);
-              }
-              const uint32_t cnt = (uint32_t)R.cnt();
-              w = (W_ALIVE | W_DEV | sign) | (e - cnt) | (cnt << W_CNT_SH);
+              if (ovf) atomicOr(rp->err, ERR_LIST);
+              recp[0] = (uint16_t)cnt;
+              recp[1] = (uint16_t)bus;
+              // after the last slice a ground list keeps its bus word in the count field
+              const uint32_t cf = (s == T - 1 && cnt == 0) ? (W_FBUS | (bus << W_CNT_SH)) : (cnt << W_CNT_SH);
+              w = (W_ALIVE | W_DEV | sign) | (e - cnt) | cf;
             } else {
               uint32_t ek = w & W_EK;
               uint32_t sign = w & W_SIGN;
@@ -1197,7 +1427,8 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
               continue;
             }
             const uint32_t cnt = ((w & W_CNT) >> W_CNT_SH) - (uint32_t)nJ;
-            w = (w & (W_SIGN | W_ALIVE | W_DEV | W_E)) | (cnt << W_CNT_SH);
+            const uint32_t cf = (s == T - 1 && cnt == 0) ? (W_FBUS | ((uint32_t)R.r[1] << W_CNT_SH)) : (cnt << W_CNT_SH);
+            w = (w & (W_SIGN | W_ALIVE | W_DEV | W_E)) | cf;
           }
           st[j * nthr + tid] = w;
           if (w & W_DEV) {
@@ -1213,9 +1444,16 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
       {
         uint32_t tot;
         uint32_t pos = block_excl_scan_u32(mydev, reinterpret_cast<uint32_t *>(sm.scanb), &tot);
+        int cur = -1;
+        uint32_t a = 0;
         for (uint64_t m = devm; m; m &= m - 1) {
           const uint32_t j = (uint32_t)__ffsll((unsigned long long)m) - 1u;
-          devl[pos++] = (uint16_t)((tid * apt + (j >> kb)) * K2 + (j & (uint32_t)(K2 - 1)));
+          const uint32_t g = tid * apt + (j >> kb);
+          if ((int)(j >> kb) != cur) {
+            cur = (int)(j >> kb);
+            a = xl ? xl[g] : g;
+          }
+          devl[pos++] = (g * K2 + (j & (uint32_t)(K2 - 1))) | (a << 16);
         }
         ndev = tot;
         __syncthreads();
@@ -1295,12 +1533,13 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
           ground = true;
           bus = dv;
         } else {
-          const uint32_t cnt = (w & W_CNT) >> W_CNT_SH;
+          const bool fb = (w & W_FBUS) != 0u;
+          const uint32_t cnt = fb ? 0u : (w & W_CNT) >> W_CNT_SH;
           const uint32_t e = (w & W_E) + cnt;
           wt = wpow[e];
           at = apow[e];
           ground = cnt == 0;
-          bus = pool[(size_t)(g * K2 + b) * rec + 1];
+          bus = fb ? (w & W_CNT) >> W_CNT_SH : (ground ? pool[(size_t)(g * K2 + b) * rec + 1] : 0u);
         }
         fin[2] += wt;
         if (!ground) continue;
@@ -1369,8 +1608,8 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
 }  // namespace
 
 uint32_t evolve_lds_bytes(int M, int D, int threads, uint32_t cdec_cap,
-                          uint32_t e_cap, bool state_lds) {
-  return fixed_bytes(M, D, threads, cdec_cap) + (state_lds ? e_cap * 4u : 0u);
+                          uint32_t e_cap, bool state_lds, uint32_t walk_bytes) {
+  return fixed_bytes(M, D, threads, cdec_cap, walk_bytes) + (state_lds ? e_cap * 4u : 0u);
 }
 
 int evolve_occupancy(int enc, bool state_lds, int threads, uint32_t lds_bytes) {

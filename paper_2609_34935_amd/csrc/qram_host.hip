@@ -63,7 +63,8 @@ struct qram_ctx {
   uint32_t *nexpl = nullptr, *order = nullptr, *counter = nullptr, *errw = nullptr;
   uint32_t *bucket_base = nullptr;
   uint64_t *badbits = nullptr, *digest = nullptr;
-  uint16_t *xlist = nullptr, *pool = nullptr, *devl = nullptr;
+  uint16_t *xlist = nullptr, *pool = nullptr;
+  uint32_t *devl = nullptr;
   uint32_t *gstate = nullptr;
   double *fid_tmp = nullptr, *uaux = nullptr;
   qram_traj_stats *st_tmp = nullptr;
@@ -334,9 +335,10 @@ qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
     b.threads = (int)thr;
     b.apt = apt;
     b.e_cap = apt * (uint32_t)c->K2 * thr;
-    const uint32_t fixed = evolve_lds_bytes(c->M, c->D, b.threads, pl.cdec_cap, 0, false);
+    const uint32_t wb = walk_table_bytes(c->T, c->n, c->k);
+    const uint32_t fixed = evolve_lds_bytes(c->M, c->D, b.threads, pl.cdec_cap, 0, false, wb);
     b.state_lds = !state_global && fixed + b.e_cap * 4u <= std::min<size_t>(c->lds_max, 96u * 1024u);
-    b.lds = evolve_lds_bytes(c->M, c->D, b.threads, pl.cdec_cap, b.e_cap, b.state_lds);
+    b.lds = evolve_lds_bytes(c->M, c->D, b.threads, pl.cdec_cap, b.e_cap, b.state_lds, wb);
     if (b.lds > c->lds_max) return fail(c, QRAM_E_RANGE, "workgroup shared memory exceeds the device limit");
     int occ = evolve_occupancy(c->enc, b.state_lds, b.threads, b.lds);
     if (occ < 1) occ = 1;
@@ -406,7 +408,7 @@ size_t buffers_bytes(const qram_ctx *c, uint32_t nb, const Plan &pl) {
     ps = std::max(ps, (size_t)pl.b[i].grid * pl.pool_slots * c->rec);
     ds = std::max(ds, (size_t)pl.b[i].grid * pl.pool_slots);
   }
-  return b + ps * 2 + ds * 2;
+  return b + ps * 2 + ds * 4;
 }
 
 size_t table_bytes(const qram_ctx *c) {

@@ -28,7 +28,9 @@ constexpr int QUBIT = 1;
 //               data bits not yet lost)
 // Tier 2 (explicit site list in the pool):
 //   bits  0..15 exposure through the previous slice
-//   bits 16..23 excited sites now (the record's count)
+//   bits 16..23 excited sites now (the record's count); after the last
+//               slice, with bit 27 set, the bus word of a ground list
+//   bit  27     ground after the last slice, bits 16..23 hold the bus word
 //   bit  28     a candidate of this slice sits on one of its sites
 // Both: bit 24 sign, bit 25 alive, bit 26 tier 2.
 constexpr uint32_t W_EK = 0xFFu;
@@ -39,6 +41,7 @@ constexpr uint32_t W_CNT = 0xFFu << W_CNT_SH;
 constexpr uint32_t W_SIGN = 1u << 24;
 constexpr uint32_t W_ALIVE = 1u << 25;
 constexpr uint32_t W_DEV = 1u << 26;
+constexpr uint32_t W_FBUS = 1u << 27;
 constexpr uint32_t W_HIT = 1u << 28;
 
 // Tier-2 record in the pool (uint16 words): [0] count, [1] bus word,
@@ -100,7 +103,7 @@ struct Run {
   uint32_t *counter;     // [MAXB] queue heads
   uint32_t *gstate;      // [grid * e_cap] tier-1 words when not in LDS
   uint16_t *pool;        // [grid * pool_slots * rec] tier-2 records
-  uint16_t *devl;        // [grid * pool_slots] tier-2 work list
+  uint32_t *devl;        // [grid * pool_slots] tier-2 work list: component | address << 16
   double *fid;           // [ntraj]
   qram_traj_stats *st;   // [ntraj] or null
   uint32_t *err;         // [1] error bits
@@ -123,7 +126,12 @@ hipError_t launch_evolve(const Tables *tb, const Run &rp, int enc,
 hipError_t launch_digest(const Run &rp, uint32_t ntraj, hipStream_t s);
 
 uint32_t evolve_lds_bytes(int M, int D, int threads, uint32_t cdec_cap,
-                          uint32_t e_cap, bool state_lds);
+                          uint32_t e_cap, bool state_lds, uint32_t walk_bytes);
+// Shared memory of the no-jump walk's exposure-count table: one byte per
+// slice and token.
+__host__ __device__ inline uint32_t walk_table_bytes(int T, int n, int k) {
+  return (uint32_t)(T * (n + k));
+}
 int evolve_occupancy(int enc, bool state_lds, int threads, uint32_t lds_bytes);
 hipError_t evolve_prepare(int lds_max, int *dyn_max);
 
