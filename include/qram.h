@@ -176,8 +176,10 @@ qram_status qram_get_launch(const qram_ctx *ctx, qram_mode mode,
 /*
  * Options (value 0/1; both default to 0).
  *   QRAM_OPT_TIER2_GLOBAL: keep every explicit site list of a component whose
- *     routing a jump changed in global memory instead of registers (same
- *     results; for testing the two list paths against each other).
+ *     routing a jump changed in global memory instead of registers, one list
+ *     per component (the qubit encoding otherwise shares one list among the
+ *     bus words of an address).  Same results; for testing the list paths
+ *     against each other.
  *   QRAM_OPT_GRAPH: run each batch (sampling, classification, bucketing and
  *     every bucket's persistent evolution launch) as one HIP graph.  The
  *     graph is captured on the context's stream, instantiated once and then

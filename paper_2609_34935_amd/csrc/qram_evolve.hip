@@ -13,9 +13,10 @@
 //           (a lost data token).  Its exposure, sign and weight follow from
 //           prefix tables of the schedule.
 //   tier 2: a jump removed an address token or a router.  The component
-//           carries an explicit site list in a per-workgroup pool and follows
-//           the gates literally; lists up to REG_CAP - 6 entries are processed
-//           in registers, longer ones in global memory.
+//           follows the gates literally on an explicit site list in a
+//           per-workgroup pool (qubit: one list per address, shared by its
+//           bus words); short lists are processed in registers, longer ones
+//           in global memory.
 // Amplitudes are c_i * sign * gamma^{|J|/2} * a^e.  gamma^{|J|/2} is the same
 // for every survivor and cancels in every ratio, so a draw uses the weights
 // (1-gamma)^e.  Per slice the kernel tests the slice's candidates against
@@ -621,6 +622,231 @@ __device__ __forceinline__ uint32_t t2_step(const Tables *__restrict__ tb,
   return cnt;
 }
 
+// Qubit tier 2, shared lists.  Routers and address tokens do not depend on
+// the bus word, so the bus words of one address follow the same gates on
+// the same routing as long as no gate acts on a data token in a way that
+// depends on which bus words carry it.  Such an address keeps one list for
+// all its bus words: the address entries (routers, address tokens in
+// transit, residues) as an ordinary list, and the site of each data token
+// its surviving components may still carry, tagged by the token.  Record:
+// [0] address entries, [1] bus mask of those tokens | the tokens << 8,
+// [2 ..] address entries, [2 + lmax + t] site of data token t (EMPTY: on the
+// bus or lost).  Bus word b carries the tokens b & tokens.  It lives in the
+// record slot of the address's bus word 0.  When a gate would treat bus words
+// differently (a data token about to be stored into a router, copied over,
+// or swapped onto the bus out of turn) the address splits into one ordinary
+// list per component (state bit W_SPLIT) before that slice's gates.
+constexpr int QK = 6;  // data tokens of the qubit encoding at most
+
+struct TokPos {
+  uint32_t p[QK / 2];  // two 16-bit sites per register
+  __device__ __forceinline__ uint32_t get(int t) const { return (p[t >> 1] >> ((t & 1) * 16)) & 0xFFFFu; }
+  __device__ __forceinline__ void set(int t, uint32_t x) {
+    const int sh = (t & 1) * 16;
+    p[t >> 1] = (p[t >> 1] & ~(0xFFFFu << sh)) | (x << sh);
+  }
+  __device__ __forceinline__ void load(const uint16_t *r, int k) {
+#pragma unroll
+    for (int t = 0; t < QK; t += 2) {
+      const uint32_t lo = t < k ? (uint32_t)r[t] : EMPTY;
+      const uint32_t hi = t + 1 < k ? (uint32_t)r[t + 1] : EMPTY;
+      p[t >> 1] = lo | (hi << 16);
+    }
+  }
+  __device__ __forceinline__ void store(uint16_t *r, int k) const {
+#pragma unroll
+    for (int t = 0; t < QK; ++t)
+      if (t < k) r[t] = (uint16_t)get(t);
+  }
+  // data token at site q, or -1
+  __device__ __forceinline__ int at(uint32_t q) const {
+    int r = -1;
+#pragma unroll
+    for (int t = 0; t < QK; ++t)
+      if (get(t) == q) r = t;
+    return r;
+  }
+};
+
+// Gates of slice s (same order and rules as t2_gates_reg) on a shared list.
+// Returns false as soon as a gate would act differently on bus words that
+// carry different tokens; the caller then discards the registers.
+template <int C>
+__device__ __forceinline__ bool t2_gates_shared(const Tables *__restrict__ tb, int s,
+                                                RList<QUBIT, C> &L, TokPos &tp, uint32_t a,
+                                                uint32_t &busm, bool &flip_all,
+                                                uint32_t &flip_tok, bool &moved, bool &ovf) {
+  const int n = tb->n;
+  const int ct = tb->copy_t[s];
+  if (ct >= 0 && ((a >> (n - 1 - ct)) & 1u)) {
+    if (tp.at(1) >= 0) return false;
+    L.toggle(1, ovf);
+  }
+  const int sl = tb->store_l[s];
+  if (sl >= 0) {
+#pragma unroll
+    for (int t = 0; t < QK; ++t) {
+      const uint32_t x = tp.get(t);
+      if (x != EMPTY && layer_of(x >> 1) == sl) return false;
+    }
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const uint32_t x = L.get(j);
+      if (x != EMPTY && layer_of(x >> 1) == sl) L.set(j, x ^ 1u);
+    }
+  }
+  const uint32_t cm = tb->cswap[s];
+  if (cm) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const uint32_t x = L.get(j);
+      if (x == EMPTY || !(x & 1u)) continue;
+      const uint32_t v = x >> 1;
+      const int l = layer_of(v);
+      if ((cm >> l) & 1u) {
+        L.set(j, 2 * (2 * v + 1 + (uint32_t)L.dir(v)) + 1);
+      } else if (l >= 1 && ((cm >> (l - 1)) & 1u)) {
+        const uint32_t p = (v - 1) >> 1;
+        if (v == 2 * p + 1 + (uint32_t)L.dir(p)) L.set(j, 2 * p + 1);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < QK; ++t) {
+      const uint32_t x = tp.get(t);
+      if (x == EMPTY) continue;
+      const uint32_t v = x >> 1;
+      const int l = layer_of(v);
+      if ((cm >> l) & 1u) {
+        tp.set(t, 2 * (2 * v + 1 + (uint32_t)L.dir(v)) + 1);
+        moved = true;
+      } else if (l >= 1 && ((cm >> (l - 1)) & 1u)) {
+        const uint32_t p = (v - 1) >> 1;
+        if (v == 2 * p + 1 + (uint32_t)L.dir(p)) {
+          tp.set(t, 2 * p + 1);
+          moved = true;
+        }
+      }
+    }
+  }
+  const int bb = tb->bus_b[s];
+  if (bb >= 0) {
+    const int t1 = tp.at(1);
+    if (L.has(1) || (t1 >= 0 && t1 != bb)) return false;
+    if (t1 == bb) {
+      tp.set(bb, EMPTY);
+      busm |= 1u << bb;
+      moved = true;
+    } else if ((busm >> bb) & 1u) {
+      tp.set(bb, 1);
+      busm &= ~(1u << bb);
+      moved = true;
+    }
+  }
+  const int fb = tb->fetch_b[s];
+  if (fb >= 0) {
+    const uint32_t v0 = (1u << (n - 1)) - 1u;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const uint32_t x = L.get(j);
+      if (x == EMPTY || !(x & 1u) || (x >> 1) < v0) continue;
+      const uint32_t v = x >> 1;
+      if ((tb->mem[2 * (v - v0) + (uint32_t)L.dir(v)] >> fb) & 1u) flip_all = !flip_all;
+    }
+#pragma unroll
+    for (int t = 0; t < QK; ++t) {
+      const uint32_t x = tp.get(t);
+      if (x == EMPTY || (x >> 1) < v0) continue;
+      const uint32_t v = x >> 1;
+      if ((tb->mem[2 * (v - v0) + (uint32_t)L.dir(v)] >> fb) & 1u) flip_tok ^= 1u << t;
+    }
+  }
+  return true;
+}
+
+// One slice on a shared list held in registers (C entries).  Returns false,
+// with nothing written, when the address has to split first.
+template <int C>
+__device__ __forceinline__ bool t2_shared_reg(const Tables *__restrict__ tb, int s, uint16_t *recp,
+                                              uint32_t cnt0, uint32_t a, bool big, int nc,
+                                              const uint32_t *cdec, const uint32_t *cbm,
+                                              uint32_t &cnt, uint32_t &busf, bool &flip_all,
+                                              uint32_t &flip_tok, bool &hit_all, uint32_t &hit_tok,
+                                              uint32_t *err) {
+  const int k = tb->k;
+  RList<QUBIT, C> L;
+  L.load(recp, cnt0);
+  TokPos tp;
+  tp.load(recp + 2 + tb->lmax, k);
+  uint32_t busm = L.bus & 0xFFu;
+  bool moved = false, ovf = false;
+  if (!t2_gates_shared<C>(tb, s, L, tp, a, busm, flip_all, flip_tok, moved, ovf)) return false;
+  if (ovf) atomicOr(err, ERR_LIST);
+  if (busm != (L.bus & 0xFFu)) {
+    L.bus = (L.bus & 0xFF00u) | busm;
+    L.dirty = true;
+  }
+  if (nc > 0) {
+    if (big) {
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const uint32_t x = L.get(j);
+        if (x != EMPTY && cand_bm(cbm, x)) hit_all = true;
+      }
+#pragma unroll
+      for (int t = 0; t < QK; ++t) {
+        const uint32_t x = tp.get(t);
+        if (x != EMPTY && cand_bm(cbm, x)) hit_tok |= 1u << t;
+      }
+    } else {
+      for (int c = 0; c < nc; ++c) {
+        const uint32_t q = cdec[c] & 0xFFFFu;
+        if (L.has(q)) hit_all = true;
+        const int t = tp.at(q);
+        if (t >= 0) hit_tok |= 1u << t;
+      }
+    }
+  }
+  cnt = L.dirty ? L.store(recp) : cnt0;
+  if (moved) tp.store(recp + 2 + tb->lmax, k);
+  busf = L.bus;
+  return true;
+}
+
+// Split a shared list (in memory, as after slice s-1) into one ordinary list
+// per live component of the address; returns nothing, marks the words.
+__device__ __forceinline__ void t2_split(const Tables *__restrict__ tb, uint16_t *pool, int rec,
+                                         uint32_t g, int K2, uint32_t *st, uint32_t wbase,
+                                         uint32_t nthr, uint32_t *err) {
+  const int k = tb->k, lmax = tb->lmax;
+  uint16_t *rs = pool + (size_t)g * K2 * rec;
+  const uint32_t cnt = rs[0], busf = rs[1], toks = (busf >> 8) & 0xFFu, busm = busf & 0xFFu;
+  TokPos tp;
+  tp.load(rs + 2 + lmax, k);
+  for (int pass = 0; pass < 2; ++pass) {  // the list's own slot (bus word 0) last
+    for (int b = pass ? 0 : 1; b < (pass ? 1 : K2); ++b) {
+      const uint32_t widx = wbase + (uint32_t)b * nthr;
+      const uint32_t w = st[widx];
+      if (!(w & W_ALIVE)) continue;
+      uint16_t *rb = pool + ((size_t)g * K2 + b) * rec;
+      if (b != 0)
+        for (uint32_t j = 0; j < cnt; ++j) rb[2 + j] = rs[2 + j];
+      const uint32_t live = (uint32_t)b & toks;
+      uint32_t m = cnt;
+      for (int t = 0; t < k; ++t) {
+        const uint32_t x = tp.get(t);
+        if (!((live >> t) & 1u) || x == EMPTY) continue;
+        if (m < (uint32_t)lmax)
+          rb[2 + m++] = (uint16_t)x;
+        else
+          atomicOr(err, ERR_LIST);
+      }
+      rb[0] = (uint16_t)m;
+      rb[1] = (uint16_t)(live & busm);
+      st[widx] = w | W_SPLIT;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // shared memory layout
 // ---------------------------------------------------------------------------
@@ -949,6 +1175,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
   load_lost(tb, wpow, sm.fw);
   load_lost(tb, apow, sm.fa);
   for (int w = tid; w < (M + 31) / 32; w += nthr) sm.cbm[w] = 0u;
+  if (tid == 0) sm.misc[4] = 0;
   {  // exposure counts of the walk, address bit p = token n-1-p
     const int nb = n + tb->k;
     for (int i = tid; i < T * nb; i += nthr) {
@@ -1018,6 +1245,35 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
     uint32_t ndev = 0;  // tier-2 components of the block (listed in devl)
     int njumps = 0, first_jump = 0;
 
+    // qubit: rebuild the tier-2 work list, one entry per shared address and
+    // one per component of a split one, in slot order
+    auto devl_qubit = [&]() {
+      uint32_t cnt = 0;
+      for (uint32_t al = 0; al < apt; ++al) {
+        const uint64_t gm = (devm >> (al * K2)) & kfull;
+        if (!gm) continue;
+        const uint32_t jf = al * K2 + (uint32_t)__ffsll((unsigned long long)gm) - 1u;
+        cnt += (st[jf * nthr + tid] & W_SPLIT) ? (uint32_t)__popcll(gm) : 1u;
+      }
+      uint32_t tot;
+      uint32_t pos = block_excl_scan_u32(cnt, reinterpret_cast<uint32_t *>(sm.scanb), &tot);
+      for (uint32_t al = 0; al < apt; ++al) {
+        const uint64_t gm = (devm >> (al * K2)) & kfull;
+        if (!gm) continue;
+        const uint32_t g = tid * apt + al;
+        const uint32_t a = xl ? (uint32_t)xl[g] : g;
+        const uint32_t jf = al * K2 + (uint32_t)__ffsll((unsigned long long)gm) - 1u;
+        if (st[jf * nthr + tid] & W_SPLIT) {
+          for (uint64_t m = gm; m; m &= m - 1)
+            devl[pos++] = (g * K2 + (uint32_t)__ffsll((unsigned long long)m) - 1u) | (a << 16);
+        } else {
+          devl[pos++] = (g * K2) | (a << 16) | 0x80000000u;
+        }
+      }
+      ndev = tot;
+      __syncthreads();
+    };
+
     for (int s = 1; s < T; ++s) {
       if (ndev == 0) {  // without tier-2 components only slices with candidates matter
         s = sm.nxt[s];
@@ -1069,27 +1325,74 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
       }
       QR_TM(1);
 
-      // tier-2 pass: the listed components follow the gates of slice s
-      // literally, spread over all threads of the block
+      // tier-2 pass: the listed components (qubit: addresses) follow the
+      // gates of slice s literally, spread over all threads of the block
       // (each thread's next entry is fetched one iteration ahead)
       uint32_t dnext = tid < ndev ? devl[tid] : 0u;
       for (uint32_t i = tid; i < ndev; i += nthr) {
         const uint32_t d = dnext;
         if (i + nthr < ndev) dnext = devl[i + nthr];
-        const uint32_t c = d & 0xFFFFu, a = d >> 16;
-        const uint32_t g = c >> kb, b = c & (uint32_t)(K2 - 1);
-        const uint32_t ow = g / apt, al = g - ow * apt;
-        const uint32_t widx = (al * K2 + b) * nthr + ow;
-        uint32_t w = st[widx];
-        const uint32_t cnt0 = (w & W_CNT) >> W_CNT_SH;
-        const uint32_t e = (w & W_E) + cnt0;  // exposure through slice s-1
-        bool hit;
-        uint32_t bus;
-        const uint32_t cnt = t2_step<ENC>(tb, s, pool + (size_t)c * rec, cnt0, a, w, slow_all, big, nc,
-                                          cd, sm.cbm, hit, bus, rp->err);
-        // after the last slice a ground list keeps its bus word in the count field
-        const uint32_t cf = (s == T - 1 && cnt == 0) ? (W_FBUS | (bus << W_CNT_SH)) : (cnt << W_CNT_SH);
-        st[widx] = (w & (W_SIGN | W_ALIVE | W_DEV)) | e | cf | (hit ? W_HIT : 0u);
+        const uint32_t c0 = d & 0xFFFFu, a = (d >> 16) & 0x7FFFu;
+        uint32_t clast = c0;  // components stepped one by one: c0 .. clast
+        if (ENC == QUBIT && (d >> 31)) {
+          // a whole qubit address: shared list, or split into its components
+          const uint32_t g = c0 >> kb, ow = g / apt, al = g - ow * apt;
+          const uint32_t wbase = al * K2 * nthr + ow;
+          uint32_t w0 = 0;
+          for (int b = 0; b < K2 && !(w0 & W_ALIVE); ++b) w0 = st[wbase + (uint32_t)b * nthr];
+          if (!(w0 & W_SPLIT)) {
+            uint16_t *recp = pool + (size_t)c0 * rec;
+            const uint32_t cnt0 = recp[0];
+            uint32_t cnt = 0, busf = 0, ftok = 0, htok = 0;
+            bool fall = false, hall = false, ok = false;
+            if (!slow_all && cnt0 + 2 <= 16)  // (a longer shared list splits)
+              ok = t2_shared_reg<16>(tb, s, recp, cnt0, a, big, nc, cd, sm.cbm, cnt, busf, fall, ftok, hall, htok, rp->err);
+
+            if (ok) {
+              const uint32_t toks = (busf >> 8) & 0xFFu, busm = busf & 0xFFu, intree = toks & ~busm;
+              for (int b = 0; b < K2; ++b) {
+                const uint32_t widx = wbase + (uint32_t)b * nthr;
+                const uint32_t w = st[widx];
+                if (!(w & W_ALIVE)) continue;
+                const uint32_t live = (uint32_t)b & toks;
+                const uint32_t e = (w & W_E) + ((w & W_CNT) >> W_CNT_SH);  // exposure through slice s-1
+                const uint32_t cb = cnt + (uint32_t)__popc(live & intree);
+                const bool flip = fall ^ (bool)(__popc(ftok & live) & 1);
+                const bool hit = hall || (htok & live);
+                // after the last slice a ground component keeps its bus word in the count field
+                const uint32_t cf = (s == T - 1 && cb == 0) ? (W_FBUS | ((live & busm) << W_CNT_SH)) : (cb << W_CNT_SH);
+                st[widx] = ((w & W_SIGN) ^ (flip ? W_SIGN : 0u)) | (w & (W_ALIVE | W_DEV)) | e | cf | (hit ? W_HIT : 0u);
+              }
+              continue;
+            }
+            t2_split(tb, pool, rec, g, K2, st, wbase, nthr, rp->err);
+            sm.misc[4] = 1;  // the work list is rebuilt after the pass
+          }
+          clast = c0 + (uint32_t)K2 - 1u;
+        }
+        for (uint32_t c = c0; c <= clast; ++c) {
+          const uint32_t g = c >> kb, b = c & (uint32_t)(K2 - 1);
+          const uint32_t ow = g / apt, al = g - ow * apt;
+          const uint32_t widx = (al * K2 + b) * nthr + ow;
+          uint32_t w = st[widx];
+          if (!(w & W_ALIVE)) continue;
+          const uint32_t cnt0 = (w & W_CNT) >> W_CNT_SH;
+          const uint32_t e = (w & W_E) + cnt0;  // exposure through slice s-1
+          bool hit;
+          uint32_t bus;
+          const uint32_t cnt = t2_step<ENC>(tb, s, pool + (size_t)c * rec, cnt0, a, w, slow_all, big, nc,
+                                            cd, sm.cbm, hit, bus, rp->err);
+          // after the last slice a ground list keeps its bus word in the count field
+          const uint32_t cf = (s == T - 1 && cnt == 0) ? (W_FBUS | (bus << W_CNT_SH)) : (cnt << W_CNT_SH);
+          st[widx] = (w & (W_SIGN | W_ALIVE | W_DEV | W_SPLIT)) | e | cf | (hit ? W_HIT : 0u);
+        }
+      }
+      if (ENC == QUBIT && ndev > 0) {
+        __syncthreads();
+        if (sm.misc[4]) {  // an address split: spread its components over the block
+          devl_qubit();
+          if (tid == 0) sm.misc[4] = 0;
+        }
       }
       QR_TM(7);
       if (nc == 0) continue;
@@ -1288,6 +1591,19 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
               if (lev && nJ < JMAX) sm.Jb[nJ++] = (uint32_t)q | ((uint32_t)lev << 16);
             }
           }
+        } else if (ENC == QUBIT && !(w & W_SPLIT)) {
+          // a shared list: its address entries and the tokens x* carries
+          const uint16_t *rs = pool + (size_t)g * K2 * rec;
+          const uint32_t live = b & ((uint32_t)rs[1] >> 8);
+          for (uint32_t c = 0; c < (uint32_t)rs[0]; ++c) {
+            const uint32_t q = rs[2 + c];
+            if ((big ? cand_bm(sm.cbm, q) : cand_list(cd, nc, q)) && nJ < JMAX) sm.Jb[nJ++] = q | (1u << 16);
+          }
+          for (int t = 0; t < tb->k; ++t) {
+            const uint32_t q = rs[2 + tb->lmax + t];
+            if (!((live >> t) & 1u) || q == EMPTY) continue;
+            if ((big ? cand_bm(sm.cbm, q) : cand_list(cd, nc, q)) && nJ < JMAX) sm.Jb[nJ++] = q | (1u << 16);
+          }
         } else {
           Rec<ENC> R{pool + (size_t)(g * K2 + b) * rec};
           for (int c = 0; c < R.cnt(); ++c) {
@@ -1312,6 +1628,148 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
         if (g >= A) break;
         const uint32_t a = xl ? xl[g] : g;
         const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
+        if (ENC == QUBIT) {
+          const uint32_t base = al * K2;
+          const uint64_t am = (alive >> base) & kfull;
+          if (!am) continue;
+          const bool t2 = ((devm >> base) & kfull) != 0ull;
+          const uint32_t jf = base + (uint32_t)__ffsll((unsigned long long)am) - 1u;
+          if (t2 && !(st[jf * nthr + tid] & W_SPLIT)) {
+            // a shared list: J's sites must be on it, J's data tokens carried
+            uint16_t *rs = pool + (size_t)g * K2 * rec;
+            Rec<ENC> R{rs};
+            const int kk = tb->k, lmax = tb->lmax;
+            const uint32_t busf = rs[1], toks = (busf >> 8) & 0xFFu;
+            bool okA = true;
+            uint32_t need = 0;
+            for (int c = 0; c < nJ && okA; ++c) {
+              const uint32_t q = sm.Jb[c] & 0xFFFFu;
+              if (R.find_site(q) >= 0) continue;
+              int tq = -1;
+              for (int t = 0; t < kk; ++t)
+                if (((toks >> t) & 1u) && rs[2 + lmax + t] == q) tq = t;
+              if (tq < 0)
+                okA = false;
+              else
+                need |= 1u << tq;
+            }
+            uint64_t surv = 0;
+            if (okA)
+              for (uint64_t m = am; m; m &= m - 1) {
+                const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+                if (!(need & ~(b & toks))) surv |= 1ull << b;
+              }
+            if (surv) {
+              for (int c = 0; c < nJ; ++c) {
+                const int jj = R.find_site(sm.Jb[c] & 0xFFFFu);
+                if (jj >= 0) R.remove(jj);
+              }
+              for (int t = 0; t < kk; ++t)
+                if ((need >> t) & 1u) rs[2 + lmax + t] = (uint16_t)EMPTY;
+              rs[1] = (uint16_t)(busf & ~(need << 8));
+            }
+            const uint32_t toks2 = toks & ~need, busm = busf & 0xFFu;
+            for (uint64_t m = am; m; m &= m - 1) {
+              const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+              const uint32_t j = base + b;
+              if (!((surv >> b) & 1ull)) {
+                st[j * nthr + tid] = 0u;
+                alive &= ~(1ull << j);
+                devm &= ~(1ull << j);
+                continue;
+              }
+              const uint32_t w = st[j * nthr + tid];
+              const uint32_t cnt = ((w & W_CNT) >> W_CNT_SH) - (uint32_t)nJ;
+              const uint32_t cf = (s == T - 1 && cnt == 0) ? (W_FBUS | ((b & toks2 & busm) << W_CNT_SH)) : (cnt << W_CNT_SH);
+              st[j * nthr + tid] = (w & (W_SIGN | W_ALIVE | W_DEV | W_E)) | cf;
+            }
+            continue;
+          }
+          if (!t2) {
+            // tier 1: J's data tokens, and whether J holds an address token
+            // (then the survivors turn tier 2): the same for every bus word
+            bool devJ = false;
+            uint32_t kill = 0;
+            for (int c = 0; c < nJ; ++c) {
+              const uint32_t q = sm.Jb[c] & 0xFFFFu;
+              const uint32_t tk = tb->tok[s][layer_of(q >> 1)][q & 1u];
+              if (tk < (uint32_t)n || tk == NONE)
+                devJ = true;
+              else
+                kill |= 1u << (tk - (uint32_t)n);
+            }
+            if (devJ) {
+              uint64_t surv = 0;
+              uint32_t toks = 0;  // data tokens the survivors still carry
+              for (uint64_t m = am; m; m &= m - 1) {
+                const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+                const uint32_t w = njumps == 0 ? init_word<ENC>(mem[a], b, kmask) : st[(base + b) * nthr + tid];
+                const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
+                bool ok = true;
+                for (int c = 0; c < nJ && ok; ++c) {
+                  const uint32_t x = sm.Jb[c];
+                  ok = t1_level<ENC>(tb, s, a, live, 0u, x & 0xFFFFu) == (int)(x >> 16);
+                }
+                if (ok) {
+                  surv |= 1ull << b;
+                  toks |= live & ~kill;
+                }
+              }
+              uint32_t caddr = 0, busm = 0;
+              if (surv) {
+                // the address's shared list: every excited site but J's
+                // (lost), written once
+                uint16_t *rs = pool + (size_t)g * K2 * rec;
+                bool ovf = false;
+                for (int t = 0; t < n; ++t) {
+                  const int q = t1_site(tb, s, a, t);
+                  if (q < 0 || !((a >> (n - 1 - t)) & 1u)) continue;
+                  bool inJ = false;
+                  for (int c = 0; c < nJ; ++c) inJ |= (sm.Jb[c] & 0xFFFFu) == (uint32_t)q;
+                  if (inJ) continue;
+                  if (caddr < (uint32_t)tb->lmax)
+                    rs[2 + caddr++] = (uint16_t)q;
+                  else
+                    ovf = true;
+                }
+                for (int bb = 0; bb < tb->k; ++bb) {
+                  const int q = ((toks >> bb) & 1u) ? t1_site(tb, s, a, n + bb) : -1;
+                  if (((toks >> bb) & 1u) && q < 0) busm |= 1u << bb;  // not yet in, or already back on the bus
+                  rs[2 + tb->lmax + bb] = (uint16_t)(q >= 0 ? (uint32_t)q : EMPTY);
+                }
+                if (ovf) atomicOr(rp->err, ERR_LIST);
+                rs[0] = (uint16_t)caddr;
+                rs[1] = (uint16_t)(busm | (toks << 8));
+              }
+              const uint32_t intree = toks & ~busm;
+              uint32_t future = 0;  // fetch phases still ahead, picked up literally in tier 2
+              for (int bb = 0; bb < tb->k; ++bb)
+                if (3 * n + 2 * bb + 1 > s) future |= 1u << bb;
+              for (uint64_t m = am; m; m &= m - 1) {
+                const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+                const uint32_t j = base + b;
+                if (!((surv >> b) & 1ull)) {
+                  st[j * nthr + tid] = 0u;
+                  alive &= ~(1ull << j);
+                  devm &= ~(1ull << j);
+                  continue;
+                }
+                const uint32_t w = njumps == 0 ? init_word<ENC>(mem[a], b, kmask) : st[j * nthr + tid];
+                const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
+                // exposure through slice s (J's sites excluded)
+                const uint32_t e = t1_exposure<ENC>(tb, s, a, live, w & W_EK) - (uint32_t)nJ;
+                uint32_t sign = w & W_SIGN;
+                if (__popc(live & mem[a] & future) & 1) sign ^= W_SIGN;
+                const uint32_t cb = caddr + (uint32_t)__popc(b & toks & intree);
+                const uint32_t cf = (s == T - 1 && cb == 0) ? (W_FBUS | ((b & toks & busm) << W_CNT_SH)) : (cb << W_CNT_SH);
+                st[j * nthr + tid] = (W_ALIVE | W_DEV | sign) | (e - cb) | cf;
+                devm |= 1ull << j;
+              }
+              continue;
+            }
+          }
+          // a split tier-2 address, or no address token in J: one component at a time (below)
+        }
         for (int b = 0; b < K2; ++b) {
           const uint32_t j = al * K2 + b;
           uint32_t w = njumps == 0 ? init_word<ENC>(mem[a], (uint32_t)b, kmask) : st[j * nthr + tid];
@@ -1428,7 +1886,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
             }
             const uint32_t cnt = ((w & W_CNT) >> W_CNT_SH) - (uint32_t)nJ;
             const uint32_t cf = (s == T - 1 && cnt == 0) ? (W_FBUS | ((uint32_t)R.r[1] << W_CNT_SH)) : (cnt << W_CNT_SH);
-            w = (w & (W_SIGN | W_ALIVE | W_DEV | W_E)) | cf;
+            w = (w & (W_SIGN | W_ALIVE | W_DEV | W_SPLIT | W_E)) | cf;
           }
           st[j * nthr + tid] = w;
           if (w & W_DEV) {
@@ -1441,7 +1899,9 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
       ++njumps;
       if (!first_jump) first_jump = s;
       // rebuild the tier-2 work list in slot order
-      {
+      if (ENC == QUBIT) {
+        devl_qubit();
+      } else {
         uint32_t tot;
         uint32_t pos = block_excl_scan_u32(mydev, reinterpret_cast<uint32_t *>(sm.scanb), &tot);
         int cur = -1;
@@ -1539,7 +1999,16 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
           wt = wpow[e];
           at = apow[e];
           ground = cnt == 0;
-          bus = fb ? (w & W_CNT) >> W_CNT_SH : (ground ? pool[(size_t)(g * K2 + b) * rec + 1] : 0u);
+          if (fb) {
+            bus = (w & W_CNT) >> W_CNT_SH;
+          } else if (!ground) {
+            bus = 0u;
+          } else if (ENC == QUBIT && !(w & W_SPLIT)) {
+            const uint32_t bf = pool[(size_t)g * K2 * rec + 1];
+            bus = (uint32_t)b & (bf >> 8) & bf & 0xFFu;
+          } else {
+            bus = pool[(size_t)(g * K2 + b) * rec + 1];
+          }
         }
         fin[2] += wt;
         if (!ground) continue;

@@ -32,6 +32,8 @@ constexpr int QUBIT = 1;
 //               slice, with bit 27 set, the bus word of a ground list
 //   bit  27     ground after the last slice, bits 16..23 hold the bus word
 //   bit  28     a candidate of this slice sits on one of its sites
+//   bit  29     qubit: the address's components keep one list each (else
+//               the address's bus words share one list)
 // Both: bit 24 sign, bit 25 alive, bit 26 tier 2.
 constexpr uint32_t W_EK = 0xFFu;
 constexpr int W_LIVE_SH = 8;
@@ -43,6 +45,7 @@ constexpr uint32_t W_ALIVE = 1u << 25;
 constexpr uint32_t W_DEV = 1u << 26;
 constexpr uint32_t W_FBUS = 1u << 27;
 constexpr uint32_t W_HIT = 1u << 28;
+constexpr uint32_t W_SPLIT = 1u << 29;  // qubit tier 2: the address keeps one list per component
 
 // Tier-2 record in the pool (uint16 words): [0] count, [1] bus word,
 // [2..] excited sites.  Qutrit router sites carry their level in bit 15

@@ -321,3 +321,36 @@ def test_graph_async_streams(lib):
             ctx.run_pruned_async(42, 0, 1000, d_f, None, stream=stream)
             torch.cuda.synchronize()
             assert np.array_equal(d_f.cpu().numpy(), ref_f)
+
+
+# ---------------------------------------------------------------------------
+# qubit tier 2: lists shared by an address's bus words, and their splits
+# ---------------------------------------------------------------------------
+def test_qubit_shared_lists_match_component_lists(lib):
+    """Shared per-address lists (default) against one global-memory list per
+    component: bitwise equal fidelities and statistics, many jumps during
+    the data phase included."""
+    n, k, gamma, nt = 6, 4, 1e-2, 3000
+    mem = memory_words(n, k, 606)
+    res = []
+    for glob in (0, 1):
+        with lib.QramContext(n, k, QUBIT, gamma, mem) as ctx:
+            ctx.set_option(lib.qram.QRAM_OPT_TIER2_GLOBAL, glob)
+            res.append([fn(4242, 0, nt) for fn in (ctx.run_full, ctx.run_pruned)])
+    for (fa, sa), (fb, sb) in zip(res[0], res[1]):
+        assert np.array_equal(fa, fb)
+        assert np.array_equal(sa, sb)
+    js = res[0][0][1]["first_jump_slice"]
+    assert np.sum((js > 2 * n) & (js < 4 * n + 2 * k)) > 100
+
+
+@pytest.mark.parametrize("s,site", [(12, 0), (14, 0), (13, 2), (15, 4), (16, 2), (17, 0)])
+def test_forced_router_jump_with_data_in_tree_qubit(lib, orc, s, site):
+    """A router jump while data tokens are below it: the tokens routed
+    through it get stuck, so the bus words of an address stop sharing their
+    routing (shared lists split)."""
+    n, k = 4, 2
+    T, M = 6 * n + 2 * k, 2 * (2**n - 1)
+    mem = memory_words(n, k, 7)
+    L = [(s - 1) * M + site]
+    forced_case(lib, orc, n, k, QUBIT, 0.05, mem, L, np.full(T, 0.99999), 0.5)
