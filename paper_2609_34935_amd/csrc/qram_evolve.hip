@@ -953,15 +953,8 @@ __device__ __forceinline__ double fA(const double *f, uint32_t a) {
 // ---------------------------------------------------------------------------
 // qubit: slices before the first jump, one wave
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double readlane_f64(double x, int l) {
-  const uint64_t b = (uint64_t)__double_as_longlong(x);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-constexpr int WALK_MAXC = 6;     // token candidates per slice the walk combines
-constexpr int WALK_MAXA = 2048;  // qutrit: addresses per slice the walk sums over
+constexpr int WALK_MAXC = 6;   // token candidates per slice the walk combines
+constexpr int WALK_MAXA = 64;  // qutrit: addresses per slice the walk sums over
 
 // Until the first jump every component keeps its initial label: address a
 // and bus word b (qubit) or the fetched data bits (qutrit).  A candidate on
@@ -972,24 +965,189 @@ constexpr int WALK_MAXA = 2048;  // qutrit: addresses per slice the walk sums ov
 // the weights of the hit components over every address equals the sum over
 // the explicit ones, and with the slice's closed-form total it decides the
 // slice's draw (Eq. maskweight) as the block does, without a pass over the
-// components.
+// components.  The draws of different slices are independent until the
+// first jump, so each thread of the block takes one slice.
 //   qubit: the weight before the layer of slice s factorises over the
 //     tokens, the product of f_p = (1-gamma)^e over the set address bits p
 //     and of g_c over the set bus bits c (e: that token's exposure through
 //     slice s-1).  An intersection of hit sets fixes some address and bus
 //     bits, so its weight is a product, and the weight of the union follows
-//     by inclusion-exclusion with one subset of candidates per lane.
-//   qutrit: the data factor depends on the memory word, so the lanes sum the
-//     weights of the hit addresses over the union of the candidates'
+//     by inclusion-exclusion over the slice's token candidates.
+//   qutrit: the data factor depends on the memory word, so the thread sums
+//     the weights of the hit addresses over the union of the candidates'
 //     subtrees (nested subtrees taken once).
 //
-// Called by the 64 lanes of wave 0 at a slice s holding candidates; returns
-// the first slice from s on that the block must evolve: a slice whose draw
-// picks a nonempty J, one with too many candidates or addresses to sum, or T.
+// Does slice s need the block: does its draw pick a nonempty J, or has it
+// more candidates (or, qutrit, addresses to sum) than one thread combines?
+template <int ENC>
+__device__ __forceinline__ bool nojump_stop(const Tables *__restrict__ tb, const Run *rp,
+                                            const Sm &sm, const uint32_t *__restrict__ cand,
+                                            bool pre, int s, uint32_t traj) {
+  const int n = tb->n, k = tb->k, nb = n + k;
+  const uint32_t cb = sm.cstart[s];
+  const int nc = (int)(sm.cstart[s + 1] - cb);
+  if (nc == 0) return false;
+  if (nc > NCS) return true;
+  // the slice's token candidates, decoded: site | layer << 16 | token << 20
+  uint32_t cq[WALK_MAXC];
+  int m = 0;
+  for (int c = 0; c < nc; ++c) {
+    uint32_t x;
+    if (pre) {
+      x = sm.cdec[cb + c];
+    } else {
+      const uint32_t q = cand[cb + c] - (uint32_t)(s - 1) * (uint32_t)tb->M;
+      const int l = layer_of(q >> 1);
+      x = q | ((uint32_t)l << 16) | ((uint32_t)tb->tok[s][l][q & 1u] << 20);
+    }
+    if (((x >> 20) & 0xFFu) == NONE) continue;
+    if (m == WALK_MAXC) return true;
+#pragma unroll
+    for (int i = 0; i < WALK_MAXC; ++i)
+      if (i == m) cq[i] = x;
+    ++m;
+  }
+  if (m == 0) return false;
+  const uint8_t *wc = sm.wc + (s - 1) * nb;  // exposure of each token through slice s-1
+  double H = 0.0;
+  if (ENC == QUBIT) {
+    for (uint32_t S = 1; S < (1u << m); ++S) {
+      // the subset S: address bits forced to 1 / to 0, bus bits forced to 1
+      uint32_t a1 = 0, a0 = 0, b1 = 0;
+#pragma unroll
+      for (int i = 0; i < WALK_MAXC; ++i) {
+        if (!((S >> i) & 1u)) continue;
+        const uint32_t x = cq[i], tk = (x >> 20) & 0xFFu;
+        const int l = (int)((x >> 16) & 15u);
+        const uint32_t idx = ((x & 0xFFFFu) >> 1) + 1u - (1u << l);
+        const uint32_t one = idx << (n - l);
+        a1 |= one;
+        a0 |= (((1u << l) - 1u) << (n - l)) & ~one;
+        if (tk < (uint32_t)n)
+          a1 |= 1u << (n - 1 - (int)tk);
+        else
+          b1 |= 1u << (tk - (uint32_t)n);
+      }
+      if (a1 & a0) continue;
+      double w = 1.0;
+      for (int p = 0; p < nb; ++p) {
+        const double f = sm.fw[F_K + wc[p]];
+        const bool one = p < n ? ((a1 >> p) & 1u) : ((b1 >> (p - n)) & 1u);
+        const bool zero = p < n && ((a0 >> p) & 1u);
+        w *= one ? f : (zero ? 1.0 : 1.0 + f);
+      }
+      H += (__popc(S) & 1) ? w : -w;
+    }
+  } else {
+    // each hit-capable candidate: subtree [lo, lo + len) and what it needs
+    // there: 1 nothing (a stored router), 2 address bit cbit set, 3 memory
+    // bit cbit fetched
+    uint32_t lo[WALK_MAXC], len[WALK_MAXC], cond[WALK_MAXC], cbit[WALK_MAXC];
+#pragma unroll
+    for (int i = 0; i < WALK_MAXC; ++i) {
+      lo[i] = len[i] = cond[i] = cbit[i] = 0;
+      if (i >= m) continue;
+      const uint32_t x = cq[i], tk = (x >> 20) & 0xFFu;
+      const int l = (int)((x >> 16) & 15u);
+      lo[i] = (((x & 0xFFFFu) >> 1) + 1u - (1u << l)) << (n - l);
+      len[i] = 1u << (n - l);
+      if (tk < (uint32_t)n) {
+        cond[i] = (x & 1u) ? 2u : 1u;
+        cbit[i] = (uint32_t)(n - 1) - tk;
+      } else {
+        cbit[i] = tk - (uint32_t)n;
+        cond[i] = ((tb->dmask[s] >> cbit[i]) & 1u) ? 3u : 0u;
+      }
+    }
+    // subtrees to sum over: inside no other one (equal ones: the first)
+    uint32_t outer = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < WALK_MAXC; ++i) {
+      if (!cond[i]) continue;
+      bool inner = false;
+#pragma unroll
+      for (int j = 0; j < WALK_MAXC; ++j)
+        if (j != i && cond[j] && lo[i] >= lo[j] && lo[i] + len[i] <= lo[j] + len[j] &&
+            (len[i] < len[j] || lo[i] != lo[j] || j < i))
+          inner = true;
+      if (!inner) {
+        outer |= 1u << i;
+        tot += len[i];
+      }
+    }
+    if (tot > (uint32_t)WALK_MAXA) return true;
+    if (outer) {
+      const uint32_t kmask = (1u << k) - 1u;
+      const double wr = tb->ftab_w[(size_t)(s - 1) * tb->nfs + F_D + (1 << k)];  // router factor
+#pragma unroll
+      for (int e = 0; e < WALK_MAXC; ++e) {
+        if (!((outer >> e) & 1u)) continue;
+        for (uint32_t a = lo[e]; a < lo[e] + len[e]; ++a) {
+          const uint32_t memw = tb->mem[a];
+          bool hit = false;
+#pragma unroll
+          for (int c = 0; c < WALK_MAXC; ++c) {
+            const bool ok = cond[c] == 1u || (cond[c] == 2u && ((a >> cbit[c]) & 1u)) ||
+                            (cond[c] == 3u && ((memw >> cbit[c]) & 1u));
+            hit |= cond[c] && (a - lo[c]) < len[c] && ok;
+          }
+          if (!hit) continue;
+          double w = wr;
+          for (int p = 0; p < n; ++p)
+            if ((a >> p) & 1u) w *= sm.fw[F_K + wc[p]];
+          const uint32_t dv = memw & kmask;
+          for (int c = 0; c < k; ++c)
+            if ((dv >> c) & 1u) w *= sm.fw[F_K + wc[n + c]];
+          H += w;
+        }
+      }
+    }
+  }
+  if (!(H > 0.0)) return false;
+  const double u = rp->forced ? rp->uaux[s] : uniform53(rp->seed, (uint32_t)s, 0, traj, 2u);
+  const double wall = tb->ctot[s - 1];
+  return !(u * wall < wall - H);
+}
+
+// The first slice from s0 on that the block must evolve (T: none), every
+// slice decided by one thread.  Called by every thread of the block.
 template <int ENC>
 __device__ __forceinline__ int nojump_walk(const Tables *__restrict__ tb, const Run *rp,
                                            const Sm &sm, const uint32_t *__restrict__ cand,
-                                           bool pre, int s, uint32_t traj) {
+                                           bool pre, int s0, uint32_t traj) {
+  const int T = tb->T;
+  const int nw = (int)(blockDim.x >> 6), wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  int *wmin = reinterpret_cast<int *>(sm.scanb);
+  for (int base = s0; base < T; base += (int)blockDim.x) {
+    const int s = base + (int)threadIdx.x;
+    const bool stop = s < T && nojump_stop<ENC>(tb, rp, sm, cand, pre, s, traj);
+    const uint64_t bal = __ballot(stop);
+    if (lane == 0) wmin[wave] = bal ? base + (wave << 6) + (__ffsll((unsigned long long)bal) - 1) : T;
+    __syncthreads();
+    int r = T;
+    for (int w = 0; w < nw; ++w) r = min(r, wmin[w]);
+    if (r < T) return r;
+    __syncthreads();
+  }
+  return T;
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+constexpr int WAVE_MAXA = 2048;  // addresses per slice the wave sums over
+
+// Qutrit, the same walk with the 64 lanes of wave 0 on one slice at a time
+// (qutrit workgroups are small, and the lanes share a slice's subtrees):
+// returns the first slice from s on that the block must evolve, or T.
+template <int ENC>
+__device__ __forceinline__ int nojump_walk_wave(const Tables *__restrict__ tb, const Run *rp,
+                                                const Sm &sm, const uint32_t *__restrict__ cand,
+                                                bool pre, int s, uint32_t traj) {
   const int n = tb->n, k = tb->k, T = tb->T, nb = n + k;
   const uint32_t M = (uint32_t)tb->M;
   const uint32_t kmask = (1u << k) - 1u;
@@ -1015,51 +1173,7 @@ __device__ __forceinline__ int nojump_walk(const Tables *__restrict__ tb, const 
     double f = 1.0;
     if (lane < nb) f = sm.fw[F_K + sm.wc[(s - 1) * nb + lane]];
     double H = 0.0;
-    if (ENC == QUBIT) {
-      const bool tokc = lane < nc && tk != NONE;
-      const uint64_t bal = __ballot(tokc);
-      const int m = __popcll(bal);
-      if (m > WALK_MAXC) return s;
-      if (m > 0) {
-        // this lane's candidate: address bits forced to 1 / to 0, bus bits forced to 1
-        uint32_t A1 = 0, A0 = 0, B1 = 0;
-        if (tokc) {
-          A1 = idx << (n - l);
-          A0 = (((1u << l) - 1u) << (n - l)) & ~A1;
-          if (tk < (uint32_t)n)
-            A1 |= 1u << (n - 1 - (int)tk);
-          else
-            B1 = 1u << (tk - (uint32_t)n);
-        }
-        // subset `lane` of the token candidates (bit i: the i-th of them)
-        uint32_t a1 = 0, a0 = 0, b1 = 0;
-        uint64_t rest = bal;
-        for (int i = 0; i < m; ++i) {
-          const int src = __ffsll((unsigned long long)rest) - 1;
-          rest &= rest - 1;
-          const uint32_t y1 = (uint32_t)__builtin_amdgcn_readlane((int)A1, src);
-          const uint32_t y0 = (uint32_t)__builtin_amdgcn_readlane((int)A0, src);
-          const uint32_t z1 = (uint32_t)__builtin_amdgcn_readlane((int)B1, src);
-          if ((lane >> i) & 1) {
-            a1 |= y1;
-            a0 |= y0;
-            b1 |= z1;
-          }
-        }
-        const bool term = lane >= 1 && lane < (1 << m) && !(a1 & a0);
-        double w = 1.0;
-        for (int p = 0; p < nb; ++p) {
-          const double fp = readlane_f64(f, p);
-          const bool one = p < n ? ((a1 >> p) & 1u) : ((b1 >> (p - n)) & 1u);
-          const bool zero = p < n && ((a0 >> p) & 1u);
-          w *= one ? fp : (zero ? 1.0 : 1.0 + fp);
-        }
-        w = term ? ((__popc((uint32_t)lane) & 1) ? w : -w) : 0.0;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
-        H = readlane_f64(w, 0);
-      }
-    } else {
+    {
       // this lane's candidate: subtree [lo, lo + len) and what it needs to be
       // excited there: 1 always (a stored router), 2 address bit cbit set,
       // 3 memory bit cbit fetched
@@ -1092,7 +1206,7 @@ __device__ __forceinline__ int nojump_walk(const Tables *__restrict__ tb, const 
         uint32_t tot = 0;
         for (uint64_t r = eb; r; r &= r - 1)
           tot += (uint32_t)__builtin_amdgcn_readlane((int)len, __ffsll((unsigned long long)r) - 1);
-        if (tot > (uint32_t)WALK_MAXA) return s;
+        if (tot > (uint32_t)WAVE_MAXA) return s;
         const double wr = tb->ftab_w[(size_t)(s - 1) * tb->nfs + F_D + (1 << k)];  // router factor
         double h = 0.0;
         for (uint64_t r = eb; r; r &= r - 1) {
@@ -1280,14 +1394,18 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
         if (s >= T) break;
       }
       if (njumps == 0) {
-        // before the first jump, wave 0 decides the draws from the initial
-        // labels and stops at the first slice the block has to evolve
-        if (tid < 64) {
-          const int sw = nojump_walk<ENC>(tb, rp, sm, cand, pre, s, traj);
-          if (tid == 0) sm.misc[3] = sw;
+        // before the first jump the draws follow from the initial labels:
+        // go straight to the first slice the block has to evolve
+        if (ENC == QUBIT) {
+          s = nojump_walk<ENC>(tb, rp, sm, cand, pre, s, traj);
+        } else {
+          if (tid < 64) {
+            const int sw = nojump_walk_wave<ENC>(tb, rp, sm, cand, pre, s, traj);
+            if (tid == 0) sm.misc[3] = sw;
+          }
+          __syncthreads();
+          s = sm.misc[3];
         }
-        __syncthreads();
-        s = sm.misc[3];
         if (s >= T) break;
       }
       const uint32_t cb = sm.cstart[s];
