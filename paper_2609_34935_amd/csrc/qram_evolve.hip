@@ -625,17 +625,21 @@ __device__ __forceinline__ uint32_t t2_step(const Tables *__restrict__ tb,
 // Qubit tier 2, shared lists.  Routers and address tokens do not depend on
 // the bus word, so the bus words of one address follow the same gates on
 // the same routing as long as no gate acts on a data token in a way that
-// depends on which bus words carry it.  Such an address keeps one list for
-// all its bus words: the address entries (routers, address tokens in
-// transit, residues) as an ordinary list, and the site of each data token
-// its surviving components may still carry, tagged by the token.  Record:
-// [0] address entries, [1] bus mask of those tokens | the tokens << 8,
-// [2 ..] address entries, [2 + lmax + t] site of data token t (EMPTY: on the
-// bus or lost).  Bus word b carries the tokens b & tokens.  It lives in the
-// record slot of the address's bus word 0.  When a gate would treat bus words
-// differently (a data token about to be stored into a router, copied over,
-// or swapped onto the bus out of turn) the address splits into one ordinary
-// list per component (state bit W_SPLIT) before that slice's gates.
+// depends on which bus words carry it.  Such bus words keep one list: the
+// address entries (routers, address tokens in transit, residues) as an
+// ordinary list, and the site of each data token they may carry, tagged by
+// the token.  Record: [0] address entries, [1] bus mask | tagged tokens << 8,
+// [2 ..] address entries, [2 + lmax + t] site of tagged token t (EMPTY: on
+// the bus or lost), [2 + lmax + k] the split set D.  Bus word b carries the
+// tagged tokens b & tokens.
+// A store that would move a tagged token into a router makes the bus words
+// that carry it route differently from those that do not, so before such a
+// store every class splits on the tokens concerned: the bus words of an
+// address fall into classes c (a subset of D) of the b with b & D = c, each
+// with its own list in the record slot of bus word c; in class c the tokens
+// of D are untagged, entries of the list when c holds them, gone otherwise.
+// Any other gate that would treat a class's bus words differently (rare)
+// turns the class into one ordinary list per component (state bit W_SPLIT).
 constexpr int QK = 6;  // data tokens of the qubit encoding at most
 
 struct TokPos {
@@ -674,7 +678,7 @@ struct TokPos {
 template <int C>
 __device__ __forceinline__ bool t2_gates_shared(const Tables *__restrict__ tb, int s,
                                                 RList<QUBIT, C> &L, TokPos &tp, uint32_t a,
-                                                uint32_t &busm, bool &flip_all,
+                                                uint32_t toks, uint32_t &busm, bool &flip_all,
                                                 uint32_t &flip_tok, bool &moved, bool &ovf) {
   const int n = tb->n;
   const int ct = tb->copy_t[s];
@@ -731,15 +735,27 @@ __device__ __forceinline__ bool t2_gates_shared(const Tables *__restrict__ tb, i
   const int bb = tb->bus_b[s];
   if (bb >= 0) {
     const int t1 = tp.at(1);
-    if (L.has(1) || (t1 >= 0 && t1 != bb)) return false;
-    if (t1 == bb) {
-      tp.set(bb, EMPTY);
-      busm |= 1u << bb;
-      moved = true;
-    } else if ((busm >> bb) & 1u) {
-      tp.set(bb, 1);
-      busm &= ~(1u << bb);
-      moved = true;
+    if ((toks >> bb) & 1u) {  // the bus qubit's own token is tagged
+      if (L.has(1) || (t1 >= 0 && t1 != bb)) return false;
+      if (t1 == bb) {
+        tp.set(bb, EMPTY);
+        busm |= 1u << bb;
+        moved = true;
+      } else if ((busm >> bb) & 1u) {
+        tp.set(bb, 1);
+        busm &= ~(1u << bb);
+        moved = true;
+      }
+    } else {  // untagged: the bus qubit is the same in every bus word of the list
+      if (t1 >= 0) return false;
+      const bool d0 = L.has(1), bbit = (busm >> bb) & 1u;
+      if (d0 && !bbit) {
+        L.remove_site(1);
+        busm |= 1u << bb;
+      } else if (!d0 && bbit) {
+        ovf |= !L.add(1);
+        busm &= ~(1u << bb);
+      }
     }
   }
   const int fb = tb->fetch_b[s];
@@ -779,7 +795,8 @@ __device__ __forceinline__ bool t2_shared_reg(const Tables *__restrict__ tb, int
   tp.load(recp + 2 + tb->lmax, k);
   uint32_t busm = L.bus & 0xFFu;
   bool moved = false, ovf = false;
-  if (!t2_gates_shared<C>(tb, s, L, tp, a, busm, flip_all, flip_tok, moved, ovf)) return false;
+  if (!t2_gates_shared<C>(tb, s, L, tp, a, (L.bus >> 8) & 0xFFu, busm, flip_all, flip_tok, moved, ovf))
+    return false;
   if (ovf) atomicOr(err, ERR_LIST);
   if (busm != (L.bus & 0xFFu)) {
     L.bus = (L.bus & 0xFF00u) | busm;
@@ -812,37 +829,97 @@ __device__ __forceinline__ bool t2_shared_reg(const Tables *__restrict__ tb, int
   return true;
 }
 
-// Split a shared list (in memory, as after slice s-1) into one ordinary list
-// per live component of the address; returns nothing, marks the words.
-__device__ __forceinline__ void t2_split(const Tables *__restrict__ tb, uint16_t *pool, int rec,
-                                         uint32_t g, int K2, uint32_t *st, uint32_t wbase,
-                                         uint32_t nthr, uint32_t *err) {
+// Classes (subsets of D) that hold members: bit c set.
+__device__ __forceinline__ uint64_t class_mask(uint64_t members, uint32_t D) {
+  uint64_t cl = 0;
+  for (uint64_t m = members; m; m &= m - 1) cl |= 1ull << ((uint32_t)(__ffsll((unsigned long long)m) - 1) & D);
+  return cl;
+}
+
+// Tagged tokens that the store of slice s would move into a router, over
+// the classes cl of the address whose class-0 record is r0.
+__device__ __forceinline__ uint32_t class_store_tokens(const Tables *__restrict__ tb, int s,
+                                                       const uint16_t *r0, int rec, uint64_t cl) {
+  const int sl = tb->store_l[s], k = tb->k, lmax = tb->lmax;
+  uint32_t X = 0;
+  for (uint64_t m = cl; m; m &= m - 1) {
+    const uint16_t *rc = r0 + (size_t)(__ffsll((unsigned long long)m) - 1) * rec;
+    const uint32_t toks = ((uint32_t)rc[1] >> 8) & 0xFFu;
+    for (int t = 0; t < k; ++t) {
+      const uint32_t x = rc[2 + lmax + t];
+      if (((toks >> t) & 1u) && x != EMPTY && layer_of(x >> 1) == sl) X |= 1u << t;
+    }
+  }
+  return X;
+}
+
+// Split every class cl of the address (split set D) on the tagged tokens X:
+// class c gives c | y for every nonempty y within X (the tokens of y untagged
+// and kept, those of X \ y dropped) and keeps c (the tokens of X dropped).
+// The new split set D | X is written to the class-0 slot.
+__device__ __forceinline__ void t2_class_split(const Tables *__restrict__ tb, uint16_t *r0, int rec,
+                                               uint64_t cl, uint32_t D, uint32_t X, uint32_t *err) {
   const int k = tb->k, lmax = tb->lmax;
-  uint16_t *rs = pool + (size_t)g * K2 * rec;
+  for (uint64_t m = cl; m; m &= m - 1) {
+    const uint32_t c = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+    uint16_t *rc = r0 + (size_t)c * rec;
+    const uint32_t cnt = rc[0], busf = rc[1], toks = (busf >> 8) & 0xFFu, busm = busf & 0xFFu;
+    for (uint32_t y = X; y; y = (y - 1) & X) {
+      uint16_t *rn = r0 + (size_t)(c | y) * rec;
+      uint32_t m2 = cnt;
+      for (uint32_t j = 0; j < cnt; ++j) rn[2 + j] = rc[2 + j];
+      for (int t = 0; t < k; ++t) {
+        const uint32_t x = rc[2 + lmax + t];
+        if (((y & toks) >> t) & 1u && x != EMPTY) {  // kept: an ordinary entry now
+          if (m2 < (uint32_t)lmax)
+            rn[2 + m2++] = (uint16_t)x;
+          else
+            atomicOr(err, ERR_LIST);
+        }
+        rn[2 + lmax + t] = ((X >> t) & 1u) ? (uint16_t)EMPTY : (uint16_t)x;
+      }
+      rn[0] = (uint16_t)m2;
+      rn[1] = (uint16_t)((busm & ~(X & ~y)) | ((toks & ~X) << 8));
+      rn[2 + lmax + k] = (uint16_t)(D | X);
+    }
+    for (int t = 0; t < k; ++t)
+      if ((X >> t) & 1u) rc[2 + lmax + t] = (uint16_t)EMPTY;
+    rc[1] = (uint16_t)((busm & ~X) | ((toks & ~X) << 8));
+    rc[2 + lmax + k] = (uint16_t)(D | X);
+  }
+  r0[2 + lmax + k] = (uint16_t)(D | X);
+}
+
+// Turn the members mc of class c (split set D) into one ordinary list per
+// component, from the class's list as after slice s-1; marks their words.
+__device__ __forceinline__ void t2_split_class(const Tables *__restrict__ tb, uint16_t *r0, int rec,
+                                               uint32_t c, uint64_t mc, uint32_t *st, uint32_t wbase,
+                                               uint32_t nthr, uint32_t *err) {
+  const int k = tb->k, lmax = tb->lmax;
+  uint16_t *rs = r0 + (size_t)c * rec;
   const uint32_t cnt = rs[0], busf = rs[1], toks = (busf >> 8) & 0xFFu, busm = busf & 0xFFu;
   TokPos tp;
   tp.load(rs + 2 + lmax, k);
-  for (int pass = 0; pass < 2; ++pass) {  // the list's own slot (bus word 0) last
-    for (int b = pass ? 0 : 1; b < (pass ? 1 : K2); ++b) {
-      const uint32_t widx = wbase + (uint32_t)b * nthr;
-      const uint32_t w = st[widx];
-      if (!(w & W_ALIVE)) continue;
-      uint16_t *rb = pool + ((size_t)g * K2 + b) * rec;
-      if (b != 0)
+  for (int pass = 0; pass < 2; ++pass) {  // the class's own slot (bus word c) last
+    for (uint64_t m = mc; m; m &= m - 1) {
+      const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+      if ((b == c) != (pass == 1)) continue;
+      uint16_t *rb = r0 + (size_t)b * rec;
+      if (b != c)
         for (uint32_t j = 0; j < cnt; ++j) rb[2 + j] = rs[2 + j];
-      const uint32_t live = (uint32_t)b & toks;
-      uint32_t m = cnt;
+      const uint32_t live = b & toks;
+      uint32_t m2 = cnt;
       for (int t = 0; t < k; ++t) {
         const uint32_t x = tp.get(t);
         if (!((live >> t) & 1u) || x == EMPTY) continue;
-        if (m < (uint32_t)lmax)
-          rb[2 + m++] = (uint16_t)x;
+        if (m2 < (uint32_t)lmax)
+          rb[2 + m2++] = (uint16_t)x;
         else
           atomicOr(err, ERR_LIST);
       }
-      rb[0] = (uint16_t)m;
-      rb[1] = (uint16_t)(live & busm);
-      st[widx] = w | W_SPLIT;
+      rb[0] = (uint16_t)m2;
+      rb[1] = (uint16_t)(busm & (~toks | b));
+      st[wbase + b * nthr] |= W_SPLIT;
     }
   }
 }
@@ -1289,7 +1366,6 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
   load_lost(tb, wpow, sm.fw);
   load_lost(tb, apow, sm.fa);
   for (int w = tid; w < (M + 31) / 32; w += nthr) sm.cbm[w] = 0u;
-  if (tid == 0) sm.misc[4] = 0;
   {  // exposure counts of the walk, address bit p = token n-1-p
     const int nb = n + tb->k;
     for (int i = tid; i < T * nb; i += nthr) {
@@ -1343,6 +1419,10 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
     if (pruned)
       for (int w = tid; w < (D + 31) / 32; w += nthr)
         sm.badl[w] = (uint32_t)(badg[w >> 1] >> (32 * (w & 1)));
+    if (tid == 0) {  // work-list rebuild requests: tagged with their slice
+      sm.misc[4] = 0;
+      sm.misc[5] = 0;
+    }
     // initial components: data-loading input after the first wall; the sign
     // already holds every fetch phase its live tokens will pick up
     // initial components: data-loading input after the first wall.  Their
@@ -1359,15 +1439,24 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
     uint32_t ndev = 0;  // tier-2 components of the block (listed in devl)
     int njumps = 0, first_jump = 0;
 
-    // qubit: rebuild the tier-2 work list, one entry per shared address and
-    // one per component of a split one, in slot order
+    // qubit: rebuild the tier-2 work list, one entry per class of an
+    // address's shared lists and one per component with a list of its own
     auto devl_qubit = [&]() {
       uint32_t cnt = 0;
+      const int lmax = tb->lmax, kk = tb->k;
       for (uint32_t al = 0; al < apt; ++al) {
-        const uint64_t gm = (devm >> (al * K2)) & kfull;
-        if (!gm) continue;
-        const uint32_t jf = al * K2 + (uint32_t)__ffsll((unsigned long long)gm) - 1u;
-        cnt += (st[jf * nthr + tid] & W_SPLIT) ? (uint32_t)__popcll(gm) : 1u;
+        uint64_t cm = 0;
+        for (uint64_t m = (devm >> (al * K2)) & kfull; m; m &= m - 1) {
+          const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+          if (st[(al * K2 + b) * nthr + tid] & W_SPLIT)
+            ++cnt;
+          else
+            cm |= 1ull << b;
+        }
+        if (cm) {
+          const uint32_t g = tid * apt + al;
+          cnt += (uint32_t)__popcll(class_mask(cm, pool[((size_t)g * K2) * rec + 2 + lmax + kk]));
+        }
       }
       uint32_t tot;
       uint32_t pos = block_excl_scan_u32(cnt, reinterpret_cast<uint32_t *>(sm.scanb), &tot);
@@ -1376,13 +1465,17 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
         if (!gm) continue;
         const uint32_t g = tid * apt + al;
         const uint32_t a = xl ? (uint32_t)xl[g] : g;
-        const uint32_t jf = al * K2 + (uint32_t)__ffsll((unsigned long long)gm) - 1u;
-        if (st[jf * nthr + tid] & W_SPLIT) {
-          for (uint64_t m = gm; m; m &= m - 1)
-            devl[pos++] = (g * K2 + (uint32_t)__ffsll((unsigned long long)m) - 1u) | (a << 16);
-        } else {
-          devl[pos++] = (g * K2) | (a << 16) | 0x80000000u;
+        uint64_t cm = 0;
+        for (uint64_t m = gm; m; m &= m - 1) {
+          const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+          if (st[(al * K2 + b) * nthr + tid] & W_SPLIT)
+            devl[pos++] = (g * K2 + b) | (a << 16);
+          else
+            cm |= 1ull << b;
         }
+        if (cm)  // one entry per class of the shared lists
+          for (uint64_t mm = class_mask(cm, pool[((size_t)g * K2) * rec + 2 + lmax + kk]); mm; mm &= mm - 1)
+            devl[pos++] = (g * K2 + (uint32_t)__ffsll((unsigned long long)mm) - 1u) | (a << 16) | 0x80000000u;
       }
       ndev = tot;
       __syncthreads();
@@ -1446,49 +1539,84 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
       // tier-2 pass: the listed components (qubit: addresses) follow the
       // gates of slice s literally, spread over all threads of the block
       // (each thread's next entry is fetched one iteration ahead)
+      if (ENC == QUBIT && ndev > 0 && tb->store_l[s] >= 0 && !slow_all) {
+        // before a store: the classes that would store a tagged token into a
+        // router split on it (each address's first class does it for all)
+        for (uint32_t i = tid; i < ndev; i += nthr) {
+          const uint32_t d = devl[i];
+          if (!(d >> 31)) continue;
+          const uint32_t cg = d & 0xFFFFu, g = cg >> kb, c = cg & (uint32_t)(K2 - 1);
+          const uint32_t ow = g / apt, al = g - ow * apt, wbase = al * K2 * nthr + ow;
+          uint16_t *r0 = pool + (size_t)g * K2 * rec;
+          const uint32_t D = r0[2 + tb->lmax + tb->k];
+          uint64_t cm = 0;
+          for (int b = 0; b < K2; ++b) {
+            const uint32_t w = st[wbase + (uint32_t)b * nthr];
+            if ((w & W_ALIVE) && !(w & W_SPLIT)) cm |= 1ull << b;
+          }
+          const uint64_t cl = class_mask(cm, D);
+          if (!cl || c != (uint32_t)__ffsll((unsigned long long)cl) - 1u) continue;
+          const uint32_t X = class_store_tokens(tb, s, r0, rec, cl);
+          if (X) {
+            t2_class_split(tb, r0, rec, cl, D, X, rp->err);
+            sm.misc[5] = s;  // the work list is rebuilt before the pass
+          }
+        }
+        __syncthreads();
+        if (sm.misc[5] == s) devl_qubit();
+      }
       uint32_t dnext = tid < ndev ? devl[tid] : 0u;
       for (uint32_t i = tid; i < ndev; i += nthr) {
         const uint32_t d = dnext;
         if (i + nthr < ndev) dnext = devl[i + nthr];
         const uint32_t c0 = d & 0xFFFFu, a = (d >> 16) & 0x7FFFu;
-        uint32_t clast = c0;  // components stepped one by one: c0 .. clast
+        uint64_t stepm = 1;  // components c0 + i stepped one by one
         if (ENC == QUBIT && (d >> 31)) {
-          // a whole qubit address: shared list, or split into its components
-          const uint32_t g = c0 >> kb, ow = g / apt, al = g - ow * apt;
+          // one class of a qubit address's shared lists: the bus words b
+          // with b & D = c
+          const uint32_t g = c0 >> kb, c = c0 & (uint32_t)(K2 - 1);
+          const uint32_t ow = g / apt, al = g - ow * apt;
           const uint32_t wbase = al * K2 * nthr + ow;
-          uint32_t w0 = 0;
-          for (int b = 0; b < K2 && !(w0 & W_ALIVE); ++b) w0 = st[wbase + (uint32_t)b * nthr];
-          if (!(w0 & W_SPLIT)) {
-            uint16_t *recp = pool + (size_t)c0 * rec;
+          uint16_t *r0 = pool + (size_t)g * K2 * rec;
+          const uint32_t D = r0[2 + tb->lmax + tb->k];
+          uint64_t mc = 0;  // the class's members
+          for (int b = 0; b < K2; ++b) {
+            const uint32_t w = st[wbase + (uint32_t)b * nthr];
+            if ((w & W_ALIVE) && !(w & W_SPLIT) && ((uint32_t)b & D) == c) mc |= 1ull << b;
+          }
+          stepm = 0;
+          if (mc) {
+            uint16_t *recp = r0 + (size_t)c * rec;
             const uint32_t cnt0 = recp[0];
             uint32_t cnt = 0, busf = 0, ftok = 0, htok = 0;
             bool fall = false, hall = false, ok = false;
             if (!slow_all && cnt0 + 2 <= 16)  // (a longer shared list splits)
               ok = t2_shared_reg<16>(tb, s, recp, cnt0, a, big, nc, cd, sm.cbm, cnt, busf, fall, ftok, hall, htok, rp->err);
-
-            if (ok) {
+            if (!ok) {  // one list per member from here on; they take this slice below
+              t2_split_class(tb, r0, rec, c, mc, st, wbase, nthr, rp->err);
+              stepm = mc;  // (bits: bus words of the address)
+              sm.misc[4] = s;  // the work list is rebuilt after the pass
+            } else {
               const uint32_t toks = (busf >> 8) & 0xFFu, busm = busf & 0xFFu, intree = toks & ~busm;
-              for (int b = 0; b < K2; ++b) {
-                const uint32_t widx = wbase + (uint32_t)b * nthr;
+              for (uint64_t m = mc; m; m &= m - 1) {
+                const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+                const uint32_t widx = wbase + b * nthr;
                 const uint32_t w = st[widx];
-                if (!(w & W_ALIVE)) continue;
-                const uint32_t live = (uint32_t)b & toks;
+                const uint32_t live = b & toks;
                 const uint32_t e = (w & W_E) + ((w & W_CNT) >> W_CNT_SH);  // exposure through slice s-1
                 const uint32_t cb = cnt + (uint32_t)__popc(live & intree);
                 const bool flip = fall ^ (bool)(__popc(ftok & live) & 1);
                 const bool hit = hall || (htok & live);
                 // after the last slice a ground component keeps its bus word in the count field
-                const uint32_t cf = (s == T - 1 && cb == 0) ? (W_FBUS | ((live & busm) << W_CNT_SH)) : (cb << W_CNT_SH);
+                const uint32_t cf = (s == T - 1 && cb == 0) ? (W_FBUS | ((busm & (~toks | b)) << W_CNT_SH)) : (cb << W_CNT_SH);
                 st[widx] = ((w & W_SIGN) ^ (flip ? W_SIGN : 0u)) | (w & (W_ALIVE | W_DEV)) | e | cf | (hit ? W_HIT : 0u);
               }
-              continue;
             }
-            t2_split(tb, pool, rec, g, K2, st, wbase, nthr, rp->err);
-            sm.misc[4] = 1;  // the work list is rebuilt after the pass
           }
-          clast = c0 + (uint32_t)K2 - 1u;
         }
-        for (uint32_t c = c0; c <= clast; ++c) {
+        const uint32_t cbase = (ENC == QUBIT && (d >> 31)) ? (c0 & ~(uint32_t)(K2 - 1)) : c0;
+        for (uint64_t mm = stepm; mm; mm &= mm - 1) {
+          const uint32_t c = cbase + (uint32_t)__ffsll((unsigned long long)mm) - 1u;
           const uint32_t g = c >> kb, b = c & (uint32_t)(K2 - 1);
           const uint32_t ow = g / apt, al = g - ow * apt;
           const uint32_t widx = (al * K2 + b) * nthr + ow;
@@ -1507,10 +1635,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
       }
       if (ENC == QUBIT && ndev > 0) {
         __syncthreads();
-        if (sm.misc[4]) {  // an address split: spread its components over the block
-          devl_qubit();
-          if (tid == 0) sm.misc[4] = 0;
-        }
+        if (sm.misc[4] == s) devl_qubit();  // a class split: spread its components over the block
       }
       QR_TM(7);
       if (nc == 0) continue;
@@ -1710,8 +1835,9 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
             }
           }
         } else if (ENC == QUBIT && !(w & W_SPLIT)) {
-          // a shared list: its address entries and the tokens x* carries
-          const uint16_t *rs = pool + (size_t)g * K2 * rec;
+          // a shared list (x*'s class): its address entries and the tokens x* carries
+          const uint16_t *r0 = pool + (size_t)g * K2 * rec;
+          const uint16_t *rs = r0 + (size_t)(b & r0[2 + tb->lmax + tb->k]) * rec;
           const uint32_t live = b & ((uint32_t)rs[1] >> 8);
           for (uint32_t c = 0; c < (uint32_t)rs[0]; ++c) {
             const uint32_t q = rs[2 + c];
@@ -1746,62 +1872,75 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
         if (g >= A) break;
         const uint32_t a = xl ? xl[g] : g;
         const uint32_t memw = ENC == QUTRIT ? mem[a] : 0u;
+        uint64_t skip = 0;  // components already handled with their shared list
         if (ENC == QUBIT) {
           const uint32_t base = al * K2;
           const uint64_t am = (alive >> base) & kfull;
           if (!am) continue;
           const bool t2 = ((devm >> base) & kfull) != 0ull;
-          const uint32_t jf = base + (uint32_t)__ffsll((unsigned long long)am) - 1u;
-          if (t2 && !(st[jf * nthr + tid] & W_SPLIT)) {
-            // a shared list: J's sites must be on it, J's data tokens carried
-            uint16_t *rs = pool + (size_t)g * K2 * rec;
-            Rec<ENC> R{rs};
+          if (t2) {
+            // the members on shared lists, class by class: J's sites must be
+            // on the class's list, J's tagged tokens carried
+            uint16_t *r0 = pool + (size_t)g * K2 * rec;
             const int kk = tb->k, lmax = tb->lmax;
-            const uint32_t busf = rs[1], toks = (busf >> 8) & 0xFFu;
-            bool okA = true;
-            uint32_t need = 0;
-            for (int c = 0; c < nJ && okA; ++c) {
-              const uint32_t q = sm.Jb[c] & 0xFFFFu;
-              if (R.find_site(q) >= 0) continue;
-              int tq = -1;
-              for (int t = 0; t < kk; ++t)
-                if (((toks >> t) & 1u) && rs[2 + lmax + t] == q) tq = t;
-              if (tq < 0)
-                okA = false;
-              else
-                need |= 1u << tq;
-            }
-            uint64_t surv = 0;
-            if (okA)
-              for (uint64_t m = am; m; m &= m - 1) {
-                const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1u;
-                if (!(need & ~(b & toks))) surv |= 1ull << b;
-              }
-            if (surv) {
-              for (int c = 0; c < nJ; ++c) {
-                const int jj = R.find_site(sm.Jb[c] & 0xFFFFu);
-                if (jj >= 0) R.remove(jj);
-              }
-              for (int t = 0; t < kk; ++t)
-                if ((need >> t) & 1u) rs[2 + lmax + t] = (uint16_t)EMPTY;
-              rs[1] = (uint16_t)(busf & ~(need << 8));
-            }
-            const uint32_t toks2 = toks & ~need, busm = busf & 0xFFu;
+            const uint32_t D = r0[2 + lmax + kk];
+            uint64_t cm = 0;
             for (uint64_t m = am; m; m &= m - 1) {
               const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1u;
-              const uint32_t j = base + b;
-              if (!((surv >> b) & 1ull)) {
-                st[j * nthr + tid] = 0u;
-                alive &= ~(1ull << j);
-                devm &= ~(1ull << j);
-                continue;
-              }
-              const uint32_t w = st[j * nthr + tid];
-              const uint32_t cnt = ((w & W_CNT) >> W_CNT_SH) - (uint32_t)nJ;
-              const uint32_t cf = (s == T - 1 && cnt == 0) ? (W_FBUS | ((b & toks2 & busm) << W_CNT_SH)) : (cnt << W_CNT_SH);
-              st[j * nthr + tid] = (w & (W_SIGN | W_ALIVE | W_DEV | W_E)) | cf;
+              if (!(st[(base + b) * nthr + tid] & W_SPLIT)) cm |= 1ull << b;
             }
-            continue;
+            for (uint64_t mm = class_mask(cm, D); mm; mm &= mm - 1) {
+              const uint32_t c = (uint32_t)__ffsll((unsigned long long)mm) - 1u;
+              uint16_t *rs = r0 + (size_t)c * rec;
+              Rec<ENC> R{rs};
+              const uint32_t busf = rs[1], toks = (busf >> 8) & 0xFFu;
+              bool okA = true;
+              uint32_t need = 0;
+              for (int cc = 0; cc < nJ && okA; ++cc) {
+                const uint32_t q = sm.Jb[cc] & 0xFFFFu;
+                if (R.find_site(q) >= 0) continue;
+                int tq = -1;
+                for (int t = 0; t < kk; ++t)
+                  if (((toks >> t) & 1u) && rs[2 + lmax + t] == q) tq = t;
+                if (tq < 0)
+                  okA = false;
+                else
+                  need |= 1u << tq;
+              }
+              uint64_t mc = 0, surv = 0;
+              for (uint64_t m = cm; m; m &= m - 1) {
+                const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+                if ((b & D) != c) continue;
+                mc |= 1ull << b;
+                if (okA && !(need & ~(b & toks))) surv |= 1ull << b;
+              }
+              if (surv) {
+                for (int cc = 0; cc < nJ; ++cc) {
+                  const int jj = R.find_site(sm.Jb[cc] & 0xFFFFu);
+                  if (jj >= 0) R.remove(jj);
+                }
+                for (int t = 0; t < kk; ++t)
+                  if ((need >> t) & 1u) rs[2 + lmax + t] = (uint16_t)EMPTY;
+                rs[1] = (uint16_t)(busf & ~(need << 8));
+              }
+              const uint32_t toks2 = toks & ~need, busm = busf & 0xFFu;
+              for (uint64_t m = mc; m; m &= m - 1) {
+                const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+                const uint32_t j = base + b;
+                if (!((surv >> b) & 1ull)) {
+                  st[j * nthr + tid] = 0u;
+                  alive &= ~(1ull << j);
+                  devm &= ~(1ull << j);
+                  continue;
+                }
+                const uint32_t w = st[j * nthr + tid];
+                const uint32_t cnt = ((w & W_CNT) >> W_CNT_SH) - (uint32_t)nJ;
+                const uint32_t cf = (s == T - 1 && cnt == 0) ? (W_FBUS | ((busm & (~toks2 | b)) << W_CNT_SH)) : (cnt << W_CNT_SH);
+                st[j * nthr + tid] = (w & (W_SIGN | W_ALIVE | W_DEV | W_E)) | cf;
+              }
+            }
+            skip = cm;
+            if (!(am & ~cm)) continue;  // (members with lists of their own: below)
           }
           if (!t2) {
             // tier 1: J's data tokens, and whether J holds an address token
@@ -1858,6 +1997,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
                 if (ovf) atomicOr(rp->err, ERR_LIST);
                 rs[0] = (uint16_t)caddr;
                 rs[1] = (uint16_t)(busm | (toks << 8));
+                rs[2 + tb->lmax + tb->k] = 0;  // one class
               }
               const uint32_t intree = toks & ~busm;
               uint32_t future = 0;  // fetch phases still ahead, picked up literally in tier 2
@@ -1886,9 +2026,11 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
               continue;
             }
           }
-          // a split tier-2 address, or no address token in J: one component at a time (below)
+          // components with lists of their own, or no address token in J:
+          // one component at a time
         }
         for (int b = 0; b < K2; ++b) {
+          if ((skip >> b) & 1ull) continue;
           const uint32_t j = al * K2 + b;
           uint32_t w = njumps == 0 ? init_word<ENC>(mem[a], (uint32_t)b, kmask) : st[j * nthr + tid];
           if (!(w & W_ALIVE)) continue;
@@ -2122,8 +2264,9 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
           } else if (!ground) {
             bus = 0u;
           } else if (ENC == QUBIT && !(w & W_SPLIT)) {
-            const uint32_t bf = pool[(size_t)g * K2 * rec + 1];
-            bus = (uint32_t)b & (bf >> 8) & bf & 0xFFu;
+            const uint16_t *r0 = pool + (size_t)g * K2 * rec;
+            const uint32_t bf = r0[(size_t)(b & r0[2 + tb->lmax + tb->k]) * rec + 1];
+            bus = bf & (~(bf >> 8) | (uint32_t)b) & 0xFFu;
           } else {
             bus = pool[(size_t)(g * K2 + b) * rec + 1];
           }

@@ -660,9 +660,9 @@ qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
   // circuit adds at most one router per store/unstore and one per fetch
   c->lmax = c->enc == QUBIT ? 2 * n_addr + k_data : 4 * n_addr + k_data;
   c->emax = (c->T - 1) * c->lmax;
-  // record: count, bus word, lmax sites (+ the data tokens' sites of a
-  // shared qubit list)
-  c->rec = (c->lmax + 2 + (c->enc == QUBIT ? k_data : 0) + 1) & ~1;
+  // record: count, bus word, lmax sites (+ the data tokens' sites and the
+  // split set of a shared qubit list)
+  c->rec = (c->lmax + 2 + (c->enc == QUBIT ? k_data + 1 : 0) + 1) & ~1;
   const double lw = c->emax * std::log(1.0 - gamma);
   if (lw < -690.0) {
     delete c;
