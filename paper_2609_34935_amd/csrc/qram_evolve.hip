@@ -166,17 +166,20 @@ __device__ __forceinline__ void t1_addr_hits(const Tables *__restrict__ tb,
 }
 
 // Integer exposure through slice s of a tier-1 component (excited sites
-// summed over slices 1..s).
+// summed over slices 1..s).  wcs: the exposure of each token through slice s
+// (address bit p, then data token b), from shared memory.
 template <int ENC>
 __device__ __forceinline__ uint32_t t1_exposure(const Tables *__restrict__ tb,
-                                                int s, uint32_t a,
+                                                const uint8_t *wcs, int s, uint32_t a,
                                                 uint32_t dv, uint32_t ek) {
-  const int n = tb->n;
+  const int n = tb->n, k = tb->k;
   uint32_t e = ek;
-  for (int t = 0; t < n; ++t)
-    if ((a >> (n - 1 - t)) & 1u) e += tb->cntA[s][t];
-  for (int b = 0; b < tb->k; ++b)
-    if ((dv >> b) & 1u) e += tb->cntD[s][b];
+#pragma unroll
+  for (int p = 0; p < MAXN; ++p)
+    if (p < n && ((a >> p) & 1u)) e += wcs[p];
+#pragma unroll
+  for (int b = 0; b < MAXK; ++b)
+    if (b < k && ((dv >> b) & 1u)) e += wcs[n + b];
   if (ENC == QUTRIT) e += tb->cntR[s];
   return e;
 }
@@ -441,6 +444,49 @@ struct RList {
     }
     return d;
   }
+  // qutrit store at node v (router site 2v, data site 2v+1): an empty
+  // router takes the data site's value (R when it holds one, else L); a set
+  // router with an empty data site is unstored (R leaves the data site set).
+  // One scan finds both sites, a second applies the change.
+  __device__ __forceinline__ void store_node(uint32_t v, bool &ovf) {
+    int jr = -1, jd = -1;
+    uint32_t xr = 0;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const uint32_t x = get(j), q = x & SM;
+      if (q == 2 * v) {
+        jr = j;
+        xr = x;
+      }
+      if (q == 2 * v + 1) jd = j;
+    }
+    int jsel = -1;
+    uint32_t val = 0;
+    bool need_add = false;
+    if (jr < 0) {
+      if (jd >= 0) {
+        jsel = jd;
+        val = 2 * v | LV_R_BIT;
+      } else {
+        need_add = true;
+        val = 2 * v;
+      }
+    } else if (jd < 0) {
+      jsel = jr;
+      val = (xr & LV_R_BIT) ? 2 * v + 1 : EMPTY;
+    }
+    bool placed = false;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      if (j == jsel) {
+        set(j, val);
+      } else if (need_add && !placed && get(j) == EMPTY) {
+        set(j, val);
+        placed = true;
+      }
+    }
+    if (need_add && !placed) ovf = true;
+  }
   // does a candidate of the slice sit on one of the sites?
   __device__ __forceinline__ bool hit(bool big, int nc, const uint32_t *cdec,
                                       const uint32_t *cbm) const {
@@ -497,20 +543,7 @@ __device__ __forceinline__ void t2_gates_reg(const Tables *__restrict__ tb, int 
       }
       for (int g = 0; g < 4; ++g) {
         if (g >= ng) break;
-        const uint32_t v = g == 0 ? g0 : g == 1 ? g1 : g == 2 ? g2 : g3;
-        const int d = L.dir(v);  // -1: W
-        const bool dd = L.has(2 * v + 1);
-        if (d < 0) {
-          if (dd) {
-            L.remove_site(2 * v + 1);
-            ovf |= !L.add(2 * v | LV_R_BIT);
-          } else {
-            ovf |= !L.add(2 * v);
-          }
-        } else if (!dd) {
-          L.remove_site(2 * v);
-          if (d == 1) ovf |= !L.add(2 * v + 1);
-        }
+        L.store_node(g == 0 ? g0 : g == 1 ? g1 : g == 2 ? g2 : g3, ovf);
       }
     }
   }
@@ -1978,8 +2011,12 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
                 // (lost), written once
                 uint16_t *rs = pool + (size_t)g * K2 * rec;
                 bool ovf = false;
-                for (int t = 0; t < n; ++t) {
-                  const int q = t1_site(tb, s, a, t);
+                int qs[MAXN];  // the address tokens' sites, loaded together
+#pragma unroll
+                for (int t = 0; t < MAXN; ++t) qs[t] = t < n ? t1_site(tb, s, a, t) : -1;
+#pragma unroll
+                for (int t = 0; t < MAXN; ++t) {
+                  const int q = qs[t];
                   if (q < 0 || !((a >> (n - 1 - t)) & 1u)) continue;
                   bool inJ = false;
                   for (int c = 0; c < nJ; ++c) inJ |= (sm.Jb[c] & 0xFFFFu) == (uint32_t)q;
@@ -2015,7 +2052,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
                 const uint32_t w = njumps == 0 ? init_word<ENC>(mem[a], b, kmask) : st[j * nthr + tid];
                 const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
                 // exposure through slice s (J's sites excluded)
-                const uint32_t e = t1_exposure<ENC>(tb, s, a, live, w & W_EK) - (uint32_t)nJ;
+                const uint32_t e = t1_exposure<ENC>(tb, sm.wc + s * (n + tb->k), s, a, live, w & W_EK) - (uint32_t)nJ;
                 uint32_t sign = w & W_SIGN;
                 if (__popc(live & mem[a] & future) & 1) sign ^= W_SIGN;
                 const uint32_t cb = caddr + (uint32_t)__popc(b & toks & intree);
@@ -2060,7 +2097,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
             if (dev) {
               // exposure through slice s and the phases fetched so far
               const uint32_t dv = ENC == QUBIT ? live : (live & memw);
-              const uint32_t e = t1_exposure<ENC>(tb, s, a, dv, w & W_EK) - (uint32_t)nJ;
+              const uint32_t e = t1_exposure<ENC>(tb, sm.wc + s * (n + tb->k), s, a, dv, w & W_EK) - (uint32_t)nJ;
               uint32_t sign = w & W_SIGN;
               if (ENC == QUBIT) {
                 uint32_t future = 0;
@@ -2081,10 +2118,14 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
                 else
                   ovf = true;
               };
-              for (int t = 0; t < n; ++t) {
-                const bool abit = (a >> (n - 1 - t)) & 1u;
-                const int q = t1_site(tb, s, a, t);
+              int qs[MAXN];  // the tokens' sites, loaded together
+#pragma unroll
+              for (int t = 0; t < MAXN; ++t) qs[t] = t < n ? t1_site(tb, s, a, t) : -1;
+#pragma unroll
+              for (int t = 0; t < MAXN; ++t) {
+                const int q = qs[t];
                 if (q < 0) continue;
+                const bool abit = (a >> (n - 1 - t)) & 1u;
                 if (ENC == QUTRIT && (q & 1) == 0)
                   put((uint32_t)q | (abit ? LV_R_BIT : 0u));
                 else if (abit)
