@@ -152,8 +152,12 @@ def main():
     ap.add_argument("--cpu-qutrit", type=int, default=6144)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--launch-cache", default=None,
-                    help="JSON file of tuned launch shapes: read if present, else written")
+    ap.add_argument("--launch-cache", default=os.path.join(ROOT, "paper_2609_34935_amd", "tuned",
+                                                        "launch_n10k4_gamma1e-3.json"),
+                    help="JSON file of tuned launch shapes: read if present, else written "
+                         "(default: the shapes shipped for this workload)")
+    ap.add_argument("--retune", action="store_true",
+                    help="run the autotuner instead of reading the launch cache")
     ap.add_argument("--modes", default="pruned,full")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -188,7 +192,7 @@ def main():
     ctxs = {enc: P.QramContext(N, K, enc, GAMMA, mem) for enc in (P.QRAM_QUBIT, P.QRAM_QUTRIT)}
     tuned = {}
     cache = None
-    if args.launch_cache and os.path.exists(args.launch_cache):
+    if args.launch_cache and os.path.exists(args.launch_cache) and not args.retune:
         cache = json.load(open(args.launch_cache))
     for enc, ctx in ctxs.items():
         for mode in (P.QRAM_MODE_PRUNED, P.QRAM_MODE_FULL):
@@ -199,7 +203,7 @@ def main():
                 ms = ctx.autotune(mode, seed, 0, min(nt, 16384))
                 log(f"autotune enc={enc} mode={mode}: {ctx.get_launch(mode)} {ms:.3f} ms")
             tuned[(enc, mode)] = ctx.get_launch(mode)
-    if args.launch_cache and cache is None:
+    if args.launch_cache and cache is None and not os.path.exists(args.launch_cache):
         json.dump({f"{e}:{m}": list(v) for (e, m), v in tuned.items()}, open(args.launch_cache, "w"))
     modes = [P.QRAM_MODE_PRUNED] + ([P.QRAM_MODE_FULL] if "full" in args.modes.split(",") else [])
     stream = torch.cuda.current_stream()

@@ -369,6 +369,7 @@ struct RList {
   uint32_t p[C / 2];
   uint32_t bus;
   bool dirty;  // changed since load: the record needs writing back
+  bool holes;  // an entry was removed: the entries may no longer be contiguous
   static constexpr uint32_t SM = ENC == QUTRIT ? 0x7FFFu : 0xFFFFu;
 
   __device__ __forceinline__ uint32_t get(int j) const {
@@ -383,6 +384,7 @@ struct RList {
     const uint32_t *r32 = reinterpret_cast<const uint32_t *>(rec);
     bus = r32[0] >> 16;
     dirty = false;
+    holes = false;
 #pragma unroll
     for (int j = 0; j < C; j += 2) {
       const uint32_t w = (uint32_t)j < cnt ? r32[1 + j / 2] : 0xFFFFFFFFu;
@@ -392,6 +394,21 @@ struct RList {
     }
   }
   __device__ __forceinline__ uint32_t store(uint16_t *rec) const {
+    if (!holes) {  // entries 0 .. cnt-1, empty after: whole words
+      uint32_t cnt = 0;
+#pragma unroll
+      for (int j = 0; j < C; ++j) cnt += get(j) != EMPTY ? 1u : 0u;
+      uint32_t *r32 = reinterpret_cast<uint32_t *>(rec);
+#pragma unroll
+      for (int j = 0; j < C; j += 2) {
+        if ((uint32_t)j + 1 < cnt)
+          r32[1 + j / 2] = p[j >> 1];
+        else if ((uint32_t)j < cnt)  // (nothing past the last entry is written)
+          rec[2 + j] = (uint16_t)(p[j >> 1] & 0xFFFFu);
+      }
+      r32[0] = cnt | (bus << 16);
+      return cnt;
+    }
     uint32_t pos = 0;
 #pragma unroll
     for (int j = 0; j < C; ++j) {
@@ -416,7 +433,10 @@ struct RList {
   __device__ __forceinline__ void remove_site(uint32_t q) {
 #pragma unroll
     for (int j = 0; j < C; ++j)
-      if ((get(j) & SM) == q) set(j, EMPTY);
+      if ((get(j) & SM) == q) {
+        set(j, EMPTY);
+        holes = true;
+      }
   }
   __device__ __forceinline__ bool add(uint32_t x) {
     bool placed = false;
@@ -474,6 +494,7 @@ struct RList {
     } else if (jd < 0) {
       jsel = jr;
       val = (xr & LV_R_BIT) ? 2 * v + 1 : EMPTY;
+      if (val == EMPTY) holes = true;
     }
     bool placed = false;
 #pragma unroll
