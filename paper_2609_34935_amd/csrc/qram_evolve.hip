@@ -1272,17 +1272,19 @@ __device__ __forceinline__ double readlane_f64(double x, int l) {
 
 constexpr int WAVE_MAXA = 2048;  // addresses per slice the wave sums over
 
-// Qutrit, the same walk with the 64 lanes of wave 0 on one slice at a time
-// (qutrit workgroups are small, and the lanes share a slice's subtrees):
-// returns the first slice from s on that the block must evolve, or T.
+// Qutrit, the same walk with the 64 lanes of a wave on one slice at a time
+// (qutrit workgroups are small, and the lanes share a slice's subtrees).
+// Wave w of nw takes the w-th, (w+nw)-th, ... slice with candidates from s
+// on; returns the first of its slices the block must evolve, or T.
 template <int ENC>
 __device__ __forceinline__ int nojump_walk_wave(const Tables *__restrict__ tb, const Run *rp,
                                                 const Sm &sm, const uint32_t *__restrict__ cand,
-                                                bool pre, int s, uint32_t traj) {
+                                                bool pre, int s, uint32_t traj, int w, int nw) {
   const int n = tb->n, k = tb->k, T = tb->T, nb = n + k;
   const uint32_t M = (uint32_t)tb->M;
   const uint32_t kmask = (1u << k) - 1u;
   const int lane = threadIdx.x & 63;
+  for (int i = 0; i < w && s < T; ++i) s = sm.nxt[s + 1];
   while (s < T) {
     const uint32_t cb = sm.cstart[s];
     const int nc = (int)(sm.cstart[s + 1] - cb);
@@ -1381,7 +1383,7 @@ __device__ __forceinline__ int nojump_walk_wave(const Tables *__restrict__ tb, c
       const double wall = tb->ctot[s - 1];
       if (!(u * wall < wall - H)) return s;
     }
-    s = sm.nxt[s + 1];
+    for (int i = 0; i < nw && s < T; ++i) s = sm.nxt[s + 1];
   }
   return T;
 }
@@ -1546,12 +1548,15 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
         if (ENC == QUBIT) {
           s = nojump_walk<ENC>(tb, rp, sm, cand, pre, s, traj);
         } else {
-          if (tid < 64) {
-            const int sw = nojump_walk_wave<ENC>(tb, rp, sm, cand, pre, s, traj);
-            if (tid == 0) sm.misc[3] = sw;
-          }
+          // every wave walks every nw-th slice; the block takes the first stop
+          const int nw = nthr >> 6, wv = tid >> 6;
+          const int sw = nojump_walk_wave<ENC>(tb, rp, sm, cand, pre, s, traj, wv, nw);
+          int *wmin = reinterpret_cast<int *>(sm.scanb);
+          if ((tid & 63) == 0) wmin[wv] = sw;
           __syncthreads();
-          s = sm.misc[3];
+          s = T;
+          for (int i = 0; i < nw; ++i) s = min(s, wmin[i]);
+          __syncthreads();
         }
         if (s >= T) break;
       }
