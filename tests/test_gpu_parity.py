@@ -141,6 +141,14 @@ def test_launch_shapes(lib, orc, spt, sched):
     compare_runs(lib, orc, 5, 3, QUBIT, 0.01, mem, 99, 0, 120, threads=(spt, sched))
 
 
+@pytest.mark.parametrize("spt,sched", [(4, 1), (8, 1), (16, 3), (32, 1)])
+def test_launch_shapes_qutrit(lib, orc, spt, sched):
+    """Qutrit workgroups of different sizes (the no-jump walk strides over
+    the workgroup's waves)."""
+    mem = memory_words(7, 2, 77)
+    compare_runs(lib, orc, 7, 2, QUTRIT, 3e-3, mem, 98, 0, 150, threads=(spt, sched))
+
+
 # ---------------------------------------------------------------------------
 # forced histories
 # ---------------------------------------------------------------------------
@@ -326,22 +334,25 @@ def test_graph_async_streams(lib):
 # ---------------------------------------------------------------------------
 # qubit tier 2: lists shared by an address's bus words, and their splits
 # ---------------------------------------------------------------------------
-def test_qubit_shared_lists_match_component_lists(lib):
-    """Shared per-address lists (default) against one global-memory list per
-    component: bitwise equal fidelities and statistics, many jumps during
-    the data phase included."""
-    n, k, gamma, nt = 6, 4, 1e-2, 3000
-    mem = memory_words(n, k, 606)
+@pytest.mark.parametrize("n,k,gamma,nt,seed", [
+    (6, 4, 1e-2, 3000, 4242),    # many jumps during the data phase
+    (6, 6, 1e-2, 1000, 4343),    # 64 bus words per address
+    (10, 4, 1e-3, 20000, 4444)])  # the benchmark's tree: splits into classes
+def test_qubit_shared_lists_match_component_lists(lib, n, k, gamma, nt, seed):
+    """Shared per-address lists, split into classes (default), against one
+    global-memory list per component: bitwise equal fidelities and
+    statistics."""
+    mem = memory_words(n, k, 600 + n + k)
     res = []
     for glob in (0, 1):
         with lib.QramContext(n, k, QUBIT, gamma, mem) as ctx:
             ctx.set_option(lib.qram.QRAM_OPT_TIER2_GLOBAL, glob)
-            res.append([fn(4242, 0, nt) for fn in (ctx.run_full, ctx.run_pruned)])
+            res.append([fn(seed, 0, nt) for fn in (ctx.run_full, ctx.run_pruned)])
     for (fa, sa), (fb, sb) in zip(res[0], res[1]):
         assert np.array_equal(fa, fb)
         assert np.array_equal(sa, sb)
     js = res[0][0][1]["first_jump_slice"]
-    assert np.sum((js > 2 * n) & (js < 4 * n + 2 * k)) > 100
+    assert np.sum((js > 2 * n) & (js < 4 * n + 2 * k)) > 50
 
 
 @pytest.mark.parametrize("s,site", [(12, 0), (14, 0), (13, 2), (15, 4), (16, 2), (17, 0)])
