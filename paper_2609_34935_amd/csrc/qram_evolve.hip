@@ -1705,7 +1705,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
         for (int c = 0; c < nc; ++c) maybe |= ((cd[c] >> 20) & 0xFFu) != NONE;
         if (!maybe) continue;
       }
-      if (ndev > 0) __syncthreads();
+      if (ENC == QUTRIT && ndev > 0) __syncthreads();  // (qubit: after the tier-2 pass above)
 
       // owner pass: which of my components does a candidate hit?
       uint64_t hmask = 0;
