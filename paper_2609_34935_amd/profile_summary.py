@@ -3,6 +3,7 @@
     python -m paper_2609_34935_amd.profile_summary trace KERNEL_TRACE.csv OUT.txt --command "..."
     python -m paper_2609_34935_amd.profile_summary counters --fetch F.csv --write W.csv [--sq S.csv] \\
         --kernel 'k_evolve<1,' OUT.json --command "..." [--command "..."]
+    python -m paper_2609_34935_amd.profile_summary states S.csv --kernel 'k_evolve<1,' OUT.txt --command "..."
 
 The counter summary scales FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by
 what the same counters read for the largest plain device copy of the run
@@ -108,6 +109,24 @@ def counter_summary(fetch, write, sq, kernel, out, commands):
     print("\n".join(lines))
 
 
+def state_summary(sq, kernel, out, commands):
+    """Per-launch SQ counters of one run, and each as a fraction of the
+    wave-cycles (SQ_WAVE_CYCLES), for the largest launch of the kernel."""
+    d = _per_dispatch(sq)
+    ks = [v for v in d.values() if kernel in v["name"] and "SQ_WAVE_CYCLES" in v]
+    if not ks:
+        raise SystemExit(f"no dispatch of {kernel} in {sq}")
+    big = max(ks, key=lambda v: v["SQ_WAVE_CYCLES"])
+    wc = big["SQ_WAVE_CYCLES"]
+    lines = ["rocprofv3 wave-state counters (largest launch of the kernel below)", ""]
+    lines += [f"command: {c}" for c in commands]
+    lines += ["", f"kernel: {kernel}", f"kernel_sha256: {kernel_sha256()}", f"workgroup: {big['wg']}", ""]
+    for c in sorted(k for k in big if k.startswith("SQ_")):
+        lines.append(f"{c:<24} {big[c]:>16.4e}   {big[c] / wc:>7.3f} of SQ_WAVE_CYCLES")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -122,9 +141,16 @@ def main():
     c.add_argument("--kernel", required=True)
     c.add_argument("out")
     c.add_argument("--command", action="append", default=[])
+    w = sub.add_parser("states")
+    w.add_argument("csv")
+    w.add_argument("--kernel", required=True)
+    w.add_argument("out")
+    w.add_argument("--command", action="append", default=[])
     a = ap.parse_args()
     if a.what == "trace":
         trace_summary(a.csv, a.out, a.command)
+    elif a.what == "states":
+        state_summary(a.csv, a.kernel, a.out, a.command)
     else:
         counter_summary(a.fetch, a.write, a.sq, a.kernel, a.out, a.command)
 
