@@ -337,6 +337,8 @@ def test_graph_async_streams(lib):
 @pytest.mark.parametrize("n,k,gamma,nt,seed", [
     (6, 4, 1e-2, 3000, 4242),    # many jumps during the data phase
     (6, 6, 1e-2, 1000, 4343),    # 64 bus words per address
+    (8, 1, 1e-2, 2000, 4545),    # two bus words per address
+    (11, 2, 8e-3, 600, 4646),    # slices with more than 16 candidates (bitmap hits)
     (10, 4, 1e-3, 20000, 4444)])  # the benchmark's tree: splits into classes
 def test_qubit_shared_lists_match_component_lists(lib, n, k, gamma, nt, seed):
     """Shared per-address lists, split into classes (default), against one
@@ -353,6 +355,13 @@ def test_qubit_shared_lists_match_component_lists(lib, n, k, gamma, nt, seed):
         assert np.array_equal(sa, sb)
     js = res[0][0][1]["first_jump_slice"]
     assert np.sum((js > 2 * n) & (js < 4 * n + 2 * k)) > 50
+
+
+def test_qubit_classes_against_oracle(lib, orc):
+    """Strong damping on a tree deep enough for stranded tokens to reach a
+    store: the class splits against the oracle trajectory by trajectory."""
+    mem = memory_words(5, 3, 5353)
+    compare_runs(lib, orc, 5, 3, QUBIT, 0.03, mem, 5353, 0, 300)
 
 
 @pytest.mark.parametrize("s,site", [(12, 0), (14, 0), (13, 2), (15, 4), (16, 2), (17, 0)])
