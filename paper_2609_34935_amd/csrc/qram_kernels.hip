@@ -141,38 +141,40 @@ __global__ void __launch_bounds__(256) k_classify(const Tables *__restrict__ tb,
       mark[range_node(enc, q >> 1)] = 1;
     }
     __syncthreads();
-    for (int l = 1; l < n; ++l) {  // a node is bad if it or an ancestor is marked
-      const int v0 = (1 << l) - 1;
-      for (int v = v0 + tid; v < 2 * v0 + 1; v += nthr)
-        if (mark[(v - 1) >> 1]) mark[v] = 1;
-      __syncthreads();
-    }
+    // address i is bad when a node on its path, root to its leaf node, is
+    // marked; one ballot per wave gives 64 addresses of the bad bitmap
     const int leaf0 = (1 << (n - 1)) - 1;
+    const int nw64 = (D + 63) >> 6;
+    uint64_t *bb = rp->badbits + (size_t)tj * nw64;
     uint32_t nbad_local = 0, first_good = 0xFFFFFFFFu;
-    for (int w = tid; w < nw32; w += nthr) {
-      uint32_t bits = 0;
-      for (int l = 0; l < 32; ++l) {
-        const int i = 32 * w + l;
-        if (i < D && mark[leaf0 + (i >> 1)]) bits |= 1u << l;
+    for (int base = 0; base < D; base += nthr) {
+      const int i = base + tid;
+      bool bad = false;
+      if (i < D) {
+        uint32_t v = (uint32_t)(leaf0 + (i >> 1));
+        for (int l = 0; l < n; ++l) {  // n nodes: the leaf node up to the root
+          bad |= mark[v] != 0;
+          v = (v - 1) >> 1;
+        }
       }
-      badw[w] = bits;
-      nbad_local += __popc(bits);
-      const uint32_t valid = (32 * w + 32 <= D) ? 0xFFFFFFFFu : ((1u << (D - 32 * w)) - 1u);
-      const uint32_t good = ~bits & valid;
-      if (good && first_good == 0xFFFFFFFFu) first_good = 32 * w + (__ffs(good) - 1);
+      const uint64_t m = __ballot(bad);
+      const int word = (base >> 6) + (tid >> 6);
+      if ((tid & 63) == 0 && word < nw64) {
+        const int nv = min(64, D - 64 * word);
+        const uint64_t valid = nv >= 64 ? ~0ull : ((1ull << nv) - 1ull);
+        bb[word] = m & valid;
+        badw[2 * word] = (uint32_t)(m & valid);
+        if (2 * word + 1 < nw32) badw[2 * word + 1] = (uint32_t)((m & valid) >> 32);
+        nbad_local += (uint32_t)__popcll(m & valid);
+        const uint64_t good = ~m & valid;
+        if (good) first_good = min(first_good, (uint32_t)(64 * word + __ffsll((unsigned long long)good) - 1));
+      }
     }
     if (first_good != 0xFFFFFFFFu) atomicMin(&sbuf[8], first_good);
     uint32_t nbad;
     block_excl_scan_u32(nbad_local, sbuf, &nbad);
     __syncthreads();
     const uint32_t ref = sbuf[8];
-    const int nw64 = (D + 63) >> 6;
-    uint64_t *bb = rp->badbits + (size_t)tj * nw64;
-    for (int w = tid; w < nw64; w += nthr) {
-      const uint64_t lo = badw[2 * w];
-      const uint64_t hi = (2 * w + 1 < nw32) ? badw[2 * w + 1] : 0;
-      bb[w] = lo | (hi << 32);
-    }
     // explicit addresses: every bad address plus the reference (pruned), in
     // ascending order; the full mode evolves every address.
     uint32_t nex;
