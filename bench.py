@@ -160,6 +160,8 @@ def main():
                     help="run the autotuner instead of reading the launch cache")
     ap.add_argument("--modes", default="pruned,full")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-subtree", action="store_true",
+                    help="skip the qubit step under the damping-only subtree marking")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-chunk", type=int, default=16384)
@@ -264,6 +266,41 @@ def main():
             assert np.array_equal(d_fid[enc].cpu().numpy(), pr["fid"][enc]), "graph replay differs"
         log(f"graph replay: {graph_value:.1f} trajectories/s")
 
+    # the damping-only subtree marking of the qubit encoding (exact for
+    # damping, fewer explicit addresses): the same step and trajectories
+    subtree = None
+    if not args.no_subtree:
+        qctx = ctxs[P.QRAM_QUBIT]
+        qctx.set_option(P.qram.QRAM_OPT_SUBTREE_MARKING, 1)
+        step(P.QRAM_MODE_PRUNED)
+        torch.cuda.synchronize()
+        qctx.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(P.QRAM_MODE_PRUNED)
+        torch.cuda.synchronize()
+        dt_sub = time.perf_counter() - t0
+        ms_s, nbs = qctx.stage_times()
+        qctx.set_timing(False)
+        qctx.set_option(P.qram.QRAM_OPT_SUBTREE_MARKING, 0)
+        qctx.errors()
+        fs = d_fid[P.QRAM_QUBIT].cpu().numpy()
+        ss = np.frombuffer(d_st[P.QRAM_QUBIT].cpu().numpy().tobytes(), dtype=P.STATS_DTYPE)
+        ref_f = pr["fid"][P.QRAM_QUBIT]
+        assert np.all(np.abs(fs - ref_f) <= 1e-12 * np.maximum(np.abs(ref_f), 1e-3)), \
+            "subtree marking changed a fidelity"
+        sub_value = total / dt_sub
+        subtree = {
+            "value": round(sub_value, 1),
+            "speedup_over_full": None if full_value is None else round(sub_value / full_value, 4),
+            "qubit_pruned_evolve_ms": round(ms_s[2] / max(nbs, 1), 3),
+            "qubit_evolved_fraction": round(float(ss["n_explicit"].mean()) / 2 ** (N + K), 4),
+            "qubit_mean_bad": round(float(ss["n_bad"].mean()), 2),
+            "rule": "qubit damping candidates mark their own subtree (Eq. subtree) instead of "
+                    "Eq. badrange; qutrit unchanged; fidelities equal the uniform rule's",
+        }
+        log(f"subtree marking: {sub_value:.1f} trajectories/s")
+
     # roofline of the dominant kernel: the qubit evolution launches
     ms_stage, nb, nlaunch = pr["stage"][P.QRAM_QUBIT]
     evolve_ms_step = ms_stage[2] / max(nb, 1)
@@ -310,6 +347,7 @@ def main():
         "full_value": None if full_value is None else round(full_value, 1),
         "speedup_pruned_over_full": None if full_value is None else round(value / full_value, 4),
         "graph_value": None if graph_value is None else round(graph_value, 1),
+        "subtree_marking": subtree,
         "per_encoding": per_enc,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_ALU_TOPS, 3),
                      "unit": "TOP/s", "frac": round(achieved / PEAK_ALU_TOPS, 4),

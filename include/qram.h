@@ -15,7 +15,7 @@
  * mode evolves every branch.  Both give the same fidelity up to rounding.
  *
  * Input class: the data-loading input with uniform address amplitudes
- * c_i = 2^{-n/2} and bus word 0 (Sec. V, App. D).
+ * c_i = 2^{-n/2} and bus word 0 (Sec. VI, App. D).
  *
  * Random numbers (fixed contract, identical for every mode and launch shape):
  * Philox4x32-10 keyed by the 64-bit seed.  Candidate history: the tree site q
@@ -174,7 +174,7 @@ qram_status qram_get_launch(const qram_ctx *ctx, qram_mode mode,
                             int *slots_per_thread, int *schedule);
 
 /*
- * Options (value 0/1; both default to 0).
+ * Options (value 0/1; all default to 0).
  *   QRAM_OPT_TIER2_GLOBAL: keep every explicit site list of a component whose
  *     routing a jump changed in global memory instead of registers, one list
  *     per component (the qubit encoding otherwise shares one list among the
@@ -186,8 +186,19 @@ qram_status qram_get_launch(const qram_ctx *ctx, qram_mode mode,
  *     updated in place for the next batch, and launched on the caller's
  *     stream.  Results are identical to the eager path.  Stage timing then
  *     reports the whole batch as the evolution stage.
+ *   QRAM_OPT_SUBTREE_MARKING: qubit encoding only (a no-op for the qutrit
+ *     encoding).  Mark each damping candidate's own subtree (Eq. subtree)
+ *     instead of the family-divergence range of Eq. badrange.  Sec. III B
+ *     and Sec. VI B: a damping jump needs an excitation and an idle qubit has
+ *     none, so damping creates no strays and its damage stays inside the
+ *     candidate's subtree; the uniform rule of Alg. 1 marks a superset.
+ *     Every path here simulates damping only, so the tighter set is exact:
+ *     fidelities equal the full evolution's, and fewer addresses are evolved
+ *     explicitly.  Changes n_bad, ref_addr, n_explicit and the bad bitmap of
+ *     the qubit encoding (sampling, candidate lists and jump statistics are
+ *     unchanged).
  */
-enum { QRAM_OPT_TIER2_GLOBAL = 1, QRAM_OPT_GRAPH = 2 };
+enum { QRAM_OPT_TIER2_GLOBAL = 1, QRAM_OPT_GRAPH = 2, QRAM_OPT_SUBTREE_MARKING = 3 };
 qram_status qram_set_option(qram_ctx *ctx, int option, int value);
 
 /*

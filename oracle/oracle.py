@@ -108,10 +108,15 @@ def sample(n, k, gamma, seed, traj):
     return L[:cnt]
 
 
-def classify(n, k, enc, L):
+def classify(n, k, enc, L, subtree=False):
+    """Bad-address bitmap of a candidate list.  subtree=True marks every
+    candidate's own subtree (Eq. subtree) whatever the encoding: the tighter
+    rule for damping candidates of the qubit encoding (Sec. III B: damping
+    creates no strays, so its damage stays inside the candidate's subtree)."""
     L = np.ascontiguousarray(L, dtype=np.uint32)
     bad = np.zeros(1 << n, dtype=np.uint8)
-    nb = lib().orc_classify(n, k, enc, _p(L, C.c_uint32), len(L), _p(bad, C.c_uint8))
+    rule = QUTRIT if subtree else enc
+    nb = lib().orc_classify(n, k, rule, _p(L, C.c_uint32), len(L), _p(bad, C.c_uint8))
     if nb < 0:
         raise ValueError("bad parameters")
     return bad

@@ -76,6 +76,9 @@ struct qram_ctx {
   // graph mode: every batch is captured once into a graph and replayed;
   // the executable graph is updated in place for the next batch
   bool use_graph = false;
+  // qubit encoding: damping candidates mark their own subtree (Eq. subtree)
+  // instead of Eq. badrange
+  bool mark_subtree = false;
   hipGraphExec_t gexec = nullptr;
   double last_ms[3] = {0, 0, 0};
   // stage timing of asynchronous runs: four events per batch
@@ -495,7 +498,7 @@ qram_status enqueue_batch(qram_ctx *c, const Plan &pl, Run r, hipStream_t s,
   if (timed) HIPCHK(c, hipEventRecord(e[0], s));
   if (!skip_sample) HIPCHK(c, launch_sample(c->dtab, r, nt, sample_grid(c, nt), s));
   if (timed) HIPCHK(c, hipEventRecord(e[1], s));
-  HIPCHK(c, launch_classify(c->dtab, r, nt, sample_grid(c, nt), c->D, s));
+  HIPCHK(c, launch_classify(c->dtab, r, nt, sample_grid(c, nt), c->D, c->mark_subtree, s));
   HIPCHK(c, launch_order(c->dtab, r, s));
   if (timed) HIPCHK(c, hipEventRecord(e[2], s));
   qram_status st = launch_buckets(c, pl, r, s);
@@ -834,7 +837,7 @@ qram_status qram_sample_faults(qram_ctx *c, uint64_t seed, uint64_t traj0,
     r.traj0 = (uint32_t)(traj0 + b0);
     r.ntraj = cnt;
     HIPCHK(c, launch_sample(c->dtab, r, cnt, sample_grid(c, cnt), c->stream));
-    HIPCHK(c, launch_classify(c->dtab, r, cnt, sample_grid(c, cnt), c->D, c->stream));
+    HIPCHK(c, launch_classify(c->dtab, r, cnt, sample_grid(c, cnt), c->D, c->mark_subtree, c->stream));
     HIPCHK(c, launch_digest(r, cnt, c->stream));
     HIPCHK(c, hipMemcpyAsync(n_cand + b0, c->ncand, cnt * 4, hipMemcpyDeviceToHost, c->stream));
     if (cand_digest) HIPCHK(c, hipMemcpyAsync(cand_digest + b0, c->digest, cnt * 8, hipMemcpyDeviceToHost, c->stream));
@@ -970,6 +973,10 @@ qram_status qram_set_option(qram_ctx *c, int option, int value) {
     c->use_graph = value != 0;
     return QRAM_OK;
   }
+  if (option == QRAM_OPT_SUBTREE_MARKING) {
+    c->mark_subtree = value != 0;
+    return QRAM_OK;
+  }
   return fail(c, QRAM_E_INVAL, "unknown option");
 }
 
@@ -1003,7 +1010,7 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
       }
       double t_best = 1e300;
       for (int rep = 0; rep < 2; ++rep) {
-        HIPCHK(c, launch_classify(c->dtab, r, nt, sample_grid(c, nt), c->D, c->stream));
+        HIPCHK(c, launch_classify(c->dtab, r, nt, sample_grid(c, nt), c->D, c->mark_subtree, c->stream));
         HIPCHK(c, launch_order(c->dtab, r, c->stream));
         HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
         if ((st = launch_buckets(c, pl, r, c->stream))) return st;

@@ -121,7 +121,7 @@ constexpr uint32_t ERR_LIST = 2u;
 hipError_t launch_sample(const Tables *tb, const Run &rp, uint32_t ntraj,
                          uint32_t grid, hipStream_t s);
 hipError_t launch_classify(const Tables *tb, const Run &rp, uint32_t ntraj,
-                           uint32_t grid, int D, hipStream_t s);
+                           uint32_t grid, int D, bool subtree, hipStream_t s);
 hipError_t launch_order(const Tables *tb, const Run &rp, hipStream_t s);
 hipError_t launch_evolve(const Tables *tb, const Run &rp, int enc,
                          uint32_t grid, int threads, uint32_t lds_bytes,

@@ -6,8 +6,10 @@
 //               the joint sampler): i.i.d. Bernoulli(gamma) site-slices drawn by
 //               a geometric walk over 64-site blocks, Philox4x32-10 counters.
 //   k_classify  bad-address set of the marking rule (Eq. subtree / Eq.
-//               badrange), reference = smallest good address, and the ascending
-//               list of explicitly evolved addresses (Alg. 1 steps 1-2).
+//               badrange, or Eq. subtree for qubit damping candidates on
+//               request), reference = smallest good address, and the
+//               ascending list of explicitly evolved addresses (Alg. 1 steps
+//               1-2).
 //   k_order     groups trajectories into buckets of explicit work, longest
 //               first inside each bucket, and resets the queue heads.
 #include "qram_device.h"
@@ -109,8 +111,10 @@ __global__ void __launch_bounds__(256) k_sample(const Tables *__restrict__ tb,
 // k_classify: marks the range node of every candidate, propagates marks down
 // the tree, and derives the bad bitmap, the reference and the explicit list.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t range_node(int enc, uint32_t v) {
-  if (enc == QUTRIT) return v;  // Eq. subtree
+__device__ __forceinline__ uint32_t range_node(int enc, bool subtree, uint32_t v) {
+  // Eq. subtree: the qutrit encoding, and the qubit encoding when the
+  // damping-only subtree marking is chosen (damping creates no strays)
+  if (enc == QUTRIT || subtree) return v;
   // Eq. badrange: a left child below the root's children inherits its
   // parent's range; right children and the root's children mark their own
   // subtree; the root marks everything.
@@ -119,7 +123,7 @@ __device__ __forceinline__ uint32_t range_node(int enc, uint32_t v) {
 }
 
 __global__ void __launch_bounds__(256) k_classify(const Tables *__restrict__ tb,
-                                                  const Run R_) {
+                                                  const Run R_, uint32_t subtree) {
   const Run *rp = &R_;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -138,7 +142,7 @@ __global__ void __launch_bounds__(256) k_classify(const Tables *__restrict__ tb,
     const uint32_t *cand = rp->cand + (size_t)tj * cap;
     for (uint32_t j = tid; j < nc; j += nthr) {
       const uint32_t q = cand[j] % (uint32_t)M;
-      mark[range_node(enc, q >> 1)] = 1;
+      mark[range_node(enc, subtree != 0, q >> 1)] = 1;
     }
     __syncthreads();
     // address i is bad when a node on its path, root to its leaf node, is
@@ -286,10 +290,10 @@ hipError_t launch_sample(const Tables *tb, const Run &rp, uint32_t ntraj,
 }
 
 hipError_t launch_classify(const Tables *tb, const Run &rp, uint32_t ntraj,
-                           uint32_t grid, int D, hipStream_t s) {
+                           uint32_t grid, int D, bool subtree, hipStream_t s) {
   (void)ntraj;
   const size_t lds = (size_t)((D + 31) / 32) * 4 + 16 * 4 + (size_t)D;
-  hipLaunchKernelGGL(k_classify, dim3(grid), dim3(256), lds, s, tb, rp);
+  hipLaunchKernelGGL(k_classify, dim3(grid), dim3(256), lds, s, tb, rp, subtree ? 1u : 0u);
   return hipGetLastError();
 }
 

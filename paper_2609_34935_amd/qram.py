@@ -49,6 +49,7 @@ EXPORTS = [
 ]
 QRAM_OPT_TIER2_GLOBAL = 1
 QRAM_OPT_GRAPH = 2
+QRAM_OPT_SUBTREE_MARKING = 3
 
 
 class QramError(RuntimeError):

@@ -176,7 +176,7 @@ def test_forced_no_jump(lib, orc, enc):
 @pytest.mark.parametrize("enc", [QUBIT, QUTRIT])
 def test_forced_reference_annihilated(lib, orc, enc):
     """A jump on the root router kills every good branch, the reference
-    included (Sec. V A: the annihilation propagates to the predicted groups)."""
+    included (Sec. VI A: the annihilation propagates to the predicted groups)."""
     n, k = 4, 2
     T, M = 6 * n + 2 * k, 2 * (2**n - 1)
     mem = memory_words(n, k, 4)

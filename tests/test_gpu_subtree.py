@@ -1,0 +1,144 @@
+"""GPU parity of the damping-only subtree marking of the qubit encoding
+(QRAM_OPT_SUBTREE_MARKING) against the CPU oracle.
+
+Sec. III B and Sec. VI B: damping creates no strays, so a damping candidate's
+damage stays inside its own subtree (Eq. subtree) and the uniform Eq.
+badrange marks a superset.  With the tighter set the pruned evolution stays
+exact: fidelities equal the oracle's full evolution (within 1e-12 relative),
+the candidate and jump statistics are those of the oracle, and the bad set and
+reference are those of the oracle's classification under Eq. subtree
+(bit-exact)."""
+import json
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from paper_2609_34935_amd.inputs import memory_words
+
+pytestmark = pytest.mark.gpu
+
+QUTRIT, QUBIT = 0, 1
+FULL, PRUNED = 0, 1
+NONE = 0xFFFFFFFF
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TUNED = os.path.join(ROOT, "paper_2609_34935_amd", "tuned", "launch_n10k4_gamma1e-3.json")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_34935_amd as P
+    P.load_library()
+    return P
+
+
+def fid_close(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b) <= 1e-12 * np.maximum(np.abs(b), 1e-3)
+
+
+def subtree_classes(orc, n, k, gamma, seed, idx):
+    """Oracle bad count and reference (smallest good address) under Eq.
+    subtree, and the bad count under Eq. badrange, per trajectory."""
+    nb, ref, nbw = [], [], []
+    for t in idx:
+        L = orc.sample(n, k, gamma, seed, int(t))
+        bad = orc.classify(n, k, QUBIT, L, subtree=True)
+        good = np.nonzero(bad == 0)[0]
+        nb.append(int(bad.sum()))
+        ref.append(int(good[0]) if len(good) else NONE)
+        nbw.append(int(orc.classify(n, k, QUBIT, L).sum()))
+    return np.array(nb, np.uint32), np.array(ref, np.uint32), np.array(nbw, np.uint32)
+
+
+@pytest.mark.parametrize("n,k,gamma,ntraj", [
+    (2, 1, 0.05, 400), (3, 3, 6e-3, 400), (4, 2, 3e-3, 400), (5, 1, 1.5e-3, 600),
+    (6, 1, 1e-3, 1000), (6, 1, 1e-2, 400), (4, 4, 0.03, 100), (8, 2, 4e-3, 200)])
+def test_subtree_marking_against_oracle(lib, orc, n, k, gamma, ntraj):
+    mem = memory_words(n, k, 2000 + n + k)
+    seed = 770000 + 10 * n + k
+    fo, fpo, so, _ = orc.run_batch(n, k, QUBIT, gamma, mem, seed, 0, ntraj)
+    nb, ref, nbw = subtree_classes(orc, n, k, gamma, seed, range(ntraj))
+    assert np.all(nb <= nbw)
+    with lib.QramContext(n, k, QUBIT, gamma, mem) as ctx:
+        ctx.set_option(lib.qram.QRAM_OPT_SUBTREE_MARKING, 1)
+        sf = ctx.sample_faults(seed, 0, ntraj)
+        for mode, fn in ((FULL, ctx.run_full), (PRUNED, ctx.run_pruned)):
+            f, st = fn(seed, 0, ntraj)
+            bad = np.nonzero(~fid_close(f, fo))[0]
+            assert len(bad) == 0, (mode, bad[:5], f[bad[:5]], fo[bad[:5]])
+            assert np.all(fid_close(st["fid_pre"], fpo)), mode
+            assert np.array_equal(st["n_cand"], so[:, 0].astype(np.uint32))
+            assert np.array_equal(st["n_jumps"], so[:, 4].astype(np.uint16))
+            assert np.array_equal(st["first_jump_slice"], so[:, 5].astype(np.uint16))
+            assert np.array_equal(st["q_ground"], so[:, 7].astype(np.uint8))
+            assert np.array_equal(st["n_bad"], nb), mode
+            assert np.array_equal(st["ref_addr"], ref), mode
+            # the reference is good: it survives exactly when no jump fired
+            want_surv = ((ref != NONE) & (so[:, 4] == 0)).astype(np.uint8)
+            assert np.array_equal(st["ref_survived"], want_surv), mode
+            nx = (nb + (ref != NONE)).astype(np.uint32) << k if mode == PRUNED else np.full(ntraj, 2 ** (n + k))
+            assert np.array_equal(st["n_explicit"], nx), mode
+        # the bad bitmaps of the sampling entry point
+        bits = np.unpackbits(sf["bad_bits"].view(np.uint8), axis=1, bitorder="little")[:, : 1 << n]
+        assert np.array_equal(sf["n_bad"], nb)
+        for t in range(0, ntraj, max(1, ntraj // 50)):
+            L = orc.sample(n, k, gamma, seed, t)
+            assert np.array_equal(bits[t], orc.classify(n, k, QUBIT, L, subtree=True)), t
+        # the option switches back to Eq. badrange
+        ctx.set_option(lib.qram.QRAM_OPT_SUBTREE_MARKING, 0)
+        f2, st2 = ctx.run_pruned(seed, 0, ntraj)
+        assert np.array_equal(st2["n_bad"], nbw)
+        assert np.all(fid_close(f2, fo))
+
+
+def test_subtree_marking_qutrit_unchanged(lib):
+    """The option is a no-op for the qutrit encoding (Eq. subtree already)."""
+    n, k, gamma, nt = 6, 2, 5e-3, 500
+    mem = memory_words(n, k, 2100)
+    with lib.QramContext(n, k, QUTRIT, gamma, mem) as ctx:
+        f0, s0 = ctx.run_pruned(5150, 0, nt)
+        ctx.set_option(lib.qram.QRAM_OPT_SUBTREE_MARKING, 1)
+        f1, s1 = ctx.run_pruned(5150, 0, nt)
+    assert np.array_equal(f0, f1)
+    assert np.array_equal(s0, s1)
+
+
+def test_subtree_marking_full_size_sampled(lib, orc):
+    """n = 10, k = 4, gamma = 1e-3, 1e5 qubit trajectories in the tuned launch
+    shapes: every trajectory's fidelity equals the full mode's under the
+    uniform rule, integer statistics agree, fewer addresses are evolved, and
+    sampled trajectories match the oracle (fidelity, bad count, reference)."""
+    n, k, gamma, nt = 10, 4, 1e-3, 100000
+    mem = memory_words(n, k, 1003)
+    seed = 880003
+    launch = json.load(open(TUNED))
+    with lib.QramContext(n, k, QUBIT, gamma, mem) as ctx:
+        for mode in (FULL, PRUNED):
+            ctx.set_launch(mode, *launch[f"{QUBIT}:{mode}"])
+        ff, sf = ctx.run_full(seed, 0, nt)
+        ctx.set_option(lib.qram.QRAM_OPT_SUBTREE_MARKING, 1)
+        fs, ss = ctx.run_pruned(seed, 0, nt)
+    assert np.all(fid_close(fs, ff))
+    assert np.all(fid_close(ss["fid_pre"], sf["fid_pre"]))
+    for f in ("n_cand", "n_jumps", "first_jump_slice", "q_ground"):
+        assert np.array_equal(ss[f], sf[f]), f
+    assert np.all(ss["n_bad"] <= sf["n_bad"])
+    assert ss["n_explicit"].mean() < 0.8 * sf["n_explicit"].mean()
+    rng = np.random.default_rng(47)
+    idx = sorted(set([0, 1, nt - 1] + rng.choice(nt, 13, replace=False).tolist()))
+    nb, ref, nbw = subtree_classes(orc, n, k, gamma, seed, idx)
+    assert np.array_equal(ss["n_bad"][idx], nb)
+    assert np.array_equal(ss["ref_addr"][idx], ref)
+    assert np.array_equal(sf["n_bad"][idx], nbw)
+
+    def one(i):
+        f, fp, ri, _ = orc.run_batch(n, k, QUBIT, gamma, mem, seed, int(i), 1, nthreads=1)
+        return f[0]
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        fo = list(ex.map(one, idx))
+    assert np.all(fid_close(fs[idx], fo))

@@ -80,3 +80,33 @@ def test_expected_bad_branches(orc, n, k, gamma, enc):
         B.append(int(orc.classify(n, k, enc, L).sum()))
     B = np.array(B)
     assert abs(B.mean() - EB) < 5 * B.std() / np.sqrt(len(B)) + 1e-9
+
+
+@pytest.mark.parametrize("n,k,gamma", [(3, 3, 6e-3), (4, 2, 3e-3), (5, 1, 1.5e-3), (4, 1, 2e-2)])
+def test_subtree_marking_exact_under_damping(orc, n, k, gamma):
+    """Sec. III B and Sec. VI B: a damping jump needs an excitation and idle
+    qubits have none, so damping creates no strays and, in the qubit
+    encoding, the components a damping jump leaves alive all lie inside the
+    candidates' own subtrees (Eq. subtree), a subset of Eq. badrange.
+    Pruning with the tighter set is exact when no address outside it
+    survives any trajectory in which a jump fired (with no jump, every
+    component follows its no-jump orbit).  Checked on the full evolution of
+    sampled histories with random auxiliary draws."""
+    T = 6 * n + 2 * k
+    rng = np.random.default_rng(100 * n + k)
+    mem = rng.integers(0, 2**k, size=2**n)
+    fired = tighter = 0
+    for t in range(400):
+        L = orc.sample(n, k, gamma, 4242, t)
+        sub = orc.classify(n, k, QUBIT, L, subtree=True).astype(bool)
+        wide = orc.classify(n, k, QUBIT, L).astype(bool)
+        assert np.all(wide[sub])  # Eq. subtree marks a subset of Eq. badrange
+        r = orc.run_traj(n, k, QUBIT, gamma, mem, forced_L=L,
+                         forced_uaux=rng.random(T), export=True)
+        if r["njumps"] == 0:
+            continue
+        fired += 1
+        addrs = r["components"]["addr"]
+        assert np.all(sub[addrs]), (t, L)
+        tighter += int(np.any(wide & ~sub))
+    assert fired >= 20 and tighter >= 5, (fired, tighter)

@@ -1,5 +1,5 @@
 """Pins of the bucket-brigade schedule (Sec. II A, Eq. schedule and
-Eq. window; Eq. caddr; the injection counts of Sec. V B)."""
+Eq. window; Eq. caddr; the injection counts of Sec. VI B)."""
 import json
 import os
 
@@ -91,7 +91,7 @@ def _nonvacuous(orc, n, k, enc, mem):
 
 
 def test_injection_counts(orc):
-    """Sec. V B: at n = 3, k = 3 there are 14 positions x 23 slices = 322
+    """Sec. VI B: at n = 3, k = 3 there are 14 positions x 23 slices = 322
     damping cases, of which 178 are vacuous and 144 are not."""
     g = json.load(open(os.path.join(GOLDEN, "single_fault_injection.json")))
     n, k = g["n"], g["k"]
