@@ -142,3 +142,55 @@ def test_subtree_marking_full_size_sampled(lib, orc):
     with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
         fo = list(ex.map(one, idx))
     assert np.all(fid_close(fs[idx], fo))
+
+
+@pytest.mark.parametrize("n,k,gamma,ntraj", [(1, 1, 0.3, 300), (2, 2, 0.2, 300), (3, 2, 0.0, 50)])
+def test_subtree_marking_degenerate(lib, orc, n, k, gamma, ntraj):
+    """n <= 2 (every node is the root or one of its children, the terminal
+    cases of Eq. badrange, so both rules agree) and gamma = 0 (no
+    candidates: every address good, the reference is 0)."""
+    mem = memory_words(n, k, 2200 + n + k)
+    seed = 771000 + n
+    fo, _, so, _ = orc.run_batch(n, k, QUBIT, gamma, mem, seed, 0, ntraj)
+    nb, ref, nbw = subtree_classes(orc, n, k, gamma, seed, range(ntraj))
+    with lib.QramContext(n, k, QUBIT, gamma, mem) as ctx:
+        ctx.set_option(lib.qram.QRAM_OPT_SUBTREE_MARKING, 1)
+        for fn in (ctx.run_full, ctx.run_pruned):
+            f, st = fn(seed, 0, ntraj)
+            assert np.all(fid_close(f, fo))
+            assert np.array_equal(st["n_bad"], nb)
+            assert np.array_equal(st["ref_addr"], ref)
+    if n <= 2:
+        assert np.array_equal(nb, nbw)
+    if gamma == 0.0:
+        assert np.all(nb == 0) and np.all(ref == 0)
+
+
+@pytest.mark.parametrize("spt,sched", [(4, 0), (16, 1), (64, 3)])
+def test_subtree_marking_launch_shapes(lib, orc, spt, sched):
+    """Every launch shape gives the oracle's fidelities under the option."""
+    n, k, gamma, nt = 6, 2, 4e-3, 300
+    mem = memory_words(n, k, 2300)
+    seed = 772000 + spt
+    fo, _, so, _ = orc.run_batch(n, k, QUBIT, gamma, mem, seed, 0, nt)
+    with lib.QramContext(n, k, QUBIT, gamma, mem) as ctx:
+        ctx.set_option(lib.qram.QRAM_OPT_SUBTREE_MARKING, 1)
+        ctx.set_launch(PRUNED, spt, sched)
+        f, st = ctx.run_pruned(seed, 0, nt)
+    assert np.all(fid_close(f, fo))
+    assert np.array_equal(st["n_jumps"], so[:, 4].astype(np.uint16))
+
+
+def test_subtree_marking_graph_replays(lib):
+    """Graph mode under the option: every replay equals the eager run."""
+    n, k, gamma, nt = 8, 2, 4e-3, 2000
+    mem = memory_words(n, k, 2400)
+    with lib.QramContext(n, k, QUBIT, gamma, mem) as ctx:
+        ctx.set_option(lib.qram.QRAM_OPT_SUBTREE_MARKING, 1)
+        f0, s0 = ctx.run_pruned(7730, 0, nt)
+        ctx.set_option(lib.qram.QRAM_OPT_GRAPH, 1)
+        for _ in range(3):
+            f1, s1 = ctx.run_pruned(7730, 0, nt)
+            assert np.array_equal(f0, f1)
+            assert np.array_equal(s0, s1)
+        ctx.set_option(lib.qram.QRAM_OPT_GRAPH, 0)
