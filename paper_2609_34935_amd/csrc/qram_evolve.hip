@@ -1392,7 +1392,7 @@ __device__ __forceinline__ int nojump_walk_wave(const Tables *__restrict__ tb, c
 // the kernel
 // ---------------------------------------------------------------------------
 template <int ENC, bool SL>
-__global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdgpu_waves_per_eu(4))) k_evolve(const Tables *__restrict__ tb,
+__global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdgpu_waves_per_eu(ENC == QUBIT ? 4 : 5))) k_evolve(const Tables *__restrict__ tb,
                                                  const Run R_) {
   const Run *rp = &R_;
   extern __shared__ __align__(16) unsigned char smem[];
