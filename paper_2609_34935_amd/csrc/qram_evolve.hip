@@ -697,11 +697,17 @@ __device__ __forceinline__ uint32_t t2_step(const Tables *__restrict__ tb,
 constexpr int QK = 6;  // data tokens of the qubit encoding at most
 
 struct TokPos {
-  uint32_t p[QK / 2];  // two 16-bit sites per register
-  __device__ __forceinline__ uint32_t get(int t) const { return (p[t >> 1] >> ((t & 1) * 16)) & 0xFFFFu; }
+  // two 16-bit sites per register; a runtime token number selects among the
+  // registers (no indexed array, which would live in scratch memory)
+  uint32_t p[QK / 2];
+  __device__ __forceinline__ uint32_t word(int t) const { return t < 2 ? p[0] : (t < 4 ? p[1] : p[2]); }
+  __device__ __forceinline__ uint32_t get(int t) const { return (word(t) >> ((t & 1) * 16)) & 0xFFFFu; }
   __device__ __forceinline__ void set(int t, uint32_t x) {
     const int sh = (t & 1) * 16;
-    p[t >> 1] = (p[t >> 1] & ~(0xFFFFu << sh)) | (x << sh);
+    const uint32_t w = (word(t) & ~(0xFFFFu << sh)) | (x << sh);
+    p[0] = t < 2 ? w : p[0];
+    p[1] = (t >= 2 && t < 4) ? w : p[1];
+    p[2] = t >= 4 ? w : p[2];
   }
   __device__ __forceinline__ void load(const uint16_t *r, int k) {
 #pragma unroll
