@@ -1606,11 +1606,21 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
       // (each thread's next entry is fetched one iteration ahead)
       if (ENC == QUBIT && ndev > 0 && tb->store_l[s] >= 0 && !slow_all) {
         // before a store: the classes that would store a tagged token into a
-        // router split on it (each address's first class does it for all)
+        // router split on it.  The address's first class entry does it for
+        // all its classes, and only that thread reads or writes the
+        // address's split set and records here.  The work list holds an
+        // address's class entries together and in ascending class order, and
+        // nothing writes it here, so the first entry is found from the list
+        // alone: a decision taken from the split set could see it change
+        // under another thread's split and split the address twice.
         for (uint32_t i = tid; i < ndev; i += nthr) {
           const uint32_t d = devl[i];
           if (!(d >> 31)) continue;
-          const uint32_t cg = d & 0xFFFFu, g = cg >> kb, c = cg & (uint32_t)(K2 - 1);
+          const uint32_t cg = d & 0xFFFFu, g = cg >> kb;
+          if (i > 0) {
+            const uint32_t dp = devl[i - 1];
+            if ((dp >> 31) && ((dp & 0xFFFFu) >> kb) == g) continue;
+          }
           const uint32_t ow = g / apt, al = g - ow * apt, wbase = al * K2 * nthr + ow;
           uint16_t *r0 = pool + (size_t)g * K2 * rec;
           const uint32_t D = r0[2 + tb->lmax + tb->k];
@@ -1620,7 +1630,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
             if ((w & W_ALIVE) && !(w & W_SPLIT)) cm |= 1ull << b;
           }
           const uint64_t cl = class_mask(cm, D);
-          if (!cl || c != (uint32_t)__ffsll((unsigned long long)cl) - 1u) continue;
+          if (!cl) continue;
           const uint32_t X = class_store_tokens(tb, s, r0, rec, cl);
           if (X) {
             t2_class_split(tb, r0, rec, cl, D, X, rp->err);

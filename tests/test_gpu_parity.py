@@ -374,3 +374,19 @@ def test_forced_router_jump_with_data_in_tree_qubit(lib, orc, s, site):
     mem = memory_words(n, k, 7)
     L = [(s - 1) * M + site]
     forced_case(lib, orc, n, k, QUBIT, 0.05, mem, L, np.full(T, 0.99999), 0.5)
+
+
+@pytest.mark.parametrize("n,k,gamma,nt,seed", [(6, 6, 3e-2, 1500, 5454), (5, 5, 4e-2, 2000, 5555)])
+def test_qubit_many_classes_pre_splits(lib, orc, n, k, gamma, nt, seed):
+    """Regression: addresses with many classes whose work-list entries span
+    wave boundaries, split again before a store.  One thread per address takes
+    the split (the others must not read the split set while it changes).
+    Fidelities and statistics against the oracle, and bitwise against one
+    global-memory list per component."""
+    mem = memory_words(n, k, 700 + n + k)
+    out, _ = compare_runs(lib, orc, n, k, QUBIT, gamma, mem, seed, 0, nt)
+    with lib.QramContext(n, k, QUBIT, gamma, mem) as ctx:
+        ctx.set_option(lib.qram.QRAM_OPT_TIER2_GLOBAL, 1)
+        fg, sg = ctx.run_pruned(seed, 0, nt)
+    assert np.array_equal(out[PRUNED][0], fg)
+    assert np.array_equal(out[PRUNED][1], sg)
