@@ -131,7 +131,8 @@ __global__ void __launch_bounds__(256) k_classify(const Tables *__restrict__ tb,
   const int nw32 = (D + 31) >> 5;
   uint32_t *badw = reinterpret_cast<uint32_t *>(smem);  // [nw32]
   uint32_t *sbuf = badw + nw32;                         // [16]
-  uint8_t *mark = reinterpret_cast<uint8_t *>(sbuf + 16);  // [D - 1]
+  uint32_t *wpos = sbuf + 16;                           // [nw32]
+  uint8_t *mark = reinterpret_cast<uint8_t *>(wpos + nw32);  // [D - 1]
   const uint32_t cap = rp->cand_cap;
   const int kb = enc == QUBIT ? tb->k : 0;
   for (uint32_t tj = blockIdx.x; tj < rp->ntraj; tj += gridDim.x) {
@@ -193,15 +194,22 @@ __global__ void __launch_bounds__(256) k_classify(const Tables *__restrict__ tb,
       }
       uint32_t tot;
       uint32_t o = block_excl_scan_u32(c, sbuf, &tot);
-      uint16_t *xl = rp->xlist + (size_t)tj * D;
+      // first list position of each bitmap word; then every address writes
+      // its own entry (position = its word's offset + the set bits below it)
       for (int w = w0; w < w1; ++w) {
         uint32_t f = badw[w];
         if (ref != 0xFFFFFFFFu && (ref >> 5) == (uint32_t)w) f |= 1u << (ref & 31);
-        while (f) {
-          const int l = __ffs(f) - 1;
-          f &= f - 1;
-          xl[o++] = (uint16_t)(32 * w + l);
-        }
+        wpos[w] = o;
+        o += __popc(f);
+      }
+      __syncthreads();
+      uint16_t *xl = rp->xlist + (size_t)tj * D;
+      for (int i = tid; i < D; i += nthr) {
+        const int w = i >> 5;
+        uint32_t f = badw[w];
+        if (ref != 0xFFFFFFFFu && (ref >> 5) == (uint32_t)w) f |= 1u << (ref & 31);
+        const uint32_t below = f & ((1u << (i & 31)) - 1u);
+        if ((f >> (i & 31)) & 1u) xl[wpos[w] + (uint32_t)__popc(below)] = (uint16_t)i;
       }
       nex = tot << kb;
     } else {
@@ -292,7 +300,7 @@ hipError_t launch_sample(const Tables *tb, const Run &rp, uint32_t ntraj,
 hipError_t launch_classify(const Tables *tb, const Run &rp, uint32_t ntraj,
                            uint32_t grid, int D, bool subtree, hipStream_t s) {
   (void)ntraj;
-  const size_t lds = (size_t)((D + 31) / 32) * 4 + 16 * 4 + (size_t)D;
+  const size_t lds = (size_t)((D + 31) / 32) * 8 + 16 * 4 + (size_t)D;
   hipLaunchKernelGGL(k_classify, dim3(grid), dim3(256), lds, s, tb, rp, subtree ? 1u : 0u);
   return hipGetLastError();
 }
