@@ -82,10 +82,20 @@ def cpu_baseline(mem, n_qubit, n_qutrit):
         per[enc] = (time.perf_counter() - t0, cnt)
     # one step holds as many qubit as qutrit trajectories
     t_pair = per[1][0] / per[1][1] + per[0][0] / per[0][1]
+    # the same oracle on one thread (the paper's simulator is single-threaded)
+    one = {}
+    for enc, cnt in ((1, max(1, n_qubit // 16)), (0, max(1, n_qutrit // 16))):
+        t0 = time.perf_counter()
+        O.run_batch(N, K, enc, GAMMA, mem, 880000 + CFG_ID, 0, cnt, nthreads=1)
+        one[enc] = (time.perf_counter() - t0, cnt)
+    t_one = one[1][0] / one[1][1] + one[0][0] / one[0][1]
     return {"value": round(2.0 / t_pair, 2), "unit": "trajectories/s", "cores": used, "kind": "oracle",
             "sample": f"first {per[1][1]} qubit and {per[0][1]} qutrit trajectories of the step's workload "
                       f"({per[1][0]:.1f} s and {per[0][0]:.1f} s wall on {used} threads), full evolution of "
-                      "every branch on the host; value = 2 / (mean qubit + mean qutrit time per trajectory)"}
+                      "every branch on the host; value = 2 / (mean qubit + mean qutrit time per trajectory)",
+            "single_thread": {"value": round(2.0 / t_one, 2), "unit": "trajectories/s",
+                              "sample": f"first {one[1][1]} qubit and {one[0][1]} qutrit trajectories on one "
+                                        f"thread ({one[1][0]:.1f} s and {one[0][0]:.1f} s)"}}
 
 
 def _serve_once(P, reqs, mems, arrivals, chunk, max_active, budget_gib, tag):
