@@ -88,3 +88,16 @@ def test_memory_generator_deterministic():
     assert a.shape == (1024,) and a.max() < 16
     assert np.array_equal(a, memory_words(10, 4, 1003))
     assert abs(((a[:, None] >> np.arange(4)) & 1).mean() - 0.5) < 0.03
+
+
+def test_option_constants_match_header():
+    """The binding's option numbers are the header's, and a null context is
+    rejected without touching the device."""
+    from paper_2609_34935_amd import qram
+    text = open(HEADER).read()
+    opts = dict((k, int(v)) for k, v in re.findall(r"\b(QRAM_OPT_[A-Z0-9_]+)\s*=\s*(\d+)", text))
+    assert opts == {"QRAM_OPT_TIER2_GLOBAL": 1, "QRAM_OPT_GRAPH": 2, "QRAM_OPT_SUBTREE_MARKING": 3}
+    for name, value in opts.items():
+        assert getattr(qram, name) == value
+    L = qram.load_library()
+    assert qram.STATUS[L.qram_set_option(None, opts["QRAM_OPT_SUBTREE_MARKING"], 1)] == "QRAM_E_INVAL"
