@@ -1641,6 +1641,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
         if (sm.misc[5] == s) devl_qubit();
       }
       uint32_t dnext = tid < ndev ? devl[tid] : 0u;
+      bool t2hit = false;  // a component this thread stepped is hit
       for (uint32_t i = tid; i < ndev; i += nthr) {
         const uint32_t d = dnext;
         if (i + nthr < ndev) dnext = devl[i + nthr];
@@ -1682,6 +1683,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
                 const uint32_t cb = cnt + (uint32_t)__popc(live & intree);
                 const bool flip = fall ^ (bool)(__popc(ftok & live) & 1);
                 const bool hit = hall || (htok & live);
+                t2hit |= hit;
                 // after the last slice a ground component keeps its bus word in the count field
                 const uint32_t cf = (s == T - 1 && cb == 0) ? (W_FBUS | ((busm & (~toks | b)) << W_CNT_SH)) : (cb << W_CNT_SH);
                 st[widx] = ((w & W_SIGN) ^ (flip ? W_SIGN : 0u)) | (w & (W_ALIVE | W_DEV)) | e | cf | (hit ? W_HIT : 0u);
@@ -1703,17 +1705,20 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
           uint32_t bus;
           const uint32_t cnt = t2_step<ENC>(tb, s, pool + (size_t)c * rec, cnt0, a, w, slow_all, big, nc,
                                             cd, sm.cbm, hit, bus, rp->err);
+          t2hit |= hit;
           // after the last slice a ground list keeps its bus word in the count field
           const uint32_t cf = (s == T - 1 && cnt == 0) ? (W_FBUS | (bus << W_CNT_SH)) : (cnt << W_CNT_SH);
           st[widx] = (w & (W_SIGN | W_ALIVE | W_DEV | W_SPLIT)) | e | cf | (hit ? W_HIT : 0u);
         }
       }
-      if (ENC == QUBIT && ndev > 0) {
-        __syncthreads();
-        if (sm.misc[4] == s) devl_qubit();  // a class split: spread its components over the block
-      }
       QR_TM(7);
-      if (nc == 0) continue;
+      if (nc == 0) {  // nothing to draw: only the qubit pass's barrier (and a work-list rebuild)
+        if (ENC == QUBIT && ndev > 0) {
+          __syncthreads();
+          if (sm.misc[4] == s) devl_qubit();  // a class split: spread its components
+        }
+        continue;
+      }
       if (ndev == 0 && !big) {
         // a tier-1 component is excited only where the schedule puts one of
         // its tokens: candidates on token-free sites hit nothing
@@ -1721,9 +1726,10 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
         for (int c = 0; c < nc; ++c) maybe |= ((cd[c] >> 20) & 0xFFu) != NONE;
         if (!maybe) continue;
       }
-      if (ENC == QUTRIT && ndev > 0) __syncthreads();  // (qubit: after the tier-2 pass above)
 
-      // owner pass: which of my components does a candidate hit?
+      // owner pass: which of my components does a candidate hit?  The tier-1
+      // tests read only this thread's own words and run before the barrier
+      // that ends the tier-2 pass; that barrier also collects the hits.
       uint64_t hmask = 0;
       if (njumps == 0) {
         // no jump so far: every component still has its initial label, so
@@ -1744,10 +1750,6 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
           hmask |= m << (al * K2);
         }
       } else {
-        for (uint64_t m = devm; m; m &= m - 1) {  // tier 2: hit flags from the tier-2 pass
-          const int j = __ffsll((unsigned long long)m) - 1;
-          if (st[j * nthr + tid] & W_HIT) hmask |= 1ull << j;
-        }
         int cur = -1;
         uint32_t memw = 0, dh = 0;
         bool ah = false;
@@ -1767,7 +1769,12 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
           if (ah || (df & dh)) hmask |= 1ull << j;
         }
       }
-      const bool any_hit = __syncthreads_or(hmask != 0ull);
+      const bool any_hit = __syncthreads_or(hmask != 0ull || t2hit);
+      if (ENC == QUBIT && ndev > 0 && sm.misc[4] == s) devl_qubit();  // a class split in the pass
+      for (uint64_t m = devm; m; m &= m - 1) {  // tier 2: hit flags from the tier-2 pass
+        const int j = __ffsll((unsigned long long)m) - 1;
+        if (st[j * nthr + tid] & W_HIT) hmask |= 1ull << j;
+      }
       QR_TM(2);
       if (!any_hit) continue;  // J is empty
 
