@@ -1856,12 +1856,11 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
 
       // auxiliary component x*: the empty-mask block first, then the other
       // components in slot order (initial-label order)
-      const double excl = block_excl_scan(my_hit_w, sm.scanb);
-      if (tid == 0) {
+      if (tid == 0) {  // (published by the scan's barrier)
         sm.misc[1] = -1;
         sm.misc[2] = 0;
       }
-      __syncthreads();
+      const double excl = block_excl_scan(my_hit_w, sm.scanb);
       if (my_hit_w > 0.0 && excl <= r2) atomicMax(&sm.misc[1], tid);
       __syncthreads();
       if (sm.misc[1] == tid) {
