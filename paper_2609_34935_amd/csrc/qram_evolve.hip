@@ -847,7 +847,7 @@ __device__ __forceinline__ bool t2_shared_reg(const Tables *__restrict__ tb, int
                                               const uint32_t *cdec, const uint32_t *cbm,
                                               uint32_t &cnt, uint32_t &busf, bool &flip_all,
                                               uint32_t &flip_tok, bool &hit_all, uint32_t &hit_tok,
-                                              uint32_t *err) {
+                                              bool &split_next, uint32_t *err) {
   const int k = tb->k;
   RList<QUBIT, C> L;
   L.load(recp, cnt0);
@@ -886,6 +886,18 @@ __device__ __forceinline__ bool t2_shared_reg(const Tables *__restrict__ tb, int
   cnt = L.dirty ? L.store(recp) : cnt0;
   if (moved) tp.store(recp + 2 + tb->lmax, k);
   busf = L.bus;
+  // a tagged token on the store layer of the next slice: the class must be
+  // split before that store
+  split_next = false;
+  if (s + 1 < tb->T && tb->store_l[s + 1] >= 0) {
+    const int nsl = tb->store_l[s + 1];
+    const uint32_t toks = (L.bus >> 8) & 0xFFu;
+#pragma unroll
+    for (int t = 0; t < QK; ++t) {
+      const uint32_t x = tp.get(t);
+      if (((toks >> t) & 1u) && x != EMPTY && layer_of(x >> 1) == nsl) split_next = true;
+    }
+  }
   return true;
 }
 
@@ -1484,6 +1496,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
     if (tid == 0) {  // work-list rebuild requests: tagged with their slice
       sm.misc[4] = 0;
       sm.misc[5] = 0;
+      sm.misc[6] = 0;
     }
     // initial components: data-loading input after the first wall; the sign
     // already holds every fetch phase its live tokens will pick up
@@ -1604,9 +1617,10 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
       // tier-2 pass: the listed components (qubit: addresses) follow the
       // gates of slice s literally, spread over all threads of the block
       // (each thread's next entry is fetched one iteration ahead)
-      if (ENC == QUBIT && ndev > 0 && tb->store_l[s] >= 0 && !slow_all) {
+      if (ENC == QUBIT && ndev > 0 && tb->store_l[s] >= 0 && !slow_all && sm.misc[6] == s) {
         // before a store: the classes that would store a tagged token into a
-        // router split on it.  The address's first class entry does it for
+        // router split on it (only when a class update or a new list of the
+        // previous slice saw such a token: a jump only ever removes tokens).  The address's first class entry does it for
         // all its classes, and only that thread reads or writes the
         // address's split set and records here.  The work list holds an
         // address's class entries together and in ascending class order, and
@@ -1665,9 +1679,11 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
             uint16_t *recp = r0 + (size_t)c * rec;
             const uint32_t cnt0 = recp[0];
             uint32_t cnt = 0, busf = 0, ftok = 0, htok = 0;
-            bool fall = false, hall = false, ok = false;
+            bool fall = false, hall = false, ok = false, split_next = false;
             if (!slow_all && cnt0 + 2 <= 16)  // (a longer shared list splits)
-              ok = t2_shared_reg<16>(tb, s, recp, cnt0, a, big, nc, cd, sm.cbm, cnt, busf, fall, ftok, hall, htok, rp->err);
+              ok = t2_shared_reg<16>(tb, s, recp, cnt0, a, big, nc, cd, sm.cbm, cnt, busf, fall, ftok, hall, htok,
+                                     split_next, rp->err);
+            if (ok && split_next) sm.misc[6] = s + 1;  // the next slice runs the pre-split
             if (!ok) {  // one list per member from here on; they take this slice below
               t2_split_class(tb, r0, rec, c, mc, st, wbase, nthr, rp->err);
               stepm = mc;  // (bits: bus words of the address)
@@ -2074,10 +2090,12 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
                   else
                     ovf = true;
                 }
+                const int nsl = s + 1 < T ? tb->store_l[s + 1] : -1;
                 for (int bb = 0; bb < tb->k; ++bb) {
                   const int q = ((toks >> bb) & 1u) ? t1_site(tb, s, a, n + bb) : -1;
                   if (((toks >> bb) & 1u) && q < 0) busm |= 1u << bb;  // not yet in, or already back on the bus
                   rs[2 + tb->lmax + bb] = (uint16_t)(q >= 0 ? (uint32_t)q : EMPTY);
+                  if (q >= 0 && nsl >= 0 && layer_of((uint32_t)q >> 1) == nsl) sm.misc[6] = s + 1;
                 }
                 if (ovf) atomicOr(rp->err, ERR_LIST);
                 rs[0] = (uint16_t)caddr;
