@@ -22,6 +22,7 @@
 // (1-gamma)^e.  Per slice the kernel tests the slice's candidates against
 // every component; weights are formed only when some component is hit.
 #include "qram_device.h"
+#include "qram_records.h"
 
 #include <algorithm>
 
@@ -192,6 +193,14 @@ struct Rec {
   uint16_t *r;
   static constexpr uint32_t SM = ENC == QUTRIT ? 0x7FFFu : 0xFFFFu;
   __device__ __forceinline__ int cnt() const { return r[0]; }
+  // a count read back from the pool is trusted up to lmax only
+  __device__ __forceinline__ Rec &bound(int lmax, uint32_t *err) {
+    if (r[0] > (uint32_t)lmax) {
+      flag_err(err, ERR_LIST);
+      r[0] = (uint16_t)lmax;
+    }
+    return *this;
+  }
   __device__ __forceinline__ uint32_t raw(int j) const { return r[2 + j]; }
   __device__ __forceinline__ uint32_t site(int j) const { return r[2 + j] & SM; }
   __device__ __forceinline__ int find_site(uint32_t q) const {
@@ -393,11 +402,16 @@ struct RList {
       p[j >> 1] = lo | (hi << 16);
     }
   }
-  __device__ __forceinline__ uint32_t store(uint16_t *rec) const {
+  // writes at most lim entries (the record's capacity); more raise ovf
+  __device__ __forceinline__ uint32_t store(uint16_t *rec, uint32_t lim, bool &ovf) const {
     if (!holes) {  // entries 0 .. cnt-1, empty after: whole words
       uint32_t cnt = 0;
 #pragma unroll
       for (int j = 0; j < C; ++j) cnt += get(j) != EMPTY ? 1u : 0u;
+      if (cnt > lim) {
+        ovf = true;
+        cnt = lim;
+      }
       uint32_t *r32 = reinterpret_cast<uint32_t *>(rec);
 #pragma unroll
       for (int j = 0; j < C; j += 2) {
@@ -414,8 +428,10 @@ struct RList {
     for (int j = 0; j < C; ++j) {
       const uint32_t x = get(j);
       if (x != EMPTY) {
-        rec[2 + pos] = (uint16_t)x;
-        ++pos;
+        if (pos < lim)
+          rec[2 + pos++] = (uint16_t)x;
+        else
+          ovf = true;
       }
     }
     rec[0] = (uint16_t)pos;
@@ -654,17 +670,18 @@ __device__ __forceinline__ uint32_t t2_step(const Tables *__restrict__ tb,
     L.load(recp, cnt0);
     t2_gates_reg<ENC, C1>(tb, s, L, a, word, ovf);
     if (nc > 0) hit = L.hit(big, nc, cdec, cbm);
-    cnt = L.dirty ? L.store(recp) : cnt0;
+    cnt = L.dirty ? L.store(recp, (uint32_t)tb->lmax, ovf) : cnt0;
     bus = L.bus;
   } else if (!slow && cnt0 + grow <= C2) {
     RList<ENC, C2> L;
     L.load(recp, cnt0);
     t2_gates_reg<ENC, C2>(tb, s, L, a, word, ovf);
     if (nc > 0) hit = L.hit(big, nc, cdec, cbm);
-    cnt = L.dirty ? L.store(recp) : cnt0;
+    cnt = L.dirty ? L.store(recp, (uint32_t)tb->lmax, ovf) : cnt0;
     bus = L.bus;
   } else {
     Rec<ENC> R{recp};
+    R.bound(tb->lmax, err);
     word ^= t2_gates_mem<ENC>(tb, s, R, a, err);
     cnt = R.cnt();
     bus = R.r[1];
@@ -883,7 +900,9 @@ __device__ __forceinline__ bool t2_shared_reg(const Tables *__restrict__ tb, int
       }
     }
   }
-  cnt = L.dirty ? L.store(recp) : cnt0;
+  bool sovf = false;
+  cnt = L.dirty ? L.store(recp, (uint32_t)tb->lmax, sovf) : cnt0;
+  if (sovf) atomicOr(err, ERR_LIST);
   if (moved) tp.store(recp + 2 + tb->lmax, k);
   busf = L.bus;
   // a tagged token on the store layer of the next slice: the class must be
@@ -901,13 +920,6 @@ __device__ __forceinline__ bool t2_shared_reg(const Tables *__restrict__ tb, int
   return true;
 }
 
-// Classes (subsets of D) that hold members: bit c set.
-__device__ __forceinline__ uint64_t class_mask(uint64_t members, uint32_t D) {
-  uint64_t cl = 0;
-  for (uint64_t m = members; m; m &= m - 1) cl |= 1ull << ((uint32_t)(__ffsll((unsigned long long)m) - 1) & D);
-  return cl;
-}
-
 // Tagged tokens that the store of slice s would move into a router, over
 // the classes cl of the address whose class-0 record is r0.
 __device__ __forceinline__ uint32_t class_store_tokens(const Tables *__restrict__ tb, int s,
@@ -923,77 +935,6 @@ __device__ __forceinline__ uint32_t class_store_tokens(const Tables *__restrict_
     }
   }
   return X;
-}
-
-// Split every class cl of the address (split set D) on the tagged tokens X:
-// class c gives c | y for every nonempty y within X (the tokens of y untagged
-// and kept, those of X \ y dropped) and keeps c (the tokens of X dropped).
-// The new split set D | X is written to the class-0 slot.
-__device__ __forceinline__ void t2_class_split(const Tables *__restrict__ tb, uint16_t *r0, int rec,
-                                               uint64_t cl, uint32_t D, uint32_t X, uint32_t *err) {
-  const int k = tb->k, lmax = tb->lmax;
-  for (uint64_t m = cl; m; m &= m - 1) {
-    const uint32_t c = (uint32_t)__ffsll((unsigned long long)m) - 1u;
-    uint16_t *rc = r0 + (size_t)c * rec;
-    const uint32_t cnt = rc[0], busf = rc[1], toks = (busf >> 8) & 0xFFu, busm = busf & 0xFFu;
-    for (uint32_t y = X; y; y = (y - 1) & X) {
-      uint16_t *rn = r0 + (size_t)(c | y) * rec;
-      uint32_t m2 = cnt;
-      for (uint32_t j = 0; j < cnt; ++j) rn[2 + j] = rc[2 + j];
-      for (int t = 0; t < k; ++t) {
-        const uint32_t x = rc[2 + lmax + t];
-        if (((y & toks) >> t) & 1u && x != EMPTY) {  // kept: an ordinary entry now
-          if (m2 < (uint32_t)lmax)
-            rn[2 + m2++] = (uint16_t)x;
-          else
-            atomicOr(err, ERR_LIST);
-        }
-        rn[2 + lmax + t] = ((X >> t) & 1u) ? (uint16_t)EMPTY : (uint16_t)x;
-      }
-      rn[0] = (uint16_t)m2;
-      rn[1] = (uint16_t)((busm & ~(X & ~y)) | ((toks & ~X) << 8));
-      rn[2 + lmax + k] = (uint16_t)(D | X);
-    }
-    for (int t = 0; t < k; ++t)
-      if ((X >> t) & 1u) rc[2 + lmax + t] = (uint16_t)EMPTY;
-    rc[1] = (uint16_t)((busm & ~X) | ((toks & ~X) << 8));
-    rc[2 + lmax + k] = (uint16_t)(D | X);
-  }
-  r0[2 + lmax + k] = (uint16_t)(D | X);
-}
-
-// Turn the members mc of class c (split set D) into one ordinary list per
-// component, from the class's list as after slice s-1; marks their words.
-__device__ __forceinline__ void t2_split_class(const Tables *__restrict__ tb, uint16_t *r0, int rec,
-                                               uint32_t c, uint64_t mc, uint32_t *st, uint32_t wbase,
-                                               uint32_t nthr, uint32_t *err) {
-  const int k = tb->k, lmax = tb->lmax;
-  uint16_t *rs = r0 + (size_t)c * rec;
-  const uint32_t cnt = rs[0], busf = rs[1], toks = (busf >> 8) & 0xFFu, busm = busf & 0xFFu;
-  TokPos tp;
-  tp.load(rs + 2 + lmax, k);
-  for (int pass = 0; pass < 2; ++pass) {  // the class's own slot (bus word c) last
-    for (uint64_t m = mc; m; m &= m - 1) {
-      const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1u;
-      if ((b == c) != (pass == 1)) continue;
-      uint16_t *rb = r0 + (size_t)b * rec;
-      if (b != c)
-        for (uint32_t j = 0; j < cnt; ++j) rb[2 + j] = rs[2 + j];
-      const uint32_t live = b & toks;
-      uint32_t m2 = cnt;
-      for (int t = 0; t < k; ++t) {
-        const uint32_t x = tp.get(t);
-        if (!((live >> t) & 1u) || x == EMPTY) continue;
-        if (m2 < (uint32_t)lmax)
-          rb[2 + m2++] = (uint16_t)x;
-        else
-          atomicOr(err, ERR_LIST);
-      }
-      rb[0] = (uint16_t)m2;
-      rb[1] = (uint16_t)(busm & (~toks | b));
-      st[wbase + b * nthr] |= W_SPLIT;
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1647,7 +1588,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
           if (!cl) continue;
           const uint32_t X = class_store_tokens(tb, s, r0, rec, cl);
           if (X) {
-            t2_class_split(tb, r0, rec, cl, D, X, rp->err);
+            rec_class_split(r0, rec, tb->k, tb->lmax, cl, D, X, rp->err);
             sm.misc[5] = s;  // the work list is rebuilt before the pass
           }
         }
@@ -1677,7 +1618,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
           stepm = 0;
           if (mc) {
             uint16_t *recp = r0 + (size_t)c * rec;
-            const uint32_t cnt0 = recp[0];
+            const uint32_t cnt0 = rec_count(recp[0], tb->lmax, rp->err);
             uint32_t cnt = 0, busf = 0, ftok = 0, htok = 0;
             bool fall = false, hall = false, ok = false, split_next = false;
             if (!slow_all && cnt0 + 2 <= 16)  // (a longer shared list splits)
@@ -1685,7 +1626,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
                                      split_next, rp->err);
             if (ok && split_next) sm.misc[6] = s + 1;  // the next slice runs the pre-split
             if (!ok) {  // one list per member from here on; they take this slice below
-              t2_split_class(tb, r0, rec, c, mc, st, wbase, nthr, rp->err);
+              rec_split_class(r0, rec, tb->k, tb->lmax, c, mc, st, wbase, nthr, rp->err);
               stepm = mc;  // (bits: bus words of the address)
               sm.misc[4] = s;  // the work list is rebuilt after the pass
             } else {
@@ -1936,7 +1877,8 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
           const uint16_t *r0 = pool + (size_t)g * K2 * rec;
           const uint16_t *rs = r0 + (size_t)(b & r0[2 + tb->lmax + tb->k]) * rec;
           const uint32_t live = b & ((uint32_t)rs[1] >> 8);
-          for (uint32_t c = 0; c < (uint32_t)rs[0]; ++c) {
+          const uint32_t nrs = rec_count(rs[0], tb->lmax, rp->err);
+          for (uint32_t c = 0; c < nrs; ++c) {
             const uint32_t q = rs[2 + c];
             if ((big ? cand_bm(sm.cbm, q) : cand_list(cd, nc, q)) && nJ < JMAX) sm.Jb[nJ++] = q | (1u << 16);
           }
@@ -1947,6 +1889,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
           }
         } else {
           Rec<ENC> R{pool + (size_t)(g * K2 + b) * rec};
+          R.bound(tb->lmax, rp->err);
           for (int c = 0; c < R.cnt(); ++c) {
             const uint32_t x = R.raw(c), q = x & Rec<ENC>::SM;
             const bool isc = big ? cand_bm(sm.cbm, q) : cand_list(cd, nc, q);
@@ -1990,6 +1933,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
               const uint32_t c = (uint32_t)__ffsll((unsigned long long)mm) - 1u;
               uint16_t *rs = r0 + (size_t)c * rec;
               Rec<ENC> R{rs};
+              R.bound(lmax, rp->err);
               const uint32_t busf = rs[1], toks = (busf >> 8) & 0xFFu;
               bool okA = true;
               uint32_t need = 0;
@@ -2235,6 +2179,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
             }
           } else {
             Rec<ENC> R{recp};
+            R.bound(tb->lmax, rp->err);
             bool ok = true;
             for (int c = 0; c < nJ && ok; ++c) {
               const uint32_t x = sm.Jb[c], q = x & 0xFFFFu;
