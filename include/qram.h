@@ -256,6 +256,33 @@ qram_status qram_reserve(qram_ctx *ctx, qram_mode mode, uint32_t ntraj);
 qram_status qram_errors(qram_ctx *ctx);
 
 /*
+ * qram_run_pruned_async with no device allocation, for callers that cannot
+ * allocate: work enqueued under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, outputs and results as
+ * qram_run_pruned_async (d_fid [ntraj] and d_st [ntraj] or NULL are the
+ * caller's device buffers; the work is enqueued on `stream` and the call
+ * returns without waiting).  The work buffers (candidate lists, bad
+ * bitmaps, explicit lists, queues, tier-2 pools) live in one static device
+ * array of 64 MiB per device, held until the process ends; the call itself
+ * allocates nothing (no hipMalloc, no events, no graphs), and the context
+ * must already exist.  Trajectories run in batches that fit the array, and
+ * the evolution launches use at most as many workgroups as the array's
+ * per-workgroup pools allow, so large configurations run with fewer
+ * workgroups in flight than qram_run_pruned_async.  Returns
+ * QRAM_E_CAPACITY when a single workgroup's buffers do not fit the array
+ * (no supported configuration reaches this), QRAM_E_DEVICE when the array
+ * has no address on the context's device.  Every call on one device
+ * shares that device's array and its contents persist between calls:
+ * calls that overlap on one device (other streams, other host threads,
+ * other contexts) race and must be ordered by the caller.  The array's
+ * error word is cleared at the start of each call; qram_errors reports a
+ * capacity overflow of the last call once its stream has been waited for.
+ */
+qram_status qram_run_pruned_async_noalloc(qram_ctx *ctx, uint64_t seed, uint64_t traj0,
+                                          uint32_t ntraj, double *d_fid,
+                                          qram_traj_stats *d_st, void *stream);
+
+/*
  * Request server: continuous batching of simulation requests on the current
  * device.  A host thread owns one context per admitted request.  Requests
  * are admitted in arrival order as soon as an execution slot is free

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -86,7 +87,54 @@ struct qram_ctx {
   std::vector<hipEvent_t> tev;
   size_t tev_used = 0;
   uint32_t tev_launches = 0;  // evolution launches inside the timed batches
+  // device address of this device's no-allocation scratch array (null if
+  // it could not be resolved), and whether a no-allocation run used it
+  unsigned char *scratch = nullptr;
+  bool scratch_used = false;
 };
+
+// ---------------------------------------------------------------------------
+// No-allocation runs.  Callers that cannot allocate device memory (work
+// under graph capture, tight serving loops) run through
+// qram_run_pruned_async_noalloc, whose work buffers live in this static
+// array instead of context-owned allocations.  Each device holds its own
+// copy until the process ends.  In host code the array's name is only a
+// stand-in: its device address on each device comes from
+// hipGetSymbolAddress, taken once per device in qram_create with that
+// device current, and only that address is handed to kernels and copies.
+// ---------------------------------------------------------------------------
+constexpr size_t SCRATCH_BYTES = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+struct ScratchDev {
+  std::once_flag once;
+  void *ptr = nullptr;
+  hipError_t err = hipSuccess;
+};
+ScratchDev g_scratch[SCRATCH_MAX_DEVICES];
+
+// The scratch array's address on `device`, which must be current.
+unsigned char *scratch_address(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return nullptr;
+  ScratchDev &d = g_scratch[device];
+  std::call_once(d.once, [&d] {
+    void *p = nullptr;
+    d.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (d.err == hipSuccess)
+      d.ptr = p;
+    else
+      (void)hipGetLastError();
+  });
+  return static_cast<unsigned char *>(d.ptr);
+}
+
+// Fixed header of the scratch array: error word, queue heads, bucket bases.
+constexpr size_t SCR_ERR = 0, SCR_COUNTER = 256, SCR_BBASE = 512, SCR_HEAD = 1024;
+
+}  // namespace
 
 namespace {
 
@@ -687,6 +735,7 @@ qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return bail(fail(c, QRAM_E_DEVICE, "hipGetDeviceProperties failed"));
   c->num_cu = prop.multiProcessorCount;
+  c->scratch = scratch_address(c->device);
   int dyn = 0;
   if (evolve_prepare((int)prop.sharedMemPerBlock, &dyn) == hipSuccess) {
     c->lds_max = (size_t)dyn;  // dynamic shared memory an evolution launch may take
@@ -919,8 +968,106 @@ qram_status qram_reserve(qram_ctx *c, qram_mode mode, uint32_t ntraj) {
 qram_status qram_errors(qram_ctx *c) {
   if (!c) return QRAM_E_INVAL;
   HIPCHK(c, hipSetDevice(c->device));
+  if (c->scratch_used && c->scratch) {
+    uint32_t e = 0;
+    HIPCHK(c, hipMemcpy(&e, c->scratch + SCR_ERR, 4, hipMemcpyDeviceToHost));
+    if (e) {
+      const uint32_t z = 0;
+      HIPCHK(c, hipMemcpy(c->scratch + SCR_ERR, &z, 4, hipMemcpyHostToDevice));
+      if (e & ERR_CAND) return fail(c, QRAM_E_CAPACITY, "candidate buffer overflow");
+      if (e & ERR_LIST) return fail(c, QRAM_E_CAPACITY, "explicit site list overflow");
+    }
+  }
   if (!c->errw) return QRAM_OK;
   return check_err(c);
+}
+
+qram_status qram_run_pruned_async_noalloc(qram_ctx *c, uint64_t seed, uint64_t traj0,
+                                          uint32_t ntraj, double *d_fid,
+                                          qram_traj_stats *d_st, void *stream) {
+  if (!d_fid) return fail(c, QRAM_E_INVAL, "d_fid is required");
+  qram_status st = check_args(c, traj0, ntraj);
+  if (st) return st;
+  if (!c->scratch) return fail(c, QRAM_E_DEVICE, "the scratch array has no address on this device");
+  const hipStream_t s = (hipStream_t)stream;
+  const int mode = 1;
+  // per trajectory: candidates, five counters, digest, bad bitmap, explicit list
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const uint32_t ccap = cand_capacity(c);
+  const size_t words64 = (size_t)(c->D + 63) / 64;
+  auto traj_bytes = [&](size_t nb) {
+    return al(nb * ccap * 4) + 5 * al(nb * 4) + al(nb * 8) + al(nb * words64 * 8) + al(nb * (size_t)c->D * 2);
+  };
+  const size_t avail = SCRATCH_BYTES - SCR_HEAD;
+  // trajectories per batch: at most half of the array, the rest for the
+  // per-workgroup pools
+  uint32_t nb = std::max<uint32_t>(1u, std::min<uint32_t>(ntraj ? ntraj : 1u, 262144u));
+  while (nb > 1 && traj_bytes(nb) > avail / 2) nb = (nb + 1) / 2;
+  Plan pl;
+  uint32_t grid_cap = 0;
+  for (;;) {
+    if ((st = make_plan(c, mode, nb, pl))) return st;
+    size_t per_wg = al((size_t)pl.pool_slots * c->rec * 2) + al((size_t)pl.pool_slots * 4);
+    per_wg += al((size_t)pl.ecap_max * 4);
+    const size_t tb = traj_bytes(nb);
+    grid_cap = tb < avail ? (uint32_t)std::min<size_t>((avail - tb) / per_wg, 1u << 20) : 0u;
+    if (grid_cap >= 1 || nb == 1) break;
+    nb = (nb + 1) / 2;
+  }
+  if (grid_cap < 1)
+    return fail(c, QRAM_E_CAPACITY, "one workgroup's buffers exceed the " + std::to_string(SCRATCH_BYTES >> 20) +
+                                         " MiB scratch array");
+  pl.grid_max = 0;
+  for (int i = 0; i < pl.nb; ++i) {
+    pl.b[i].grid = std::min(pl.b[i].grid, grid_cap);
+    pl.grid_max = std::max(pl.grid_max, pl.b[i].grid);
+  }
+  // carve the array
+  unsigned char *base = c->scratch;
+  size_t off = SCR_HEAD;
+  auto take = [&](size_t bytes) {
+    unsigned char *p = base + off;
+    off += al(bytes);
+    return p;
+  };
+  Run r{};
+  r.seed = seed;
+  r.mode = mode;
+  r.cand_cap = ccap;
+  r.tier2_slow = c->tier2_global ? 1u : 0u;
+  r.cdec_all = pl.cdec_all ? 1u : 0u;
+  r.nbkt = (uint32_t)pl.nb;
+  for (int i = 0; i < pl.nb; ++i) r.bkt_emax[i] = pl.b[i].emax;
+  r.pool_slots = pl.pool_slots;
+  r.persistent = pl.persistent ? 1u : 0u;
+  r.err = reinterpret_cast<uint32_t *>(base + SCR_ERR);
+  r.counter = reinterpret_cast<uint32_t *>(base + SCR_COUNTER);
+  r.bucket_base = reinterpret_cast<uint32_t *>(base + SCR_BBASE);
+  r.cand = reinterpret_cast<uint32_t *>(take((size_t)nb * ccap * 4));
+  r.ncand = reinterpret_cast<uint32_t *>(take((size_t)nb * 4));
+  r.nbad = reinterpret_cast<uint32_t *>(take((size_t)nb * 4));
+  r.ref = reinterpret_cast<uint32_t *>(take((size_t)nb * 4));
+  r.nexpl = reinterpret_cast<uint32_t *>(take((size_t)nb * 4));
+  r.order = reinterpret_cast<uint32_t *>(take((size_t)nb * 4));
+  r.digest = reinterpret_cast<uint64_t *>(take((size_t)nb * 8));
+  r.badbits = reinterpret_cast<uint64_t *>(take((size_t)nb * words64 * 8));
+  r.xlist = reinterpret_cast<uint16_t *>(take((size_t)nb * c->D * 2));
+  r.pool = reinterpret_cast<uint16_t *>(take((size_t)pl.grid_max * pl.pool_slots * c->rec * 2));
+  r.devl = reinterpret_cast<uint32_t *>(take((size_t)pl.grid_max * pl.pool_slots * 4));
+  r.gstate = reinterpret_cast<uint32_t *>(take((size_t)pl.grid_max * pl.ecap_max * 4));
+  if (off > SCRATCH_BYTES) return fail(c, QRAM_E_CAPACITY, "scratch layout exceeds the array");
+  c->scratch_used = true;
+  // the error word starts each call at zero (a fill kernel, no memset node)
+  HIPCHK(c, launch_fill_u32(r.err, 0u, 1u, s));
+  for (uint32_t b0 = 0; b0 < ntraj; b0 += nb) {
+    Run rb = r;
+    rb.traj0 = (uint32_t)(traj0 + b0);
+    rb.ntraj = std::min(nb, ntraj - b0);
+    rb.fid = d_fid + b0;
+    rb.st = d_st ? d_st + b0 : nullptr;
+    if ((st = enqueue_batch(c, pl, rb, s, false, false, true))) return st;
+  }
+  return QRAM_OK;
 }
 
 qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,

@@ -127,6 +127,7 @@ hipError_t launch_evolve(const Tables *tb, const Run &rp, int enc,
                          uint32_t grid, int threads, uint32_t lds_bytes,
                          bool state_lds, hipStream_t s);
 hipError_t launch_digest(const Run &rp, uint32_t ntraj, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint32_t n, hipStream_t s);
 
 uint32_t evolve_lds_bytes(int M, int D, int threads, uint32_t cdec_cap,
                           uint32_t e_cap, bool state_lds, uint32_t walk_bytes);

@@ -311,6 +311,19 @@ hipError_t launch_order(const Tables *tb, const Run &rp, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Fill n words with v: clears flags and counters without a memset node, so
+// the enqueued work can sit inside a caller's graph capture.
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint32_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_digest(const Run &rp, uint32_t ntraj, hipStream_t s) {
   hipLaunchKernelGGL(k_digest, dim3((ntraj + 255) / 256), dim3(256), 0, s, rp);
   return hipGetLastError();

@@ -43,7 +43,7 @@ EXPORTS = [
     "qram_run_full", "qram_run_pruned", "qram_run_full_async", "qram_run_pruned_async",
     "qram_fidelity", "qram_set_launch", "qram_get_launch", "qram_autotune",
     "qram_last_kernel_ms", "qram_set_timing", "qram_stage_times", "qram_stage_launches", "qram_set_option",
-    "qram_run_forced", "qram_footprint", "qram_reserve", "qram_errors",
+    "qram_run_forced", "qram_footprint", "qram_reserve", "qram_errors", "qram_run_pruned_async_noalloc",
     "qram_server_create", "qram_server_submit", "qram_server_poll", "qram_server_wait",
     "qram_server_fidelities", "qram_server_release", "qram_server_destroy",
 ]
@@ -83,7 +83,7 @@ def load_library(path: str = LIB_PATH):
     L.qram_sample_faults.argtypes = [vp, u64, u64, u32, p(u32), p(u64), p(u32), p(u64), p(u32), u64]
     for f in (L.qram_run_full, L.qram_run_pruned):
         f.argtypes = [vp, u64, u64, u32, p(f64), vp]
-    for f in (L.qram_run_full_async, L.qram_run_pruned_async):
+    for f in (L.qram_run_full_async, L.qram_run_pruned_async, L.qram_run_pruned_async_noalloc):
         f.argtypes = [vp, u64, u64, u32, vp, vp, vp]
     L.qram_fidelity.argtypes = [p(f64), u32, p(f64), p(f64)]
     L.qram_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int]
@@ -219,6 +219,11 @@ class QramContext:
 
     def run_pruned_async(self, seed, traj0, ntraj, d_fid, d_st=None, stream=None):
         self._run_async(self._L.qram_run_pruned_async, seed, traj0, ntraj, d_fid, d_st, stream)
+
+    def run_pruned_async_noalloc(self, seed, traj0, ntraj, d_fid, d_st=None, stream=None):
+        """As run_pruned_async, with the work buffers in the library's static
+        per-device scratch array (no device allocation in the call)."""
+        self._run_async(self._L.qram_run_pruned_async_noalloc, seed, traj0, ntraj, d_fid, d_st, stream)
 
     def run_forced(self, mode, cand_L, u_aux, u_fin):
         L = np.ascontiguousarray(cand_L, dtype=np.uint32)
