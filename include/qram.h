@@ -242,6 +242,53 @@ qram_status qram_run_forced(qram_ctx *ctx, qram_mode mode,
                             qram_traj_stats *st);
 
 /*
+ * Test entry: the final pre-measurement state of one trajectory, component by
+ * component, and its jump log.  The paper validates its pruned evolution by
+ * matching complete complex amplitudes, the residual tree configuration and
+ * the input-branch label of every component, and the jump decisions, between
+ * pruned and full runs driven from the same history (Sec. VI A, App. D).
+ *   history   sampled from (seed, traj) when u_aux is NULL; otherwise forced
+ *             as in qram_run_forced (cand_L [ncand] ascending, u_aux [T],
+ *             u_fin), and seed/traj are ignored.
+ *   comp      [comp_cap * (3 + lmax)] uint32 words, lmax = 2n + k (qubit) or
+ *             4n + k (qutrit); comp_cap >= 2^n * 2^k (qubit) or 2^n
+ *             (qutrit), else QRAM_E_CAPACITY.  Record x = address * 2^k + bus
+ *             word (qubit) or address (qutrit) of the initial label:
+ *               [0] final address | final bus word << 16 | sign << 24 |
+ *                   1 << 25 (bit 25 clear: the component was annihilated);
+ *               [1] exposure e;
+ *               [2] number m of excited tree sites after the last slice;
+ *               [3 .. 3+m) site | level << 16 (1: excited qubit, qutrit L or
+ *                   data qubit; 2: qutrit R).
+ *             The state before the second Hadamard wall and the tree
+ *             measurement is sum_x A_x |label, bus, tree> with
+ *             A_x = c_i 2^(-k/2) (-1)^sign gamma^(J/2) a^e (qubit; the qutrit
+ *             has no 2^(-k/2)), c_i = 2^(-n/2), a = sqrt(1-gamma) and J the
+ *             total number of jump-log entries.  Pruned runs export the
+ *             explicit components and the predicted good branches (Theorem 3,
+ *             Proposition 1); a predicted branch is present only while the
+ *             reference survives.
+ *   jlog      [jcap] jump-log entries in order of slice: site | level << 16 |
+ *             slice << 24 (levels as above); *njl receives the number of
+ *             entries, which may exceed jcap (the rest are not written).
+ *   fid, st   as in qram_run_forced.
+ */
+qram_status qram_export_state(qram_ctx *ctx, qram_mode mode, uint64_t seed, uint32_t traj,
+                              const uint32_t *cand_L, uint32_t ncand, const double *u_aux,
+                              double u_fin, uint32_t *comp, uint32_t comp_cap, uint32_t *jlog,
+                              uint32_t jcap, uint32_t *njl, double *fid, qram_traj_stats *st);
+
+/*
+ * Test entry: qram_run_full / qram_run_pruned (mode) with the jump log of
+ * every trajectory (the jump decisions of Sec. VI A): jlog [ntraj * jcap]
+ * entries as in qram_export_state, trajectory t's at jlog + t * jcap;
+ * njl [ntraj] the number of entries of each (may exceed jcap).
+ */
+qram_status qram_run_jumplog(qram_ctx *ctx, qram_mode mode, uint64_t seed, uint64_t traj0,
+                             uint32_t ntraj, double *fid, qram_traj_stats *st, uint32_t *jlog,
+                             uint32_t jcap, uint32_t *njl);
+
+/*
  * Device memory.  qram_footprint: bytes of device memory the context holds
  * for runs of `mode` with up to ntraj trajectories per call (its tables plus
  * the work buffers of one batch; the caller's output arrays not included).

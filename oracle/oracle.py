@@ -57,12 +57,15 @@ def lib():
             C.c_int, C.c_int, C.c_int, C.c_double, u32p, C.c_uint64, C.c_uint32,
             u32p, C.c_int, f64p, C.c_double, C.c_int, f64p, i32p,
             i32p, i32p, i32p, C.c_int, i32p,
-            u32p, u32p, f64p, u8p, C.c_int]
+            u32p, u32p, f64p, u8p, u32p, C.c_int]
         L.orc_layer_masks.argtypes = [
             C.c_int, C.c_int, C.c_int, C.c_double, u32p, u32p, C.c_int, f64p,
             C.c_int, i32p, C.c_int, u8p, f64p, C.c_int, f64p]
         L.orc_run_batch.argtypes = [
             C.c_int, C.c_int, C.c_int, C.c_double, u32p, C.c_uint64, C.c_uint32,
+            C.c_int, C.c_int, f64p, f64p, i32p]
+        L.orc_run_indices.argtypes = [
+            C.c_int, C.c_int, C.c_int, C.c_double, u32p, C.c_uint64, u32p,
             C.c_int, C.c_int, f64p, f64p, i32p]
         _lib = L
     return _lib
@@ -158,6 +161,7 @@ def run_traj(n, k, enc, gamma, mem, seed=0, traj=0, forced_L=None,
     eb = np.zeros(max(cap, 1), dtype=np.uint32)
     eamp = np.zeros(2 * max(cap, 1))
     etree = np.zeros(max(cap, 1) * M, dtype=np.uint8)
+    elab = np.zeros(max(cap, 1), dtype=np.uint32)
     ne = lib().orc_run_traj(
         n, k, enc, gamma, _p(mem, C.c_uint32), seed, traj,
         _p(fL, C.c_uint32) if fL is not None else None,
@@ -166,7 +170,7 @@ def run_traj(n, k, enc, gamma, mem, seed=0, traj=0, forced_L=None,
         1 if check_counts else 0, _p(rd, C.c_double), _p(ri, C.c_int),
         _p(js, C.c_int), _p(jq, C.c_int), _p(jv, C.c_int), jcap, _p(njl, C.c_int),
         _p(ea, C.c_uint32), _p(eb, C.c_uint32), _p(eamp, C.c_double),
-        _p(etree, C.c_uint8), cap)
+        _p(etree, C.c_uint8), _p(elab, C.c_uint32), cap)
     if ne < 0:
         raise ValueError(f"oracle error {ne}")
     out = dict(fid=rd[0], fid_pre=rd[1], w_ground=rd[2], w_total=rd[3],
@@ -177,7 +181,7 @@ def run_traj(n, k, enc, gamma, mem, seed=0, traj=0, forced_L=None,
     out["jumps"] = [(int(js[j]), int(jq[j]), int(jv[j])) for j in range(min(nj, jcap))]
     if export:
         out["components"] = dict(
-            addr=ea[:ne].copy(), bus=eb[:ne].copy(),
+            label=elab[:ne].copy(), addr=ea[:ne].copy(), bus=eb[:ne].copy(),
             amp=(eamp[0:2 * ne:2] + 1j * eamp[1:2 * ne:2]).copy(),
             tree=etree[:ne * M].reshape(ne, M).copy())
     return out
@@ -215,6 +219,21 @@ def run_batch(n, k, enc, gamma, mem, seed, traj0, ntraj, nthreads=0):
     if used < 0:
         raise ValueError("oracle error")
     return fid, fpre, ri.reshape(ntraj, NRI), used
+
+
+def run_indices(n, k, enc, gamma, mem, seed, idx, nthreads=0):
+    """The listed trajectory indices; returns (fid, fid_pre, stats, threads)."""
+    mem = _mem(mem)
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    nt = len(idx)
+    fid = np.zeros(nt)
+    fpre = np.zeros(nt)
+    ri = np.zeros(max(nt, 1) * NRI, dtype=np.int32)
+    used = lib().orc_run_indices(n, k, enc, gamma, _p(mem, C.c_uint32), seed, _p(idx, C.c_uint32),
+                                 nt, nthreads, _p(fid, C.c_double), _p(fpre, C.c_double), _p(ri, C.c_int))
+    if used < 0:
+        raise ValueError("oracle error")
+    return fid, fpre, ri[:nt * NRI].reshape(nt, NRI), used
 
 
 STAT_FIELDS = ["ncand", "nbad", "ref", "nexplicit", "njumps", "first_jump",

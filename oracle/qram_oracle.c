@@ -838,9 +838,11 @@ static void pack_result(const orc_result *r, double *rd, int *ri) {
  * auxiliary uniforms; forced_ufin >= 0 overrides the final uniform.
  * Outputs: rd[ORC_NRD], ri[ORC_NRI]; optional jump log (jslice, jsite,
  * jlevel, capacity jcap, count in *njl); optional export of the final
- * pre-wall components (exp_cap entries): address, bus word, excitation count,
- * amplitude (re, im), and the sites/levels of each (M bytes per component in
- * exp_tree).  Returns the number of exported components, or < 0 on error.
+ * pre-wall components (exp_cap entries): initial label (address * 2^k + bus
+ * word for the qubit encoding, the address for the qutrit), address, bus
+ * word, amplitude (re, im), and the sites/levels of each (M bytes per
+ * component in exp_tree).  Returns the number of exported components, or < 0
+ * on error.
  */
 int orc_run_traj(int n, int k, int enc, double gamma, const uint32_t *mem,
                  uint64_t seed, uint32_t traj, const uint32_t *forced_L,
@@ -848,7 +850,7 @@ int orc_run_traj(int n, int k, int enc, double gamma, const uint32_t *mem,
                  double forced_ufin, int check_counts, double *rd, int *ri,
                  int *jslice, int *jsite, int *jlevel, int jcap, int *njl,
                  uint32_t *exp_addr, uint32_t *exp_bus, double *exp_amp,
-                 uint8_t *exp_tree, int exp_cap) {
+                 uint8_t *exp_tree, uint32_t *exp_label, int exp_cap) {
   orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, enc, gamma, mem);
   if (rc) {
@@ -881,6 +883,7 @@ int orc_run_traj(int n, int k, int enc, double gamma, const uint32_t *mem,
       if (!st.alive[x])
         continue;
       if (ne < exp_cap) {
+        exp_label[ne] = (uint32_t)x;
         exp_addr[ne] = st.addr[x];
         exp_bus[ne] = st.bus[x];
         exp_amp[2 * ne] = creal(st.amp[x]);
@@ -978,14 +981,34 @@ int orc_layer_masks(int n, int k, int enc, double gamma, const uint32_t *mem,
 }
 
 /*
- * Batch of trajectories traj0 .. traj0+ntraj-1 with OpenMP over
- * trajectories.  fid[ntraj], fid_pre[ntraj] (or NULL), ri[ntraj*ORC_NRI]
- * (or NULL).  nthreads <= 0 uses the OpenMP default.  Returns the number of
- * threads used.
+ * Batch of trajectories with OpenMP over trajectories: traj0 .. traj0+ntraj-1,
+ * or the listed indices idx[0..ntraj-1] when idx is not NULL.  fid[ntraj],
+ * fid_pre[ntraj] (or NULL), ri[ntraj*ORC_NRI] (or NULL).  nthreads <= 0 uses
+ * the OpenMP default.  Returns the number of threads used.
  */
+static int run_many(int n, int k, int enc, double gamma, const uint32_t *mem,
+                    uint64_t seed, uint32_t traj0, const uint32_t *idx,
+                    int ntraj, int nthreads, double *fid, double *fid_pre,
+                    int *ri);
+
 int orc_run_batch(int n, int k, int enc, double gamma, const uint32_t *mem,
                   uint64_t seed, uint32_t traj0, int ntraj, int nthreads,
                   double *fid, double *fid_pre, int *ri) {
+  return run_many(n, k, enc, gamma, mem, seed, traj0, NULL, ntraj, nthreads,
+                  fid, fid_pre, ri);
+}
+
+int orc_run_indices(int n, int k, int enc, double gamma, const uint32_t *mem,
+                    uint64_t seed, const uint32_t *idx, int nidx, int nthreads,
+                    double *fid, double *fid_pre, int *ri) {
+  return run_many(n, k, enc, gamma, mem, seed, 0, idx, nidx, nthreads, fid,
+                  fid_pre, ri);
+}
+
+static int run_many(int n, int k, int enc, double gamma, const uint32_t *mem,
+                    uint64_t seed, uint32_t traj0, const uint32_t *idx,
+                    int ntraj, int nthreads, double *fid, double *fid_pre,
+                    int *ri) {
   orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, enc, gamma, mem);
   if (rc) {
@@ -1005,7 +1028,8 @@ int orc_run_batch(int n, int k, int enc, double gamma, const uint32_t *mem,
 #pragma omp for schedule(dynamic, 1)
     for (int t = 0; t < ntraj; ++t) {
       orc_result res;
-      run_traj(c, seed, traj0 + (uint32_t)t, NULL, 0, &st, &res, NULL);
+      run_traj(c, seed, idx ? idx[t] : traj0 + (uint32_t)t, NULL, 0, &st, &res,
+               NULL);
       fid[t] = res.fid;
       if (fid_pre)
         fid_pre[t] = res.fid_pre;
@@ -1020,7 +1044,8 @@ int orc_run_batch(int n, int k, int enc, double gamma, const uint32_t *mem,
   state_alloc(&st, c->E, c->M);
   for (int t = 0; t < ntraj; ++t) {
     orc_result res;
-    run_traj(c, seed, traj0 + (uint32_t)t, NULL, 0, &st, &res, NULL);
+    run_traj(c, seed, idx ? idx[t] : traj0 + (uint32_t)t, NULL, 0, &st, &res,
+             NULL);
     fid[t] = res.fid;
     if (fid_pre)
       fid_pre[t] = res.fid_pre;

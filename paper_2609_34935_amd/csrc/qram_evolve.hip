@@ -1348,6 +1348,82 @@ __device__ __forceinline__ int nojump_walk_wave(const Tables *__restrict__ tb, c
 }
 
 // ---------------------------------------------------------------------------
+// test entry: export of the final pre-measurement components
+// ---------------------------------------------------------------------------
+
+// Exposure through the last slice of a component on its no-jump routing:
+// address bits of a, carried data tokens dv, lost-token exposure ek.
+template <int ENC>
+__device__ uint32_t t1_final_exposure(const Tables *__restrict__ tb, uint32_t a, uint32_t dv, uint32_t ek) {
+  const int T = tb->T, n = tb->n;
+  uint32_t e = ek;
+  for (int p = 0; p < n; ++p)
+    if ((a >> p) & 1u) e += tb->cntA[T - 1][n - 1 - p];
+  for (int b = 0; b < tb->k; ++b)
+    if ((dv >> b) & 1u) e += tb->cntD[T - 1][b];
+  if (ENC == QUTRIT) e += tb->cntR[T - 1];
+  return e;
+}
+
+// Record of a component without a site list (ground tree at the end).
+template <int ENC>
+__device__ void export_ground(const Tables *__restrict__ tb, uint32_t *out, uint32_t a, uint32_t b,
+                              uint32_t bus, bool sign, uint32_t e) {
+  const int K2 = ENC == QUBIT ? tb->K2 : 1;
+  uint32_t *o = out + (size_t)(a * (uint32_t)K2 + b) * (3u + (uint32_t)tb->lmax);
+  o[0] = a | (bus << 16) | (sign ? 1u << 24 : 0u) | EXP_PRESENT;
+  o[1] = e;
+  o[2] = 0;
+}
+
+// Record of an explicit component (state word w) of address a (slot g) and
+// bus word b after the last slice.
+template <int ENC>
+__device__ void export_explicit(const Tables *__restrict__ tb, uint32_t *out, const uint16_t *pool, int rec,
+                                uint32_t g, uint32_t a, uint32_t b, uint32_t w, uint32_t memw) {
+  const int K2 = ENC == QUBIT ? tb->K2 : 1, lmax = tb->lmax, k = tb->k;
+  if (!(w & W_DEV)) {
+    const uint32_t live = (w >> W_LIVE_SH) & 0xFFu;
+    const uint32_t dv = ENC == QUBIT ? live : (live & memw);
+    export_ground<ENC>(tb, out, a, b, dv, (w & W_SIGN) != 0, t1_final_exposure<ENC>(tb, a, dv, w & W_EK));
+    return;
+  }
+  uint32_t *o = out + (size_t)(a * (uint32_t)K2 + b) * (3u + (uint32_t)lmax);
+  const bool fb = (w & W_FBUS) != 0u;
+  const uint32_t cnt = fb ? 0u : (w & W_CNT) >> W_CNT_SH;
+  uint32_t bus, m = 0;
+  if (fb) {
+    bus = (w & W_CNT) >> W_CNT_SH;
+  } else if (ENC == QUBIT && !(w & W_SPLIT)) {
+    // a shared list: the class's entries plus the tagged tokens b carries
+    const uint16_t *r0 = pool + (size_t)g * K2 * rec;
+    const uint16_t *rc = r0 + (size_t)(b & r0[2 + lmax + k]) * rec;
+    const uint32_t bf = rc[1], toks = (bf >> 8) & 0xFFu;
+    bus = bf & (~toks | b) & 0xFFu;
+    const uint32_t nc = min((uint32_t)rc[0], (uint32_t)lmax);
+    for (uint32_t j = 0; j < nc && m < (uint32_t)lmax; ++j) o[3 + m++] = (uint32_t)rc[2 + j] | (1u << 16);
+    for (int t = 0; t < k; ++t) {
+      const uint32_t x = rc[2 + lmax + t];
+      if (((b & toks) >> t) & 1u && x != EMPTY && m < (uint32_t)lmax) o[3 + m++] = x | (1u << 16);
+    }
+  } else {
+    const uint16_t *r = pool + (size_t)(g * K2 + b) * rec;
+    bus = r[1];
+    const uint32_t nc = min((uint32_t)r[0], (uint32_t)lmax);
+    for (uint32_t j = 0; j < nc; ++j) {
+      const uint32_t x = r[2 + j], q = ENC == QUTRIT ? (x & 0x7FFFu) : x;
+      const uint32_t lev = (ENC == QUTRIT && (x & LV_R_BIT)) ? 2u : 1u;
+      o[3 + m++] = q | (lev << 16);
+    }
+  }
+  if (fb) m = 0;
+  (void)cnt;
+  o[0] = a | (bus << 16) | ((w & W_SIGN) ? 1u << 24 : 0u) | EXP_PRESENT;
+  o[1] = (w & W_E) + cnt;
+  o[2] = m;
+}
+
+// ---------------------------------------------------------------------------
 // the kernel
 // ---------------------------------------------------------------------------
 template <int ENC, bool SL>
@@ -1454,6 +1530,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
     bool ref_alive = pruned && ref != 0xFFFFFFFFu;
     uint32_t ndev = 0;  // tier-2 components of the block (listed in devl)
     int njumps = 0, first_jump = 0;
+    uint32_t jl_n = 0;  // jump-log entries (thread 0, test entry)
 
     // qubit: rebuild the tier-2 work list, one entry per class of an
     // address's shared lists and one per component with a list of its own
@@ -1904,6 +1981,10 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
       const int nJ = sm.misc[2];
       QR_TM(4);
       if (nJ == 0) continue;
+      if (rp->jlog && tid == 0) {
+        for (int c = 0; c < nJ; ++c, ++jl_n)
+          if (jl_n < rp->jcap) rp->jlog[(size_t)tj * rp->jcap + jl_n] = sm.Jb[c] | ((uint32_t)s << 24);
+      }
 
       // K_J on every component: survivors carry every site of J
       uint32_t mydev = 0;
@@ -2245,7 +2326,16 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
 
     // second wall, tree measurement and fidelity (Alg. 1 steps 4-6)
     __syncthreads();
+    if (rp->jn && tid == 0) rp->jn[tj] = jl_n;
     if (njumps == 0) {
+      if (rp->exp && tj == 0) {  // every branch on its no-jump orbit
+        for (uint32_t x = tid; x < (uint32_t)(D * K2); x += nthr) {
+          const uint32_t a = x / (uint32_t)K2, b = x % (uint32_t)K2;
+          const uint32_t w = init_word<ENC>(mem[a], b, kmask);
+          const uint32_t dv = ENC == QUBIT ? b : (mem[a] & kmask);
+          export_ground<ENC>(tb, rp->exp, a, b, dv, (w & W_SIGN) != 0, t1_final_exposure<ENC>(tb, a, dv, 0u));
+        }
+      }
       // no jump: every branch ends on its no-jump orbit in the ground
       // configuration, so the sums are the context's closed-form constants
       if (tid == 0) {
@@ -2282,6 +2372,7 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
       int cur = -1;
       uint32_t memw = 0, g = 0;
       double wa = 0.0, aa = 0.0;
+      uint32_t acur = 0;
       for (uint64_t m = alive; m; m &= m - 1) {
         const int j = __ffsll((unsigned long long)m) - 1;
         const int al = j >> kb, b = j & (K2 - 1);
@@ -2289,11 +2380,13 @@ __global__ void __launch_bounds__(ENC == QUBIT ? 1024 : 512) __attribute__((amdg
           cur = al;
           g = tid * apt + (uint32_t)al;
           const uint32_t a = xl ? xl[g] : g;
+          acur = a;
           memw = mem[a] & kmask;
           wa = fA(sm.fw, a) * wr;
           aa = fA(sm.fa, a) * ar;
         }
         const uint32_t w = st[j * nthr + tid];
+        if (rp->exp && tj == 0) export_explicit<ENC>(tb, rp->exp, pool, rec, g, acur, (uint32_t)b, w, memw);
         double wt, at;
         bool ground;
         uint32_t bus;

@@ -68,6 +68,9 @@ struct qram_ctx {
   uint32_t *devl = nullptr;
   uint32_t *gstate = nullptr;
   double *fid_tmp = nullptr, *uaux = nullptr;
+  // test entries: component export and jump logs
+  uint32_t *dexp = nullptr, *djlog = nullptr, *djn = nullptr;
+  size_t dexp_cap = 0, djlog_cap = 0, djn_cap = 0;
   qram_traj_stats *st_tmp = nullptr;
   uint32_t out_cap = 0;
   // launch choice per mode: slots per thread (0 = automatic), schedule
@@ -625,10 +628,20 @@ qram_status ensure_out(qram_ctx *c, uint32_t nb) {
 // Runs trajectories [traj0, traj0+ntraj) in batches.  Outputs go to device
 // arrays d_fid/d_st (async) or through the context's staging buffers to host
 // arrays h_fid/h_st (sync).
+// Device buffer of at least `count` elements, grown on demand.
+template <typename T>
+qram_status grow(qram_ctx *c, T **p, size_t *cap, size_t count) {
+  if (count <= *cap && *p) return QRAM_OK;
+  qram_status st = dev_alloc(c, p, count);
+  *cap = st ? 0 : count;
+  return st;
+}
+
 qram_status run_mode(qram_ctx *c, int mode, uint64_t seed, uint64_t traj0,
                      uint32_t ntraj, double *d_fid, qram_traj_stats *d_st,
                      double *h_fid, qram_traj_stats *h_st, hipStream_t s,
-                     bool sync) {
+                     bool sync, uint32_t *h_jlog = nullptr, uint32_t jcap = 0,
+                     uint32_t *h_njl = nullptr) {
   qram_status st = check_args(c, traj0, ntraj);
   if (st) return st;
   if (ntraj == 0) return QRAM_OK;
@@ -637,6 +650,11 @@ qram_status run_mode(qram_ctx *c, int mode, uint64_t seed, uint64_t traj0,
   if ((st = make_plan(c, mode, nb, pl))) return st;
   if ((st = ensure_buffers(c, nb, &pl))) return st;
   if (sync && (st = ensure_out(c, nb))) return st;
+  const bool logs = sync && h_njl != nullptr;
+  if (logs) {
+    if ((st = grow(c, &c->djlog, &c->djlog_cap, (size_t)nb * std::max<uint32_t>(jcap, 1u)))) return st;
+    if ((st = grow(c, &c->djn, &c->djn_cap, (size_t)nb))) return st;
+  }
   const bool timed = sync && ntraj <= nb;
   for (uint32_t b0 = 0; b0 < ntraj; b0 += nb) {
     const uint32_t cnt = std::min(nb, ntraj - b0);
@@ -645,6 +663,11 @@ qram_status run_mode(qram_ctx *c, int mode, uint64_t seed, uint64_t traj0,
     r.ntraj = cnt;
     r.fid = sync ? c->fid_tmp : d_fid + b0;
     r.st = sync ? (h_st ? c->st_tmp : nullptr) : (d_st ? d_st + b0 : nullptr);
+    if (logs) {
+      r.jlog = c->djlog;
+      r.jn = c->djn;
+      r.jcap = jcap;
+    }
     if (c->use_graph) {
       if (timed) HIPCHK(c, hipEventRecord(c->ev[0], s));
       if ((st = launch_batch_graph(c, pl, r, s))) return st;
@@ -656,6 +679,12 @@ qram_status run_mode(qram_ctx *c, int mode, uint64_t seed, uint64_t traj0,
       HIPCHK(c, hipMemcpyAsync(h_fid + b0, c->fid_tmp, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
       if (h_st)
         HIPCHK(c, hipMemcpyAsync(h_st + b0, c->st_tmp, cnt * sizeof(qram_traj_stats), hipMemcpyDeviceToHost, s));
+      if (logs) {
+        HIPCHK(c, hipMemcpyAsync(h_njl + b0, c->djn, cnt * 4, hipMemcpyDeviceToHost, s));
+        if (jcap && h_jlog)
+          HIPCHK(c, hipMemcpyAsync(h_jlog + (size_t)b0 * jcap, c->djlog, (size_t)cnt * jcap * 4,
+                                   hipMemcpyDeviceToHost, s));
+      }
       HIPCHK(c, hipStreamSynchronize(s));
     }
   }
@@ -853,6 +882,9 @@ void qram_destroy(qram_ctx *c) {
   dev_free(&c->fid_tmp);
   dev_free(&c->st_tmp);
   dev_free(&c->uaux);
+  dev_free(&c->dexp);
+  dev_free(&c->djlog);
+  dev_free(&c->djn);
   for (auto &e : c->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto &e : c->tev) (void)hipEventDestroy(e);
@@ -1219,47 +1251,101 @@ qram_status qram_stage_times(qram_ctx *c, double *ms, uint32_t *nbatches) {
   return QRAM_OK;
 }
 
-qram_status qram_run_forced(qram_ctx *c, qram_mode mode, const uint32_t *cand_L,
-                            uint32_t ncand, const double *u_aux, double u_fin,
-                            double *fid, qram_traj_stats *stt) {
-  qram_status st = check_args(c, 0, 1);
+// One trajectory, sampled from (seed, traj) or under a forced history,
+// optionally exporting its final components and its jump log.
+static qram_status run_single(qram_ctx *c, int mode, uint64_t seed, uint32_t traj, bool forced,
+                              const uint32_t *cand_L, uint32_t ncand, const double *u_aux, double u_fin,
+                              uint32_t *h_exp, uint32_t exp_cap, uint32_t *h_jlog, uint32_t jcap,
+                              uint32_t *h_njl, double *fid, qram_traj_stats *stt) {
+  qram_status st = check_args(c, traj, 1);
   if (st) return st;
   if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return fail(c, QRAM_E_INVAL, "bad mode");
-  if (!fid || !u_aux || (ncand && !cand_L)) return fail(c, QRAM_E_INVAL, "null argument");
-  const uint64_t S = (uint64_t)(c->T - 1) * c->M;
-  for (uint32_t j = 0; j < ncand; ++j) {
-    if (cand_L[j] >= S) return fail(c, QRAM_E_INVAL, "candidate index out of range");
-    if (j && cand_L[j] <= cand_L[j - 1]) return fail(c, QRAM_E_INVAL, "candidates must be strictly ascending");
+  if (!fid) return fail(c, QRAM_E_INVAL, "null argument");
+  if (forced) {
+    if (!u_aux || (ncand && !cand_L)) return fail(c, QRAM_E_INVAL, "null argument");
+    const uint64_t S = (uint64_t)(c->T - 1) * c->M;
+    for (uint32_t j = 0; j < ncand; ++j) {
+      if (cand_L[j] >= S) return fail(c, QRAM_E_INVAL, "candidate index out of range");
+      if (j && cand_L[j] <= cand_L[j - 1]) return fail(c, QRAM_E_INVAL, "candidates must be strictly ascending");
+    }
   }
+  const size_t rec_words = 3 + (size_t)c->lmax;
+  const size_t ncomp = (size_t)c->D * c->K2;
+  if (h_exp && exp_cap < ncomp) return fail(c, QRAM_E_CAPACITY, "the export needs one record per component (2^n * 2^k or 2^n)");
   Plan pl;
   if ((st = make_plan(c, mode, 1, pl))) return st;
   if ((st = ensure_buffers(c, 1, &pl))) return st;
-  if (ncand > c->cand_cap) {
+  if (forced && ncand > c->cand_cap) {
     if ((st = dev_alloc(c, &c->cand, ncand))) return st;
     c->cand_cap = ncand;
     c->batch_cap = 1;
   }
   if ((st = ensure_out(c, 1))) return st;
-  if (!c->uaux)
-    if ((st = dev_alloc(c, &c->uaux, MAXT))) return st;
-  std::vector<double> ua(MAXT, 0.0);
-  for (int s = 0; s < c->T; ++s) ua[s] = u_aux[s];
-  HIPCHK(c, hipMemcpy(c->uaux, ua.data(), MAXT * 8, hipMemcpyHostToDevice));
-  if (ncand) HIPCHK(c, hipMemcpy(c->cand, cand_L, ncand * 4, hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->ncand, &ncand, 4, hipMemcpyHostToDevice));
-  Run r = base_run(c, mode, 0, &pl);
-  r.traj0 = 0;
+  Run r = base_run(c, mode, seed, &pl);
+  r.traj0 = traj;
   r.ntraj = 1;
-  r.forced = 1;
-  r.uaux = c->uaux;
-  r.ufin = u_fin;
+  if (forced) {
+    if (!c->uaux)
+      if ((st = dev_alloc(c, &c->uaux, MAXT))) return st;
+    std::vector<double> ua(MAXT, 0.0);
+    for (int s = 0; s < c->T; ++s) ua[s] = u_aux[s];
+    HIPCHK(c, hipMemcpy(c->uaux, ua.data(), MAXT * 8, hipMemcpyHostToDevice));
+    if (ncand) HIPCHK(c, hipMemcpy(c->cand, cand_L, ncand * 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ncand, &ncand, 4, hipMemcpyHostToDevice));
+    r.traj0 = 0;
+    r.forced = 1;
+    r.uaux = c->uaux;
+    r.ufin = u_fin;
+  }
+  if (h_exp) {
+    if ((st = grow(c, &c->dexp, &c->dexp_cap, ncomp * rec_words))) return st;
+    HIPCHK(c, hipMemsetAsync(c->dexp, 0, ncomp * rec_words * 4, c->stream));
+    r.exp = c->dexp;
+  }
+  if (h_njl) {
+    if ((st = grow(c, &c->djlog, &c->djlog_cap, std::max<size_t>(jcap, 1)))) return st;
+    if ((st = grow(c, &c->djn, &c->djn_cap, 1))) return st;
+    r.jlog = c->djlog;
+    r.jn = c->djn;
+    r.jcap = jcap;
+  }
   r.fid = c->fid_tmp;
   r.st = c->st_tmp;
-  if ((st = enqueue_batch(c, pl, r, c->stream, false, true))) return st;
+  if ((st = enqueue_batch(c, pl, r, c->stream, false, forced))) return st;
   HIPCHK(c, hipMemcpyAsync(fid, c->fid_tmp, 8, hipMemcpyDeviceToHost, c->stream));
   if (stt) HIPCHK(c, hipMemcpyAsync(stt, c->st_tmp, sizeof(qram_traj_stats), hipMemcpyDeviceToHost, c->stream));
+  if (h_exp)
+    HIPCHK(c, hipMemcpyAsync(h_exp, c->dexp, ncomp * rec_words * 4, hipMemcpyDeviceToHost, c->stream));
+  if (h_njl) {
+    HIPCHK(c, hipMemcpyAsync(h_njl, c->djn, 4, hipMemcpyDeviceToHost, c->stream));
+    if (jcap && h_jlog) HIPCHK(c, hipMemcpyAsync(h_jlog, c->djlog, (size_t)jcap * 4, hipMemcpyDeviceToHost, c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return check_err(c);
+}
+
+qram_status qram_run_forced(qram_ctx *c, qram_mode mode, const uint32_t *cand_L,
+                            uint32_t ncand, const double *u_aux, double u_fin,
+                            double *fid, qram_traj_stats *stt) {
+  return run_single(c, mode, 0, 0, true, cand_L, ncand, u_aux, u_fin, nullptr, 0, nullptr, 0, nullptr, fid, stt);
+}
+
+qram_status qram_export_state(qram_ctx *c, qram_mode mode, uint64_t seed, uint32_t traj,
+                              const uint32_t *cand_L, uint32_t ncand, const double *u_aux,
+                              double u_fin, uint32_t *comp, uint32_t comp_cap, uint32_t *jlog,
+                              uint32_t jcap, uint32_t *njl, double *fid, qram_traj_stats *stt) {
+  if (!comp || !njl) return fail(c, QRAM_E_INVAL, "comp and njl are required");
+  return run_single(c, mode, seed, traj, u_aux != nullptr, cand_L, ncand, u_aux, u_fin, comp, comp_cap, jlog,
+                    jcap, njl, fid, stt);
+}
+
+qram_status qram_run_jumplog(qram_ctx *c, qram_mode mode, uint64_t seed, uint64_t traj0,
+                             uint32_t ntraj, double *fid, qram_traj_stats *stt, uint32_t *jlog,
+                             uint32_t jcap, uint32_t *njl) {
+  if (!c) return fail(nullptr, QRAM_E_INVAL, "null context");
+  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return fail(c, QRAM_E_INVAL, "bad mode");
+  if (!fid || !njl || (jcap && !jlog)) return fail(c, QRAM_E_INVAL, "null argument");
+  return run_mode(c, (int)mode, seed, traj0, ntraj, nullptr, nullptr, fid, stt, c->stream, true, jlog, jcap, njl);
 }
 
 }  // extern "C"

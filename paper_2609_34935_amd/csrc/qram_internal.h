@@ -112,7 +112,20 @@ struct Run {
   uint32_t *err;         // [1] error bits
   const double *uaux;    // forced auxiliary uniforms [T]
   double ufin;           // forced final uniform
+  // test entries (null otherwise)
+  uint32_t *exp;         // [D * K2 * (3 + lmax)] component records of trajectory 0
+  uint32_t *jlog;        // [ntraj * jcap] jump log: site | level << 16 | slice << 24
+  uint32_t *jn;          // [ntraj] jump-log entries of each trajectory (may exceed jcap)
+  uint32_t jcap;         // jump-log entries kept per trajectory
 };
+
+// Export record of one component (test entry), (3 + lmax) words:
+// [0] address | bus word << 16 | sign << 24 | 1 << 25, [1] exposure e (the
+// amplitude is c_i * K2^(-1/2) * (-1)^sign * gamma^(|J_all|/2) * a^e, with
+// |J_all| the trajectory's jump-log length), [2] excited sites,
+// [3 + j] site | level << 16 (level 1: excited qubit, qutrit L or data
+// qubit; 2: qutrit R).
+constexpr uint32_t EXP_PRESENT = 1u << 25;
 
 constexpr uint32_t ERR_CAND = 1u;
 constexpr uint32_t ERR_LIST = 2u;

@@ -44,6 +44,7 @@ EXPORTS = [
     "qram_fidelity", "qram_set_launch", "qram_get_launch", "qram_autotune",
     "qram_last_kernel_ms", "qram_set_timing", "qram_stage_times", "qram_stage_launches", "qram_set_option",
     "qram_run_forced", "qram_footprint", "qram_reserve", "qram_errors", "qram_run_pruned_async_noalloc",
+    "qram_export_state", "qram_run_jumplog",
     "qram_server_create", "qram_server_submit", "qram_server_poll", "qram_server_wait",
     "qram_server_fidelities", "qram_server_release", "qram_server_destroy",
 ]
@@ -91,6 +92,9 @@ def load_library(path: str = LIB_PATH):
     L.qram_autotune.argtypes = [vp, C.c_int, u64, u64, u32, p(f64)]
     L.qram_last_kernel_ms.argtypes = [vp, p(f64)]
     L.qram_run_forced.argtypes = [vp, C.c_int, p(u32), u32, p(f64), f64, p(f64), vp]
+    L.qram_export_state.argtypes = [vp, C.c_int, u64, u32, p(u32), u32, p(f64), f64, p(u32), u32, p(u32), u32,
+                                    p(u32), p(f64), vp]
+    L.qram_run_jumplog.argtypes = [vp, C.c_int, u64, u64, u32, p(f64), vp, p(u32), u32, p(u32)]
     L.qram_set_timing.argtypes = [vp, C.c_int]
     L.qram_stage_times.argtypes = [vp, p(f64), p(u32)]
     L.qram_stage_launches.argtypes = [vp, p(u32)]
@@ -237,6 +241,47 @@ class QramContext:
                                      st_arr.ctypes.data_as(C.c_void_p))
         self._check(st, "qram_run_forced")
         return fid.value, st_arr[0]
+
+    def export_state(self, mode, seed=0, traj=0, cand_L=None, u_aux=None, u_fin=-1.0, jcap=4096):
+        """qram_export_state: the final pre-measurement components of one
+        trajectory (sampled, or forced when u_aux is given) and its jump log.
+        Returns dict(fid, st, records [ncomp, 3 + lmax] uint32, jlog uint32
+        entries, njl)."""
+        K2 = (1 << self.k) if self.enc == 1 else 1
+        lmax = 2 * self.n + self.k if self.enc == 1 else 4 * self.n + self.k
+        ncomp = self.D * K2
+        comp = np.zeros(ncomp * (3 + lmax), dtype=np.uint32)
+        jl = np.zeros(max(jcap, 1), dtype=np.uint32)
+        njl = C.c_uint32()
+        fid = C.c_double()
+        st_arr = np.zeros(1, dtype=STATS_DTYPE)
+        L = ua = None
+        if u_aux is not None:
+            ua = np.ascontiguousarray(u_aux, dtype=np.float64)
+            if len(ua) < self.T:
+                raise ValueError("u_aux needs T entries (index = slice)")
+            L = np.ascontiguousarray(cand_L if cand_L is not None else [], dtype=np.uint32)
+        st = self._L.qram_export_state(
+            self._h, mode, seed, traj, _ptr(L, C.c_uint32) if L is not None and len(L) else None,
+            0 if L is None else len(L), _ptr(ua, C.c_double) if ua is not None else None, float(u_fin),
+            _ptr(comp, C.c_uint32), ncomp, _ptr(jl, C.c_uint32), jcap, C.byref(njl), C.byref(fid),
+            st_arr.ctypes.data_as(C.c_void_p))
+        self._check(st, "qram_export_state")
+        return dict(fid=fid.value, st=st_arr[0], records=comp.reshape(ncomp, 3 + lmax),
+                    jlog=jl[:min(njl.value, jcap)].copy(), njl=njl.value)
+
+    def run_jumplog(self, mode, seed, traj0, ntraj, jcap=64):
+        """qram_run_jumplog: fidelities, statistics and every trajectory's
+        jump log ([ntraj, jcap] uint32 entries, counts [ntraj])."""
+        fid = np.zeros(ntraj)
+        st_arr = np.zeros(ntraj, dtype=STATS_DTYPE)
+        jl = np.zeros(max(ntraj * jcap, 1), dtype=np.uint32)
+        njl = np.zeros(ntraj, dtype=np.uint32)
+        st = self._L.qram_run_jumplog(self._h, mode, seed, traj0, ntraj, _ptr(fid, C.c_double),
+                                      st_arr.ctypes.data_as(C.c_void_p), _ptr(jl, C.c_uint32), jcap,
+                                      _ptr(njl, C.c_uint32))
+        self._check(st, "qram_run_jumplog")
+        return fid, st_arr, jl[:ntraj * jcap].reshape(ntraj, jcap), njl
 
     def set_launch(self, mode, slots_per_thread, schedule):
         self._check(self._L.qram_set_launch(self._h, mode, slots_per_thread, schedule), "qram_set_launch")

@@ -6,7 +6,6 @@ one by one against the oracle (fidelities within 1e-12 relative, candidate
 lists and statistics bit-exact)."""
 import json
 import os
-from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -36,22 +35,38 @@ def fid_close(a, b):
     return np.abs(a - b) <= 1e-12 * np.maximum(np.abs(b), 1e-3)
 
 
+def fnv_digest(L):
+    h = 0xcbf29ce484222325
+    for x in L.tolist():
+        for b in range(4):
+            h ^= (x >> (8 * b)) & 0xFF
+            h = (h * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
 def oracle_at(orc, n, k, enc, gamma, mem, seed, idx):
-    def one(i):
-        f, fp, ri, _ = orc.run_batch(n, k, enc, gamma, mem, seed, int(i), 1, nthreads=1)
-        return f[0], fp[0], ri[0]
-    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
-        return list(ex.map(one, idx))
+    """The oracle on the listed trajectories, OpenMP over the host's cores
+    (at most 16 threads, the GPU machine's share)."""
+    f, fp, ri, _ = orc.run_indices(n, k, enc, gamma, mem, seed, idx, nthreads=min(16, os.cpu_count() or 1))
+    return list(zip(f, fp, ri))
 
 
-def check_run(lib, orc, n, k, enc, gamma, mem, seed, nt, idx, launch=None):
+def sampled_indices(nt, nfirst, nrand, seed):
+    rng = np.random.default_rng(seed)
+    rest = np.arange(nfirst, nt)
+    pick = rng.choice(rest, min(nrand, len(rest)), replace=False)
+    return sorted(set(range(min(nfirst, nt))) | set(pick.tolist()) | {nt - 1})
+
+
+def check_run(lib, orc, n, k, enc, gamma, mem, seed, nt, idx, launch=None, ndump=32):
     with lib.QramContext(n, k, enc, gamma, mem) as ctx:
         if launch:
             for mode in (FULL, PRUNED):
                 ctx.set_launch(mode, *launch[f"{enc}:{mode}"])
         fp, sp = ctx.run_pruned(seed, 0, nt)
         ff, sf = ctx.run_full(seed, 0, nt)
-        dump = {int(i): ctx.sample_faults(seed, int(i), 1, dump=True) for i in idx}
+        faults = ctx.sample_faults(seed, 0, nt, dump=False)
+        dump = {int(i): ctx.sample_faults(seed, int(i), 1, dump=True) for i in idx[:ndump]}
     # every trajectory: pruned equals full, statistics agree across modes
     assert np.all(fid_close(fp, ff))
     assert np.all(fid_close(sp["fid_pre"], sf["fid_pre"]))
@@ -70,10 +85,13 @@ def check_run(lib, orc, n, k, enc, gamma, mem, seed, nt, idx, launch=None):
         assert fid_close(fp[i], fo) and fid_close(ff[i], fo), (i, fp[i], ff[i], fo)
         assert fid_close(sp["fid_pre"][i], fpo), i
         assert sp["n_cand"][i] == ri[0] and sp["n_bad"][i] == ri[1], i
+        assert sp["ref_addr"][i] == (0xFFFFFFFF if ri[2] < 0 else ri[2]), i
         assert sp["n_jumps"][i] == ri[4] and sp["first_jump_slice"][i] == ri[5], i
         assert sp["ref_survived"][i] == ri[6] and sp["q_ground"][i] == ri[7], i
         L = orc.sample(n, k, gamma, seed, int(i))
-        assert np.array_equal(dump[int(i)]["cand_L"][0], L), i
+        assert int(faults["digest"][i]) == fnv_digest(L), i
+        if int(i) in dump:
+            assert np.array_equal(dump[int(i)]["cand_L"][0], L), i
     return fp, sp
 
 
@@ -82,8 +100,9 @@ def test_c3_full_size_sampled(lib, orc, enc):
     n, k, gamma, nt = 10, 4, 1e-3, 100000
     mem = memory_words(n, k, 1003)
     launch = json.load(open(TUNED))
-    rng = np.random.default_rng(31 + enc)
-    idx = sorted(set([0, 1, 2, nt - 1] + rng.choice(nt, 24, replace=False).tolist()))
+    # the first 1000 trajectories and 1000 more drawn from the rest
+    idx = sampled_indices(nt, 1000, 1000, 31 + enc)
+    print(f"C3 enc={enc}: {len(idx)} trajectories against the oracle", flush=True)
     fp, sp = check_run(lib, orc, n, k, enc, gamma, mem, 880003, nt, idx, launch)
     # the no-jump trajectories of the qubit encoding hit the closed form
     if enc == QUBIT:
@@ -96,11 +115,14 @@ def test_c3_full_size_sampled(lib, orc, enc):
         assert np.all(np.abs(sp["fid_pre"][sel] - F0) <= 1e-12)
 
 
-def test_c5_qutrit_n14_sampled(lib, orc):
-    n, k, gamma, nt = 14, 1, 1e-2, 4096
+def test_c5_qutrit_n14_full_size(lib, orc):
+    """All 1e5 trajectories: pruned equals full on every one; 64 against the
+    oracle (the first 32 and 32 more drawn from the rest)."""
+    n, k, gamma, nt = 14, 1, 1e-2, 100000
     mem = memory_words(n, k, 1005)
-    idx = [0, 1, 2, 1000, 2047, nt - 1]
-    fp, sp = check_run(lib, orc, n, k, QUTRIT, gamma, mem, 880005, nt, idx)
+    idx = sampled_indices(nt, 32, 31, 55)
+    print(f"C5: {nt} trajectories, {len(idx)} against the oracle", flush=True)
+    fp, sp = check_run(lib, orc, n, k, QUTRIT, gamma, mem, 880005, nt, idx, ndump=8)
     assert np.all(sp["n_bad"] == 2**n)  # every branch bad at this noise level
 
 

@@ -129,10 +129,12 @@ def test_config1_qutrit_all_trajectories(lib, orc):
 
 
 @pytest.mark.parametrize("gamma", [1e-4, 1e-3, 1e-2])
-def test_config2_qubit_sample(lib, orc, gamma):
-    """Qubit n = 6, k = 1: 400 trajectories per gamma against the oracle."""
+def test_config2_qubit_all_trajectories(lib, orc, gamma):
+    """Qubit n = 6, k = 1: every one of the 1e4 trajectories per gamma against
+    the oracle, both modes."""
     mem = memory_words(6, 1, 1002)
-    compare_runs(lib, orc, 6, 1, QUBIT, gamma, mem, 880002, 0, 400)
+    out, (fo, _, so) = compare_runs(lib, orc, 6, 1, QUBIT, gamma, mem, 880002, 0, 10000)
+    assert so[:, 4].sum() > 0
 
 
 @pytest.mark.parametrize("spt,sched", [(4, 0), (8, 1), (16, 0), (32, 1), (64, 1), (8, 2), (32, 3), (64, 3)])

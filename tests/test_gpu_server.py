@@ -1,5 +1,10 @@
 """Request server (continuous batching) on the GPU: every result equals the
-direct run of the same request, alone or in a mix; admission by footprint."""
+direct run of the same request and the oracle's trajectories (fidelities
+within 1e-12 relative), alone or in a mix; admission by footprint; requests
+of the serving mix's largest shape (n = 12, k = 4) checked on sampled
+trajectories against the oracle."""
+import os
+
 import numpy as np
 import pytest
 
@@ -35,6 +40,21 @@ def small_mix(nreq, seed):
     return out
 
 
+def fid_close(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b) <= 1e-12 * np.maximum(np.abs(b), 1e-3)
+
+
+def oracle_fids(orc, r, idx=None):
+    mem = memory_words(r["n"], r["k"], r["mem_seed"])
+    nth = min(16, os.cpu_count() or 1)
+    if idx is None:
+        return orc.run_batch(r["n"], r["k"], r["enc"], r["gamma"], mem, r["seed"], r["traj0"], r["shots"],
+                             nthreads=nth)[0]
+    return orc.run_indices(r["n"], r["k"], r["enc"], r["gamma"], mem, r["seed"],
+                           [r["traj0"] + i for i in idx], nthreads=nth)[0]
+
+
 def direct(P, r):
     mem = memory_words(r["n"], r["k"], r["mem_seed"])
     with P.QramContext(r["n"], r["k"], r["enc"], r["gamma"], mem) as ctx:
@@ -48,7 +68,7 @@ def submit(P, srv, r):
     return srv.submit(r["n"], r["k"], r["enc"], r["gamma"], mem, r["seed"], r["shots"], r["mode"], r["traj0"])
 
 
-def test_mix_results_equal_direct_runs(P):
+def test_mix_results_equal_direct_runs(P, orc):
     reqs = small_mix(12, 77)
     with P.QramServer(8 << 30, max_active=4, chunk=300) as srv:
         tickets = [submit(P, srv, r) for r in reqs]
@@ -58,6 +78,8 @@ def test_mix_results_equal_direct_runs(P):
             f = srv.fidelities(t, r["shots"])
             ref = direct(P, r)
             assert np.array_equal(f, ref), r
+            fo = oracle_fids(orc, r)
+            assert np.all(fid_close(f, fo)), r
             m, s = P.qram_fidelity(ref)
             assert res["mean"] == m and res["sem"] == s
             assert res["latency_ms"] >= res["queue_ms"] >= 0.0
@@ -106,3 +128,30 @@ def test_admission_by_footprint(P):
         t = submit(P, srv, big)
         res = srv.wait(t)
         assert res["state"] == "failed" and res["status"] == "QRAM_E_CAPACITY"
+
+
+def test_largest_mix_shape_against_oracle(P, orc):
+    """Two requests of the mix's largest shape (n = 12, k = 4; both
+    encodings, up to 1e5 shots) served among smaller ones: every result equals
+    the direct run, and sampled trajectories equal the oracle's."""
+    big = [dict(id=900, n=12, k=4, enc=QUBIT, gamma=1e-3, shots=100000, mode=PRUNED, seed=4242900,
+                traj0=0, mem_seed=5900),
+           dict(id=901, n=12, k=4, enc=QUTRIT, gamma=1e-4, shots=30000, mode=PRUNED, seed=4242901,
+                traj0=17, mem_seed=5901)]
+    reqs = small_mix(6, 80)
+    with P.QramServer(16 << 30, max_active=4, chunk=8192) as srv:
+        ts = [submit(P, srv, r) for r in reqs[:3]]
+        tb = [submit(P, srv, r) for r in big]
+        ts += [submit(P, srv, r) for r in reqs[3:]]
+        for r, t in zip(big, tb):
+            print(f"request n={r['n']} k={r['k']} enc={r['enc']} shots={r['shots']}", flush=True)
+            res = srv.wait(t)
+            assert res["state"] == "done", res
+            f = srv.fidelities(t, r["shots"])
+            assert np.array_equal(f, direct(P, r)), r["id"]
+            rng = np.random.default_rng(r["id"])
+            idx = sorted(set([0, 1, r["shots"] - 1] + rng.choice(r["shots"], 5, replace=False).tolist()))
+            fo = oracle_fids(orc, r, idx)
+            assert np.all(fid_close(f[idx], fo)), (r["id"], f[idx], fo)
+        for t in ts:
+            assert srv.wait(t)["state"] == "done"
