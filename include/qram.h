@@ -57,7 +57,15 @@ typedef enum {
   QRAM_E_CAPACITY = -5  /* an output or work buffer is too small */
 } qram_status;
 
-typedef enum { QRAM_MODE_FULL = 0, QRAM_MODE_PRUNED = 1 } qram_mode;
+/* FULL: every branch explicit in the trajectory kernel, which carries a
+ * component untouched by any jump implicitly (its sites follow from the
+ * schedule) and decides the slices before a trajectory's first jump and the
+ * final sums of a jump-free trajectory in closed form.  PRUNED: Alg. 1, the
+ * bad branches plus the reference explicit, the good branches predicted.
+ * PLAIN: the plain full evolution of App. D / Table 2 ("full: D explicit
+ * branches"): every component of every branch carries its own site list and
+ * complex amplitude through every slice, nothing predicted or implicit. */
+typedef enum { QRAM_MODE_FULL = 0, QRAM_MODE_PRUNED = 1, QRAM_MODE_PLAIN = 2 } qram_mode;
 
 /* Per-trajectory statistics (32 bytes, naturally aligned). */
 typedef struct {
@@ -138,6 +146,15 @@ qram_status qram_run_pruned(qram_ctx *ctx, uint64_t seed, uint64_t traj0,
                             uint32_t ntraj, double *fid, qram_traj_stats *st);
 
 /*
+ * Plain full evolution (QRAM_MODE_PLAIN), the comparator of App. D: all D
+ * branches evolved explicitly, every component slice by slice with its own
+ * site list and complex FP64 amplitude; one workgroup per trajectory.  Same
+ * arguments as qram_run_full; same results up to rounding.
+ */
+qram_status qram_run_plain(qram_ctx *ctx, uint64_t seed, uint64_t traj0,
+                           uint32_t ntraj, double *fid, qram_traj_stats *st);
+
+/*
  * Device-buffer variants: d_fid [ntraj] and d_st [ntraj] (or NULL) are device
  * pointers; the work is enqueued on stream (a hipStream_t, NULL = the null
  * stream) and the call returns without waiting.  The outputs are valid once
@@ -151,6 +168,9 @@ qram_status qram_run_full_async(qram_ctx *ctx, uint64_t seed, uint64_t traj0,
 qram_status qram_run_pruned_async(qram_ctx *ctx, uint64_t seed, uint64_t traj0,
                                   uint32_t ntraj, double *d_fid,
                                   qram_traj_stats *d_st, void *stream);
+qram_status qram_run_plain_async(qram_ctx *ctx, uint64_t seed, uint64_t traj0,
+                                 uint32_t ntraj, double *d_fid,
+                                 qram_traj_stats *d_st, void *stream);
 
 /* Mean and standard error of the mean of fid[0..ntraj-1] (host arrays). */
 qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,
@@ -164,7 +184,9 @@ qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,
  * trajectories to workgroups round robin, 1 takes them from a device queue,
  * longest first; bit 1: keep the component state words in device memory
  * instead of workgroup shared memory (smaller workgroups per compute unit
- * footprint, more trajectories in flight).  The shape changes only the speed:
+ * footprint, more trajectories in flight).  QRAM_MODE_PLAIN: slots_per_thread
+ * is the number of workgroups per compute unit (1..8, 0 = 2), schedule is
+ * ignored.  The shape changes only the speed:
  * results are identical across shapes up to the rounding of the per-slice
  * weight sums.
  */
@@ -267,7 +289,11 @@ qram_status qram_run_forced(qram_ctx *ctx, qram_mode mode,
  *             total number of jump-log entries.  Pruned runs export the
  *             explicit components and the predicted good branches (Theorem 3,
  *             Proposition 1); a predicted branch is present only while the
- *             reference survives.
+ *             reference survives.  QRAM_MODE_PLAIN carries amplitudes as
+ *             numbers: its records hold sign 0 and exposure 0, and
+ *   amp       [comp_cap * 2] (plain mode, required there; else may be NULL
+ *             and is not written) receives each record's complex amplitude
+ *             (real, imaginary), the factor gamma^(J/2) included.
  *   jlog      [jcap] jump-log entries in order of slice: site | level << 16 |
  *             slice << 24 (levels as above); *njl receives the number of
  *             entries, which may exceed jcap (the rest are not written).
@@ -275,8 +301,9 @@ qram_status qram_run_forced(qram_ctx *ctx, qram_mode mode,
  */
 qram_status qram_export_state(qram_ctx *ctx, qram_mode mode, uint64_t seed, uint32_t traj,
                               const uint32_t *cand_L, uint32_t ncand, const double *u_aux,
-                              double u_fin, uint32_t *comp, uint32_t comp_cap, uint32_t *jlog,
-                              uint32_t jcap, uint32_t *njl, double *fid, qram_traj_stats *st);
+                              double u_fin, uint32_t *comp, uint32_t comp_cap, double *amp,
+                              uint32_t *jlog, uint32_t jcap, uint32_t *njl, double *fid,
+                              qram_traj_stats *st);
 
 /*
  * Test entry: qram_run_full / qram_run_pruned (mode) with the jump log of

@@ -38,6 +38,10 @@ struct Plan {
   uint32_t cdec_cap = 0;    // decoded-candidate entries in shared memory
   uint32_t grid_max = 0;
   uint32_t ecap_max = 0;
+  // plain full evolution: one launch of `grid` workgroups, grid-stride over
+  // the batch's trajectories
+  bool plain = false;
+  uint32_t plds = 0;
 };
 
 struct qram_ctx {
@@ -71,11 +75,19 @@ struct qram_ctx {
   // test entries: component export and jump logs
   uint32_t *dexp = nullptr, *djlog = nullptr, *djn = nullptr;
   size_t dexp_cap = 0, djlog_cap = 0, djn_cap = 0;
+  double *dexpamp = nullptr;
+  size_t dexpamp_cap = 0;
+  // plain full evolution: record length, workgroups per CU, buffers
+  int prec = 0;
+  int plain_per_cu = 2;
+  double *pamp = nullptr, *pgrp = nullptr;
+  uint8_t *phit = nullptr;
+  size_t pamp_cap = 0, pgrp_cap = 0, phit_cap = 0;
   qram_traj_stats *st_tmp = nullptr;
   uint32_t out_cap = 0;
   // launch choice per mode: slots per thread (0 = automatic), schedule
-  int spt[2] = {0, 0};
-  int schedule[2] = {1, 1};
+  int spt[3] = {0, 0, 0};
+  int schedule[3] = {1, 1, 0};
   bool tier2_global = false;
   // graph mode: every batch is captured once into a graph and replayed;
   // the executable graph is updated in place for the next batch
@@ -179,6 +191,15 @@ void dev_free(T **p) {
   *p = nullptr;
 }
 
+// Device buffer of at least `count` elements, grown on demand.
+template <typename T>
+qram_status grow(qram_ctx *c, T **p, size_t *cap, size_t count) {
+  if (count <= *cap && *p) return QRAM_OK;
+  qram_status st = dev_alloc(c, p, count);
+  *cap = st ? 0 : count;
+  return st;
+}
+
 // ---------------------------------------------------------------------------
 // Schedule tables.  Events follow the bucket-brigade query of Sec. II A:
 // address bit t is copied into the root data slot at 2t+1, moves down one
@@ -199,6 +220,7 @@ bool build_tables(qram_ctx *c, std::string &why) {
   t.D = c->D;
   t.K2 = c->K2;
   t.lmax = c->lmax;
+  t.sg = std::sqrt(c->gamma);
   t.emax = c->emax;
   t.rec = c->rec;
   // geometric-walk thresholds: G[o] = floor(2^64 (1 - (1-gamma)^(o+1)))
@@ -354,6 +376,19 @@ uint32_t pow2ceil(uint32_t x) {
 // addresses plus the reference), so trajectories are grouped by it, each
 // group with a workgroup size and LDS footprint sized for its largest member.
 qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
+  if (mode == QRAM_MODE_PLAIN) {
+    pl = Plan{};
+    pl.plain = true;
+    pl.nb = 1;
+    pl.plds = plain_lds_bytes(c->M);
+    int occ = plain_occupancy(c->enc, PLAIN_THREADS, pl.plds);
+    occ = std::max(1, std::min(occ, c->plain_per_cu));
+    pl.b[0].threads = PLAIN_THREADS;
+    pl.b[0].emax = (uint32_t)c->Emax;
+    pl.b[0].grid = std::max<uint32_t>(1u, std::min<uint32_t>((uint32_t)(c->num_cu * occ), ntraj));
+    pl.grid_max = pl.b[0].grid;
+    return QRAM_OK;
+  }
   const int spt_target = c->spt[mode] ? c->spt[mode] : 16;
   std::vector<uint32_t> ems;
   if (mode == 0) {
@@ -427,6 +462,17 @@ qram_status ensure_buffers(qram_ctx *c, uint32_t nb, const Plan *pl) {
     if ((st = dev_alloc(c, &c->errw, 4))) return st;
     HIPCHK(c, hipMemset(c->errw, 0, 16));
   }
+  if (pl && pl->plain) {
+    const size_t g = pl->grid_max, E = (size_t)c->Emax;
+    if (g * E * c->prec > c->pool_cap) {
+      if ((st = dev_alloc(c, &c->pool, g * E * c->prec))) return st;
+      c->pool_cap = g * E * c->prec;
+    }
+    if ((st = grow(c, &c->pamp, &c->pamp_cap, g * E * 2))) return st;
+    if ((st = grow(c, &c->phit, &c->phit_cap, g * E))) return st;
+    if ((st = grow(c, &c->pgrp, &c->pgrp_cap, g * PLAIN_THREADS * (size_t)c->K2 * 2))) return st;
+    return QRAM_OK;
+  }
   if (pl) {
     const size_t gs = (size_t)pl->grid_max * pl->ecap_max;
     if (gs > c->gstate_cap) {
@@ -456,6 +502,10 @@ size_t buffers_bytes(const qram_ctx *c, uint32_t nb, const Plan &pl) {
   const size_t n = nb;
   size_t b = n * cand_capacity(c) * 4 + n * 5 * 4 + n * 8 + n * ((c->D + 63) / 64) * 8 + n * c->D * 2;
   b += (2 * MAXB + 1 + 4) * 4;
+  if (pl.plain) {
+    const size_t g = pl.grid_max, E = (size_t)c->Emax;
+    return b + g * E * ((size_t)c->prec * 2 + 16 + 1) + g * PLAIN_THREADS * (size_t)c->K2 * 16;
+  }
   b += (size_t)pl.grid_max * pl.ecap_max * 4;
   size_t ps = 0, ds = 0;
   for (int i = 0; i < pl.nb; ++i) {
@@ -510,6 +560,10 @@ Run base_run(qram_ctx *c, int mode, uint64_t seed, const Plan *pl) {
   r.pool = c->pool;
   r.devl = c->devl;
   r.err = c->errw;
+  r.prec = (uint32_t)c->prec;
+  r.pamp = c->pamp;
+  r.phit = c->phit;
+  r.pgrp = c->pgrp;
   return r;
 }
 
@@ -550,10 +604,14 @@ qram_status enqueue_batch(qram_ctx *c, const Plan &pl, Run r, hipStream_t s,
   if (!skip_sample) HIPCHK(c, launch_sample(c->dtab, r, nt, sample_grid(c, nt), s));
   if (timed) HIPCHK(c, hipEventRecord(e[1], s));
   HIPCHK(c, launch_classify(c->dtab, r, nt, sample_grid(c, nt), c->D, c->mark_subtree, s));
-  HIPCHK(c, launch_order(c->dtab, r, s));
+  if (!pl.plain) HIPCHK(c, launch_order(c->dtab, r, s));
   if (timed) HIPCHK(c, hipEventRecord(e[2], s));
-  qram_status st = launch_buckets(c, pl, r, s);
-  if (st) return st;
+  if (pl.plain) {
+    HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.b[0].grid, pl.b[0].threads, pl.plds, s));
+  } else {
+    qram_status st = launch_buckets(c, pl, r, s);
+    if (st) return st;
+  }
   if (timed) HIPCHK(c, hipEventRecord(e[3], s));
   return QRAM_OK;
 }
@@ -628,15 +686,6 @@ qram_status ensure_out(qram_ctx *c, uint32_t nb) {
 // Runs trajectories [traj0, traj0+ntraj) in batches.  Outputs go to device
 // arrays d_fid/d_st (async) or through the context's staging buffers to host
 // arrays h_fid/h_st (sync).
-// Device buffer of at least `count` elements, grown on demand.
-template <typename T>
-qram_status grow(qram_ctx *c, T **p, size_t *cap, size_t count) {
-  if (count <= *cap && *p) return QRAM_OK;
-  qram_status st = dev_alloc(c, p, count);
-  *cap = st ? 0 : count;
-  return st;
-}
-
 qram_status run_mode(qram_ctx *c, int mode, uint64_t seed, uint64_t traj0,
                      uint32_t ntraj, double *d_fid, qram_traj_stats *d_st,
                      double *h_fid, qram_traj_stats *h_st, hipStream_t s,
@@ -743,6 +792,7 @@ qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
   // record: count, bus word, lmax sites (+ the data tokens' sites and the
   // split set of a shared qubit list)
   c->rec = (c->lmax + 2 + (c->enc == QUBIT ? k_data + 1 : 0) + 1) & ~1;
+  c->prec = (c->lmax + PLAIN_EXTRA + 2 + 1) & ~1;
   const double lw = c->emax * std::log(1.0 - gamma);
   if (lw < -690.0) {
     delete c;
@@ -883,6 +933,10 @@ void qram_destroy(qram_ctx *c) {
   dev_free(&c->st_tmp);
   dev_free(&c->uaux);
   dev_free(&c->dexp);
+  dev_free(&c->dexpamp);
+  dev_free(&c->pamp);
+  dev_free(&c->pgrp);
+  dev_free(&c->phit);
   dev_free(&c->djlog);
   dev_free(&c->djn);
   for (auto &e : c->ev)
@@ -973,10 +1027,23 @@ qram_status qram_run_pruned_async(qram_ctx *c, uint64_t seed, uint64_t traj0,
   return run_mode(c, 1, seed, traj0, ntraj, d_fid, d_st, nullptr, nullptr, (hipStream_t)stream, false);
 }
 
+qram_status qram_run_plain(qram_ctx *c, uint64_t seed, uint64_t traj0,
+                           uint32_t ntraj, double *fid, qram_traj_stats *st) {
+  if (!fid) return fail(c, QRAM_E_INVAL, "fid is required");
+  return run_mode(c, QRAM_MODE_PLAIN, seed, traj0, ntraj, nullptr, nullptr, fid, st, c ? c->stream : nullptr, true);
+}
+
+qram_status qram_run_plain_async(qram_ctx *c, uint64_t seed, uint64_t traj0,
+                                 uint32_t ntraj, double *d_fid,
+                                 qram_traj_stats *d_st, void *stream) {
+  if (!d_fid) return fail(c, QRAM_E_INVAL, "d_fid is required");
+  return run_mode(c, QRAM_MODE_PLAIN, seed, traj0, ntraj, d_fid, d_st, nullptr, nullptr, (hipStream_t)stream, false);
+}
+
 qram_status qram_footprint(qram_ctx *c, qram_mode mode, uint32_t ntraj,
                            uint64_t *bytes) {
   if (!c || !bytes) return fail(c, QRAM_E_INVAL, "null argument");
-  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return fail(c, QRAM_E_INVAL, "bad mode");
+  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED && mode != QRAM_MODE_PLAIN) return fail(c, QRAM_E_INVAL, "bad mode");
   HIPCHK(c, hipSetDevice(c->device));
   const uint32_t nb = batch_size(c, std::max<uint32_t>(ntraj, 1u));
   Plan pl;
@@ -988,7 +1055,7 @@ qram_status qram_footprint(qram_ctx *c, qram_mode mode, uint32_t ntraj,
 
 qram_status qram_reserve(qram_ctx *c, qram_mode mode, uint32_t ntraj) {
   if (!c) return QRAM_E_INVAL;
-  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return fail(c, QRAM_E_INVAL, "bad mode");
+  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED && mode != QRAM_MODE_PLAIN) return fail(c, QRAM_E_INVAL, "bad mode");
   HIPCHK(c, hipSetDevice(c->device));
   const uint32_t nb = batch_size(c, std::max<uint32_t>(ntraj, 1u));
   Plan pl;
@@ -1123,6 +1190,12 @@ qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,
 qram_status qram_set_launch(qram_ctx *c, qram_mode mode, int slots_per_thread,
                             int schedule) {
   if (!c) return QRAM_E_INVAL;
+  if (mode == QRAM_MODE_PLAIN) {  // workgroups per compute unit
+    if (slots_per_thread < 0 || slots_per_thread > 8) return fail(c, QRAM_E_INVAL, "plain mode: 0..8 workgroups per CU");
+    c->plain_per_cu = slots_per_thread ? slots_per_thread : 2;
+    c->spt[mode] = slots_per_thread;
+    return QRAM_OK;
+  }
   if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return fail(c, QRAM_E_INVAL, "bad mode");
   if (slots_per_thread != 0 && slots_per_thread != 4 && slots_per_thread != 8 && slots_per_thread != 16 &&
       slots_per_thread != 32 && slots_per_thread != 64)
@@ -1136,6 +1209,11 @@ qram_status qram_set_launch(qram_ctx *c, qram_mode mode, int slots_per_thread,
 qram_status qram_get_launch(const qram_ctx *c, qram_mode mode,
                             int *slots_per_thread, int *schedule) {
   if (!c || !slots_per_thread || !schedule) return QRAM_E_INVAL;
+  if (mode == QRAM_MODE_PLAIN) {
+    *slots_per_thread = c->plain_per_cu;
+    *schedule = 0;
+    return QRAM_OK;
+  }
   if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return QRAM_E_INVAL;
   *slots_per_thread = c->spt[mode] ? c->spt[mode] : 16;
   *schedule = c->schedule[mode];
@@ -1255,11 +1333,11 @@ qram_status qram_stage_times(qram_ctx *c, double *ms, uint32_t *nbatches) {
 // optionally exporting its final components and its jump log.
 static qram_status run_single(qram_ctx *c, int mode, uint64_t seed, uint32_t traj, bool forced,
                               const uint32_t *cand_L, uint32_t ncand, const double *u_aux, double u_fin,
-                              uint32_t *h_exp, uint32_t exp_cap, uint32_t *h_jlog, uint32_t jcap,
+                              uint32_t *h_exp, uint32_t exp_cap, double *h_amp, uint32_t *h_jlog, uint32_t jcap,
                               uint32_t *h_njl, double *fid, qram_traj_stats *stt) {
   qram_status st = check_args(c, traj, 1);
   if (st) return st;
-  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return fail(c, QRAM_E_INVAL, "bad mode");
+  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED && mode != QRAM_MODE_PLAIN) return fail(c, QRAM_E_INVAL, "bad mode");
   if (!fid) return fail(c, QRAM_E_INVAL, "null argument");
   if (forced) {
     if (!u_aux || (ncand && !cand_L)) return fail(c, QRAM_E_INVAL, "null argument");
@@ -1301,6 +1379,11 @@ static qram_status run_single(qram_ctx *c, int mode, uint64_t seed, uint32_t tra
     if ((st = grow(c, &c->dexp, &c->dexp_cap, ncomp * rec_words))) return st;
     HIPCHK(c, hipMemsetAsync(c->dexp, 0, ncomp * rec_words * 4, c->stream));
     r.exp = c->dexp;
+    if (mode == QRAM_MODE_PLAIN) {
+      if ((st = grow(c, &c->dexpamp, &c->dexpamp_cap, ncomp * 2))) return st;
+      HIPCHK(c, hipMemsetAsync(c->dexpamp, 0, ncomp * 16, c->stream));
+      r.expamp = c->dexpamp;
+    }
   }
   if (h_njl) {
     if ((st = grow(c, &c->djlog, &c->djlog_cap, std::max<size_t>(jcap, 1)))) return st;
@@ -1316,6 +1399,8 @@ static qram_status run_single(qram_ctx *c, int mode, uint64_t seed, uint32_t tra
   if (stt) HIPCHK(c, hipMemcpyAsync(stt, c->st_tmp, sizeof(qram_traj_stats), hipMemcpyDeviceToHost, c->stream));
   if (h_exp)
     HIPCHK(c, hipMemcpyAsync(h_exp, c->dexp, ncomp * rec_words * 4, hipMemcpyDeviceToHost, c->stream));
+  if (h_exp && h_amp && mode == QRAM_MODE_PLAIN)
+    HIPCHK(c, hipMemcpyAsync(h_amp, c->dexpamp, ncomp * 16, hipMemcpyDeviceToHost, c->stream));
   if (h_njl) {
     HIPCHK(c, hipMemcpyAsync(h_njl, c->djn, 4, hipMemcpyDeviceToHost, c->stream));
     if (jcap && h_jlog) HIPCHK(c, hipMemcpyAsync(h_jlog, c->djlog, (size_t)jcap * 4, hipMemcpyDeviceToHost, c->stream));
@@ -1327,15 +1412,18 @@ static qram_status run_single(qram_ctx *c, int mode, uint64_t seed, uint32_t tra
 qram_status qram_run_forced(qram_ctx *c, qram_mode mode, const uint32_t *cand_L,
                             uint32_t ncand, const double *u_aux, double u_fin,
                             double *fid, qram_traj_stats *stt) {
-  return run_single(c, mode, 0, 0, true, cand_L, ncand, u_aux, u_fin, nullptr, 0, nullptr, 0, nullptr, fid, stt);
+  return run_single(c, mode, 0, 0, true, cand_L, ncand, u_aux, u_fin, nullptr, 0, nullptr, nullptr, 0, nullptr, fid,
+                    stt);
 }
 
 qram_status qram_export_state(qram_ctx *c, qram_mode mode, uint64_t seed, uint32_t traj,
                               const uint32_t *cand_L, uint32_t ncand, const double *u_aux,
-                              double u_fin, uint32_t *comp, uint32_t comp_cap, uint32_t *jlog,
-                              uint32_t jcap, uint32_t *njl, double *fid, qram_traj_stats *stt) {
+                              double u_fin, uint32_t *comp, uint32_t comp_cap, double *amp,
+                              uint32_t *jlog, uint32_t jcap, uint32_t *njl, double *fid,
+                              qram_traj_stats *stt) {
   if (!comp || !njl) return fail(c, QRAM_E_INVAL, "comp and njl are required");
-  return run_single(c, mode, seed, traj, u_aux != nullptr, cand_L, ncand, u_aux, u_fin, comp, comp_cap, jlog,
+  if (mode == QRAM_MODE_PLAIN && !amp) return fail(c, QRAM_E_INVAL, "the plain mode exports amplitudes: amp is required");
+  return run_single(c, mode, seed, traj, u_aux != nullptr, cand_L, ncand, u_aux, u_fin, comp, comp_cap, amp, jlog,
                     jcap, njl, fid, stt);
 }
 
@@ -1343,7 +1431,7 @@ qram_status qram_run_jumplog(qram_ctx *c, qram_mode mode, uint64_t seed, uint64_
                              uint32_t ntraj, double *fid, qram_traj_stats *stt, uint32_t *jlog,
                              uint32_t jcap, uint32_t *njl) {
   if (!c) return fail(nullptr, QRAM_E_INVAL, "null context");
-  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return fail(c, QRAM_E_INVAL, "bad mode");
+  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED && mode != QRAM_MODE_PLAIN) return fail(c, QRAM_E_INVAL, "bad mode");
   if (!fid || !njl || (jcap && !jlog)) return fail(c, QRAM_E_INVAL, "null argument");
   return run_mode(c, (int)mode, seed, traj0, ntraj, nullptr, nullptr, fid, stt, c->stream, true, jlog, jcap, njl);
 }

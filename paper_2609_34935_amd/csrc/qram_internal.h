@@ -75,6 +75,7 @@ struct Tables {
   uint16_t cntA[MAXT][MAXN];       // exposure of address token t through s
   uint16_t cntD[MAXT][MAXK];       // exposure of data token b through s
   uint16_t cntR[MAXT];             // qutrit: router exposure through s
+  double sg;                       // sqrt(gamma), the amplitude of a jump
 };
 
 struct Run {
@@ -117,6 +118,13 @@ struct Run {
   uint32_t *jlog;        // [ntraj * jcap] jump log: site | level << 16 | slice << 24
   uint32_t *jn;          // [ntraj] jump-log entries of each trajectory (may exceed jcap)
   uint32_t jcap;         // jump-log entries kept per trajectory
+  double *expamp;        // [D * K2 * 2] plain mode: amplitude of each exported record
+  // plain full evolution: per-workgroup component lists (pool, prec uint16
+  // words each), amplitudes, hit flags and finalize scratch
+  uint32_t prec;
+  double *pamp;          // [grid * E * 2]
+  uint8_t *phit;         // [grid * E]
+  double *pgrp;          // [grid * threads * K2 * 2]
 };
 
 // Export record of one component (test entry), (3 + lmax) words:
@@ -150,6 +158,13 @@ __host__ __device__ inline uint32_t walk_table_bytes(int T, int n, int k) {
   return (uint32_t)(T * (n + k));
 }
 int evolve_occupancy(int enc, bool state_lds, int threads, uint32_t lds_bytes);
+// plain full evolution (every component explicit, slice by slice)
+constexpr int PLAIN_THREADS = 256;
+constexpr int PLAIN_EXTRA = 8;  // list entries beyond the excitation bound
+uint32_t plain_lds_bytes(int M);
+int plain_occupancy(int enc, int threads, uint32_t lds_bytes);
+hipError_t launch_plain(const Tables *tb, const Run &rp, int enc, uint32_t grid, int threads, uint32_t lds_bytes,
+                        hipStream_t s);
 hipError_t evolve_prepare(int lds_max, int *dyn_max);
 
 }  // namespace qr

@@ -1,0 +1,531 @@
+// Plain full evolution (gfx950): the comparator of the pruned simulator.
+// One workgroup per trajectory carries every component of every branch
+// through the T-1 slices of the schedule, each with its own explicit list of
+// excited tree sites and its own complex FP64 amplitude:
+//   - each slice applies the schedule's gates to every component's list
+//     (the bucket-brigade schedule of Sec. II A, the gate set of App. C),
+//   - then one joint damping layer (Eq. layerkraus, Theorem 4): the
+//     components hit by a candidate of the slice are weighed (Eq.
+//     maskweight), one auxiliary draw picks x*, J = C_s cap X(x*), and K_J
+//     multiplies every survivor by sqrt(gamma)^|J| a^(|X|-|J|),
+//   - at the end the second Hadamard wall (qubit encoding), the tree
+//     measurement and the fidelity with the ideal output (App. C).
+// Nothing is predicted: no closed-form no-jump walk, no implicit components,
+// no closed-form finalize.  Same random numbers as the other modes, so the
+// same history, jumps and fidelity up to rounding.
+#include "qram_device.h"
+
+namespace qr {
+namespace {
+
+constexpr int PL_GATED = 16;  // gated nodes of one qutrit store / fetch at most
+
+// Explicit site list of one component in the workgroup's pool: [0] count
+// (PL_DEAD once annihilated), [1] bus word, [2 ..] sites; a qutrit router
+// site carries its level in bit 15 (set: R, clear: L).
+constexpr uint16_t PL_DEAD = 0xFFFFu;
+
+template <int ENC>
+struct PList {
+  uint16_t *r;
+  int cap;
+  static constexpr uint32_t SM = ENC == QUTRIT ? 0x7FFFu : 0xFFFFu;
+  __device__ __forceinline__ int cnt() const { return r[0]; }
+  __device__ __forceinline__ uint32_t raw(int j) const { return r[2 + j]; }
+  __device__ __forceinline__ int find(uint32_t q) const {
+    const int c = r[0];
+    for (int j = 0; j < c; ++j)
+      if ((r[2 + j] & SM) == q) return j;
+    return -1;
+  }
+  __device__ __forceinline__ void remove(int j) {
+    const int c = r[0] - 1;
+    r[2 + j] = r[2 + c];
+    r[0] = (uint16_t)c;
+  }
+  __device__ __forceinline__ void add(uint32_t x, uint32_t *err) {
+    const int c = r[0];
+    if (c >= cap) {
+      atomicOr(err, ERR_LIST);
+      return;
+    }
+    r[2 + c] = (uint16_t)x;
+    r[0] = (uint16_t)(c + 1);
+  }
+  __device__ __forceinline__ void toggle(uint32_t q, uint32_t *err) {
+    const int j = find(q);
+    if (j >= 0)
+      remove(j);
+    else
+      add(q, err);
+  }
+  // router of node v: qubit 0/1 (route left / right); qutrit -1 (W), 0 (L), 1 (R)
+  __device__ __forceinline__ int dir(uint32_t v) const {
+    const int j = find(2 * v);
+    if (ENC == QUBIT) return j >= 0 ? 1 : 0;
+    if (j < 0) return -1;
+    return (r[2 + j] & LV_R_BIT) ? 1 : 0;
+  }
+};
+
+// Nodes of layer l whose parent routes into them (the root for l = 0),
+// collected before a qutrit store changes the list.
+template <int ENC>
+__device__ __forceinline__ int gated_nodes(const PList<ENC> &L, int l, uint32_t *gv, uint32_t *err) {
+  if (l == 0) {
+    gv[0] = 0;
+    return 1;
+  }
+  int ng = 0;
+  for (int j = 0; j < L.cnt(); ++j) {
+    const uint32_t x = L.raw(j), q = x & PList<ENC>::SM;
+    if (q & 1u) continue;
+    const uint32_t p = q >> 1;
+    if (layer_of(p) != l - 1) continue;
+    if (ng < PL_GATED)
+      gv[ng++] = 2 * p + 1 + ((x & LV_R_BIT) ? 1u : 0u);
+    else
+      atomicOr(err, ERR_LIST);
+  }
+  return ng;
+}
+
+// The gates of slice s on one component (address a).  Returns true when the
+// qubit fetch flips its sign.  Every gate is a permutation of basis labels;
+// it is applied entry by entry from the list as it was before the gate.
+template <int ENC>
+__device__ bool plain_gates(const Tables *__restrict__ tb, int s, PList<ENC> L, uint32_t a, uint32_t *err) {
+  const int n = tb->n;
+  bool flip = false;
+  const int ct = tb->copy_t[s];
+  if (ct >= 0 && ((a >> (n - 1 - ct)) & 1u)) L.toggle(1, err);  // CNOT into d_0
+  const int sl = tb->store_l[s];
+  if (sl >= 0) {
+    if (ENC == QUBIT) {  // SWAP(a_v, d_v) on every node of the layer
+      for (int j = 0; j < L.cnt(); ++j) {
+        const uint32_t q = L.raw(j);
+        if (layer_of(q >> 1) == sl) L.r[2 + j] = (uint16_t)(q ^ 1u);
+      }
+    } else {  // (W,b) <-> (L or R by b, 0) on the gated nodes
+      uint32_t gv[PL_GATED];
+      const int ng = gated_nodes<ENC>(L, sl, gv, err);
+      for (int g = 0; g < ng && g < PL_GATED; ++g) {
+        const uint32_t v = gv[g];
+        const int jr = L.find(2 * v), jd = L.find(2 * v + 1);
+        if (jr < 0) {  // W: the data bit moves into the router
+          if (jd >= 0) {
+            L.remove(jd);
+            L.add(2 * v | LV_R_BIT, err);
+          } else {
+            L.add(2 * v, err);
+          }
+        } else if (jd < 0) {  // (L,0) -> (W,0), (R,0) -> (W,1)
+          const bool isR = (L.raw(jr) & LV_R_BIT) != 0;
+          L.remove(jr);
+          if (isR) L.add(2 * v + 1, err);
+        }
+      }
+    }
+  }
+  const uint32_t cm = tb->cswap[s];
+  if (cm) {  // SWAP(d_v, d_child) on the layers of the slice, child by v's router
+    for (int j = 0; j < L.cnt(); ++j) {
+      const uint32_t q = L.raw(j) & PList<ENC>::SM;
+      if (!(q & 1u)) continue;
+      const uint32_t v = q >> 1;
+      const int l = layer_of(v);
+      if ((cm >> l) & 1u) {
+        const int d = L.dir(v);
+        if (d >= 0) L.r[2 + j] = (uint16_t)(2 * (2 * v + 1 + (uint32_t)d) + 1);
+      } else if (l >= 1 && ((cm >> (l - 1)) & 1u)) {
+        const uint32_t p = (v - 1) >> 1;
+        const int d = L.dir(p);
+        if (d >= 0 && v == 2 * p + 1 + (uint32_t)d) L.r[2 + j] = (uint16_t)(2 * p + 1);
+      }
+    }
+  }
+  const int bb = tb->bus_b[s];
+  if (bb >= 0) {  // SWAP(bus_b, d_0)
+    const int j = L.find(1);
+    const uint32_t bus = L.r[1];
+    const bool bbit = (bus >> bb) & 1u;
+    if (j >= 0 && !bbit) {
+      L.remove(j);
+      L.r[1] = (uint16_t)(bus | (1u << bb));
+    } else if (j < 0 && bbit) {
+      L.add(1, err);
+      L.r[1] = (uint16_t)(bus & ~(1u << bb));
+    }
+  }
+  const int fb = tb->fetch_b[s];
+  if (fb >= 0) {
+    const uint32_t v0 = (1u << (n - 1)) - 1u;
+    if (ENC == QUBIT) {  // phase kickback: -1 on d_v = 1 when the routed cell holds 1
+      for (int j = 0; j < L.cnt(); ++j) {
+        const uint32_t q = L.raw(j);
+        if (!(q & 1u) || (q >> 1) < v0) continue;
+        const uint32_t v = q >> 1;
+        const uint32_t cell = 2 * (v - v0) + (uint32_t)L.dir(v);
+        if ((tb->mem[cell] >> fb) & 1u) flip = !flip;
+      }
+    } else {  // d_v ^= bit of the routed cell when r_v != W
+      uint32_t gv[PL_GATED];
+      int ng = 0;
+      for (int j = 0; j < L.cnt(); ++j) {
+        const uint32_t x = L.raw(j), q = x & PList<ENC>::SM;
+        if ((q & 1u) || (q >> 1) < v0) continue;
+        const uint32_t v = q >> 1;
+        const uint32_t cell = 2 * (v - v0) + ((x & LV_R_BIT) ? 1u : 0u);
+        if (!((tb->mem[cell] >> fb) & 1u)) continue;
+        if (ng < PL_GATED)
+          gv[ng++] = 2 * v + 1;
+        else
+          atomicOr(err, ERR_LIST);
+      }
+      for (int g = 0; g < ng && g < PL_GATED; ++g) L.toggle(gv[g], err);
+    }
+  }
+  return flip;
+}
+
+struct PlainSm {
+  uint32_t *cbm;     // candidate bitmap of the slice [(M + 31) / 32]
+  uint32_t *cstart;  // [MAXT + 1] first candidate of each slice
+  uint32_t *J;       // [JMAX] joint outcome: site | level << 16
+  double *red;       // [16 * 8] reduction buffer
+  int *misc;         // [8]
+};
+
+__host__ __device__ inline uint32_t plain_sm_bytes(int M) {
+  return (uint32_t)(((M + 31) / 32) * 4 + (MAXT + 1) * 4 + JMAX * 4 + 16 * 8 * 8 + 8 * 4 + 64);
+}
+
+__device__ inline PlainSm plain_carve(unsigned char *base, int M) {
+  PlainSm s;
+  size_t o = 0;
+  s.red = reinterpret_cast<double *>(base + o);
+  o += 16 * 8 * 8;
+  s.cbm = reinterpret_cast<uint32_t *>(base + o);
+  o += (size_t)((M + 31) / 32) * 4;
+  s.cstart = reinterpret_cast<uint32_t *>(base + o);
+  o += (MAXT + 1) * 4;
+  s.J = reinterpret_cast<uint32_t *>(base + o);
+  o += JMAX * 4;
+  s.misc = reinterpret_cast<int *>(base + o);
+  return s;
+}
+
+__device__ __forceinline__ double abs2(double2 z) { return z.x * z.x + z.y * z.y; }
+
+template <int ENC>
+__global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, const Run R_) {
+  const Run *rp = &R_;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int n = tb->n, T = tb->T, M = tb->M, D = tb->D, k = tb->k;
+  const int K2 = ENC == QUBIT ? tb->K2 : 1;
+  const int kb = ENC == QUBIT ? k : 0;
+  const uint32_t kmask = (1u << k) - 1u;
+  const uint32_t E = (uint32_t)(D * K2);
+  const int rec = rp->prec;
+  const int lcap = rec - 2;
+  PlainSm sm = plain_carve(smem, M);
+  uint16_t *pool = rp->pool + (size_t)blockIdx.x * E * rec;
+  double2 *amp = reinterpret_cast<double2 *>(rp->pamp) + (size_t)blockIdx.x * E;
+  uint8_t *hitf = rp->phit + (size_t)blockIdx.x * E;
+  double2 *grp = reinterpret_cast<double2 *>(rp->pgrp) + ((size_t)blockIdx.x * nthr + tid) * K2;
+  const double *__restrict__ apow = tb->apow + tb->emax;
+  const double sg = tb->sg;
+  const uint32_t ccap = rp->cand_cap;
+  for (int w = tid; w < (M + 31) / 32; w += nthr) sm.cbm[w] = 0u;
+
+  for (uint32_t tj = blockIdx.x; tj < rp->ntraj; tj += gridDim.x) {
+    const uint32_t traj = rp->traj0 + tj;
+    const uint32_t nct = min(rp->ncand[tj], ccap);
+    const uint32_t *__restrict__ cand = rp->cand + (size_t)tj * ccap;
+    const uint32_t ref = rp->ref[tj];
+    for (uint32_t j = tid; j <= nct; j += nthr) {  // first candidate of each slice
+      const int sj = j < nct ? (int)(cand[j] / (uint32_t)M) + 1 : T;
+      const int sp = j > 0 ? (int)(cand[j - 1] / (uint32_t)M) + 1 : 0;
+      for (int ss = sp + 1; ss <= sj; ++ss) sm.cstart[ss] = j;
+    }
+    // the data-loading input after the first wall (qubit: 2^k bus words of
+    // amplitude 2^(-n/2) 2^(-k/2); qutrit: bus word 0, amplitude 2^(-n/2))
+    const double c0 = 1.0 / sqrt((double)D * (double)K2);
+    for (uint32_t x = tid; x < E; x += nthr) {
+      uint16_t *r = pool + (size_t)x * rec;
+      r[0] = 0;
+      r[1] = (uint16_t)(ENC == QUBIT ? (x & (uint32_t)(K2 - 1)) : 0u);
+      amp[x] = make_double2(c0, 0.0);
+    }
+    int njumps = 0, first_jump = 0;
+    uint32_t jl_n = 0;
+    __syncthreads();
+
+    for (int s = 1; s < T; ++s) {
+      const uint32_t cb = sm.cstart[s], ce = sm.cstart[s + 1];
+      const uint32_t nc = ce - cb;
+      for (uint32_t j = cb + tid; j < ce; j += nthr) {
+        const uint32_t q = cand[j] - (uint32_t)(s - 1) * M;
+        atomicOr(&sm.cbm[q >> 5], 1u << (q & 31));
+      }
+      __syncthreads();
+      // gates, then (without candidates) K0 at once; with candidates the
+      // hit test of every component against the slice's candidate set
+      int anyhit = 0;
+      for (uint32_t x = tid; x < E; x += nthr) {
+        PList<ENC> L{pool + (size_t)x * rec, lcap};
+        if (L.cnt() == PL_DEAD) continue;
+        const uint32_t a = x >> kb;
+        if (plain_gates<ENC>(tb, s, L, a, rp->err)) amp[x] = make_double2(-amp[x].x, -amp[x].y);
+        if (nc == 0) {
+          const double f = apow[L.cnt()];
+          amp[x] = make_double2(amp[x].x * f, amp[x].y * f);
+          continue;
+        }
+        uint8_t h = 0;
+        for (int j = 0; j < L.cnt() && !h; ++j) {
+          const uint32_t q = L.raw(j) & PList<ENC>::SM;
+          h = (uint8_t)((sm.cbm[q >> 5] >> (q & 31)) & 1u);
+        }
+        hitf[x] = h;
+        anyhit |= h;
+      }
+      if (nc == 0) continue;  // (the bitmap is already clean)
+      anyhit = __syncthreads_or(anyhit);
+      int nJ = 0;
+      if (anyhit) {
+        // Eq. maskweight: the empty-mask block and the hit components
+        double acc[2] = {0.0, 0.0};
+        for (uint32_t x = tid; x < E; x += nthr) {
+          if (pool[(size_t)x * rec] == PL_DEAD) continue;
+          acc[hitf[x] ? 1 : 0] += abs2(amp[x]);
+        }
+        block_sum<2>(acc, sm.red);
+        const double wall = acc[0] + acc[1];
+        const double u = rp->forced ? rp->uaux[s] : uniform53(rp->seed, (uint32_t)s, 0, traj, 2u);
+        const double r = u * wall;
+        if (!(r < acc[0])) {
+          // x*: first hit component, in label order, whose running weight
+          // exceeds r - w(empty); the last hit one if rounding runs out
+          const double r2 = r - acc[0];
+          double base = 0.0;
+          int pick = -1, last = -1;
+          for (uint32_t x0 = 0; x0 < E && pick < 0; x0 += (uint32_t)nthr) {
+            const uint32_t x = x0 + (uint32_t)tid;
+            double w = 0.0;
+            bool h = false;
+            if (x < E && pool[(size_t)x * rec] != PL_DEAD && hitf[x]) {
+              h = true;
+              w = abs2(amp[x]);
+            }
+            __syncthreads();  // (the scan buffer is reused)
+            const double ex = block_excl_scan(w, sm.red);
+            __syncthreads();
+            if (tid == nthr - 1) sm.red[64] = ex + w;
+            const int mine = (h && base + ex + w > r2) ? (int)x : 0x7FFFFFFF;
+            int lowest = mine;
+            for (int off = 32; off > 0; off >>= 1) lowest = min(lowest, __shfl_xor(lowest, off, 64));
+            if ((tid & 63) == 0) sm.misc[1 + (tid >> 6)] = lowest;
+            int lastm = h ? (int)x : -1;
+            for (int off = 32; off > 0; off >>= 1) lastm = max(lastm, __shfl_xor(lastm, off, 64));
+            if ((tid & 63) == 0) reinterpret_cast<int *>(sm.J)[JMAX - 1 - (tid >> 6)] = lastm;
+            __syncthreads();
+            int best = 0x7FFFFFFF;
+            for (int w8 = 0; w8 < nthr / 64; ++w8) {
+              best = min(best, sm.misc[1 + w8]);
+              last = max(last, reinterpret_cast<int *>(sm.J)[JMAX - 1 - w8]);
+            }
+            base += sm.red[64];
+            if (best != 0x7FFFFFFF) pick = best;
+            __syncthreads();
+          }
+          if (pick < 0) pick = last;
+          // J = the slice's candidates among x*'s excited sites, with levels
+          if (tid == 0) {
+            PList<ENC> L{pool + (size_t)pick * rec, lcap};
+            int m = 0;
+            for (int j = 0; j < L.cnt(); ++j) {
+              const uint32_t x = L.raw(j), q = x & PList<ENC>::SM;
+              if (!((sm.cbm[q >> 5] >> (q & 31)) & 1u)) continue;
+              const uint32_t lev = (ENC == QUTRIT && (x & LV_R_BIT)) ? 2u : 1u;
+              if (m < JMAX) sm.J[m++] = q | (lev << 16);
+            }
+            // ascending site order, as the oracle logs them
+            for (int i = 1; i < m; ++i)
+              for (int j = i; j > 0 && (sm.J[j] & 0xFFFFu) < (sm.J[j - 1] & 0xFFFFu); --j) {
+                const uint32_t t = sm.J[j];
+                sm.J[j] = sm.J[j - 1];
+                sm.J[j - 1] = t;
+              }
+            sm.misc[0] = m;
+          }
+          __syncthreads();
+          nJ = sm.misc[0];
+        }
+      }
+      // K_J on every component: survivors carry J's sites at J's levels
+      for (uint32_t x = tid; x < E; x += nthr) {
+        PList<ENC> L{pool + (size_t)x * rec, lcap};
+        if (L.cnt() == PL_DEAD) continue;
+        bool ok = true;
+        for (int c = 0; c < nJ && ok; ++c) {
+          const uint32_t q = sm.J[c] & 0xFFFFu, lev = sm.J[c] >> 16;
+          const int j = L.find(q);
+          ok = j >= 0 && ((ENC == QUTRIT && (L.raw(j) & LV_R_BIT)) ? 2u : 1u) == lev;
+        }
+        if (!ok) {
+          L.r[0] = PL_DEAD;
+          amp[x] = make_double2(0.0, 0.0);
+          continue;
+        }
+        double f = apow[L.cnt() - nJ];
+        for (int c = 0; c < nJ; ++c) f *= sg;
+        amp[x] = make_double2(amp[x].x * f, amp[x].y * f);
+        for (int c = 0; c < nJ; ++c) L.remove(L.find(sm.J[c] & 0xFFFFu));
+      }
+      if (nJ > 0) {
+        ++njumps;
+        if (!first_jump) first_jump = s;
+        if (rp->jlog && tid == 0)
+          for (int c = 0; c < nJ; ++c, ++jl_n)
+            if (jl_n < rp->jcap) rp->jlog[(size_t)tj * rp->jcap + jl_n] = sm.J[c] | ((uint32_t)s << 24);
+      }
+      __syncthreads();
+      for (uint32_t j = cb + tid; j < ce; j += nthr) {  // leave the bitmap clean
+        const uint32_t q = cand[j] - (uint32_t)(s - 1) * M;
+        sm.cbm[q >> 5] = 0u;
+      }
+      __syncthreads();
+    }
+
+    // the last slice may have ended without a barrier (no candidates): every
+    // thread's lists must be final before any thread reads another's
+    __syncthreads();
+    if (rp->exp && tj == 0) {  // test entry: every component's final list and amplitude
+      const uint32_t rw = 3u + (uint32_t)tb->lmax;
+      for (uint32_t x = tid; x < E; x += nthr) {
+        const uint16_t *r = pool + (size_t)x * rec;
+        uint32_t *o = rp->exp + (size_t)x * rw;
+        if (r[0] == PL_DEAD) continue;
+        const uint32_t m = min((uint32_t)r[0], (uint32_t)tb->lmax);
+        o[0] = (x >> kb) | ((uint32_t)r[1] << 16) | EXP_PRESENT;
+        o[1] = 0;
+        o[2] = m;
+        for (uint32_t j = 0; j < m; ++j) {
+          const uint32_t e = r[2 + j];
+          const uint32_t q = e & PList<ENC>::SM, lev = (ENC == QUTRIT && (e & LV_R_BIT)) ? 2u : 1u;
+          o[3 + j] = q | (lev << 16);
+        }
+        rp->expamp[2 * x] = amp[x].x;
+        rp->expamp[2 * x + 1] = amp[x].y;
+      }
+    }
+    // second wall (qubit), tree measurement, fidelity.  Components with an
+    // excited tree are orthogonal to the ideal output and to every other
+    // group, so only their weight counts; the ground components of an
+    // address are grouped by bus word before the wall.
+    double fin[5] = {0, 0, 0, 0, 0};  // overlap re, im, w_ground, w_excited, ref alive
+    const double ci = 1.0 / sqrt((double)D);
+    if (ENC == QUBIT) {
+      const double h = 1.0 / sqrt((double)K2);
+      for (int i = tid; i < D; i += nthr) {
+        bool any = false;
+        for (int b = 0; b < K2; ++b) grp[b] = make_double2(0.0, 0.0);
+        for (int b = 0; b < K2; ++b) {
+          const uint32_t x = (uint32_t)i * K2 + (uint32_t)b;
+          const uint16_t *r = pool + (size_t)x * rec;
+          if (r[0] == PL_DEAD) continue;
+          if ((uint32_t)i == ref) fin[4] = 1.0;
+          if (r[0] != 0) {
+            fin[3] += abs2(amp[x]);
+            continue;
+          }
+          const uint32_t bw = r[1] & (uint32_t)(K2 - 1);
+          grp[bw] = make_double2(grp[bw].x + amp[x].x, grp[bw].y + amp[x].y);
+          any = true;
+        }
+        if (!any) continue;
+        for (int len = 1; len < K2; len <<= 1)  // Walsh-Hadamard transform in place
+          for (int b = 0; b < K2; ++b)
+            if (!(b & len)) {
+              const double2 u = grp[b], v = grp[b + len];
+              grp[b] = make_double2(u.x + v.x, u.y + v.y);
+              grp[b + len] = make_double2(u.x - v.x, u.y - v.y);
+            }
+        const uint32_t want = tb->mem[i] & kmask;
+        for (int c = 0; c < K2; ++c) {
+          const double2 v = make_double2(grp[c].x * h, grp[c].y * h);
+          fin[2] += abs2(v);
+          if ((uint32_t)c == want) {
+            fin[0] += ci * v.x;
+            fin[1] += ci * v.y;
+          }
+        }
+      }
+    } else {
+      for (uint32_t x = tid; x < E; x += nthr) {
+        const uint16_t *r = pool + (size_t)x * rec;
+        if (r[0] == PL_DEAD) continue;
+        if (x == ref) fin[4] = 1.0;
+        if (r[0] != 0) {
+          fin[3] += abs2(amp[x]);
+          continue;
+        }
+        fin[2] += abs2(amp[x]);
+        if ((uint32_t)r[1] == (tb->mem[x] & kmask)) {
+          fin[0] += ci * amp[x].x;
+          fin[1] += ci * amp[x].y;
+        }
+      }
+    }
+    block_sum<5>(fin, sm.red);
+    if (tid == 0) {
+      const double ov2 = fin[0] * fin[0] + fin[1] * fin[1];
+      const double wg = fin[2], wt = fin[2] + fin[3];
+      const double uf = rp->forced ? rp->ufin : uniform53(rp->seed, 0, 0, traj, 3u);
+      const bool qg = uf * wt < wg;
+      rp->fid[tj] = (qg && wg > 0.0) ? ov2 / wg : 0.0;
+      if (rp->jn) rp->jn[tj] = jl_n;
+      if (rp->st) {
+        qram_traj_stats o;
+        o.n_cand = rp->ncand[tj];
+        o.n_bad = rp->nbad[tj];
+        o.ref_addr = ref;
+        o.n_explicit = E;
+        o.n_jumps = (uint16_t)njumps;
+        o.first_jump_slice = (uint16_t)first_jump;
+        o.ref_survived = (uint8_t)(ref != 0xFFFFFFFFu && fin[4] > 0.0);
+        o.q_ground = (uint8_t)qg;
+        o.flags = (uint8_t)((rp->ncand[tj] > ccap ? 1 : 0));
+        o.pad = 0;
+        o.fid_pre = wt > 0.0 ? ov2 / wt : 0.0;
+        rp->st[tj] = o;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+uint32_t plain_lds_bytes(int M) { return plain_sm_bytes(M); }
+
+int plain_occupancy(int enc, int threads, uint32_t lds_bytes) {
+  int blocks = 0;
+  const hipError_t e = enc == QUBIT
+                           ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<QUBIT>, threads, lds_bytes)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<QUTRIT>, threads, lds_bytes);
+  return e == hipSuccess ? blocks : 0;
+}
+
+hipError_t launch_plain(const Tables *tb, const Run &rp, int enc, uint32_t grid, int threads, uint32_t lds_bytes,
+                        hipStream_t s) {
+  if (enc == QUBIT)
+    hipLaunchKernelGGL(k_plain<QUBIT>, dim3(grid), dim3(threads), lds_bytes, s, tb, rp);
+  else
+    hipLaunchKernelGGL(k_plain<QUTRIT>, dim3(grid), dim3(threads), lds_bytes, s, tb, rp);
+  return hipGetLastError();
+}
+
+}  // namespace qr

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqram_hip.so")
 
 QRAM_QUTRIT, QRAM_QUBIT = 0, 1
-QRAM_MODE_FULL, QRAM_MODE_PRUNED = 0, 1
+QRAM_MODE_FULL, QRAM_MODE_PRUNED, QRAM_MODE_PLAIN = 0, 1, 2
 STATUS = {0: "QRAM_OK", -1: "QRAM_E_INVAL", -2: "QRAM_E_NOMEM", -3: "QRAM_E_DEVICE",
           -4: "QRAM_E_RANGE", -5: "QRAM_E_CAPACITY"}
 
@@ -44,7 +44,7 @@ EXPORTS = [
     "qram_fidelity", "qram_set_launch", "qram_get_launch", "qram_autotune",
     "qram_last_kernel_ms", "qram_set_timing", "qram_stage_times", "qram_stage_launches", "qram_set_option",
     "qram_run_forced", "qram_footprint", "qram_reserve", "qram_errors", "qram_run_pruned_async_noalloc",
-    "qram_export_state", "qram_run_jumplog",
+    "qram_export_state", "qram_run_jumplog", "qram_run_plain", "qram_run_plain_async",
     "qram_server_create", "qram_server_submit", "qram_server_poll", "qram_server_wait",
     "qram_server_fidelities", "qram_server_release", "qram_server_destroy",
 ]
@@ -82,9 +82,10 @@ def load_library(path: str = LIB_PATH):
     L.qram_last_error.argtypes = [vp]
     L.qram_last_error.restype = C.c_char_p
     L.qram_sample_faults.argtypes = [vp, u64, u64, u32, p(u32), p(u64), p(u32), p(u64), p(u32), u64]
-    for f in (L.qram_run_full, L.qram_run_pruned):
+    for f in (L.qram_run_full, L.qram_run_pruned, L.qram_run_plain):
         f.argtypes = [vp, u64, u64, u32, p(f64), vp]
-    for f in (L.qram_run_full_async, L.qram_run_pruned_async, L.qram_run_pruned_async_noalloc):
+    for f in (L.qram_run_full_async, L.qram_run_pruned_async, L.qram_run_pruned_async_noalloc,
+              L.qram_run_plain_async):
         f.argtypes = [vp, u64, u64, u32, vp, vp, vp]
     L.qram_fidelity.argtypes = [p(f64), u32, p(f64), p(f64)]
     L.qram_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int]
@@ -92,8 +93,8 @@ def load_library(path: str = LIB_PATH):
     L.qram_autotune.argtypes = [vp, C.c_int, u64, u64, u32, p(f64)]
     L.qram_last_kernel_ms.argtypes = [vp, p(f64)]
     L.qram_run_forced.argtypes = [vp, C.c_int, p(u32), u32, p(f64), f64, p(f64), vp]
-    L.qram_export_state.argtypes = [vp, C.c_int, u64, u32, p(u32), u32, p(f64), f64, p(u32), u32, p(u32), u32,
-                                    p(u32), p(f64), vp]
+    L.qram_export_state.argtypes = [vp, C.c_int, u64, u32, p(u32), u32, p(f64), f64, p(u32), u32, p(f64),
+                                    p(u32), u32, p(u32), p(f64), vp]
     L.qram_run_jumplog.argtypes = [vp, C.c_int, u64, u64, u32, p(f64), vp, p(u32), u32, p(u32)]
     L.qram_set_timing.argtypes = [vp, C.c_int]
     L.qram_stage_times.argtypes = [vp, p(f64), p(u32)]
@@ -208,6 +209,9 @@ class QramContext:
     def run_pruned(self, seed, traj0, ntraj, stats=True):
         return self._run(self._L.qram_run_pruned, seed, traj0, ntraj, stats)
 
+    def run_plain(self, seed, traj0, ntraj, stats=True):
+        return self._run(self._L.qram_run_plain, seed, traj0, ntraj, stats)
+
     def _run_async(self, fn, seed, traj0, ntraj, d_fid, d_st, stream):
         """d_fid: device tensor of ntraj float64; d_st: device uint8 tensor of
         ntraj*32 bytes or None; stream: torch.cuda.Stream, raw handle or None."""
@@ -223,6 +227,9 @@ class QramContext:
 
     def run_pruned_async(self, seed, traj0, ntraj, d_fid, d_st=None, stream=None):
         self._run_async(self._L.qram_run_pruned_async, seed, traj0, ntraj, d_fid, d_st, stream)
+
+    def run_plain_async(self, seed, traj0, ntraj, d_fid, d_st=None, stream=None):
+        self._run_async(self._L.qram_run_plain_async, seed, traj0, ntraj, d_fid, d_st, stream)
 
     def run_pruned_async_noalloc(self, seed, traj0, ntraj, d_fid, d_st=None, stream=None):
         """As run_pruned_async, with the work buffers in the library's static
@@ -245,12 +252,13 @@ class QramContext:
     def export_state(self, mode, seed=0, traj=0, cand_L=None, u_aux=None, u_fin=-1.0, jcap=4096):
         """qram_export_state: the final pre-measurement components of one
         trajectory (sampled, or forced when u_aux is given) and its jump log.
-        Returns dict(fid, st, records [ncomp, 3 + lmax] uint32, jlog uint32
-        entries, njl)."""
+        Returns dict(fid, st, records [ncomp, 3 + lmax] uint32, amp (plain
+        mode: complex amplitude of each record), jlog uint32 entries, njl)."""
         K2 = (1 << self.k) if self.enc == 1 else 1
         lmax = 2 * self.n + self.k if self.enc == 1 else 4 * self.n + self.k
         ncomp = self.D * K2
         comp = np.zeros(ncomp * (3 + lmax), dtype=np.uint32)
+        amp = np.zeros(2 * ncomp)
         jl = np.zeros(max(jcap, 1), dtype=np.uint32)
         njl = C.c_uint32()
         fid = C.c_double()
@@ -264,11 +272,12 @@ class QramContext:
         st = self._L.qram_export_state(
             self._h, mode, seed, traj, _ptr(L, C.c_uint32) if L is not None and len(L) else None,
             0 if L is None else len(L), _ptr(ua, C.c_double) if ua is not None else None, float(u_fin),
-            _ptr(comp, C.c_uint32), ncomp, _ptr(jl, C.c_uint32), jcap, C.byref(njl), C.byref(fid),
+            _ptr(comp, C.c_uint32), ncomp, _ptr(amp, C.c_double), _ptr(jl, C.c_uint32), jcap, C.byref(njl),
+            C.byref(fid),
             st_arr.ctypes.data_as(C.c_void_p))
         self._check(st, "qram_export_state")
         return dict(fid=fid.value, st=st_arr[0], records=comp.reshape(ncomp, 3 + lmax),
-                    jlog=jl[:min(njl.value, jcap)].copy(), njl=njl.value)
+                    amp=amp[0::2] + 1j * amp[1::2], jlog=jl[:min(njl.value, jcap)].copy(), njl=njl.value)
 
     def run_jumplog(self, mode, seed, traj0, ntraj, jcap=64):
         """qram_run_jumplog: fidelities, statistics and every trajectory's

@@ -4,8 +4,9 @@ oracle, component by component (qram_export_state, qram_run_jumplog).
 Sec. VI A checks the pruned evolution by matching the complete amplitudes,
 the residual tree configuration and the input-branch label of every
 component, and the jump decisions, between runs driven from the same history.
-Here the GPU's export (explicit components, and in pruned mode the predicted
-good branches) is compared with the oracle's full evolution:
+Here the GPU's export (explicit components, in pruned mode the predicted
+good branches, in plain mode every component with its amplitude) is compared
+with the oracle's full evolution:
   - the set of surviving initial labels is identical;
   - each component's address, bus word and tree configuration (sites and
     qutrit levels) are identical;
@@ -25,7 +26,7 @@ from paper_2609_34935_amd.inputs import memory_words
 pytestmark = pytest.mark.gpu
 
 QUTRIT, QUBIT = 0, 1
-FULL, PRUNED = 0, 1
+FULL, PRUNED, PLAIN = 0, 1, 2
 
 
 @pytest.fixture(scope="module")
@@ -42,7 +43,7 @@ def decode_jlog(entries):
     return sorted((int(x) >> 24, int(x) & 0xFFFF, (int(x) >> 16) & 0xFF) for x in entries)
 
 
-def gpu_components(out, n, k, enc, gamma):
+def gpu_components(out, n, k, enc, gamma, plain=False):
     """Present records -> {label: (addr, bus, tree levels[M], amplitude)}."""
     M = 2 * (2**n - 1)
     K2 = 2**k if enc == QUBIT else 1
@@ -58,13 +59,16 @@ def gpu_components(out, n, k, enc, gamma):
             q, lev = int(r[3 + j]) & 0xFFFF, int(r[3 + j]) >> 16
             assert tree[q] == 0, ("site listed twice", x, q)
             tree[q] = lev
-        amp = (2.0 ** (-n / 2)) / np.sqrt(K2) * (-1.0 if sign else 1.0) * np.sqrt(gamma) ** nJ * a ** int(r[1])
+        if plain:  # the plain mode carries amplitudes as numbers
+            amp = out["amp"][x]
+        else:
+            amp = (2.0 ** (-n / 2)) / np.sqrt(K2) * (-1.0 if sign else 1.0) * np.sqrt(gamma) ** nJ * a ** int(r[1])
         comps[x] = (addr, bus, tree, amp)
     return comps
 
 
-def compare_state(out, ref, n, k, enc, gamma, what):
-    g = gpu_components(out, n, k, enc, gamma)
+def compare_state(out, ref, n, k, enc, gamma, what, plain=False):
+    g = gpu_components(out, n, k, enc, gamma, plain)
     oc = ref["components"]
     assert sorted(g) == sorted(int(x) for x in oc["label"]), (what, sorted(g)[:8], list(oc["label"][:8]))
     scale = max(np.abs(oc["amp"]).max(), 1e-300) if len(oc["amp"]) else 1.0
@@ -74,7 +78,7 @@ def compare_state(out, ref, n, k, enc, gamma, what):
         assert bus == oc["bus"][j], (what, x, bus, oc["bus"][j])
         assert np.array_equal(tree, oc["tree"][j]), (what, x, np.nonzero(tree)[0], np.nonzero(oc["tree"][j])[0])
         assert abs(oc["amp"][j].imag) == 0.0
-        assert abs(amp - oc["amp"][j].real) <= 1e-12 * max(abs(oc["amp"][j]), 1e-3 * scale), (what, x, amp, oc["amp"][j])
+        assert abs(amp - oc["amp"][j]) <= 1e-12 * max(abs(oc["amp"][j]), 1e-3 * scale), (what, x, amp, oc["amp"][j])
     assert decode_jlog(out["jlog"]) == sorted(ref["jumps"]), (what, decode_jlog(out["jlog"]), ref["jumps"])
     assert out["njl"] == len(ref["jumps"])
     f = out["fid"]
@@ -87,9 +91,9 @@ def export_both_modes(lib, orc, n, k, enc, gamma, mem, what, seed=0, traj=0, L=N
     else:
         ref = orc.run_traj(n, k, enc, gamma, mem, forced_L=L, forced_uaux=ua, forced_ufin=uf, export=True)
     with lib.QramContext(n, k, enc, gamma, mem) as ctx:
-        for mode in (FULL, PRUNED):
+        for mode in (FULL, PRUNED, PLAIN):
             out = ctx.export_state(mode, seed, traj, cand_L=L, u_aux=ua, u_fin=uf)
-            compare_state(out, ref, n, k, enc, gamma, (what, mode))
+            compare_state(out, ref, n, k, enc, gamma, (what, mode), plain=mode == PLAIN)
     return ref
 
 
