@@ -1,13 +1,22 @@
-"""Throughput benchmark: trajectories/s of pruned vs full evolution of
+"""Throughput benchmark: trajectories/s of pruned vs plain full evolution of
 amplitude-damped bucket-brigade QRAM queries on one MI355X, plus the serving
 mix's p50/p99 request latency.
 
-Workload of one step: the n = 10, k = 4, gamma = 1e-3 data-loading query in
-both encodings, 1e5 trajectories each (seeded synthetic memory and noise),
-pruned evolution, inputs and outputs resident on the device.  The full mode is
-timed the same way as the comparator, the same pruned step once more as one
-HIP graph per batch, and the serving mix (Poisson arrivals, mixed n, k,
-encoding, gamma and shots) through the request server.  Prints one JSON line.
+Headline step: the n = 10, k = 4, gamma = 1e-3 data-loading query in both
+encodings, 1e5 trajectories each (seeded synthetic memory and noise), pruned
+evolution (Alg. 1), inputs and outputs resident on the device.  Timed beside
+it on the same trajectories:
+  - the plain full evolution (every component of every branch explicit,
+    slice by slice, nothing predicted): full_value, the comparator;
+  - the trajectory kernel's full mode (every branch explicit, components
+    untouched by jumps implicit): full_engine_value;
+  - the pruned step as HIP graphs; the qubit step under the damping-only
+    subtree marking;
+  - the n = 6, k = 1 qubit query at three gammas (pruned, full, plain) and
+    the n = 14, k = 1 qutrit stress case (traj/s and device footprint);
+  - the serving mix through the request server (Poisson arrivals);
+  - the oracle on the host's cores (cpu_baseline).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -25,42 +34,36 @@ sys.path.insert(0, ROOT)
 
 N, K, GAMMA = 10, 4, 1e-3
 CFG_ID = 3
+PEAK_HBM_GBS = 8000.0                    # MI355X HBM3E
 PEAK_ALU_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes per clock x 2.4 GHz
-COUNTER_FILE = os.path.join(ROOT, "profiles", "evolve_qubit_n10k4_counters.json")
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2609_34935_amd", "csrc", f)
-               for f in ("qram_evolve.hip", "qram_device.h", "qram_internal.h")]
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_2609_34935_amd", "csrc")
+# committed rocprofv3 counter summaries: (file, kernel sources)
+COUNTERS = {
+    "evolve_qubit": ("evolve_qubit_n10k4_main_counters.json", ("qram_evolve.hip", "qram_device.h",
+                                                               "qram_internal.h", "qram_records.h")),
+    "evolve_qutrit": ("evolve_qutrit_n10k4_main_counters.json", ("qram_evolve.hip", "qram_device.h",
+                                                                 "qram_internal.h", "qram_records.h")),
+    "plain_qubit": ("plain_qubit_n10k4_counters.json", ("qram_plain.hip", "qram_device.h", "qram_internal.h")),
+}
 
 
-def kernel_sha256():
+def sources_sha256(files):
     h = hashlib.sha256()
-    for f in KERNEL_SRCS:
-        h.update(open(f, "rb").read())
+    for f in files:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()
 
 
-# Algorithmic unit of the dominant kernel: one mask test of the joint damping
-# layer (Eq. maskweight), i.e. one (candidate, explicit component) pair: the
-# candidate's site and level compared with the component's excited set, and
-# the outcome merged into the component's mask (2 integer operations).
-OPS_PER_MASK_TEST = 2
-
-
-def ops_per_component_slice(n, k):
-    """Work of one explicit component through one slice when every component
-    is carried explicitly slice by slice: about 6 FP64 operations (K0
-    weight, |A|^2, accumulation) and 2n + 3k integer operations (site moves
-    and mask merge).  Reported for comparison only."""
-    return 6 + 2 * n + 3 * k
-
-
-def traffic_from_profile():
-    """HBM bytes per launch of the qubit evolution kernel from the committed
-    rocprofv3 counter summary, or None if the kernel changed since."""
+def traffic_from_profile(key):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the
+    committed counter summary, or None if the kernel's sources changed since."""
+    name, srcs = COUNTERS[key]
     try:
-        prof = json.load(open(COUNTER_FILE))
+        prof = json.load(open(os.path.join(PROFILES, name)))
     except (OSError, ValueError):
         return None
-    if prof.get("kernel_sha256") != kernel_sha256():
+    if prof.get("kernel_sha256") != sources_sha256(srcs):
         return None
     return prof.get("hbm_bytes_per_launch")
 
@@ -69,11 +72,27 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def ops_per_component_slice(n, k):
+    """The explicit sweep's work per component and slice: about 6 FP64
+    operations (K0 scale, |A|^2, accumulation) and 2n + 3k integer operations
+    (site moves, mask merge)."""
+    return 6 + 2 * n + 3 * k
+
+
+def bytes_per_component(n, k):
+    """Explicit state of one component in the plain sweep: complex FP64
+    amplitude (16 B), its site list (2 B per entry, 2n + 3k entries at
+    most) and a count (4 B), rounded up to 8 B."""
+    b = 16 + 2 * (2 * n + 3 * k) + 4
+    return (b + 7) // 8 * 8
+
+
 def cpu_baseline(mem, n_qubit, n_qutrit):
     """The oracle (full evolution of every branch, plain C, OpenMP over
     trajectories) on the first trajectories of each encoding."""
     from oracle import oracle as O
-    threads = min(16, os.cpu_count() or 1)
+    host = os.cpu_count() or 1
+    threads = min(16, host)  # the GPU box's CPU share for one GPU
     per = {}
     used = threads
     for enc, cnt in ((1, n_qubit), (0, n_qutrit)):
@@ -82,7 +101,6 @@ def cpu_baseline(mem, n_qubit, n_qutrit):
         per[enc] = (time.perf_counter() - t0, cnt)
     # one step holds as many qubit as qutrit trajectories
     t_pair = per[1][0] / per[1][1] + per[0][0] / per[0][1]
-    # the same oracle on one thread (the paper's simulator is single-threaded)
     one = {}
     for enc, cnt in ((1, max(1, n_qubit // 16)), (0, max(1, n_qutrit // 16))):
         t0 = time.perf_counter()
@@ -90,9 +108,11 @@ def cpu_baseline(mem, n_qubit, n_qutrit):
         one[enc] = (time.perf_counter() - t0, cnt)
     t_one = one[1][0] / one[1][1] + one[0][0] / one[0][1]
     return {"value": round(2.0 / t_pair, 2), "unit": "trajectories/s", "cores": used, "kind": "oracle",
+            "host_cpu_count": host,
             "sample": f"first {per[1][1]} qubit and {per[0][1]} qutrit trajectories of the step's workload "
-                      f"({per[1][0]:.1f} s and {per[0][0]:.1f} s wall on {used} threads), full evolution of "
-                      "every branch on the host; value = 2 / (mean qubit + mean qutrit time per trajectory)",
+                      f"({per[1][0]:.1f} s and {per[0][0]:.1f} s wall on {used} threads: the host reports "
+                      f"{host} CPUs, one GPU's share is 16), full evolution of every branch on the host; "
+                      "value = 2 / (mean qubit + mean qutrit time per trajectory)",
             "single_thread": {"value": round(2.0 / t_one, 2), "unit": "trajectories/s",
                               "sample": f"first {one[1][1]} qubit and {one[0][1]} qutrit trajectories on one "
                                         f"thread ({one[1][0]:.1f} s and {one[0][0]:.1f} s)"}}
@@ -111,7 +131,7 @@ def _serve_once(P, reqs, mems, arrivals, chunk, max_active, budget_gib, tag):
         res = []
         for i, t in enumerate(tickets):
             res.append(srv.wait(t))
-            if (i + 1) % 64 == 0:
+            if (i + 1) % 250 == 0:
                 log(f"serving {tag}: {i + 1}/{len(reqs)} requests done")
         wall = time.perf_counter() - t0
     bad = [x for x in res if x["state"] != "done"]
@@ -126,17 +146,17 @@ def _serve_once(P, reqs, mems, arrivals, chunk, max_active, budget_gib, tag):
             "aggregate_traj_per_s": round(shots / wall, 1), "wall_s": round(wall, 3)}
 
 
-def serving_leg(P, nreq, seed, chunk, max_active, budget_gib):
+def serving_leg(P, nreq, ncap, seed, chunk, max_active, budget_gib):
     """The serving mix through the request server.  The capacity mu (requests
-    per second) is measured with every request submitted at once; then the
-    mix arrives as a Poisson stream at 0.5 mu and 0.8 mu.  Latency is
-    submission to results on the host, measured by the server."""
+    per second) is measured on the first ncap requests submitted at once (a
+    warm-up too); then nreq requests arrive as a Poisson stream at 0.5 mu and
+    at 0.8 mu.  Latency is submission to results on the host."""
     from paper_2609_34935_amd.inputs import memory_words, request_mix
     out = {}
     reqs = request_mix(nreq, seed)
     mems = [memory_words(r["n"], r["k"], r["mem_seed"]) for r in reqs]
-    sat = _serve_once(P, reqs, mems, np.zeros(nreq), chunk, max_active, budget_gib, "saturated")
-    mu = nreq / sat["wall_s"]
+    sat = _serve_once(P, reqs[:ncap], mems[:ncap], np.zeros(ncap), chunk, max_active, budget_gib, "saturated")
+    mu = ncap / sat["wall_s"]
     out["saturated"] = dict(sat, capacity_req_per_s=round(mu, 2))
     for frac, key in ((0.5, "load_0.5"), (0.8, "load_0.8")):
         rng = np.random.default_rng(seed + 100 + int(frac * 10))
@@ -148,8 +168,90 @@ def serving_leg(P, nreq, seed, chunk, max_active, budget_gib):
             "aggregate_traj_per_s": out["saturated"]["aggregate_traj_per_s"], **out,
             "mix": "n~U{4..12}, k~U{1,2,4}, encoding~U, gamma log-uniform [1e-5,1e-2], "
                    "shots log-uniform [1e3,1e5], seeded Bernoulli(0.5) memory, pruned mode, master seed "
-                   f"{seed}; the same requests in every phase, arrival times seeded {seed + 105} and {seed + 108}",
+                   f"{seed}; capacity from the first {ncap} requests at once, then {nreq} requests per "
+                   f"Poisson phase, arrival times seeded {seed + 105} and {seed + 108}",
             "server": {"max_active": max_active, "chunk": chunk, "hbm_budget_gib": budget_gib}}
+
+
+def time_mode(ctx, fn, seed, nt, reps, d_fid, d_st, stream):
+    import torch
+    fn(seed, 0, nt, d_fid, d_st, stream=stream)  # warm-up (buffers, code)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn(seed, 0, nt, d_fid, d_st, stream=stream)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def stats_of(P, d_st):
+    return np.frombuffer(d_st.cpu().numpy().tobytes(), dtype=P.STATS_DTYPE)
+
+
+def config2_leg(P, reps):
+    """Qubit n = 6, k = 1 at gamma in {1e-4, 1e-3, 1e-2}, 1e4 trajectories:
+    pruned, the kernel's full mode and the plain full evolution."""
+    import torch
+    from paper_2609_34935_amd.inputs import memory_words
+    n, k, nt, seed = 6, 1, 10000, 880002
+    mem = memory_words(n, k, 1002)
+    stream = torch.cuda.current_stream()
+    d_fid = torch.empty(nt, dtype=torch.float64, device="cuda")
+    d_st = torch.empty(nt * 32, dtype=torch.uint8, device="cuda")
+    out = {}
+    for gamma in (1e-4, 1e-3, 1e-2):
+        with P.QramContext(n, k, P.QRAM_QUBIT, gamma, mem) as ctx:
+            row, fids = {}, {}
+            for name, fn in (("pruned", ctx.run_pruned_async), ("full_engine", ctx.run_full_async),
+                             ("plain", ctx.run_plain_async)):
+                dt = time_mode(ctx, fn, seed, nt, reps, d_fid, d_st, stream)
+                row[name] = round(nt / dt, 1)
+                fids[name] = d_fid.cpu().numpy()
+                if name == "pruned":
+                    s = stats_of(P, d_st)
+                    row["evolved_fraction"] = round(float(s["n_explicit"].mean()) / 2 ** (n + k), 4)
+                    row["mean_bad"] = round(float(s["n_bad"].mean()), 3)
+            ctx.errors()
+        for name in ("full_engine", "plain"):
+            assert np.all(np.abs(fids[name] - fids["pruned"]) <= 1e-12 * np.maximum(np.abs(fids["pruned"]), 1e-3))
+        row["speedup_pruned_over_plain"] = round(row["pruned"] / row["plain"], 3)
+        row["ideal_speedup"] = round(1.0 / row["evolved_fraction"], 3)
+        out[f"gamma={gamma:g}"] = row
+        log(f"C2 gamma={gamma:g}: {row}")
+    return {"workload": "qubit n=6 k=1, 1e4 trajectories per gamma, seed 880002, mem_seed 1002",
+            "unit": "trajectories/s", **out}
+
+
+def config5_leg(P, nt, nt_plain):
+    """Qutrit n = 14, k = 1, gamma = 1e-2: every branch is bad, so pruned
+    evolves what full does; traj/s and device footprint of each mode."""
+    import torch
+    from paper_2609_34935_amd.inputs import memory_words
+    n, k, gamma, seed = 14, 1, 1e-2, 880005
+    mem = memory_words(n, k, 1005)
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"qutrit n=14 k=1 gamma=1e-2, seed {seed}, mem_seed 1005", "unit": "trajectories/s"}
+    with P.QramContext(n, k, P.QRAM_QUTRIT, gamma, mem) as ctx:
+        for name, mode, fn, cnt in (("pruned", P.QRAM_MODE_PRUNED, ctx.run_pruned_async, nt),
+                                    ("full_engine", P.QRAM_MODE_FULL, ctx.run_full_async, nt),
+                                    ("plain", P.QRAM_MODE_PLAIN, ctx.run_plain_async, nt_plain)):
+            d_fid = torch.empty(cnt, dtype=torch.float64, device="cuda")
+            d_st = torch.empty(cnt * 32, dtype=torch.uint8, device="cuda")
+            dt = time_mode(ctx, fn, seed, cnt, 1, d_fid, d_st, stream)
+            f1, f_all = ctx.footprint(mode, 1), ctx.footprint(mode, cnt)
+            out[name] = {"traj_per_s": round(cnt / dt, 1), "trajectories": cnt,
+                         "footprint_one_in_flight_bytes": int(f1), "footprint_bytes": int(f_all)}
+            if name == "pruned":
+                s = stats_of(P, d_st)
+                out["mean_candidates"] = round(float(s["n_cand"].mean()), 1)
+                out["evolved_fraction"] = round(float(s["n_explicit"].mean()) / 2 ** n, 4)
+            log(f"C5 {name}: {out[name]}")
+            del d_fid, d_st
+        ctx.errors()
+    out["footprint_note"] = ("footprint_one_in_flight_bytes: device bytes held for runs of one trajectory "
+                             "(context tables plus one workgroup's work state); footprint_bytes: for the whole "
+                             "run as batched")
+    return out
 
 
 def main():
@@ -158,22 +260,26 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--ntraj", type=int, default=100000)
+    ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--cpu-qubit", type=int, default=768)
     ap.add_argument("--cpu-qutrit", type=int, default=6144)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--launch-cache", default=os.path.join(ROOT, "paper_2609_34935_amd", "tuned",
                                                         "launch_n10k4_gamma1e-3.json"),
-                    help="JSON file of tuned launch shapes: read if present, else written "
-                         "(default: the shapes shipped for this workload)")
+                    help="JSON file of launch shapes chosen by the autotuner: read if present")
     ap.add_argument("--retune", action="store_true",
-                    help="run the autotuner instead of reading the launch cache")
-    ap.add_argument("--modes", default="pruned,full")
+                    help="run the autotuner on the whole step and write its picks to --launch-cache")
+    ap.add_argument("--modes", default="pruned,full,plain")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-subtree", action="store_true",
                     help="skip the qubit step under the damping-only subtree marking")
+    ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--c5-ntraj", type=int, default=100000)
+    ap.add_argument("--c5-plain-ntraj", type=int, default=20000)
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-capacity-requests", type=int, default=400)
     ap.add_argument("--serve-chunk", type=int, default=16384)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=96.0)
@@ -201,76 +307,85 @@ def main():
     seed = 880000 + CFG_ID
     nt = args.ntraj
     T = 6 * N + 2 * K
+    modes_req = args.modes.split(",")
     ctxs = {enc: P.QramContext(N, K, enc, GAMMA, mem) for enc in (P.QRAM_QUBIT, P.QRAM_QUTRIT)}
-    tuned = {}
+    all_modes = (P.QRAM_MODE_PRUNED, P.QRAM_MODE_FULL, P.QRAM_MODE_PLAIN)
+
+    # launch shapes: the autotuner's picks on the whole step (cached)
+    tuned, tune_ms = {}, {}
     cache = None
     if args.launch_cache and os.path.exists(args.launch_cache) and not args.retune:
         cache = json.load(open(args.launch_cache))
     for enc, ctx in ctxs.items():
-        for mode in (P.QRAM_MODE_PRUNED, P.QRAM_MODE_FULL):
+        for mode in all_modes:
             key = f"{enc}:{mode}"
             if cache and key in cache:
                 ctx.set_launch(mode, *cache[key])
-            elif not args.no_tune:
-                ms = ctx.autotune(mode, seed, 0, min(nt, 16384))
-                log(f"autotune enc={enc} mode={mode}: {ctx.get_launch(mode)} {ms:.3f} ms")
+            else:
+                tune_ms[key] = round(ctx.autotune(mode, seed, 0, nt), 3)
+                log(f"autotune enc={enc} mode={mode}: {ctx.get_launch(mode)} {tune_ms[key]:.3f} ms")
             tuned[(enc, mode)] = ctx.get_launch(mode)
-    if args.launch_cache and cache is None and not os.path.exists(args.launch_cache):
+    if args.launch_cache and cache is None:
         json.dump({f"{e}:{m}": list(v) for (e, m), v in tuned.items()}, open(args.launch_cache, "w"))
-    modes = [P.QRAM_MODE_PRUNED] + ([P.QRAM_MODE_FULL] if "full" in args.modes.split(",") else [])
+
     stream = torch.cuda.current_stream()
     d_fid = {enc: torch.empty(nt, dtype=torch.float64, device="cuda") for enc in ctxs}
     d_st = {enc: torch.empty(nt * 32, dtype=torch.uint8, device="cuda") for enc in ctxs}
 
     def step(mode):
         for enc, ctx in ctxs.items():
-            fn = ctx.run_pruned_async if mode == P.QRAM_MODE_PRUNED else ctx.run_full_async
+            fn = {P.QRAM_MODE_PRUNED: ctx.run_pruned_async, P.QRAM_MODE_FULL: ctx.run_full_async,
+                  P.QRAM_MODE_PLAIN: ctx.run_plain_async}[mode]
             fn(seed, 0, nt, d_fid[enc], d_st[enc], stream=stream)
 
-    results = {}
-    for mode in modes:
-        for _ in range(args.warmup):
+    def timed(mode, steps, warmup):
+        for _ in range(warmup):
             step(mode)
         torch.cuda.synchronize()
         for ctx in ctxs.values():
             ctx.set_timing(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             step(mode)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        stage = {}
+        stage, buckets = {}, {}
         for enc, ctx in ctxs.items():
             launches = ctx.stage_launches()
+            buckets[enc] = ctx.stage_buckets()
             stage[enc] = ctx.stage_times() + (launches,)
             ctx.set_timing(False)
             ctx.errors()
-        st = {enc: np.frombuffer(d_st[enc].cpu().numpy().tobytes(), dtype=P.STATS_DTYPE) for enc in ctxs}
+        st = {enc: stats_of(P, d_st[enc]) for enc in ctxs}
         fids = {enc: d_fid[enc].cpu().numpy() for enc in ctxs}
-        results[mode] = dict(dt=dt, stage=stage, st=st, fid=fids)
-        log(f"mode={mode}: {args.steps} steps in {dt:.3f} s")
+        log(f"mode={mode}: {steps} steps in {dt:.3f} s")
+        return dict(dt=dt, steps=steps, stage=stage, buckets=buckets, st=st, fid=fids)
 
-    pr, fu = results[P.QRAM_MODE_PRUNED], results.get(P.QRAM_MODE_FULL)
-    total = 2 * nt * args.steps
-    value = total / pr["dt"]
-    full_value = total / fu["dt"] if fu else None
-    if fu:
-        for enc in ctxs:  # the two modes must agree trajectory by trajectory
-            a, b = pr["fid"][enc], fu["fid"][enc]
-            assert np.all(np.abs(a - b) <= 1e-12 * np.maximum(np.abs(b), 1e-3)), "pruned and full disagree"
+    pr = timed(P.QRAM_MODE_PRUNED, args.steps, args.warmup)
+    fe = timed(P.QRAM_MODE_FULL, args.steps, args.warmup) if "full" in modes_req else None
+    pl = timed(P.QRAM_MODE_PLAIN, args.plain_steps, 1) if "plain" in modes_req else None
+    total = 2 * nt
+    value = total * pr["steps"] / pr["dt"]
+    full_engine_value = total * fe["steps"] / fe["dt"] if fe else None
+    full_value = total * pl["steps"] / pl["dt"] if pl else None
+    for other in (fe, pl):  # every mode agrees with the pruned one trajectory by trajectory
+        if other:
+            for enc in ctxs:
+                a, b = pr["fid"][enc], other["fid"][enc]
+                assert np.all(np.abs(a - b) <= 1e-12 * np.maximum(np.abs(a), 1e-3)), "modes disagree"
 
     graph_value = None
     if not args.no_graph:
         for ctx in ctxs.values():
             ctx.set_option(P.qram.QRAM_OPT_GRAPH, 1)
-        step(P.QRAM_MODE_PRUNED)
+        step(P.QRAM_MODE_PRUNED)  # capture and instantiate once; the timed steps replay
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             step(P.QRAM_MODE_PRUNED)
         torch.cuda.synchronize()
-        graph_value = total / (time.perf_counter() - t0)
+        graph_value = total * args.steps / (time.perf_counter() - t0)
         for enc, ctx in ctxs.items():
             ctx.set_option(P.qram.QRAM_OPT_GRAPH, 0)
             assert np.array_equal(d_fid[enc].cpu().numpy(), pr["fid"][enc]), "graph replay differs"
@@ -295,14 +410,14 @@ def main():
         qctx.set_option(P.qram.QRAM_OPT_SUBTREE_MARKING, 0)
         qctx.errors()
         fs = d_fid[P.QRAM_QUBIT].cpu().numpy()
-        ss = np.frombuffer(d_st[P.QRAM_QUBIT].cpu().numpy().tobytes(), dtype=P.STATS_DTYPE)
+        ss = stats_of(P, d_st[P.QRAM_QUBIT])
         ref_f = pr["fid"][P.QRAM_QUBIT]
         assert np.all(np.abs(fs - ref_f) <= 1e-12 * np.maximum(np.abs(ref_f), 1e-3)), \
             "subtree marking changed a fidelity"
-        sub_value = total / dt_sub
+        sub_value = total * args.steps / dt_sub
         subtree = {
             "value": round(sub_value, 1),
-            "speedup_over_full": None if full_value is None else round(sub_value / full_value, 4),
+            "speedup_over_plain_full": None if full_value is None else round(sub_value / full_value, 3),
             "qubit_pruned_evolve_ms": round(ms_s[2] / max(nbs, 1), 3),
             "qubit_evolved_fraction": round(float(ss["n_explicit"].mean()) / 2 ** (N + K), 4),
             "qubit_mean_bad": round(float(ss["n_bad"].mean()), 2),
@@ -311,32 +426,82 @@ def main():
         }
         log(f"subtree marking: {sub_value:.1f} trajectories/s")
 
-    # roofline of the dominant kernel: the qubit evolution launches
-    ms_stage, nb, nlaunch = pr["stage"][P.QRAM_QUBIT]
-    evolve_ms_step = ms_stage[2] / max(nb, 1)
-    launch_ms = ms_stage[2] / max(nlaunch, 1)
+    # roofline of the dominant kernel: the largest bucket launch of the
+    # qubit evolution kernel in the pruned step
+    bk = pr["buckets"][P.QRAM_QUBIT]
+    dom = max(range(len(bk)), key=lambda i: bk[i]["ms"])
+    launch_ms = bk[dom]["ms"] / max(bk[dom]["launches"], 1)
     sq = pr["st"][P.QRAM_QUBIT]
-    units_step = float((sq["n_cand"].astype(np.float64) * sq["n_explicit"].astype(np.float64)).sum())
-    achieved = units_step * OPS_PER_MASK_TEST / (evolve_ms_step * 1e-3) / 1e12
-    sweep_units = float(sq["n_explicit"].astype(np.float64).sum()) * (T - 1)
-    sweep_rate = sweep_units * ops_per_component_slice(N, K) / (evolve_ms_step * 1e-3) / 1e12
+    lo = bk[dom - 1]["emax"] if dom > 0 else 0
+    sel = (sq["n_explicit"] > lo) & (sq["n_explicit"] <= bk[dom]["emax"])
+    assert int(sel.sum()) == bk[dom]["ntraj_last"], "bucket membership"
+    # compulsory bytes of the stage per trajectory: its candidate list in
+    # (4 B each), its explicit-address list in (2 B each), fidelity and
+    # statistics out (8 + 32 B)
+    traj_bytes = 4.0 * sq["n_cand"][sel] + 2.0 * (sq["n_explicit"][sel] >> K) + 40.0
+    bytes_launch = float(traj_bytes.sum())
+    achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
+    sweep_units = float(sq["n_explicit"][sel].astype(np.float64).sum()) * (T - 1)
+    sweep_rate = sweep_units * ops_per_component_slice(N, K) / (launch_ms * 1e-3) / 1e12
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        "frac": round(achieved / PEAK_HBM_GBS, 5), "traffic": traffic_from_profile("evolve_qubit"),
+        "kernel": f"k_evolve<qubit> bucket {dom} (up to {bk[dom]['emax']} components; pruned step)",
+        "launch_ms": round(launch_ms, 3), "launches_timed": bk[dom]["launches"],
+        "units_per_launch": int(sel.sum()), "unit_of_work": "trajectory",
+        "bytes_per_unit": round(bytes_launch / max(int(sel.sum()), 1), 2),
+        "bytes_rule": "4 B per candidate in + 2 B per explicit address in + 40 B out (fid, stats)",
+        "other_launches": [{"bucket": i, "ms": round(b["ms"] / max(b["launches"], 1), 3),
+                            "trajectories": b["ntraj_last"]} for i, b in enumerate(bk) if i != dom],
+        "explicit_sweep_equivalent": {
+            "unit": "component-slice", "ops_per_unit": ops_per_component_slice(N, K),
+            "units_per_launch": sweep_units, "rate_tops": round(sweep_rate, 3),
+            "of_alu_peak": round(sweep_rate / PEAK_ALU_TOPS, 3)},
+    }
+
+    # the plain comparator's own roofline (the explicit sweep itself)
+    roofline_plain = None
+    if pl:
+        ms_q = pl["stage"][P.QRAM_QUBIT][0][2] / max(pl["stage"][P.QRAM_QUBIT][1], 1)
+        E = 2 ** (N + K)
+        units = float(nt) * E * (T - 1)
+        rate_alu = units * ops_per_component_slice(N, K) / (ms_q * 1e-3) / 1e12
+        b_hbm = units * 2 * bytes_per_component(N, K)
+        rate_hbm = b_hbm / (ms_q * 1e-3) / 1e9
+        roofline_plain = {
+            "bound": "hbm", "achieved": round(rate_hbm, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(rate_hbm / PEAK_HBM_GBS, 4), "traffic": traffic_from_profile("plain_qubit"),
+            "kernel": "k_plain<qubit> (plain full evolution)", "launch_ms": round(ms_q, 3),
+            "units_per_launch": units, "unit_of_work": "component-slice",
+            "bytes_per_unit": 2 * bytes_per_component(N, K),
+            "bytes_rule": "the component's state read and written once per slice",
+            "alu": {"ops_per_unit": ops_per_component_slice(N, K), "rate_tops": round(rate_alu, 3),
+                    "peak": round(PEAK_ALU_TOPS, 3), "frac": round(rate_alu / PEAK_ALU_TOPS, 4)}}
+
     per_enc = {}
     for enc, name in ((P.QRAM_QUBIT, "qubit"), (P.QRAM_QUTRIT, "qutrit")):
         s = pr["st"][enc]
         ms_p, nbp, _ = pr["stage"][enc]
-        ms_f, nbf, _ = fu["stage"][enc] if fu else (np.full(3, np.nan), 1, 0)
-        per_enc[name] = {
+        row = {
             "pruned_evolve_ms": round(ms_p[2] / max(nbp, 1), 3),
-            "full_evolve_ms": None if not fu else round(ms_f[2] / max(nbf, 1), 3),
             "sample_classify_ms": round((ms_p[0] + ms_p[1]) / max(nbp, 1), 3),
-            "pruned_traj_per_s_kernels": round(nt / (ms_p.sum() / max(nbp, 1) * 1e-3), 1),
-            "full_traj_per_s_kernels": None if not fu else round(nt / (ms_f.sum() / max(nbf, 1) * 1e-3), 1),
+            "pruned_buckets": [{"ms": round(b["ms"] / max(b["launches"], 1), 3), "trajectories": b["ntraj_last"],
+                                "emax": b["emax"]} for b in pr["buckets"][enc]],
             "evolved_fraction": round(float(s["n_explicit"].mean()) / (2**N * (2**K if enc == P.QRAM_QUBIT else 1)), 4),
             "mean_fidelity": round(float(pr["fid"][enc].mean()), 6),
             "mean_jumps": round(float(s["n_jumps"].mean()), 4),
-            "launch_pruned": tuned[(enc, P.QRAM_MODE_PRUNED)],
-            "launch_full": tuned[(enc, P.QRAM_MODE_FULL)],
+            "launch": {m: tuned[(enc, mode)] for m, mode in (("pruned", P.QRAM_MODE_PRUNED),
+                                                              ("full_engine", P.QRAM_MODE_FULL),
+                                                              ("plain", P.QRAM_MODE_PLAIN))},
         }
+        for key, res in (("full_engine", fe), ("plain", pl)):
+            if res:
+                ms_x, nbx, _ = res["stage"][enc]
+                row[f"{key}_evolve_ms"] = round(ms_x[2] / max(nbx, 1), 3)
+                row[f"{key}_traj_per_s"] = round(nt * res["steps"] / (ms_x.sum() * 1e-3), 1)
+        row["pruned_traj_per_s"] = round(nt / (ms_p.sum() / max(nbp, 1) * 1e-3), 1)
+        per_enc[name] = row
+
     line = {
         "metric": "trajectories/sec pruned vs full at n=10, gamma=1e-3 (1 GPU); p50/p99 req latency",
         "value": round(value, 1),
@@ -344,7 +509,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(pr["dt"] / args.steps * 1e3, 3),
+        "ms_per_step": round(pr["dt"] / pr["steps"] * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -352,24 +517,22 @@ def main():
         "data": "synthetic",
         "config": {"workload": "bucket-brigade QRAM query n=10 k=4 gamma=1e-3, qubit and qutrit "
                                "encodings, 1e5 trajectories each, pruned evolution",
-                   "n": N, "k": K, "gamma": GAMMA, "trajectories_per_step": 2 * nt,
+                   "n": N, "k": K, "gamma": GAMMA, "trajectories_per_step": total,
                    "memory": "seeded Bernoulli(0.5), mem_seed 1003", "seed": seed},
         "full_value": None if full_value is None else round(full_value, 1),
-        "speedup_pruned_over_full": None if full_value is None else round(value / full_value, 4),
+        "full_kind": "plain full evolution: every component of every branch explicit, slice by slice",
+        "speedup_pruned_over_full": None if full_value is None else round(value / full_value, 3),
+        "full_engine_value": None if full_engine_value is None else round(full_engine_value, 1),
+        "speedup_pruned_over_full_engine": None if full_engine_value is None else round(value / full_engine_value, 4),
         "graph_value": None if graph_value is None else round(graph_value, 1),
         "subtree_marking": subtree,
         "per_encoding": per_enc,
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_ALU_TOPS, 3),
-                     "unit": "TOP/s", "frac": round(achieved / PEAK_ALU_TOPS, 4),
-                     "traffic": traffic_from_profile(),
-                     "kernel": "k_evolve<qubit> (pruned step)", "launch_ms": round(launch_ms, 3),
-                     "launches_per_step": round(nlaunch / max(nb, 1), 2),
-                     "work_unit": "mask test (candidate x explicit component)",
-                     "units_per_launch": units_step / max(nlaunch / max(nb, 1), 1),
-                     "ops_per_unit": OPS_PER_MASK_TEST,
-                     "explicit_sweep_equivalent": {
-                         "unit": "explicit component-slice", "ops_per_unit": ops_per_component_slice(N, K),
-                         "rate_tops": round(sweep_rate, 3)}},
+        "launch_shapes": {"source": "autotuner on the whole step" if tune_ms else
+                          f"cache {os.path.relpath(args.launch_cache, ROOT)} (written by bench.py --retune)",
+                          "tune_ms": tune_ms or None},
+        "roofline": roofline,
+        "roofline_plain": roofline_plain,
+        "config2": None, "config5": None,
         "latency": None,
         "cpu_baseline": None,
     }
@@ -377,10 +540,15 @@ def main():
         ctx.close()
     del d_fid, d_st
     torch.cuda.empty_cache()
+    if not args.no_c2:
+        line["config2"] = config2_leg(P, reps=5)
+    if not args.no_c5:
+        line["config5"] = config5_leg(P, args.c5_ntraj, args.c5_plain_ntraj)
+    torch.cuda.empty_cache()
     if not args.no_serve:
         log("serving mix")
-        line["latency"] = serving_leg(P, args.serve_requests, 4242, args.serve_chunk,
-                                      args.serve_slots, args.serve_budget_gib)
+        line["latency"] = serving_leg(P, args.serve_requests, args.serve_capacity_requests, 4242,
+                                      args.serve_chunk, args.serve_slots, args.serve_budget_gib)
     if not args.no_cpu:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(mem, args.cpu_qubit, args.cpu_qutrit)

@@ -225,7 +225,12 @@ qram_status qram_set_option(qram_ctx *ctx, int option, int value);
 
 /*
  * Measure every launch shape of a mode on trajectories [traj0, traj0+ntraj)
- * of seed and keep the fastest (the autotuner).  best_ms receives its time.
+ * of seed and keep the fastest (the autotuner).  Each shape times the whole
+ * evolution of the sample (every work bucket's launch).  A shape with the
+ * component state in device memory must be 3% faster than the best with
+ * the state in shared memory to be kept: within that margin it only adds
+ * HBM traffic.  The plain mode tries 1, 2 and 4 workgroups per compute
+ * unit.  best_ms receives the kept shape's time.
  */
 qram_status qram_autotune(qram_ctx *ctx, qram_mode mode, uint64_t seed,
                           uint64_t traj0, uint32_t ntraj, double *best_ms);
@@ -251,6 +256,16 @@ qram_status qram_stage_times(qram_ctx *ctx, double *ms, uint32_t *nbatches);
  * batches the current accumulation timed; read it before qram_stage_times,
  * which starts a new accumulation. */
 qram_status qram_stage_launches(const qram_ctx *ctx, uint32_t *evolve_launches);
+/* Per-bucket evolution timing of the same accumulation (read it before
+ * qram_stage_times): arrays of 6 entries, one per work bucket (trajectories
+ * grouped by explicit-component count, largest last).  ms[i]: summed
+ * milliseconds of bucket i's evolution launches (HIP events around each
+ * launch on the caller's stream); launches[i]: their number; ntraj_last[i]:
+ * trajectories bucket i held in the last timed batch; emax[i]: the bucket's
+ * bound on explicit components; *nbuckets: buckets in use.  The plain mode
+ * has no buckets (*nbuckets = 0). */
+qram_status qram_stage_buckets(qram_ctx *ctx, double *ms, uint32_t *launches, uint32_t *ntraj_last,
+                               uint32_t *emax, int *nbuckets);
 
 /*
  * Test entry: one trajectory under a forced history instead of the random

@@ -96,12 +96,16 @@ struct qram_ctx {
   // instead of Eq. badrange
   bool mark_subtree = false;
   hipGraphExec_t gexec = nullptr;
+  Run graph_run{};       // the arguments the executable graph was captured with
+  uint64_t graph_sig = 0;  // launch-plan signature of the executable graph
   double last_ms[3] = {0, 0, 0};
   // stage timing of asynchronous runs: four events per batch
   bool timing = false;
-  std::vector<hipEvent_t> tev;
+  std::vector<hipEvent_t> tev;  // EVB per timed batch: 4 stage events, then 2 per bucket
   size_t tev_used = 0;
   uint32_t tev_launches = 0;  // evolution launches inside the timed batches
+  std::vector<int> tev_nb;    // buckets of each timed batch
+  uint32_t tev_emax[MAXB] = {0, 0, 0, 0, 0, 0};  // bucket bounds of the last timed batch
   // device address of this device's no-allocation scratch array (null if
   // it could not be resolved), and whether a no-allocation run used it
   unsigned char *scratch = nullptr;
@@ -481,13 +485,13 @@ qram_status ensure_buffers(qram_ctx *c, uint32_t nb, const Plan *pl) {
     }
     size_t ps = 0;
     for (int i = 0; i < pl->nb; ++i)
-      ps = std::max(ps, (size_t)pl->b[i].grid * pl->pool_slots * c->rec);
+      ps = std::max(ps, (size_t)pl->b[i].grid * pl->b[i].emax * c->rec);
     if (ps > c->pool_cap) {
       if ((st = dev_alloc(c, &c->pool, ps))) return st;
       c->pool_cap = ps;
     }
     size_t ds = 0;
-    for (int i = 0; i < pl->nb; ++i) ds = std::max(ds, (size_t)pl->b[i].grid * pl->pool_slots);
+    for (int i = 0; i < pl->nb; ++i) ds = std::max(ds, (size_t)pl->b[i].grid * pl->b[i].emax);
     if (ds > c->devl_cap) {
       if ((st = dev_alloc(c, &c->devl, ds))) return st;
       c->devl_cap = ds;
@@ -509,8 +513,8 @@ size_t buffers_bytes(const qram_ctx *c, uint32_t nb, const Plan &pl) {
   b += (size_t)pl.grid_max * pl.ecap_max * 4;
   size_t ps = 0, ds = 0;
   for (int i = 0; i < pl.nb; ++i) {
-    ps = std::max(ps, (size_t)pl.b[i].grid * pl.pool_slots * c->rec);
-    ds = std::max(ds, (size_t)pl.b[i].grid * pl.pool_slots);
+    ps = std::max(ps, (size_t)pl.b[i].grid * pl.b[i].emax * c->rec);
+    ds = std::max(ds, (size_t)pl.b[i].grid * pl.b[i].emax);
   }
   return b + ps * 2 + ds * 4;
 }
@@ -533,7 +537,8 @@ uint32_t batch_size(const qram_ctx *c, uint32_t ntraj) {
 }
 
 Run base_run(qram_ctx *c, int mode, uint64_t seed, const Plan *pl) {
-  Run r{};
+  Run r;
+  std::memset(&r, 0, sizeof(Run));  // padding too: graph replay compares runs bytewise
   r.seed = seed;
   r.mode = mode;
   r.cand_cap = c->cand_cap;
@@ -571,13 +576,19 @@ uint32_t sample_grid(const qram_ctx *c, uint32_t ntraj) {
   return std::max<uint32_t>(1u, std::min<uint32_t>(ntraj, (uint32_t)c->num_cu * 8u));
 }
 
-qram_status launch_buckets(qram_ctx *c, const Plan &pl, Run r, hipStream_t s) {
+constexpr size_t EVB = 4 + 2 * MAXB;  // timing events per batch
+
+// be (optional): two events per bucket, recorded around its launch.
+qram_status launch_buckets(qram_ctx *c, const Plan &pl, Run r, hipStream_t s, hipEvent_t *be = nullptr) {
   for (int i = 0; i < pl.nb; ++i) {
     const BucketShape &b = pl.b[i];
     r.bucket = (uint32_t)i;
     r.apt = b.apt;
     r.e_cap = b.e_cap;
+    r.pool_slots = b.emax;  // a workgroup's records: one per explicit component of the bucket
+    if (be) HIPCHK(c, hipEventRecord(be[2 * i], s));
     HIPCHK(c, launch_evolve(c->dtab, r, c->enc, b.grid, b.threads, b.lds, b.state_lds, s));
+    if (be) HIPCHK(c, hipEventRecord(be[2 * i + 1], s));
   }
   return QRAM_OK;
 }
@@ -589,15 +600,19 @@ qram_status enqueue_batch(qram_ctx *c, const Plan &pl, Run r, hipStream_t s,
   const uint32_t nt = r.ntraj;
   hipEvent_t e[4] = {c->ev[0], c->ev[1], c->ev[2], c->ev[3]};
   if (capture) timed = false;
-  if (!timed && !capture && c->timing) {  // async stage timing: four pooled events
-    while (c->tev.size() < c->tev_used + 4) {
+  hipEvent_t *be = nullptr;
+  if (!timed && !capture && c->timing) {  // async stage timing: pooled events
+    while (c->tev.size() < c->tev_used + EVB) {
       hipEvent_t x;
       HIPCHK(c, hipEventCreate(&x));
       c->tev.push_back(x);
     }
     for (int i = 0; i < 4; ++i) e[i] = c->tev[c->tev_used + i];
-    c->tev_used += 4;
+    be = &c->tev[c->tev_used + 4];
+    c->tev_used += EVB;
     c->tev_launches += (uint32_t)pl.nb;
+    c->tev_nb.push_back(pl.nb);
+    for (int i = 0; i < MAXB; ++i) c->tev_emax[i] = i < pl.nb ? pl.b[i].emax : 0u;
     timed = true;
   }
   if (timed) HIPCHK(c, hipEventRecord(e[0], s));
@@ -609,7 +624,7 @@ qram_status enqueue_batch(qram_ctx *c, const Plan &pl, Run r, hipStream_t s,
   if (pl.plain) {
     HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.b[0].grid, pl.b[0].threads, pl.plds, s));
   } else {
-    qram_status st = launch_buckets(c, pl, r, s);
+    qram_status st = launch_buckets(c, pl, r, s, be);
     if (st) return st;
   }
   if (timed) HIPCHK(c, hipEventRecord(e[3], s));
@@ -619,8 +634,39 @@ qram_status enqueue_batch(qram_ctx *c, const Plan &pl, Run r, hipStream_t s,
 // The batch as one graph: captured on the context's stream, instantiated
 // once (or updated in place when the executable graph exists) and launched
 // on stream s.  The captured work holds no memset node.
+// FNV-1a over the launch shapes of a plan (what a captured graph bakes in
+// besides the kernel arguments).
+uint64_t plan_signature(const Plan &pl) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  auto mix = [&h](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (v >> (8 * i)) & 0xFFu;
+      h *= 0x100000001b3ull;
+    }
+  };
+  mix((uint64_t)pl.nb);
+  mix(pl.plain ? 1u : 0u);
+  mix(pl.plds);
+  for (int i = 0; i < pl.nb; ++i) {
+    const BucketShape &b = pl.b[i];
+    mix(b.emax);
+    mix((uint64_t)b.threads);
+    mix(b.apt);
+    mix(b.e_cap);
+    mix(b.state_lds ? 1u : 0u);
+    mix(b.lds);
+    mix(b.grid);
+  }
+  return h;
+}
+
 qram_status launch_batch_graph(qram_ctx *c, const Plan &pl, const Run &r,
                                hipStream_t s) {
+  const uint64_t sig = plan_signature(pl);
+  if (c->gexec && sig == c->graph_sig && std::memcmp(&r, &c->graph_run, sizeof(Run)) == 0) {
+    HIPCHK(c, hipGraphLaunch(c->gexec, s));  // same work as captured: replay
+    return QRAM_OK;
+  }
   hipGraph_t g = nullptr;
   HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   qram_status st = enqueue_batch(c, pl, r, c->stream, false, false, true);
@@ -650,6 +696,8 @@ qram_status launch_batch_graph(qram_ctx *c, const Plan &pl, const Run &r,
     }
   }
   (void)hipGraphDestroy(g);
+  c->graph_run = r;
+  c->graph_sig = sig;
   HIPCHK(c, hipGraphLaunch(c->gexec, s));
   return QRAM_OK;
 }
@@ -1241,10 +1289,42 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
                           uint64_t traj0, uint32_t ntraj, double *best_ms) {
   qram_status st = check_args(c, traj0, ntraj);
   if (st) return st;
-  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return fail(c, QRAM_E_INVAL, "bad mode");
+  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED && mode != QRAM_MODE_PLAIN)
+    return fail(c, QRAM_E_INVAL, "bad mode");
   if (ntraj == 0) return fail(c, QRAM_E_INVAL, "ntraj must be positive");
   const uint32_t nt = std::min(ntraj, batch_size(c, ntraj));
   if ((st = ensure_out(c, nt))) return st;
+  if (mode == QRAM_MODE_PLAIN) {  // workgroups per compute unit
+    double best = 1e300;
+    int bw = 2;
+    for (int w : {1, 2, 4}) {
+      c->plain_per_cu = w;
+      Plan pl;
+      if (make_plan(c, mode, nt, pl) != QRAM_OK) continue;
+      if ((st = ensure_buffers(c, nt, &pl))) return st;
+      Run r = base_run(c, mode, seed, &pl);
+      r.traj0 = (uint32_t)traj0;
+      r.ntraj = nt;
+      r.fid = c->fid_tmp;
+      r.st = nullptr;
+      HIPCHK(c, launch_sample(c->dtab, r, nt, sample_grid(c, nt), c->stream));
+      HIPCHK(c, launch_classify(c->dtab, r, nt, sample_grid(c, nt), c->D, c->mark_subtree, c->stream));
+      HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+      HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.b[0].grid, pl.b[0].threads, pl.plds, c->stream));
+      HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+      HIPCHK(c, hipEventSynchronize(c->ev[1]));
+      float ms;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+      if (ms < best) {
+        best = ms;
+        bw = w;
+      }
+    }
+    c->plain_per_cu = bw;
+    c->spt[mode] = bw;
+    if (best_ms) *best_ms = best;
+    return check_err(c);
+  }
   const int cands[5] = {4, 8, 16, 32, 64};
   double best = 1e300;
   int bs = 16, bsched = 1;
@@ -1277,8 +1357,12 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
         t_best = std::min(t_best, (double)ms);
       }
-      if (t_best < best) {
-        best = t_best;
+      // state words in device memory must beat shared memory by 3% to be
+      // chosen: within that they only add HBM traffic (other work on the
+      // device pays for it)
+      const double score = (sched & 2) ? t_best * 1.03 : t_best;
+      if (score < best) {
+        best = score;
         bs = cands[ci];
         bsched = sched;
       }
@@ -1286,7 +1370,7 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
   }
   c->spt[mode] = bs;
   c->schedule[mode] = bsched;
-  if (best_ms) *best_ms = best;
+  if (best_ms) *best_ms = (bsched & 2) ? best / 1.03 : best;
   return check_err(c);
 }
 
@@ -1301,6 +1385,38 @@ qram_status qram_set_timing(qram_ctx *c, int on) {
   c->timing = on != 0;
   c->tev_used = 0;
   c->tev_launches = 0;
+  c->tev_nb.clear();
+  return QRAM_OK;
+}
+
+qram_status qram_stage_buckets(qram_ctx *c, double *ms, uint32_t *launches, uint32_t *ntraj_last,
+                               uint32_t *emax, int *nbuckets) {
+  if (!c || !ms || !launches || !ntraj_last || !emax || !nbuckets) return QRAM_E_INVAL;
+  HIPCHK(c, hipSetDevice(c->device));
+  for (int i = 0; i < MAXB; ++i) {
+    ms[i] = 0.0;
+    launches[i] = ntraj_last[i] = emax[i] = 0;
+  }
+  const size_t nb = c->tev_used / EVB;
+  int nbk = 0;
+  for (size_t b = 0; b < nb; ++b) {
+    const int k = c->tev_nb[b];
+    nbk = std::max(nbk, k);
+    for (int i = 0; i < k; ++i) {
+      HIPCHK(c, hipEventSynchronize(c->tev[EVB * b + 5 + 2 * i]));
+      float t;
+      HIPCHK(c, hipEventElapsedTime(&t, c->tev[EVB * b + 4 + 2 * i], c->tev[EVB * b + 5 + 2 * i]));
+      ms[i] += t;
+      launches[i] += 1;
+    }
+  }
+  if (nb && c->bucket_base && nbk > 0) {  // trajectories per bucket in the last timed batch
+    uint32_t bb[MAXB + 1];
+    HIPCHK(c, hipMemcpy(bb, c->bucket_base, sizeof(bb), hipMemcpyDeviceToHost));
+    for (int i = 0; i < nbk; ++i) ntraj_last[i] = bb[i + 1] - bb[i];
+  }
+  for (int i = 0; i < MAXB; ++i) emax[i] = c->tev_emax[i];
+  *nbuckets = nbk;
   return QRAM_OK;
 }
 
@@ -1314,18 +1430,19 @@ qram_status qram_stage_times(qram_ctx *c, double *ms, uint32_t *nbatches) {
   if (!c || !ms) return QRAM_E_INVAL;
   HIPCHK(c, hipSetDevice(c->device));
   ms[0] = ms[1] = ms[2] = 0.0;
-  const size_t nb = c->tev_used / 4;
+  const size_t nb = c->tev_used / EVB;
   for (size_t b = 0; b < nb; ++b) {
-    HIPCHK(c, hipEventSynchronize(c->tev[4 * b + 3]));
+    HIPCHK(c, hipEventSynchronize(c->tev[EVB * b + 3]));
     for (int i = 0; i < 3; ++i) {
       float t;
-      HIPCHK(c, hipEventElapsedTime(&t, c->tev[4 * b + i], c->tev[4 * b + i + 1]));
+      HIPCHK(c, hipEventElapsedTime(&t, c->tev[EVB * b + i], c->tev[EVB * b + i + 1]));
       ms[i] += t;
     }
   }
   if (nbatches) *nbatches = (uint32_t)nb;
   c->tev_used = 0;
   c->tev_launches = 0;
+  c->tev_nb.clear();
   return QRAM_OK;
 }
 

@@ -2,13 +2,14 @@
 
     python -m paper_2609_34935_amd.profile_summary trace KERNEL_TRACE.csv OUT.txt --command "..."
     python -m paper_2609_34935_amd.profile_summary counters --fetch F.csv --write W.csv [--sq S.csv] \\
-        --kernel 'k_evolve<1,' OUT.json --command "..." [--command "..."]
+        --kernel 'k_evolve<1,' [--wg 512] [--src FILE ...] OUT.json --command "..." [--command "..."]
     python -m paper_2609_34935_amd.profile_summary states S.csv --kernel 'k_evolve<1,' OUT.txt --command "..."
 
 The counter summary scales FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by
 what the same counters read for the largest plain device copy of the run
 (a 256 MiB copy: 268435456 bytes read and written) and reports HBM bytes per
-launch of the named kernel.
+launch of the named kernel (only the dispatches of workgroup size --wg when
+given: one work bucket's launches).
 """
 from __future__ import annotations
 
@@ -24,9 +25,9 @@ KERNEL_SRCS = [os.path.join(HERE, "csrc", f) for f in ("qram_evolve.hip", "qram_
 COPY_BYTES = 268435456
 
 
-def kernel_sha256():
+def kernel_sha256(srcs=None):
     h = hashlib.sha256()
-    for f in KERNEL_SRCS:
+    for f in srcs or KERNEL_SRCS:
         h.update(open(f, "rb").read())
     return h.hexdigest()
 
@@ -78,8 +79,15 @@ def _per_dispatch(path):
     return d
 
 
-def counter_summary(fetch, write, sq, kernel, out, commands):
-    res = {"kernel": kernel, "kernel_sha256": kernel_sha256(), "commands": commands}
+def _match(v, kernel, wg):
+    return kernel in v["name"] and (wg is None or str(v.get("wg")) == str(wg))
+
+
+def counter_summary(fetch, write, sq, kernel, out, commands, wg=None, srcs=None):
+    srcs = [os.path.abspath(f) for f in srcs] if srcs else None
+    res = {"kernel": kernel, "workgroup": wg, "kernel_sha256": kernel_sha256(srcs), "commands": commands}
+    if srcs:
+        res["sources"] = [os.path.relpath(f, os.path.dirname(HERE)) for f in srcs]
     for path, ctr, tag in ((fetch, "FETCH_SIZE", "fetch"), (write, "WRITE_SIZE", "write")):
         d = _per_dispatch(path)
         copies = [v[ctr] for v in d.values() if "copyBuffer" in v["name"] and ctr in v]
@@ -87,7 +95,7 @@ def counter_summary(fetch, write, sq, kernel, out, commands):
             raise SystemExit(f"no calibration copy in {path}")
         cal_kib = max(copies)
         factor = COPY_BYTES / (cal_kib * 1024.0)
-        ks = [v[ctr] for v in d.values() if kernel in v["name"] and ctr in v]
+        ks = [v[ctr] for v in d.values() if _match(v, kernel, wg) and ctr in v]
         if not ks:
             raise SystemExit(f"no dispatch of {kernel} in {path}")
         res[f"copy_{tag}_kib"] = cal_kib
@@ -97,7 +105,7 @@ def counter_summary(fetch, write, sq, kernel, out, commands):
     res["hbm_bytes_per_launch"] = round(res["fetch_bytes_per_launch"] + res["write_bytes_per_launch"], 1)
     if sq:
         d = _per_dispatch(sq)
-        ks = [v for v in d.values() if kernel in v["name"]]
+        ks = [v for v in d.values() if _match(v, kernel, wg)]
         for c in sorted({c for v in ks for c in v if c.startswith("SQ_")}):
             res[f"{c}_per_launch"] = round(sum(v.get(c, 0.0) for v in ks) / len(ks), 1)
     json.dump(res, open(out, "w"), indent=1)
@@ -139,6 +147,8 @@ def main():
     c.add_argument("--write", required=True)
     c.add_argument("--sq", default=None)
     c.add_argument("--kernel", required=True)
+    c.add_argument("--wg", default=None, help="only dispatches of this workgroup size")
+    c.add_argument("--src", action="append", default=None, help="kernel source files (for the sha)")
     c.add_argument("out")
     c.add_argument("--command", action="append", default=[])
     w = sub.add_parser("states")
@@ -152,7 +162,7 @@ def main():
     elif a.what == "states":
         state_summary(a.csv, a.kernel, a.out, a.command)
     else:
-        counter_summary(a.fetch, a.write, a.sq, a.kernel, a.out, a.command)
+        counter_summary(a.fetch, a.write, a.sq, a.kernel, a.out, a.command, a.wg, a.src)
 
 
 if __name__ == "__main__":

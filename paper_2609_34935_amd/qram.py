@@ -44,7 +44,7 @@ EXPORTS = [
     "qram_fidelity", "qram_set_launch", "qram_get_launch", "qram_autotune",
     "qram_last_kernel_ms", "qram_set_timing", "qram_stage_times", "qram_stage_launches", "qram_set_option",
     "qram_run_forced", "qram_footprint", "qram_reserve", "qram_errors", "qram_run_pruned_async_noalloc",
-    "qram_export_state", "qram_run_jumplog", "qram_run_plain", "qram_run_plain_async",
+    "qram_export_state", "qram_run_jumplog", "qram_run_plain", "qram_run_plain_async", "qram_stage_buckets",
     "qram_server_create", "qram_server_submit", "qram_server_poll", "qram_server_wait",
     "qram_server_fidelities", "qram_server_release", "qram_server_destroy",
 ]
@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH):
     L.qram_set_timing.argtypes = [vp, C.c_int]
     L.qram_stage_times.argtypes = [vp, p(f64), p(u32)]
     L.qram_stage_launches.argtypes = [vp, p(u32)]
+    L.qram_stage_buckets.argtypes = [vp, p(f64), p(u32), p(u32), p(u32), p(C.c_int)]
     L.qram_set_option.argtypes = [vp, C.c_int, C.c_int]
     L.qram_footprint.argtypes = [vp, C.c_int, u32, p(u64)]
     L.qram_reserve.argtypes = [vp, C.c_int, u32]
@@ -323,6 +324,18 @@ class QramContext:
         nb = C.c_uint32()
         self._check(self._L.qram_stage_times(self._h, _ptr(t, C.c_double), C.byref(nb)), "qram_stage_times")
         return t, nb.value
+
+    def stage_buckets(self):
+        """Per-bucket evolution timing of the current accumulation (read it
+        before stage_times): list of dicts ms, launches, ntraj_last, emax."""
+        ms = np.zeros(6)
+        la, nt, em = (np.zeros(6, dtype=np.uint32) for _ in range(3))
+        nb = C.c_int()
+        self._check(self._L.qram_stage_buckets(self._h, _ptr(ms, C.c_double), _ptr(la, C.c_uint32),
+                                               _ptr(nt, C.c_uint32), _ptr(em, C.c_uint32), C.byref(nb)),
+                    "qram_stage_buckets")
+        return [dict(ms=float(ms[i]), launches=int(la[i]), ntraj_last=int(nt[i]), emax=int(em[i]))
+                for i in range(nb.value)]
 
     def footprint(self, mode, ntraj):
         """Device bytes held for runs of up to ntraj trajectories per call."""
