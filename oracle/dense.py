@@ -7,7 +7,10 @@ numpy array, each gate is a permutation of the full basis built by vectorised
 digit arithmetic, and noise is either a forced joint Kraus outcome K_J
 (Eq. layerkraus) applied to a state vector, or the full amplitude-damping
 channel (Eq. kraus, Eq. kraus-tri) applied site by site to a density matrix,
-as in the circuit-level cross-check of App. C.
+as in the circuit-level cross-check of App. C.  Depolarizing noise (Sec. II
+B) is the uniform mixture of X, Z and ZX on a qubit and of the eight
+nontrivial Weyl operators Z^b X^a on a qutrit router, on the active positions
+of App. C's placement, before the slice's damping.
 
 Register digits, in order: address bit t (t = 0 is the root's bit, the most
 significant bit of i), bus bit b, then tree sites q = 2v (router) and
@@ -204,6 +207,51 @@ class Machine:
         """Boolean table: tree site q excited in basis state x."""
         return self.digits[:, self.n + self.k:] != 0
 
+    # ---- depolarizing faults ----
+    def active_sites(self, s):
+        """Sites of the layers above the leaf layer whose router holds its
+        address bit before and after the gates of slice s (stored at 3t+2,
+        unstored at T-3t-2): every site of those layers."""
+        l = sum(1 for t in range(self.n - 1) if 3 * t + 2 < s < self.T - 3 * t - 2)
+        return list(range(2 * (2 ** l - 1)))
+
+    def levels(self, q):
+        return 3 if (self.enc == QUTRIT and q % 2 == 0) else 2
+
+    def fault_ops(self, q):
+        """The (a, b) of the depolarizing mixture at site q: Z^b X^a."""
+        if self.levels(q) == 2:
+            return [(1, 0), (0, 1), (1, 1)]
+        return [(a, b) for a in range(3) for b in range(3) if (a, b) != (0, 0)]
+
+    def _fault_map(self, q, a, b):
+        d = self.levels(q)
+        dig = self.digits.copy()
+        new = (dig[:, self.S(q)] + a) % d
+        dig[:, self.S(q)] = new
+        w = np.exp(2j * np.pi / d)
+        return self.index(dig), w ** (b * new)
+
+    def fault(self, psi, q, a, b):
+        """Apply Z^b X^a to site q of a state vector."""
+        dest, ph = self._fault_map(q, a, b)
+        out = np.zeros_like(psi)
+        out[dest] = ph * psi
+        return out
+
+    def depol_rho(self, rho, s, p):
+        """Depolarizing channel of strength p on every active site of slice s."""
+        for q in self.active_sites(s):
+            ops = self.fault_ops(q)
+            new = (1.0 - p) * rho
+            for a, b in ops:
+                dest, ph = self._fault_map(q, a, b)
+                r = np.zeros_like(rho)
+                r[np.ix_(dest, dest)] = (ph[:, None] * np.conj(ph)[None, :]) * rho
+                new = new + (p / len(ops)) * r
+            rho = new
+        return rho
+
     # ---- noise ----
     def kraus_J(self, psi, J, gamma):
         """Apply K_J (Eq. layerkraus) for the joint outcome J = {(site, level)}."""
@@ -242,8 +290,10 @@ class Machine:
         return rho
 
 
-def density_fidelity(n, k, enc, mem, gamma):
-    """F_rho = <psi_id| rho |psi_id> of the whole query under damping."""
+def density_fidelity(n, k, enc, mem, gamma, eps=0.0):
+    """F_rho = <psi_id| rho |psi_id> of the whole query under damping and
+    (eps > 0) depolarizing noise: per slice the gates, then the depolarizing
+    channel on the active sites, then damping on every tree site."""
     m = Machine(n, k, enc, mem)
     psi = m.input_state()
     if enc == QUBIT:
@@ -251,17 +301,22 @@ def density_fidelity(n, k, enc, mem, gamma):
     rho = np.outer(psi, psi.conj())
     for s in range(1, m.T):
         rho = m.gates_rho(rho, s)
-        rho = m.damp_rho(rho, gamma)
+        if eps > 0.0:
+            rho = m.depol_rho(rho, s, eps)
+        if gamma > 0.0:
+            rho = m.damp_rho(rho, gamma)
     if enc == QUBIT:
         rho = m.wall_rho(rho)
     pid = m.ideal_state()
     return float(np.real(pid.conj() @ rho @ pid)), float(np.real(np.trace(rho)))
 
 
-def forced_evolution(n, k, enc, mem, gamma, jumps, stop_before_wall=True, machine=None):
+def forced_evolution(n, k, enc, mem, gamma, jumps, stop_before_wall=True, machine=None, faults=()):
     """State vector under a forced sequence of joint outcomes.
 
     jumps: list of (slice, site, level).  Every other layer applies K_empty.
+    faults: depolarizing faults (slice, site, a, b), applied after the gates
+    of their slice and before its damping layer.
     Returns the final state (before the second wall unless told otherwise)."""
     m = machine if machine is not None else Machine(n, k, enc, mem)
     psi = m.input_state()
@@ -270,8 +325,13 @@ def forced_evolution(n, k, enc, mem, gamma, jumps, stop_before_wall=True, machin
     byslice = {}
     for s, q, lev in jumps:
         byslice.setdefault(s, []).append((q, lev))
+    fby = {}
+    for s, q, a, b in faults:
+        fby.setdefault(s, []).append((q, a, b))
     for s in range(1, m.T):
         psi = m.gates(psi, s)
+        for q, a, b in fby.get(s, []):
+            psi = m.fault(psi, q, a, b)
         psi = m.kraus_J(psi, byslice.get(s, []), gamma)
     if enc == QUBIT and not stop_before_wall:
         psi = m.wall(psi)

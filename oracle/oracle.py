@@ -67,6 +67,18 @@ def lib():
         L.orc_run_indices.argtypes = [
             C.c_int, C.c_int, C.c_int, C.c_double, u32p, C.c_uint64, u32p,
             C.c_int, C.c_int, f64p, f64p, i32p]
+        L.orc_run_traj_ex.argtypes = [
+            C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, u32p, f64p, u32p,
+            C.c_uint64, C.c_uint32, u32p, C.c_int, f64p, C.c_double,
+            C.c_int, u32p, u32p, u8p, C.c_int, C.c_int, f64p, i32p,
+            i32p, i32p, i32p, C.c_int, i32p,
+            u32p, u32p, f64p, u8p, u32p, C.c_int]
+        L.orc_run_many_ex.argtypes = [
+            C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, u32p, f64p, u32p,
+            C.c_uint64, C.c_uint32, u32p, C.c_int, C.c_int, f64p, f64p, i32p]
+        L.orc_sample_depol.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_uint64, C.c_uint32,
+                                       u32p, u8p, C.c_int]
+        L.orc_depol_active.argtypes = [C.c_int, C.c_int, i32p]
         _lib = L
     return _lib
 
@@ -133,14 +145,35 @@ def _mem(mem):
     return np.ascontiguousarray(mem, dtype=np.uint32)
 
 
+def _cin(cin, n):
+    if cin is None:
+        return None
+    c = np.asarray(cin, dtype=np.complex128)
+    assert c.shape == (1 << n,)
+    out = np.empty(2 * len(c))
+    out[0::2], out[1::2] = c.real, c.imag
+    return out
+
+
+def _jin(jin, n):
+    if jin is None:
+        return None
+    j = np.ascontiguousarray(jin, dtype=np.uint32)
+    assert j.shape == (1 << n,)
+    return j
+
+
 def run_traj(n, k, enc, gamma, mem, seed=0, traj=0, forced_L=None,
              forced_uaux=None, forced_ufin=-1.0, check_counts=False,
-             export=False, jcap=4096):
+             export=False, jcap=4096, eps=0.0, cin=None, jin=None, forced_dep=None):
     """One trajectory of the full (unpruned) evolution.
 
-    Returns a dict with fid, fid_pre, w_ground, w_total, ncand, nbad, ref,
-    nexplicit, njumps, first_jump, ref_survived, q_ground, max_exc, the jump
-    log and, if export, the final pre-wall components."""
+    eps: depolarizing strength; cin / jin: input amplitude and bus word of
+    every address (None: uniform, 0); forced_dep: list of faults (slice,
+    site, a, b), the operator Z^b X^a, replacing the depolarizing draws.  Returns a dict with fid, fid_pre, w_ground,
+    w_total, ncand, nbad, ref, nexplicit, njumps, first_jump, ref_survived,
+    q_ground, max_exc, ndep, the jump log and, if export, the final pre-wall
+    components."""
     mem = _mem(mem)
     T = 6 * n + 2 * k
     M = 2 * ((1 << n) - 1)
@@ -162,11 +195,23 @@ def run_traj(n, k, enc, gamma, mem, seed=0, traj=0, forced_L=None,
     eamp = np.zeros(2 * max(cap, 1))
     etree = np.zeros(max(cap, 1) * M, dtype=np.uint8)
     elab = np.zeros(max(cap, 1), dtype=np.uint32)
-    ne = lib().orc_run_traj(
-        n, k, enc, gamma, _p(mem, C.c_uint32), seed, traj,
+    cinp, jinp = _cin(cin, n), _jin(jin, n)
+    dS = dQ = dT = None
+    if forced_dep is not None:  # list of (slice, site, a, b), slices ascending
+        fd = sorted(forced_dep, key=lambda f: f[0])
+        dS = np.array([f[0] for f in fd], dtype=np.uint32)
+        dQ = np.array([f[1] for f in fd], dtype=np.uint32)
+        dT = np.array([f[2] | (f[3] << 2) for f in fd], dtype=np.uint8)
+    ne = lib().orc_run_traj_ex(
+        n, k, enc, gamma, eps, _p(mem, C.c_uint32), _p(cinp, C.c_double), _p(jinp, C.c_uint32), seed, traj,
         _p(fL, C.c_uint32) if fL is not None else None,
         len(fL) if fL is not None else 0,
         _p(fU, C.c_double) if fU is not None else None, forced_ufin,
+        1 if forced_dep is not None else 0,
+        _p(dS, C.c_uint32) if dS is not None and len(dS) else None,
+        _p(dQ, C.c_uint32) if dQ is not None and len(dQ) else None,
+        _p(dT, C.c_uint8) if dT is not None and len(dT) else None,
+        0 if dS is None else len(dS),
         1 if check_counts else 0, _p(rd, C.c_double), _p(ri, C.c_int),
         _p(js, C.c_int), _p(jq, C.c_int), _p(jv, C.c_int), jcap, _p(njl, C.c_int),
         _p(ea, C.c_uint32), _p(eb, C.c_uint32), _p(eamp, C.c_double),
@@ -176,7 +221,7 @@ def run_traj(n, k, enc, gamma, mem, seed=0, traj=0, forced_L=None,
     out = dict(fid=rd[0], fid_pre=rd[1], w_ground=rd[2], w_total=rd[3],
                ncand=int(ri[0]), nbad=int(ri[1]), ref=int(ri[2]),
                nexplicit=int(ri[3]), njumps=int(ri[4]), first_jump=int(ri[5]),
-               ref_survived=int(ri[6]), q_ground=int(ri[7]), max_exc=int(ri[8]))
+               ref_survived=int(ri[6]), q_ground=int(ri[7]), max_exc=int(ri[8]), ndep=int(ri[9]))
     nj = int(njl[0])
     out["jumps"] = [(int(js[j]), int(jq[j]), int(jv[j])) for j in range(min(nj, jcap))]
     if export:
@@ -221,6 +266,44 @@ def run_batch(n, k, enc, gamma, mem, seed, traj0, ntraj, nthreads=0):
     return fid, fpre, ri.reshape(ntraj, NRI), used
 
 
+def run_many(n, k, enc, gamma, mem, seed, traj0=0, ntraj=None, idx=None, nthreads=0, eps=0.0, cin=None,
+             jin=None):
+    """Trajectories traj0.. (or the listed indices) with depolarizing
+    strength eps and a general input; returns (fid, fid_pre, stats, threads)."""
+    mem = _mem(mem)
+    if idx is not None:
+        idx = np.ascontiguousarray(idx, dtype=np.uint32)
+        ntraj = len(idx)
+    fid = np.zeros(ntraj)
+    fpre = np.zeros(ntraj)
+    ri = np.zeros(max(ntraj, 1) * NRI, dtype=np.int32)
+    cinp, jinp = _cin(cin, n), _jin(jin, n)
+    used = lib().orc_run_many_ex(n, k, enc, gamma, eps, _p(mem, C.c_uint32), _p(cinp, C.c_double),
+                                 _p(jinp, C.c_uint32), seed, traj0, _p(idx, C.c_uint32), ntraj, nthreads,
+                                 _p(fid, C.c_double), _p(fpre, C.c_double), _p(ri, C.c_int))
+    if used < 0:
+        raise ValueError("oracle error")
+    return fid, fpre, ri[:ntraj * NRI].reshape(ntraj, NRI), used
+
+
+def sample_depol(n, k, enc, eps, seed, traj):
+    """Depolarizing faults of one trajectory: (linear indices, types a | b << 2)."""
+    cnt = lib().orc_sample_depol(n, k, enc, eps, seed, traj, None, None, 0)
+    if cnt < 0:
+        raise ValueError("bad parameters")
+    L = np.zeros(max(cnt, 1), dtype=np.uint32)
+    t = np.zeros(max(cnt, 1), dtype=np.uint8)
+    lib().orc_sample_depol(n, k, enc, eps, seed, traj, _p(L, C.c_uint32), _p(t, C.c_uint8), cnt)
+    return L[:cnt], t[:cnt]
+
+
+def depol_active(n, k):
+    """Active depolarizing positions of each slice (index = slice)."""
+    a = np.zeros(6 * n + 2 * k, dtype=np.int32)
+    T = lib().orc_depol_active(n, k, _p(a, C.c_int))
+    return a[:T]
+
+
 def run_indices(n, k, enc, gamma, mem, seed, idx, nthreads=0):
     """The listed trajectory indices; returns (fid, fid_pre, stats, threads)."""
     mem = _mem(mem)
@@ -237,4 +320,4 @@ def run_indices(n, k, enc, gamma, mem, seed, idx, nthreads=0):
 
 
 STAT_FIELDS = ["ncand", "nbad", "ref", "nexplicit", "njumps", "first_jump",
-               "ref_survived", "q_ground", "max_exc", "unused"]
+               "ref_survived", "q_ground", "max_exc", "ndep"]

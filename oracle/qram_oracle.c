@@ -24,6 +24,11 @@
  *   4. The end of the query: the second Hadamard wall (qubit encoding), the
  *      tree measurement, and the fidelity of the post-measurement state with
  *      the ideal output sum_i c_i |i>|d_i>|ground> (Eq. nk-qram, App. C).
+ *   Optionally (the _ex entry points): depolarizing faults of strength eps
+ *   (Sec. II B; placement of App. C), drawn in advance like the damping
+ *   candidates, applied as unitaries after the gates of their slice and
+ *   before its damping layer, and marked by the same rule; and a general
+ *   input sum_i c_i |i>|j_i> with one bus word per address (Sec. IV D).
  *
  * Conventions fixed here where the paper is silent (they are restated in the
  * design notes):
@@ -51,6 +56,22 @@
  *     orders the final tree measurement: the ground-configuration block
  *     first.  Any fixed order samples the distribution of Theorem 4.
  *   - Amplitudes are kept unnormalised; draws use ratios (Sec. II B).
+ *   - Depolarizing placement (pinned by the Pauli and Mixed rows of Table 4):
+ *     in slice s the active positions are every site of the layers above the
+ *     leaf layer whose router holds its address bit both before and after
+ *     the gates of s (address bit t is stored at 3t+2 and unstored at
+ *     T-3t-2), a prefix of the site numbering.  Each active position suffers
+ *     a fault with probability eps; the faults form a geometric walk in
+ *     64-site blocks over the linear index L = (active positions of slices
+ *     1..s-1) + q, counters (block, draw, trajectory, 4).  The type comes from
+ *     word w2 of the same draw: qubits (and the qutrit data slot) take X, Z
+ *     or ZX = iY, index (w2 * 3) >> 32; a qutrit router takes one of the
+ *     eight nontrivial Weyl operators, index (w2 * 8) >> 32 into (a, b) =
+ *     (0,1) (0,2) (1,0) (1,1) (1,2) (2,0) (2,1) (2,2).  A fault (a, b) maps
+ *     level x to x + a (mod d), then multiplies by w_d^(b (x + a)), w_2 = -1,
+ *     w_3 = exp(2 pi i / 3); qubit X = (1,0), Z = (0,1), ZX = (1,1).
+ *     Within a slice: gates, then the slice's depolarizing faults, then its
+ *     damping layer.
  */
 #include <complex.h>
 #include <math.h>
@@ -67,6 +88,7 @@
 #define ORC_TAG_FAULT 1u
 #define ORC_TAG_AUX 2u
 #define ORC_TAG_FINAL 3u
+#define ORC_TAG_DEPOL 4u
 
 /* qutrit router levels; a qubit site uses 0/1 */
 #define LV_W 0
@@ -113,6 +135,13 @@ static uint64_t draw_u64(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t traj,
   return (uint64_t)w[0] | ((uint64_t)w[1] << 32);
 }
 
+static void draw_words(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t traj,
+                       uint32_t tag, uint32_t w[4]) {
+  uint32_t ctr[4] = {c0, c1, traj, tag};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  orc_philox4x32_10(ctr, key, w);
+}
+
 static double u53(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
 
 double orc_uniform(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t traj,
@@ -147,6 +176,13 @@ typedef struct {
   double gamma, a, sg;
   const uint32_t *mem;
   uint64_t G[64];
+  /* depolarizing faults and general inputs (zero / NULL: none, uniform) */
+  double eps;
+  uint64_t Gp[64];
+  int nact[512];          /* active positions of slice s: sites 0 .. nact-1 */
+  uint64_t dep_off[513];  /* linear index of slice s's first active position */
+  double complex *cin;    /* normalised input amplitude of each address */
+  uint32_t *jin;          /* input bus word of each address */
   int nev[512];
   int ev_type[512][ORC_MAXEV];
   int ev_arg[512][ORC_MAXEV];
@@ -214,7 +250,75 @@ static int cfg_init(orc_cfg *c, int n, int k, int enc, double gamma,
   c->mem = mem;
   orc_thresholds(gamma, c->G);
   build_schedule(c);
+  c->eps = 0.0;
+  c->cin = NULL;
+  c->jin = NULL;
+  memset(c->nact, 0, sizeof(c->nact));
+  memset(c->dep_off, 0, sizeof(c->dep_off));
   return 0;
+}
+
+/* Layers whose router holds its address bit both before and after the gates
+ * of slice s, among the layers above the leaf layer (App. C placement). */
+static int active_layers(const orc_cfg *c, int s) {
+  int l = 0;
+  for (int t = 0; t + 1 < c->n; ++t)
+    if (3 * t + 2 < s && s < c->T - 3 * t - 2)
+      ++l;
+  return l;
+}
+
+/* Depolarizing strength and general input (cin: 2 doubles per address, or
+ * NULL; jin: bus word per address, or NULL).  Returns < 0 on bad input. */
+static int cfg_extras(orc_cfg *c, double eps, const double *cin,
+                      const uint32_t *jin) {
+  if (!(eps >= 0.0 && eps < 1.0))
+    return -1;
+  c->eps = eps;
+  orc_thresholds(eps, c->Gp);
+  uint64_t off = 0;
+  for (int s = 1; s < c->T; ++s) {
+    int l = active_layers(c, s);
+    c->nact[s] = 2 * ((1 << l) - 1);
+    c->dep_off[s] = off;
+    off += (uint64_t)c->nact[s];
+  }
+  c->dep_off[c->T] = off;
+  if (cin) {
+    double norm = 0.0;
+    c->cin = (double complex *)malloc(sizeof(double complex) * c->D);
+    for (int i = 0; i < c->D; ++i) {
+      c->cin[i] = cin[2 * i] + I * cin[2 * i + 1];
+      norm += creal(c->cin[i]) * creal(c->cin[i]) +
+              cimag(c->cin[i]) * cimag(c->cin[i]);
+    }
+    if (!(norm > 0.0))
+      return -1;
+    for (int i = 0; i < c->D; ++i)
+      c->cin[i] /= sqrt(norm);
+  }
+  if (jin) {
+    c->jin = (uint32_t *)malloc(sizeof(uint32_t) * c->D);
+    for (int i = 0; i < c->D; ++i)
+      c->jin[i] = jin[i] & (uint32_t)(c->K2 - 1);
+  }
+  return 0;
+}
+
+static void cfg_free(orc_cfg *c) {
+  if (!c)
+    return;
+  free(c->cin);
+  free(c->jin);
+  free(c);
+}
+
+static double complex in_amp(const orc_cfg *c, uint32_t i) {
+  return c->cin ? c->cin[i] : 1.0 / sqrt((double)c->D);
+}
+
+static uint32_t in_bus(const orc_cfg *c, uint32_t i) {
+  return c->jin ? c->jin[i] : 0u;
 }
 
 /* Export the event list of slice s (for schedule tests). */
@@ -279,6 +383,92 @@ int orc_sample(int n, int k, double gamma, uint64_t seed, uint32_t traj,
   return cnt;
 }
 
+/* Depolarizing faults: linear indices L (ascending) over the active
+ * positions and their types (a | b << 2, see the header). */
+static int sample_depol(const orc_cfg *c, uint64_t seed, uint32_t traj,
+                        uint32_t *L, uint8_t *type, int cap) {
+  uint64_t S = c->dep_off[c->T];
+  if (c->eps <= 0.0 || S == 0)
+    return 0;
+  static const uint8_t weyl[8][2] = {{0, 1}, {0, 2}, {1, 0}, {1, 1},
+                                     {1, 2}, {2, 0}, {2, 1}, {2, 2}};
+  static const uint8_t pauli[3][2] = {{1, 0}, {0, 1}, {1, 1}};
+  uint64_t nb = (S + 63) / 64;
+  int cnt = 0;
+  int s = 1;
+  for (uint64_t b = 0; b < nb; ++b) {
+    uint64_t len = S - 64 * b < 64 ? S - 64 * b : 64;
+    uint64_t pos = 0;
+    for (uint32_t j = 0;; ++j) {
+      uint32_t w[4];
+      draw_words(seed, (uint32_t)b, j, traj, ORC_TAG_DEPOL, w);
+      uint64_t u = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+      int o = 0;
+      while (o < 64 && !(u < c->Gp[o]))
+        ++o;
+      if (o == 64 || pos + (uint64_t)o >= len)
+        break;
+      uint64_t Lx = 64 * b + pos + (uint64_t)o;
+      while (c->dep_off[s + 1] <= Lx)
+        ++s;
+      int q = (int)(Lx - c->dep_off[s]);
+      int router3 = c->enc == ORC_QUTRIT && (q & 1) == 0;
+      const uint8_t *ab = router3 ? weyl[((uint64_t)w[2] * 8u) >> 32]
+                                  : pauli[((uint64_t)w[2] * 3u) >> 32];
+      if (cnt < cap && L) {
+        L[cnt] = (uint32_t)Lx;
+        type[cnt] = (uint8_t)(ab[0] | (ab[1] << 2));
+      }
+      ++cnt;
+      pos += (uint64_t)o + 1;
+    }
+  }
+  return cnt;
+}
+
+/* Slice and site of a depolarizing linear index. */
+static void depol_site(const orc_cfg *c, uint32_t Lx, int *s, int *q) {
+  int ss = 1;
+  while (c->dep_off[ss + 1] <= Lx)
+    ++ss;
+  *s = ss;
+  *q = (int)(Lx - c->dep_off[ss]);
+}
+
+int orc_sample_depol(int n, int k, int enc, double eps, uint64_t seed,
+                     uint32_t traj, uint32_t *L, uint8_t *type, int cap) {
+  static const uint32_t zero_mem[1] = {0};
+  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  int rc = cfg_init(c, n, k, enc, 0.0, zero_mem);
+  if (!rc)
+    rc = cfg_extras(c, eps, NULL, NULL);
+  if (rc) {
+    cfg_free(c);
+    return rc;
+  }
+  int cnt = sample_depol(c, seed, traj, L, type, cap);
+  cfg_free(c);
+  return cnt;
+}
+
+/* Active positions per slice (for the tests): nact[s] for s = 0..T-1. */
+int orc_depol_active(int n, int k, int *nact) {
+  static const uint32_t zero_mem[1] = {0};
+  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  int rc = cfg_init(c, n, k, ORC_QUBIT, 0.0, zero_mem);
+  if (!rc)
+    rc = cfg_extras(c, 0.0, NULL, NULL);
+  if (rc) {
+    cfg_free(c);
+    return rc;
+  }
+  for (int s = 0; s < c->T; ++s)
+    nact[s] = c->nact[s];
+  int T = c->T;
+  cfg_free(c);
+  return T;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Marking rule (Eq. subtree, Eq. badrange; Alg. 1 steps 1-2).              */
 /* ------------------------------------------------------------------------ */
@@ -300,9 +490,11 @@ static uint32_t range_node(int enc, uint32_t v) {
   }
 }
 
-/* bad[i] = 1 if address i lies in the bad range of some candidate. */
-static int classify(const orc_cfg *c, const uint32_t *L, int ncand,
-                    uint8_t *bad) {
+/* bad[i] = 1 if address i lies in the bad range of some candidate or of
+ * some depolarizing fault (dsites: their tree sites; the rule is the same
+ * whatever the fault's type, Sec. III B). */
+static int classify_all(const orc_cfg *c, const uint32_t *L, int ncand,
+                        const int *dsites, int ndep, uint8_t *bad) {
   int n = c->n;
   uint32_t nodes = (uint32_t)c->D - 1;
   uint8_t *mark = (uint8_t *)calloc(nodes, 1);
@@ -310,6 +502,8 @@ static int classify(const orc_cfg *c, const uint32_t *L, int ncand,
     uint32_t q = L[j] % (uint32_t)c->M;
     mark[range_node(c->enc, q >> 1)] = 1;
   }
+  for (int j = 0; j < ndep; ++j)
+    mark[range_node(c->enc, (uint32_t)dsites[j] >> 1)] = 1;
   int nbad = 0;
   for (uint32_t i = 0; i < (uint32_t)c->D; ++i) {
     int b = 0;
@@ -323,6 +517,11 @@ static int classify(const orc_cfg *c, const uint32_t *L, int ncand,
   }
   free(mark);
   return nbad;
+}
+
+static int classify(const orc_cfg *c, const uint32_t *L, int ncand,
+                    uint8_t *bad) {
+  return classify_all(c, L, ncand, NULL, 0, bad);
 }
 
 int orc_classify(int n, int k, int enc, const uint32_t *L, int ncand,
@@ -384,17 +583,45 @@ static void state_free(orc_state *st) {
  * For the qubit encoding the first Hadamard wall acts on the noiseless bus
  * before any tree gate touches it, so it is applied here. */
 static void state_init(const orc_cfg *c, orc_state *st) {
-  double ci = 1.0 / sqrt((double)c->D);
   double wall = c->enc == ORC_QUBIT ? 1.0 / sqrt((double)c->K2) : 1.0;
   for (int x = 0; x < c->E; ++x) {
     uint32_t i = c->enc == ORC_QUBIT ? (uint32_t)x >> c->k : (uint32_t)x;
     uint32_t beta = c->enc == ORC_QUBIT ? (uint32_t)x & (uint32_t)(c->K2 - 1) : 0;
+    double complex ci = in_amp(c, i);
     st->addr[x] = i;
-    st->bus[x] = beta;
-    st->alive[x] = 1;
     st->nexc[x] = 0;
-    st->amp[x] = ci * wall;
     memset(st->tree + (size_t)x * c->M, 0, c->M);
+    if (c->enc == ORC_QUBIT) {
+      /* the first wall on |j_i>: sum_beta (-1)^(beta . j_i) |beta> / sqrt(K2) */
+      int par = __builtin_popcount(beta & in_bus(c, i)) & 1;
+      st->bus[x] = beta;
+      st->amp[x] = (par ? -ci : ci) * wall;
+    } else {
+      st->bus[x] = in_bus(c, i);
+      st->amp[x] = ci;
+    }
+    st->alive[x] = ci != 0.0;
+  }
+}
+
+/* One depolarizing fault (a, b) on site q of component x: level v becomes
+ * v + a (mod d), then the amplitude takes w_d^(b (v + a)). */
+static void apply_depol(const orc_cfg *c, orc_state *st, int x, int q,
+                        int a, int b) {
+  uint8_t *tr = st->tree + (size_t)x * c->M;
+  int d = (c->enc == ORC_QUTRIT && (q & 1) == 0) ? 3 : 2;
+  int v = tr[q];
+  int w = (v + a) % d;
+  tr[q] = (uint8_t)w;
+  st->nexc[x] += (w != 0) - (v != 0);
+  int ph = (b * w) % d;
+  if (ph == 0)
+    return;
+  if (d == 2) {
+    st->amp[x] = -st->amp[x];
+  } else {
+    const double complex w3 = -0.5 + I * (sqrt(3.0) / 2.0);
+    st->amp[x] *= ph == 1 ? w3 : conj(w3);
   }
 }
 
@@ -535,6 +762,7 @@ typedef struct {
   int njumps, first_jump;
   int ref_survived, q_ground;
   int max_exc;
+  int ndep; /* depolarizing faults of the trajectory */
 } orc_result;
 
 #define ORC_JLOG_MAX 4096
@@ -659,6 +887,11 @@ typedef struct {
   int ncand;
   const double *uaux; /* forced auxiliary uniforms indexed by slice, or NULL */
   double ufin;        /* forced final uniform if >= 0 */
+  int dep_forced;     /* 1: the depolarizing faults below replace the draws */
+  const uint32_t *dS; /* forced depolarizing faults: slices (ascending), */
+  const uint32_t *dQ; /* sites (any site of the tree), */
+  const uint8_t *dtype; /* and types (a | b << 2) */
+  int ndep;
 } orc_forced;
 
 /* Evolve one trajectory; optionally stop after the gates of slice
@@ -678,11 +911,37 @@ static int run_traj(const orc_cfg *c, uint64_t seed, uint32_t traj,
     L = (uint32_t *)malloc(sizeof(uint32_t) * (ncand > 0 ? ncand : 1));
     sample_candidates(c, seed, traj, L, ncand);
   }
+  /* depolarizing faults: sampled, or forced */
+  int ndep;
+  uint32_t *dL = NULL;
+  uint8_t *dty;
+  int *dslice, *dsite;
+  if (fh && fh->dep_forced) {
+    ndep = fh->ndep;
+    dty = (uint8_t *)malloc(ndep > 0 ? ndep : 1);
+    dslice = (int *)malloc(sizeof(int) * (ndep > 0 ? ndep : 1));
+    dsite = (int *)malloc(sizeof(int) * (ndep > 0 ? ndep : 1));
+    for (int j = 0; j < ndep; ++j) {
+      dslice[j] = (int)fh->dS[j];
+      dsite[j] = (int)fh->dQ[j];
+      dty[j] = fh->dtype[j];
+    }
+  } else {
+    ndep = sample_depol(c, seed, traj, NULL, NULL, 0);
+    dL = (uint32_t *)malloc(sizeof(uint32_t) * (ndep > 0 ? ndep : 1));
+    dty = (uint8_t *)malloc(ndep > 0 ? ndep : 1);
+    sample_depol(c, seed, traj, dL, dty, ndep);
+    dslice = (int *)malloc(sizeof(int) * (ndep > 0 ? ndep : 1));
+    dsite = (int *)malloc(sizeof(int) * (ndep > 0 ? ndep : 1));
+    for (int j = 0; j < ndep; ++j)
+      depol_site(c, dL[j], &dslice[j], &dsite[j]);
+  }
   uint8_t *bad = (uint8_t *)malloc(c->D);
-  int nbad = classify(c, L, ncand, bad);
+  int nbad = classify_all(c, L, ncand, dsite, ndep, bad);
+  /* the reference: the smallest good address the input holds */
   int ref = -1;
   for (int i = 0; i < c->D; ++i)
-    if (!bad[i]) {
+    if (!bad[i] && in_amp(c, (uint32_t)i) != 0.0) {
       ref = i;
       break;
     }
@@ -692,13 +951,18 @@ static int run_traj(const orc_cfg *c, uint64_t seed, uint32_t traj,
   int *cq = (int *)malloc(sizeof(int) * (ncand > 0 ? ncand : 1));
   int *jsite = (int *)malloc(sizeof(int) * (ncand > 0 ? ncand : 1));
   int *jlev = (int *)malloc(sizeof(int) * (ncand > 0 ? ncand : 1));
-  int cpos = 0, njumps = 0, first_jump = 0, max_exc = 0;
+  int cpos = 0, njumps = 0, first_jump = 0, max_exc = 0, dpos = 0;
   for (int s = 1; s < T; ++s) {
+    int d0 = dpos;
+    while (dpos < ndep && dslice[dpos] == s)
+      ++dpos;
     for (int x = 0; x < c->E; ++x) {
       if (!st->alive[x])
         continue;
       for (int e = 0; e < c->nev[s]; ++e)
         apply_event(c, st, x, c->ev_type[s][e], c->ev_arg[s][e]);
+      for (int j = d0; j < dpos; ++j)
+        apply_depol(c, st, x, dsite[j], dty[j] & 3, dty[j] >> 2);
       if (st->nexc[x] > max_exc)
         max_exc = st->nexc[x];
       if (check_counts && count_exc(c, st, x) != st->nexc[x])
@@ -721,8 +985,8 @@ static int run_traj(const orc_cfg *c, uint64_t seed, uint32_t traj,
   free(jsite);
   free(jlev);
 
-  /* End of the query: wall 2 (qubit), tree measurement, fidelity. */
-  double ci = 1.0 / sqrt((double)c->D);
+  /* End of the query: wall 2 (qubit), tree measurement, fidelity.  The
+   * ideal output is sum_i c_i |i>|j_i xor d_i>|ground>. */
   double complex overlap = 0.0;
   nsum wg = {0, 0}, wt = {0, 0};
   if (c->enc == ORC_QUBIT) {
@@ -750,8 +1014,8 @@ static int run_traj(const orc_cfg *c, uint64_t seed, uint32_t traj,
                                                                : grp[beta];
         v *= h;
         nadd(&wg, abs2(v));
-        if ((uint32_t)cw == (c->mem[i] & (uint32_t)(K2 - 1)))
-          overlap += ci * v; /* conj(c_i) = c_i, real input */
+        if ((uint32_t)cw == ((in_bus(c, (uint32_t)i) ^ c->mem[i]) & (uint32_t)(K2 - 1)))
+          overlap += conj(in_amp(c, (uint32_t)i)) * v;
       }
     }
     free(grp);
@@ -765,8 +1029,9 @@ static int run_traj(const orc_cfg *c, uint64_t seed, uint32_t traj,
         continue;
       if (st->nexc[x] == 0) {
         nadd(&wg, abs2(st->amp[x]));
-        if (st->bus[x] == (c->mem[st->addr[x]] & (uint32_t)(c->K2 - 1)))
-          overlap += ci * st->amp[x];
+        uint32_t i = st->addr[x];
+        if (st->bus[x] == ((in_bus(c, i) ^ c->mem[i]) & (uint32_t)((1 << c->k) - 1)))
+          overlap += conj(in_amp(c, i)) * st->amp[x];
       } else {
         nadd(&wt, abs2(st->amp[x]));
       }
@@ -798,8 +1063,13 @@ static int run_traj(const orc_cfg *c, uint64_t seed, uint32_t traj,
       if (st->alive[x] && st->addr[x] == (uint32_t)ref)
         rs = 1;
   res->ref_survived = rs;
+  res->ndep = ndep;
   free(bad);
   free(L);
+  free(dL);
+  free(dty);
+  free(dslice);
+  free(dsite);
   return 0;
 }
 
@@ -828,7 +1098,7 @@ static void pack_result(const orc_result *r, double *rd, int *ri) {
     ri[6] = r->ref_survived;
     ri[7] = r->q_ground;
     ri[8] = r->max_exc;
-    ri[9] = 0;
+    ri[9] = r->ndep;
   }
 }
 
@@ -844,26 +1114,40 @@ static void pack_result(const orc_result *r, double *rd, int *ri) {
  * component in exp_tree).  Returns the number of exported components, or < 0
  * on error.
  */
-int orc_run_traj(int n, int k, int enc, double gamma, const uint32_t *mem,
-                 uint64_t seed, uint32_t traj, const uint32_t *forced_L,
-                 int forced_ncand, const double *forced_uaux,
-                 double forced_ufin, int check_counts, double *rd, int *ri,
-                 int *jslice, int *jsite, int *jlevel, int jcap, int *njl,
-                 uint32_t *exp_addr, uint32_t *exp_bus, double *exp_amp,
-                 uint8_t *exp_tree, uint32_t *exp_label, int exp_cap) {
+/*
+ * The same with depolarizing faults of strength eps and a general input
+ * (cin: 2 doubles per address or NULL; jin: bus word per address or NULL).
+ * dep_forced = 1 replaces the depolarizing draws by the faults
+ * (dep_slice, dep_site, dep_type) [ndep], slices ascending, any site, types
+ * a | b << 2.
+ */
+int orc_run_traj_ex(int n, int k, int enc, double gamma, double eps,
+                    const uint32_t *mem, const double *cin, const uint32_t *jin,
+                    uint64_t seed, uint32_t traj, const uint32_t *forced_L,
+                    int forced_ncand, const double *forced_uaux,
+                    double forced_ufin, int dep_forced,
+                    const uint32_t *dep_slice, const uint32_t *dep_site,
+                    const uint8_t *dep_type, int ndep, int check_counts,
+                    double *rd, int *ri, int *jslice, int *jsite, int *jlevel,
+                    int jcap, int *njl, uint32_t *exp_addr, uint32_t *exp_bus,
+                    double *exp_amp, uint8_t *exp_tree, uint32_t *exp_label,
+                    int exp_cap) {
   orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, enc, gamma, mem);
+  if (!rc)
+    rc = cfg_extras(c, eps, cin, jin);
   if (rc) {
-    free(c);
+    cfg_free(c);
     return rc;
   }
   orc_state st;
   if (state_alloc(&st, c->E, c->M)) {
     state_free(&st);
-    free(c);
+    cfg_free(c);
     return -2;
   }
-  orc_forced fh = {forced_L, forced_ncand, forced_uaux, forced_ufin};
+  orc_forced fh = {forced_L, forced_ncand, forced_uaux, forced_ufin,
+                   dep_forced, dep_slice, dep_site, dep_type, ndep};
   orc_jlog *jl = (orc_jlog *)malloc(sizeof(orc_jlog));
   orc_result res;
   run_traj(c, seed, traj, &fh, check_counts, &st, &res, jl);
@@ -895,8 +1179,22 @@ int orc_run_traj(int n, int k, int enc, double gamma, const uint32_t *mem,
   }
   free(jl);
   state_free(&st);
-  free(c);
+  cfg_free(c);
   return ne;
+}
+
+int orc_run_traj(int n, int k, int enc, double gamma, const uint32_t *mem,
+                 uint64_t seed, uint32_t traj, const uint32_t *forced_L,
+                 int forced_ncand, const double *forced_uaux,
+                 double forced_ufin, int check_counts, double *rd, int *ri,
+                 int *jslice, int *jsite, int *jlevel, int jcap, int *njl,
+                 uint32_t *exp_addr, uint32_t *exp_bus, double *exp_amp,
+                 uint8_t *exp_tree, uint32_t *exp_label, int exp_cap) {
+  return orc_run_traj_ex(n, k, enc, gamma, 0.0, mem, NULL, NULL, seed, traj,
+                         forced_L, forced_ncand, forced_uaux, forced_ufin, 0,
+                         NULL, NULL, NULL, 0, check_counts, rd, ri, jslice, jsite,
+                         jlevel, jcap, njl, exp_addr, exp_bus, exp_amp,
+                         exp_tree, exp_label, exp_cap);
 }
 
 /*
@@ -986,7 +1284,8 @@ int orc_layer_masks(int n, int k, int enc, double gamma, const uint32_t *mem,
  * fid_pre[ntraj] (or NULL), ri[ntraj*ORC_NRI] (or NULL).  nthreads <= 0 uses
  * the OpenMP default.  Returns the number of threads used.
  */
-static int run_many(int n, int k, int enc, double gamma, const uint32_t *mem,
+static int run_many(int n, int k, int enc, double gamma, double eps,
+                    const uint32_t *mem, const double *cin, const uint32_t *jin,
                     uint64_t seed, uint32_t traj0, const uint32_t *idx,
                     int ntraj, int nthreads, double *fid, double *fid_pre,
                     int *ri);
@@ -994,25 +1293,39 @@ static int run_many(int n, int k, int enc, double gamma, const uint32_t *mem,
 int orc_run_batch(int n, int k, int enc, double gamma, const uint32_t *mem,
                   uint64_t seed, uint32_t traj0, int ntraj, int nthreads,
                   double *fid, double *fid_pre, int *ri) {
-  return run_many(n, k, enc, gamma, mem, seed, traj0, NULL, ntraj, nthreads,
-                  fid, fid_pre, ri);
+  return run_many(n, k, enc, gamma, 0.0, mem, NULL, NULL, seed, traj0, NULL,
+                  ntraj, nthreads, fid, fid_pre, ri);
 }
 
 int orc_run_indices(int n, int k, int enc, double gamma, const uint32_t *mem,
                     uint64_t seed, const uint32_t *idx, int nidx, int nthreads,
                     double *fid, double *fid_pre, int *ri) {
-  return run_many(n, k, enc, gamma, mem, seed, 0, idx, nidx, nthreads, fid,
-                  fid_pre, ri);
+  return run_many(n, k, enc, gamma, 0.0, mem, NULL, NULL, seed, 0, idx, nidx,
+                  nthreads, fid, fid_pre, ri);
 }
 
-static int run_many(int n, int k, int enc, double gamma, const uint32_t *mem,
+/* Batches with depolarizing faults and a general input (see
+ * orc_run_traj_ex); idx may be NULL (then traj0 .. traj0+ntraj-1). */
+int orc_run_many_ex(int n, int k, int enc, double gamma, double eps,
+                    const uint32_t *mem, const double *cin, const uint32_t *jin,
+                    uint64_t seed, uint32_t traj0, const uint32_t *idx,
+                    int ntraj, int nthreads, double *fid, double *fid_pre,
+                    int *ri) {
+  return run_many(n, k, enc, gamma, eps, mem, cin, jin, seed, traj0, idx,
+                  ntraj, nthreads, fid, fid_pre, ri);
+}
+
+static int run_many(int n, int k, int enc, double gamma, double eps,
+                    const uint32_t *mem, const double *cin, const uint32_t *jin,
                     uint64_t seed, uint32_t traj0, const uint32_t *idx,
                     int ntraj, int nthreads, double *fid, double *fid_pre,
                     int *ri) {
   orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, enc, gamma, mem);
+  if (!rc)
+    rc = cfg_extras(c, eps, cin, jin);
   if (rc) {
-    free(c);
+    cfg_free(c);
     return rc;
   }
   int used = 1;
@@ -1054,6 +1367,6 @@ static int run_many(int n, int k, int enc, double gamma, const uint32_t *mem,
   }
   state_free(&st);
 #endif
-  free(c);
+  cfg_free(c);
   return used;
 }
