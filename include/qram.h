@@ -86,8 +86,9 @@ typedef struct {
  * Create a context for an (n,k)-QRAM in the given encoding with damping
  * strength gamma (Sec. II B; Theorem 4 needs gamma < 1).
  *   n_addr      1..15 (qubit), 1..14 (qutrit); k_data 1..8 with k <= n; the
- *               qubit encoding also needs k <= 6 and n + k <= 16 (at most
- *               65536 components per trajectory).
+ *               qubit encoding also needs n + k <= 16 (at most 65536
+ *               components per trajectory).  Qubit k_data 7 and 8 run on the
+ *               plain engine (see qram_create_ex).
  *   memory_bits host array of 2^n words; bit b of word i is d_i^(b); only the
  *               low k bits are used.  Copied: the caller may free it after the
  *               call returns.
@@ -98,6 +99,44 @@ typedef struct {
  */
 qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
                         const uint32_t *memory_bits, qram_ctx **out);
+
+/*
+ * Context with depolarizing noise and a general input (Sec. II B, Sec. IV D,
+ * App. C).  gamma, enc, n_addr, k_data and memory_bits as in qram_create.
+ *   eps          depolarizing strength in [0, 1).  In slice s every site of
+ *                the layers above the leaf layer whose router holds its
+ *                address bit both before and after the gates of s (stored at
+ *                slice 3t+2, unstored at T-3t-2) suffers a fault with
+ *                probability eps: X, Z or ZX (= iY) with equal probability
+ *                on a qubit site (and the qutrit data slot), one of the eight
+ *                nontrivial Weyl operators on a qutrit router.  Faults act
+ *                after the slice's gates and before its damping layer, are
+ *                drawn in advance (Philox counters (block, draw, trajectory,
+ *                4), a geometric walk over the active positions, the type
+ *                from the draw's third word) and mark their bad range by the
+ *                encoding's rule, whatever their type (Alg. 1).
+ *   input_amp    [2 * 2^n] amplitude (re, im) of each address, normalised by
+ *                the library; NULL = uniform.  Addresses with amplitude 0 are
+ *                absent (no branch).
+ *   input_bus    [2^n] bus word of each address (one column per address);
+ *                NULL = 0.  The ideal output is sum_i c_i |i>|j_i xor d_i>.
+ * The qubit encoding accepts k_data up to 8 here (n + k <= 16).  Contexts
+ * with eps > 0, a general input, or qubit k > 6 run every mode on the plain
+ * engine: QRAM_MODE_FULL as QRAM_MODE_PLAIN, QRAM_MODE_PRUNED as Alg. 1 on
+ * explicit site lists (bad branches plus the reference explicit, the good
+ * branches carried by the reference's weights and final state).
+ */
+typedef struct {
+  int n_addr, k_data;
+  qram_encoding enc;
+  double gamma;
+  double eps;
+  const uint32_t *memory_bits;  /* host, 2^n words; copied */
+  const double *input_amp;      /* host, 2 * 2^n doubles, or NULL; copied */
+  const uint32_t *input_bus;    /* host, 2^n words, or NULL; copied */
+} qram_params;
+
+qram_status qram_create_ex(const qram_params *params, qram_ctx **out);
 
 /* Release a context and all device memory it owns.  NULL is allowed. */
 void qram_destroy(qram_ctx *ctx);
@@ -126,6 +165,17 @@ qram_status qram_sample_faults(qram_ctx *ctx, uint64_t seed, uint64_t traj0,
                                uint64_t *cand_digest, uint32_t *n_bad,
                                uint64_t *bad_bits, uint32_t *cand_L,
                                uint64_t cand_cap);
+
+/*
+ * Depolarizing faults of trajectories traj0 .. traj0+ntraj-1 (contexts with
+ * eps > 0; otherwise every count is 0): n_dep [ntraj] counts; dep (optional)
+ * all lists concatenated in trajectory order, each entry site | slice << 16
+ * | type << 24 with type a | b << 2 for the operator Z^b X^a, ascending
+ * (slice, site); cap entries available, else the dump is skipped and
+ * QRAM_E_CAPACITY returned after the counts are written.
+ */
+qram_status qram_sample_depol(qram_ctx *ctx, uint64_t seed, uint64_t traj0, uint32_t ntraj,
+                              uint32_t *n_dep, uint32_t *dep, uint64_t cap);
 
 /*
  * Full evolution of every branch (the comparator mode), synchronously.
@@ -271,7 +321,9 @@ qram_status qram_stage_buckets(qram_ctx *ctx, double *ms, uint32_t *launches, ui
  * Test entry: one trajectory under a forced history instead of the random
  * draws.  cand_L [ncand] ascending linear indices; u_aux [T] auxiliary
  * uniforms indexed by slice (entry 0 unused); u_fin the final uniform.
- * Runs the given mode; returns the fidelity and statistics.
+ * Runs the given mode; returns the fidelity and statistics.  In a context
+ * with eps > 0 the depolarizing faults are still drawn, for seed 0 and
+ * trajectory 0.
  */
 qram_status qram_run_forced(qram_ctx *ctx, qram_mode mode,
                             const uint32_t *cand_L, uint32_t ncand,
@@ -286,7 +338,8 @@ qram_status qram_run_forced(qram_ctx *ctx, qram_mode mode,
  * pruned and full runs driven from the same history (Sec. VI A, App. D).
  *   history   sampled from (seed, traj) when u_aux is NULL; otherwise forced
  *             as in qram_run_forced (cand_L [ncand] ascending, u_aux [T],
- *             u_fin), and seed/traj are ignored.
+ *             u_fin), and seed/traj only draw the depolarizing faults of a
+ *             context with eps > 0.
  *   comp      [comp_cap * (3 + lmax)] uint32 words, lmax = 2n + k (qubit) or
  *             4n + k (qutrit); comp_cap >= 2^n * 2^k (qubit) or 2^n
  *             (qutrit), else QRAM_E_CAPACITY.  Record x = address * 2^k + bus
@@ -304,11 +357,15 @@ qram_status qram_run_forced(qram_ctx *ctx, qram_mode mode,
  *             total number of jump-log entries.  Pruned runs export the
  *             explicit components and the predicted good branches (Theorem 3,
  *             Proposition 1); a predicted branch is present only while the
- *             reference survives.  QRAM_MODE_PLAIN carries amplitudes as
- *             numbers: its records hold sign 0 and exposure 0, and
- *   amp       [comp_cap * 2] (plain mode, required there; else may be NULL
- *             and is not written) receives each record's complex amplitude
- *             (real, imaginary), the factor gamma^(J/2) included.
+ *             reference survives.  The plain engine (QRAM_MODE_PLAIN, and
+ *             every mode of a context made by qram_create_ex with eps > 0,
+ *             a general input or qubit k > 6) carries amplitudes as
+ *             numbers: its records hold sign 0 and exposure 0; its pruned
+ *             mode exports the explicit components only, and
+ *   amp       [comp_cap * 2] (plain engine, required there; else may be
+ *             NULL and is not written) receives each record's complex
+ *             amplitude (real, imaginary), the factor gamma^(J/2) and the
+ *             input amplitude c_i included.
  *   jlog      [jcap] jump-log entries in order of slice: site | level << 16 |
  *             slice << 24 (levels as above); *njl receives the number of
  *             entries, which may exceed jcap (the rest are not written).

@@ -324,7 +324,7 @@ static uint32_t in_bus(const orc_cfg *c, uint32_t i) {
 /* Export the event list of slice s (for schedule tests). */
 int orc_schedule(int n, int k, int s, int *types, int *args) {
   static const uint32_t zero_mem[1] = {0};
-  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  orc_cfg *c = (orc_cfg *)calloc(1, sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, ORC_QUBIT, 0.0, zero_mem);
   if (rc) {
     free(c);
@@ -372,7 +372,7 @@ static int sample_candidates(const orc_cfg *c, uint64_t seed, uint32_t traj,
 int orc_sample(int n, int k, double gamma, uint64_t seed, uint32_t traj,
                uint32_t *L, int cap) {
   static const uint32_t zero_mem[1] = {0};
-  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  orc_cfg *c = (orc_cfg *)calloc(1, sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, ORC_QUBIT, gamma, zero_mem);
   if (rc) {
     free(c);
@@ -438,7 +438,7 @@ static void depol_site(const orc_cfg *c, uint32_t Lx, int *s, int *q) {
 int orc_sample_depol(int n, int k, int enc, double eps, uint64_t seed,
                      uint32_t traj, uint32_t *L, uint8_t *type, int cap) {
   static const uint32_t zero_mem[1] = {0};
-  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  orc_cfg *c = (orc_cfg *)calloc(1, sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, enc, 0.0, zero_mem);
   if (!rc)
     rc = cfg_extras(c, eps, NULL, NULL);
@@ -454,7 +454,7 @@ int orc_sample_depol(int n, int k, int enc, double eps, uint64_t seed,
 /* Active positions per slice (for the tests): nact[s] for s = 0..T-1. */
 int orc_depol_active(int n, int k, int *nact) {
   static const uint32_t zero_mem[1] = {0};
-  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  orc_cfg *c = (orc_cfg *)calloc(1, sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, ORC_QUBIT, 0.0, zero_mem);
   if (!rc)
     rc = cfg_extras(c, 0.0, NULL, NULL);
@@ -527,7 +527,7 @@ static int classify(const orc_cfg *c, const uint32_t *L, int ncand,
 int orc_classify(int n, int k, int enc, const uint32_t *L, int ncand,
                  uint8_t *bad) {
   static const uint32_t zero_mem[1] = {0};
-  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  orc_cfg *c = (orc_cfg *)calloc(1, sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, enc, 0.0, zero_mem);
   if (rc) {
     free(c);
@@ -1132,7 +1132,7 @@ int orc_run_traj_ex(int n, int k, int enc, double gamma, double eps,
                     int jcap, int *njl, uint32_t *exp_addr, uint32_t *exp_bus,
                     double *exp_amp, uint8_t *exp_tree, uint32_t *exp_label,
                     int exp_cap) {
-  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  orc_cfg *c = (orc_cfg *)calloc(1, sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, enc, gamma, mem);
   if (!rc)
     rc = cfg_extras(c, eps, cin, jin);
@@ -1208,7 +1208,7 @@ int orc_layer_masks(int n, int k, int enc, double gamma, const uint32_t *mem,
                     const uint32_t *forced_L, int forced_ncand,
                     const double *forced_uaux, int s, const int *cand, int nc,
                     uint8_t *masks, double *weights, int cap, double *w_empty) {
-  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  orc_cfg *c = (orc_cfg *)calloc(1, sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, enc, gamma, mem);
   if (rc) {
     free(c);
@@ -1320,7 +1320,7 @@ static int run_many(int n, int k, int enc, double gamma, double eps,
                     uint64_t seed, uint32_t traj0, const uint32_t *idx,
                     int ntraj, int nthreads, double *fid, double *fid_pre,
                     int *ri) {
-  orc_cfg *c = (orc_cfg *)malloc(sizeof(orc_cfg));
+  orc_cfg *c = (orc_cfg *)calloc(1, sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, enc, gamma, mem);
   if (!rc)
     rc = cfg_extras(c, eps, cin, jin);

@@ -47,6 +47,12 @@ struct Plan {
 struct qram_ctx {
   int n = 0, k = 0, enc = 0;
   double gamma = 0.0;
+  double eps = 0.0;       // depolarizing strength
+  bool general = false;   // depolarizing noise or a general input: the plain engine runs every mode
+  double *dcin = nullptr;  // general input amplitudes (device)
+  uint32_t *djin = nullptr;
+  uint32_t *dep = nullptr, *ndep = nullptr;  // depolarizing faults of a batch
+  uint32_t dep_cap = 0;
   int T = 0, M = 0, D = 0, K2 = 1, Emax = 0, lmax = 0, emax = 0, rec = 0;
   int device = 0, num_cu = 0;
   size_t lds_max = 0;
@@ -227,16 +233,37 @@ bool build_tables(qram_ctx *c, std::string &why) {
   t.sg = std::sqrt(c->gamma);
   t.emax = c->emax;
   t.rec = c->rec;
-  // geometric-walk thresholds: G[o] = floor(2^64 (1 - (1-gamma)^(o+1)))
-  {
-    const double q = 1.0 - c->gamma;
+  // geometric-walk thresholds: G[o] = floor(2^64 (1 - (1-p)^(o+1))), for
+  // the damping candidates (p = gamma) and the depolarizing faults (p = eps)
+  auto thresholds = [](double p, uint64_t *G) {
+    const double q = 1.0 - p;
     double qp = 1.0;
     for (int o = 0; o < 64; ++o) {
       qp = qp * q;
       const double x = std::ldexp(1.0 - qp, 64);
-      t.G[o] = x >= 18446744073709551616.0 ? UINT64_MAX : (uint64_t)x;
+      G[o] = x >= 18446744073709551616.0 ? UINT64_MAX : (uint64_t)x;
     }
+  };
+  thresholds(c->gamma, t.G);
+  thresholds(c->eps, t.Gp);
+  // depolarizing placement (App. C): in slice s every site of the layers
+  // above the leaf layer whose router holds its address bit both before and
+  // after the gates of s (stored at 3t+2, unstored at T-3t-2)
+  t.depol = c->eps > 0.0 ? 1 : 0;
+  {
+    uint32_t off = 0;
+    for (int sl = 0; sl <= MAXT; ++sl) t.dep_off[sl] = 0;
+    for (int sl = 1; sl < T; ++sl) {
+      int l = 0;
+      for (int tt = 0; tt + 1 < c->n; ++tt)
+        if (3 * tt + 2 < sl && sl < T - 3 * tt - 2) ++l;
+      t.dep_off[sl] = off;
+      off += 2u * ((1u << l) - 1u);
+    }
+    t.dep_off[T] = off;
   }
+  t.cin = nullptr;
+  t.jin = nullptr;
   for (int s = 0; s < MAXT; ++s) {
     t.copy_t[s] = t.store_l[s] = t.bus_b[s] = t.fetch_b[s] = -1;
     t.cswap[s] = 0;
@@ -369,6 +396,15 @@ uint32_t cand_capacity(const qram_ctx *c) {
   return std::max<uint32_t>(r, 32u);
 }
 
+// Depolarizing faults per trajectory: mean + 10 sd over the active positions.
+uint32_t dep_capacity(const qram_ctx *c) {
+  if (c->eps <= 0.0) return 0;
+  const double S = (double)c->htab.dep_off[c->T];
+  double cap = S * c->eps + 10.0 * std::sqrt(S * c->eps * (1.0 - c->eps)) + 32.0;
+  if (cap > S) cap = S;
+  return std::max<uint32_t>((uint32_t)std::ceil(cap), 32u);
+}
+
 uint32_t pow2ceil(uint32_t x) {
   uint32_t p = 1;
   while (p < x) p <<= 1;
@@ -380,7 +416,7 @@ uint32_t pow2ceil(uint32_t x) {
 // addresses plus the reference), so trajectories are grouped by it, each
 // group with a workgroup size and LDS footprint sized for its largest member.
 qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
-  if (mode == QRAM_MODE_PLAIN) {
+  if (mode == QRAM_MODE_PLAIN || c->general) {
     pl = Plan{};
     pl.plain = true;
     pl.nb = 1;
@@ -458,6 +494,11 @@ qram_status ensure_buffers(qram_ctx *c, uint32_t nb, const Plan *pl) {
     if ((st = dev_alloc(c, &c->digest, nb))) return st;
     if ((st = dev_alloc(c, &c->badbits, (size_t)nb * ((c->D + 63) / 64)))) return st;
     if ((st = dev_alloc(c, &c->xlist, (size_t)nb * c->D))) return st;
+    if (c->eps > 0.0) {
+      c->dep_cap = dep_capacity(c);
+      if ((st = dev_alloc(c, &c->dep, (size_t)nb * c->dep_cap))) return st;
+      if ((st = dev_alloc(c, &c->ndep, nb))) return st;
+    }
     c->batch_cap = nb;
   }
   if (!c->counter) {
@@ -505,6 +546,7 @@ qram_status ensure_buffers(qram_ctx *c, uint32_t nb, const Plan *pl) {
 size_t buffers_bytes(const qram_ctx *c, uint32_t nb, const Plan &pl) {
   const size_t n = nb;
   size_t b = n * cand_capacity(c) * 4 + n * 5 * 4 + n * 8 + n * ((c->D + 63) / 64) * 8 + n * c->D * 2;
+  b += n * ((size_t)dep_capacity(c) + 1) * 4;
   b += (2 * MAXB + 1 + 4) * 4;
   if (pl.plain) {
     const size_t g = pl.grid_max, E = (size_t)c->Emax;
@@ -565,6 +607,11 @@ Run base_run(qram_ctx *c, int mode, uint64_t seed, const Plan *pl) {
   r.pool = c->pool;
   r.devl = c->devl;
   r.err = c->errw;
+  if (c->eps > 0.0) {
+    r.dep = c->dep;
+    r.ndep = c->ndep;
+    r.dep_cap = c->dep_cap;
+  }
   r.prec = (uint32_t)c->prec;
   r.pamp = c->pamp;
   r.phit = c->phit;
@@ -617,6 +664,7 @@ qram_status enqueue_batch(qram_ctx *c, const Plan &pl, Run r, hipStream_t s,
   }
   if (timed) HIPCHK(c, hipEventRecord(e[0], s));
   if (!skip_sample) HIPCHK(c, launch_sample(c->dtab, r, nt, sample_grid(c, nt), s));
+  if (r.dep) HIPCHK(c, launch_sample_depol(c->dtab, r, sample_grid(c, nt), s));
   if (timed) HIPCHK(c, hipEventRecord(e[1], s));
   HIPCHK(c, launch_classify(c->dtab, r, nt, sample_grid(c, nt), c->D, c->mark_subtree, s));
   if (!pl.plain) HIPCHK(c, launch_order(c->dtab, r, s));
@@ -709,6 +757,7 @@ qram_status check_err(qram_ctx *c) {
     HIPCHK(c, hipMemset(c->errw, 0, 4));
     if (e & ERR_CAND) return fail(c, QRAM_E_CAPACITY, "candidate buffer overflow");
     if (e & ERR_LIST) return fail(c, QRAM_E_CAPACITY, "explicit site list overflow");
+    if (e & ERR_DEP) return fail(c, QRAM_E_CAPACITY, "depolarizing fault buffer overflow");
   }
   return QRAM_OK;
 }
@@ -812,21 +861,50 @@ extern "C" {
 
 qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
                         const uint32_t *memory_bits, qram_ctx **out) {
-  if (!out || !memory_bits) return fail(nullptr, QRAM_E_INVAL, "null argument");
+  qram_params p{};
+  p.n_addr = n_addr;
+  p.k_data = k_data;
+  p.enc = enc;
+  p.gamma = gamma;
+  p.eps = 0.0;
+  p.memory_bits = memory_bits;
+  return qram_create_ex(&p, out);
+}
+
+qram_status qram_create_ex(const qram_params *p, qram_ctx **out) {
+  if (!out || !p || !p->memory_bits) return fail(nullptr, QRAM_E_INVAL, "null argument");
   *out = nullptr;
+  const int n_addr = p->n_addr, k_data = p->k_data;
+  const qram_encoding enc = p->enc;
+  const double gamma = p->gamma, eps = p->eps;
+  const uint32_t *memory_bits = p->memory_bits;
   if (enc != QRAM_QUBIT && enc != QRAM_QUTRIT) return fail(nullptr, QRAM_E_INVAL, "unknown encoding");
   if (!(gamma >= 0.0 && gamma < 1.0)) return fail(nullptr, QRAM_E_INVAL, "gamma must lie in [0, 1)");
+  if (!(eps >= 0.0 && eps < 1.0)) return fail(nullptr, QRAM_E_INVAL, "eps must lie in [0, 1)");
   const int nmax = enc == QRAM_QUTRIT ? 14 : 15;
   if (n_addr < 1 || n_addr > nmax) return fail(nullptr, QRAM_E_RANGE, "n_addr out of range");
   if (k_data < 1 || k_data > 8 || k_data > n_addr) return fail(nullptr, QRAM_E_RANGE, "k_data out of range (1..8, k <= n)");
-  if (enc == QRAM_QUBIT && (k_data > 6 || n_addr + k_data > 16))
-    return fail(nullptr, QRAM_E_RANGE, "qubit encoding needs k <= 6 and n + k <= 16");
+  if (enc == QRAM_QUBIT && n_addr + k_data > 16)
+    return fail(nullptr, QRAM_E_RANGE, "qubit encoding needs n + k <= 16 (at most 65536 components)");
+  std::vector<double> cin;
+  if (p->input_amp) {  // normalised general input
+    double norm = 0.0;
+    cin.assign(p->input_amp, p->input_amp + 2 * ((size_t)1 << n_addr));
+    for (double v : cin) norm += v * v;
+    if (!(norm > 0.0) || !std::isfinite(norm)) return fail(nullptr, QRAM_E_INVAL, "input amplitudes must be finite and not all zero");
+    const double f = 1.0 / std::sqrt(norm);
+    for (double &v : cin) v *= f;
+  }
   qram_ctx *c = new (std::nothrow) qram_ctx();
   if (!c) return fail(nullptr, QRAM_E_NOMEM, "host allocation failed");
   c->n = n_addr;
   c->k = k_data;
   c->enc = enc == QRAM_QUBIT ? QUBIT : QUTRIT;
   c->gamma = gamma;
+  c->eps = eps;
+  // the trajectory kernel covers damping on the data-loading input with up
+  // to six qubit data bits; everything else runs on the plain engine
+  c->general = eps > 0.0 || p->input_amp || p->input_bus || (c->enc == QUBIT && k_data > 6);
   c->T = 6 * n_addr + 2 * k_data;
   c->M = 2 * ((1 << n_addr) - 1);
   c->D = 1 << n_addr;
@@ -934,6 +1012,20 @@ qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
   c->htab.ov_nojump = nojump_sum(1, c->T - 1);
   if ((st = dev_alloc(c, &c->dctot, ctot.size()))) return bail(st);
   if ((st = dev_alloc(c, &c->dftab, ft.size()))) return bail(st);
+  if (!cin.empty()) {
+    if ((st = dev_alloc(c, &c->dcin, cin.size()))) return bail(st);
+    if (hipMemcpy(c->dcin, cin.data(), cin.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(c, QRAM_E_DEVICE, "input upload failed"));
+    c->htab.cin = c->dcin;
+  }
+  if (p->input_bus) {
+    std::vector<uint32_t> jin(p->input_bus, p->input_bus + c->D);
+    for (auto &j : jin) j &= (1u << k_data) - 1u;
+    if ((st = dev_alloc(c, &c->djin, jin.size()))) return bail(st);
+    if (hipMemcpy(c->djin, jin.data(), jin.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(c, QRAM_E_DEVICE, "input upload failed"));
+    c->htab.jin = c->djin;
+  }
   c->htab.mem = c->dmem;
   c->htab.wpow = c->dwpow;
   c->htab.apow = c->dapow;
@@ -980,6 +1072,10 @@ void qram_destroy(qram_ctx *c) {
   dev_free(&c->fid_tmp);
   dev_free(&c->st_tmp);
   dev_free(&c->uaux);
+  dev_free(&c->dcin);
+  dev_free(&c->djin);
+  dev_free(&c->dep);
+  dev_free(&c->ndep);
   dev_free(&c->dexp);
   dev_free(&c->dexpamp);
   dev_free(&c->pamp);
@@ -1020,6 +1116,7 @@ qram_status qram_sample_faults(qram_ctx *c, uint64_t seed, uint64_t traj0,
     r.traj0 = (uint32_t)(traj0 + b0);
     r.ntraj = cnt;
     HIPCHK(c, launch_sample(c->dtab, r, cnt, sample_grid(c, cnt), c->stream));
+    if (r.dep) HIPCHK(c, launch_sample_depol(c->dtab, r, sample_grid(c, cnt), c->stream));
     HIPCHK(c, launch_classify(c->dtab, r, cnt, sample_grid(c, cnt), c->D, c->mark_subtree, c->stream));
     HIPCHK(c, launch_digest(r, cnt, c->stream));
     HIPCHK(c, hipMemcpyAsync(n_cand + b0, c->ncand, cnt * 4, hipMemcpyDeviceToHost, c->stream));
@@ -1046,6 +1143,50 @@ qram_status qram_sample_faults(qram_ctx *c, uint64_t seed, uint64_t traj0,
   }
   if ((st = check_err(c))) return st;
   if (overflow) return fail(c, QRAM_E_CAPACITY, "cand_L too small for the candidate dump");
+  return QRAM_OK;
+}
+
+qram_status qram_sample_depol(qram_ctx *c, uint64_t seed, uint64_t traj0, uint32_t ntraj,
+                              uint32_t *n_dep, uint32_t *dep, uint64_t cap) {
+  qram_status st = check_args(c, traj0, ntraj);
+  if (st) return st;
+  if (!n_dep) return fail(c, QRAM_E_INVAL, "n_dep is required");
+  if (c->eps <= 0.0) {
+    std::memset(n_dep, 0, (size_t)ntraj * 4);
+    return QRAM_OK;
+  }
+  if (ntraj == 0) return QRAM_OK;
+  const uint32_t nb = batch_size(c, ntraj);
+  if ((st = ensure_buffers(c, nb, nullptr))) return st;
+  uint64_t written = 0;
+  bool overflow = false;
+  std::vector<uint32_t> hd;
+  for (uint32_t b0 = 0; b0 < ntraj; b0 += nb) {
+    const uint32_t cnt = std::min(nb, ntraj - b0);
+    Run r = base_run(c, 0, seed, nullptr);
+    r.traj0 = (uint32_t)(traj0 + b0);
+    r.ntraj = cnt;
+    HIPCHK(c, launch_sample_depol(c->dtab, r, sample_grid(c, cnt), c->stream));
+    HIPCHK(c, hipMemcpyAsync(n_dep + b0, c->ndep, cnt * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (dep && !overflow) {
+      uint64_t need = written;
+      for (uint32_t t = 0; t < cnt; ++t) need += std::min(n_dep[b0 + t], c->dep_cap);
+      if (need > cap) {
+        overflow = true;
+      } else {
+        hd.resize((size_t)cnt * c->dep_cap);
+        HIPCHK(c, hipMemcpy(hd.data(), c->dep, hd.size() * 4, hipMemcpyDeviceToHost));
+        for (uint32_t t = 0; t < cnt; ++t) {
+          const uint32_t m = std::min(n_dep[b0 + t], c->dep_cap);
+          std::memcpy(dep + written, hd.data() + (size_t)t * c->dep_cap, m * 4);
+          written += m;
+        }
+      }
+    }
+  }
+  if ((st = check_err(c))) return st;
+  if (overflow) return fail(c, QRAM_E_CAPACITY, "dep buffer too small for the dump");
   return QRAM_OK;
 }
 
@@ -1487,8 +1628,7 @@ static qram_status run_single(qram_ctx *c, int mode, uint64_t seed, uint32_t tra
     HIPCHK(c, hipMemcpy(c->uaux, ua.data(), MAXT * 8, hipMemcpyHostToDevice));
     if (ncand) HIPCHK(c, hipMemcpy(c->cand, cand_L, ncand * 4, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->ncand, &ncand, 4, hipMemcpyHostToDevice));
-    r.traj0 = 0;
-    r.forced = 1;
+    r.forced = 1;  // (depolarizing faults are still drawn for (seed, traj))
     r.uaux = c->uaux;
     r.ufin = u_fin;
   }
@@ -1496,7 +1636,7 @@ static qram_status run_single(qram_ctx *c, int mode, uint64_t seed, uint32_t tra
     if ((st = grow(c, &c->dexp, &c->dexp_cap, ncomp * rec_words))) return st;
     HIPCHK(c, hipMemsetAsync(c->dexp, 0, ncomp * rec_words * 4, c->stream));
     r.exp = c->dexp;
-    if (mode == QRAM_MODE_PLAIN) {
+    if (pl.plain) {
       if ((st = grow(c, &c->dexpamp, &c->dexpamp_cap, ncomp * 2))) return st;
       HIPCHK(c, hipMemsetAsync(c->dexpamp, 0, ncomp * 16, c->stream));
       r.expamp = c->dexpamp;
@@ -1516,7 +1656,7 @@ static qram_status run_single(qram_ctx *c, int mode, uint64_t seed, uint32_t tra
   if (stt) HIPCHK(c, hipMemcpyAsync(stt, c->st_tmp, sizeof(qram_traj_stats), hipMemcpyDeviceToHost, c->stream));
   if (h_exp)
     HIPCHK(c, hipMemcpyAsync(h_exp, c->dexp, ncomp * rec_words * 4, hipMemcpyDeviceToHost, c->stream));
-  if (h_exp && h_amp && mode == QRAM_MODE_PLAIN)
+  if (h_exp && h_amp && pl.plain)
     HIPCHK(c, hipMemcpyAsync(h_amp, c->dexpamp, ncomp * 16, hipMemcpyDeviceToHost, c->stream));
   if (h_njl) {
     HIPCHK(c, hipMemcpyAsync(h_njl, c->djn, 4, hipMemcpyDeviceToHost, c->stream));
@@ -1539,7 +1679,8 @@ qram_status qram_export_state(qram_ctx *c, qram_mode mode, uint64_t seed, uint32
                               uint32_t *jlog, uint32_t jcap, uint32_t *njl, double *fid,
                               qram_traj_stats *stt) {
   if (!comp || !njl) return fail(c, QRAM_E_INVAL, "comp and njl are required");
-  if (mode == QRAM_MODE_PLAIN && !amp) return fail(c, QRAM_E_INVAL, "the plain mode exports amplitudes: amp is required");
+  if (c && (mode == QRAM_MODE_PLAIN || c->general) && !amp)
+    return fail(c, QRAM_E_INVAL, "the plain engine exports amplitudes: amp is required");
   return run_single(c, mode, seed, traj, u_aux != nullptr, cand_L, ncand, u_aux, u_fin, comp, comp_cap, amp, jlog,
                     jcap, njl, fid, stt);
 }

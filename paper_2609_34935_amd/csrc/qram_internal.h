@@ -76,6 +76,14 @@ struct Tables {
   uint16_t cntD[MAXT][MAXK];       // exposure of data token b through s
   uint16_t cntR[MAXT];             // qutrit: router exposure through s
   double sg;                       // sqrt(gamma), the amplitude of a jump
+  // depolarizing faults (eps > 0): active positions of slice s are the sites
+  // 0 .. dep_off[s+1]-dep_off[s]-1; geometric-walk thresholds for eps
+  int depol;                       // 1 if eps > 0
+  uint64_t Gp[64];
+  uint32_t dep_off[MAXT + 1];      // linear index of slice s's first active position
+  // general input (null: uniform amplitudes, bus word 0)
+  const double *cin;               // [2 D] normalised amplitude (re, im) of each address
+  const uint32_t *jin;             // [D] bus word of each address
 };
 
 struct Run {
@@ -119,6 +127,11 @@ struct Run {
   uint32_t *jn;          // [ntraj] jump-log entries of each trajectory (may exceed jcap)
   uint32_t jcap;         // jump-log entries kept per trajectory
   double *expamp;        // [D * K2 * 2] plain mode: amplitude of each exported record
+  // depolarizing faults of each trajectory: site | slice << 16 | type << 24
+  // (type a | b << 2, the operator Z^b X^a), ascending slice and site
+  uint32_t *dep;         // [ntraj * dep_cap]
+  uint32_t *ndep;        // [ntraj]
+  uint32_t dep_cap;
   // plain full evolution: per-workgroup component lists (pool, prec uint16
   // words each), amplitudes, hit flags and finalize scratch
   uint32_t prec;
@@ -149,6 +162,8 @@ hipError_t launch_evolve(const Tables *tb, const Run &rp, int enc,
                          bool state_lds, hipStream_t s);
 hipError_t launch_digest(const Run &rp, uint32_t ntraj, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint32_t n, hipStream_t s);
+hipError_t launch_sample_depol(const Tables *tb, const Run &rp, uint32_t grid, hipStream_t s);
+constexpr uint32_t ERR_DEP = 4u;  // depolarizing fault buffer overflow
 
 uint32_t evolve_lds_bytes(int M, int D, int threads, uint32_t cdec_cap,
                           uint32_t e_cap, bool state_lds, uint32_t walk_bytes);

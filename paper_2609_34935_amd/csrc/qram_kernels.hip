@@ -12,6 +12,10 @@
 //               1-2).
 //   k_order     groups trajectories into buckets of explicit work, longest
 //               first inside each bucket, and resets the queue heads.
+//   k_sample_depol  depolarizing faults (Sec. II B, placement of App. C):
+//               Bernoulli(eps) on the active positions of each slice, the
+//               same geometric walk with its own counters (tag 4), the type
+//               from the third word of the same Philox draw.
 #include "qram_device.h"
 
 namespace qr {
@@ -108,6 +112,90 @@ __global__ void __launch_bounds__(256) k_sample(const Tables *__restrict__ tb,
 }
 
 // ---------------------------------------------------------------------------
+// k_sample_depol
+// ---------------------------------------------------------------------------
+// Fault types: qubits and the qutrit data slot take X, Z or ZX (index
+// (w2 * 3) >> 32), a qutrit router one of the eight nontrivial Weyl
+// operators Z^b X^a (index (w2 * 8) >> 32); stored as a | b << 2.
+__device__ __forceinline__ uint32_t depol_type(bool router3, uint32_t w2) {
+  if (!router3) {
+    const uint32_t i = (uint32_t)(((uint64_t)w2 * 3u) >> 32);
+    return i == 0 ? 1u : (i == 1 ? 4u : 5u);  // X, Z, ZX
+  }
+  const uint32_t i = (uint32_t)(((uint64_t)w2 * 8u) >> 32);
+  const uint32_t a = (i + 1) / 3, b = (i + 1) % 3;  // (0,1) (0,2) (1,0) ... (2,2)
+  return a | (b << 2);
+}
+
+// Walk block b of the depolarizing index space; MODE 0 counts, 1 writes.
+template <int MODE>
+__device__ __forceinline__ uint32_t walk_block_dep(const Tables *__restrict__ tb, uint32_t b, uint32_t len,
+                                                   uint32_t traj, uint32_t k0, uint32_t k1, const uint64_t *G,
+                                                   uint32_t *out, uint32_t base, uint32_t cap) {
+  uint32_t pos = 0, cnt = 0;
+  int s = 1;
+  for (uint32_t j = 0;; ++j) {
+    const uint4 w = philox10(make_uint4(b, j, traj, 4u), k0, k1);
+    const uint64_t u = (uint64_t)w.x | ((uint64_t)w.y << 32);
+    const uint32_t rem = len - pos;
+    if (!(u < G[rem - 1])) break;
+    uint32_t lo = 0, hi = rem - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (u < G[mid])
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    const uint32_t L = 64u * b + pos + lo;
+    if (MODE == 1 && base + cnt < cap) {
+      while (tb->dep_off[s + 1] <= L) ++s;
+      const uint32_t q = L - tb->dep_off[s];
+      const bool router3 = tb->enc == QUTRIT && (q & 1u) == 0;
+      out[base + cnt] = q | ((uint32_t)s << 16) | (depol_type(router3, w.z) << 24);
+    }
+    ++cnt;
+    pos += lo + 1;
+    if (pos >= len) break;
+  }
+  return cnt;
+}
+
+__global__ void __launch_bounds__(256) k_sample_depol(const Tables *__restrict__ tb, const Run R_) {
+  const Run *rp = &R_;
+  __shared__ uint64_t G[64];
+  __shared__ uint32_t sbuf[16];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  if (tid < 64) G[tid] = tb->Gp[tid];
+  __syncthreads();
+  const uint32_t S = tb->dep_off[tb->T];
+  const uint32_t nb = (S + 63) / 64;
+  const uint32_t per = (nb + nthr - 1) / nthr;
+  const uint32_t b0 = min(nb, tid * per), b1 = min(nb, b0 + per);
+  const uint32_t k0 = (uint32_t)rp->seed, k1 = (uint32_t)(rp->seed >> 32);
+  const uint32_t cap = rp->dep_cap;
+  for (uint32_t tj = blockIdx.x; tj < rp->ntraj; tj += gridDim.x) {
+    const uint32_t traj = rp->traj0 + tj;
+    uint32_t cnt = 0;
+    for (uint32_t b = b0; b < b1; ++b)
+      cnt += walk_block_dep<0>(tb, b, min(64u, S - 64u * b), traj, k0, k1, G, nullptr, 0, 0);
+    uint32_t total;
+    const uint32_t off = block_excl_scan_u32(cnt, sbuf, &total);
+    uint32_t *out = rp->dep + (size_t)tj * cap;
+    if (cnt) {
+      uint32_t o = off;
+      for (uint32_t b = b0; b < b1; ++b)
+        o += walk_block_dep<1>(tb, b, min(64u, S - 64u * b), traj, k0, k1, G, out, o, cap);
+    }
+    if (tid == 0) {
+      rp->ndep[tj] = total;
+      if (total > cap) atomicOr(rp->err, ERR_DEP);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // k_classify: marks the range node of every candidate, propagates marks down
 // the tree, and derives the bad bitmap, the reference and the explicit list.
 // ---------------------------------------------------------------------------
@@ -145,6 +233,11 @@ __global__ void __launch_bounds__(256) k_classify(const Tables *__restrict__ tb,
       const uint32_t q = cand[j] % (uint32_t)M;
       mark[range_node(enc, subtree != 0, q >> 1)] = 1;
     }
+    if (rp->dep) {  // depolarizing faults: the encoding's rule whatever their type
+      const uint32_t nd = min(rp->ndep[tj], rp->dep_cap);
+      const uint32_t *dp = rp->dep + (size_t)tj * rp->dep_cap;
+      for (uint32_t j = tid; j < nd; j += nthr) mark[range_node(enc, false, (dp[j] & 0xFFFFu) >> 1)] = 1;
+    }
     __syncthreads();
     // address i is bad when a node on its path, root to its leaf node, is
     // marked; one ballot per wave gives 64 addresses of the bad bitmap
@@ -154,15 +247,17 @@ __global__ void __launch_bounds__(256) k_classify(const Tables *__restrict__ tb,
     uint32_t nbad_local = 0, first_good = 0xFFFFFFFFu;
     for (int base = 0; base < D; base += nthr) {
       const int i = base + tid;
-      bool bad = false;
+      bool bad = false, present = i < D;
       if (i < D) {
         uint32_t v = (uint32_t)(leaf0 + (i >> 1));
         for (int l = 0; l < n; ++l) {  // n nodes: the leaf node up to the root
           bad |= mark[v] != 0;
           v = (v - 1) >> 1;
         }
+        if (tb->cin) present = tb->cin[2 * i] != 0.0 || tb->cin[2 * i + 1] != 0.0;
       }
       const uint64_t m = __ballot(bad);
+      const uint64_t pm = __ballot(present);  // the reference must be in the input
       const int word = (base >> 6) + (tid >> 6);
       if ((tid & 63) == 0 && word < nw64) {
         const int nv = min(64, D - 64 * word);
@@ -171,7 +266,7 @@ __global__ void __launch_bounds__(256) k_classify(const Tables *__restrict__ tb,
         badw[2 * word] = (uint32_t)(m & valid);
         if (2 * word + 1 < nw32) badw[2 * word + 1] = (uint32_t)((m & valid) >> 32);
         nbad_local += (uint32_t)__popcll(m & valid);
-        const uint64_t good = ~m & valid;
+        const uint64_t good = ~m & valid & pm;
         if (good) first_good = min(first_good, (uint32_t)(64 * word + __ffsll((unsigned long long)good) - 1));
       }
     }
@@ -302,6 +397,11 @@ hipError_t launch_classify(const Tables *tb, const Run &rp, uint32_t ntraj,
   (void)ntraj;
   const size_t lds = (size_t)((D + 31) / 32) * 8 + 16 * 4 + (size_t)D;
   hipLaunchKernelGGL(k_classify, dim3(grid), dim3(256), lds, s, tb, rp, subtree ? 1u : 0u);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_depol(const Tables *tb, const Run &rp, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample_depol, dim3(grid), dim3(256), 0, s, tb, rp);
   return hipGetLastError();
 }
 

@@ -188,23 +188,57 @@ __device__ bool plain_gates(const Tables *__restrict__ tb, int s, PList<ENC> L, 
   return flip;
 }
 
+// A depolarizing fault Z^b X^a on site q of one component (Sec. II B): the
+// site's level x becomes x + a (mod d), then the amplitude takes
+// w_d^(b (x + a)), w_2 = -1, w_3 = exp(2 pi i / 3).  A qutrit router has
+// three levels (W absent from the list, L, R with the level bit); every
+// other site two.
+template <int ENC>
+__device__ void plain_fault(PList<ENC> L, double2 &amp, uint32_t q, uint32_t a, uint32_t b, uint32_t *err) {
+  const bool tri = ENC == QUTRIT && (q & 1u) == 0;
+  const int j = L.find(q);
+  uint32_t x;
+  if (!tri) {
+    x = (j >= 0 ? 1u : 0u) ^ (a & 1u);
+    if (a & 1u) {
+      if (j >= 0)
+        L.remove(j);
+      else
+        L.add(q, err);
+    }
+    if ((b & 1u) && x) amp = make_double2(-amp.x, -amp.y);
+    return;
+  }
+  const uint32_t v = j < 0 ? 0u : ((L.raw(j) & LV_R_BIT) ? 2u : 1u);
+  x = (v + a) % 3u;
+  if (v != x) {
+    if (j >= 0) L.remove(j);
+    if (x) L.add(q | (x == 2 ? LV_R_BIT : 0u), err);
+  }
+  const uint32_t ph = (b * x) % 3u;
+  if (ph) {  // multiply by exp(+-2 pi i / 3) = -1/2 +- i sqrt(3)/2
+    const double c = -0.5, sn = ph == 1 ? 0.86602540378443864676 : -0.86602540378443864676;
+    amp = make_double2(amp.x * c - amp.y * sn, amp.x * sn + amp.y * c);
+  }
+}
+
 struct PlainSm {
   uint32_t *cbm;     // candidate bitmap of the slice [(M + 31) / 32]
   uint32_t *cstart;  // [MAXT + 1] first candidate of each slice
   uint32_t *J;       // [JMAX] joint outcome: site | level << 16
-  double *red;       // [16 * 8] reduction buffer
-  int *misc;         // [8]
+  double *red;       // [16 * 16] reduction buffer
+  int *misc;         // [16]
 };
 
 __host__ __device__ inline uint32_t plain_sm_bytes(int M) {
-  return (uint32_t)(((M + 31) / 32) * 4 + (MAXT + 1) * 4 + JMAX * 4 + 16 * 8 * 8 + 8 * 4 + 64);
+  return (uint32_t)(((M + 31) / 32) * 4 + (MAXT + 1) * 4 + JMAX * 4 + 16 * 16 * 8 + 16 * 4 + 64);
 }
 
 __device__ inline PlainSm plain_carve(unsigned char *base, int M) {
   PlainSm s;
   size_t o = 0;
   s.red = reinterpret_cast<double *>(base + o);
-  o += 16 * 8 * 8;
+  o += 16 * 16 * 8;
   s.cbm = reinterpret_cast<uint32_t *>(base + o);
   o += (size_t)((M + 31) / 32) * 4;
   s.cstart = reinterpret_cast<uint32_t *>(base + o);
@@ -217,24 +251,51 @@ __device__ inline PlainSm plain_carve(unsigned char *base, int M) {
 
 __device__ __forceinline__ double abs2(double2 z) { return z.x * z.x + z.y * z.y; }
 
+__device__ __forceinline__ double2 in_amp(const Tables *__restrict__ tb, uint32_t i) {
+  return tb->cin ? make_double2(tb->cin[2 * i], tb->cin[2 * i + 1]) : make_double2(1.0 / sqrt((double)tb->D), 0.0);
+}
+
+// Exposure of branch i on its no-jump orbit through slice s, the part that
+// differs between branches: its address tokens, and (qutrit) its data slots,
+// which hold j_b before the fetch of bit b and j_b xor d_b after it (the
+// qubit's bus words, and every router level, are common to all branches).
+template <int ENC>
+__device__ __forceinline__ int branch_exposure(const Tables *__restrict__ tb, uint32_t i, int s) {
+  const int n = tb->n;
+  int e = 0;
+  for (int t = 0; t < n; ++t)
+    if ((i >> (n - 1 - t)) & 1u) e += tb->cntA[s][t];
+  if (ENC == QUTRIT) {
+    const uint32_t j = tb->jin ? tb->jin[i] : 0u, d = tb->mem[i];
+    for (int b = 0; b < tb->k; ++b) {
+      const int in_tree = max(0, min(s, 4 * n + 2 * b) - (2 * n + 2 * b));
+      const int after = tb->cntD[s][b];
+      e += (int)((j >> b) & 1u) * (in_tree - after) + (int)(((j ^ d) >> b) & 1u) * after;
+    }
+  }
+  return e;
+}
+
 template <int ENC>
 __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, const Run R_) {
   const Run *rp = &R_;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int n = tb->n, T = tb->T, M = tb->M, D = tb->D, k = tb->k;
+  const int T = tb->T, M = tb->M, D = tb->D, k = tb->k;
   const int K2 = ENC == QUBIT ? tb->K2 : 1;
   const int kb = ENC == QUBIT ? k : 0;
   const uint32_t kmask = (1u << k) - 1u;
-  const uint32_t E = (uint32_t)(D * K2);
   const int rec = rp->prec;
   const int lcap = rec - 2;
+  const bool pruned = rp->mode == 1;
   PlainSm sm = plain_carve(smem, M);
-  uint16_t *pool = rp->pool + (size_t)blockIdx.x * E * rec;
-  double2 *amp = reinterpret_cast<double2 *>(rp->pamp) + (size_t)blockIdx.x * E;
-  uint8_t *hitf = rp->phit + (size_t)blockIdx.x * E;
+  const uint32_t Emax = (uint32_t)(D * K2);
+  uint16_t *pool = rp->pool + (size_t)blockIdx.x * Emax * rec;
+  double2 *amp = reinterpret_cast<double2 *>(rp->pamp) + (size_t)blockIdx.x * Emax;
+  uint8_t *hitf = rp->phit + (size_t)blockIdx.x * Emax;
   double2 *grp = reinterpret_cast<double2 *>(rp->pgrp) + ((size_t)blockIdx.x * nthr + tid) * K2;
   const double *__restrict__ apow = tb->apow + tb->emax;
+  const double *__restrict__ wpow = tb->wpow + tb->emax;
   const double sg = tb->sg;
   const uint32_t ccap = rp->cand_cap;
   for (int w = tid; w < (M + 31) / 32; w += nthr) sm.cbm[w] = 0u;
@@ -244,43 +305,86 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
     const uint32_t nct = min(rp->ncand[tj], ccap);
     const uint32_t *__restrict__ cand = rp->cand + (size_t)tj * ccap;
     const uint32_t ref = rp->ref[tj];
+    // explicit addresses: every address (full), or the bad ones plus the
+    // reference in ascending order (pruned, Alg. 1); explicit component y =
+    // g * K2 + beta of explicit address xl[g]
+    const uint16_t *__restrict__ xl = pruned ? rp->xlist + (size_t)tj * D : nullptr;
+    const uint32_t A = pruned ? (rp->nexpl[tj] >> kb) : (uint32_t)D;
+    const uint32_t E = A * (uint32_t)K2;
+    const uint64_t *__restrict__ badg = rp->badbits + (size_t)tj * ((D + 63) >> 6);
+    // the good branches ride on the reference (pruned, a reference exists)
+    const bool goods = pruned && ref != 0xFFFFFFFFu && A < (uint32_t)D;
+    if (tid == 0) sm.misc[8] = -1;
     for (uint32_t j = tid; j <= nct; j += nthr) {  // first candidate of each slice
       const int sj = j < nct ? (int)(cand[j] / (uint32_t)M) + 1 : T;
       const int sp = j > 0 ? (int)(cand[j - 1] / (uint32_t)M) + 1 : 0;
       for (int ss = sp + 1; ss <= sj; ++ss) sm.cstart[ss] = j;
     }
-    // the data-loading input after the first wall (qubit: 2^k bus words of
-    // amplitude 2^(-n/2) 2^(-k/2); qutrit: bus word 0, amplitude 2^(-n/2))
-    const double c0 = 1.0 / sqrt((double)D * (double)K2);
-    for (uint32_t x = tid; x < E; x += nthr) {
-      uint16_t *r = pool + (size_t)x * rec;
-      r[0] = 0;
-      r[1] = (uint16_t)(ENC == QUBIT ? (x & (uint32_t)(K2 - 1)) : 0u);
-      amp[x] = make_double2(c0, 0.0);
+    __syncthreads();
+    // the input after the first wall: qubit, the 2^k bus words beta of each
+    // address i with amplitude c_i 2^(-k/2) (-1)^(beta . j_i); qutrit, bus
+    // word j_i with amplitude c_i.  The data-loading input has c_i =
+    // 2^(-n/2), j_i = 0; an address absent from the input has no component.
+    const double wall = 1.0 / sqrt((double)K2);
+    for (uint32_t y = tid; y < E; y += nthr) {
+      uint16_t *r = pool + (size_t)y * rec;
+      const uint32_t g = y >> kb, beta = y & (uint32_t)(K2 - 1);
+      const uint32_t i = xl ? xl[g] : g;
+      if (i == ref) sm.misc[8] = (int)g;
+      double2 c = in_amp(tb, i);
+      const uint32_t j = tb->jin ? tb->jin[i] : 0u;
+      if (ENC == QUBIT && (__popc(beta & j) & 1)) c = make_double2(-c.x, -c.y);
+      r[0] = (c.x != 0.0 || c.y != 0.0) ? 0 : PL_DEAD;
+      r[1] = (uint16_t)(ENC == QUBIT ? beta : j);
+      amp[y] = make_double2(c.x * wall, c.y * wall);
     }
+    const uint32_t nd = rp->dep ? min(rp->ndep[tj], rp->dep_cap) : 0u;
+    const uint32_t *__restrict__ dep = rp->dep ? rp->dep + (size_t)tj * rp->dep_cap : nullptr;
+    uint32_t dpos = 0;
     int njumps = 0, first_jump = 0;
     uint32_t jl_n = 0;
     __syncthreads();
+    const int gref = sm.misc[8];  // explicit index of the reference, or -1
+    double cref2 = 0.0;
+    if (goods) cref2 = abs2(in_amp(tb, ref));
+    // a good address (present, outside the bad set, not the reference):
+    // its weight relative to the reference's through slice s
+    auto good_ratio = [&](uint32_t i, int s, int eref) -> double {
+      if (i == ref || ((badg[i >> 6] >> (i & 63)) & 1ull)) return 0.0;
+      const double c2 = abs2(in_amp(tb, i));
+      if (c2 == 0.0) return 0.0;
+      return c2 / cref2 * wpow[branch_exposure<ENC>(tb, i, s) - eref];
+    };
 
     for (int s = 1; s < T; ++s) {
       const uint32_t cb = sm.cstart[s], ce = sm.cstart[s + 1];
       const uint32_t nc = ce - cb;
+      const uint32_t d0 = dpos;  // the slice's depolarizing faults: dep[d0 .. dpos)
+      while (dpos < nd && ((dep[dpos] >> 16) & 0xFFu) == (uint32_t)s) ++dpos;
       for (uint32_t j = cb + tid; j < ce; j += nthr) {
         const uint32_t q = cand[j] - (uint32_t)(s - 1) * M;
         atomicOr(&sm.cbm[q >> 5], 1u << (q & 31));
       }
       __syncthreads();
-      // gates, then (without candidates) K0 at once; with candidates the
-      // hit test of every component against the slice's candidate set
+      // gates and faults, then (without candidates) K0 at once; with
+      // candidates the hit test of every component against the slice's set
       int anyhit = 0;
-      for (uint32_t x = tid; x < E; x += nthr) {
-        PList<ENC> L{pool + (size_t)x * rec, lcap};
+      for (uint32_t y = tid; y < E; y += nthr) {
+        PList<ENC> L{pool + (size_t)y * rec, lcap};
         if (L.cnt() == PL_DEAD) continue;
-        const uint32_t a = x >> kb;
-        if (plain_gates<ENC>(tb, s, L, a, rp->err)) amp[x] = make_double2(-amp[x].x, -amp[x].y);
+        const uint32_t a = xl ? xl[y >> kb] : (y >> kb);
+        if (plain_gates<ENC>(tb, s, L, a, rp->err)) amp[y] = make_double2(-amp[y].x, -amp[y].y);
+        if (dpos > d0) {  // faults after the gates, before the damping layer
+          double2 am = amp[y];
+          for (uint32_t f = d0; f < dpos; ++f) {
+            const uint32_t e = dep[f], t = e >> 24;
+            plain_fault<ENC>(L, am, e & 0xFFFFu, t & 3u, t >> 2, rp->err);
+          }
+          amp[y] = am;
+        }
         if (nc == 0) {
           const double f = apow[L.cnt()];
-          amp[x] = make_double2(amp[x].x * f, amp[x].y * f);
+          amp[y] = make_double2(amp[y].x * f, amp[y].y * f);
           continue;
         }
         uint8_t h = 0;
@@ -288,62 +392,118 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
           const uint32_t q = L.raw(j) & PList<ENC>::SM;
           h = (uint8_t)((sm.cbm[q >> 5] >> (q & 31)) & 1u);
         }
-        hitf[x] = h;
+        hitf[y] = h;
         anyhit |= h;
       }
       if (nc == 0) continue;  // (the bitmap is already clean)
       anyhit = __syncthreads_or(anyhit);
       int nJ = 0;
       if (anyhit) {
-        // Eq. maskweight: the empty-mask block and the hit components
-        double acc[2] = {0.0, 0.0};
-        for (uint32_t x = tid; x < E; x += nthr) {
-          if (pool[(size_t)x * rec] == PL_DEAD) continue;
-          acc[hitf[x] ? 1 : 0] += abs2(amp[x]);
+        // Eq. maskweight: the empty-mask block and the hit components; a
+        // good branch has the reference's mask for the same bus word and the
+        // reference's weight times its ratio
+        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // empty, hit, ref empty, ref hit, sum of ratios
+        for (uint32_t y = tid; y < E; y += nthr) {
+          if (pool[(size_t)y * rec] == PL_DEAD) continue;
+          const double w = abs2(amp[y]);
+          const int h = hitf[y] ? 1 : 0;
+          acc[h] += w;
+          if (goods && (int)(y >> kb) == gref) acc[2 + h] += w;
         }
-        block_sum<2>(acc, sm.red);
-        const double wall = acc[0] + acc[1];
+        const int eref = goods ? branch_exposure<ENC>(tb, ref, s) : 0;
+        if (goods)
+          for (int i = tid; i < D; i += nthr) acc[4] += good_ratio((uint32_t)i, s, eref);
+        block_sum<5>(acc, sm.red);
+        const double w_empty = acc[0] + acc[4] * acc[2];
+        const double w_hit = acc[1] + acc[4] * acc[3];
         const double u = rp->forced ? rp->uaux[s] : uniform53(rp->seed, (uint32_t)s, 0, traj, 2u);
-        const double r = u * wall;
-        if (!(r < acc[0])) {
-          // x*: first hit component, in label order, whose running weight
-          // exceeds r - w(empty); the last hit one if rounding runs out
-          const double r2 = r - acc[0];
+        const double r = u * (w_empty + w_hit);
+        if (!(r < w_empty)) {
+          // x*: first hit component, in initial-label order over every
+          // branch, whose running weight exceeds r - w(empty); the last hit
+          // one if rounding runs out.  pick = (label, explicit index whose
+          // list holds x*'s mask)
+          const double r2 = r - w_empty;
           double base = 0.0;
-          int pick = -1, last = -1;
-          for (uint32_t x0 = 0; x0 < E && pick < 0; x0 += (uint32_t)nthr) {
+          int pick = -1, last = -1, pick_y = -1, last_y = -1;
+          const uint32_t Lx = (uint32_t)(D * K2);
+          for (uint32_t x0 = 0; x0 < Lx && pick < 0; x0 += (uint32_t)nthr) {
             const uint32_t x = x0 + (uint32_t)tid;
             double w = 0.0;
-            bool h = false;
-            if (x < E && pool[(size_t)x * rec] != PL_DEAD && hitf[x]) {
-              h = true;
-              w = abs2(amp[x]);
+            int my = -1;
+            if (x < Lx) {
+              const uint32_t a = x >> kb, beta = x & (uint32_t)(K2 - 1);
+              int g = -1;
+              if (!xl) {
+                g = (int)a;
+              } else if (a == ref || ((badg[a >> 6] >> (a & 63)) & 1ull)) {
+                int lo = 0, hi = (int)A - 1;  // a's position in the ascending explicit list
+                while (lo < hi) {
+                  const int mid = (lo + hi) >> 1;
+                  if (xl[mid] < a)
+                    lo = mid + 1;
+                  else
+                    hi = mid;
+                }
+                g = lo;
+              }
+              if (g >= 0) {
+                const uint32_t y = (uint32_t)g * K2 + beta;
+                if (pool[(size_t)y * rec] != PL_DEAD && hitf[y]) {
+                  w = abs2(amp[y]);
+                  my = (int)y;
+                }
+              } else if (goods) {
+                const uint32_t y = (uint32_t)gref * K2 + beta;
+                if (pool[(size_t)y * rec] != PL_DEAD && hitf[y]) {
+                  w = abs2(amp[y]) * good_ratio(a, s, eref);
+                  if (w > 0.0) my = (int)y;
+                }
+              }
             }
             __syncthreads();  // (the scan buffer is reused)
             const double ex = block_excl_scan(w, sm.red);
             __syncthreads();
             if (tid == nthr - 1) sm.red[64] = ex + w;
-            const int mine = (h && base + ex + w > r2) ? (int)x : 0x7FFFFFFF;
-            int lowest = mine;
+            const bool mine = my >= 0 && base + ex + w > r2;
+            int lowest = mine ? (int)x : 0x7FFFFFFF;
             for (int off = 32; off > 0; off >>= 1) lowest = min(lowest, __shfl_xor(lowest, off, 64));
-            if ((tid & 63) == 0) sm.misc[1 + (tid >> 6)] = lowest;
-            int lastm = h ? (int)x : -1;
+            int lastm = my >= 0 ? (int)x : -1;
             for (int off = 32; off > 0; off >>= 1) lastm = max(lastm, __shfl_xor(lastm, off, 64));
-            if ((tid & 63) == 0) reinterpret_cast<int *>(sm.J)[JMAX - 1 - (tid >> 6)] = lastm;
+            if ((tid & 63) == 0) {
+              sm.misc[1 + (tid >> 6)] = lowest;
+              reinterpret_cast<int *>(sm.J)[JMAX - 1 - (tid >> 6)] = lastm;
+            }
+            if (mine && (int)x == lowest) sm.misc[5 + (tid >> 6)] = my;  // explicit index of the wave's pick
+            if (my >= 0 && (int)x == lastm) reinterpret_cast<int *>(sm.J)[JMAX - 5 - (tid >> 6)] = my;
             __syncthreads();
-            int best = 0x7FFFFFFF;
+            int best = 0x7FFFFFFF, bw = -1, lw = -1, lst = -1;
             for (int w8 = 0; w8 < nthr / 64; ++w8) {
-              best = min(best, sm.misc[1 + w8]);
-              last = max(last, reinterpret_cast<int *>(sm.J)[JMAX - 1 - w8]);
+              if (sm.misc[1 + w8] < best) {
+                best = sm.misc[1 + w8];
+                bw = w8;
+              }
+              const int l8 = reinterpret_cast<int *>(sm.J)[JMAX - 1 - w8];
+              if (l8 > lst) {
+                lst = l8;
+                lw = w8;
+              }
+            }
+            if (lst >= 0 && lst > last) {
+              last = lst;
+              last_y = reinterpret_cast<int *>(sm.J)[JMAX - 5 - lw];
             }
             base += sm.red[64];
-            if (best != 0x7FFFFFFF) pick = best;
+            if (best != 0x7FFFFFFF) {
+              pick = best;
+              pick_y = sm.misc[5 + bw];
+            }
             __syncthreads();
           }
-          if (pick < 0) pick = last;
+          if (pick < 0) pick_y = last_y;
           // J = the slice's candidates among x*'s excited sites, with levels
           if (tid == 0) {
-            PList<ENC> L{pool + (size_t)pick * rec, lcap};
+            PList<ENC> L{pool + (size_t)pick_y * rec, lcap};
             int m = 0;
             for (int j = 0; j < L.cnt(); ++j) {
               const uint32_t x = L.raw(j), q = x & PList<ENC>::SM;
@@ -351,8 +511,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
               const uint32_t lev = (ENC == QUTRIT && (x & LV_R_BIT)) ? 2u : 1u;
               if (m < JMAX) sm.J[m++] = q | (lev << 16);
             }
-            // ascending site order, as the oracle logs them
-            for (int i = 1; i < m; ++i)
+            for (int i = 1; i < m; ++i)  // ascending site order
               for (int j = i; j > 0 && (sm.J[j] & 0xFFFFu) < (sm.J[j - 1] & 0xFFFFu); --j) {
                 const uint32_t t = sm.J[j];
                 sm.J[j] = sm.J[j - 1];
@@ -364,9 +523,10 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
           nJ = sm.misc[0];
         }
       }
-      // K_J on every component: survivors carry J's sites at J's levels
-      for (uint32_t x = tid; x < E; x += nthr) {
-        PList<ENC> L{pool + (size_t)x * rec, lcap};
+      // K_J on every explicit component: survivors carry J's sites at J's
+      // levels (the good branches survive exactly when the reference does)
+      for (uint32_t y = tid; y < E; y += nthr) {
+        PList<ENC> L{pool + (size_t)y * rec, lcap};
         if (L.cnt() == PL_DEAD) continue;
         bool ok = true;
         for (int c = 0; c < nJ && ok; ++c) {
@@ -376,12 +536,12 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
         }
         if (!ok) {
           L.r[0] = PL_DEAD;
-          amp[x] = make_double2(0.0, 0.0);
+          amp[y] = make_double2(0.0, 0.0);
           continue;
         }
         double f = apow[L.cnt() - nJ];
         for (int c = 0; c < nJ; ++c) f *= sg;
-        amp[x] = make_double2(amp[x].x * f, amp[x].y * f);
+        amp[y] = make_double2(amp[y].x * f, amp[y].y * f);
         for (int c = 0; c < nJ; ++c) L.remove(L.find(sm.J[c] & 0xFFFFu));
       }
       if (nJ > 0) {
@@ -402,14 +562,16 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
     // the last slice may have ended without a barrier (no candidates): every
     // thread's lists must be final before any thread reads another's
     __syncthreads();
-    if (rp->exp && tj == 0) {  // test entry: every component's final list and amplitude
+    if (rp->exp && tj == 0) {  // test entry: every explicit component's final list and amplitude
       const uint32_t rw = 3u + (uint32_t)tb->lmax;
-      for (uint32_t x = tid; x < E; x += nthr) {
-        const uint16_t *r = pool + (size_t)x * rec;
+      for (uint32_t y = tid; y < E; y += nthr) {
+        const uint16_t *r = pool + (size_t)y * rec;
+        const uint32_t a = xl ? xl[y >> kb] : (y >> kb);
+        const uint32_t x = (a << kb) | (y & (uint32_t)(K2 - 1));
         uint32_t *o = rp->exp + (size_t)x * rw;
         if (r[0] == PL_DEAD) continue;
         const uint32_t m = min((uint32_t)r[0], (uint32_t)tb->lmax);
-        o[0] = (x >> kb) | ((uint32_t)r[1] << 16) | EXP_PRESENT;
+        o[0] = a | ((uint32_t)r[1] << 16) | EXP_PRESENT;
         o[1] = 0;
         o[2] = m;
         for (uint32_t j = 0; j < m; ++j) {
@@ -417,35 +579,55 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
           const uint32_t q = e & PList<ENC>::SM, lev = (ENC == QUTRIT && (e & LV_R_BIT)) ? 2u : 1u;
           o[3 + j] = q | (lev << 16);
         }
-        rp->expamp[2 * x] = amp[x].x;
-        rp->expamp[2 * x + 1] = amp[x].y;
+        if (rp->expamp) {
+          rp->expamp[2 * x] = amp[y].x;
+          rp->expamp[2 * x + 1] = amp[y].y;
+        }
       }
     }
     // second wall (qubit), tree measurement, fidelity.  Components with an
     // excited tree are orthogonal to the ideal output and to every other
     // group, so only their weight counts; the ground components of an
-    // address are grouped by bus word before the wall.
-    double fin[5] = {0, 0, 0, 0, 0};  // overlap re, im, w_ground, w_excited, ref alive
-    const double ci = 1.0 / sqrt((double)D);
-    if (ENC == QUBIT) {
-      const double h = 1.0 / sqrt((double)K2);
-      for (int i = tid; i < D; i += nthr) {
-        bool any = false;
-        for (int b = 0; b < K2; ++b) grp[b] = make_double2(0.0, 0.0);
-        for (int b = 0; b < K2; ++b) {
-          const uint32_t x = (uint32_t)i * K2 + (uint32_t)b;
-          const uint16_t *r = pool + (size_t)x * rec;
-          if (r[0] == PL_DEAD) continue;
-          if ((uint32_t)i == ref) fin[4] = 1.0;
-          if (r[0] != 0) {
-            fin[3] += abs2(amp[x]);
-            continue;
-          }
-          const uint32_t bw = r[1] & (uint32_t)(K2 - 1);
-          grp[bw] = make_double2(grp[bw].x + amp[x].x, grp[bw].y + amp[x].y);
-          any = true;
+    // address are grouped by bus word before the wall.  The ideal output is
+    // sum_i c_i |i>|j_i xor d_i>|ground>: overlap terms conj(c_i) A(i, j_i
+    // xor d_i).  The reference's own terms are kept apart as well: a good
+    // branch i adds |c_i|^2 a^(e_i - e_ref) / |c_ref|^2 times the
+    // reference's overlap term and |c_i / c_ref|^2 (1-gamma)^(e_i - e_ref)
+    // times its weights (Theorem 3 with the XOR mirror, Proposition 1).
+    double fin[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // overlap re, im, w_ground, w_excited, ref alive, ref overlap re, im,
+    // ref w_ground, ref w_excited, ratio sums (below)
+    for (uint32_t g = (uint32_t)tid; g < A; g += (uint32_t)nthr) {
+      const uint32_t i = xl ? xl[g] : g;
+      const bool isref = i == ref;
+      const double2 ci = in_amp(tb, i);
+      const double2 cc = make_double2(ci.x, -ci.y);
+      const uint32_t want = ((tb->jin ? tb->jin[i] : 0u) ^ tb->mem[i]) & kmask;
+      bool any = false;
+      for (int b = 0; b < K2; ++b) grp[b] = make_double2(0.0, 0.0);
+      for (int b = 0; b < K2; ++b) {
+        const uint32_t y = g * (uint32_t)K2 + (uint32_t)b;
+        const uint16_t *r = pool + (size_t)y * rec;
+        if (r[0] == PL_DEAD) continue;
+        if (isref) fin[4] = 1.0;
+        if (r[0] != 0) {
+          fin[3] += abs2(amp[y]);
+          if (isref) fin[8] += abs2(amp[y]);
+          continue;
         }
-        if (!any) continue;
+        // qubit: grouped by bus word for the wall; qutrit (one component
+        // per address): slot 0, its bus word must be the ideal one
+        if (ENC == QUTRIT && ((uint32_t)r[1] & kmask) != want) {
+          fin[2] += abs2(amp[y]);
+          if (isref) fin[7] += abs2(amp[y]);
+          continue;
+        }
+        const uint32_t bw = ENC == QUBIT ? ((uint32_t)r[1] & (uint32_t)(K2 - 1)) : 0u;
+        grp[bw] = make_double2(grp[bw].x + amp[y].x, grp[bw].y + amp[y].y);
+        any = true;
+      }
+      if (!any) continue;
+      if (ENC == QUBIT)
         for (int len = 1; len < K2; len <<= 1)  // Walsh-Hadamard transform in place
           for (int b = 0; b < K2; ++b)
             if (!(b & len)) {
@@ -453,36 +635,48 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
               grp[b] = make_double2(u.x + v.x, u.y + v.y);
               grp[b + len] = make_double2(u.x - v.x, u.y - v.y);
             }
-        const uint32_t want = tb->mem[i] & kmask;
-        for (int c = 0; c < K2; ++c) {
-          const double2 v = make_double2(grp[c].x * h, grp[c].y * h);
-          fin[2] += abs2(v);
-          if ((uint32_t)c == want) {
-            fin[0] += ci * v.x;
-            fin[1] += ci * v.y;
+      const double h = ENC == QUBIT ? 1.0 / sqrt((double)K2) : 1.0;
+      const uint32_t slot = ENC == QUBIT ? want : 0u;
+      for (int c = 0; c < K2; ++c) {
+        const double2 v = make_double2(grp[c].x * h, grp[c].y * h);
+        fin[2] += abs2(v);
+        if (isref) fin[7] += abs2(v);
+        if ((uint32_t)c == slot) {
+          const double ox = cc.x * v.x - cc.y * v.y, oy = cc.x * v.y + cc.y * v.x;
+          fin[0] += ox;
+          fin[1] += oy;
+          if (isref) {
+            fin[5] += ox;
+            fin[6] += oy;
           }
         }
       }
-    } else {
-      for (uint32_t x = tid; x < E; x += nthr) {
-        const uint16_t *r = pool + (size_t)x * rec;
-        if (r[0] == PL_DEAD) continue;
-        if (x == ref) fin[4] = 1.0;
-        if (r[0] != 0) {
-          fin[3] += abs2(amp[x]);
-          continue;
-        }
-        fin[2] += abs2(amp[x]);
-        if ((uint32_t)r[1] == (tb->mem[x] & kmask)) {
-          fin[0] += ci * amp[x].x;
-          fin[1] += ci * amp[x].y;
-        }
+    }
+    double gw = 0.0, ga = 0.0;  // sums over good branches of (1-gamma)^de |c_i/c_ref|^2 and a^de |c_i|^2
+    if (goods) {
+      const int eref = branch_exposure<ENC>(tb, ref, T - 1);
+      for (int i = tid; i < D; i += nthr) {
+        const double rw = good_ratio((uint32_t)i, T - 1, eref);
+        if (rw == 0.0) continue;
+        gw += rw;
+        ga += abs2(in_amp(tb, (uint32_t)i)) * apow[branch_exposure<ENC>(tb, (uint32_t)i, T - 1) - eref];
       }
     }
-    block_sum<5>(fin, sm.red);
+    fin[9] = gw;
+    double fin2[1] = {ga};
+    block_sum<10>(fin, sm.red);
+    block_sum<1>(fin2, sm.red + 160);
     if (tid == 0) {
-      const double ov2 = fin[0] * fin[0] + fin[1] * fin[1];
-      const double wg = fin[2], wt = fin[2] + fin[3];
+      double ovx = fin[0], ovy = fin[1], wg = fin[2], wx = fin[3];
+      if (goods && cref2 > 0.0) {
+        const double ga_ref = fin2[0] / cref2;
+        ovx += ga_ref * fin[5];
+        ovy += ga_ref * fin[6];
+        wg += fin[9] * fin[7];
+        wx += fin[9] * fin[8];
+      }
+      const double ov2 = ovx * ovx + ovy * ovy;
+      const double wt = wg + wx;
       const double uf = rp->forced ? rp->ufin : uniform53(rp->seed, 0, 0, traj, 3u);
       const bool qg = uf * wt < wg;
       rp->fid[tj] = (qg && wg > 0.0) ? ov2 / wg : 0.0;

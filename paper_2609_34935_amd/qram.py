@@ -32,6 +32,12 @@ class QramRequest(C.Structure):
                 ("shots", C.c_uint32), ("mode", C.c_int)]
 
 
+class QramParams(C.Structure):
+    _fields_ = [("n_addr", C.c_int), ("k_data", C.c_int), ("enc", C.c_int), ("gamma", C.c_double),
+                ("eps", C.c_double), ("memory_bits", C.POINTER(C.c_uint32)),
+                ("input_amp", C.POINTER(C.c_double)), ("input_bus", C.POINTER(C.c_uint32))]
+
+
 class QramResult(C.Structure):
     _fields_ = [("ticket", C.c_uint64), ("state", C.c_int), ("status", C.c_int), ("mean", C.c_double),
                 ("sem", C.c_double), ("shots", C.c_uint32), ("footprint_bytes", C.c_uint64),
@@ -39,7 +45,7 @@ class QramResult(C.Structure):
 
 # Every entry point declared in include/qram.h.
 EXPORTS = [
-    "qram_create", "qram_destroy", "qram_last_error", "qram_sample_faults",
+    "qram_create", "qram_create_ex", "qram_destroy", "qram_last_error", "qram_sample_faults", "qram_sample_depol",
     "qram_run_full", "qram_run_pruned", "qram_run_full_async", "qram_run_pruned_async",
     "qram_fidelity", "qram_set_launch", "qram_get_launch", "qram_autotune",
     "qram_last_kernel_ms", "qram_set_timing", "qram_stage_times", "qram_stage_launches", "qram_set_option",
@@ -76,6 +82,9 @@ def load_library(path: str = LIB_PATH):
     p = C.POINTER
     L.qram_create.argtypes = [C.c_int, C.c_int, C.c_int, f64, p(u32), p(vp)]
     L.qram_create.restype = C.c_int
+    L.qram_create_ex.argtypes = [C.POINTER(QramParams), p(vp)]
+    L.qram_create_ex.restype = C.c_int
+    L.qram_sample_depol.argtypes = [vp, u64, u64, u32, p(u32), p(u32), u64]
     L.qram_destroy.argtypes = [vp]
     L.qram_destroy.restype = None
     L.qram_server_destroy.restype = None
@@ -137,9 +146,12 @@ class QramContext:
     """One (n, k, encoding, gamma, memory) simulator context on the current
     HIP device (``qram_create`` ... ``qram_destroy``)."""
 
-    def __init__(self, n_addr, k_data, encoding, gamma, memory_bits):
+    def __init__(self, n_addr, k_data, encoding, gamma, memory_bits, eps=0.0, input_amp=None, input_bus=None):
+        """eps: depolarizing strength; input_amp (complex, 2^n) and input_bus
+        (2^n words): a general input sum_i c_i |i>|j_i> (``qram_create_ex``)."""
         L = load_library()
         self.n, self.k, self.enc, self.gamma = int(n_addr), int(k_data), int(encoding), float(gamma)
+        self.eps = float(eps)
         self.T = 6 * self.n + 2 * self.k
         self.M = 2 * ((1 << self.n) - 1)
         self.D = 1 << self.n
@@ -147,11 +159,40 @@ class QramContext:
         if mem.shape != (self.D,):
             raise ValueError(f"memory_bits must hold 2^n = {self.D} words")
         h = C.c_void_p()
-        st = L.qram_create(self.n, self.k, self.enc, self.gamma, _ptr(mem, C.c_uint32), C.byref(h))
+        if self.eps == 0.0 and input_amp is None and input_bus is None:
+            st = L.qram_create(self.n, self.k, self.enc, self.gamma, _ptr(mem, C.c_uint32), C.byref(h))
+        else:
+            amp = bus = None
+            if input_amp is not None:
+                c = np.asarray(input_amp, dtype=np.complex128)
+                if c.shape != (self.D,):
+                    raise ValueError(f"input_amp must hold 2^n = {self.D} amplitudes")
+                amp = np.empty(2 * self.D)
+                amp[0::2], amp[1::2] = c.real, c.imag
+            if input_bus is not None:
+                bus = np.ascontiguousarray(input_bus, dtype=np.uint32)
+                if bus.shape != (self.D,):
+                    raise ValueError(f"input_bus must hold 2^n = {self.D} words")
+            prm = QramParams(self.n, self.k, self.enc, self.gamma, self.eps, _ptr(mem, C.c_uint32),
+                             _ptr(amp, C.c_double), _ptr(bus, C.c_uint32))
+            st = L.qram_create_ex(C.byref(prm), C.byref(h))
         if st:
             raise QramError(st, L.qram_last_error(None).decode())
         self._h = h
         self._L = L
+
+    def sample_depol(self, seed, traj0, ntraj, cap=None):
+        """Depolarizing faults: (counts [ntraj], entries site | slice << 16 |
+        type << 24 concatenated in trajectory order)."""
+        cnt = np.zeros(ntraj, dtype=np.uint32)
+        self._check(self._L.qram_sample_depol(self._h, seed, traj0, ntraj, _ptr(cnt, C.c_uint32), None, 0),
+                    "qram_sample_depol")
+        tot = int(cnt.sum())
+        cap = tot if cap is None else cap
+        dep = np.zeros(max(cap, 1), dtype=np.uint32)
+        self._check(self._L.qram_sample_depol(self._h, seed, traj0, ntraj, _ptr(cnt, C.c_uint32),
+                                              _ptr(dep, C.c_uint32), cap), "qram_sample_depol")
+        return cnt, dep[:tot]
 
     def _check(self, st, what):
         if st:

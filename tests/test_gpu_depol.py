@@ -1,0 +1,222 @@
+"""Depolarizing faults (App. C) and general inputs (Sec. II B) on the HIP
+path against the oracle.
+
+Contexts made with eps > 0, a general input sum_i c_i |i>|j_i>, or qubit
+k > 6 run every mode on the plain engine: QRAM_MODE_FULL and QRAM_MODE_PLAIN
+as the full evolution, QRAM_MODE_PRUNED as Alg. 1 on explicit lists (bad
+branches plus the reference; the good branches carried by the reference's
+weights).  Checked here:
+  - the fault sampler is bit-exact against the oracle's (same Philox
+    counters, the same geometric walk over the active positions, the same
+    type draw);
+  - fidelities within 1e-12 relative and the integer statistics identical,
+    every mode, small trees with strong noise and the qubit k = 7, 8 range;
+  - pruned equals full on the same trajectories;
+  - exported components (label, address, bus word, tree, complex amplitude)
+    and jump logs equal the oracle's;
+  - the trajectory mean at App. C's configuration reproduces Table 4's
+    density-matrix fidelities (Pauli 0.7263, Mixed 0.5841) within four
+    standard errors plus half a unit of the printed last digit."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2609_34935_amd.inputs import memory_words
+
+pytestmark = pytest.mark.gpu
+
+QUTRIT, QUBIT = 0, 1
+FULL, PRUNED, PLAIN = 0, 1, 2
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_34935_amd as P
+    P.load_library()
+    return P
+
+
+def fid_close(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b) <= 1e-12 * np.maximum(np.abs(b), 1e-3)
+
+
+def decode_jlog(entries):
+    return sorted((int(x) >> 24, int(x) & 0xFFFF, (int(x) >> 16) & 0xFF) for x in entries)
+
+
+def random_input(n, k, enc, seed, absent=0.25):
+    """Complex amplitudes with about a quarter of the addresses absent, and a
+    random bus word per address."""
+    rng = np.random.default_rng(seed)
+    D = 1 << n
+    c = rng.normal(size=D) + 1j * rng.normal(size=D)
+    c[rng.uniform(size=D) < absent] = 0.0
+    c[rng.integers(D)] = 0.7 + 0.2j  # never empty
+    j = rng.integers(0, 1 << k, size=D).astype(np.uint32)
+    return c, j
+
+
+def check_stats(f, st, fo, fpo, so, label, explicit=None):
+    bad = np.nonzero(~fid_close(f, fo))[0]
+    assert len(bad) == 0, (label, bad[:5], f[bad[:5]], fo[bad[:5]])
+    assert np.all(fid_close(st["fid_pre"], fpo)), label
+    ref = np.where(so[:, 2] < 0, 0xFFFFFFFF, so[:, 2]).astype(np.uint32)
+    assert np.array_equal(st["n_cand"], so[:, 0].astype(np.uint32)), label
+    assert np.array_equal(st["n_bad"], so[:, 1].astype(np.uint32)), label
+    assert np.array_equal(st["ref_addr"], ref), label
+    assert np.array_equal(st["n_jumps"], so[:, 4].astype(np.uint16)), label
+    assert np.array_equal(st["first_jump_slice"], so[:, 5].astype(np.uint16)), label
+    assert np.array_equal(st["ref_survived"], so[:, 6].astype(np.uint8)), label
+    assert np.array_equal(st["q_ground"], so[:, 7].astype(np.uint8)), label
+    assert np.all((st["flags"] & 2) == 0), label
+
+
+@pytest.mark.parametrize("n,k,enc,eps", [
+    (2, 1, QUBIT, 0.02), (3, 2, QUBIT, 0.2), (5, 3, QUBIT, 1e-3), (8, 4, QUBIT, 0.01),
+    (2, 1, QUTRIT, 0.02), (4, 2, QUTRIT, 0.2), (6, 1, QUTRIT, 1e-3), (10, 4, QUTRIT, 1e-3)])
+def test_depol_sampler_bit_exact(lib, orc, n, k, enc, eps):
+    nt = 300
+    mem = memory_words(n, k, 5)
+    M = 2 * ((1 << n) - 1)
+    act = orc.depol_active(n, k)
+    off = np.concatenate([[0, 0], np.cumsum(act[1:])])  # off[s] = first linear index of slice s
+    with lib.QramContext(n, k, enc, 1e-3, mem, eps=eps) as ctx:
+        cnt, dep = ctx.sample_depol(4242, 17, nt)
+    pos = np.concatenate([[0], np.cumsum(cnt.astype(np.int64))])
+    total = 0
+    for t in range(nt):
+        L, ty = orc.sample_depol(n, k, enc, eps, 4242, 17 + t)
+        assert cnt[t] == len(L), t
+        got = dep[pos[t]:pos[t + 1]]
+        sl = np.searchsorted(off, L, side="right") - 1
+        want = (L - off[sl]).astype(np.uint32) | (sl.astype(np.uint32) << 16) | (ty.astype(np.uint32) << 24)
+        assert np.array_equal(got, want), (t, got[:4], want[:4])
+        assert np.all((got & 0xFFFF) < M)
+        total += len(L)
+    assert total > 0
+
+
+CASES = [
+    # n, k, enc, gamma, eps, general input, trajectories
+    (2, 1, QUBIT, 0.05, 0.05, False, 400), (3, 2, QUBIT, 0.03, 0.03, False, 300),
+    (4, 2, QUBIT, 0.02, 0.01, True, 200), (2, 1, QUBIT, 0.1, 0.0, True, 400),
+    (5, 3, QUBIT, 0.01, 0.005, True, 150),
+    (2, 1, QUTRIT, 0.05, 0.05, False, 400), (3, 1, QUTRIT, 0.03, 0.03, False, 300),
+    (4, 2, QUTRIT, 0.02, 0.01, True, 200), (3, 2, QUTRIT, 0.1, 0.0, True, 300),
+    (6, 2, QUTRIT, 0.005, 0.002, True, 150)]
+
+
+@pytest.mark.parametrize("n,k,enc,gamma,eps,general,nt", CASES)
+def test_depol_general_every_mode(lib, orc, n, k, enc, gamma, eps, general, nt):
+    mem = memory_words(n, k, 90 + n)
+    cin, jin = random_input(n, k, enc, 600 + n + 10 * enc) if general else (None, None)
+    fo, fpo, so, _ = orc.run_many(n, k, enc, gamma, mem, 2024, traj0=5, ntraj=nt, eps=eps, cin=cin, jin=jin)
+    assert so[:, 4].sum() > 0 or eps > 0
+    if eps > 0:
+        assert so[:, 9].sum() > 0  # faults were drawn
+    with lib.QramContext(n, k, enc, gamma, mem, eps=eps, input_amp=cin, input_bus=jin) as ctx:
+        out = {}
+        for mode in (FULL, PRUNED, PLAIN):
+            if mode == PLAIN:
+                f, st = ctx.run_plain(2024, 5, nt)
+            elif mode == FULL:
+                f, st = ctx.run_full(2024, 5, nt)
+            else:
+                f, st = ctx.run_pruned(2024, 5, nt)
+            check_stats(f, st, fo, fpo, so, (n, k, enc, eps, general, mode))
+            out[mode] = (f, st)
+    # pruned evolves only the bad branches plus the reference
+    nb = out[PRUNED][1]["n_bad"].astype(np.int64)
+    has_ref = out[PRUNED][1]["ref_addr"] != 0xFFFFFFFF
+    K2 = (1 << k) if enc == QUBIT else 1
+    assert np.array_equal(out[PRUNED][1]["n_explicit"], ((nb + has_ref) * K2).astype(np.uint32))
+    assert np.all(out[FULL][1]["n_explicit"] == (1 << n) * K2)
+
+
+@pytest.mark.parametrize("n,k,gamma,nt", [(7, 7, 0.01, 100), (8, 8, 2e-3, 40)])
+def test_qubit_wide_bus(lib, orc, n, k, gamma, nt):
+    """Qubit k = 7, 8 (beyond the trajectory kernel's six data bits) run on the
+    plain engine in every mode."""
+    mem = memory_words(n, k, 70 + k)
+    fo, fpo, so, _ = orc.run_many(n, k, QUBIT, gamma, mem, 77, traj0=0, ntraj=nt)
+    assert so[:, 4].sum() > 0
+    with lib.QramContext(n, k, QUBIT, gamma, mem) as ctx:
+        for mode in (FULL, PRUNED):
+            f, st = (ctx.run_full if mode == FULL else ctx.run_pruned)(77, 0, nt)
+            check_stats(f, st, fo, fpo, so, (n, k, mode))
+
+
+def components(out):
+    comps = {}
+    for x, r in enumerate(out["records"]):
+        if not (r[0] >> 25) & 1:
+            continue
+        comps[x] = (int(r[0]) & 0xFFFF, (int(r[0]) >> 16) & 0xFF,
+                    sorted((int(v) & 0xFFFF, int(v) >> 16) for v in r[3:3 + int(r[2])]), out["amp"][x])
+    return comps
+
+
+@pytest.mark.parametrize("enc", [QUBIT, QUTRIT])
+def test_export_depol_general(lib, orc, enc):
+    """Full and plain exports carry every component; the pruned export its
+    explicit ones, which must be the oracle's components of those labels."""
+    n, k, gamma, eps = 3, 2, 0.04, 0.03
+    M = 2 * ((1 << n) - 1)
+    mem = memory_words(n, k, 13)
+    cin, jin = random_input(n, k, enc, 77 + enc)
+    K2 = (1 << k) if enc == QUBIT else 1
+    seen_dep = seen_jump = 0
+    with lib.QramContext(n, k, enc, gamma, mem, eps=eps, input_amp=cin, input_bus=jin) as ctx:
+        for t in range(60):
+            ref = orc.run_traj(n, k, enc, gamma, mem, seed=31, traj=t, export=True, eps=eps, cin=cin, jin=jin)
+            seen_dep += ref["ndep"] > 0
+            seen_jump += ref["njumps"] > 0
+            oc = ref["components"]
+            want = {}
+            for j, x in enumerate(oc["label"]):
+                tree = sorted((q, int(v)) for q, v in enumerate(oc["tree"][j]) if v)
+                want[int(x)] = (int(oc["addr"][j]), int(oc["bus"][j]), tree, oc["amp"][j])
+            scale = max(np.abs(oc["amp"]).max(), 1e-300) if len(oc["amp"]) else 1.0
+            for mode in (FULL, PRUNED, PLAIN):
+                out = ctx.export_state(mode, 31, t)
+                got = components(out)
+                keys = set(got)
+                if mode == PRUNED:  # explicit components: bad addresses and the reference
+                    st = out["st"]
+                    assert keys <= set(want), (t, sorted(keys - set(want)))
+                    assert len({x // K2 for x in keys}) <= int(st["n_bad"]) + 1
+                    if st["ref_addr"] != 0xFFFFFFFF:
+                        assert {x for x in want if x // K2 == st["ref_addr"]} <= keys, t
+                else:
+                    assert sorted(got) == sorted(want), (t, mode, sorted(got)[:6], sorted(want)[:6])
+                for x in keys:
+                    a, b, tree, amp = got[x]
+                    wa, wb, wt, wamp = want[x]
+                    assert (a, b) == (wa, wb), (t, mode, x)
+                    assert tree == wt, (t, mode, x, tree, wt)
+                    assert all(q < M for q, _ in tree)
+                    assert abs(amp - wamp) <= 1e-12 * max(abs(wamp), 1e-3 * scale), (t, mode, x, amp, wamp)
+                assert decode_jlog(out["jlog"]) == sorted(ref["jumps"]), (t, mode)
+                assert abs(out["fid"] - ref["fid"]) <= 1e-12 * max(abs(ref["fid"]), 1e-3), (t, mode)
+    assert seen_dep > 5 and seen_jump > 0
+
+
+@pytest.mark.parametrize("row", [0, 1])
+def test_table4_trajectory_mean(lib, row):
+    g = json.load(open(os.path.join(GOLDEN, "table4_depolarizing.json")))
+    r = g["rows"][row]
+    n, k = g["n"], g["k"]
+    mem = np.array(g["memory_cells"], dtype=np.uint32)
+    nt = 1 << 20
+    with lib.QramContext(n, k, QUBIT, r["gamma"], mem, eps=r["eps"]) as ctx:
+        for mode in (PRUNED, FULL):
+            f, _ = (ctx.run_pruned if mode == PRUNED else ctx.run_full)(99, 0, nt)
+            m, sem = f.mean(), f.std(ddof=1) / np.sqrt(nt)
+            assert abs(m - r["F_rho"]) <= 4 * sem + 0.5e-4, (r["noise"], mode, m, sem, r["F_rho"])

@@ -282,3 +282,17 @@ def test_general_input_trajectory_mean(orc, enc, gamma, eps):
     # no noise: the query is exact
     f0, _, _, _ = orc.run_many(n, k, enc, 0.0, mem, 1, 0, 10, cin=cin, jin=jin)
     assert np.allclose(f0, 1.0, atol=1e-12)
+
+
+def test_invalid_shapes_raise(orc):
+    """Shapes outside the schedule's range (k > n, k > 8) are refused with an
+    error, on every entry, with and without the depolarizing extras."""
+    from paper_2609_34935_amd.inputs import memory_words
+    for n, k in [(2, 7), (3, 4), (9, 9)]:
+        mem = memory_words(n, min(k, 8), 1)
+        with pytest.raises(ValueError):
+            orc.run_many(n, k, 1, 0.01, mem, 1, 0, 4)
+        with pytest.raises(ValueError):
+            orc.run_many(n, k, 0, 0.01, mem, 1, 0, 4, eps=0.01)
+        with pytest.raises(ValueError):
+            orc.sample_depol(n, k, 1, 0.01, 1, 0)
