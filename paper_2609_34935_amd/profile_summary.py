@@ -4,6 +4,7 @@
     python -m paper_2609_34935_amd.profile_summary counters --fetch F.csv --write W.csv [--sq S.csv] \\
         --kernel 'k_evolve<1,' [--wg 512] [--src FILE ...] OUT.json --command "..." [--command "..."]
     python -m paper_2609_34935_amd.profile_summary states S.csv --kernel 'k_evolve<1,' OUT.txt --command "..."
+    python -m paper_2609_34935_amd.profile_summary pmc A.csv [B.csv ...] --kernel KERNEL [--wg 512] --out OUT.txt --command "..."
 
 The counter summary scales FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by
 what the same counters read for the largest plain device copy of the run
@@ -135,6 +136,31 @@ def state_summary(sq, kernel, out, commands):
     print("\n".join(lines))
 
 
+def pmc_summary(paths, kernel, out, commands, wg=None, srcs=None):
+    """Per-launch means of every counter in the given runs (each run one
+    pass of counters) for the named kernel, with the L2 hit rate when both
+    TCC_HIT and TCC_MISS were taken."""
+    srcs = [os.path.abspath(f) for f in srcs] if srcs else None
+    lines = ["rocprofv3 counters, mean per launch of the kernel below", ""]
+    lines += [f"command: {c}" for c in commands]
+    lines += ["", f"kernel: {kernel}", f"workgroup: {wg}", f"kernel_sha256: {kernel_sha256(srcs)}", ""]
+    vals = OrderedDict()
+    for path in paths:
+        ks = [v for v in _per_dispatch(path).values() if _match(v, kernel, wg)]
+        if not ks:
+            raise SystemExit(f"no dispatch of {kernel} in {path}")
+        for c in sorted({c for v in ks for c in v if c not in ("name", "grid", "wg")}):
+            vals[c] = (sum(v.get(c, 0.0) for v in ks) / len(ks), len(ks))
+    for c, (v, n) in vals.items():
+        lines.append(f"{c:<24} {v:>16.4e}   ({n} launches)")
+    hit = next((vals[c][0] for c in vals if c.startswith("TCC_HIT")), None)
+    miss = next((vals[c][0] for c in vals if c.startswith("TCC_MISS")), None)
+    if hit is not None and miss is not None and hit + miss > 0:
+        lines.append(f"{'L2 hit rate':<24} {hit / (hit + miss):>16.4f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -156,9 +182,18 @@ def main():
     w.add_argument("--kernel", required=True)
     w.add_argument("out")
     w.add_argument("--command", action="append", default=[])
+    m = sub.add_parser("pmc")
+    m.add_argument("csv", nargs="+")
+    m.add_argument("--kernel", required=True)
+    m.add_argument("--wg", default=None)
+    m.add_argument("--src", action="append", default=None)
+    m.add_argument("--out", required=True)
+    m.add_argument("--command", action="append", default=[])
     a = ap.parse_args()
     if a.what == "trace":
         trace_summary(a.csv, a.out, a.command)
+    elif a.what == "pmc":
+        pmc_summary(a.csv, a.kernel, a.out, a.command, a.wg, a.src)
     elif a.what == "states":
         state_summary(a.csv, a.kernel, a.out, a.command)
     else:
