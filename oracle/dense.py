@@ -183,25 +183,40 @@ class Machine:
         return rho
 
     # ---- states ----
-    def input_state(self):
-        psi = np.zeros(self.N, dtype=complex)
-        for i in range(1 << self.n):
-            dig = np.zeros(self.ndig, dtype=np.int64)
-            for t in range(self.n):
-                dig[self.A(t)] = (i >> (self.n - 1 - t)) & 1
-            psi[self.index(dig)] = 1.0 / np.sqrt(1 << self.n)
-        return psi
+    def _basis(self, i, j):
+        dig = np.zeros(self.ndig, dtype=np.int64)
+        for t in range(self.n):
+            dig[self.A(t)] = (i >> (self.n - 1 - t)) & 1
+        for b in range(self.k):
+            dig[self.B(b)] = (j >> b) & 1
+        return self.index(dig)
 
-    def ideal_state(self):
+    def input_state(self, cab=None):
+        """sum_ij c_ij |i>|j>|ground> (cab[i, j], normalised here); None: the
+        data-loading input, uniform over addresses with bus word 0."""
         psi = np.zeros(self.N, dtype=complex)
+        if cab is None:
+            for i in range(1 << self.n):
+                psi[self._basis(i, 0)] = 1.0 / np.sqrt(1 << self.n)
+            return psi
+        cab = np.asarray(cab, dtype=complex).reshape(1 << self.n, 1 << self.k)
         for i in range(1 << self.n):
-            dig = np.zeros(self.ndig, dtype=np.int64)
-            for t in range(self.n):
-                dig[self.A(t)] = (i >> (self.n - 1 - t)) & 1
-            for b in range(self.k):
-                dig[self.B(b)] = (self.mem[i] >> b) & 1
-            psi[self.index(dig)] = 1.0 / np.sqrt(1 << self.n)
-        return psi
+            for j in range(1 << self.k):
+                psi[self._basis(i, j)] = cab[i, j]
+        return psi / np.linalg.norm(psi)
+
+    def ideal_state(self, cab=None):
+        """The ideal output sum_ij c_ij |i>|j xor d_i>|ground>."""
+        psi = np.zeros(self.N, dtype=complex)
+        if cab is None:
+            for i in range(1 << self.n):
+                psi[self._basis(i, self.mem[i])] = 1.0 / np.sqrt(1 << self.n)
+            return psi
+        cab = np.asarray(cab, dtype=complex).reshape(1 << self.n, 1 << self.k)
+        for i in range(1 << self.n):
+            for j in range(1 << self.k):
+                psi[self._basis(i, j ^ self.mem[i])] = cab[i, j]
+        return psi / np.linalg.norm(psi)
 
     def excited(self):
         """Boolean table: tree site q excited in basis state x."""
@@ -290,12 +305,13 @@ class Machine:
         return rho
 
 
-def density_fidelity(n, k, enc, mem, gamma, eps=0.0):
+def density_fidelity(n, k, enc, mem, gamma, eps=0.0, cab=None):
     """F_rho = <psi_id| rho |psi_id> of the whole query under damping and
     (eps > 0) depolarizing noise: per slice the gates, then the depolarizing
-    channel on the active sites, then damping on every tree site."""
+    channel on the active sites, then damping on every tree site.  cab: a
+    general input c_ij (None: the data-loading input)."""
     m = Machine(n, k, enc, mem)
-    psi = m.input_state()
+    psi = m.input_state(cab)
     if enc == QUBIT:
         psi = m.wall(psi)
     rho = np.outer(psi, psi.conj())
@@ -307,19 +323,19 @@ def density_fidelity(n, k, enc, mem, gamma, eps=0.0):
             rho = m.damp_rho(rho, gamma)
     if enc == QUBIT:
         rho = m.wall_rho(rho)
-    pid = m.ideal_state()
+    pid = m.ideal_state(cab)
     return float(np.real(pid.conj() @ rho @ pid)), float(np.real(np.trace(rho)))
 
 
-def forced_evolution(n, k, enc, mem, gamma, jumps, stop_before_wall=True, machine=None, faults=()):
+def forced_evolution(n, k, enc, mem, gamma, jumps, stop_before_wall=True, machine=None, faults=(), cab=None):
     """State vector under a forced sequence of joint outcomes.
 
     jumps: list of (slice, site, level).  Every other layer applies K_empty.
     faults: depolarizing faults (slice, site, a, b), applied after the gates
-    of their slice and before its damping layer.
+    of their slice and before its damping layer.  cab: a general input.
     Returns the final state (before the second wall unless told otherwise)."""
     m = machine if machine is not None else Machine(n, k, enc, mem)
-    psi = m.input_state()
+    psi = m.input_state(cab)
     if enc == QUBIT:
         psi = m.wall(psi)
     byslice = {}

@@ -68,13 +68,13 @@ def lib():
             C.c_int, C.c_int, C.c_int, C.c_double, u32p, C.c_uint64, u32p,
             C.c_int, C.c_int, f64p, f64p, i32p]
         L.orc_run_traj_ex.argtypes = [
-            C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, u32p, f64p, u32p,
+            C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, u32p, f64p, u32p, f64p, C.c_int,
             C.c_uint64, C.c_uint32, u32p, C.c_int, f64p, C.c_double,
             C.c_int, u32p, u32p, u8p, C.c_int, C.c_int, f64p, i32p,
             i32p, i32p, i32p, C.c_int, i32p,
             u32p, u32p, f64p, u8p, u32p, C.c_int]
         L.orc_run_many_ex.argtypes = [
-            C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, u32p, f64p, u32p,
+            C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, u32p, f64p, u32p, f64p, C.c_int,
             C.c_uint64, C.c_uint32, u32p, C.c_int, C.c_int, f64p, f64p, i32p]
         L.orc_sample_depol.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_uint64, C.c_uint32,
                                        u32p, u8p, C.c_int]
@@ -155,6 +155,17 @@ def _cin(cin, n):
     return out
 
 
+def _cab(cab, n, k):
+    """c_ij of every (address, bus word), address-major, as (re, im) pairs."""
+    if cab is None:
+        return None
+    c = np.asarray(cab, dtype=np.complex128).reshape(-1)
+    assert c.shape == ((1 << n) << k,)
+    out = np.empty(2 * len(c))
+    out[0::2], out[1::2] = c.real, c.imag
+    return out
+
+
 def _jin(jin, n):
     if jin is None:
         return None
@@ -165,11 +176,13 @@ def _jin(jin, n):
 
 def run_traj(n, k, enc, gamma, mem, seed=0, traj=0, forced_L=None,
              forced_uaux=None, forced_ufin=-1.0, check_counts=False,
-             export=False, jcap=4096, eps=0.0, cin=None, jin=None, forced_dep=None):
+             export=False, jcap=4096, eps=0.0, cin=None, jin=None, forced_dep=None, cab=None, wmax=-1):
     """One trajectory of the full (unpruned) evolution.
 
     eps: depolarizing strength; cin / jin: input amplitude and bus word of
-    every address (None: uniform, 0); forced_dep: list of faults (slice,
+    every address (None: uniform, 0); or cab: amplitude c_ij of every
+    (address i, bus word j), shape (2^n, 2^k); wmax: Hamming truncation of
+    the predicted good branches (-1: none); forced_dep: list of faults (slice,
     site, a, b), the operator Z^b X^a, replacing the depolarizing draws.  Returns a dict with fid, fid_pre, w_ground,
     w_total, ncand, nbad, ref, nexplicit, njumps, first_jump, ref_survived,
     q_ground, max_exc, ndep, the jump log and, if export, the final pre-wall
@@ -177,7 +190,7 @@ def run_traj(n, k, enc, gamma, mem, seed=0, traj=0, forced_L=None,
     mem = _mem(mem)
     T = 6 * n + 2 * k
     M = 2 * ((1 << n) - 1)
-    E = (1 << n) * ((1 << k) if enc == QUBIT else 1)
+    E = (1 << n) * ((1 << k) if enc == QUBIT or cab is not None else 1)
     rd = np.zeros(NRD)
     ri = np.zeros(NRI, dtype=np.int32)
     js = np.zeros(jcap, dtype=np.int32)
@@ -195,7 +208,7 @@ def run_traj(n, k, enc, gamma, mem, seed=0, traj=0, forced_L=None,
     eamp = np.zeros(2 * max(cap, 1))
     etree = np.zeros(max(cap, 1) * M, dtype=np.uint8)
     elab = np.zeros(max(cap, 1), dtype=np.uint32)
-    cinp, jinp = _cin(cin, n), _jin(jin, n)
+    cinp, jinp, cabp = _cin(cin, n), _jin(jin, n), _cab(cab, n, k)
     dS = dQ = dT = None
     if forced_dep is not None:  # list of (slice, site, a, b), slices ascending
         fd = sorted(forced_dep, key=lambda f: f[0])
@@ -203,7 +216,8 @@ def run_traj(n, k, enc, gamma, mem, seed=0, traj=0, forced_L=None,
         dQ = np.array([f[1] for f in fd], dtype=np.uint32)
         dT = np.array([f[2] | (f[3] << 2) for f in fd], dtype=np.uint8)
     ne = lib().orc_run_traj_ex(
-        n, k, enc, gamma, eps, _p(mem, C.c_uint32), _p(cinp, C.c_double), _p(jinp, C.c_uint32), seed, traj,
+        n, k, enc, gamma, eps, _p(mem, C.c_uint32), _p(cinp, C.c_double), _p(jinp, C.c_uint32),
+        _p(cabp, C.c_double), int(wmax), seed, traj,
         _p(fL, C.c_uint32) if fL is not None else None,
         len(fL) if fL is not None else 0,
         _p(fU, C.c_double) if fU is not None else None, forced_ufin,
@@ -267,9 +281,10 @@ def run_batch(n, k, enc, gamma, mem, seed, traj0, ntraj, nthreads=0):
 
 
 def run_many(n, k, enc, gamma, mem, seed, traj0=0, ntraj=None, idx=None, nthreads=0, eps=0.0, cin=None,
-             jin=None):
+             jin=None, cab=None, wmax=-1):
     """Trajectories traj0.. (or the listed indices) with depolarizing
-    strength eps and a general input; returns (fid, fid_pre, stats, threads)."""
+    strength eps and a general input (cin/jin, or cab as in run_traj) and
+    the truncation wmax; returns (fid, fid_pre, stats, threads)."""
     mem = _mem(mem)
     if idx is not None:
         idx = np.ascontiguousarray(idx, dtype=np.uint32)
@@ -277,9 +292,10 @@ def run_many(n, k, enc, gamma, mem, seed, traj0=0, ntraj=None, idx=None, nthread
     fid = np.zeros(ntraj)
     fpre = np.zeros(ntraj)
     ri = np.zeros(max(ntraj, 1) * NRI, dtype=np.int32)
-    cinp, jinp = _cin(cin, n), _jin(jin, n)
+    cinp, jinp, cabp = _cin(cin, n), _jin(jin, n), _cab(cab, n, k)
     used = lib().orc_run_many_ex(n, k, enc, gamma, eps, _p(mem, C.c_uint32), _p(cinp, C.c_double),
-                                 _p(jinp, C.c_uint32), seed, traj0, _p(idx, C.c_uint32), ntraj, nthreads,
+                                 _p(jinp, C.c_uint32), _p(cabp, C.c_double), int(wmax), seed, traj0,
+                                 _p(idx, C.c_uint32), ntraj, nthreads,
                                  _p(fid, C.c_double), _p(fpre, C.c_double), _p(ri, C.c_int))
     if used < 0:
         raise ValueError("oracle error")

@@ -183,6 +183,11 @@ typedef struct {
   uint64_t dep_off[513];  /* linear index of slice s's first active position */
   double complex *cin;    /* normalised input amplitude of each address */
   uint32_t *jin;          /* input bus word of each address */
+  double complex *cab;    /* or: normalised amplitude of each (address, bus
+                             word) pair, 2^k per address */
+  uint8_t *single;        /* cab: the address holds exactly one bus word */
+  int wmax;               /* output words of the predicted good branches kept
+                             up to this Hamming weight (-1: all) */
   int nev[512];
   int ev_type[512][ORC_MAXEV];
   int ev_arg[512][ORC_MAXEV];
@@ -253,6 +258,9 @@ static int cfg_init(orc_cfg *c, int n, int k, int enc, double gamma,
   c->eps = 0.0;
   c->cin = NULL;
   c->jin = NULL;
+  c->cab = NULL;
+  c->single = NULL;
+  c->wmax = -1;
   memset(c->nact, 0, sizeof(c->nact));
   memset(c->dep_off, 0, sizeof(c->dep_off));
   return 0;
@@ -268,13 +276,22 @@ static int active_layers(const orc_cfg *c, int s) {
   return l;
 }
 
-/* Depolarizing strength and general input (cin: 2 doubles per address, or
- * NULL; jin: bus word per address, or NULL).  Returns < 0 on bad input. */
+/* Depolarizing strength and general input: cin (2 doubles per address) and
+ * jin (bus word per address), or cab (2 doubles per (address, bus word),
+ * address-major), or none (the data-loading input).  wmax >= 0 truncates
+ * the predicted good branches' output words at that Hamming weight from
+ * their ideal word (qubit encoding, one bus word per address).  Returns < 0
+ * on bad input. */
 static int cfg_extras(orc_cfg *c, double eps, const double *cin,
-                      const uint32_t *jin) {
+                      const uint32_t *jin, const double *cab, int wmax) {
   if (!(eps >= 0.0 && eps < 1.0))
     return -1;
+  if (cab && (cin || jin))
+    return -1;
+  if (wmax < -1 || wmax > c->k)
+    return -1;
   c->eps = eps;
+  c->wmax = wmax == c->k ? -1 : wmax;
   orc_thresholds(eps, c->Gp);
   uint64_t off = 0;
   for (int s = 1; s < c->T; ++s) {
@@ -302,6 +319,32 @@ static int cfg_extras(orc_cfg *c, double eps, const double *cin,
     for (int i = 0; i < c->D; ++i)
       c->jin[i] = jin[i] & (uint32_t)(c->K2 - 1);
   }
+  if (cab) {
+    size_t na = (size_t)c->D * c->K2;
+    double norm = 0.0;
+    c->cab = (double complex *)malloc(sizeof(double complex) * na);
+    c->single = (uint8_t *)malloc(c->D);
+    for (size_t x = 0; x < na; ++x) {
+      c->cab[x] = cab[2 * x] + I * cab[2 * x + 1];
+      norm += cab[2 * x] * cab[2 * x] + cab[2 * x + 1] * cab[2 * x + 1];
+    }
+    if (!(norm > 0.0))
+      return -1;
+    for (size_t x = 0; x < na; ++x)
+      c->cab[x] /= sqrt(norm);
+    for (int i = 0; i < c->D; ++i) {
+      int m = 0;
+      for (int j = 0; j < c->K2; ++j)
+        m += c->cab[(size_t)i * c->K2 + j] != 0.0;
+      c->single[i] = m == 1;
+      /* truncation is defined for one bus word per address (Theorem 2) */
+      if (m > 1 && c->wmax >= 0)
+        return -1;
+    }
+    /* the qutrit encoding carries one component per (address, bus word) */
+    if (c->enc == ORC_QUTRIT)
+      c->E = c->D * c->K2;
+  }
   return 0;
 }
 
@@ -310,6 +353,8 @@ static void cfg_free(orc_cfg *c) {
     return;
   free(c->cin);
   free(c->jin);
+  free(c->cab);
+  free(c->single);
   free(c);
 }
 
@@ -319,6 +364,33 @@ static double complex in_amp(const orc_cfg *c, uint32_t i) {
 
 static uint32_t in_bus(const orc_cfg *c, uint32_t i) {
   return c->jin ? c->jin[i] : 0u;
+}
+
+/* Amplitude of (address i, bus word j) in the input. */
+static double complex in_ab(const orc_cfg *c, uint32_t i, uint32_t j) {
+  if (c->cab)
+    return c->cab[(size_t)i * c->K2 + j];
+  return j == in_bus(c, i) ? in_amp(c, i) : 0.0;
+}
+
+/* Does the input hold address i? */
+static int present(const orc_cfg *c, uint32_t i) {
+  if (!c->cab)
+    return in_amp(c, i) != 0.0;
+  for (int j = 0; j < c->K2; ++j)
+    if (c->cab[(size_t)i * c->K2 + j] != 0.0)
+      return 1;
+  return 0;
+}
+
+/* The single bus word of address i (cab with one bus word, or cin/jin). */
+static uint32_t single_bus(const orc_cfg *c, uint32_t i) {
+  if (!c->cab)
+    return in_bus(c, i);
+  for (int j = 0; j < c->K2; ++j)
+    if (c->cab[(size_t)i * c->K2 + j] != 0.0)
+      return (uint32_t)j;
+  return 0u;
 }
 
 /* Export the event list of slice s (for schedule tests). */
@@ -441,7 +513,7 @@ int orc_sample_depol(int n, int k, int enc, double eps, uint64_t seed,
   orc_cfg *c = (orc_cfg *)calloc(1, sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, enc, 0.0, zero_mem);
   if (!rc)
-    rc = cfg_extras(c, eps, NULL, NULL);
+    rc = cfg_extras(c, eps, NULL, NULL, NULL, -1);
   if (rc) {
     cfg_free(c);
     return rc;
@@ -457,7 +529,7 @@ int orc_depol_active(int n, int k, int *nact) {
   orc_cfg *c = (orc_cfg *)calloc(1, sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, ORC_QUBIT, 0.0, zero_mem);
   if (!rc)
-    rc = cfg_extras(c, 0.0, NULL, NULL);
+    rc = cfg_extras(c, 0.0, NULL, NULL, NULL, -1);
   if (rc) {
     cfg_free(c);
     return rc;
@@ -579,28 +651,52 @@ static void state_free(orc_state *st) {
   free(st->tree);
 }
 
-/* The data-loading input with uniform address amplitudes and bus word 0.
- * For the qubit encoding the first Hadamard wall acts on the noiseless bus
- * before any tree gate touches it, so it is applied here. */
+/* The input state after the first wall.  The data-loading input has
+ * uniform address amplitudes and bus word 0; a general input sum_i c_i
+ * |i>|j_i> or sum_ij c_ij |i>|j> (Sec. IV D).  For the qubit encoding the
+ * first Hadamard wall acts on the noiseless bus before any tree gate touches
+ * it, so it is applied here: component (i, beta) starts with amplitude
+ * 2^(-k/2) sum_j c_ij (-1)^(beta . j) (j ascending), alive when the input
+ * holds address i.  The qutrit encoding carries the bus word in the
+ * computational basis: one component per address (bus word j_i), or with
+ * c_ij one per (address, bus word), alive when its amplitude is nonzero. */
 static void state_init(const orc_cfg *c, orc_state *st) {
   double wall = c->enc == ORC_QUBIT ? 1.0 / sqrt((double)c->K2) : 1.0;
   for (int x = 0; x < c->E; ++x) {
-    uint32_t i = c->enc == ORC_QUBIT ? (uint32_t)x >> c->k : (uint32_t)x;
-    uint32_t beta = c->enc == ORC_QUBIT ? (uint32_t)x & (uint32_t)(c->K2 - 1) : 0;
-    double complex ci = in_amp(c, i);
-    st->addr[x] = i;
-    st->nexc[x] = 0;
     memset(st->tree + (size_t)x * c->M, 0, c->M);
+    st->nexc[x] = 0;
     if (c->enc == ORC_QUBIT) {
-      /* the first wall on |j_i>: sum_beta (-1)^(beta . j_i) |beta> / sqrt(K2) */
-      int par = __builtin_popcount(beta & in_bus(c, i)) & 1;
+      uint32_t i = (uint32_t)x >> c->k;
+      uint32_t beta = (uint32_t)x & (uint32_t)(c->K2 - 1);
+      double complex v = 0.0;
+      if (c->cab) {
+        for (int j = 0; j < c->K2; ++j) {
+          double complex cj = c->cab[(size_t)i * c->K2 + j];
+          v += (__builtin_popcount(beta & (uint32_t)j) & 1) ? -cj : cj;
+        }
+      } else {
+        /* the first wall on |j_i>: sum_beta (-1)^(beta . j_i) |beta> */
+        double complex ci = in_amp(c, i);
+        v = (__builtin_popcount(beta & in_bus(c, i)) & 1) ? -ci : ci;
+      }
+      st->addr[x] = i;
       st->bus[x] = beta;
-      st->amp[x] = (par ? -ci : ci) * wall;
+      st->amp[x] = v * wall;
+      st->alive[x] = present(c, i);
+    } else if (c->cab) {
+      uint32_t i = (uint32_t)x / (uint32_t)c->K2;
+      uint32_t j = (uint32_t)x % (uint32_t)c->K2;
+      st->addr[x] = i;
+      st->bus[x] = j;
+      st->amp[x] = c->cab[x];
+      st->alive[x] = c->cab[x] != 0.0;
     } else {
-      st->bus[x] = in_bus(c, i);
+      double complex ci = in_amp(c, (uint32_t)x);
+      st->addr[x] = (uint32_t)x;
+      st->bus[x] = in_bus(c, (uint32_t)x);
       st->amp[x] = ci;
+      st->alive[x] = ci != 0.0;
     }
-    st->alive[x] = ci != 0.0;
   }
 }
 
@@ -938,10 +1034,11 @@ static int run_traj(const orc_cfg *c, uint64_t seed, uint32_t traj,
   }
   uint8_t *bad = (uint8_t *)malloc(c->D);
   int nbad = classify_all(c, L, ncand, dsite, ndep, bad);
-  /* the reference: the smallest good address the input holds */
+  /* the reference: the smallest good address the input holds (with a
+   * c_ij input, the smallest holding one bus word: a single branch) */
   int ref = -1;
   for (int i = 0; i < c->D; ++i)
-    if (!bad[i] && in_amp(c, (uint32_t)i) != 0.0) {
+    if (!bad[i] && present(c, (uint32_t)i) && (!c->cab || c->single[i])) {
       ref = i;
       break;
     }
@@ -986,56 +1083,56 @@ static int run_traj(const orc_cfg *c, uint64_t seed, uint32_t traj,
   free(jlev);
 
   /* End of the query: wall 2 (qubit), tree measurement, fidelity.  The
-   * ideal output is sum_i c_i |i>|j_i xor d_i>|ground>. */
+   * ideal output is sum_ij c_ij |i>|j xor d_i>|ground>.  Ground components
+   * of one address are grouped by bus word (after the wall, qubit); groups
+   * with an excited tree are orthogonal to it and to each other.  With wmax,
+   * the output words of the predicted good branches (good addresses other
+   * than the reference) farther than wmax bit flips from their ideal word
+   * are dropped (Sec. V). */
   double complex overlap = 0.0;
   nsum wg = {0, 0}, wt = {0, 0};
-  if (c->enc == ORC_QUBIT) {
+  {
     int K2 = c->K2;
+    uint32_t kmask = (uint32_t)((1 << c->k) - 1);
+    int per = c->E / c->D; /* components per address */
     double complex *grp = (double complex *)malloc(sizeof(double complex) * K2);
-    double h = 1.0 / sqrt((double)K2);
+    double h = c->enc == ORC_QUBIT ? 1.0 / sqrt((double)K2) : 1.0;
     for (int i = 0; i < c->D; ++i) {
-      /* components of address i with the ground tree: Hadamard wall over
-       * the bus word within the group */
       int any = 0;
-      for (int beta = 0; beta < K2; ++beta)
-        grp[beta] = 0.0;
-      for (int x = i * K2; x < (i + 1) * K2; ++x) {
-        if (!st->alive[x] || st->nexc[x] != 0)
+      for (int w = 0; w < K2; ++w)
+        grp[w] = 0.0;
+      for (int x = i * per; x < (i + 1) * per; ++x) {
+        if (!st->alive[x])
           continue;
-        grp[st->bus[x]] += st->amp[x];
+        if (st->nexc[x] != 0) {
+          nadd(&wt, abs2(st->amp[x]));
+          continue;
+        }
+        grp[st->bus[x] & kmask] += st->amp[x];
         any = 1;
       }
       if (!any)
         continue;
+      int trunc = c->wmax >= 0 && c->enc == ORC_QUBIT && !bad[i] && i != ref &&
+                  present(c, (uint32_t)i);
+      uint32_t want = (single_bus(c, (uint32_t)i) ^ c->mem[i]) & kmask;
       for (int cw = 0; cw < K2; ++cw) {
         double complex v = 0.0;
-        for (int beta = 0; beta < K2; ++beta)
-          v += (__builtin_popcount((unsigned)(beta & cw)) & 1) ? -grp[beta]
-                                                               : grp[beta];
-        v *= h;
+        if (c->enc == ORC_QUBIT) {
+          for (int beta = 0; beta < K2; ++beta)
+            v += (__builtin_popcount((unsigned)(beta & cw)) & 1) ? -grp[beta]
+                                                                 : grp[beta];
+          v *= h;
+        } else {
+          v = grp[cw];
+        }
+        if (trunc && __builtin_popcount((unsigned)cw ^ want) > c->wmax)
+          continue;
         nadd(&wg, abs2(v));
-        if ((uint32_t)cw == ((in_bus(c, (uint32_t)i) ^ c->mem[i]) & (uint32_t)(K2 - 1)))
-          overlap += conj(in_amp(c, (uint32_t)i)) * v;
+        overlap += conj(in_ab(c, (uint32_t)i, ((uint32_t)cw ^ c->mem[i]) & kmask)) * v;
       }
     }
     free(grp);
-    /* groups with an excited tree: the wall is orthogonal on each group */
-    for (int x = 0; x < c->E; ++x)
-      if (st->alive[x] && st->nexc[x] != 0)
-        nadd(&wt, abs2(st->amp[x]));
-  } else {
-    for (int x = 0; x < c->E; ++x) {
-      if (!st->alive[x])
-        continue;
-      if (st->nexc[x] == 0) {
-        nadd(&wg, abs2(st->amp[x]));
-        uint32_t i = st->addr[x];
-        if (st->bus[x] == ((in_bus(c, i) ^ c->mem[i]) & (uint32_t)((1 << c->k) - 1)))
-          overlap += conj(in_amp(c, i)) * st->amp[x];
-      } else {
-        nadd(&wt, abs2(st->amp[x]));
-      }
-    }
   }
   double w_ground = nval(&wg);
   double w_total = w_ground + nval(&wt);
@@ -1116,13 +1213,17 @@ static void pack_result(const orc_result *r, double *rd, int *ri) {
  */
 /*
  * The same with depolarizing faults of strength eps and a general input
- * (cin: 2 doubles per address or NULL; jin: bus word per address or NULL).
+ * (cin: 2 doubles per address or NULL; jin: bus word per address or NULL;
+ * or cab: 2 doubles per (address, bus word), address-major, or NULL), and
+ * the truncation wmax of the predicted good branches (-1: none).  With cab
+ * the qutrit components are labelled address * 2^k + bus word.
  * dep_forced = 1 replaces the depolarizing draws by the faults
  * (dep_slice, dep_site, dep_type) [ndep], slices ascending, any site, types
  * a | b << 2.
  */
 int orc_run_traj_ex(int n, int k, int enc, double gamma, double eps,
                     const uint32_t *mem, const double *cin, const uint32_t *jin,
+                    const double *cab, int wmax,
                     uint64_t seed, uint32_t traj, const uint32_t *forced_L,
                     int forced_ncand, const double *forced_uaux,
                     double forced_ufin, int dep_forced,
@@ -1135,7 +1236,7 @@ int orc_run_traj_ex(int n, int k, int enc, double gamma, double eps,
   orc_cfg *c = (orc_cfg *)calloc(1, sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, enc, gamma, mem);
   if (!rc)
-    rc = cfg_extras(c, eps, cin, jin);
+    rc = cfg_extras(c, eps, cin, jin, cab, wmax);
   if (rc) {
     cfg_free(c);
     return rc;
@@ -1190,7 +1291,7 @@ int orc_run_traj(int n, int k, int enc, double gamma, const uint32_t *mem,
                  int *jslice, int *jsite, int *jlevel, int jcap, int *njl,
                  uint32_t *exp_addr, uint32_t *exp_bus, double *exp_amp,
                  uint8_t *exp_tree, uint32_t *exp_label, int exp_cap) {
-  return orc_run_traj_ex(n, k, enc, gamma, 0.0, mem, NULL, NULL, seed, traj,
+  return orc_run_traj_ex(n, k, enc, gamma, 0.0, mem, NULL, NULL, NULL, -1, seed, traj,
                          forced_L, forced_ncand, forced_uaux, forced_ufin, 0,
                          NULL, NULL, NULL, 0, check_counts, rd, ri, jslice, jsite,
                          jlevel, jcap, njl, exp_addr, exp_bus, exp_amp,
@@ -1286,44 +1387,44 @@ int orc_layer_masks(int n, int k, int enc, double gamma, const uint32_t *mem,
  */
 static int run_many(int n, int k, int enc, double gamma, double eps,
                     const uint32_t *mem, const double *cin, const uint32_t *jin,
-                    uint64_t seed, uint32_t traj0, const uint32_t *idx,
-                    int ntraj, int nthreads, double *fid, double *fid_pre,
-                    int *ri);
+                    const double *cab, int wmax, uint64_t seed, uint32_t traj0,
+                    const uint32_t *idx, int ntraj, int nthreads, double *fid,
+                    double *fid_pre, int *ri);
 
 int orc_run_batch(int n, int k, int enc, double gamma, const uint32_t *mem,
                   uint64_t seed, uint32_t traj0, int ntraj, int nthreads,
                   double *fid, double *fid_pre, int *ri) {
-  return run_many(n, k, enc, gamma, 0.0, mem, NULL, NULL, seed, traj0, NULL,
-                  ntraj, nthreads, fid, fid_pre, ri);
+  return run_many(n, k, enc, gamma, 0.0, mem, NULL, NULL, NULL, -1, seed,
+                  traj0, NULL, ntraj, nthreads, fid, fid_pre, ri);
 }
 
 int orc_run_indices(int n, int k, int enc, double gamma, const uint32_t *mem,
                     uint64_t seed, const uint32_t *idx, int nidx, int nthreads,
                     double *fid, double *fid_pre, int *ri) {
-  return run_many(n, k, enc, gamma, 0.0, mem, NULL, NULL, seed, 0, idx, nidx,
-                  nthreads, fid, fid_pre, ri);
+  return run_many(n, k, enc, gamma, 0.0, mem, NULL, NULL, NULL, -1, seed, 0,
+                  idx, nidx, nthreads, fid, fid_pre, ri);
 }
 
 /* Batches with depolarizing faults and a general input (see
  * orc_run_traj_ex); idx may be NULL (then traj0 .. traj0+ntraj-1). */
 int orc_run_many_ex(int n, int k, int enc, double gamma, double eps,
                     const uint32_t *mem, const double *cin, const uint32_t *jin,
-                    uint64_t seed, uint32_t traj0, const uint32_t *idx,
-                    int ntraj, int nthreads, double *fid, double *fid_pre,
-                    int *ri) {
-  return run_many(n, k, enc, gamma, eps, mem, cin, jin, seed, traj0, idx,
-                  ntraj, nthreads, fid, fid_pre, ri);
+                    const double *cab, int wmax, uint64_t seed, uint32_t traj0,
+                    const uint32_t *idx, int ntraj, int nthreads, double *fid,
+                    double *fid_pre, int *ri) {
+  return run_many(n, k, enc, gamma, eps, mem, cin, jin, cab, wmax, seed, traj0,
+                  idx, ntraj, nthreads, fid, fid_pre, ri);
 }
 
 static int run_many(int n, int k, int enc, double gamma, double eps,
                     const uint32_t *mem, const double *cin, const uint32_t *jin,
-                    uint64_t seed, uint32_t traj0, const uint32_t *idx,
-                    int ntraj, int nthreads, double *fid, double *fid_pre,
-                    int *ri) {
+                    const double *cab, int wmax, uint64_t seed, uint32_t traj0,
+                    const uint32_t *idx, int ntraj, int nthreads, double *fid,
+                    double *fid_pre, int *ri) {
   orc_cfg *c = (orc_cfg *)calloc(1, sizeof(orc_cfg));
   int rc = cfg_init(c, n, k, enc, gamma, mem);
   if (!rc)
-    rc = cfg_extras(c, eps, cin, jin);
+    rc = cfg_extras(c, eps, cin, jin, cab, wmax);
   if (rc) {
     cfg_free(c);
     return rc;
