@@ -120,9 +120,27 @@ qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
  *                absent (no branch).
  *   input_bus    [2^n] bus word of each address (one column per address);
  *                NULL = 0.  The ideal output is sum_i c_i |i>|j_i xor d_i>.
+ *   input_ab     [2 * 2^n * 2^k] amplitude (re, im) of every (address i,
+ *                bus word j) pair, address-major (index i * 2^k + j),
+ *                normalised by the library; NULL = none.  Excludes
+ *                input_amp and input_bus.  The ideal output is
+ *                sum_ij c_ij |i>|j xor d_i> (the random branch sets of
+ *                Sec. VI draw such pairs).  The qutrit encoding then carries
+ *                one component per pair.  The reference (Alg. 1) is the
+ *                smallest good address holding exactly one bus word; good
+ *                addresses holding several are predicted bus word by bus
+ *                word from it (Theorem 3: O(k 2^k) each, Table 2).
+ *   truncate     nonzero: Hamming truncation at w_max (Sec. V): the output
+ *                words of every good address but the reference that lie
+ *                more than w_max bit flips from its ideal word are dropped
+ *                before the tree measurement (qubit encoding; no effect on
+ *                the qutrit, whose good branches end in the ideal word).
+ *                Every mode computes the same truncated quantity.  Needs
+ *                one bus word per address (else QRAM_E_INVAL) and
+ *                0 <= w_max <= k.
  * The qubit encoding accepts k_data up to 8 here (n + k <= 16).  Contexts
- * with eps > 0, a general input, or qubit k > 6 run every mode on the plain
- * engine: QRAM_MODE_FULL as QRAM_MODE_PLAIN, QRAM_MODE_PRUNED as Alg. 1 on
+ * with eps > 0, a general input, truncation, or qubit k > 6 run every mode
+ * on the plain engine: QRAM_MODE_FULL as QRAM_MODE_PLAIN, QRAM_MODE_PRUNED as Alg. 1 on
  * explicit site lists (bad branches plus the reference explicit, the good
  * branches carried by the reference's weights and final state).
  */
@@ -134,6 +152,8 @@ typedef struct {
   const uint32_t *memory_bits;  /* host, 2^n words; copied */
   const double *input_amp;      /* host, 2 * 2^n doubles, or NULL; copied */
   const uint32_t *input_bus;    /* host, 2^n words, or NULL; copied */
+  const double *input_ab;       /* host, 2 * 2^n * 2^k doubles, or NULL; copied */
+  int truncate, w_max;          /* Hamming truncation (truncate = 0: none) */
 } qram_params;
 
 qram_status qram_create_ex(const qram_params *params, qram_ctx **out);

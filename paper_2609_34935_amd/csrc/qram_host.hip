@@ -51,6 +51,8 @@ struct qram_ctx {
   bool general = false;   // depolarizing noise or a general input: the plain engine runs every mode
   double *dcin = nullptr;  // general input amplitudes (device)
   uint32_t *djin = nullptr;
+  double *dcab = nullptr, *dcamp = nullptr;  // pair amplitudes, component amplitudes
+  uint8_t *daflag = nullptr;
   uint32_t *dep = nullptr, *ndep = nullptr;  // depolarizing faults of a batch
   uint32_t dep_cap = 0;
   int T = 0, M = 0, D = 0, K2 = 1, Emax = 0, lmax = 0, emax = 0, rec = 0;
@@ -895,6 +897,17 @@ qram_status qram_create_ex(const qram_params *p, qram_ctx **out) {
     const double f = 1.0 / std::sqrt(norm);
     for (double &v : cin) v *= f;
   }
+  std::vector<double> cab;  // normalised c_ij of every (address, bus word) pair
+  if (p->input_ab) {
+    if (p->input_amp || p->input_bus) return fail(nullptr, QRAM_E_INVAL, "input_ab excludes input_amp and input_bus");
+    double norm = 0.0;
+    cab.assign(p->input_ab, p->input_ab + 2 * (((size_t)1 << n_addr) << k_data));
+    for (double v : cab) norm += v * v;
+    if (!(norm > 0.0) || !std::isfinite(norm)) return fail(nullptr, QRAM_E_INVAL, "input amplitudes must be finite and not all zero");
+    const double f = 1.0 / std::sqrt(norm);
+    for (double &v : cab) v *= f;
+  }
+  if (p->truncate && (p->w_max < 0 || p->w_max > k_data)) return fail(nullptr, QRAM_E_INVAL, "w_max must lie in 0..k");
   qram_ctx *c = new (std::nothrow) qram_ctx();
   if (!c) return fail(nullptr, QRAM_E_NOMEM, "host allocation failed");
   c->n = n_addr;
@@ -904,11 +917,14 @@ qram_status qram_create_ex(const qram_params *p, qram_ctx **out) {
   c->eps = eps;
   // the trajectory kernel covers damping on the data-loading input with up
   // to six qubit data bits; everything else runs on the plain engine
-  c->general = eps > 0.0 || p->input_amp || p->input_bus || (c->enc == QUBIT && k_data > 6);
+  c->general = eps > 0.0 || p->input_amp || p->input_bus || p->input_ab || p->truncate ||
+               (c->enc == QUBIT && k_data > 6);
   c->T = 6 * n_addr + 2 * k_data;
   c->M = 2 * ((1 << n_addr) - 1);
   c->D = 1 << n_addr;
-  c->K2 = c->enc == QUBIT ? (1 << k_data) : 1;
+  // qubit: one component per (address, bus word after the wall); qutrit: one
+  // per address, or per (address, bus word) pair with a pair input
+  c->K2 = (c->enc == QUBIT || !cab.empty()) ? (1 << k_data) : 1;
   c->Emax = c->D * c->K2;
   // excitations per component: the CNOT copies are the only gates that
   // create them in the qubit circuit (<= 2n, plus k bus bits); the qutrit
@@ -930,7 +946,13 @@ qram_status qram_create_ex(const qram_params *p, qram_ctx **out) {
   if (!build_tables(c, why)) {
     delete c;
     return fail(nullptr, QRAM_E_INVAL, "schedule: " + why);
-  }
+  }  // plain engine records: an X-type depolarizing fault on an idle site adds
+  // one excitation to every branch (a stray), so the lists hold up to the
+  // trajectory's fault capacity beyond lmax
+  if (c->eps > 0.0)
+    c->prec = (int)((std::min<uint32_t>((uint32_t)(c->lmax + PLAIN_EXTRA) + dep_capacity(c), (uint32_t)(c->M + c->lmax)) +
+                     2u + 1u) & ~1u);
+
   auto bail = [&](qram_status st) {
     std::string m = c->err;
     qram_destroy(c);
@@ -1026,6 +1048,65 @@ qram_status qram_create_ex(const qram_params *p, qram_ctx **out) {
       return bail(fail(c, QRAM_E_DEVICE, "input upload failed"));
     c->htab.jin = c->djin;
   }
+  c->htab.trunc_w = (p->truncate && p->w_max < k_data) ? p->w_max : -1;
+  if (!cab.empty()) {
+    // per address: presence, one bus word (its amplitude and word go to
+    // cin/jin); per component: the amplitude after the first wall
+    const int K = 1 << k_data;
+    std::vector<double> cs(2 * (size_t)c->D, 0.0);
+    std::vector<uint32_t> js(c->D, 0u);
+    std::vector<uint8_t> af(c->D, 0);
+    for (int i = 0; i < c->D; ++i) {
+      int m = 0, jl = 0;
+      for (int j = 0; j < K; ++j) {
+        const size_t x = (size_t)i * K + j;
+        if (cab[2 * x] != 0.0 || cab[2 * x + 1] != 0.0) {
+          ++m;
+          jl = j;
+        }
+      }
+      af[i] = (uint8_t)((m > 0 ? 1 : 0) | (m == 1 ? 2 : 0));
+      if (m == 1) {
+        cs[2 * i] = cab[2 * ((size_t)i * K + jl)];
+        cs[2 * i + 1] = cab[2 * ((size_t)i * K + jl) + 1];
+        js[i] = (uint32_t)jl;
+      }
+      if (m > 1 && c->htab.trunc_w >= 0) return bail(fail(c, QRAM_E_INVAL, "truncation needs one bus word per address"));
+    }
+    std::vector<double> ca(2 * (size_t)c->D * c->K2);
+    if (c->enc == QUBIT) {  // 2^(-k/2) sum_j c_ij (-1)^(beta . j), j ascending
+      const double h = 1.0 / std::sqrt((double)K);
+      for (int i = 0; i < c->D; ++i)
+        for (int b = 0; b < K; ++b) {
+          double re = 0.0, im = 0.0;
+          for (int j = 0; j < K; ++j) {
+            const size_t x = (size_t)i * K + j;
+            const bool neg = __builtin_popcount((unsigned)(b & j)) & 1;
+            re += neg ? -cab[2 * x] : cab[2 * x];
+            im += neg ? -cab[2 * x + 1] : cab[2 * x + 1];
+          }
+          ca[2 * ((size_t)i * K + b)] = re * h;
+          ca[2 * ((size_t)i * K + b) + 1] = im * h;
+        }
+    } else {
+      ca = cab;
+    }
+    if ((st = dev_alloc(c, &c->dcab, cab.size())) || (st = dev_alloc(c, &c->dcamp, ca.size())) ||
+        (st = dev_alloc(c, &c->daflag, af.size())) || (st = dev_alloc(c, &c->dcin, cs.size())) ||
+        (st = dev_alloc(c, &c->djin, js.size())))
+      return bail(st);
+    if (hipMemcpy(c->dcab, cab.data(), cab.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->dcamp, ca.data(), ca.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->daflag, af.data(), af.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->dcin, cs.data(), cs.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->djin, js.data(), js.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(c, QRAM_E_DEVICE, "input upload failed"));
+    c->htab.cab = c->dcab;
+    c->htab.camp = c->dcamp;
+    c->htab.aflag = c->daflag;
+    c->htab.cin = c->dcin;
+    c->htab.jin = c->djin;
+  }
   c->htab.mem = c->dmem;
   c->htab.wpow = c->dwpow;
   c->htab.apow = c->dapow;
@@ -1074,6 +1155,9 @@ void qram_destroy(qram_ctx *c) {
   dev_free(&c->uaux);
   dev_free(&c->dcin);
   dev_free(&c->djin);
+  dev_free(&c->dcab);
+  dev_free(&c->dcamp);
+  dev_free(&c->daflag);
   dev_free(&c->dep);
   dev_free(&c->ndep);
   dev_free(&c->dexp);

@@ -84,6 +84,13 @@ struct Tables {
   // general input (null: uniform amplitudes, bus word 0)
   const double *cin;               // [2 D] normalised amplitude (re, im) of each address
   const uint32_t *jin;             // [D] bus word of each address
+  // input with amplitudes on (address, bus word) pairs: cin/jin then hold
+  // the amplitude and bus word of each address holding one bus word (0
+  // for the others)
+  const double *cab;               // [2 D 2^k] normalised c_ij, address-major
+  const double *camp;              // [2 D K2] amplitude of each component after the first wall
+  const uint8_t *aflag;            // [D] bit 0: the input holds the address; bit 1: with one bus word
+  int trunc_w;                     // Hamming truncation of the predicted good branches (-1: none)
 };
 
 struct Run {

@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(256) k_classify(const Tables *__restrict__ tb,
   uint32_t *wpos = sbuf + 16;                           // [nw32]
   uint8_t *mark = reinterpret_cast<uint8_t *>(wpos + nw32);  // [D - 1]
   const uint32_t cap = rp->cand_cap;
-  const int kb = enc == QUBIT ? tb->k : 0;
+  const int kb = __ffs(tb->K2) - 1;  // components per address = 2^kb
   for (uint32_t tj = blockIdx.x; tj < rp->ntraj; tj += gridDim.x) {
     for (int v = tid; v < D - 1; v += nthr) mark[v] = 0;
     if (tid == 0) sbuf[8] = 0xFFFFFFFFu;
@@ -254,7 +254,10 @@ __global__ void __launch_bounds__(256) k_classify(const Tables *__restrict__ tb,
           bad |= mark[v] != 0;
           v = (v - 1) >> 1;
         }
-        if (tb->cin) present = tb->cin[2 * i] != 0.0 || tb->cin[2 * i + 1] != 0.0;
+        if (tb->aflag)  // pair input: the reference holds one bus word
+          present = (tb->aflag[i] & 2u) != 0;
+        else if (tb->cin)
+          present = tb->cin[2 * i] != 0.0 || tb->cin[2 * i + 1] != 0.0;
       }
       const uint64_t m = __ballot(bad);
       const uint64_t pm = __ballot(present);  // the reference must be in the input
@@ -282,27 +285,30 @@ __global__ void __launch_bounds__(256) k_classify(const Tables *__restrict__ tb,
       const int per = (nw32 + nthr - 1) / nthr;
       const int w0 = min(nw32, tid * per), w1 = min(nw32, w0 + per);
       uint32_t c = 0;
-      for (int w = w0; w < w1; ++w) {
+      // without a reference nothing can be predicted: with a pair input a
+      // good address may hold several bus words, so every address is explicit
+      const bool all = ref == 0xFFFFFFFFu && tb->aflag;
+      const uint32_t vlast = (D & 31) ? ((1u << (D & 31)) - 1u) : 0xFFFFFFFFu;
+      auto expl = [&](int w) -> uint32_t {
+        if (all) return w == nw32 - 1 ? vlast : 0xFFFFFFFFu;
         uint32_t f = badw[w];
         if (ref != 0xFFFFFFFFu && (ref >> 5) == (uint32_t)w) f |= 1u << (ref & 31);
-        c += __popc(f);
-      }
+        return f;
+      };
+      for (int w = w0; w < w1; ++w) c += __popc(expl(w));
       uint32_t tot;
       uint32_t o = block_excl_scan_u32(c, sbuf, &tot);
       // first list position of each bitmap word; then every address writes
       // its own entry (position = its word's offset + the set bits below it)
       for (int w = w0; w < w1; ++w) {
-        uint32_t f = badw[w];
-        if (ref != 0xFFFFFFFFu && (ref >> 5) == (uint32_t)w) f |= 1u << (ref & 31);
         wpos[w] = o;
-        o += __popc(f);
+        o += __popc(expl(w));
       }
       __syncthreads();
       uint16_t *xl = rp->xlist + (size_t)tj * D;
       for (int i = tid; i < D; i += nthr) {
         const int w = i >> 5;
-        uint32_t f = badw[w];
-        if (ref != 0xFFFFFFFFu && (ref >> 5) == (uint32_t)w) f |= 1u << (ref & 31);
+        const uint32_t f = expl(w);
         const uint32_t below = f & ((1u << (i & 31)) - 1u);
         if ((f >> (i & 31)) & 1u) xl[wpos[w] + (uint32_t)__popc(below)] = (uint16_t)i;
       }

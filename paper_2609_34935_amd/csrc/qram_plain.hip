@@ -255,18 +255,19 @@ __device__ __forceinline__ double2 in_amp(const Tables *__restrict__ tb, uint32_
   return tb->cin ? make_double2(tb->cin[2 * i], tb->cin[2 * i + 1]) : make_double2(1.0 / sqrt((double)tb->D), 0.0);
 }
 
-// Exposure of branch i on its no-jump orbit through slice s, the part that
-// differs between branches: its address tokens, and (qutrit) its data slots,
-// which hold j_b before the fetch of bit b and j_b xor d_b after it (the
-// qubit's bus words, and every router level, are common to all branches).
+// Exposure of branch (i, j) on its no-jump orbit through slice s, the part
+// that differs between branches: its address tokens, and (qutrit) its data
+// slots, which hold j_b before the fetch of bit b and j_b xor d_b after it
+// (the qubit's bus words, and every router level, are common to all
+// branches).
 template <int ENC>
-__device__ __forceinline__ int branch_exposure(const Tables *__restrict__ tb, uint32_t i, int s) {
+__device__ __forceinline__ int branch_exposure(const Tables *__restrict__ tb, uint32_t i, uint32_t j, int s) {
   const int n = tb->n;
   int e = 0;
   for (int t = 0; t < n; ++t)
     if ((i >> (n - 1 - t)) & 1u) e += tb->cntA[s][t];
   if (ENC == QUTRIT) {
-    const uint32_t j = tb->jin ? tb->jin[i] : 0u, d = tb->mem[i];
+    const uint32_t d = tb->mem[i];
     for (int b = 0; b < tb->k; ++b) {
       const int in_tree = max(0, min(s, 4 * n + 2 * b) - (2 * n + 2 * b));
       const int after = tb->cntD[s][b];
@@ -276,14 +277,31 @@ __device__ __forceinline__ int branch_exposure(const Tables *__restrict__ tb, ui
   return e;
 }
 
+__device__ __forceinline__ uint32_t in_bus(const Tables *__restrict__ tb, uint32_t i) {
+  return tb->jin ? tb->jin[i] : 0u;
+}
+
+__device__ __forceinline__ double2 camp_of(const Tables *__restrict__ tb, size_t x) {
+  return make_double2(tb->camp[2 * x], tb->camp[2 * x + 1]);
+}
+
+// c_ij of the input (pair input, or the one bus word of each address)
+__device__ __forceinline__ double2 in_ab(const Tables *__restrict__ tb, uint32_t i, uint32_t j) {
+  if (tb->cab) {
+    const size_t x = ((size_t)i << tb->k) + j;
+    return make_double2(tb->cab[2 * x], tb->cab[2 * x + 1]);
+  }
+  return j == in_bus(tb, i) ? in_amp(tb, i) : make_double2(0.0, 0.0);
+}
+
 template <int ENC>
 __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, const Run R_) {
   const Run *rp = &R_;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int T = tb->T, M = tb->M, D = tb->D, k = tb->k;
-  const int K2 = ENC == QUBIT ? tb->K2 : 1;
-  const int kb = ENC == QUBIT ? k : 0;
+  const int K2 = tb->K2;  // components per address (qutrit: 1, or 2^k with a pair input)
+  const int kb = __ffs(K2) - 1;
   const uint32_t kmask = (1u << k) - 1u;
   const int rec = rp->prec;
   const int lcap = rec - 2;
@@ -325,14 +343,25 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
     // address i with amplitude c_i 2^(-k/2) (-1)^(beta . j_i); qutrit, bus
     // word j_i with amplitude c_i.  The data-loading input has c_i =
     // 2^(-n/2), j_i = 0; an address absent from the input has no component.
-    const double wall = 1.0 / sqrt((double)K2);
+    // A pair input sum_ij c_ij |i>|j> comes with each component's amplitude
+    // (qubit: 2^(-k/2) sum_j c_ij (-1)^(beta . j), alive with its address;
+    // qutrit: c_ij, alive when nonzero).
+    const double wall = ENC == QUBIT ? 1.0 / sqrt((double)K2) : 1.0;
     for (uint32_t y = tid; y < E; y += nthr) {
       uint16_t *r = pool + (size_t)y * rec;
       const uint32_t g = y >> kb, beta = y & (uint32_t)(K2 - 1);
       const uint32_t i = xl ? xl[g] : g;
       if (i == ref) sm.misc[8] = (int)g;
+      if (tb->camp) {
+        const double2 c = camp_of(tb, ((size_t)i << kb) + beta);
+        const bool alive = ENC == QUBIT ? (tb->aflag[i] & 1u) != 0 : (c.x != 0.0 || c.y != 0.0);
+        r[0] = alive ? 0 : PL_DEAD;
+        r[1] = (uint16_t)beta;
+        amp[y] = c;
+        continue;
+      }
       double2 c = in_amp(tb, i);
-      const uint32_t j = tb->jin ? tb->jin[i] : 0u;
+      const uint32_t j = in_bus(tb, i);
       if (ENC == QUBIT && (__popc(beta & j) & 1)) c = make_double2(-c.x, -c.y);
       r[0] = (c.x != 0.0 || c.y != 0.0) ? 0 : PL_DEAD;
       r[1] = (uint16_t)(ENC == QUBIT ? beta : j);
@@ -345,15 +374,73 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
     uint32_t jl_n = 0;
     __syncthreads();
     const int gref = sm.misc[8];  // explicit index of the reference, or -1
+    const uint32_t jref = goods ? in_bus(tb, ref) : 0u;
     double cref2 = 0.0;
     if (goods) cref2 = abs2(in_amp(tb, ref));
-    // a good address (present, outside the bad set, not the reference):
-    // its weight relative to the reference's through slice s
-    auto good_ratio = [&](uint32_t i, int s, int eref) -> double {
-      if (i == ref || ((badg[i >> 6] >> (i & 63)) & 1ull)) return 0.0;
-      const double c2 = abs2(in_amp(tb, i));
-      if (c2 == 0.0) return 0.0;
-      return c2 / cref2 * wpow[branch_exposure<ENC>(tb, i, s) - eref];
+    auto is_bad = [&](uint32_t i) -> bool { return (badg[i >> 6] >> (i & 63)) & 1ull; };
+    // The predicted branches (good, present, not the reference) relative to
+    // the reference, through slice s: the sum over branches (i, j) holding
+    // one bus word of |c_ij / c_ref|^2 (1-gamma)^(e(i,j) - e(ref)) (qutrit
+    // pair input: every (address, bus word) pair is such a branch).  Good
+    // qubit addresses holding several bus words enter bus word by bus word
+    // below (multi_sum).
+    auto good_sum = [&](int s, int eref) -> double {
+      double acc = 0.0;
+      if (ENC == QUTRIT && tb->cab) {
+        for (uint32_t x = (uint32_t)tid; x < ((uint32_t)D << kb); x += (uint32_t)nthr) {
+          const uint32_t i = x >> kb, j = x & (uint32_t)(K2 - 1);
+          if (i == ref || is_bad(i)) continue;
+          const double c2 = abs2(in_ab(tb, i, j));
+          if (c2 != 0.0) acc += c2 / cref2 * wpow[branch_exposure<ENC>(tb, i, j, s) - eref];
+        }
+        return acc;
+      }
+      for (int ii = tid; ii < D; ii += nthr) {
+        const uint32_t i = (uint32_t)ii;
+        if (i == ref || is_bad(i)) continue;
+        const double c2 = abs2(in_amp(tb, i));  // (0 for an address holding several bus words)
+        if (c2 != 0.0) acc += c2 / cref2 * wpow[branch_exposure<ENC>(tb, i, in_bus(tb, i), s) - eref];
+      }
+      return acc;
+    };
+    // qubit, good addresses holding several bus words: component (i, beta)
+    // has the reference's component beta times camp(i, beta) / camp(ref,
+    // beta) a^(e(i) - e(ref)) (Theorem 3); its weight through slice s
+    auto multi_ratio = [&](uint32_t i, uint32_t beta, int s, int eref) -> double {
+      const double f = abs2(camp_of(tb, ((size_t)i << kb) + beta)) / abs2(camp_of(tb, ((size_t)ref << kb) + beta));
+      return f * wpow[branch_exposure<ENC>(tb, i, 0u, s) - eref];
+    };
+    // ... summed over those addresses, split by whether the reference's
+    // component is hit (a good branch carries no excitation of its own on a
+    // candidate site, but it shares the reference's strays: an X-type fault
+    // on an idle site excites every branch off its range alike)
+    auto multi_sum = [&](int s, int eref, double &we, double &wh) {
+      if (ENC != QUBIT || !tb->cab) return;
+      for (uint32_t z = (uint32_t)tid; z < ((uint32_t)D << kb); z += (uint32_t)nthr) {
+        const uint32_t i = z >> kb, beta = z & (uint32_t)(K2 - 1);
+        if (tb->aflag[i] != 1u || is_bad(i)) continue;  // present, several bus words
+        const uint32_t yr = (uint32_t)gref * K2 + beta;
+        if (pool[(size_t)yr * rec] == PL_DEAD) continue;
+        const double w = multi_ratio(i, beta, s, eref) * abs2(amp[yr]);
+        if (hitf[yr])
+          wh += w;
+        else
+          we += w;
+      }
+    };
+    // weight of good label (a, beta) relative to the reference component it
+    // follows (index yr), through slice s; 0 for a label that is no branch
+    auto good_label = [&](uint32_t a, uint32_t beta, int s, int eref, uint32_t &yr) -> double {
+      if (ENC == QUBIT) {
+        yr = (uint32_t)gref * K2 + beta;
+        if (tb->aflag && tb->aflag[a] == 1u) return multi_ratio(a, beta, s, eref);
+        const double c2 = abs2(in_amp(tb, a));
+        return c2 == 0.0 ? 0.0 : c2 / cref2 * wpow[branch_exposure<ENC>(tb, a, 0u, s) - eref];
+      }
+      yr = (uint32_t)gref * K2 + (tb->cab ? jref : 0u);
+      const double c2 = tb->cab ? abs2(in_ab(tb, a, beta)) : abs2(in_amp(tb, a));
+      const uint32_t j = tb->cab ? beta : in_bus(tb, a);
+      return c2 == 0.0 ? 0.0 : c2 / cref2 * wpow[branch_exposure<ENC>(tb, a, j, s) - eref];
     };
 
     for (int s = 1; s < T; ++s) {
@@ -402,7 +489,9 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
         // Eq. maskweight: the empty-mask block and the hit components; a
         // good branch has the reference's mask for the same bus word and the
         // reference's weight times its ratio
-        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // empty, hit, ref empty, ref hit, sum of ratios
+        // empty, hit, ref empty, ref hit, ratio sum, predicted several-word
+        // weight not hit and hit
+        double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (uint32_t y = tid; y < E; y += nthr) {
           if (pool[(size_t)y * rec] == PL_DEAD) continue;
           const double w = abs2(amp[y]);
@@ -410,12 +499,16 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
           acc[h] += w;
           if (goods && (int)(y >> kb) == gref) acc[2 + h] += w;
         }
-        const int eref = goods ? branch_exposure<ENC>(tb, ref, s) : 0;
-        if (goods)
-          for (int i = tid; i < D; i += nthr) acc[4] += good_ratio((uint32_t)i, s, eref);
-        block_sum<5>(acc, sm.red);
-        const double w_empty = acc[0] + acc[4] * acc[2];
-        const double w_hit = acc[1] + acc[4] * acc[3];
+        const int eref = goods ? branch_exposure<ENC>(tb, ref, jref, s) : 0;
+        if (goods) {
+          acc[4] = good_sum(s, eref);
+          multi_sum(s, eref, acc[5], acc[6]);
+        }
+        block_sum<7>(acc, sm.red);
+        // a good branch is hit exactly when the reference's component it
+        // follows is
+        const double w_empty = acc[0] + acc[4] * acc[2] + acc[5];
+        const double w_hit = acc[1] + acc[4] * acc[3] + acc[6];
         const double u = rp->forced ? rp->uaux[s] : uniform53(rp->seed, (uint32_t)s, 0, traj, 2u);
         const double r = u * (w_empty + w_hit);
         if (!(r < w_empty)) {
@@ -434,9 +527,9 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
             if (x < Lx) {
               const uint32_t a = x >> kb, beta = x & (uint32_t)(K2 - 1);
               int g = -1;
-              if (!xl) {
+              if (!xl || A == (uint32_t)D) {  // (every address explicit, in order)
                 g = (int)a;
-              } else if (a == ref || ((badg[a >> 6] >> (a & 63)) & 1ull)) {
+              } else if (a == ref || is_bad(a)) {
                 int lo = 0, hi = (int)A - 1;  // a's position in the ascending explicit list
                 while (lo < hi) {
                   const int mid = (lo + hi) >> 1;
@@ -453,11 +546,12 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
                   w = abs2(amp[y]);
                   my = (int)y;
                 }
-              } else if (goods) {
-                const uint32_t y = (uint32_t)gref * K2 + beta;
-                if (pool[(size_t)y * rec] != PL_DEAD && hitf[y]) {
-                  w = abs2(amp[y]) * good_ratio(a, s, eref);
-                  if (w > 0.0) my = (int)y;
+              } else if (goods) {  // a good label follows the reference's component
+                uint32_t yr = 0;
+                const double rw = good_label(a, beta, s, eref, yr);
+                if (rw > 0.0 && pool[(size_t)yr * rec] != PL_DEAD && hitf[yr]) {
+                  w = abs2(amp[yr]) * rw;
+                  if (w > 0.0) my = (int)yr;
                 }
               }
             }
@@ -588,23 +682,30 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
     // second wall (qubit), tree measurement, fidelity.  Components with an
     // excited tree are orthogonal to the ideal output and to every other
     // group, so only their weight counts; the ground components of an
-    // address are grouped by bus word before the wall.  The ideal output is
-    // sum_i c_i |i>|j_i xor d_i>|ground>: overlap terms conj(c_i) A(i, j_i
-    // xor d_i).  The reference's own terms are kept apart as well: a good
-    // branch i adds |c_i|^2 a^(e_i - e_ref) / |c_ref|^2 times the
-    // reference's overlap term and |c_i / c_ref|^2 (1-gamma)^(e_i - e_ref)
-    // times its weights (Theorem 3 with the XOR mirror, Proposition 1).
-    double fin[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // address are grouped by bus word (before the wall, qubit).  The ideal
+    // output is sum_ij c_ij |i>|j xor d_i>|ground>: overlap terms
+    // conj(c_{i, w xor d_i}) A(i, w) over the output words w.  The
+    // reference's own terms are kept apart as well: a predicted branch
+    // (i, j) adds |c_ij|^2 a^(e - e_ref) / |c_ref|^2 times the reference's
+    // overlap term and |c_ij / c_ref|^2 (1-gamma)^(e - e_ref) times its
+    // weights (Theorem 3 with the XOR mirror, Proposition 1).  With
+    // truncation, the output words of every good address but the reference
+    // that lie more than trunc_w bit flips from its ideal word are dropped
+    // (Sec. V); the reference's weight within that radius carries the
+    // predicted branches.
+    const int tw = ENC == QUBIT ? tb->trunc_w : -1;
+    double fin[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     // overlap re, im, w_ground, w_excited, ref alive, ref overlap re, im,
-    // ref w_ground, ref w_excited, ratio sums (below)
+    // ref w_ground, ref w_excited, ratio sums (below), ref w_ground within
+    // the truncation radius
+    const int nw = (ENC == QUBIT || tb->cab) ? K2 : 1;  // output words held per address
     for (uint32_t g = (uint32_t)tid; g < A; g += (uint32_t)nthr) {
       const uint32_t i = xl ? xl[g] : g;
       const bool isref = i == ref;
-      const double2 ci = in_amp(tb, i);
-      const double2 cc = make_double2(ci.x, -ci.y);
-      const uint32_t want = ((tb->jin ? tb->jin[i] : 0u) ^ tb->mem[i]) & kmask;
+      const uint32_t want = (in_bus(tb, i) ^ tb->mem[i]) & kmask;
+      const bool trunc = tw >= 0 && !isref && !is_bad(i);
       bool any = false;
-      for (int b = 0; b < K2; ++b) grp[b] = make_double2(0.0, 0.0);
+      for (int b = 0; b < nw; ++b) grp[b] = make_double2(0.0, 0.0);
       for (int b = 0; b < K2; ++b) {
         const uint32_t y = g * (uint32_t)K2 + (uint32_t)b;
         const uint16_t *r = pool + (size_t)y * rec;
@@ -615,14 +716,17 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
           if (isref) fin[8] += abs2(amp[y]);
           continue;
         }
-        // qubit: grouped by bus word for the wall; qutrit (one component
-        // per address): slot 0, its bus word must be the ideal one
-        if (ENC == QUTRIT && ((uint32_t)r[1] & kmask) != want) {
+        // qutrit with one component per address: slot 0, holding it only
+        // when its bus word is the ideal one
+        if (nw == 1 && ((uint32_t)r[1] & kmask) != want) {
           fin[2] += abs2(amp[y]);
-          if (isref) fin[7] += abs2(amp[y]);
+          if (isref) {
+            fin[7] += abs2(amp[y]);
+            fin[10] += abs2(amp[y]);
+          }
           continue;
         }
-        const uint32_t bw = ENC == QUBIT ? ((uint32_t)r[1] & (uint32_t)(K2 - 1)) : 0u;
+        const uint32_t bw = nw == 1 ? 0u : ((uint32_t)r[1] & (uint32_t)(nw - 1));
         grp[bw] = make_double2(grp[bw].x + amp[y].x, grp[bw].y + amp[y].y);
         any = true;
       }
@@ -636,35 +740,100 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
               grp[b + len] = make_double2(u.x - v.x, u.y - v.y);
             }
       const double h = ENC == QUBIT ? 1.0 / sqrt((double)K2) : 1.0;
-      const uint32_t slot = ENC == QUBIT ? want : 0u;
-      for (int c = 0; c < K2; ++c) {
+      for (int c = 0; c < nw; ++c) {
         const double2 v = make_double2(grp[c].x * h, grp[c].y * h);
+        const int dist = __popc(((uint32_t)c ^ want) & kmask);
+        if (trunc && dist > tw) continue;
         fin[2] += abs2(v);
-        if (isref) fin[7] += abs2(v);
-        if ((uint32_t)c == slot) {
-          const double ox = cc.x * v.x - cc.y * v.y, oy = cc.x * v.y + cc.y * v.x;
-          fin[0] += ox;
-          fin[1] += oy;
-          if (isref) {
-            fin[5] += ox;
-            fin[6] += oy;
-          }
+        if (isref) {
+          fin[7] += abs2(v);
+          if (tw < 0 || dist <= tw) fin[10] += abs2(v);
+        }
+        // the input amplitude whose ideal output word is c
+        const double2 ci = nw == 1 ? in_amp(tb, i) : in_ab(tb, i, ((uint32_t)c ^ tb->mem[i]) & kmask);
+        const double ox = ci.x * v.x + ci.y * v.y, oy = ci.x * v.y - ci.y * v.x;  // conj(ci) v
+        fin[0] += ox;
+        fin[1] += oy;
+        if (isref) {
+          fin[5] += ox;
+          fin[6] += oy;
         }
       }
     }
-    double gw = 0.0, ga = 0.0;  // sums over good branches of (1-gamma)^de |c_i/c_ref|^2 and a^de |c_i|^2
+    double gw = 0.0, ga = 0.0;  // sums over predicted branches of (1-gamma)^de |c/c_ref|^2 and a^de |c|^2
     if (goods) {
-      const int eref = branch_exposure<ENC>(tb, ref, T - 1);
-      for (int i = tid; i < D; i += nthr) {
-        const double rw = good_ratio((uint32_t)i, T - 1, eref);
-        if (rw == 0.0) continue;
-        gw += rw;
-        ga += abs2(in_amp(tb, (uint32_t)i)) * apow[branch_exposure<ENC>(tb, (uint32_t)i, T - 1) - eref];
+      const int eref = branch_exposure<ENC>(tb, ref, jref, T - 1);
+      if (ENC == QUTRIT && tb->cab) {
+        for (uint32_t x = (uint32_t)tid; x < ((uint32_t)D << kb); x += (uint32_t)nthr) {
+          const uint32_t i = x >> kb, j = x & (uint32_t)(K2 - 1);
+          if (i == ref || is_bad(i)) continue;
+          const double c2 = abs2(in_ab(tb, i, j));
+          if (c2 == 0.0) continue;
+          const int de = branch_exposure<ENC>(tb, i, j, T - 1) - eref;
+          gw += c2 / cref2 * wpow[de];
+          ga += c2 * apow[de];
+        }
+      } else {
+        for (int ii = tid; ii < D; ii += nthr) {
+          const uint32_t i = (uint32_t)ii;
+          if (i == ref || is_bad(i)) continue;
+          const double c2 = abs2(in_amp(tb, i));
+          if (c2 == 0.0) continue;
+          const int de = branch_exposure<ENC>(tb, i, in_bus(tb, i), T - 1) - eref;
+          gw += c2 / cref2 * wpow[de];
+          ga += c2 * apow[de];
+        }
       }
+      // qubit, good addresses holding several bus words: component (i,
+      // beta) = camp(i, beta) / camp(ref, beta) a^(e(i) - e(ref)) (-1)^(beta
+      // . (d_i xor d_ref)) times the reference's, then the wall (O(k 2^k)
+      // per address, Table 2)
+      if (ENC == QUBIT && tb->cab && gref >= 0)
+        for (int ii = tid; ii < D; ii += nthr) {
+          const uint32_t i = (uint32_t)ii;
+          if (tb->aflag[i] != 1u || is_bad(i)) continue;
+          const int de = branch_exposure<ENC>(tb, i, 0u, T - 1) - eref;
+          const uint32_t dd = (tb->mem[i] ^ tb->mem[ref]) & kmask;
+          bool any = false;
+          for (int b = 0; b < K2; ++b) {
+            const uint32_t yr = (uint32_t)gref * K2 + (uint32_t)b;
+            const uint16_t *r = pool + (size_t)yr * rec;
+            grp[b] = make_double2(0.0, 0.0);
+            if (r[0] == PL_DEAD) continue;
+            const double2 ca = camp_of(tb, ((size_t)i << kb) + b), cr = camp_of(tb, ((size_t)ref << kb) + b);
+            const double den = abs2(cr);
+            if (r[0] != 0) {  // (an excited reference: the mirrored branch is excited too)
+              fin[3] += abs2(ca) / den * wpow[de] * abs2(amp[yr]);
+              continue;
+            }
+            // q = ca / cr a^de (+-1), then times the reference's amplitude
+            const double qx = (ca.x * cr.x + ca.y * cr.y) / den, qy = (ca.y * cr.x - ca.x * cr.y) / den;
+            const double f = apow[de] * ((__popc((uint32_t)b & dd) & 1) ? -1.0 : 1.0);
+            const double2 u = amp[yr];
+            grp[b] = make_double2(f * (qx * u.x - qy * u.y), f * (qx * u.y + qy * u.x));
+            any = true;
+          }
+          if (!any) continue;
+          for (int len = 1; len < K2; len <<= 1)
+            for (int b = 0; b < K2; ++b)
+              if (!(b & len)) {
+                const double2 u = grp[b], v = grp[b + len];
+                grp[b] = make_double2(u.x + v.x, u.y + v.y);
+                grp[b + len] = make_double2(u.x - v.x, u.y - v.y);
+              }
+          const double h = 1.0 / sqrt((double)K2);
+          for (int c = 0; c < K2; ++c) {
+            const double2 v = make_double2(grp[c].x * h, grp[c].y * h);
+            fin[2] += abs2(v);
+            const double2 ci = in_ab(tb, i, ((uint32_t)c ^ tb->mem[i]) & kmask);
+            fin[0] += ci.x * v.x + ci.y * v.y;
+            fin[1] += ci.x * v.y - ci.y * v.x;
+          }
+        }
     }
     fin[9] = gw;
     double fin2[1] = {ga};
-    block_sum<10>(fin, sm.red);
+    block_sum<11>(fin, sm.red);
     block_sum<1>(fin2, sm.red + 160);
     if (tid == 0) {
       double ovx = fin[0], ovy = fin[1], wg = fin[2], wx = fin[3];
@@ -672,7 +841,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
         const double ga_ref = fin2[0] / cref2;
         ovx += ga_ref * fin[5];
         ovy += ga_ref * fin[6];
-        wg += fin[9] * fin[7];
+        wg += fin[9] * fin[10];  // (fin[10] = fin[7] without truncation)
         wx += fin[9] * fin[8];
       }
       const double ov2 = ovx * ovx + ovy * ovy;

@@ -35,7 +35,8 @@ class QramRequest(C.Structure):
 class QramParams(C.Structure):
     _fields_ = [("n_addr", C.c_int), ("k_data", C.c_int), ("enc", C.c_int), ("gamma", C.c_double),
                 ("eps", C.c_double), ("memory_bits", C.POINTER(C.c_uint32)),
-                ("input_amp", C.POINTER(C.c_double)), ("input_bus", C.POINTER(C.c_uint32))]
+                ("input_amp", C.POINTER(C.c_double)), ("input_bus", C.POINTER(C.c_uint32)),
+                ("input_ab", C.POINTER(C.c_double)), ("truncate", C.c_int), ("w_max", C.c_int)]
 
 
 class QramResult(C.Structure):
@@ -146,9 +147,12 @@ class QramContext:
     """One (n, k, encoding, gamma, memory) simulator context on the current
     HIP device (``qram_create`` ... ``qram_destroy``)."""
 
-    def __init__(self, n_addr, k_data, encoding, gamma, memory_bits, eps=0.0, input_amp=None, input_bus=None):
+    def __init__(self, n_addr, k_data, encoding, gamma, memory_bits, eps=0.0, input_amp=None, input_bus=None,
+                 input_ab=None, w_max=None):
         """eps: depolarizing strength; input_amp (complex, 2^n) and input_bus
-        (2^n words): a general input sum_i c_i |i>|j_i> (``qram_create_ex``)."""
+        (2^n words): a general input sum_i c_i |i>|j_i>; or input_ab
+        (complex, 2^n x 2^k): sum_ij c_ij |i>|j>; w_max: Hamming truncation
+        of the predicted good branches (``qram_create_ex``)."""
         L = load_library()
         self.n, self.k, self.enc, self.gamma = int(n_addr), int(k_data), int(encoding), float(gamma)
         self.eps = float(eps)
@@ -158,8 +162,9 @@ class QramContext:
         mem = np.ascontiguousarray(memory_bits, dtype=np.uint32)
         if mem.shape != (self.D,):
             raise ValueError(f"memory_bits must hold 2^n = {self.D} words")
+        self.K2 = (1 << self.k) if (self.enc == 1 or input_ab is not None) else 1
         h = C.c_void_p()
-        if self.eps == 0.0 and input_amp is None and input_bus is None:
+        if self.eps == 0.0 and input_amp is None and input_bus is None and input_ab is None and w_max is None:
             st = L.qram_create(self.n, self.k, self.enc, self.gamma, _ptr(mem, C.c_uint32), C.byref(h))
         else:
             amp = bus = None
@@ -173,8 +178,16 @@ class QramContext:
                 bus = np.ascontiguousarray(input_bus, dtype=np.uint32)
                 if bus.shape != (self.D,):
                     raise ValueError(f"input_bus must hold 2^n = {self.D} words")
+            ab = None
+            if input_ab is not None:
+                c = np.asarray(input_ab, dtype=np.complex128).reshape(-1)
+                if c.shape != (self.D << self.k,):
+                    raise ValueError(f"input_ab must hold 2^n * 2^k = {self.D << self.k} amplitudes")
+                ab = np.empty(2 * len(c))
+                ab[0::2], ab[1::2] = c.real, c.imag
             prm = QramParams(self.n, self.k, self.enc, self.gamma, self.eps, _ptr(mem, C.c_uint32),
-                             _ptr(amp, C.c_double), _ptr(bus, C.c_uint32))
+                             _ptr(amp, C.c_double), _ptr(bus, C.c_uint32), _ptr(ab, C.c_double),
+                             0 if w_max is None else 1, 0 if w_max is None else int(w_max))
             st = L.qram_create_ex(C.byref(prm), C.byref(h))
         if st:
             raise QramError(st, L.qram_last_error(None).decode())
@@ -296,7 +309,7 @@ class QramContext:
         trajectory (sampled, or forced when u_aux is given) and its jump log.
         Returns dict(fid, st, records [ncomp, 3 + lmax] uint32, amp (plain
         mode: complex amplitude of each record), jlog uint32 entries, njl)."""
-        K2 = (1 << self.k) if self.enc == 1 else 1
+        K2 = self.K2
         lmax = 2 * self.n + self.k if self.enc == 1 else 4 * self.n + self.k
         ncomp = self.D * K2
         comp = np.zeros(ncomp * (3 + lmax), dtype=np.uint32)
