@@ -1519,7 +1519,7 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
   if (ntraj == 0) return fail(c, QRAM_E_INVAL, "ntraj must be positive");
   const uint32_t nt = std::min(ntraj, batch_size(c, ntraj));
   if ((st = ensure_out(c, nt))) return st;
-  if (mode == QRAM_MODE_PLAIN) {  // workgroups per compute unit
+  if (mode == QRAM_MODE_PLAIN || c->general) {  // the plain engine: workgroups per compute unit
     double best = 1e300;
     int bw = 2;
     for (int w : {1, 2, 4}) {
@@ -1533,6 +1533,7 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
       r.fid = c->fid_tmp;
       r.st = nullptr;
       HIPCHK(c, launch_sample(c->dtab, r, nt, sample_grid(c, nt), c->stream));
+      if (r.dep) HIPCHK(c, launch_sample_depol(c->dtab, r, sample_grid(c, nt), c->stream));
       HIPCHK(c, launch_classify(c->dtab, r, nt, sample_grid(c, nt), c->D, c->mark_subtree, c->stream));
       HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
       HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.b[0].grid, pl.b[0].threads, pl.plds, c->stream));
@@ -1546,7 +1547,6 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
       }
     }
     c->plain_per_cu = bw;
-    c->spt[mode] = bw;
     if (best_ms) *best_ms = best;
     return check_err(c);
   }
