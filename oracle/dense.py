@@ -284,6 +284,39 @@ class Machine:
         out[self.index(dig[src])] = fac[src] * psi[src]
         return out
 
+    def dephase_rho(self, rho, p):
+        """Dephasing of strength p on every tree site (an outlook channel of
+        Sec. VII): (1-p) rho + p Z rho Z+ on a qubit site, (1-p) rho + (p/2)
+        (Z rho Z+ + Z^2 rho Z^2+) on a qutrit router, Z = diag(w^v)."""
+        for q in range(self.M):
+            d = self.levels(q)
+            col = self.digits[:, self.S(q)]
+            new = (1.0 - p) * rho
+            for m in range(1, d):
+                z = np.exp(2j * np.pi * m * col / d)
+                new = new + (p / (d - 1)) * (z[:, None] * rho * np.conj(z)[None, :])
+            rho = new
+        return rho
+
+    def heat_rho(self, rho, p):
+        """Heating of strength p on every tree site (an outlook channel of
+        Sec. VII): level 0 rises with probability p, to 1 on a qubit site and
+        to L or R with p/2 each on a qutrit router; the no-jump operator is
+        diag(sqrt(1-p), 1, 1)."""
+        for q in range(self.M):
+            d = self.levels(q)
+            col = self.digits[:, self.S(q)]
+            k0 = np.where(col == 0, np.sqrt(1.0 - p), 1.0)
+            new = (k0[:, None] * k0[None, :]) * rho
+            src = np.nonzero(col == 0)[0]
+            for lev in range(1, d):
+                dig = self.digits[src].copy()
+                dig[:, self.S(q)] = lev
+                dst = self.index(dig)
+                new[np.ix_(dst, dst)] += (p / (d - 1)) * rho[np.ix_(src, src)]
+            rho = new
+        return rho
+
     def damp_rho(self, rho, gamma):
         """Amplitude damping on every tree site (Eq. kraus / kraus-tri)."""
         a = np.sqrt(1.0 - gamma)
@@ -305,10 +338,11 @@ class Machine:
         return rho
 
 
-def density_fidelity(n, k, enc, mem, gamma, eps=0.0, cab=None):
+def density_fidelity(n, k, enc, mem, gamma, eps=0.0, cab=None, dephase=0.0, heat=0.0):
     """F_rho = <psi_id| rho |psi_id> of the whole query under damping and
     (eps > 0) depolarizing noise: per slice the gates, then the depolarizing
-    channel on the active sites, then damping on every tree site.  cab: a
+    channel on the active sites, then damping on every tree site, then
+    (dephase, heat > 0) dephasing and heating on every tree site.  cab: a
     general input c_ij (None: the data-loading input)."""
     m = Machine(n, k, enc, mem)
     psi = m.input_state(cab)
@@ -321,6 +355,10 @@ def density_fidelity(n, k, enc, mem, gamma, eps=0.0, cab=None):
             rho = m.depol_rho(rho, s, eps)
         if gamma > 0.0:
             rho = m.damp_rho(rho, gamma)
+        if dephase > 0.0:
+            rho = m.dephase_rho(rho, dephase)
+        if heat > 0.0:
+            rho = m.heat_rho(rho, heat)
     if enc == QUBIT:
         rho = m.wall_rho(rho)
     pid = m.ideal_state(cab)
