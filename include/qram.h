@@ -351,6 +351,46 @@ qram_status qram_run_forced(qram_ctx *ctx, qram_mode mode,
                             qram_traj_stats *st);
 
 /*
+ * Dense whole-register cross-check for tiny trees (App. C): the complete
+ * loading circuit of the context (same schedule, memory, input, gamma and
+ * eps) on an ordinary register whose basis labels hold every digit:
+ * address bit t (t = 0 the root's bit) most significant, then bus bit b,
+ * then tree site q (router 2v, data slot 2v+1); a qutrit router has three
+ * levels (W, L, R = 0, 1, 2), every other digit two; the last digit varies
+ * fastest.  No sampling, no branch bookkeeping.
+ *
+ * qram_dense_dim: the number N of basis labels.
+ *
+ * qram_dense_density: the density matrix of the query under explicit
+ * channels, slice by slice: the gates, the depolarizing channel of strength
+ * eps on the active positions, amplitude damping on every tree site
+ * (Eq. kraus, Eq. kraus-tri), then two channels the outlook of Sec. VII
+ * names (each with a diagonal no-jump operator, applied to every tree
+ * site): dephasing of strength `dephase` ((1-p) rho + p Z rho Z+ on a qubit
+ * site; (1-p) rho + (p/2) sum_{m=1,2} Z^m rho Z^m+ on a qutrit router) and
+ * heating of strength `heat` (level 0 rises with probability p: to 1 on a
+ * qubit site, to L or R with p/2 each on a qutrit router; no-jump operator
+ * diag(sqrt(1-p), 1, 1)).  Hadamard walls on the bus for the qubit
+ * encoding.  Outputs F_rho = <psi_id| rho |psi_id> against the ideal output
+ * sum_ij c_ij |i>|j xor d_i>|ground>, and the trace.  N <= 4096 (n <= 2),
+ * else QRAM_E_RANGE.  Device memory: two N x N complex buffers, allocated
+ * and freed by the call.
+ *
+ * qram_dense_forced: the state vector before the second wall under a given
+ * history: jumps [njumps] in the jump-log format of qram_export_state (site
+ * | level << 16 | slice << 24, slices ascending; every other damping layer
+ * applies K_empty) and depolarizing faults [nfaults] in the format of
+ * qram_sample_depol (site | slice << 16 | type << 24, slices ascending),
+ * each fault after its slice's gates and before its damping layer.  psi
+ * [2 * cap] host doubles receive (re, im) of every basis label; cap >= N
+ * (else QRAM_E_CAPACITY).  n <= 3 and N <= 2^25, else QRAM_E_RANGE.
+ */
+qram_status qram_dense_dim(const qram_ctx *ctx, uint64_t *N);
+qram_status qram_dense_density(qram_ctx *ctx, double dephase, double heat, double *F_rho, double *trace);
+qram_status qram_dense_forced(qram_ctx *ctx, const uint32_t *jumps, uint32_t njumps, const uint32_t *faults,
+                              uint32_t nfaults, double *psi, uint64_t cap);
+
+/*
  * Test entry: the final pre-measurement state of one trajectory, component by
  * component, and its jump log.  The paper validates its pruned evolution by
  * matching complete complex amplitudes, the residual tree configuration and

@@ -5,7 +5,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("qram_host.hip", "qram_kernels.hip", "qram_evolve.hip", "qram_plain.hip", "qram_server.hip")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("qram_host.hip", "qram_kernels.hip", "qram_evolve.hip", "qram_plain.hip", "qram_server.hip", "qram_dense.hip")]
 LIB = os.path.join(HERE, "libqram_hip.so")
 
 HIPCC_FLAGS = [

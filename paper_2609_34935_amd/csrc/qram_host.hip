@@ -53,6 +53,10 @@ struct qram_ctx {
   uint32_t *djin = nullptr;
   double *dcab = nullptr, *dcamp = nullptr;  // pair amplitudes, component amplitudes
   uint8_t *daflag = nullptr;
+  // the input as (address << 8 | bus word, normalised amplitude) pairs, for
+  // the dense cross-check
+  std::vector<uint32_t> in_idx;
+  std::vector<double> in_amp;
   uint32_t *dep = nullptr, *ndep = nullptr;  // depolarizing faults of a batch
   uint32_t dep_cap = 0;
   int T = 0, M = 0, D = 0, K2 = 1, Emax = 0, lmax = 0, emax = 0, rec = 0;
@@ -942,6 +946,28 @@ qram_status qram_create_ex(const qram_params *p, qram_ctx **out) {
   }
   c->mem.assign(memory_bits, memory_bits + c->D);
   for (auto &m : c->mem) m &= (1u << k_data) - 1u;
+  {  // the input's (address, bus word) pairs with their normalised amplitudes
+    const uint32_t K = 1u << k_data;
+    for (uint32_t i = 0; i < (uint32_t)c->D; ++i) {
+      if (!cab.empty()) {
+        for (uint32_t j = 0; j < K; ++j) {
+          const double re = cab[2 * ((size_t)i * K + j)], im = cab[2 * ((size_t)i * K + j) + 1];
+          if (re == 0.0 && im == 0.0) continue;
+          c->in_idx.push_back(i << 8 | j);
+          c->in_amp.push_back(re);
+          c->in_amp.push_back(im);
+        }
+        continue;
+      }
+      const double re = cin.empty() ? 1.0 / std::sqrt((double)c->D) : cin[2 * i];
+      const double im = cin.empty() ? 0.0 : cin[2 * i + 1];
+      if (re == 0.0 && im == 0.0) continue;
+      const uint32_t j = p->input_bus ? (p->input_bus[i] & (K - 1u)) : 0u;
+      c->in_idx.push_back(i << 8 | j);
+      c->in_amp.push_back(re);
+      c->in_amp.push_back(im);
+    }
+  }
   std::string why;
   if (!build_tables(c, why)) {
     delete c;
@@ -1776,6 +1802,64 @@ qram_status qram_run_jumplog(qram_ctx *c, qram_mode mode, uint64_t seed, uint64_
   if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED && mode != QRAM_MODE_PLAIN) return fail(c, QRAM_E_INVAL, "bad mode");
   if (!fid || !njl || (jcap && !jlog)) return fail(c, QRAM_E_INVAL, "null argument");
   return run_mode(c, (int)mode, seed, traj0, ntraj, nullptr, nullptr, fid, stt, c->stream, true, jlog, jcap, njl);
+}
+
+qram_status qram_dense_dim(const qram_ctx *c, uint64_t *N) {
+  if (!c || !N) return QRAM_E_INVAL;
+  *N = dense_dim(c->n, c->k, c->enc);
+  return QRAM_OK;
+}
+
+static DenseJob dense_job(const qram_ctx *c, double dephase, double heat) {
+  DenseJob j;
+  j.n = c->n;
+  j.k = c->k;
+  j.enc = c->enc;
+  j.gamma = c->gamma;
+  j.eps = c->eps;
+  j.dephase = dephase;
+  j.heat = heat;
+  j.mem = c->mem;
+  j.in_idx = c->in_idx;
+  j.in_amp = c->in_amp;
+  return j;
+}
+
+qram_status qram_dense_density(qram_ctx *c, double dephase, double heat, double *F_rho, double *trace) {
+  if (!c || !F_rho || !trace) return fail(c, QRAM_E_INVAL, "null argument");
+  if (!(dephase >= 0.0 && dephase <= 1.0) || !(heat >= 0.0 && heat <= 1.0))
+    return fail(c, QRAM_E_INVAL, "dephase and heat must lie in [0, 1]");
+  if (dense_dim(c->n, c->k, c->enc) > 4096) return fail(c, QRAM_E_RANGE, "density matrix: at most 4096 basis states (n <= 2)");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, dense_density(c->dtab, dense_job(c, dephase, heat), c->stream, F_rho, trace));
+  return QRAM_OK;
+}
+
+qram_status qram_dense_forced(qram_ctx *c, const uint32_t *jumps, uint32_t njumps, const uint32_t *faults,
+                              uint32_t nfaults, double *psi, uint64_t cap) {
+  if (!c || !psi || (njumps && !jumps) || (nfaults && !faults)) return fail(c, QRAM_E_INVAL, "null argument");
+  const uint64_t N = dense_dim(c->n, c->k, c->enc);
+  if (c->n > 3 || N > (1ull << 25)) return fail(c, QRAM_E_RANGE, "dense state: n <= 3 and at most 2^25 basis states");
+  if (cap < N) return fail(c, QRAM_E_CAPACITY, "psi needs 2 * N doubles (qram_dense_dim)");
+  uint32_t prev = 0;
+  for (uint32_t t = 0; t < njumps; ++t) {
+    const uint32_t s = jumps[t] >> 24, q = jumps[t] & 0xFFFFu, lev = (jumps[t] >> 16) & 0xFFu;
+    const uint32_t levmax = (c->enc == QUTRIT && (q & 1u) == 0) ? 2u : 1u;
+    if (s < 1 || s >= (uint32_t)c->T || s < prev || q >= (uint32_t)c->M || lev < 1 || lev > levmax)
+      return fail(c, QRAM_E_INVAL, "jumps: site | level << 16 | slice << 24, slices ascending in 1..T-1");
+    prev = s;
+  }
+  prev = 0;
+  for (uint32_t t = 0; t < nfaults; ++t) {
+    const uint32_t s = (faults[t] >> 16) & 0xFFu, q = faults[t] & 0xFFFFu, ty = faults[t] >> 24;
+    const uint32_t d = (c->enc == QUTRIT && (q & 1u) == 0) ? 3u : 2u;
+    if (s < 1 || s >= (uint32_t)c->T || s < prev || q >= (uint32_t)c->M || (ty & 3u) >= d || (ty >> 2) >= d)
+      return fail(c, QRAM_E_INVAL, "faults: site | slice << 16 | type << 24, slices ascending in 1..T-1");
+    prev = s;
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, dense_forced(c->dtab, dense_job(c, 0.0, 0.0), jumps, njumps, faults, nfaults, c->stream, psi));
+  return QRAM_OK;
 }
 
 }  // extern "C"

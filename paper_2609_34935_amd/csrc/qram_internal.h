@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "../../include/qram.h"
 
@@ -188,5 +189,19 @@ int plain_occupancy(int enc, int threads, uint32_t lds_bytes);
 hipError_t launch_plain(const Tables *tb, const Run &rp, int enc, uint32_t grid, int threads, uint32_t lds_bytes,
                         hipStream_t s);
 hipError_t evolve_prepare(int lds_max, int *dyn_max);
+
+// dense whole-register cross-check (tiny trees)
+constexpr int DENSE_MAXD = 24;  // digits: n + k + 2 (2^n - 1)
+struct DenseJob {
+  int n, k, enc;
+  double gamma, eps, dephase, heat;
+  std::vector<uint32_t> mem;     // [2^n] memory words
+  std::vector<uint32_t> in_idx;  // address << 8 | bus word of each input pair
+  std::vector<double> in_amp;    // its normalised amplitude (re, im)
+};
+uint64_t dense_dim(int n, int k, int enc);
+hipError_t dense_density(const Tables *dtab, const DenseJob &job, hipStream_t st, double *F, double *tr);
+hipError_t dense_forced(const Tables *dtab, const DenseJob &job, const uint32_t *jumps, uint32_t njumps,
+                        const uint32_t *faults, uint32_t nfaults, hipStream_t st, double *psi_host);
 
 }  // namespace qr

@@ -52,6 +52,7 @@ EXPORTS = [
     "qram_last_kernel_ms", "qram_set_timing", "qram_stage_times", "qram_stage_launches", "qram_set_option",
     "qram_run_forced", "qram_footprint", "qram_reserve", "qram_errors", "qram_run_pruned_async_noalloc",
     "qram_export_state", "qram_run_jumplog", "qram_run_plain", "qram_run_plain_async", "qram_stage_buckets",
+    "qram_dense_dim", "qram_dense_density", "qram_dense_forced",
     "qram_server_create", "qram_server_submit", "qram_server_poll", "qram_server_wait",
     "qram_server_fidelities", "qram_server_release", "qram_server_destroy",
 ]
@@ -86,6 +87,9 @@ def load_library(path: str = LIB_PATH):
     L.qram_create_ex.argtypes = [C.POINTER(QramParams), p(vp)]
     L.qram_create_ex.restype = C.c_int
     L.qram_sample_depol.argtypes = [vp, u64, u64, u32, p(u32), p(u32), u64]
+    L.qram_dense_dim.argtypes = [vp, p(u64)]
+    L.qram_dense_density.argtypes = [vp, f64, f64, p(f64), p(f64)]
+    L.qram_dense_forced.argtypes = [vp, p(u32), u32, p(u32), u32, p(f64), u64]
     L.qram_destroy.argtypes = [vp]
     L.qram_destroy.restype = None
     L.qram_server_destroy.restype = None
@@ -193,6 +197,29 @@ class QramContext:
             raise QramError(st, L.qram_last_error(None).decode())
         self._h = h
         self._L = L
+
+    def dense_density(self, dephase=0.0, heat=0.0):
+        """qram_dense_density: (F_rho, trace) of the whole query as a density
+        matrix under the context's channels plus dephasing / heating."""
+        F, tr = C.c_double(), C.c_double()
+        self._check(self._L.qram_dense_density(self._h, float(dephase), float(heat), C.byref(F), C.byref(tr)),
+                    "qram_dense_density")
+        return F.value, tr.value
+
+    def dense_forced(self, jumps=(), faults=()):
+        """qram_dense_forced: the state vector (complex, N) before the second
+        wall under the given jumps (slice, site, level) and faults (slice,
+        site, a, b)."""
+        N = C.c_uint64()
+        self._check(self._L.qram_dense_dim(self._h, C.byref(N)), "qram_dense_dim")
+        js = sorted(jumps)
+        fs = sorted(faults, key=lambda f: f[0])
+        ja = np.array([q | (lev << 16) | (s << 24) for s, q, lev in js] or [0], dtype=np.uint32)
+        fa = np.array([q | (s << 16) | ((a | (b << 2)) << 24) for s, q, a, b in fs] or [0], dtype=np.uint32)
+        psi = np.zeros(2 * N.value)
+        self._check(self._L.qram_dense_forced(self._h, _ptr(ja, C.c_uint32), len(js), _ptr(fa, C.c_uint32), len(fs),
+                                              _ptr(psi, C.c_double), N.value), "qram_dense_forced")
+        return psi[0::2] + 1j * psi[1::2]
 
     def sample_depol(self, seed, traj0, ntraj, cap=None):
         """Depolarizing faults: (counts [ntraj], entries site | slice << 16 |
