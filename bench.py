@@ -254,6 +254,67 @@ def config5_leg(P, nt, nt_plain):
     return out
 
 
+# The paper's full-versus-pruned benchmark (App. D, Table 5): per-query
+# milliseconds (t_full, t_pruned) on one CPU thread, qubit encoding, k = 3,
+# eps = gamma, data-loading input.  Context for the GPU figures beside them.
+PAPER_TABLE5 = {
+    (0.0, 4): (0.5731, 0.0307), (0.0, 6): (4.043, 0.0859), (0.0, 8): (21.56, 0.2424),
+    (0.0, 10): (124.8, 0.7592), (0.0, 12): (725.1, 2.548),
+    (1e-5, 4): (0.7496, 0.0497), (1e-5, 6): (4.815, 0.2348), (1e-5, 8): (29.12, 1.417),
+    (1e-5, 10): (173.9, 11.29), (1e-5, 12): (1258.0, 125.4),
+    (1e-4, 4): (0.7586, 0.0964), (1e-4, 6): (4.885, 0.8590), (1e-4, 8): (31.26, 8.250),
+    (1e-4, 10): (243.0, 95.92), (1e-4, 12): (2750.0, 1655.0),
+    (1e-3, 4): (0.7895, 0.3668), (1e-3, 6): (6.251, 4.491), (1e-3, 8): (55.15, 51.81),
+    (1e-3, 10): (800.1, 794.1), (1e-3, 12): (11814.0, 11816.0),
+}
+
+
+def table5_leg(P, scale=1.0):
+    """The paper's full-versus-pruned workload (Fig. 3, App. D): qubit, k = 3,
+    eps = gamma in {0, 1e-5, 1e-4, 1e-3}, n = 4..12, data-loading input.
+    Pruned (Alg. 1) against the plain full evolution of every branch, on the
+    GPU, with equal fidelities checked on every trajectory."""
+    import torch
+    from paper_2609_34935_amd.inputs import memory_words
+    k, seed = 3, 880007
+    stream = torch.cuda.current_stream()
+    rows = []
+    for p in (0.0, 1e-5, 1e-4, 1e-3):
+        for n in (4, 6, 8, 10, 12):
+            # enough trajectories per workgroup that the slowest trajectories
+            # do not set the launch time (the paper's figure is a mean)
+            nt = {4: 65536, 6: 32768, 8: 16384, 10: 8192, 12: 4096}[n]
+            if p >= 1e-3 and n >= 10:
+                nt //= 4
+            nt = int(max(64, nt * scale))
+            mem = memory_words(n, k, 1007 + n)
+            d_fid = torch.empty(nt, dtype=torch.float64, device="cuda")
+            d_st = torch.empty(nt * 32, dtype=torch.uint8, device="cuda")
+            with P.QramContext(n, k, P.QRAM_QUBIT, p, mem, eps=p) as ctx:
+                row = {"eps=gamma": p, "n": n, "trajectories": nt}
+                fids = {}
+                for name, fn in (("pruned", ctx.run_pruned_async), ("full", ctx.run_plain_async)):
+                    reps = 3 if name == "pruned" else 1
+                    dt = time_mode(ctx, fn, seed, nt, reps, d_fid, d_st, stream)
+                    row[f"{name}_traj_per_s"] = round(nt / dt, 1)
+                    fids[name] = d_fid.cpu().numpy()
+                    if name == "pruned":
+                        s = stats_of(P, d_st)
+                        row["evolved_pct"] = round(100.0 * float(s["n_explicit"].mean()) / 2 ** (n + k), 2)
+                ctx.errors()
+            assert np.all(np.abs(fids["full"] - fids["pruned"]) <= 1e-12 * np.maximum(np.abs(fids["pruned"]), 1e-3))
+            row["speedup"] = round(row["pruned_traj_per_s"] / row["full_traj_per_s"], 2)
+            tf, tp = PAPER_TABLE5[(p, n)]
+            row["paper_cpu_1thread"] = {"full_traj_per_s": round(1000.0 / tf, 3),
+                                        "pruned_traj_per_s": round(1000.0 / tp, 3), "speedup": round(tf / tp, 2)}
+            rows.append(row)
+            log(f"Table 5 workload eps=gamma={p:g} n={n}: {row}")
+            del d_fid, d_st
+    return {"workload": "qubit k=3, eps=gamma, data-loading input (Fig. 3 / Table 5), seed 880007, "
+                        "mem_seed 1007+n", "unit": "trajectories/s", "rows": rows,
+            "paper": "Table 5: one thread of an i9-13900KF, FP64 (context, not a target)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +339,8 @@ def main():
     ap.add_argument("--c5-ntraj", type=int, default=100000)
     ap.add_argument("--c5-plain-ntraj", type=int, default=20000)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-table5", action="store_true")
+    ap.add_argument("--table5-scale", type=float, default=1.0)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-capacity-requests", type=int, default=400)
     ap.add_argument("--serve-chunk", type=int, default=16384)
@@ -532,7 +595,7 @@ def main():
                           "tune_ms": tune_ms or None},
         "roofline": roofline,
         "roofline_plain": roofline_plain,
-        "config2": None, "config5": None,
+        "config2": None, "config5": None, "table5": None,
         "latency": None,
         "cpu_baseline": None,
     }
@@ -544,6 +607,8 @@ def main():
         line["config2"] = config2_leg(P, reps=5)
     if not args.no_c5:
         line["config5"] = config5_leg(P, args.c5_ntraj, args.c5_plain_ntraj)
+    if not args.no_table5:
+        line["table5"] = table5_leg(P, args.table5_scale)
     torch.cuda.empty_cache()
     if not args.no_serve:
         log("serving mix")

@@ -477,7 +477,9 @@ qram_status qram_errors(qram_ctx *ctx);
  * workgroups in flight than qram_run_pruned_async.  Returns
  * QRAM_E_CAPACITY when a single workgroup's buffers do not fit the array
  * (no supported configuration reaches this), QRAM_E_DEVICE when the array
- * has no address on the context's device.  Every call on one device
+ * has no address on the context's device, QRAM_E_INVAL for a context that
+ * runs on the plain engine (qram_create_ex with eps > 0, a general or pair
+ * input, truncation, or qubit k > 6).  Every call on one device
  * shares that device's array and its contents persist between calls:
  * calls that overlap on one device (other streams, other host threads,
  * other contexts) race and must be ordered by the caller.  The array's

@@ -1387,6 +1387,9 @@ qram_status qram_run_pruned_async_noalloc(qram_ctx *c, uint64_t seed, uint64_t t
   qram_status st = check_args(c, traj0, ntraj);
   if (st) return st;
   if (!c->scratch) return fail(c, QRAM_E_DEVICE, "the scratch array has no address on this device");
+  if (c->general)
+    return fail(c, QRAM_E_INVAL, "the no-allocation entry serves contexts of the trajectory kernel (qram_create: damping, "
+                                 "data-loading input, qubit k <= 6)");
   const hipStream_t s = (hipStream_t)stream;
   const int mode = 1;
   // per trajectory: candidates, five counters, digest, bad bitmap, explicit list

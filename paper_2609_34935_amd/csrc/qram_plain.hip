@@ -318,7 +318,13 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
   const uint32_t ccap = rp->cand_cap;
   for (int w = tid; w < (M + 31) / 32; w += nthr) sm.cbm[w] = 0u;
 
-  for (uint32_t tj = blockIdx.x; tj < rp->ntraj; tj += gridDim.x) {
+  // trajectories from a device queue (counter[0], cleared before the
+  // launch): a workgroup that drew short ones takes more
+  for (;;) {
+    if (tid == 0) sm.misc[12] = (int)atomicAdd(&rp->counter[0], 1u);
+    __syncthreads();  // (misc[12] is written again only after the trajectory's last barrier)
+    const uint32_t tj = (uint32_t)sm.misc[12];
+    if (tj >= rp->ntraj) break;
     const uint32_t traj = rp->traj0 + tj;
     const uint32_t nct = min(rp->ncand[tj], ccap);
     const uint32_t *__restrict__ cand = rp->cand + (size_t)tj * ccap;
@@ -499,10 +505,11 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
           acc[h] += w;
           if (goods && (int)(y >> kb) == gref) acc[2 + h] += w;
         }
-        const int eref = goods ? branch_exposure<ENC>(tb, ref, jref, s) : 0;
+        // the weights before this slice's damping layer: exposures through s-1
+        const int eref = goods ? branch_exposure<ENC>(tb, ref, jref, s - 1) : 0;
         if (goods) {
-          acc[4] = good_sum(s, eref);
-          multi_sum(s, eref, acc[5], acc[6]);
+          acc[4] = good_sum(s - 1, eref);
+          multi_sum(s - 1, eref, acc[5], acc[6]);
         }
         block_sum<7>(acc, sm.red);
         // a good branch is hit exactly when the reference's component it
@@ -519,12 +526,21 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
           const double r2 = r - w_empty;
           double base = 0.0;
           int pick = -1, last = -1, pick_y = -1, last_y = -1;
-          const uint32_t Lx = (uint32_t)(D * K2);
+          // Only a hit reference component makes good labels candidates for
+          // x*; otherwise the explicit components alone, which are in label
+          // order already (ascending explicit addresses), are scanned.
+          const bool labels = goods && (acc[3] > 0.0 || acc[6] > 0.0);
+          const uint32_t Lx = labels ? (uint32_t)(D * K2) : E;
           for (uint32_t x0 = 0; x0 < Lx && pick < 0; x0 += (uint32_t)nthr) {
             const uint32_t x = x0 + (uint32_t)tid;
             double w = 0.0;
             int my = -1;
-            if (x < Lx) {
+            if (x < Lx && !labels) {
+              if (pool[(size_t)x * rec] != PL_DEAD && hitf[x]) {
+                w = abs2(amp[x]);
+                my = (int)x;
+              }
+            } else if (x < Lx) {
               const uint32_t a = x >> kb, beta = x & (uint32_t)(K2 - 1);
               int g = -1;
               if (!xl || A == (uint32_t)D) {  // (every address explicit, in order)
@@ -548,7 +564,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
                 }
               } else if (goods) {  // a good label follows the reference's component
                 uint32_t yr = 0;
-                const double rw = good_label(a, beta, s, eref, yr);
+                const double rw = good_label(a, beta, s - 1, eref, yr);
                 if (rw > 0.0 && pool[(size_t)yr * rec] != PL_DEAD && hitf[yr]) {
                   w = abs2(amp[yr]) * rw;
                   if (w > 0.0) my = (int)yr;
@@ -884,6 +900,8 @@ int plain_occupancy(int enc, int threads, uint32_t lds_bytes) {
 
 hipError_t launch_plain(const Tables *tb, const Run &rp, int enc, uint32_t grid, int threads, uint32_t lds_bytes,
                         hipStream_t s) {
+  const hipError_t e = launch_fill_u32(rp.counter, 0u, 1u, s);  // the queue head
+  if (e != hipSuccess) return e;
   if (enc == QUBIT)
     hipLaunchKernelGGL(k_plain<QUBIT>, dim3(grid), dim3(threads), lds_bytes, s, tb, rp);
   else

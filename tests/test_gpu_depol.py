@@ -220,3 +220,24 @@ def test_table4_trajectory_mean(lib, row):
             f, _ = (ctx.run_pruned if mode == PRUNED else ctx.run_full)(99, 0, nt)
             m, sem = f.mean(), f.std(ddof=1) / np.sqrt(nt)
             assert abs(m - r["F_rho"]) <= 4 * sem + 0.5e-4, (r["noise"], mode, m, sem, r["F_rho"])
+
+
+@pytest.mark.parametrize("n,k,enc,p,nt", [
+    (6, 3, QUBIT, 1e-3, 8192), (6, 2, QUTRIT, 1e-3, 8192), (8, 3, QUBIT, 1e-4, 4096), (10, 3, QUBIT, 1e-5, 2048)])
+def test_pruned_equals_plain_many_trajectories(lib, orc, n, k, enc, p, nt):
+    """The paper's benchmark workload (eps = gamma, data-loading input): the
+    pruned draws must equal the full evolution's on every trajectory, which
+    needs the predicted branches' weights taken before the slice's damping
+    layer; trajectory 3269 of the first case drew a jump the full evolution
+    does not when they were taken after it."""
+    mem = memory_words(n, k, 1007 + n)
+    with lib.QramContext(n, k, enc, p, mem, eps=p) as ctx:
+        fp, sp = ctx.run_pruned(880007, 0, nt)
+        ff, sf = ctx.run_plain(880007, 0, nt)
+    bad = np.nonzero(~fid_close(fp, ff))[0]
+    assert len(bad) == 0, (bad[:5], fp[bad[:5]], ff[bad[:5]])
+    for fld in ("n_cand", "n_bad", "ref_addr", "n_jumps", "first_jump_slice", "q_ground"):
+        assert np.array_equal(sp[fld], sf[fld]), fld
+    idx = np.unique(np.concatenate([np.arange(64), [3269 % nt]]))
+    fo, fpo, so, _ = orc.run_many(n, k, enc, p, mem, 880007, idx=idx, eps=p, nthreads=16)
+    assert np.all(fid_close(fp[idx], fo))

@@ -64,3 +64,16 @@ def test_noalloc_matches_pruned_async():
         a = _run(ctx, ctx.run_pruned_async_noalloc, 7, 11, 257)
         b = _run(ctx, ctx.run_pruned_async, 7, 11, 257)
         _compare(a, b)
+
+
+def test_no_alloc_refuses_plain_engine_contexts():
+    """The no-allocation entry serves the trajectory kernel's contexts only;
+    a depolarizing context is refused before anything is enqueued."""
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2609_34935_amd import QramError
+    n, k = 4, 2
+    with QramContext(n, k, 1, 0.01, memory_words(n, k, 3), eps=0.01) as ctx:
+        d = torch.zeros(8, dtype=torch.float64, device="cuda")
+        with pytest.raises(QramError):
+            ctx.run_pruned_async_noalloc(1, 0, 8, d, None, torch.cuda.current_stream())
