@@ -426,6 +426,9 @@ qram_status qram_dense_forced(qram_ctx *ctx, const uint32_t *jumps, uint32_t nju
  *             NULL and is not written) receives each record's complex
  *             amplitude (real, imaginary), the factor gamma^(J/2) and the
  *             input amplitude c_i included.
+ *             A component holding more than lmax excited sites (depolarizing
+ *             strays on the plain engine) makes the call return
+ *             QRAM_E_CAPACITY after writing the first lmax.
  *   jlog      [jcap] jump-log entries in order of slice: site | level << 16 |
  *             slice << 24 (levels as above); *njl receives the number of
  *             entries, which may exceed jcap (the rest are not written).

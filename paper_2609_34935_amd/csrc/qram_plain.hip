@@ -680,6 +680,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
         const uint32_t x = (a << kb) | (y & (uint32_t)(K2 - 1));
         uint32_t *o = rp->exp + (size_t)x * rw;
         if (r[0] == PL_DEAD) continue;
+        if (r[0] > (uint32_t)tb->lmax) atomicOr(rp->err, ERR_LIST);  // (strays: more sites than an export record holds)
         const uint32_t m = min((uint32_t)r[0], (uint32_t)tb->lmax);
         o[0] = a | ((uint32_t)r[1] << 16) | EXP_PRESENT;
         o[1] = 0;
