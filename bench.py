@@ -92,7 +92,7 @@ def cpu_baseline(mem, n_qubit, n_qutrit):
     trajectories) on the first trajectories of each encoding."""
     from oracle import oracle as O
     host = os.cpu_count() or 1
-    threads = min(16, host)  # the GPU box's CPU share for one GPU
+    threads = min(16, host)  # one GPU's share of a 16-CPU-per-GPU host
     per = {}
     used = threads
     for enc, cnt in ((1, n_qubit), (0, n_qutrit)):

@@ -46,7 +46,7 @@ def fnv_digest(L):
 
 def oracle_at(orc, n, k, enc, gamma, mem, seed, idx):
     """The oracle on the listed trajectories, OpenMP over the host's cores
-    (at most 16 threads, the GPU machine's share)."""
+    (at most 16 threads, one GPU's share of the host)."""
     f, fp, ri, _ = orc.run_indices(n, k, enc, gamma, mem, seed, idx, nthreads=min(16, os.cpu_count() or 1))
     return list(zip(f, fp, ri))
 
