@@ -202,6 +202,8 @@ def config2_leg(P, reps):
     for gamma in (1e-4, 1e-3, 1e-2):
         with P.QramContext(n, k, P.QRAM_QUBIT, gamma, mem) as ctx:
             row, fids = {}, {}
+            ctx.autotune(P.QRAM_MODE_PLAIN, seed + 1, 0, nt)  # (plain engine: shape by the autotuner)
+            row["plain_launch"] = list(ctx.get_launch(P.QRAM_MODE_PLAIN))
             for name, fn in (("pruned", ctx.run_pruned_async), ("full_engine", ctx.run_full_async),
                              ("plain", ctx.run_plain_async)):
                 dt = time_mode(ctx, fn, seed, nt, reps, d_fid, d_st, stream)
@@ -232,6 +234,8 @@ def config5_leg(P, nt, nt_plain):
     stream = torch.cuda.current_stream()
     out = {"workload": f"qutrit n=14 k=1 gamma=1e-2, seed {seed}, mem_seed 1005", "unit": "trajectories/s"}
     with P.QramContext(n, k, P.QRAM_QUTRIT, gamma, mem) as ctx:
+        ctx.autotune(P.QRAM_MODE_PLAIN, seed + 1, 0, min(nt_plain, 8192))  # (plain engine: shape by the autotuner)
+        out["plain_launch"] = list(ctx.get_launch(P.QRAM_MODE_PLAIN))
         for name, mode, fn, cnt in (("pruned", P.QRAM_MODE_PRUNED, ctx.run_pruned_async, nt),
                                     ("full_engine", P.QRAM_MODE_FULL, ctx.run_full_async, nt),
                                     ("plain", P.QRAM_MODE_PLAIN, ctx.run_plain_async, nt_plain)):
@@ -294,6 +298,14 @@ def table5_leg(P, scale=1.0):
                 row = {"eps=gamma": p, "n": n, "trajectories": nt}
                 fids = {}
                 for name, fn in (("pruned", ctx.run_pruned_async), ("full", ctx.run_plain_async)):
+                    # plain-engine launch shape: the autotuner's pick where a
+                    # trajectory holds at most 4096 components, else the
+                    # automatic one (256 threads, all workgroups that fit)
+                    mode = P.QRAM_MODE_PRUNED if name == "pruned" else P.QRAM_MODE_PLAIN
+                    if (p > 0 or name == "full") and 2 ** (n + k) <= 4096:
+                        ctx.autotune(mode, seed + 1, 0, min(nt, 8192))
+                    if p > 0 or name == "full":
+                        row.setdefault("launch", {})[name] = list(ctx.get_launch(mode))
                     reps = 3 if name == "pruned" else 1
                     dt = time_mode(ctx, fn, seed, nt, reps, d_fid, d_st, stream)
                     row[f"{name}_traj_per_s"] = round(nt / dt, 1)

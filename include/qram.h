@@ -254,9 +254,17 @@ qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,
  * trajectories to workgroups round robin, 1 takes them from a device queue,
  * longest first; bit 1: keep the component state words in device memory
  * instead of workgroup shared memory (smaller workgroups per compute unit
- * footprint, more trajectories in flight).  QRAM_MODE_PLAIN: slots_per_thread
- * is the number of workgroups per compute unit (1..8, 0 = 2), schedule is
- * ignored.  The shape changes only the speed:
+ * footprint, more trajectories in flight).  Modes that run on the plain
+ * engine (QRAM_MODE_PLAIN, and every mode of a context with depolarizing
+ * noise, a general input, truncation or qubit k > 6): slots_per_thread is the
+ * number of workgroups per compute unit (1..32, capped by what fits; 0 =
+ * automatic: all that fit) and schedule the threads per workgroup (64, 128
+ * or 256; 0 = automatic: 256, or 64 (pruned) / 128 (full) when a trajectory
+ * holds at most 256 components), plus 1 to work on each component record in
+ * device memory instead of staging it in shared memory while a thread
+ * applies a slice's gates to it.  The launch also stays within 16 GiB of
+ * per-trajectory state.  qram_get_launch returns the shape in use.  The
+ * shape changes only the speed:
  * results are identical across shapes up to the rounding of the per-slice
  * weight sums.
  */
@@ -270,8 +278,9 @@ qram_status qram_get_launch(const qram_ctx *ctx, qram_mode mode,
  *   QRAM_OPT_TIER2_GLOBAL: keep every explicit site list of a component whose
  *     routing a jump changed in global memory instead of registers, one list
  *     per component (the qubit encoding otherwise shares one list among the
- *     bus words of an address).  Same results; for testing the list paths
- *     against each other.
+ *     bus words of an address); on the plain engine, work on each component
+ *     record in device memory instead of staging it in shared memory.  Same
+ *     results; for testing the list paths against each other.
  *   QRAM_OPT_GRAPH: run each batch (sampling, classification, bucketing and
  *     every bucket's persistent evolution launch) as one HIP graph.  The
  *     graph is captured on the context's stream, instantiated once and then
@@ -299,8 +308,10 @@ qram_status qram_set_option(qram_ctx *ctx, int option, int value);
  * evolution of the sample (every work bucket's launch).  A shape with the
  * component state in device memory must be 3% faster than the best with
  * the state in shared memory to be kept: within that margin it only adds
- * HBM traffic.  The plain mode tries 1, 2 and 4 workgroups per compute
- * unit.  best_ms receives the kept shape's time.
+ * HBM traffic.  On the plain engine it tries 64, 128 and 256 threads per
+ * workgroup, each with all, half and a quarter of the workgroups that fit a
+ * compute unit, with the records staged in shared memory and in device
+ * memory.  best_ms receives the kept shape's time.
  */
 qram_status qram_autotune(qram_ctx *ctx, qram_mode mode, uint64_t seed,
                           uint64_t traj0, uint32_t ntraj, double *best_ms);

@@ -42,6 +42,7 @@ struct Plan {
   // the batch's trajectories
   bool plain = false;
   uint32_t plds = 0;
+  bool pslab = false;  // records staged through shared memory
 };
 
 struct qram_ctx {
@@ -89,9 +90,12 @@ struct qram_ctx {
   size_t dexp_cap = 0, djlog_cap = 0, djn_cap = 0;
   double *dexpamp = nullptr;
   size_t dexpamp_cap = 0;
-  // plain full evolution: record length, workgroups per CU, buffers
+  // plain engine: record length; launch shape per mode (full, pruned,
+  // plain): workgroups per CU and threads per workgroup, 0 = automatic
   int prec = 0;
-  int plain_per_cu = 2;
+  int plain_per_cu[3] = {0, 0, 0};
+  int plain_thr[3] = {0, 0, 0};
+  bool plain_glob[3] = {false, false, false};  // records worked on in device memory
   double *pamp = nullptr, *pgrp = nullptr;
   uint8_t *phit = nullptr;
   size_t pamp_cap = 0, pgrp_cap = 0, phit_cap = 0;
@@ -417,6 +421,30 @@ uint32_t pow2ceil(uint32_t x) {
   return p;
 }
 
+// Plain-engine launch shape of a mode: the caller's choice where one was set,
+// else the automatic one.
+// The automatic shape: as many workgroups per compute unit as fit (the
+// engine waits on memory more than it computes), of 256 threads, or of 64 /
+// 128 threads when a trajectory holds at most 256 components (pruned /
+// full), so that small trajectories do not leave most lanes idle.
+void plain_shape(const qram_ctx *c, int mode, int &threads, int &per_cu, bool &glob) {
+  const int m = mode;
+  threads = c->plain_thr[m];
+  if (!threads) threads = c->Emax > 256 ? PLAIN_THREADS : (mode == QRAM_MODE_PRUNED ? 64 : 128);
+  per_cu = c->plain_per_cu[m] ? c->plain_per_cu[m] : 32;  // (capped by occupancy)
+  glob = c->plain_glob[m];
+}
+
+// Shared memory of a plain-engine workgroup of `threads`: the slice state,
+// and a record slab per thread unless the records stay in device memory
+// (asked for, QRAM_OPT_TIER2_GLOBAL, or slabs beyond PLAIN_SLAB_BYTES).
+bool plain_slab(const qram_ctx *c, int threads, bool glob) {
+  return !glob && !c->tier2_global && (size_t)threads * c->prec * 2 <= PLAIN_SLAB_BYTES;
+}
+uint32_t plain_lds(const qram_ctx *c, int threads, bool glob) {
+  return plain_lds_bytes(c->M, plain_slab(c, threads, glob) ? (uint32_t)(threads * c->prec) : 0u);
+}
+
 // Launch plan of a mode.  The full mode evolves every address, so it has one
 // bucket.  The pruned mode's explicit work varies per trajectory (bad
 // addresses plus the reference), so trajectories are grouped by it, each
@@ -426,13 +454,24 @@ qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
     pl = Plan{};
     pl.plain = true;
     pl.nb = 1;
-    pl.plds = plain_lds_bytes(c->M);
-    int occ = plain_occupancy(c->enc, PLAIN_THREADS, pl.plds);
-    occ = std::max(1, std::min(occ, c->plain_per_cu));
-    pl.b[0].threads = PLAIN_THREADS;
+    int threads = 0, per_cu = 0;
+    bool glob = false;
+    plain_shape(c, mode, threads, per_cu, glob);
+    pl.plds = plain_lds(c, threads, glob);
+    pl.pslab = plain_slab(c, threads, glob);
+    const int occ = plain_occupancy(c->enc, threads, pl.plds);
+    if (occ < 1) return fail(c, QRAM_E_DEVICE, "plain engine: no workgroup fits a compute unit");
+    per_cu = std::min(per_cu, occ);
+    // every workgroup holds a trajectory's whole explicit state in device
+    // memory: keep the pool within PLAIN_POOL_BYTES
+    const double per_wg = (double)c->Emax * ((double)c->prec * 2.0 + 17.0) + (double)threads * c->K2 * 16.0;
+    const double fit = std::max(1.0, std::floor((double)PLAIN_POOL_BYTES / per_wg));
+    uint32_t grid = (uint32_t)std::min<double>((double)c->num_cu * per_cu, fit);
+    grid = std::max<uint32_t>(1u, std::min<uint32_t>(grid, ntraj));
+    pl.b[0].threads = threads;
     pl.b[0].emax = (uint32_t)c->Emax;
-    pl.b[0].grid = std::max<uint32_t>(1u, std::min<uint32_t>((uint32_t)(c->num_cu * occ), ntraj));
-    pl.grid_max = pl.b[0].grid;
+    pl.b[0].grid = grid;
+    pl.grid_max = grid;
     return QRAM_OK;
   }
   const int spt_target = c->spt[mode] ? c->spt[mode] : 16;
@@ -521,7 +560,7 @@ qram_status ensure_buffers(qram_ctx *c, uint32_t nb, const Plan *pl) {
     }
     if ((st = grow(c, &c->pamp, &c->pamp_cap, g * E * 2))) return st;
     if ((st = grow(c, &c->phit, &c->phit_cap, g * E))) return st;
-    if ((st = grow(c, &c->pgrp, &c->pgrp_cap, g * PLAIN_THREADS * (size_t)c->K2 * 2))) return st;
+    if ((st = grow(c, &c->pgrp, &c->pgrp_cap, g * (size_t)pl->b[0].threads * c->K2 * 2))) return st;
     return QRAM_OK;
   }
   if (pl) {
@@ -556,7 +595,7 @@ size_t buffers_bytes(const qram_ctx *c, uint32_t nb, const Plan &pl) {
   b += (2 * MAXB + 1 + 4) * 4;
   if (pl.plain) {
     const size_t g = pl.grid_max, E = (size_t)c->Emax;
-    return b + g * E * ((size_t)c->prec * 2 + 16 + 1) + g * PLAIN_THREADS * (size_t)c->K2 * 16;
+    return b + g * E * ((size_t)c->prec * 2 + 16 + 1) + g * (size_t)pl.b[0].threads * c->K2 * 16;
   }
   b += (size_t)pl.grid_max * pl.ecap_max * 4;
   size_t ps = 0, ds = 0;
@@ -619,6 +658,7 @@ Run base_run(qram_ctx *c, int mode, uint64_t seed, const Plan *pl) {
     r.dep_cap = c->dep_cap;
   }
   r.prec = (uint32_t)c->prec;
+  if (pl) r.pslab = pl->pslab ? 1u : 0u;
   r.pamp = c->pamp;
   r.phit = c->phit;
   r.pgrp = c->pgrp;
@@ -938,7 +978,7 @@ qram_status qram_create_ex(const qram_params *p, qram_ctx **out) {
   // record: count, bus word, lmax sites (+ the data tokens' sites and the
   // split set of a shared qubit list)
   c->rec = (c->lmax + 2 + (c->enc == QUBIT ? k_data + 1 : 0) + 1) & ~1;
-  c->prec = (c->lmax + PLAIN_EXTRA + 2 + 1) & ~1;
+  c->prec = (c->lmax + PLAIN_EXTRA + 2 + 7) & ~7;  // (16-byte records)
   const double lw = c->emax * std::log(1.0 - gamma);
   if (lw < -690.0) {
     delete c;
@@ -977,7 +1017,7 @@ qram_status qram_create_ex(const qram_params *p, qram_ctx **out) {
   // trajectory's fault capacity beyond lmax
   if (c->eps > 0.0)
     c->prec = (int)((std::min<uint32_t>((uint32_t)(c->lmax + PLAIN_EXTRA) + dep_capacity(c), (uint32_t)(c->M + c->lmax)) +
-                     2u + 1u) & ~1u);
+                     2u + 7u) & ~7u);
 
   auto bail = [&](qram_status st) {
     std::string m = c->err;
@@ -1492,13 +1532,19 @@ qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,
 qram_status qram_set_launch(qram_ctx *c, qram_mode mode, int slots_per_thread,
                             int schedule) {
   if (!c) return QRAM_E_INVAL;
-  if (mode == QRAM_MODE_PLAIN) {  // workgroups per compute unit
-    if (slots_per_thread < 0 || slots_per_thread > 8) return fail(c, QRAM_E_INVAL, "plain mode: 0..8 workgroups per CU");
-    c->plain_per_cu = slots_per_thread ? slots_per_thread : 2;
-    c->spt[mode] = slots_per_thread;
+  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED && mode != QRAM_MODE_PLAIN)
+    return fail(c, QRAM_E_INVAL, "bad mode");
+  if (mode == QRAM_MODE_PLAIN || c->general) {  // workgroups per CU, threads per workgroup
+    if (slots_per_thread < 0 || slots_per_thread > 32)
+      return fail(c, QRAM_E_INVAL, "plain engine: 0..32 workgroups per compute unit");
+    const int t = schedule & ~1;
+    if (t != 0 && t != 64 && t != 128 && t != 256)
+      return fail(c, QRAM_E_INVAL, "plain engine: 0, 64, 128 or 256 threads per workgroup (+1: records in device memory)");
+    c->plain_per_cu[mode] = slots_per_thread;
+    c->plain_thr[mode] = t;
+    c->plain_glob[mode] = (schedule & 1) != 0;
     return QRAM_OK;
   }
-  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return fail(c, QRAM_E_INVAL, "bad mode");
   if (slots_per_thread != 0 && slots_per_thread != 4 && slots_per_thread != 8 && slots_per_thread != 16 &&
       slots_per_thread != 32 && slots_per_thread != 64)
     return fail(c, QRAM_E_INVAL, "slots_per_thread must be 0, 4, 8, 16, 32 or 64");
@@ -1511,12 +1557,16 @@ qram_status qram_set_launch(qram_ctx *c, qram_mode mode, int slots_per_thread,
 qram_status qram_get_launch(const qram_ctx *c, qram_mode mode,
                             int *slots_per_thread, int *schedule) {
   if (!c || !slots_per_thread || !schedule) return QRAM_E_INVAL;
-  if (mode == QRAM_MODE_PLAIN) {
-    *slots_per_thread = c->plain_per_cu;
-    *schedule = 0;
+  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED && mode != QRAM_MODE_PLAIN) return QRAM_E_INVAL;
+  if (mode == QRAM_MODE_PLAIN || c->general) {  // the shape in use: explicit or automatic
+    int threads = 0, per_cu = 0;
+    bool glob = false;
+    plain_shape(c, mode, threads, per_cu, glob);
+    const int occ = plain_occupancy(c->enc, threads, plain_lds(c, threads, glob));
+    *slots_per_thread = occ > 0 ? std::min(per_cu, occ) : per_cu;
+    *schedule = threads + (plain_slab(c, threads, glob) ? 0 : 1);
     return QRAM_OK;
   }
-  if (mode != QRAM_MODE_FULL && mode != QRAM_MODE_PRUNED) return QRAM_E_INVAL;
   *slots_per_thread = c->spt[mode] ? c->spt[mode] : 16;
   *schedule = c->schedule[mode];
   return QRAM_OK;
@@ -1548,11 +1598,35 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
   if (ntraj == 0) return fail(c, QRAM_E_INVAL, "ntraj must be positive");
   const uint32_t nt = std::min(ntraj, batch_size(c, ntraj));
   if ((st = ensure_out(c, nt))) return st;
-  if (mode == QRAM_MODE_PLAIN || c->general) {  // the plain engine: workgroups per compute unit
+  if (mode == QRAM_MODE_PLAIN || c->general) {
+    // the plain engine: threads per workgroup, and workgroups per compute
+    // unit up to what fits
     double best = 1e300;
-    int bw = 2;
-    for (int w : {1, 2, 4}) {
-      c->plain_per_cu = w;
+    int bw = 0, bt = 0;
+    bool bg = false;
+    const int m = mode;
+    const int keep_w = c->plain_per_cu[m], keep_t = c->plain_thr[m];
+    const bool keep_g = c->plain_glob[m];
+    struct Shape {
+      int t, w;
+      bool g;
+    };
+    std::vector<Shape> shapes;
+    for (bool g : {false, true}) {
+      if (g && c->tier2_global) continue;  // (every shape keeps its records in device memory already)
+      for (int t : {64, 128, 256}) {
+        if (!g && !plain_slab(c, t, false)) continue;  // (no slab fits: the same as in device memory)
+        const int occ = plain_occupancy(c->enc, t, plain_lds(c, t, g));
+        if (occ < 1) continue;
+        for (int w : {occ, (occ + 1) / 2, (occ + 3) / 4})
+          if (shapes.empty() || shapes.back().t != t || shapes.back().w != w || shapes.back().g != g)
+            shapes.push_back({t, w, g});
+      }
+    }
+    for (const auto &sh : shapes) {
+      c->plain_thr[m] = sh.t;
+      c->plain_per_cu[m] = sh.w;
+      c->plain_glob[m] = sh.g;
       Plan pl;
       if (make_plan(c, mode, nt, pl) != QRAM_OK) continue;
       if ((st = ensure_buffers(c, nt, &pl))) return st;
@@ -1572,10 +1646,14 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
       HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
       if (ms < best) {
         best = ms;
-        bw = w;
+        bw = sh.w;
+        bt = sh.t;
+        bg = sh.g;
       }
     }
-    c->plain_per_cu = bw;
+    c->plain_per_cu[m] = bw ? bw : keep_w;
+    c->plain_thr[m] = bt ? bt : keep_t;
+    c->plain_glob[m] = bw ? bg : keep_g;
     if (best_ms) *best_ms = best;
     return check_err(c);
   }

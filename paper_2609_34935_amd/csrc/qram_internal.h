@@ -143,6 +143,7 @@ struct Run {
   // plain full evolution: per-workgroup component lists (pool, prec uint16
   // words each), amplitudes, hit flags and finalize scratch
   uint32_t prec;
+  uint32_t pslab;        // 1: each thread stages the record it works on in shared memory
   double *pamp;          // [grid * E * 2]
   uint8_t *phit;         // [grid * E]
   double *pgrp;          // [grid * threads * K2 * 2]
@@ -182,9 +183,11 @@ __host__ __device__ inline uint32_t walk_table_bytes(int T, int n, int k) {
 }
 int evolve_occupancy(int enc, bool state_lds, int threads, uint32_t lds_bytes);
 // plain full evolution (every component explicit, slice by slice)
-constexpr int PLAIN_THREADS = 256;
+constexpr int PLAIN_THREADS = 256;  // (largest plain-engine workgroup)
+constexpr double PLAIN_POOL_BYTES = 16.0 * 1024 * 1024 * 1024;  // plain-engine state of one launch
+constexpr uint32_t PLAIN_SLAB_BYTES = 40 * 1024;  // per-workgroup record slabs in shared memory, at most
 constexpr int PLAIN_EXTRA = 8;  // list entries beyond the excitation bound
-uint32_t plain_lds_bytes(int M);
+uint32_t plain_lds_bytes(int M, uint32_t slab_words);
 int plain_occupancy(int enc, int threads, uint32_t lds_bytes);
 hipError_t launch_plain(const Tables *tb, const Run &rp, int enc, uint32_t grid, int threads, uint32_t lds_bytes,
                         hipStream_t s);

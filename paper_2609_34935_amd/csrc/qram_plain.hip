@@ -228,10 +228,11 @@ struct PlainSm {
   uint32_t *J;       // [JMAX] joint outcome: site | level << 16
   double *red;       // [16 * 16] reduction buffer
   int *misc;         // [16]
+  uint16_t *slab;    // [threads * prec] one record per thread (16-byte aligned)
 };
 
-__host__ __device__ inline uint32_t plain_sm_bytes(int M) {
-  return (uint32_t)(((M + 31) / 32) * 4 + (MAXT + 1) * 4 + JMAX * 4 + 16 * 16 * 8 + 16 * 4 + 64);
+__host__ __device__ inline uint32_t plain_sm_head(int M) {
+  return (uint32_t)((((M + 31) / 32) * 4 + (MAXT + 1) * 4 + JMAX * 4 + 16 * 16 * 8 + 16 * 4 + 64 + 15) & ~15);
 }
 
 __device__ inline PlainSm plain_carve(unsigned char *base, int M) {
@@ -246,7 +247,46 @@ __device__ inline PlainSm plain_carve(unsigned char *base, int M) {
   s.J = reinterpret_cast<uint32_t *>(base + o);
   o += JMAX * 4;
   s.misc = reinterpret_cast<int *>(base + o);
+  s.slab = reinterpret_cast<uint16_t *>(base + plain_sm_head(M));
   return s;
+}
+
+// A record (rec words, a multiple of 8) copied between the pool and a
+// thread's slab in 16-byte pieces: the count and bus word and the sites in
+// use.  The first pieces are loaded together, before the count is known.
+__device__ __forceinline__ void rec_load(uint16_t *dst, const uint16_t *__restrict__ src, int rec) {
+  const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+  uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+  const int nv_all = rec >> 3;
+  const uint4 v0 = s4[0];
+  const uint4 v1 = nv_all > 1 ? s4[1] : v0;
+  const uint4 v2 = nv_all > 2 ? s4[2] : v0;
+  const uint4 v3 = nv_all > 3 ? s4[3] : v0;
+  d4[0] = v0;
+  if (nv_all > 1) d4[1] = v1;
+  if (nv_all > 2) d4[2] = v2;
+  if (nv_all > 3) d4[3] = v3;
+  const uint32_t c = v0.x & 0xFFFFu;
+  if (c == PL_DEAD) return;
+  const int nv = min(nv_all, (int)(2 + c + 7) >> 3);
+  for (int i = 4; i < nv; i += 4) {  // longer lists: four pieces in flight at a time
+    const uint4 w0 = s4[i];
+    const uint4 w1 = i + 1 < nv ? s4[i + 1] : w0;
+    const uint4 w2 = i + 2 < nv ? s4[i + 2] : w0;
+    const uint4 w3 = i + 3 < nv ? s4[i + 3] : w0;
+    d4[i] = w0;
+    if (i + 1 < nv) d4[i + 1] = w1;
+    if (i + 2 < nv) d4[i + 2] = w2;
+    if (i + 3 < nv) d4[i + 3] = w3;
+  }
+}
+
+__device__ __forceinline__ void rec_store(uint16_t *__restrict__ dst, const uint16_t *src, int rec) {
+  const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+  uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+  const uint32_t c = src[0];
+  const int nv = c == PL_DEAD ? 1 : min(rec >> 3, (int)(2 + c + 7) >> 3);
+  for (int i = 0; i < nv; ++i) d4[i] = s4[i];
 }
 
 __device__ __forceinline__ double abs2(double2 z) { return z.x * z.x + z.y * z.y; }
@@ -316,6 +356,9 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
   const double *__restrict__ wpow = tb->wpow + tb->emax;
   const double sg = tb->sg;
   const uint32_t ccap = rp->cand_cap;
+  // the record this thread works on: staged in its slab of shared memory
+  // (the gates' list scans then stay on chip), else worked on in the pool
+  uint16_t *const slab = rp->pslab ? sm.slab + (size_t)tid * rec : nullptr;
   for (int w = tid; w < (M + 31) / 32; w += nthr) sm.cbm[w] = 0u;
 
   // trajectories from a device queue (counter[0], cleared before the
@@ -463,30 +506,31 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
       // candidates the hit test of every component against the slice's set
       int anyhit = 0;
       for (uint32_t y = tid; y < E; y += nthr) {
-        PList<ENC> L{pool + (size_t)y * rec, lcap};
+        uint16_t *const g = pool + (size_t)y * rec;
+        if (slab) rec_load(slab, g, rec);
+        PList<ENC> L{slab ? slab : g, lcap};
         if (L.cnt() == PL_DEAD) continue;
         const uint32_t a = xl ? xl[y >> kb] : (y >> kb);
-        if (plain_gates<ENC>(tb, s, L, a, rp->err)) amp[y] = make_double2(-amp[y].x, -amp[y].y);
-        if (dpos > d0) {  // faults after the gates, before the damping layer
-          double2 am = amp[y];
-          for (uint32_t f = d0; f < dpos; ++f) {
-            const uint32_t e = dep[f], t = e >> 24;
-            plain_fault<ENC>(L, am, e & 0xFFFFu, t & 3u, t >> 2, rp->err);
-          }
-          amp[y] = am;
+        double2 am = amp[y];
+        if (plain_gates<ENC>(tb, s, L, a, rp->err)) am = make_double2(-am.x, -am.y);
+        for (uint32_t f = d0; f < dpos; ++f) {  // faults after the gates, before the damping layer
+          const uint32_t e = dep[f], t = e >> 24;
+          plain_fault<ENC>(L, am, e & 0xFFFFu, t & 3u, t >> 2, rp->err);
         }
         if (nc == 0) {
           const double f = apow[L.cnt()];
-          amp[y] = make_double2(amp[y].x * f, amp[y].y * f);
-          continue;
+          amp[y] = make_double2(am.x * f, am.y * f);
+        } else {
+          amp[y] = am;
+          uint8_t h = 0;
+          for (int j = 0; j < L.cnt() && !h; ++j) {
+            const uint32_t q = L.raw(j) & PList<ENC>::SM;
+            h = (uint8_t)((sm.cbm[q >> 5] >> (q & 31)) & 1u);
+          }
+          hitf[y] = h;
+          anyhit |= h;
         }
-        uint8_t h = 0;
-        for (int j = 0; j < L.cnt() && !h; ++j) {
-          const uint32_t q = L.raw(j) & PList<ENC>::SM;
-          h = (uint8_t)((sm.cbm[q >> 5] >> (q & 31)) & 1u);
-        }
-        hitf[y] = h;
-        anyhit |= h;
+        if (slab) rec_store(g, slab, rec);
       }
       if (nc == 0) continue;  // (the bitmap is already clean)
       anyhit = __syncthreads_or(anyhit);
@@ -636,8 +680,16 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
       // K_J on every explicit component: survivors carry J's sites at J's
       // levels (the good branches survive exactly when the reference does)
       for (uint32_t y = tid; y < E; y += nthr) {
-        PList<ENC> L{pool + (size_t)y * rec, lcap};
-        if (L.cnt() == PL_DEAD) continue;
+        uint16_t *const g = pool + (size_t)y * rec;
+        const int c0 = g[0];
+        if (c0 == PL_DEAD) continue;
+        if (nJ == 0) {  // K_0 on every component: a^|X|
+          const double f = apow[c0];
+          amp[y] = make_double2(amp[y].x * f, amp[y].y * f);
+          continue;
+        }
+        // (a jump changes few entries: the record is edited in place)
+        PList<ENC> L{g, lcap};
         bool ok = true;
         for (int c = 0; c < nJ && ok; ++c) {
           const uint32_t q = sm.J[c] & 0xFFFFu, lev = sm.J[c] >> 16;
@@ -645,7 +697,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
           ok = j >= 0 && ((ENC == QUTRIT && (L.raw(j) & LV_R_BIT)) ? 2u : 1u) == lev;
         }
         if (!ok) {
-          L.r[0] = PL_DEAD;
+          g[0] = PL_DEAD;
           amp[y] = make_double2(0.0, 0.0);
           continue;
         }
@@ -889,7 +941,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
 
 }  // namespace
 
-uint32_t plain_lds_bytes(int M) { return plain_sm_bytes(M); }
+uint32_t plain_lds_bytes(int M, uint32_t slab_words) { return plain_sm_head(M) + slab_words * 2u; }
 
 int plain_occupancy(int enc, int threads, uint32_t lds_bytes) {
   int blocks = 0;

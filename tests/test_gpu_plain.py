@@ -127,15 +127,57 @@ def test_plain_forced_histories(lib, orc, enc):
             assert st["q_ground"] == ref["q_ground"] and st["ref_survived"] == ref["ref_survived"]
 
 
-@pytest.mark.parametrize("per_cu", [1, 2, 4, 8])
-def test_plain_launch_shapes(lib, orc, per_cu):
+@pytest.mark.parametrize("per_cu,threads", [(1, 0), (2, 256), (4, 128), (8, 64), (32, 64), (3, 128)])
+def test_plain_launch_shapes(lib, orc, per_cu, threads):
     n, k, enc, gamma, nt = 5, 3, QUBIT, 0.03, 700
     mem = memory_words(n, k, 55)
     fo, fpo, so, _ = orc.run_batch(n, k, enc, gamma, mem, 99, 3, nt)
     with lib.QramContext(n, k, enc, gamma, mem) as ctx:
-        ctx.set_launch(PLAIN, per_cu, 0)
+        ctx.set_launch(PLAIN, per_cu, threads)
+        got = ctx.get_launch(PLAIN)
+        assert got[1] == (threads or got[1]) and 1 <= got[0] <= per_cu
         f, st = ctx.run_plain(99, 3, nt)
     check_against_oracle(f, st, fo, fpo, so, per_cu)
+
+
+def test_plain_engine_shapes_on_depolarizing_context(lib, orc):
+    """Both modes of a depolarizing context run on the plain engine; every
+    workgroup size gives the oracle's fidelities."""
+    n, k, enc, p, nt = 4, 2, QUBIT, 0.01, 600
+    mem = memory_words(n, k, 56)
+    fo, _, so, _ = orc.run_many(n, k, enc, p, mem, 31, 0, nt, eps=p)
+    with lib.QramContext(n, k, enc, p, mem, eps=p) as ctx:
+        for mode in (PRUNED, FULL):
+            for threads in (64, 128, 256):
+                ctx.set_launch(mode, 0, threads)
+                assert ctx.get_launch(mode)[1] == threads
+                f, st = (ctx.run_pruned if mode == PRUNED else ctx.run_full)(31, 0, nt)
+                assert np.all(np.abs(f - fo) <= 1e-12 * np.maximum(np.abs(fo), 1e-3)), (mode, threads)
+                assert np.array_equal(st["n_jumps"], so[:, 4].astype(np.uint16))
+        with pytest.raises(lib.QramError):
+            ctx.set_launch(PRUNED, 0, 96)
+        with pytest.raises(lib.QramError):
+            ctx.set_launch(FULL, 33, 64)
+
+
+@pytest.mark.parametrize("n,k,enc,p,threads", [(3, 2, QUBIT, 0.03, 256), (4, 3, QUBIT, 0.01, 64),
+                                               (3, 1, QUTRIT, 0.03, 128), (5, 2, QUTRIT, 0.005, 64)])
+def test_plain_record_paths(lib, orc, n, k, enc, p, threads):
+    """The records staged through shared memory and worked on in device
+    memory (QRAM_OPT_TIER2_GLOBAL, or the launch shape's device-memory bit)
+    give the oracle's results, with depolarizing strays lengthening the
+    lists, in both plain-engine modes."""
+    nt = 500
+    mem = memory_words(n, k, 60 + n)
+    fo, fpo, so, _ = orc.run_many(n, k, enc, p, mem, 17, 0, nt, eps=p)
+    with lib.QramContext(n, k, enc, p, mem, eps=p) as ctx:
+        for glob, sched in ((0, threads), (1, threads), (0, threads + 1)):
+            ctx.set_option(lib.qram.QRAM_OPT_TIER2_GLOBAL, glob)
+            for mode in (PRUNED, FULL):
+                ctx.set_launch(mode, 0, sched)
+                assert ctx.get_launch(mode)[1] == threads + (1 if glob or sched & 1 else 0)
+                f, st = (ctx.run_pruned if mode == PRUNED else ctx.run_full)(17, 0, nt)
+                check_against_oracle(f, st, fo, fpo, so, (glob, sched, mode))
 
 
 def test_plain_async_device_buffers(lib):
