@@ -142,7 +142,13 @@ qram_status qram_create(int n_addr, int k_data, qram_encoding enc, double gamma,
  * with eps > 0, a general input, truncation, or qubit k > 6 run every mode
  * on the plain engine: QRAM_MODE_FULL as QRAM_MODE_PLAIN, QRAM_MODE_PRUNED as Alg. 1 on
  * explicit site lists (bad branches plus the reference explicit, the good
- * branches carried by the reference's weights and final state).
+ * branches carried by the reference's weights and final state).  One
+ * exception: with eps > 0 on the data-loading input (qubit k <= 6), a
+ * pruned run hands every trajectory that drew no depolarizing fault to the
+ * trajectory kernel of the damping-only contexts (such a trajectory is a
+ * damping-only one: same candidates, bad set, draws and result), and only
+ * the others to the plain engine.  qram_export_state and qram_run_forced
+ * keep such contexts on the plain engine.
  */
 typedef struct {
   int n_addr, k_data;

@@ -41,8 +41,15 @@ struct Plan {
   // plain full evolution: one launch of `grid` workgroups, grid-stride over
   // the batch's trajectories
   bool plain = false;
+  // the plain engine's launch (plain plans, and the plain half of a split
+  // plan): workgroup shape in pb, shared memory per workgroup
+  BucketShape pb{};
   uint32_t plds = 0;
   bool pslab = false;  // records staged through shared memory
+  // split plan (pruned mode with depolarizing noise on the data-loading
+  // input): the trajectory kernel's buckets take the trajectories without a
+  // depolarizing fault, the plain engine the others
+  bool split = false;
 };
 
 struct qram_ctx {
@@ -50,6 +57,7 @@ struct qram_ctx {
   double gamma = 0.0;
   double eps = 0.0;       // depolarizing strength
   bool general = false;   // depolarizing noise or a general input: the plain engine runs every mode
+  bool dsplit = false;    // depolarizing noise only: pruned runs split by whether a trajectory drew a fault
   double *dcin = nullptr;  // general input amplitudes (device)
   uint32_t *djin = nullptr;
   double *dcab = nullptr, *dcamp = nullptr;  // pair amplitudes, component amplitudes
@@ -449,30 +457,36 @@ uint32_t plain_lds(const qram_ctx *c, int threads, bool glob) {
 // bucket.  The pruned mode's explicit work varies per trajectory (bad
 // addresses plus the reference), so trajectories are grouped by it, each
 // group with a workgroup size and LDS footprint sized for its largest member.
-qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
-  if (mode == QRAM_MODE_PLAIN || c->general) {
+// The plain engine's launch of a mode (pl.pb, plds, pslab).
+qram_status plain_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
+  int threads = 0, per_cu = 0;
+  bool glob = false;
+  plain_shape(c, mode, threads, per_cu, glob);
+  pl.plds = plain_lds(c, threads, glob);
+  pl.pslab = plain_slab(c, threads, glob);
+  const int occ = plain_occupancy(c->enc, threads, pl.plds);
+  if (occ < 1) return fail(c, QRAM_E_DEVICE, "plain engine: no workgroup fits a compute unit");
+  per_cu = std::min(per_cu, occ);
+  // every workgroup holds a trajectory's whole explicit state in device
+  // memory: keep the pool within PLAIN_POOL_BYTES
+  const double per_wg = (double)c->Emax * ((double)c->prec * 2.0 + 17.0) + (double)threads * c->K2 * 16.0;
+  const double fit = std::max(1.0, std::floor((double)PLAIN_POOL_BYTES / per_wg));
+  uint32_t grid = (uint32_t)std::min<double>((double)c->num_cu * per_cu, fit);
+  grid = std::max<uint32_t>(1u, std::min<uint32_t>(grid, ntraj));
+  pl.pb.threads = threads;
+  pl.pb.emax = (uint32_t)c->Emax;
+  pl.pb.grid = grid;
+  return QRAM_OK;
+}
+
+// split = false keeps a depolarizing context's pruned mode on the plain
+// engine alone (the test entries, which export one trajectory's state).
+qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl, bool split) {
+  const bool hybrid = split && c->dsplit && mode == QRAM_MODE_PRUNED;
+  if (mode == QRAM_MODE_PLAIN || (c->general && !hybrid)) {
     pl = Plan{};
     pl.plain = true;
-    pl.nb = 1;
-    int threads = 0, per_cu = 0;
-    bool glob = false;
-    plain_shape(c, mode, threads, per_cu, glob);
-    pl.plds = plain_lds(c, threads, glob);
-    pl.pslab = plain_slab(c, threads, glob);
-    const int occ = plain_occupancy(c->enc, threads, pl.plds);
-    if (occ < 1) return fail(c, QRAM_E_DEVICE, "plain engine: no workgroup fits a compute unit");
-    per_cu = std::min(per_cu, occ);
-    // every workgroup holds a trajectory's whole explicit state in device
-    // memory: keep the pool within PLAIN_POOL_BYTES
-    const double per_wg = (double)c->Emax * ((double)c->prec * 2.0 + 17.0) + (double)threads * c->K2 * 16.0;
-    const double fit = std::max(1.0, std::floor((double)PLAIN_POOL_BYTES / per_wg));
-    uint32_t grid = (uint32_t)std::min<double>((double)c->num_cu * per_cu, fit);
-    grid = std::max<uint32_t>(1u, std::min<uint32_t>(grid, ntraj));
-    pl.b[0].threads = threads;
-    pl.b[0].emax = (uint32_t)c->Emax;
-    pl.b[0].grid = grid;
-    pl.grid_max = grid;
-    return QRAM_OK;
+    return plain_plan(c, mode, ntraj, pl);
   }
   const int spt_target = c->spt[mode] ? c->spt[mode] : 16;
   std::vector<uint32_t> ems;
@@ -521,6 +535,10 @@ qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
     pl.grid_max = std::max(pl.grid_max, b.grid);
     pl.ecap_max = std::max(pl.ecap_max, b.state_lds ? 0u : b.e_cap);
   }
+  if (hybrid) {
+    pl.split = true;
+    return plain_plan(c, mode, ntraj, pl);
+  }
   return QRAM_OK;
 }
 
@@ -548,40 +566,39 @@ qram_status ensure_buffers(qram_ctx *c, uint32_t nb, const Plan *pl) {
   }
   if (!c->counter) {
     if ((st = dev_alloc(c, &c->counter, MAXB))) return st;
-    if ((st = dev_alloc(c, &c->bucket_base, MAXB + 1))) return st;
+    if ((st = dev_alloc(c, &c->bucket_base, MAXB + 2))) return st;
     if ((st = dev_alloc(c, &c->errw, 4))) return st;
     HIPCHK(c, hipMemset(c->errw, 0, 16));
   }
-  if (pl && pl->plain) {
-    const size_t g = pl->grid_max, E = (size_t)c->Emax;
-    if (g * E * c->prec > c->pool_cap) {
-      if ((st = dev_alloc(c, &c->pool, g * E * c->prec))) return st;
-      c->pool_cap = g * E * c->prec;
-    }
+  if (!pl) return QRAM_OK;
+  // the record pool serves the plain engine and the trajectory kernel (one
+  // after the other in a split batch): sized for the larger
+  size_t ps = 0;
+  if (pl->plain || pl->split) {
+    const size_t g = pl->pb.grid, E = (size_t)c->Emax;
+    ps = g * E * c->prec;
     if ((st = grow(c, &c->pamp, &c->pamp_cap, g * E * 2))) return st;
     if ((st = grow(c, &c->phit, &c->phit_cap, g * E))) return st;
-    if ((st = grow(c, &c->pgrp, &c->pgrp_cap, g * (size_t)pl->b[0].threads * c->K2 * 2))) return st;
-    return QRAM_OK;
+    if ((st = grow(c, &c->pgrp, &c->pgrp_cap, g * (size_t)pl->pb.threads * c->K2 * 2))) return st;
   }
-  if (pl) {
+  if (!pl->plain) {
     const size_t gs = (size_t)pl->grid_max * pl->ecap_max;
     if (gs > c->gstate_cap) {
       if ((st = dev_alloc(c, &c->gstate, gs))) return st;
       c->gstate_cap = gs;
     }
-    size_t ps = 0;
     for (int i = 0; i < pl->nb; ++i)
       ps = std::max(ps, (size_t)pl->b[i].grid * pl->b[i].emax * c->rec);
-    if (ps > c->pool_cap) {
-      if ((st = dev_alloc(c, &c->pool, ps))) return st;
-      c->pool_cap = ps;
-    }
     size_t ds = 0;
     for (int i = 0; i < pl->nb; ++i) ds = std::max(ds, (size_t)pl->b[i].grid * pl->b[i].emax);
     if (ds > c->devl_cap) {
       if ((st = dev_alloc(c, &c->devl, ds))) return st;
       c->devl_cap = ds;
     }
+  }
+  if (ps > c->pool_cap) {
+    if ((st = dev_alloc(c, &c->pool, ps))) return st;
+    c->pool_cap = ps;
   }
   return QRAM_OK;
 }
@@ -593,15 +610,18 @@ size_t buffers_bytes(const qram_ctx *c, uint32_t nb, const Plan &pl) {
   size_t b = n * cand_capacity(c) * 4 + n * 5 * 4 + n * 8 + n * ((c->D + 63) / 64) * 8 + n * c->D * 2;
   b += n * ((size_t)dep_capacity(c) + 1) * 4;
   b += (2 * MAXB + 1 + 4) * 4;
-  if (pl.plain) {
-    const size_t g = pl.grid_max, E = (size_t)c->Emax;
-    return b + g * E * ((size_t)c->prec * 2 + 16 + 1) + g * (size_t)pl.b[0].threads * c->K2 * 16;
+  size_t ps = 0, ds = 0;  // pool words, list-index words
+  if (pl.plain || pl.split) {
+    const size_t g = pl.pb.grid, E = (size_t)c->Emax;
+    ps = g * E * c->prec;
+    b += g * E * (16 + 1) + g * (size_t)pl.pb.threads * c->K2 * 16;
   }
-  b += (size_t)pl.grid_max * pl.ecap_max * 4;
-  size_t ps = 0, ds = 0;
-  for (int i = 0; i < pl.nb; ++i) {
-    ps = std::max(ps, (size_t)pl.b[i].grid * pl.b[i].emax * c->rec);
-    ds = std::max(ds, (size_t)pl.b[i].grid * pl.b[i].emax);
+  if (!pl.plain) {
+    b += (size_t)pl.grid_max * pl.ecap_max * 4;
+    for (int i = 0; i < pl.nb; ++i) {
+      ps = std::max(ps, (size_t)pl.b[i].grid * pl.b[i].emax * c->rec);
+      ds = std::max(ds, (size_t)pl.b[i].grid * pl.b[i].emax);
+    }
   }
   return b + ps * 2 + ds * 4;
 }
@@ -612,7 +632,7 @@ size_t table_bytes(const qram_ctx *c) {
 }
 
 uint32_t batch_size(const qram_ctx *c, uint32_t ntraj);
-qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl);
+qram_status make_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl, bool split = true);
 
 uint32_t batch_size(const qram_ctx *c, uint32_t ntraj) {
   // keep the per-trajectory buffers within about 2 GiB
@@ -659,6 +679,7 @@ Run base_run(qram_ctx *c, int mode, uint64_t seed, const Plan *pl) {
   }
   r.prec = (uint32_t)c->prec;
   if (pl) r.pslab = pl->pslab ? 1u : 0u;
+  if (pl) r.dsplit = pl->split ? 1u : 0u;
   r.pamp = c->pamp;
   r.phit = c->phit;
   r.pgrp = c->pgrp;
@@ -716,10 +737,12 @@ qram_status enqueue_batch(qram_ctx *c, const Plan &pl, Run r, hipStream_t s,
   if (!pl.plain) HIPCHK(c, launch_order(c->dtab, r, s));
   if (timed) HIPCHK(c, hipEventRecord(e[2], s));
   if (pl.plain) {
-    HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.b[0].grid, pl.b[0].threads, pl.plds, s));
+    HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.pb.grid, pl.pb.threads, pl.plds, s));
   } else {
     qram_status st = launch_buckets(c, pl, r, s, be);
     if (st) return st;
+    if (pl.split)  // the trajectories that drew a depolarizing fault
+      HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.pb.grid, pl.pb.threads, pl.plds, s));
   }
   if (timed) HIPCHK(c, hipEventRecord(e[3], s));
   return QRAM_OK;
@@ -740,7 +763,11 @@ uint64_t plan_signature(const Plan &pl) {
   };
   mix((uint64_t)pl.nb);
   mix(pl.plain ? 1u : 0u);
+  mix(pl.split ? 1u : 0u);
   mix(pl.plds);
+  mix(pl.pslab ? 1u : 0u);
+  mix((uint64_t)pl.pb.threads);
+  mix(pl.pb.grid);
   for (int i = 0; i < pl.nb; ++i) {
     const BucketShape &b = pl.b[i];
     mix(b.emax);
@@ -963,6 +990,10 @@ qram_status qram_create_ex(const qram_params *p, qram_ctx **out) {
   // to six qubit data bits; everything else runs on the plain engine
   c->general = eps > 0.0 || p->input_amp || p->input_bus || p->input_ab || p->truncate ||
                (c->enc == QUBIT && k_data > 6);
+  // a trajectory that drew no depolarizing fault is a damping-only one: on
+  // the data-loading input the trajectory kernel runs it
+  c->dsplit = eps > 0.0 && !p->input_amp && !p->input_bus && !p->input_ab && !p->truncate &&
+              !(c->enc == QUBIT && k_data > 6);
   c->T = 6 * n_addr + 2 * k_data;
   c->M = 2 * ((1 << n_addr) - 1);
   c->D = 1 << n_addr;
@@ -1638,8 +1669,9 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
       HIPCHK(c, launch_sample(c->dtab, r, nt, sample_grid(c, nt), c->stream));
       if (r.dep) HIPCHK(c, launch_sample_depol(c->dtab, r, sample_grid(c, nt), c->stream));
       HIPCHK(c, launch_classify(c->dtab, r, nt, sample_grid(c, nt), c->D, c->mark_subtree, c->stream));
+      if (pl.split) HIPCHK(c, launch_order(c->dtab, r, c->stream));  // (the plain engine's share)
       HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
-      HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.b[0].grid, pl.b[0].threads, pl.plds, c->stream));
+      HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.pb.grid, pl.pb.threads, pl.plds, c->stream));
       HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
       HIPCHK(c, hipEventSynchronize(c->ev[1]));
       float ms;
@@ -1800,7 +1832,7 @@ static qram_status run_single(qram_ctx *c, int mode, uint64_t seed, uint32_t tra
   const size_t ncomp = (size_t)c->D * c->K2;
   if (h_exp && exp_cap < ncomp) return fail(c, QRAM_E_CAPACITY, "the export needs one record per component (2^n * 2^k or 2^n)");
   Plan pl;
-  if ((st = make_plan(c, mode, 1, pl))) return st;
+  if ((st = make_plan(c, mode, 1, pl, false))) return st;
   if ((st = ensure_buffers(c, 1, &pl))) return st;
   if (forced && ncand > c->cand_cap) {
     if ((st = dev_alloc(c, &c->cand, ncand))) return st;

@@ -119,7 +119,7 @@ struct Run {
   uint16_t *xlist;       // [ntraj * D] explicit addresses (pruned)
   uint32_t *nexpl;       // [ntraj] explicit components
   uint32_t *order;       // [ntraj] trajectories grouped by bucket
-  uint32_t *bucket_base; // [MAXB + 1]
+  uint32_t *bucket_base; // [MAXB + 2] (the last: end of a split run's plain-engine segment)
   uint32_t *counter;     // [MAXB] queue heads
   uint32_t *gstate;      // [grid * e_cap] tier-1 words when not in LDS
   uint16_t *pool;        // [grid * pool_slots * rec] tier-2 records
@@ -144,6 +144,10 @@ struct Run {
   // words each), amplitudes, hit flags and finalize scratch
   uint32_t prec;
   uint32_t pslab;        // 1: each thread stages the record it works on in shared memory
+  // 1 (pruned runs with depolarizing noise): the trajectory kernel takes the
+  // trajectories that drew no depolarizing fault (ndep 0), the plain engine
+  // the others, which k_order lists after every bucket
+  uint32_t dsplit;
   double *pamp;          // [grid * E * 2]
   uint8_t *phit;         // [grid * E]
   double *pgrp;          // [grid * threads * K2 * 2]

@@ -328,25 +328,31 @@ __global__ void __launch_bounds__(256) k_classify(const Tables *__restrict__ tb,
 // ---------------------------------------------------------------------------
 // k_order: bucket b admits trajectories with at most bkt_emax[b] explicit
 // components; inside a bucket trajectories are ordered by decreasing log2 of
-// their work.  One workgroup.
+// their work.  In a split run the trajectories that drew a depolarizing
+// fault go to a segment of their own after every bucket, [bucket_base[MAXB],
+// bucket_base[MAXB + 1]), which the plain engine takes.  One workgroup.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_order(const Run R_) {
   const Run *rp = &R_;
   constexpr int NF = 33;  // log2 bins inside a bucket
-  __shared__ uint32_t hist[MAXB * NF];
-  __shared__ uint32_t base[MAXB * NF];
+  constexpr int XF = MAXB * NF;  // the split run's plain-engine bin
+  __shared__ uint32_t hist[XF + 1];
+  __shared__ uint32_t base[XF + 1];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const uint32_t nt = rp->ntraj;
   const uint32_t nb = rp->nbkt;
-  for (int i = tid; i < MAXB * NF; i += nthr) hist[i] = 0;
+  const bool split = rp->dsplit != 0;
+  for (int i = tid; i <= XF; i += nthr) hist[i] = 0;
   __syncthreads();
-  auto key = [&](uint32_t e) -> int {
+  auto key = [&](uint32_t t) -> int {
+    if (split && rp->ndep[t] != 0) return XF;
+    const uint32_t e = rp->nexpl[t];
     uint32_t b = 0;
     while (b + 1 < nb && e > rp->bkt_emax[b]) ++b;
     const int f = 32 - __clz(e);  // larger work -> earlier
     return (int)b * NF + (NF - 1 - f);
   };
-  for (uint32_t t = tid; t < nt; t += nthr) atomicAdd(&hist[key(rp->nexpl[t])], 1u);
+  for (uint32_t t = tid; t < nt; t += nthr) atomicAdd(&hist[key(t)], 1u);
   __syncthreads();
   if (tid == 0) {
     uint32_t acc = 0;
@@ -359,10 +365,12 @@ __global__ void __launch_bounds__(1024) k_order(const Run R_) {
       rp->counter[b] = 0;
     }
     rp->bucket_base[MAXB] = acc;
+    base[XF] = acc;
+    if (split) rp->bucket_base[MAXB + 1] = acc + hist[XF];
   }
   __syncthreads();
   for (uint32_t t = tid; t < nt; t += nthr) {
-    const uint32_t o = atomicAdd(&base[key(rp->nexpl[t])], 1u);
+    const uint32_t o = atomicAdd(&base[key(t)], 1u);
     rp->order[o] = t;
   }
 }

@@ -362,12 +362,17 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
   for (int w = tid; w < (M + 31) / 32; w += nthr) sm.cbm[w] = 0u;
 
   // trajectories from a device queue (counter[0], cleared before the
-  // launch): a workgroup that drew short ones takes more
+  // launch): a workgroup that drew short ones takes more.  A split run
+  // queues only the trajectories that drew a depolarizing fault (their
+  // segment of the order); the trajectory kernel runs the others.
+  const uint32_t q0 = rp->dsplit ? rp->bucket_base[MAXB] : 0u;
+  const uint32_t qn = rp->dsplit ? rp->bucket_base[MAXB + 1] - q0 : rp->ntraj;
   for (;;) {
     if (tid == 0) sm.misc[12] = (int)atomicAdd(&rp->counter[0], 1u);
     __syncthreads();  // (misc[12] is written again only after the trajectory's last barrier)
-    const uint32_t tj = (uint32_t)sm.misc[12];
-    if (tj >= rp->ntraj) break;
+    const uint32_t slot = (uint32_t)sm.misc[12];
+    if (slot >= qn) break;
+    const uint32_t tj = rp->dsplit ? rp->order[q0 + slot] : slot;
     const uint32_t traj = rp->traj0 + tj;
     const uint32_t nct = min(rp->ncand[tj], ccap);
     const uint32_t *__restrict__ cand = rp->cand + (size_t)tj * ccap;

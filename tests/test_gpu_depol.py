@@ -241,3 +241,28 @@ def test_pruned_equals_plain_many_trajectories(lib, orc, n, k, enc, p, nt):
     idx = np.unique(np.concatenate([np.arange(64), [3269 % nt]]))
     fo, fpo, so, _ = orc.run_many(n, k, enc, p, mem, 880007, idx=idx, eps=p, nthreads=16)
     assert np.all(fid_close(fp[idx], fo))
+
+@pytest.mark.parametrize("enc", [QUBIT, QUTRIT])
+def test_split_pruned_run(lib, orc, enc):
+    """Depolarizing noise on the data-loading input: a pruned run hands the
+    trajectories that drew no fault to the trajectory kernel (they are
+    damping-only trajectories) and the others to the plain engine.  Both
+    halves match the oracle (fidelities, statistics, jump decisions) and the
+    plain full evolution."""
+    n, k, p, nt, jcap = 4, 2, 0.004, 400, 32
+    mem = memory_words(n, k, 91)
+    fo, fpo, so, _ = orc.run_many(n, k, enc, p, mem, 23, 0, nt, eps=p)
+    nf = np.array([len(orc.sample_depol(n, k, enc, p, 23, t)[0]) for t in range(nt)])
+    assert 0 < int((nf == 0).sum()) < nt
+    with lib.QramContext(n, k, enc, p, mem, eps=p) as ctx:
+        f, st, jl, njl = ctx.run_jumplog(PRUNED, 23, 0, nt, jcap)
+        check_stats(f, st, fo, fpo, so, ("split", enc))
+        ff, _ = ctx.run_full(23, 0, nt)
+        assert np.all(fid_close(f, ff))
+    seen = [0, 0]
+    for t in range(nt):
+        ref = orc.run_traj(n, k, enc, p, mem, seed=23, traj=t, eps=p)["jumps"]
+        assert njl[t] == len(ref), t
+        assert decode_jlog(jl[t, :min(njl[t], jcap)]) == sorted(ref)[:jcap], t
+        seen[int(nf[t] > 0)] += len(ref) > 0
+    assert seen[0] > 0 and seen[1] > 0  # jumps on both halves
