@@ -45,7 +45,7 @@ struct Plan {
   // plan): workgroup shape in pb, shared memory per workgroup
   BucketShape pb{};
   uint32_t plds = 0;
-  bool pslab = false;  // records staged through shared memory
+  uint32_t pslab = 0;  // words of each thread's record slab in shared memory (0: none)
   // split plan (pruned mode with depolarizing noise on the data-loading
   // input): the trajectory kernel's buckets take the trajectories without a
   // depolarizing fault, the plain engine the others
@@ -444,13 +444,18 @@ void plain_shape(const qram_ctx *c, int mode, int &threads, int &per_cu, bool &g
 }
 
 // Shared memory of a plain-engine workgroup of `threads`: the slice state,
-// and a record slab per thread unless the records stay in device memory
-// (asked for, QRAM_OPT_TIER2_GLOBAL, or slabs beyond PLAIN_SLAB_BYTES).
-bool plain_slab(const qram_ctx *c, int threads, bool glob) {
-  return !glob && !c->tier2_global && (size_t)threads * c->prec * 2 <= PLAIN_SLAB_BYTES;
+// and a record slab per thread (words; 0 when the records stay in device
+// memory: asked for, QRAM_OPT_TIER2_GLOBAL, or a slab within
+// PLAIN_SLAB_BYTES that is shorter than both the record and 32 words).  A
+// slab shorter than the record capacity (which counts every depolarizing
+// stray a trajectory may hold) takes the records that fit it.
+uint32_t plain_slab(const qram_ctx *c, int threads, bool glob) {
+  if (glob || c->tier2_global) return 0;
+  const uint32_t sw = std::min<uint32_t>((uint32_t)c->prec, (PLAIN_SLAB_BYTES / 2u / (uint32_t)threads) & ~7u);
+  return (sw == (uint32_t)c->prec || sw >= 32u) ? sw : 0u;
 }
 uint32_t plain_lds(const qram_ctx *c, int threads, bool glob) {
-  return plain_lds_bytes(c->M, plain_slab(c, threads, glob) ? (uint32_t)(threads * c->prec) : 0u);
+  return plain_lds_bytes(c->M, (uint32_t)threads * plain_slab(c, threads, glob));
 }
 
 // Launch plan of a mode.  The full mode evolves every address, so it has one
@@ -678,7 +683,7 @@ Run base_run(qram_ctx *c, int mode, uint64_t seed, const Plan *pl) {
     r.dep_cap = c->dep_cap;
   }
   r.prec = (uint32_t)c->prec;
-  if (pl) r.pslab = pl->pslab ? 1u : 0u;
+  if (pl) r.pslab = pl->pslab;
   if (pl) r.dsplit = pl->split ? 1u : 0u;
   r.pamp = c->pamp;
   r.phit = c->phit;
@@ -765,7 +770,7 @@ uint64_t plan_signature(const Plan &pl) {
   mix(pl.plain ? 1u : 0u);
   mix(pl.split ? 1u : 0u);
   mix(pl.plds);
-  mix(pl.pslab ? 1u : 0u);
+  mix(pl.pslab);
   mix((uint64_t)pl.pb.threads);
   mix(pl.pb.grid);
   for (int i = 0; i < pl.nb; ++i) {
@@ -1595,7 +1600,7 @@ qram_status qram_get_launch(const qram_ctx *c, qram_mode mode,
     plain_shape(c, mode, threads, per_cu, glob);
     const int occ = plain_occupancy(c->enc, threads, plain_lds(c, threads, glob));
     *slots_per_thread = occ > 0 ? std::min(per_cu, occ) : per_cu;
-    *schedule = threads + (plain_slab(c, threads, glob) ? 0 : 1);
+    *schedule = threads + (plain_slab(c, threads, glob) ? 0 : 1);  // (+1: records in device memory)
     return QRAM_OK;
   }
   *slots_per_thread = c->spt[mode] ? c->spt[mode] : 16;

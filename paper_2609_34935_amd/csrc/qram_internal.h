@@ -143,7 +143,7 @@ struct Run {
   // plain full evolution: per-workgroup component lists (pool, prec uint16
   // words each), amplitudes, hit flags and finalize scratch
   uint32_t prec;
-  uint32_t pslab;        // 1: each thread stages the record it works on in shared memory
+  uint32_t pslab;        // words of each thread's record slab in shared memory (0: none)
   // 1 (pruned runs with depolarizing noise): the trajectory kernel takes the
   // trajectories that drew no depolarizing fault (ndep 0), the plain engine
   // the others, which k_order lists after every bucket

@@ -251,13 +251,16 @@ __device__ inline PlainSm plain_carve(unsigned char *base, int M) {
   return s;
 }
 
-// A record (rec words, a multiple of 8) copied between the pool and a
-// thread's slab in 16-byte pieces: the count and bus word and the sites in
-// use.  The first pieces are loaded together, before the count is known.
-__device__ __forceinline__ void rec_load(uint16_t *dst, const uint16_t *__restrict__ src, int rec) {
+// A record copied from the pool into a thread's slab (sw words, a multiple
+// of 8) in 16-byte pieces: the count and bus word and the sites in use.  The
+// first pieces are loaded together, before the count is known.  A record
+// is staged only when it fits the slab with `margin` words to spare (the
+// most a slice's gates and faults can add); returns false, having copied
+// only the first pieces, when it does not.
+__device__ __forceinline__ bool rec_load(uint16_t *dst, const uint16_t *__restrict__ src, int sw, int margin) {
   const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
   uint4 *d4 = reinterpret_cast<uint4 *>(dst);
-  const int nv_all = rec >> 3;
+  const int nv_all = sw >> 3;
   const uint4 v0 = s4[0];
   const uint4 v1 = nv_all > 1 ? s4[1] : v0;
   const uint4 v2 = nv_all > 2 ? s4[2] : v0;
@@ -267,8 +270,9 @@ __device__ __forceinline__ void rec_load(uint16_t *dst, const uint16_t *__restri
   if (nv_all > 2) d4[2] = v2;
   if (nv_all > 3) d4[3] = v3;
   const uint32_t c = v0.x & 0xFFFFu;
-  if (c == PL_DEAD) return;
-  const int nv = min(nv_all, (int)(2 + c + 7) >> 3);
+  if (c == PL_DEAD) return true;
+  if ((int)(2 + c) + margin > sw) return false;
+  const int nv = (int)(2 + c + 7) >> 3;
   for (int i = 4; i < nv; i += 4) {  // longer lists: four pieces in flight at a time
     const uint4 w0 = s4[i];
     const uint4 w1 = i + 1 < nv ? s4[i + 1] : w0;
@@ -279,13 +283,14 @@ __device__ __forceinline__ void rec_load(uint16_t *dst, const uint16_t *__restri
     if (i + 2 < nv) d4[i + 2] = w2;
     if (i + 3 < nv) d4[i + 3] = w3;
   }
+  return true;
 }
 
-__device__ __forceinline__ void rec_store(uint16_t *__restrict__ dst, const uint16_t *src, int rec) {
+__device__ __forceinline__ void rec_store(uint16_t *__restrict__ dst, const uint16_t *src, int sw) {
   const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
   uint4 *d4 = reinterpret_cast<uint4 *>(dst);
   const uint32_t c = src[0];
-  const int nv = c == PL_DEAD ? 1 : min(rec >> 3, (int)(2 + c + 7) >> 3);
+  const int nv = c == PL_DEAD ? 1 : min(sw >> 3, (int)(2 + c + 7) >> 3);
   for (int i = 0; i < nv; ++i) d4[i] = s4[i];
 }
 
@@ -357,8 +362,10 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
   const double sg = tb->sg;
   const uint32_t ccap = rp->cand_cap;
   // the record this thread works on: staged in its slab of shared memory
-  // (the gates' list scans then stay on chip), else worked on in the pool
-  uint16_t *const slab = rp->pslab ? sm.slab + (size_t)tid * rec : nullptr;
+  // (sw words; the gates' list scans then stay on chip) when it fits, else
+  // worked on in the pool
+  const int sw = (int)rp->pslab;
+  uint16_t *const slab = sw ? sm.slab + (size_t)tid * sw : nullptr;
   for (int w = tid; w < (M + 31) / 32; w += nthr) sm.cbm[w] = 0u;
 
   // trajectories from a device queue (counter[0], cleared before the
@@ -510,10 +517,13 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
       // gates and faults, then (without candidates) K0 at once; with
       // candidates the hit test of every component against the slice's set
       int anyhit = 0;
+      // a slice adds at most: qubit, the copy and bus-swap sites; qutrit,
+      // those and one per gated node of a store and of a fetch; one per fault
+      const int margin = (ENC == QUTRIT ? 2 + 2 * PL_GATED : 2) + (int)(dpos - d0);
       for (uint32_t y = tid; y < E; y += nthr) {
         uint16_t *const g = pool + (size_t)y * rec;
-        if (slab) rec_load(slab, g, rec);
-        PList<ENC> L{slab ? slab : g, lcap};
+        const bool staged = slab && rec_load(slab, g, sw, margin);
+        PList<ENC> L = staged ? PList<ENC>{slab, sw - 2} : PList<ENC>{g, lcap};
         if (L.cnt() == PL_DEAD) continue;
         const uint32_t a = xl ? xl[y >> kb] : (y >> kb);
         double2 am = amp[y];
@@ -535,7 +545,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
           hitf[y] = h;
           anyhit |= h;
         }
-        if (slab) rec_store(g, slab, rec);
+        if (staged) rec_store(g, slab, sw);
       }
       if (nc == 0) continue;  // (the bitmap is already clean)
       anyhit = __syncthreads_or(anyhit);

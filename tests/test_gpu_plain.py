@@ -161,12 +161,16 @@ def test_plain_engine_shapes_on_depolarizing_context(lib, orc):
 
 
 @pytest.mark.parametrize("n,k,enc,p,threads", [(3, 2, QUBIT, 0.03, 256), (4, 3, QUBIT, 0.01, 64),
-                                               (3, 1, QUTRIT, 0.03, 128), (5, 2, QUTRIT, 0.005, 64)])
+                                               (3, 1, QUTRIT, 0.03, 128), (5, 2, QUTRIT, 0.005, 64),
+                                               (7, 3, QUBIT, 0.002, 256), (4, 2, QUTRIT, 0.03, 256)])
 def test_plain_record_paths(lib, orc, n, k, enc, p, threads):
     """The records staged through shared memory and worked on in device
     memory (QRAM_OPT_TIER2_GLOBAL, or the launch shape's device-memory bit)
     give the oracle's results, with depolarizing strays lengthening the
-    lists, in both plain-engine modes."""
+    lists, in both plain-engine modes.  The slabs cover: whole records;
+    records longer than a slab (n = 7 at 256 threads); qutrit lists that
+    leave too little room for a slice's growth and stay in device memory
+    (n = 3, 4)."""
     nt = 500
     mem = memory_words(n, k, 60 + n)
     fo, fpo, so, _ = orc.run_many(n, k, enc, p, mem, 17, 0, nt, eps=p)
