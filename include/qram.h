@@ -266,11 +266,13 @@ qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,
  * number of workgroups per compute unit (1..32, capped by what fits; 0 =
  * automatic: all that fit) and schedule the threads per workgroup (64, 128
  * or 256; 0 = automatic: 256, or 64 (pruned) / 128 (full) when a trajectory
- * holds at most 256 components), plus 1 to work on each component record in
- * device memory instead of staging it in shared memory while a thread
- * applies a slice's gates to it.  The launch also stays within 16 GiB of
- * per-trajectory state.  qram_get_launch returns the shape in use.  The
- * shape changes only the speed:
+ * holds at most 256 components and the run is not split), plus 1 to work on
+ * each component record in device memory instead of staging it in shared
+ * memory while a thread applies a slice's gates to it.  The launch stays
+ * within 16 GiB of per-trajectory state, and the plain share of a split
+ * pruned run takes at most 1.5 times its expected number of trajectories in
+ * workgroups.  qram_get_launch returns the shape in use.  The shape changes
+ * only the speed:
  * results are identical across shapes up to the rounding of the per-slice
  * weight sums.
  */
@@ -317,7 +319,9 @@ qram_status qram_set_option(qram_ctx *ctx, int option, int value);
  * HBM traffic.  On the plain engine it tries 64, 128 and 256 threads per
  * workgroup, each with all, half and a quarter of the workgroups that fit a
  * compute unit, with the records staged in shared memory and in device
- * memory.  best_ms receives the kept shape's time.
+ * memory, on the first 16384 trajectories of the sample, best of two (a
+ * split pruned run is timed whole: ordering, the trajectory kernel's buckets
+ * and the plain share).  best_ms receives the kept shape's time.
  */
 qram_status qram_autotune(qram_ctx *ctx, qram_mode mode, uint64_t seed,
                           uint64_t traj0, uint32_t ntraj, double *best_ms);
