@@ -639,7 +639,7 @@ size_t buffers_bytes(const qram_ctx *c, uint32_t nb, const Plan &pl) {
 }
 
 size_t table_bytes(const qram_ctx *c) {
-  return (size_t)c->D * 4 + (size_t)(2 * c->emax + 1) * 8 * 2 + sizeof(Tables) + (size_t)(MAXT + 1) * 8 +
+  return (size_t)c->D * 4 + (size_t)(c->emax + std::max(c->emax, c->prec) + 1) * 8 * 2 + sizeof(Tables) + (size_t)(MAXT + 1) * 8 +
          (size_t)2 * c->T * (97 + (1 << c->k)) * 8;
 }
 
@@ -1021,7 +1021,8 @@ qram_status qram_create_ex(const qram_params *p, qram_ctx **out) {
   // record: count, bus word, lmax sites (+ the data tokens' sites and the
   // split set of a shared qubit list)
   c->rec = (c->lmax + 2 + (c->enc == QUBIT ? k_data + 1 : 0) + 1) & ~1;
-  c->prec = (c->lmax + PLAIN_EXTRA + 2 + 7) & ~7;  // (16-byte records)
+  // plain-engine record: count, bus word, exposure, phase, sites (16-byte records)
+  c->prec = (c->lmax + PLAIN_EXTRA + 4 + 7) & ~7;
   const double lw = c->emax * std::log(1.0 - gamma);
   if (lw < -690.0) {
     delete c;
@@ -1060,7 +1061,7 @@ qram_status qram_create_ex(const qram_params *p, qram_ctx **out) {
   // trajectory's fault capacity beyond lmax
   if (c->eps > 0.0)
     c->prec = (int)((std::min<uint32_t>((uint32_t)(c->lmax + PLAIN_EXTRA) + dep_capacity(c), (uint32_t)(c->M + c->lmax)) +
-                     2u + 7u) & ~7u);
+                     4u + 7u) & ~7u);
 
   auto bail = [&](qram_status st) {
     std::string m = c->err;
@@ -1084,9 +1085,12 @@ qram_status qram_create_ex(const qram_params *p, qram_ctx **out) {
     if (hipEventCreate(&e) != hipSuccess) return bail(fail(c, QRAM_E_DEVICE, "event creation failed"));
   qram_status st;
   if ((st = dev_alloc(c, &c->dmem, c->D))) return bail(st);
-  std::vector<double> wp(2 * c->emax + 1), ap(2 * c->emax + 1);
+  // exponents -emax .. phi: phi covers a plain-engine list's length too,
+  // which with depolarizing strays can exceed emax
+  const int phi = std::max(c->emax, c->prec);
+  std::vector<double> wp(c->emax + phi + 1), ap(c->emax + phi + 1);
   const double a = std::sqrt(1.0 - gamma);
-  for (int m = 0; m <= 2 * c->emax; ++m) {
+  for (int m = 0; m <= c->emax + phi; ++m) {
     wp[m] = std::pow(1.0 - gamma, (double)(m - c->emax));
     ap[m] = std::pow(a, (double)(m - c->emax));
   }

@@ -59,8 +59,8 @@ struct Tables {
   int n, k, enc, T, M, D, K2, lmax, emax, rec;  // rec = pool record length (even)
   uint64_t G[64];                 // geometric-walk thresholds
   const uint32_t *mem;            // [D] memory words
-  const double *wpow;             // [2 emax + 1] (1-gamma)^(m - emax)
-  const double *apow;             // [2 emax + 1] a^(m - emax)
+  const double *wpow;             // [emax + max(emax, prec) + 1] (1-gamma)^(m - emax)
+  const double *apow;             // [emax + max(emax, prec) + 1] a^(m - emax)
   const double *ftab_w;           // [(T + 1) * nfs] per-slice factor tables, (1-gamma)^e
   const double *ftab_a;           // the same with a^e
   int nfs;                        // entries per slice: 96 address-chunk, 2^k data, 1 router

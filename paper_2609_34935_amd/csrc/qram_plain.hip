@@ -21,9 +21,16 @@ namespace {
 constexpr int PL_GATED = 16;  // gated nodes of one qutrit store / fetch at most
 
 // Explicit site list of one component in the workgroup's pool: [0] count
-// (PL_DEAD once annihilated), [1] bus word, [2 ..] sites; a qutrit router
-// site carries its level in bit 15 (set: R, clear: L).
+// (PL_DEAD once annihilated), [1] bus word, [2] exposure e, [3] phase
+// index, [4 ..] sites; a qutrit router site carries its level in bit 15
+// (set: R, clear: L).  The component's amplitude is the stored complex
+// number times a^e times (-1)^(ph & 1) w3^(ph >> 1): the damping factors
+// a^|X| of the slices and the phases of the gates and faults are counted
+// in the record and multiplied in where an amplitude is needed (the draw's
+// weights, a jump, the final sums), so that a slice without a jump does
+// not touch the amplitude.
 constexpr uint16_t PL_DEAD = 0xFFFFu;
+constexpr int PL_HDR = 4;  // header words before the sites
 
 template <int ENC>
 struct PList {
@@ -31,16 +38,16 @@ struct PList {
   int cap;
   static constexpr uint32_t SM = ENC == QUTRIT ? 0x7FFFu : 0xFFFFu;
   __device__ __forceinline__ int cnt() const { return r[0]; }
-  __device__ __forceinline__ uint32_t raw(int j) const { return r[2 + j]; }
+  __device__ __forceinline__ uint32_t raw(int j) const { return r[PL_HDR + j]; }
   __device__ __forceinline__ int find(uint32_t q) const {
     const int c = r[0];
     for (int j = 0; j < c; ++j)
-      if ((r[2 + j] & SM) == q) return j;
+      if ((r[PL_HDR + j] & SM) == q) return j;
     return -1;
   }
   __device__ __forceinline__ void remove(int j) {
     const int c = r[0] - 1;
-    r[2 + j] = r[2 + c];
+    r[PL_HDR + j] = r[PL_HDR + c];
     r[0] = (uint16_t)c;
   }
   __device__ __forceinline__ void add(uint32_t x, uint32_t *err) {
@@ -49,7 +56,7 @@ struct PList {
       atomicOr(err, ERR_LIST);
       return;
     }
-    r[2 + c] = (uint16_t)x;
+    r[PL_HDR + c] = (uint16_t)x;
     r[0] = (uint16_t)(c + 1);
   }
   __device__ __forceinline__ void toggle(uint32_t q, uint32_t *err) {
@@ -64,7 +71,7 @@ struct PList {
     const int j = find(2 * v);
     if (ENC == QUBIT) return j >= 0 ? 1 : 0;
     if (j < 0) return -1;
-    return (r[2 + j] & LV_R_BIT) ? 1 : 0;
+    return (r[PL_HDR + j] & LV_R_BIT) ? 1 : 0;
   }
 };
 
@@ -104,7 +111,7 @@ __device__ bool plain_gates(const Tables *__restrict__ tb, int s, PList<ENC> L, 
     if (ENC == QUBIT) {  // SWAP(a_v, d_v) on every node of the layer
       for (int j = 0; j < L.cnt(); ++j) {
         const uint32_t q = L.raw(j);
-        if (layer_of(q >> 1) == sl) L.r[2 + j] = (uint16_t)(q ^ 1u);
+        if (layer_of(q >> 1) == sl) L.r[PL_HDR + j] = (uint16_t)(q ^ 1u);
       }
     } else {  // (W,b) <-> (L or R by b, 0) on the gated nodes
       uint32_t gv[PL_GATED];
@@ -136,11 +143,11 @@ __device__ bool plain_gates(const Tables *__restrict__ tb, int s, PList<ENC> L, 
       const int l = layer_of(v);
       if ((cm >> l) & 1u) {
         const int d = L.dir(v);
-        if (d >= 0) L.r[2 + j] = (uint16_t)(2 * (2 * v + 1 + (uint32_t)d) + 1);
+        if (d >= 0) L.r[PL_HDR + j] = (uint16_t)(2 * (2 * v + 1 + (uint32_t)d) + 1);
       } else if (l >= 1 && ((cm >> (l - 1)) & 1u)) {
         const uint32_t p = (v - 1) >> 1;
         const int d = L.dir(p);
-        if (d >= 0 && v == 2 * p + 1 + (uint32_t)d) L.r[2 + j] = (uint16_t)(2 * p + 1);
+        if (d >= 0 && v == 2 * p + 1 + (uint32_t)d) L.r[PL_HDR + j] = (uint16_t)(2 * p + 1);
       }
     }
   }
@@ -190,11 +197,16 @@ __device__ bool plain_gates(const Tables *__restrict__ tb, int s, PList<ENC> L, 
 
 // A depolarizing fault Z^b X^a on site q of one component (Sec. II B): the
 // site's level x becomes x + a (mod d), then the amplitude takes
-// w_d^(b (x + a)), w_2 = -1, w_3 = exp(2 pi i / 3).  A qutrit router has
-// three levels (W absent from the list, L, R with the level bit); every
-// other site two.
+// w_d^(b (x + a)), w_2 = -1, w_3 = exp(2 pi i / 3), counted in the phase
+// index ph (bit 0: a factor -1; ph >> 1: the power of w_3).  A qutrit
+// router has three levels (W absent from the list, L, R with the level
+// bit); every other site two.
+__device__ __forceinline__ uint32_t phase_w3(uint32_t ph, uint32_t t) {
+  return (ph & 1u) | ((((ph >> 1) + t) % 3u) << 1);
+}
+
 template <int ENC>
-__device__ void plain_fault(PList<ENC> L, double2 &amp, uint32_t q, uint32_t a, uint32_t b, uint32_t *err) {
+__device__ void plain_fault(PList<ENC> L, uint32_t &ph, uint32_t q, uint32_t a, uint32_t b, uint32_t *err) {
   const bool tri = ENC == QUTRIT && (q & 1u) == 0;
   const int j = L.find(q);
   uint32_t x;
@@ -206,7 +218,7 @@ __device__ void plain_fault(PList<ENC> L, double2 &amp, uint32_t q, uint32_t a, 
       else
         L.add(q, err);
     }
-    if ((b & 1u) && x) amp = make_double2(-amp.x, -amp.y);
+    if ((b & 1u) && x) ph ^= 1u;
     return;
   }
   const uint32_t v = j < 0 ? 0u : ((L.raw(j) & LV_R_BIT) ? 2u : 1u);
@@ -215,11 +227,18 @@ __device__ void plain_fault(PList<ENC> L, double2 &amp, uint32_t q, uint32_t a, 
     if (j >= 0) L.remove(j);
     if (x) L.add(q | (x == 2 ? LV_R_BIT : 0u), err);
   }
-  const uint32_t ph = (b * x) % 3u;
-  if (ph) {  // multiply by exp(+-2 pi i / 3) = -1/2 +- i sqrt(3)/2
-    const double c = -0.5, sn = ph == 1 ? 0.86602540378443864676 : -0.86602540378443864676;
-    amp = make_double2(amp.x * c - amp.y * sn, amp.x * sn + amp.y * c);
+  ph = phase_w3(ph, (b * x) % 3u);
+}
+
+// (-1)^(ph & 1) w3^(ph >> 1) times z; w3 = exp(2 pi i / 3) = -1/2 + i sqrt(3)/2
+__device__ __forceinline__ double2 apply_phase(double2 z, uint32_t ph) {
+  if (ph & 1u) z = make_double2(-z.x, -z.y);
+  const uint32_t t = ph >> 1;
+  if (t) {
+    const double c = -0.5, sn = t == 1 ? 0.86602540378443864676 : -0.86602540378443864676;
+    z = make_double2(z.x * c - z.y * sn, z.x * sn + z.y * c);
   }
+  return z;
 }
 
 struct PlainSm {
@@ -271,8 +290,8 @@ __device__ __forceinline__ bool rec_load(uint16_t *dst, const uint16_t *__restri
   if (nv_all > 3) d4[3] = v3;
   const uint32_t c = v0.x & 0xFFFFu;
   if (c == PL_DEAD) return true;
-  if ((int)(2 + c) + margin > sw) return false;
-  const int nv = (int)(2 + c + 7) >> 3;
+  if ((int)(PL_HDR + c) + margin > sw) return false;
+  const int nv = (int)(PL_HDR + c + 7) >> 3;
   for (int i = 4; i < nv; i += 4) {  // longer lists: four pieces in flight at a time
     const uint4 w0 = s4[i];
     const uint4 w1 = i + 1 < nv ? s4[i + 1] : w0;
@@ -290,7 +309,7 @@ __device__ __forceinline__ void rec_store(uint16_t *__restrict__ dst, const uint
   const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
   uint4 *d4 = reinterpret_cast<uint4 *>(dst);
   const uint32_t c = src[0];
-  const int nv = c == PL_DEAD ? 1 : min(sw >> 3, (int)(2 + c + 7) >> 3);
+  const int nv = c == PL_DEAD ? 1 : min(sw >> 3, (int)(PL_HDR + c + 7) >> 3);
   for (int i = 0; i < nv; ++i) d4[i] = s4[i];
 }
 
@@ -349,8 +368,11 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
   const int kb = __ffs(K2) - 1;
   const uint32_t kmask = (1u << k) - 1u;
   const int rec = rp->prec;
-  const int lcap = rec - 2;
+  const int lcap = rec - PL_HDR;
   const bool pruned = rp->mode == 1;
+  // exposures counted in a record stay within the power tables' range
+  // (they are multiplied into the amplitude before they would leave it)
+  const int emat = max(tb->emax, rec);
   PlainSm sm = plain_carve(smem, M);
   const uint32_t Emax = (uint32_t)(D * K2);
   uint16_t *pool = rp->pool + (size_t)blockIdx.x * Emax * rec;
@@ -418,6 +440,8 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
         const bool alive = ENC == QUBIT ? (tb->aflag[i] & 1u) != 0 : (c.x != 0.0 || c.y != 0.0);
         r[0] = alive ? 0 : PL_DEAD;
         r[1] = (uint16_t)beta;
+        r[2] = 0;
+        r[3] = 0;
         amp[y] = c;
         continue;
       }
@@ -426,6 +450,8 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
       if (ENC == QUBIT && (__popc(beta & j) & 1)) c = make_double2(-c.x, -c.y);
       r[0] = (c.x != 0.0 || c.y != 0.0) ? 0 : PL_DEAD;
       r[1] = (uint16_t)(ENC == QUBIT ? beta : j);
+      r[2] = 0;
+      r[3] = 0;
       amp[y] = make_double2(c.x * wall, c.y * wall);
     }
     const uint32_t nd = rp->dep ? min(rp->ndep[tj], rp->dep_cap) : 0u;
@@ -439,6 +465,18 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
     double cref2 = 0.0;
     if (goods) cref2 = abs2(in_amp(tb, ref));
     auto is_bad = [&](uint32_t i) -> bool { return (badg[i >> 6] >> (i & 63)) & 1ull; };
+    // explicit component y's weight |A|^2 before the current slice's
+    // damping layer (its record counts that layer's a^|X| already), and its
+    // amplitude with every counted factor multiplied in
+    auto wt = [&](uint32_t y) -> double {
+      const uint16_t *r = pool + (size_t)y * rec;
+      return abs2(amp[y]) * wpow[(int)r[2] - (int)r[0]];
+    };
+    auto amp_of = [&](uint32_t y) -> double2 {
+      const uint16_t *r = pool + (size_t)y * rec;
+      const double f = apow[r[2]];
+      return apply_phase(make_double2(amp[y].x * f, amp[y].y * f), r[3]);
+    };
     // The predicted branches (good, present, not the reference) relative to
     // the reference, through slice s: the sum over branches (i, j) holding
     // one bus word of |c_ij / c_ref|^2 (1-gamma)^(e(i,j) - e(ref)) (qutrit
@@ -482,7 +520,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
         if (tb->aflag[i] != 1u || is_bad(i)) continue;  // present, several bus words
         const uint32_t yr = (uint32_t)gref * K2 + beta;
         if (pool[(size_t)yr * rec] == PL_DEAD) continue;
-        const double w = multi_ratio(i, beta, s, eref) * abs2(amp[yr]);
+        const double w = multi_ratio(i, beta, s, eref) * wt(yr);
         if (hitf[yr])
           wh += w;
         else
@@ -523,20 +561,28 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
       for (uint32_t y = tid; y < E; y += nthr) {
         uint16_t *const g = pool + (size_t)y * rec;
         const bool staged = slab && rec_load(slab, g, sw, margin);
-        PList<ENC> L = staged ? PList<ENC>{slab, sw - 2} : PList<ENC>{g, lcap};
+        PList<ENC> L = staged ? PList<ENC>{slab, sw - PL_HDR} : PList<ENC>{g, lcap};
         if (L.cnt() == PL_DEAD) continue;
         const uint32_t a = xl ? xl[y >> kb] : (y >> kb);
-        double2 am = amp[y];
-        if (plain_gates<ENC>(tb, s, L, a, rp->err)) am = make_double2(-am.x, -am.y);
+        uint32_t ph = L.r[3];
+        if (plain_gates<ENC>(tb, s, L, a, rp->err)) ph ^= 1u;
         for (uint32_t f = d0; f < dpos; ++f) {  // faults after the gates, before the damping layer
           const uint32_t e = dep[f], t = e >> 24;
-          plain_fault<ENC>(L, am, e & 0xFFFFu, t & 3u, t >> 2, rp->err);
+          plain_fault<ENC>(L, ph, e & 0xFFFFu, t & 3u, t >> 2, rp->err);
         }
-        if (nc == 0) {
-          const double f = apow[L.cnt()];
-          amp[y] = make_double2(am.x * f, am.y * f);
-        } else {
-          amp[y] = am;
+        // the slice's K_0 = a^|X| joins the record's exposure (a jump takes
+        // back its sites' share); the exposure is multiplied into the
+        // amplitude before it would leave the power tables
+        int e = L.r[2];
+        const int cx = L.cnt();
+        if (e + cx > emat) {
+          const double f = apow[e];
+          amp[y] = make_double2(amp[y].x * f, amp[y].y * f);
+          e = 0;
+        }
+        L.r[2] = (uint16_t)(e + cx);
+        L.r[3] = (uint16_t)ph;
+        if (nc > 0) {
           uint8_t h = 0;
           for (int j = 0; j < L.cnt() && !h; ++j) {
             const uint32_t q = L.raw(j) & PList<ENC>::SM;
@@ -559,7 +605,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
         double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (uint32_t y = tid; y < E; y += nthr) {
           if (pool[(size_t)y * rec] == PL_DEAD) continue;
-          const double w = abs2(amp[y]);
+          const double w = wt(y);
           const int h = hitf[y] ? 1 : 0;
           acc[h] += w;
           if (goods && (int)(y >> kb) == gref) acc[2 + h] += w;
@@ -596,7 +642,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
             int my = -1;
             if (x < Lx && !labels) {
               if (pool[(size_t)x * rec] != PL_DEAD && hitf[x]) {
-                w = abs2(amp[x]);
+                w = wt(x);
                 my = (int)x;
               }
             } else if (x < Lx) {
@@ -618,14 +664,14 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
               if (g >= 0) {
                 const uint32_t y = (uint32_t)g * K2 + beta;
                 if (pool[(size_t)y * rec] != PL_DEAD && hitf[y]) {
-                  w = abs2(amp[y]);
+                  w = wt(y);
                   my = (int)y;
                 }
               } else if (goods) {  // a good label follows the reference's component
                 uint32_t yr = 0;
                 const double rw = good_label(a, beta, s - 1, eref, yr);
                 if (rw > 0.0 && pool[(size_t)yr * rec] != PL_DEAD && hitf[yr]) {
-                  w = abs2(amp[yr]) * rw;
+                  w = wt(yr) * rw;
                   if (w > 0.0) my = (int)yr;
                 }
               }
@@ -692,17 +738,14 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
           nJ = sm.misc[0];
         }
       }
-      // K_J on every explicit component: survivors carry J's sites at J's
-      // levels (the good branches survive exactly when the reference does)
-      for (uint32_t y = tid; y < E; y += nthr) {
+      // K_J on every explicit component after a jump: survivors carry J's
+      // sites at J's levels (the good branches survive exactly when the
+      // reference does) and take sqrt(gamma)^|J| a^(|X| - |J|), the record
+      // having counted a^|X| for the slice.  Without a jump K_0 = a^|X| is
+      // counted already.
+      for (uint32_t y = tid; nJ > 0 && y < E; y += nthr) {
         uint16_t *const g = pool + (size_t)y * rec;
-        const int c0 = g[0];
-        if (c0 == PL_DEAD) continue;
-        if (nJ == 0) {  // K_0 on every component: a^|X|
-          const double f = apow[c0];
-          amp[y] = make_double2(amp[y].x * f, amp[y].y * f);
-          continue;
-        }
+        if (g[0] == PL_DEAD) continue;
         // (a jump changes few entries: the record is edited in place)
         PList<ENC> L{g, lcap};
         bool ok = true;
@@ -716,10 +759,11 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
           amp[y] = make_double2(0.0, 0.0);
           continue;
         }
-        double f = apow[L.cnt() - nJ];
+        double f = 1.0;
         for (int c = 0; c < nJ; ++c) f *= sg;
         amp[y] = make_double2(amp[y].x * f, amp[y].y * f);
         for (int c = 0; c < nJ; ++c) L.remove(L.find(sm.J[c] & 0xFFFFu));
+        g[2] = (uint16_t)(g[2] - nJ);
       }
       if (nJ > 0) {
         ++njumps;
@@ -753,13 +797,14 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
         o[1] = 0;
         o[2] = m;
         for (uint32_t j = 0; j < m; ++j) {
-          const uint32_t e = r[2 + j];
+          const uint32_t e = r[PL_HDR + j];
           const uint32_t q = e & PList<ENC>::SM, lev = (ENC == QUTRIT && (e & LV_R_BIT)) ? 2u : 1u;
           o[3 + j] = q | (lev << 16);
         }
         if (rp->expamp) {
-          rp->expamp[2 * x] = amp[y].x;
-          rp->expamp[2 * x + 1] = amp[y].y;
+          const double2 at = amp_of(y);
+          rp->expamp[2 * x] = at.x;
+          rp->expamp[2 * x + 1] = at.y;
         }
       }
     }
@@ -795,23 +840,24 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
         const uint16_t *r = pool + (size_t)y * rec;
         if (r[0] == PL_DEAD) continue;
         if (isref) fin[4] = 1.0;
+        const double2 at = amp_of(y);
         if (r[0] != 0) {
-          fin[3] += abs2(amp[y]);
-          if (isref) fin[8] += abs2(amp[y]);
+          fin[3] += abs2(at);
+          if (isref) fin[8] += abs2(at);
           continue;
         }
         // qutrit with one component per address: slot 0, holding it only
         // when its bus word is the ideal one
         if (nw == 1 && ((uint32_t)r[1] & kmask) != want) {
-          fin[2] += abs2(amp[y]);
+          fin[2] += abs2(at);
           if (isref) {
-            fin[7] += abs2(amp[y]);
-            fin[10] += abs2(amp[y]);
+            fin[7] += abs2(at);
+            fin[10] += abs2(at);
           }
           continue;
         }
         const uint32_t bw = nw == 1 ? 0u : ((uint32_t)r[1] & (uint32_t)(nw - 1));
-        grp[bw] = make_double2(grp[bw].x + amp[y].x, grp[bw].y + amp[y].y);
+        grp[bw] = make_double2(grp[bw].x + at.x, grp[bw].y + at.y);
         any = true;
       }
       if (!any) continue;
@@ -887,13 +933,13 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
             const double2 ca = camp_of(tb, ((size_t)i << kb) + b), cr = camp_of(tb, ((size_t)ref << kb) + b);
             const double den = abs2(cr);
             if (r[0] != 0) {  // (an excited reference: the mirrored branch is excited too)
-              fin[3] += abs2(ca) / den * wpow[de] * abs2(amp[yr]);
+              fin[3] += abs2(ca) / den * wpow[de] * abs2(amp_of(yr));
               continue;
             }
             // q = ca / cr a^de (+-1), then times the reference's amplitude
             const double qx = (ca.x * cr.x + ca.y * cr.y) / den, qy = (ca.y * cr.x - ca.x * cr.y) / den;
             const double f = apow[de] * ((__popc((uint32_t)b & dd) & 1) ? -1.0 : 1.0);
-            const double2 u = amp[yr];
+            const double2 u = amp_of(yr);
             grp[b] = make_double2(f * (qx * u.x - qy * u.y), f * (qx * u.y + qy * u.x));
             any = true;
           }
