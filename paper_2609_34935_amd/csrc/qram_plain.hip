@@ -271,8 +271,9 @@ __device__ inline PlainSm plain_carve(unsigned char *base, int M) {
 }
 
 // A record copied from the pool into a thread's slab (sw words, a multiple
-// of 8) in 16-byte pieces: the count and bus word and the sites in use.  The
-// first pieces are loaded together, before the count is known.  A record
+// of 8) in 16-byte pieces: the header words and the sites in use.  The
+// first two pieces (the header and up to 12 sites) are loaded together,
+// before the count is known.  A record
 // is staged only when it fits the slab with `margin` words to spare (the
 // most a slice's gates and faults can add); returns false, having copied
 // only the first pieces, when it does not.
@@ -282,17 +283,13 @@ __device__ __forceinline__ bool rec_load(uint16_t *dst, const uint16_t *__restri
   const int nv_all = sw >> 3;
   const uint4 v0 = s4[0];
   const uint4 v1 = nv_all > 1 ? s4[1] : v0;
-  const uint4 v2 = nv_all > 2 ? s4[2] : v0;
-  const uint4 v3 = nv_all > 3 ? s4[3] : v0;
   d4[0] = v0;
   if (nv_all > 1) d4[1] = v1;
-  if (nv_all > 2) d4[2] = v2;
-  if (nv_all > 3) d4[3] = v3;
   const uint32_t c = v0.x & 0xFFFFu;
   if (c == PL_DEAD) return true;
   if ((int)(PL_HDR + c) + margin > sw) return false;
   const int nv = (int)(PL_HDR + c + 7) >> 3;
-  for (int i = 4; i < nv; i += 4) {  // longer lists: four pieces in flight at a time
+  for (int i = 2; i < nv; i += 4) {  // longer lists: four pieces in flight at a time
     const uint4 w0 = s4[i];
     const uint4 w1 = i + 1 < nv ? s4[i + 1] : w0;
     const uint4 w2 = i + 2 < nv ? s4[i + 2] : w0;
