@@ -110,7 +110,11 @@ CASES = [
     (5, 3, QUBIT, 0.01, 0.005, True, 150),
     (2, 1, QUTRIT, 0.05, 0.05, False, 400), (3, 1, QUTRIT, 0.03, 0.03, False, 300),
     (4, 2, QUTRIT, 0.02, 0.01, True, 200), (3, 2, QUTRIT, 0.1, 0.0, True, 300),
-    (6, 2, QUTRIT, 0.005, 0.002, True, 150)]
+    (6, 2, QUTRIT, 0.005, 0.002, True, 150),
+    # strays in plenty: lists run past the excitation bound for most of the
+    # query, and the plain engine multiplies counted exposures into the
+    # amplitudes before they would leave its power tables
+    (3, 1, QUBIT, 0.05, 0.4, False, 300), (2, 1, QUTRIT, 0.05, 0.5, False, 300)]
 
 
 @pytest.mark.parametrize("n,k,enc,gamma,eps,general,nt", CASES)
