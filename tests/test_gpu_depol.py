@@ -270,3 +270,26 @@ def test_split_pruned_run(lib, orc, enc):
         assert decode_jlog(jl[t, :min(njl[t], jcap)]) == sorted(ref)[:jcap], t
         seen[int(nf[t] > 0)] += len(ref) > 0
     assert seen[0] > 0 and seen[1] > 0  # jumps on both halves
+
+
+@pytest.mark.parametrize("enc", [QUBIT, QUTRIT])
+def test_split_runs_as_graphs(lib, enc):
+    """Graph mode on a depolarizing context: the captured batch holds the
+    ordering, the trajectory kernel's buckets, the queue reset and the plain
+    share; every replay (with other device work between) equals the eager
+    run bitwise, for both modes, on repeated and changed batches."""
+    import torch
+    n, k, p = 5, 2, 0.004
+    mem = memory_words(n, k, 17)
+    calls = [(3, 0, 500), (3, 500, 500), (4, 0, 500), (3, 0, 500), (5, 9, 200), (5, 9, 200)]
+    with lib.QramContext(n, k, enc, p, mem, eps=p) as eager, lib.QramContext(n, k, enc, p, mem, eps=p) as g:
+        g.set_option(lib.qram.QRAM_OPT_GRAPH, 1)
+        for mode in (FULL, PRUNED):
+            for seed, traj0, nt in calls:
+                fe, se = (eager.run_pruned if mode == PRUNED else eager.run_full)(seed, traj0, nt)
+                x = torch.randn(1 << 16, device="cuda", dtype=torch.float64)
+                torch.cuda.synchronize()
+                fg, sg = (g.run_pruned if mode == PRUNED else g.run_full)(seed, traj0, nt)
+                assert float((x * x).sum()) > 0
+                assert np.array_equal(fg, fe), (mode, seed, traj0, nt)
+                assert np.array_equal(sg, se), (mode, seed, traj0, nt)
