@@ -224,8 +224,10 @@ qram_status qram_run_pruned(qram_ctx *ctx, uint64_t seed, uint64_t traj0,
 /*
  * Plain full evolution (QRAM_MODE_PLAIN), the comparator of App. D: all D
  * branches evolved explicitly, every component slice by slice with its own
- * site list and complex FP64 amplitude; one workgroup per trajectory.  Same
- * arguments as qram_run_full; same results up to rounding.
+ * site list and complex FP64 amplitude (the damping factors and phases of
+ * the slices without a jump counted beside it and multiplied in where an
+ * amplitude is needed); one workgroup per trajectory.  Same arguments as
+ * qram_run_full; same results up to rounding.
  */
 qram_status qram_run_plain(qram_ctx *ctx, uint64_t seed, uint64_t traj0,
                            uint32_t ntraj, double *fid, qram_traj_stats *st);
