@@ -136,17 +136,48 @@ __device__ bool plain_gates(const Tables *__restrict__ tb, int s, PList<ENC> L, 
   }
   const uint32_t cm = tb->cswap[s];
   if (cm) {  // SWAP(d_v, d_child) on the layers of the slice, child by v's router
+    // qubit: every router lookup below is of a node on a swap layer, so
+    // those routers are collected first (up to eight node ids, two to a
+    // register) and each data site tests them instead of scanning the list
+    // (lists that collect depolarizing strays grow long); with more than
+    // eight the list is scanned as usual
+    int nr = 0;
+    uint32_t rr0 = 0xFFFFFFFFu, rr1 = 0xFFFFFFFFu, rr2 = 0xFFFFFFFFu, rr3 = 0xFFFFFFFFu;
+    if (ENC == QUBIT) {
+      for (int j = 0; j < L.cnt() && nr <= 8; ++j) {
+        const uint32_t q = L.raw(j);
+        if (q & 1u) continue;
+        const uint32_t u = q >> 1;
+        if (!((cm >> layer_of(u)) & 1u)) continue;
+        if (nr < 8) {
+          const uint32_t sh = (uint32_t)(nr & 1) * 16u, keep = ~(0xFFFFu << sh), x = u << sh;
+          const int w = nr >> 1;
+          rr0 = w == 0 ? ((rr0 & keep) | x) : rr0;
+          rr1 = w == 1 ? ((rr1 & keep) | x) : rr1;
+          rr2 = w == 2 ? ((rr2 & keep) | x) : rr2;
+          rr3 = w == 3 ? ((rr3 & keep) | x) : rr3;
+        }
+        ++nr;
+      }
+    }
+    const bool few = ENC == QUBIT && nr <= 8;
+    auto routed = [&](uint32_t u) -> int {  // qubit: 1 when u's router is excited (route right)
+      if (!few) return L.dir(u);
+      const bool hit = (rr0 & 0xFFFFu) == u || (rr0 >> 16) == u || (rr1 & 0xFFFFu) == u || (rr1 >> 16) == u ||
+                       (rr2 & 0xFFFFu) == u || (rr2 >> 16) == u || (rr3 & 0xFFFFu) == u || (rr3 >> 16) == u;
+      return hit ? 1 : 0;
+    };
     for (int j = 0; j < L.cnt(); ++j) {
       const uint32_t q = L.raw(j) & PList<ENC>::SM;
       if (!(q & 1u)) continue;
       const uint32_t v = q >> 1;
       const int l = layer_of(v);
       if ((cm >> l) & 1u) {
-        const int d = L.dir(v);
+        const int d = routed(v);
         if (d >= 0) L.r[PL_HDR + j] = (uint16_t)(2 * (2 * v + 1 + (uint32_t)d) + 1);
       } else if (l >= 1 && ((cm >> (l - 1)) & 1u)) {
         const uint32_t p = (v - 1) >> 1;
-        const int d = L.dir(p);
+        const int d = routed(p);
         if (d >= 0 && v == 2 * p + 1 + (uint32_t)d) L.r[PL_HDR + j] = (uint16_t)(2 * p + 1);
       }
     }
