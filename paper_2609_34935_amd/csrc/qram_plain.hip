@@ -136,36 +136,44 @@ __device__ bool plain_gates(const Tables *__restrict__ tb, int s, PList<ENC> L, 
   }
   const uint32_t cm = tb->cswap[s];
   if (cm) {  // SWAP(d_v, d_child) on the layers of the slice, child by v's router
-    // qubit: every router lookup below is of a node on a swap layer, so
-    // those routers are collected first (up to eight node ids, two to a
-    // register) and each data site tests them instead of scanning the list
-    // (lists that collect depolarizing strays grow long); with more than
-    // eight the list is scanned as usual
+    // every router lookup below is of a node on a swap layer, so those
+    // routers are collected first (up to eight; node id | R level << 15, two
+    // to a register) and each data site tests them instead of scanning the
+    // list (lists that collect depolarizing strays grow long); with more
+    // than eight the list is scanned as usual
     int nr = 0;
     uint32_t rr0 = 0xFFFFFFFFu, rr1 = 0xFFFFFFFFu, rr2 = 0xFFFFFFFFu, rr3 = 0xFFFFFFFFu;
-    if (ENC == QUBIT) {
-      for (int j = 0; j < L.cnt() && nr <= 8; ++j) {
-        const uint32_t q = L.raw(j);
-        if (q & 1u) continue;
-        const uint32_t u = q >> 1;
-        if (!((cm >> layer_of(u)) & 1u)) continue;
-        if (nr < 8) {
-          const uint32_t sh = (uint32_t)(nr & 1) * 16u, keep = ~(0xFFFFu << sh), x = u << sh;
-          const int w = nr >> 1;
-          rr0 = w == 0 ? ((rr0 & keep) | x) : rr0;
-          rr1 = w == 1 ? ((rr1 & keep) | x) : rr1;
-          rr2 = w == 2 ? ((rr2 & keep) | x) : rr2;
-          rr3 = w == 3 ? ((rr3 & keep) | x) : rr3;
-        }
-        ++nr;
+    for (int j = 0; j < L.cnt() && nr <= 8; ++j) {
+      const uint32_t x = L.raw(j), q = x & PList<ENC>::SM;
+      if (q & 1u) continue;
+      const uint32_t u = q >> 1;
+      if (!((cm >> layer_of(u)) & 1u)) continue;
+      if (nr < 8) {
+        const uint32_t tag = u | ((ENC == QUTRIT && (x & LV_R_BIT)) ? 0x8000u : 0u);
+        const uint32_t sh = (uint32_t)(nr & 1) * 16u, keep = ~(0xFFFFu << sh), t = tag << sh;
+        const int w = nr >> 1;
+        rr0 = w == 0 ? ((rr0 & keep) | t) : rr0;
+        rr1 = w == 1 ? ((rr1 & keep) | t) : rr1;
+        rr2 = w == 2 ? ((rr2 & keep) | t) : rr2;
+        rr3 = w == 3 ? ((rr3 & keep) | t) : rr3;
       }
+      ++nr;
     }
-    const bool few = ENC == QUBIT && nr <= 8;
-    auto routed = [&](uint32_t u) -> int {  // qubit: 1 when u's router is excited (route right)
+    const bool few = nr <= 8;
+    // the route of node u: qubit 0/1; qutrit -1 (W), 0 (L), 1 (R), as dir()
+    auto routed = [&](uint32_t u) -> int {
       if (!few) return L.dir(u);
-      const bool hit = (rr0 & 0xFFFFu) == u || (rr0 >> 16) == u || (rr1 & 0xFFFFu) == u || (rr1 >> 16) == u ||
-                       (rr2 & 0xFFFFu) == u || (rr2 >> 16) == u || (rr3 & 0xFFFFu) == u || (rr3 >> 16) == u;
-      return hit ? 1 : 0;
+      bool hit = false, right = false;
+      const uint32_t h[8] = {rr0 & 0xFFFFu, rr0 >> 16, rr1 & 0xFFFFu, rr1 >> 16,
+                             rr2 & 0xFFFFu, rr2 >> 16, rr3 & 0xFFFFu, rr3 >> 16};
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const bool m = (h[i] & 0x7FFFu) == u;
+        hit |= m;
+        right |= m && (h[i] & 0x8000u);
+      }
+      if (ENC == QUBIT) return hit ? 1 : 0;
+      return hit ? (right ? 1 : 0) : -1;
     };
     for (int j = 0; j < L.cnt(); ++j) {
       const uint32_t q = L.raw(j) & PList<ENC>::SM;
