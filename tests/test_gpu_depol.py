@@ -293,3 +293,19 @@ def test_split_runs_as_graphs(lib, enc):
                 assert float((x * x).sum()) > 0
                 assert np.array_equal(fg, fe), (mode, seed, traj0, nt)
                 assert np.array_equal(sg, se), (mode, seed, traj0, nt)
+
+
+@pytest.mark.parametrize("p,n,nt", [(1e-5, 6, 2048), (1e-4, 8, 1024), (1e-3, 6, 1024), (1e-3, 8, 512)])
+def test_table5_workload_points(lib, orc, p, n, nt):
+    """The paper's full-versus-pruned workload (App. D, Table 5: qubit,
+    k = 3, eps = gamma, data-loading input) with the bench's seed and
+    memory: the split pruned run and the plain full evolution against the
+    oracle on every trajectory."""
+    k = 3
+    mem = memory_words(n, k, 1007 + n)
+    fo, fpo, so, _ = orc.run_many(n, k, QUBIT, p, mem, 880007, traj0=0, ntraj=nt, eps=p)
+    assert so[:, 9].sum() > 0  # faults were drawn
+    with lib.QramContext(n, k, QUBIT, p, mem, eps=p) as ctx:
+        for mode, fn in ((PRUNED, ctx.run_pruned), (PLAIN, ctx.run_plain)):
+            f, st = fn(880007, 0, nt)
+            check_stats(f, st, fo, fpo, so, (p, n, mode))
