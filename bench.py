@@ -273,7 +273,7 @@ PAPER_TABLE5 = {
 }
 
 
-def table5_leg(P, scale=1.0):
+def table5_leg(P, scale=1.0, points=None):
     """The paper's full-versus-pruned workload (Fig. 3, App. D): qubit, k = 3,
     eps = gamma in {0, 1e-5, 1e-4, 1e-3}, n = 4..12, data-loading input.
     Pruned (Alg. 1) against the plain full evolution of every branch, on the
@@ -285,6 +285,8 @@ def table5_leg(P, scale=1.0):
     rows = []
     for p in (0.0, 1e-5, 1e-4, 1e-3):
         for n in (4, 6, 8, 10, 12):
+            if points is not None and (p, n) not in points:
+                continue
             # enough trajectories per workgroup that the slowest trajectories
             # do not set the launch time (the paper's figure is a mean)
             nt = {4: 65536, 6: 32768, 8: 16384, 10: 8192, 12: 4096}[n]
@@ -353,6 +355,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-table5", action="store_true")
     ap.add_argument("--table5-scale", type=float, default=1.0)
+    ap.add_argument("--table5-points", default=None,
+                    help="only these points of the Table 5 workload, as eps:n,eps:n (e.g. 1e-5:8)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-capacity-requests", type=int, default=400)
     ap.add_argument("--serve-chunk", type=int, default=16384)
@@ -620,7 +624,10 @@ def main():
     if not args.no_c5:
         line["config5"] = config5_leg(P, args.c5_ntraj, args.c5_plain_ntraj)
     if not args.no_table5:
-        line["table5"] = table5_leg(P, args.table5_scale)
+        pts = None
+        if args.table5_points:
+            pts = {(float(e), int(n)) for e, n in (x.split(":") for x in args.table5_points.split(","))}
+        line["table5"] = table5_leg(P, args.table5_scale, pts)
     torch.cuda.empty_cache()
     if not args.no_serve:
         log("serving mix")
