@@ -330,26 +330,27 @@ __global__ void __launch_bounds__(256) k_classify(const Tables *__restrict__ tb,
 // components; inside a bucket trajectories are ordered by decreasing log2 of
 // their work.  In a split run the trajectories that drew a depolarizing
 // fault go to a segment of their own after every bucket, [bucket_base[MAXB],
-// bucket_base[MAXB + 1]), which the plain engine takes.  One workgroup.
+// bucket_base[MAXB + 1]), also longest first, which the plain engine takes.
+// One workgroup.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_order(const Run R_) {
   const Run *rp = &R_;
   constexpr int NF = 33;  // log2 bins inside a bucket
-  constexpr int XF = MAXB * NF;  // the split run's plain-engine bin
-  __shared__ uint32_t hist[XF + 1];
-  __shared__ uint32_t base[XF + 1];
+  constexpr int XF = MAXB * NF;  // the split run's plain-engine bins: XF .. XF + NF - 1
+  __shared__ uint32_t hist[XF + NF];
+  __shared__ uint32_t base[XF + NF];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const uint32_t nt = rp->ntraj;
   const uint32_t nb = rp->nbkt;
   const bool split = rp->dsplit != 0;
-  for (int i = tid; i <= XF; i += nthr) hist[i] = 0;
+  for (int i = tid; i < XF + NF; i += nthr) hist[i] = 0;
   __syncthreads();
   auto key = [&](uint32_t t) -> int {
-    if (split && rp->ndep[t] != 0) return XF;
     const uint32_t e = rp->nexpl[t];
+    const int f = 32 - __clz(e);  // larger work -> earlier
+    if (split && rp->ndep[t] != 0) return XF + (NF - 1 - f);
     uint32_t b = 0;
     while (b + 1 < nb && e > rp->bkt_emax[b]) ++b;
-    const int f = 32 - __clz(e);  // larger work -> earlier
     return (int)b * NF + (NF - 1 - f);
   };
   for (uint32_t t = tid; t < nt; t += nthr) atomicAdd(&hist[key(t)], 1u);
@@ -365,8 +366,11 @@ __global__ void __launch_bounds__(1024) k_order(const Run R_) {
       rp->counter[b] = 0;
     }
     rp->bucket_base[MAXB] = acc;
-    base[XF] = acc;
-    if (split) rp->bucket_base[MAXB + 1] = acc + hist[XF];
+    for (int f = 0; f < NF; ++f) {
+      base[XF + f] = acc;
+      acc += hist[XF + f];
+    }
+    if (split) rp->bucket_base[MAXB + 1] = acc;
   }
   __syncthreads();
   for (uint32_t t = tid; t < nt; t += nthr) {
