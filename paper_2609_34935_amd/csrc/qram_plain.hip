@@ -32,9 +32,17 @@ constexpr int PL_GATED = 16;  // gated nodes of one qutrit store / fetch at most
 constexpr uint16_t PL_DEAD = 0xFFFFu;
 constexpr int PL_HDR = 4;  // header words before the sites
 
-template <int ENC>
+// Words of a record in the workgroup's shared memory (a thread's slab),
+// typed so that their accesses compile to LDS instructions, which wait on
+// no outstanding device-memory operation (a generic access would wait for
+// the previous record's stores to the pool as well).
+using lds_u16 = __attribute__((address_space(3))) uint16_t;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+using lds_u4 = __attribute__((address_space(3))) u32x4;
+
+template <int ENC, typename W = uint16_t>
 struct PList {
-  uint16_t *r;
+  W *r;
   int cap;
   static constexpr uint32_t SM = ENC == QUTRIT ? 0x7FFFu : 0xFFFFu;
   __device__ __forceinline__ int cnt() const { return r[0]; }
@@ -77,8 +85,8 @@ struct PList {
 
 // Nodes of layer l whose parent routes into them (the root for l = 0),
 // collected before a qutrit store changes the list.
-template <int ENC>
-__device__ __forceinline__ int gated_nodes(const PList<ENC> &L, int l, uint32_t *gv, uint32_t *err) {
+template <int ENC, typename W>
+__device__ __forceinline__ int gated_nodes(const PList<ENC, W> &L, int l, uint32_t *gv, uint32_t *err) {
   if (l == 0) {
     gv[0] = 0;
     return 1;
@@ -100,8 +108,9 @@ __device__ __forceinline__ int gated_nodes(const PList<ENC> &L, int l, uint32_t 
 // The gates of slice s on one component (address a).  Returns true when the
 // qubit fetch flips its sign.  Every gate is a permutation of basis labels;
 // it is applied entry by entry from the list as it was before the gate.
-template <int ENC>
-__device__ bool plain_gates(const Tables *__restrict__ tb, int s, PList<ENC> L, uint32_t a, uint32_t *err) {
+template <int ENC, typename W>
+__device__ __forceinline__ bool plain_gates(const Tables *__restrict__ tb, int s, PList<ENC, W> L, uint32_t a,
+                                            uint32_t *err) {
   const int n = tb->n;
   bool flip = false;
   const int ct = tb->copy_t[s];
@@ -115,7 +124,7 @@ __device__ bool plain_gates(const Tables *__restrict__ tb, int s, PList<ENC> L, 
       }
     } else {  // (W,b) <-> (L or R by b, 0) on the gated nodes
       uint32_t gv[PL_GATED];
-      const int ng = gated_nodes<ENC>(L, sl, gv, err);
+      const int ng = gated_nodes<ENC, W>(L, sl, gv, err);
       for (int g = 0; g < ng && g < PL_GATED; ++g) {
         const uint32_t v = gv[g];
         const int jr = L.find(2 * v), jd = L.find(2 * v + 1);
@@ -244,8 +253,9 @@ __device__ __forceinline__ uint32_t phase_w3(uint32_t ph, uint32_t t) {
   return (ph & 1u) | ((((ph >> 1) + t) % 3u) << 1);
 }
 
-template <int ENC>
-__device__ void plain_fault(PList<ENC> L, uint32_t &ph, uint32_t q, uint32_t a, uint32_t b, uint32_t *err) {
+template <int ENC, typename W>
+__device__ __forceinline__ void plain_fault(PList<ENC, W> L, uint32_t &ph, uint32_t q, uint32_t a, uint32_t b,
+                                            uint32_t *err) {
   const bool tri = ENC == QUTRIT && (q & 1u) == 0;
   const int j = L.find(q);
   uint32_t x;
@@ -278,6 +288,51 @@ __device__ __forceinline__ double2 apply_phase(double2 z, uint32_t ph) {
     z = make_double2(z.x * c - z.y * sn, z.x * sn + z.y * c);
   }
   return z;
+}
+
+// One component's slice: the gates, the slice's faults, the slice's
+// damping factor a^|X| counted in the record (the count multiplied into the
+// amplitude first when it would leave the power tables), and with
+// candidates the hit test (returned).
+template <int ENC, typename W>
+__device__ __forceinline__ int plain_slice(const Tables *__restrict__ tb, int s, PList<ENC, W> L, uint32_t a,
+                                           const uint32_t *__restrict__ dep, uint32_t d0, uint32_t d1,
+                                           uint32_t nc, const uint32_t *cbm, double2 *ampy,
+                                           const double *__restrict__ apow, int emat, uint32_t *err) {
+  uint32_t ph = L.r[3];
+  if (plain_gates<ENC>(tb, s, L, a, err)) ph ^= 1u;
+  for (uint32_t f = d0; f < d1; ++f) {  // faults after the gates, before the damping layer
+    const uint32_t e = dep[f], t = e >> 24;
+    plain_fault<ENC>(L, ph, e & 0xFFFFu, t & 3u, t >> 2, err);
+  }
+  int e = L.r[2];
+  const int cx = L.cnt();
+  if (e + cx > emat) {
+    const double f = apow[e];
+    *ampy = make_double2(ampy->x * f, ampy->y * f);
+    e = 0;
+  }
+  L.r[2] = (uint16_t)(e + cx);
+  L.r[3] = (uint16_t)ph;
+  int hit = 0;
+  if (nc > 0)
+    for (int j = 0; j < L.cnt() && !hit; ++j) {
+      const uint32_t q = L.raw(j) & PList<ENC>::SM;
+      hit = (int)((cbm[q >> 5] >> (q & 31)) & 1u);
+    }
+  return hit;
+}
+
+// The same on a record in device memory (one that does not fit its slab, or
+// a launch without slabs): a call of its own, so that its registers do not
+// add to the staged path's.
+template <int ENC>
+__device__ __attribute__((noinline)) int plain_slice_mem(const Tables *__restrict__ tb, int s, uint16_t *g, int lcap,
+                                                         uint32_t a, const uint32_t *__restrict__ dep, uint32_t d0,
+                                                         uint32_t d1, uint32_t nc, const uint32_t *cbm,
+                                                         double2 *ampy, const double *__restrict__ apow, int emat,
+                                                         uint32_t *err) {
+  return plain_slice<ENC, uint16_t>(tb, s, PList<ENC>{g, lcap}, a, dep, d0, d1, nc, cbm, ampy, apow, emat, err);
 }
 
 struct PlainSm {
@@ -316,12 +371,12 @@ __device__ inline PlainSm plain_carve(unsigned char *base, int M) {
 // is staged only when it fits the slab with `margin` words to spare (the
 // most a slice's gates and faults can add); returns false, having copied
 // only the first pieces, when it does not.
-__device__ __forceinline__ bool rec_load(uint16_t *dst, const uint16_t *__restrict__ src, int sw, int margin) {
-  const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
-  uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+__device__ __forceinline__ bool rec_load(lds_u16 *dst, const uint16_t *__restrict__ src, int sw, int margin) {
+  const u32x4 *s4 = reinterpret_cast<const u32x4 *>(src);
+  lds_u4 *d4 = (lds_u4 *)dst;
   const int nv_all = sw >> 3;
-  const uint4 v0 = s4[0];
-  const uint4 v1 = nv_all > 1 ? s4[1] : v0;
+  const u32x4 v0 = s4[0];
+  const u32x4 v1 = nv_all > 1 ? s4[1] : v0;
   d4[0] = v0;
   if (nv_all > 1) d4[1] = v1;
   const uint32_t c = v0.x & 0xFFFFu;
@@ -329,10 +384,10 @@ __device__ __forceinline__ bool rec_load(uint16_t *dst, const uint16_t *__restri
   if ((int)(PL_HDR + c) + margin > sw) return false;
   const int nv = (int)(PL_HDR + c + 7) >> 3;
   for (int i = 2; i < nv; i += 4) {  // longer lists: four pieces in flight at a time
-    const uint4 w0 = s4[i];
-    const uint4 w1 = i + 1 < nv ? s4[i + 1] : w0;
-    const uint4 w2 = i + 2 < nv ? s4[i + 2] : w0;
-    const uint4 w3 = i + 3 < nv ? s4[i + 3] : w0;
+    const u32x4 w0 = s4[i];
+    const u32x4 w1 = i + 1 < nv ? s4[i + 1] : w0;
+    const u32x4 w2 = i + 2 < nv ? s4[i + 2] : w0;
+    const u32x4 w3 = i + 3 < nv ? s4[i + 3] : w0;
     d4[i] = w0;
     if (i + 1 < nv) d4[i + 1] = w1;
     if (i + 2 < nv) d4[i + 2] = w2;
@@ -341,9 +396,9 @@ __device__ __forceinline__ bool rec_load(uint16_t *dst, const uint16_t *__restri
   return true;
 }
 
-__device__ __forceinline__ void rec_store(uint16_t *__restrict__ dst, const uint16_t *src, int sw) {
-  const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
-  uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+__device__ __forceinline__ void rec_store(uint16_t *__restrict__ dst, const lds_u16 *src, int sw) {
+  const lds_u4 *s4 = (const lds_u4 *)src;
+  u32x4 *d4 = reinterpret_cast<u32x4 *>(dst);
   const uint32_t c = src[0];
   const int nv = c == PL_DEAD ? 1 : min(sw >> 3, (int)(PL_HDR + c + 7) >> 3);
   for (int i = 0; i < nv; ++i) d4[i] = s4[i];
@@ -594,40 +649,25 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
       // a slice adds at most: qubit, the copy and bus-swap sites; qutrit,
       // those and one per gated node of a store and of a fetch; one per fault
       const int margin = (ENC == QUTRIT ? 2 + 2 * PL_GATED : 2) + (int)(dpos - d0);
+      // (the slice's K_0 = a^|X| joins each record's exposure; a jump takes
+      // back its sites' share below)
       for (uint32_t y = tid; y < E; y += nthr) {
         uint16_t *const g = pool + (size_t)y * rec;
-        const bool staged = slab && rec_load(slab, g, sw, margin);
-        PList<ENC> L = staged ? PList<ENC>{slab, sw - PL_HDR} : PList<ENC>{g, lcap};
-        if (L.cnt() == PL_DEAD) continue;
         const uint32_t a = xl ? xl[y >> kb] : (y >> kb);
-        uint32_t ph = L.r[3];
-        if (plain_gates<ENC>(tb, s, L, a, rp->err)) ph ^= 1u;
-        for (uint32_t f = d0; f < dpos; ++f) {  // faults after the gates, before the damping layer
-          const uint32_t e = dep[f], t = e >> 24;
-          plain_fault<ENC>(L, ph, e & 0xFFFFu, t & 3u, t >> 2, rp->err);
+        int hit;
+        if (slab && rec_load((lds_u16 *)slab, g, sw, margin)) {
+          PList<ENC, lds_u16> L{(lds_u16 *)slab, sw - PL_HDR};
+          if (L.cnt() == PL_DEAD) continue;
+          hit = plain_slice<ENC>(tb, s, L, a, dep, d0, dpos, nc, sm.cbm, amp + y, apow, emat, rp->err);
+          rec_store(g, (lds_u16 *)slab, sw);
+        } else {
+          if (g[0] == PL_DEAD) continue;
+          hit = plain_slice_mem<ENC>(tb, s, g, lcap, a, dep, d0, dpos, nc, sm.cbm, amp + y, apow, emat, rp->err);
         }
-        // the slice's K_0 = a^|X| joins the record's exposure (a jump takes
-        // back its sites' share); the exposure is multiplied into the
-        // amplitude before it would leave the power tables
-        int e = L.r[2];
-        const int cx = L.cnt();
-        if (e + cx > emat) {
-          const double f = apow[e];
-          amp[y] = make_double2(amp[y].x * f, amp[y].y * f);
-          e = 0;
-        }
-        L.r[2] = (uint16_t)(e + cx);
-        L.r[3] = (uint16_t)ph;
         if (nc > 0) {
-          uint8_t h = 0;
-          for (int j = 0; j < L.cnt() && !h; ++j) {
-            const uint32_t q = L.raw(j) & PList<ENC>::SM;
-            h = (uint8_t)((sm.cbm[q >> 5] >> (q & 31)) & 1u);
-          }
-          hitf[y] = h;
-          anyhit |= h;
+          hitf[y] = (uint8_t)hit;
+          anyhit |= hit;
         }
-        if (staged) rec_store(g, slab, sw);
       }
       if (nc == 0) continue;  // (the bitmap is already clean)
       anyhit = __syncthreads_or(anyhit);
