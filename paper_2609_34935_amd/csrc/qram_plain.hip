@@ -22,7 +22,11 @@ constexpr int PL_GATED = 16;  // gated nodes of one qutrit store / fetch at most
 
 // Explicit site list of one component in the workgroup's pool: [0] count
 // (PL_DEAD once annihilated), [1] bus word, [2] exposure e, [3] phase
-// index, [4 ..] sites; a qutrit router site carries its level in bit 15
+// index, [4 ..] sites.  In the pool the words of a record sit in pieces of
+// eight (16 bytes): piece p of component y at word (p E + y) 8 of the
+// trajectory's E components, so the threads of a wave, which work on
+// consecutive components, read and write each piece as one contiguous
+// run; a slab in shared memory holds a record contiguously. a qutrit router site carries its level in bit 15
 // (set: R, clear: L).  The component's amplitude is the stored complex
 // number times a^e times (-1)^(ph & 1) w3^(ph >> 1): the damping factors
 // a^|X| of the slices and the phases of the gates and faults are counted
@@ -40,32 +44,35 @@ using lds_u16 = __attribute__((address_space(3))) uint16_t;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 using lds_u4 = __attribute__((address_space(3))) u32x4;
 
-template <int ENC, typename W = uint16_t>
+// (STR: a record in the pool, its pieces ps words apart; else contiguous)
+template <int ENC, typename W = uint16_t, bool STR = false>
 struct PList {
   W *r;
   int cap;
+  uint32_t ps;
   static constexpr uint32_t SM = ENC == QUTRIT ? 0x7FFFu : 0xFFFFu;
-  __device__ __forceinline__ int cnt() const { return r[0]; }
-  __device__ __forceinline__ uint32_t raw(int j) const { return r[PL_HDR + j]; }
+  __device__ __forceinline__ W &at(int w) const { return STR ? r[(size_t)(w >> 3) * ps + (w & 7)] : r[w]; }
+  __device__ __forceinline__ int cnt() const { return at(0); }
+  __device__ __forceinline__ uint32_t raw(int j) const { return at(PL_HDR + j); }
   __device__ __forceinline__ int find(uint32_t q) const {
-    const int c = r[0];
+    const int c = at(0);
     for (int j = 0; j < c; ++j)
-      if ((r[PL_HDR + j] & SM) == q) return j;
+      if ((at(PL_HDR + j) & SM) == q) return j;
     return -1;
   }
   __device__ __forceinline__ void remove(int j) {
-    const int c = r[0] - 1;
-    r[PL_HDR + j] = r[PL_HDR + c];
-    r[0] = (uint16_t)c;
+    const int c = at(0) - 1;
+    at(PL_HDR + j) = at(PL_HDR + c);
+    at(0) = (uint16_t)c;
   }
   __device__ __forceinline__ void add(uint32_t x, uint32_t *err) {
-    const int c = r[0];
+    const int c = at(0);
     if (c >= cap) {
       atomicOr(err, ERR_LIST);
       return;
     }
-    r[PL_HDR + c] = (uint16_t)x;
-    r[0] = (uint16_t)(c + 1);
+    at(PL_HDR + c) = (uint16_t)x;
+    at(0) = (uint16_t)(c + 1);
   }
   __device__ __forceinline__ void toggle(uint32_t q, uint32_t *err) {
     const int j = find(q);
@@ -79,14 +86,14 @@ struct PList {
     const int j = find(2 * v);
     if (ENC == QUBIT) return j >= 0 ? 1 : 0;
     if (j < 0) return -1;
-    return (r[PL_HDR + j] & LV_R_BIT) ? 1 : 0;
+    return (at(PL_HDR + j) & LV_R_BIT) ? 1 : 0;
   }
 };
 
 // Nodes of layer l whose parent routes into them (the root for l = 0),
 // collected before a qutrit store changes the list.
-template <int ENC, typename W>
-__device__ __forceinline__ int gated_nodes(const PList<ENC, W> &L, int l, uint32_t *gv, uint32_t *err) {
+template <int ENC, typename W, bool STR>
+__device__ __forceinline__ int gated_nodes(const PList<ENC, W, STR> &L, int l, uint32_t *gv, uint32_t *err) {
   if (l == 0) {
     gv[0] = 0;
     return 1;
@@ -108,8 +115,8 @@ __device__ __forceinline__ int gated_nodes(const PList<ENC, W> &L, int l, uint32
 // The gates of slice s on one component (address a).  Returns true when the
 // qubit fetch flips its sign.  Every gate is a permutation of basis labels;
 // it is applied entry by entry from the list as it was before the gate.
-template <int ENC, typename W>
-__device__ __forceinline__ bool plain_gates(const Tables *__restrict__ tb, int s, PList<ENC, W> L, uint32_t a,
+template <int ENC, typename W, bool STR>
+__device__ __forceinline__ bool plain_gates(const Tables *__restrict__ tb, int s, PList<ENC, W, STR> L, uint32_t a,
                                             uint32_t *err) {
   const int n = tb->n;
   bool flip = false;
@@ -120,11 +127,11 @@ __device__ __forceinline__ bool plain_gates(const Tables *__restrict__ tb, int s
     if (ENC == QUBIT) {  // SWAP(a_v, d_v) on every node of the layer
       for (int j = 0; j < L.cnt(); ++j) {
         const uint32_t q = L.raw(j);
-        if (layer_of(q >> 1) == sl) L.r[PL_HDR + j] = (uint16_t)(q ^ 1u);
+        if (layer_of(q >> 1) == sl) L.at(PL_HDR + j) = (uint16_t)(q ^ 1u);
       }
     } else {  // (W,b) <-> (L or R by b, 0) on the gated nodes
       uint32_t gv[PL_GATED];
-      const int ng = gated_nodes<ENC, W>(L, sl, gv, err);
+      const int ng = gated_nodes(L, sl, gv, err);
       for (int g = 0; g < ng && g < PL_GATED; ++g) {
         const uint32_t v = gv[g];
         const int jr = L.find(2 * v), jd = L.find(2 * v + 1);
@@ -191,25 +198,25 @@ __device__ __forceinline__ bool plain_gates(const Tables *__restrict__ tb, int s
       const int l = layer_of(v);
       if ((cm >> l) & 1u) {
         const int d = routed(v);
-        if (d >= 0) L.r[PL_HDR + j] = (uint16_t)(2 * (2 * v + 1 + (uint32_t)d) + 1);
+        if (d >= 0) L.at(PL_HDR + j) = (uint16_t)(2 * (2 * v + 1 + (uint32_t)d) + 1);
       } else if (l >= 1 && ((cm >> (l - 1)) & 1u)) {
         const uint32_t p = (v - 1) >> 1;
         const int d = routed(p);
-        if (d >= 0 && v == 2 * p + 1 + (uint32_t)d) L.r[PL_HDR + j] = (uint16_t)(2 * p + 1);
+        if (d >= 0 && v == 2 * p + 1 + (uint32_t)d) L.at(PL_HDR + j) = (uint16_t)(2 * p + 1);
       }
     }
   }
   const int bb = tb->bus_b[s];
   if (bb >= 0) {  // SWAP(bus_b, d_0)
     const int j = L.find(1);
-    const uint32_t bus = L.r[1];
+    const uint32_t bus = L.at(1);
     const bool bbit = (bus >> bb) & 1u;
     if (j >= 0 && !bbit) {
       L.remove(j);
-      L.r[1] = (uint16_t)(bus | (1u << bb));
+      L.at(1) = (uint16_t)(bus | (1u << bb));
     } else if (j < 0 && bbit) {
       L.add(1, err);
-      L.r[1] = (uint16_t)(bus & ~(1u << bb));
+      L.at(1) = (uint16_t)(bus & ~(1u << bb));
     }
   }
   const int fb = tb->fetch_b[s];
@@ -253,8 +260,8 @@ __device__ __forceinline__ uint32_t phase_w3(uint32_t ph, uint32_t t) {
   return (ph & 1u) | ((((ph >> 1) + t) % 3u) << 1);
 }
 
-template <int ENC, typename W>
-__device__ __forceinline__ void plain_fault(PList<ENC, W> L, uint32_t &ph, uint32_t q, uint32_t a, uint32_t b,
+template <int ENC, typename W, bool STR>
+__device__ __forceinline__ void plain_fault(PList<ENC, W, STR> L, uint32_t &ph, uint32_t q, uint32_t a, uint32_t b,
                                             uint32_t *err) {
   const bool tri = ENC == QUTRIT && (q & 1u) == 0;
   const int j = L.find(q);
@@ -294,26 +301,26 @@ __device__ __forceinline__ double2 apply_phase(double2 z, uint32_t ph) {
 // damping factor a^|X| counted in the record (the count multiplied into the
 // amplitude first when it would leave the power tables), and with
 // candidates the hit test (returned).
-template <int ENC, typename W>
-__device__ __forceinline__ int plain_slice(const Tables *__restrict__ tb, int s, PList<ENC, W> L, uint32_t a,
+template <int ENC, typename W, bool STR>
+__device__ __forceinline__ int plain_slice(const Tables *__restrict__ tb, int s, PList<ENC, W, STR> L, uint32_t a,
                                            const uint32_t *__restrict__ dep, uint32_t d0, uint32_t d1,
                                            uint32_t nc, const uint32_t *cbm, double2 *ampy,
                                            const double *__restrict__ apow, int emat, uint32_t *err) {
-  uint32_t ph = L.r[3];
+  uint32_t ph = L.at(3);
   if (plain_gates<ENC>(tb, s, L, a, err)) ph ^= 1u;
   for (uint32_t f = d0; f < d1; ++f) {  // faults after the gates, before the damping layer
     const uint32_t e = dep[f], t = e >> 24;
     plain_fault<ENC>(L, ph, e & 0xFFFFu, t & 3u, t >> 2, err);
   }
-  int e = L.r[2];
+  int e = L.at(2);
   const int cx = L.cnt();
   if (e + cx > emat) {
     const double f = apow[e];
     *ampy = make_double2(ampy->x * f, ampy->y * f);
     e = 0;
   }
-  L.r[2] = (uint16_t)(e + cx);
-  L.r[3] = (uint16_t)ph;
+  L.at(2) = (uint16_t)(e + cx);
+  L.at(3) = (uint16_t)ph;
   int hit = 0;
   if (nc > 0)
     for (int j = 0; j < L.cnt() && !hit; ++j) {
@@ -328,11 +335,11 @@ __device__ __forceinline__ int plain_slice(const Tables *__restrict__ tb, int s,
 // add to the staged path's.
 template <int ENC>
 __device__ __attribute__((noinline)) int plain_slice_mem(const Tables *__restrict__ tb, int s, uint16_t *g, int lcap,
-                                                         uint32_t a, const uint32_t *__restrict__ dep, uint32_t d0,
-                                                         uint32_t d1, uint32_t nc, const uint32_t *cbm,
+                                                         uint32_t ps, uint32_t a, const uint32_t *__restrict__ dep,
+                                                         uint32_t d0, uint32_t d1, uint32_t nc, const uint32_t *cbm,
                                                          double2 *ampy, const double *__restrict__ apow, int emat,
                                                          uint32_t *err) {
-  return plain_slice<ENC, uint16_t>(tb, s, PList<ENC>{g, lcap}, a, dep, d0, d1, nc, cbm, ampy, apow, emat, err);
+  return plain_slice(tb, s, PList<ENC, uint16_t, true>{g, lcap, ps}, a, dep, d0, d1, nc, cbm, ampy, apow, emat, err);
 }
 
 struct PlainSm {
@@ -364,19 +371,22 @@ __device__ inline PlainSm plain_carve(unsigned char *base, int M) {
   return s;
 }
 
-// A record copied from the pool into a thread's slab (sw words, a multiple
-// of 8) in 16-byte pieces: the header words and the sites in use.  The
+// A record copied from the pool (its pieces ps words apart) into a thread's
+// slab (sw words, a multiple of 8) in 16-byte pieces: the header words and
+// the sites in use.  The
 // first two pieces (the header and up to 12 sites) are loaded together,
 // before the count is known.  A record
 // is staged only when it fits the slab with `margin` words to spare (the
 // most a slice's gates and faults can add); returns false, having copied
 // only the first pieces, when it does not.
-__device__ __forceinline__ bool rec_load(lds_u16 *dst, const uint16_t *__restrict__ src, int sw, int margin) {
+__device__ __forceinline__ bool rec_load(lds_u16 *dst, const uint16_t *__restrict__ src, uint32_t ps, int sw,
+                                         int margin) {
   const u32x4 *s4 = reinterpret_cast<const u32x4 *>(src);
+  const size_t pv = ps >> 3;  // (pieces apart, in 16-byte units)
   lds_u4 *d4 = (lds_u4 *)dst;
   const int nv_all = sw >> 3;
   const u32x4 v0 = s4[0];
-  const u32x4 v1 = nv_all > 1 ? s4[1] : v0;
+  const u32x4 v1 = nv_all > 1 ? s4[pv] : v0;
   d4[0] = v0;
   if (nv_all > 1) d4[1] = v1;
   const uint32_t c = v0.x & 0xFFFFu;
@@ -384,10 +394,10 @@ __device__ __forceinline__ bool rec_load(lds_u16 *dst, const uint16_t *__restric
   if ((int)(PL_HDR + c) + margin > sw) return false;
   const int nv = (int)(PL_HDR + c + 7) >> 3;
   for (int i = 2; i < nv; i += 4) {  // longer lists: four pieces in flight at a time
-    const u32x4 w0 = s4[i];
-    const u32x4 w1 = i + 1 < nv ? s4[i + 1] : w0;
-    const u32x4 w2 = i + 2 < nv ? s4[i + 2] : w0;
-    const u32x4 w3 = i + 3 < nv ? s4[i + 3] : w0;
+    const u32x4 w0 = s4[i * pv];
+    const u32x4 w1 = i + 1 < nv ? s4[(i + 1) * pv] : w0;
+    const u32x4 w2 = i + 2 < nv ? s4[(i + 2) * pv] : w0;
+    const u32x4 w3 = i + 3 < nv ? s4[(i + 3) * pv] : w0;
     d4[i] = w0;
     if (i + 1 < nv) d4[i + 1] = w1;
     if (i + 2 < nv) d4[i + 2] = w2;
@@ -396,12 +406,13 @@ __device__ __forceinline__ bool rec_load(lds_u16 *dst, const uint16_t *__restric
   return true;
 }
 
-__device__ __forceinline__ void rec_store(uint16_t *__restrict__ dst, const lds_u16 *src, int sw) {
+__device__ __forceinline__ void rec_store(uint16_t *__restrict__ dst, uint32_t ps, const lds_u16 *src, int sw) {
   const lds_u4 *s4 = (const lds_u4 *)src;
   u32x4 *d4 = reinterpret_cast<u32x4 *>(dst);
+  const size_t pv = ps >> 3;
   const uint32_t c = src[0];
   const int nv = c == PL_DEAD ? 1 : min(sw >> 3, (int)(PL_HDR + c + 7) >> 3);
-  for (int i = 0; i < nv; ++i) d4[i] = s4[i];
+  for (int i = 0; i < nv; ++i) d4[i * pv] = s4[i];
 }
 
 __device__ __forceinline__ double abs2(double2 z) { return z.x * z.x + z.y * z.y; }
@@ -503,6 +514,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
     const uint16_t *__restrict__ xl = pruned ? rp->xlist + (size_t)tj * D : nullptr;
     const uint32_t A = pruned ? (rp->nexpl[tj] >> kb) : (uint32_t)D;
     const uint32_t E = A * (uint32_t)K2;
+    const uint32_t ps = E * 8u;  // words between the pieces of a record in the pool
     const uint64_t *__restrict__ badg = rp->badbits + (size_t)tj * ((D + 63) >> 6);
     // the good branches ride on the reference (pruned, a reference exists)
     const bool goods = pruned && ref != 0xFFFFFFFFu && A < (uint32_t)D;
@@ -522,7 +534,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
     // qutrit: c_ij, alive when nonzero).
     const double wall = ENC == QUBIT ? 1.0 / sqrt((double)K2) : 1.0;
     for (uint32_t y = tid; y < E; y += nthr) {
-      uint16_t *r = pool + (size_t)y * rec;
+      uint16_t *r = pool + (size_t)y * 8;  // (the header: piece 0)
       const uint32_t g = y >> kb, beta = y & (uint32_t)(K2 - 1);
       const uint32_t i = xl ? xl[g] : g;
       if (i == ref) sm.misc[8] = (int)g;
@@ -560,11 +572,11 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
     // damping layer (its record counts that layer's a^|X| already), and its
     // amplitude with every counted factor multiplied in
     auto wt = [&](uint32_t y) -> double {
-      const uint16_t *r = pool + (size_t)y * rec;
+      const uint16_t *r = pool + (size_t)y * 8;
       return abs2(amp[y]) * wpow[(int)r[2] - (int)r[0]];
     };
     auto amp_of = [&](uint32_t y) -> double2 {
-      const uint16_t *r = pool + (size_t)y * rec;
+      const uint16_t *r = pool + (size_t)y * 8;
       const double f = apow[r[2]];
       return apply_phase(make_double2(amp[y].x * f, amp[y].y * f), r[3]);
     };
@@ -610,7 +622,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
         const uint32_t i = z >> kb, beta = z & (uint32_t)(K2 - 1);
         if (tb->aflag[i] != 1u || is_bad(i)) continue;  // present, several bus words
         const uint32_t yr = (uint32_t)gref * K2 + beta;
-        if (pool[(size_t)yr * rec] == PL_DEAD) continue;
+        if (pool[(size_t)yr * 8] == PL_DEAD) continue;
         const double w = multi_ratio(i, beta, s, eref) * wt(yr);
         if (hitf[yr])
           wh += w;
@@ -652,17 +664,18 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
       // (the slice's K_0 = a^|X| joins each record's exposure; a jump takes
       // back its sites' share below)
       for (uint32_t y = tid; y < E; y += nthr) {
-        uint16_t *const g = pool + (size_t)y * rec;
+        uint16_t *const g = pool + (size_t)y * 8;
         const uint32_t a = xl ? xl[y >> kb] : (y >> kb);
         int hit;
-        if (slab && rec_load((lds_u16 *)slab, g, sw, margin)) {
+        if (slab && rec_load((lds_u16 *)slab, g, ps, sw, margin)) {
           PList<ENC, lds_u16> L{(lds_u16 *)slab, sw - PL_HDR};
           if (L.cnt() == PL_DEAD) continue;
-          hit = plain_slice<ENC>(tb, s, L, a, dep, d0, dpos, nc, sm.cbm, amp + y, apow, emat, rp->err);
-          rec_store(g, (lds_u16 *)slab, sw);
+          hit = plain_slice(tb, s, L, a, dep, d0, dpos, nc, sm.cbm, amp + y, apow, emat, rp->err);
+          rec_store(g, ps, (lds_u16 *)slab, sw);
         } else {
           if (g[0] == PL_DEAD) continue;
-          hit = plain_slice_mem<ENC>(tb, s, g, lcap, a, dep, d0, dpos, nc, sm.cbm, amp + y, apow, emat, rp->err);
+          hit = plain_slice_mem<ENC>(tb, s, g, lcap, ps, a, dep, d0, dpos, nc, sm.cbm, amp + y, apow, emat,
+                                     rp->err);
         }
         if (nc > 0) {
           hitf[y] = (uint8_t)hit;
@@ -680,7 +693,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
         // weight not hit and hit
         double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (uint32_t y = tid; y < E; y += nthr) {
-          if (pool[(size_t)y * rec] == PL_DEAD) continue;
+          if (pool[(size_t)y * 8] == PL_DEAD) continue;
           const double w = wt(y);
           const int h = hitf[y] ? 1 : 0;
           acc[h] += w;
@@ -717,7 +730,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
             double w = 0.0;
             int my = -1;
             if (x < Lx && !labels) {
-              if (pool[(size_t)x * rec] != PL_DEAD && hitf[x]) {
+              if (pool[(size_t)x * 8] != PL_DEAD && hitf[x]) {
                 w = wt(x);
                 my = (int)x;
               }
@@ -739,14 +752,14 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
               }
               if (g >= 0) {
                 const uint32_t y = (uint32_t)g * K2 + beta;
-                if (pool[(size_t)y * rec] != PL_DEAD && hitf[y]) {
+                if (pool[(size_t)y * 8] != PL_DEAD && hitf[y]) {
                   w = wt(y);
                   my = (int)y;
                 }
               } else if (goods) {  // a good label follows the reference's component
                 uint32_t yr = 0;
                 const double rw = good_label(a, beta, s - 1, eref, yr);
-                if (rw > 0.0 && pool[(size_t)yr * rec] != PL_DEAD && hitf[yr]) {
+                if (rw > 0.0 && pool[(size_t)yr * 8] != PL_DEAD && hitf[yr]) {
                   w = wt(yr) * rw;
                   if (w > 0.0) my = (int)yr;
                 }
@@ -794,7 +807,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
           if (pick < 0) pick_y = last_y;
           // J = the slice's candidates among x*'s excited sites, with levels
           if (tid == 0) {
-            PList<ENC> L{pool + (size_t)pick_y * rec, lcap};
+            PList<ENC, uint16_t, true> L{pool + (size_t)pick_y * 8, lcap, ps};
             int m = 0;
             for (int j = 0; j < L.cnt(); ++j) {
               const uint32_t x = L.raw(j), q = x & PList<ENC>::SM;
@@ -820,10 +833,10 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
       // having counted a^|X| for the slice.  Without a jump K_0 = a^|X| is
       // counted already.
       for (uint32_t y = tid; nJ > 0 && y < E; y += nthr) {
-        uint16_t *const g = pool + (size_t)y * rec;
+        uint16_t *const g = pool + (size_t)y * 8;
         if (g[0] == PL_DEAD) continue;
         // (a jump changes few entries: the record is edited in place)
-        PList<ENC> L{g, lcap};
+        PList<ENC, uint16_t, true> L{g, lcap, ps};
         bool ok = true;
         for (int c = 0; c < nJ && ok; ++c) {
           const uint32_t q = sm.J[c] & 0xFFFFu, lev = sm.J[c] >> 16;
@@ -862,7 +875,8 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
     if (rp->exp && tj == 0) {  // test entry: every explicit component's final list and amplitude
       const uint32_t rw = 3u + (uint32_t)tb->lmax;
       for (uint32_t y = tid; y < E; y += nthr) {
-        const uint16_t *r = pool + (size_t)y * rec;
+        uint16_t *const r = pool + (size_t)y * 8;
+        const PList<ENC, uint16_t, true> L{r, lcap, ps};
         const uint32_t a = xl ? xl[y >> kb] : (y >> kb);
         const uint32_t x = (a << kb) | (y & (uint32_t)(K2 - 1));
         uint32_t *o = rp->exp + (size_t)x * rw;
@@ -873,7 +887,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
         o[1] = 0;
         o[2] = m;
         for (uint32_t j = 0; j < m; ++j) {
-          const uint32_t e = r[PL_HDR + j];
+          const uint32_t e = L.raw(j);
           const uint32_t q = e & PList<ENC>::SM, lev = (ENC == QUTRIT && (e & LV_R_BIT)) ? 2u : 1u;
           o[3 + j] = q | (lev << 16);
         }
@@ -913,7 +927,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
       for (int b = 0; b < nw; ++b) grp[b] = make_double2(0.0, 0.0);
       for (int b = 0; b < K2; ++b) {
         const uint32_t y = g * (uint32_t)K2 + (uint32_t)b;
-        const uint16_t *r = pool + (size_t)y * rec;
+        const uint16_t *r = pool + (size_t)y * 8;
         if (r[0] == PL_DEAD) continue;
         if (isref) fin[4] = 1.0;
         const double2 at = amp_of(y);
@@ -1003,7 +1017,7 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
           bool any = false;
           for (int b = 0; b < K2; ++b) {
             const uint32_t yr = (uint32_t)gref * K2 + (uint32_t)b;
-            const uint16_t *r = pool + (size_t)yr * rec;
+            const uint16_t *r = pool + (size_t)yr * 8;
             grp[b] = make_double2(0.0, 0.0);
             if (r[0] == PL_DEAD) continue;
             const double2 ca = camp_of(tb, ((size_t)i << kb) + b), cr = camp_of(tb, ((size_t)ref << kb) + b);
