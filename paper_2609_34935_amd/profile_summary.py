@@ -22,7 +22,8 @@ import os
 from collections import OrderedDict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SRCS = [os.path.join(HERE, "csrc", f) for f in ("qram_evolve.hip", "qram_device.h", "qram_internal.h")]
+KERNEL_SRCS = [os.path.join(HERE, "csrc", f)
+               for f in ("qram_evolve.hip", "qram_device.h", "qram_internal.h", "qram_records.h")]
 COPY_BYTES = 268435456
 
 
@@ -85,10 +86,9 @@ def _match(v, kernel, wg):
 
 
 def counter_summary(fetch, write, sq, kernel, out, commands, wg=None, srcs=None):
-    srcs = [os.path.abspath(f) for f in srcs] if srcs else None
-    res = {"kernel": kernel, "workgroup": wg, "kernel_sha256": kernel_sha256(srcs), "commands": commands}
-    if srcs:
-        res["sources"] = [os.path.relpath(f, os.path.dirname(HERE)) for f in srcs]
+    srcs = [os.path.abspath(f) for f in srcs] if srcs else KERNEL_SRCS
+    res = {"kernel": kernel, "workgroup": wg, "kernel_sha256": kernel_sha256(srcs), "commands": commands,
+           "sources": [os.path.relpath(f, os.path.dirname(HERE)) for f in srcs]}
     for path, ctr, tag in ((fetch, "FETCH_SIZE", "fetch"), (write, "WRITE_SIZE", "write")):
         d = _per_dispatch(path)
         copies = [v[ctr] for v in d.values() if "copyBuffer" in v["name"] and ctr in v]
