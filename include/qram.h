@@ -266,7 +266,9 @@ qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,
  * engine (QRAM_MODE_PLAIN, and every mode of a context with depolarizing
  * noise, a general input, truncation or qubit k > 6): slots_per_thread is the
  * number of workgroups per compute unit (1..32, capped by what fits; 0 =
- * automatic: all that fit) and schedule the threads per workgroup (64, 128
+ * automatic: all that fit; the kernel has builds for three register budgets,
+ * and a launch takes the largest budget that still fits the number asked
+ * for) and schedule the threads per workgroup (64, 128
  * or 256; 0 = automatic: 256, or 64 (pruned) / 128 (full) when a trajectory
  * holds at most 256 components and the run is not split), plus 1 to work on
  * each component record in device memory instead of staging it in shared

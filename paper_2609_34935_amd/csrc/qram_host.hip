@@ -46,6 +46,7 @@ struct Plan {
   BucketShape pb{};
   uint32_t plds = 0;
   uint32_t pslab = 0;  // words of each thread's record slab in shared memory (0: none)
+  int pvar = 0;        // the plain kernel's register budget (plain_variant)
   // split plan (pruned mode with depolarizing noise on the data-loading
   // input): the trajectory kernel's buckets take the trajectories without a
   // depolarizing fault, the plain engine the others
@@ -472,7 +473,8 @@ qram_status plain_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
   plain_shape(c, mode, threads, per_cu, glob);
   pl.plds = plain_lds(c, threads, glob);
   pl.pslab = plain_slab(c, threads, glob);
-  const int occ = plain_occupancy(c->enc, threads, pl.plds);
+  int occ = 0;
+  pl.pvar = plain_variant(c->enc, threads, pl.plds, per_cu, occ);
   if (occ < 1) return fail(c, QRAM_E_DEVICE, "plain engine: no workgroup fits a compute unit");
   per_cu = std::min(per_cu, occ);
   // every workgroup holds a trajectory's whole explicit state in device
@@ -749,12 +751,12 @@ qram_status enqueue_batch(qram_ctx *c, const Plan &pl, Run r, hipStream_t s,
   if (!pl.plain) HIPCHK(c, launch_order(c->dtab, r, s));
   if (timed) HIPCHK(c, hipEventRecord(e[2], s));
   if (pl.plain) {
-    HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.pb.grid, pl.pb.threads, pl.plds, s));
+    HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.pvar, pl.pb.grid, pl.pb.threads, pl.plds, s));
   } else {
     qram_status st = launch_buckets(c, pl, r, s, be);
     if (st) return st;
     if (pl.split)  // the trajectories that drew a depolarizing fault
-      HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.pb.grid, pl.pb.threads, pl.plds, s));
+      HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.pvar, pl.pb.grid, pl.pb.threads, pl.plds, s));
   }
   if (timed) HIPCHK(c, hipEventRecord(e[3], s));
   return QRAM_OK;
@@ -780,6 +782,7 @@ uint64_t plan_signature(const Plan &pl) {
   mix(pl.pslab);
   mix((uint64_t)pl.pb.threads);
   mix(pl.pb.grid);
+  mix((uint64_t)pl.pvar);
   for (int i = 0; i < pl.nb; ++i) {
     const BucketShape &b = pl.b[i];
     mix(b.emax);
@@ -1693,7 +1696,7 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
           HIPCHK(c, launch_order(c->dtab, r, c->stream));
           if ((st = launch_buckets(c, pl, r, c->stream))) return st;
         }
-        HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.pb.grid, pl.pb.threads, pl.plds, c->stream));
+        HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.pvar, pl.pb.grid, pl.pb.threads, pl.plds, c->stream));
         HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
         HIPCHK(c, hipEventSynchronize(c->ev[1]));
         float t;

@@ -192,8 +192,14 @@ constexpr double PLAIN_POOL_BYTES = 16.0 * 1024 * 1024 * 1024;  // plain-engine 
 constexpr uint32_t PLAIN_SLAB_BYTES = 40 * 1024;  // per-workgroup record slabs in shared memory, at most
 constexpr int PLAIN_EXTRA = 8;  // list entries beyond the excitation bound
 uint32_t plain_lds_bytes(int M, uint32_t slab_words);
+// the most plain-engine workgroups of `threads` a compute unit holds, over
+// the kernel's register budgets
 int plain_occupancy(int enc, int threads, uint32_t lds_bytes);
-hipError_t launch_plain(const Tables *tb, const Run &rp, int enc, uint32_t grid, int threads, uint32_t lds_bytes,
+// the register budget for a launch asking for per_cu workgroups per compute
+// unit (occ: how many it holds)
+int plain_variant(int enc, int threads, uint32_t lds_bytes, int per_cu, int &occ);
+hipError_t launch_plain(const Tables *tb, const Run &rp, int enc, int variant, uint32_t grid, int threads,
+                        uint32_t lds_bytes,
                         hipStream_t s);
 hipError_t evolve_prepare(int lds_max, int *dyn_max);
 

@@ -460,8 +460,11 @@ __device__ __forceinline__ double2 in_ab(const Tables *__restrict__ tb, uint32_t
   return j == in_bus(tb, i) ? in_amp(tb, i) : make_double2(0.0, 0.0);
 }
 
-template <int ENC>
-__global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, const Run R_) {
+// WPE: the register budget, as waves per SIMD the kernel must allow (1:
+// unconstrained; see plain_variant below)
+template <int ENC, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_plain(const Tables *__restrict__ tb, const Run R_) {
   const Run *rp = &R_;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -1094,22 +1097,70 @@ __global__ void __launch_bounds__(256) k_plain(const Tables *__restrict__ tb, co
 
 uint32_t plain_lds_bytes(int M, uint32_t slab_words) { return plain_sm_head(M) + slab_words * 2u; }
 
-int plain_occupancy(int enc, int threads, uint32_t lds_bytes) {
+// Register budgets of the plain kernel, tried in this order: unconstrained
+// (about 150 registers, three waves per SIMD), at most 128 registers (four
+// waves) and, qubit only, at most 96 (five).  The capped builds spill a few
+// words outside the record loop; they pay where registers, not shared
+// memory, limit the workgroups a compute unit holds (short records in
+// small slabs).  A launch takes the first budget that fits the workgroups
+// per compute unit it asks for, else the one that fits the most.
+namespace {
+template <int ENC, int WPE>
+int plain_occ_one(int threads, uint32_t lds_bytes) {
   int blocks = 0;
-  const hipError_t e = enc == QUBIT
-                           ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<QUBIT>, threads, lds_bytes)
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<QUTRIT>, threads, lds_bytes);
-  return e == hipSuccess ? blocks : 0;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<ENC, WPE>, threads, lds_bytes) == hipSuccess
+             ? blocks
+             : 0;
+}
+int plain_occ_variant(int enc, int threads, uint32_t lds_bytes, int v) {
+  if (enc == QUBIT)
+    return v == 0 ? plain_occ_one<QUBIT, 1>(threads, lds_bytes)
+                  : (v == 1 ? plain_occ_one<QUBIT, 4>(threads, lds_bytes) : plain_occ_one<QUBIT, 5>(threads, lds_bytes));
+  return v == 0 ? plain_occ_one<QUTRIT, 1>(threads, lds_bytes) : plain_occ_one<QUTRIT, 4>(threads, lds_bytes);
+}
+}  // namespace
+
+int plain_variant(int enc, int threads, uint32_t lds_bytes, int per_cu, int &occ) {
+  int var = 0;
+  occ = 0;
+  for (int v = 0; v < (enc == QUBIT ? 3 : 2); ++v) {
+    const int o = plain_occ_variant(enc, threads, lds_bytes, v);
+    if (o >= per_cu) {
+      occ = o;
+      return v;
+    }
+    if (o > occ) {
+      occ = o;
+      var = v;
+    }
+  }
+  return var;
 }
 
-hipError_t launch_plain(const Tables *tb, const Run &rp, int enc, uint32_t grid, int threads, uint32_t lds_bytes,
-                        hipStream_t s) {
+int plain_occupancy(int enc, int threads, uint32_t lds_bytes) {
+  int occ = 0;
+  plain_variant(enc, threads, lds_bytes, 1 << 30, occ);
+  return occ;
+}
+
+hipError_t launch_plain(const Tables *tb, const Run &rp, int enc, int variant, uint32_t grid, int threads,
+                        uint32_t lds_bytes, hipStream_t s) {
   const hipError_t e = launch_fill_u32(rp.counter, 0u, 1u, s);  // the queue head
   if (e != hipSuccess) return e;
-  if (enc == QUBIT)
-    hipLaunchKernelGGL(k_plain<QUBIT>, dim3(grid), dim3(threads), lds_bytes, s, tb, rp);
-  else
-    hipLaunchKernelGGL(k_plain<QUTRIT>, dim3(grid), dim3(threads), lds_bytes, s, tb, rp);
+  const dim3 g(grid), b(threads);
+  if (enc == QUBIT) {
+    if (variant == 2)
+      hipLaunchKernelGGL((k_plain<QUBIT, 5>), g, b, lds_bytes, s, tb, rp);
+    else if (variant == 1)
+      hipLaunchKernelGGL((k_plain<QUBIT, 4>), g, b, lds_bytes, s, tb, rp);
+    else
+      hipLaunchKernelGGL((k_plain<QUBIT, 1>), g, b, lds_bytes, s, tb, rp);
+  } else {
+    if (variant == 1)
+      hipLaunchKernelGGL((k_plain<QUTRIT, 4>), g, b, lds_bytes, s, tb, rp);
+    else
+      hipLaunchKernelGGL((k_plain<QUTRIT, 1>), g, b, lds_bytes, s, tb, rp);
+  }
   return hipGetLastError();
 }
 

@@ -140,6 +140,30 @@ def test_plain_launch_shapes(lib, orc, per_cu, threads):
     check_against_oracle(f, st, fo, fpo, so, per_cu)
 
 
+@pytest.mark.parametrize("enc,n,k", [(QUBIT, 5, 3), (QUTRIT, 6, 2)])
+def test_plain_register_budgets(lib, orc, enc, n, k):
+    """Asking for more workgroups per compute unit than the unconstrained
+    build holds selects the kernel's capped register budgets (short records,
+    small slabs: registers set the limit); every budget gives the oracle's
+    results, and the same fidelities bit for bit."""
+    gamma, nt = 0.03, 900
+    mem = memory_words(n, k, 57)
+    fo, fpo, so, _ = orc.run_batch(n, k, enc, gamma, mem, 98, 0, nt)
+    with lib.QramContext(n, k, enc, gamma, mem) as ctx:
+        first = None
+        for per_cu in (1, 3, 4, 5, 32):
+            ctx.set_launch(PLAIN, per_cu, 256)
+            got = ctx.get_launch(PLAIN)
+            assert got[1] == 256 and 1 <= got[0] <= per_cu
+            f, st = ctx.run_plain(98, 0, nt)
+            check_against_oracle(f, st, fo, fpo, so, (enc, per_cu))
+            if first is None:
+                first = f
+            assert np.array_equal(f, first), (enc, per_cu)
+        ctx.set_launch(PLAIN, 32, 256)
+        assert ctx.get_launch(PLAIN)[0] >= (5 if enc == QUBIT else 4)
+
+
 def test_plain_engine_shapes_on_depolarizing_context(lib, orc):
     """Both modes of a depolarizing context run on the plain engine; every
     workgroup size gives the oracle's fidelities."""
