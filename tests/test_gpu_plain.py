@@ -127,6 +127,27 @@ def test_plain_forced_histories(lib, orc, enc):
             assert st["q_ground"] == ref["q_ground"] and st["ref_survived"] == ref["ref_survived"]
 
 
+@pytest.mark.parametrize("n,k,enc,gamma,nsample,nt", [
+    (15, 1, QUBIT, 1e-3, 2, 64),    # largest qubit tree: 65536 components per trajectory
+    (14, 8, QUTRIT, 2e-3, 2, 64),   # largest qutrit tree and data word
+    (8, 8, QUBIT, 1e-2, 4, 128)])   # widest qubit bus word (every mode on the plain engine)
+def test_plain_maximum_sizes(lib, orc, n, k, enc, gamma, nsample, nt):
+    """The plain evolution at the largest trajectories, where its pool's
+    pieces lie furthest apart: the first trajectories equal the oracle, all
+    of them the pruned mode."""
+    mem = memory_words(n, k, 4100 + n + k)
+    seed = 991000 + n
+    print(f"plain maximum size n={n} k={k} enc={enc}: {nt} trajectories", flush=True)
+    fo, fpo, so, _ = orc.run_batch(n, k, enc, gamma, mem, seed, 0, nsample, nthreads=min(16, os.cpu_count() or 1))
+    with lib.QramContext(n, k, enc, gamma, mem) as ctx:
+        f, st = ctx.run_plain(seed, 0, nt)
+        fp, sp = ctx.run_pruned(seed, 0, nt)
+    check_against_oracle(f[:nsample], st[:nsample], fo, fpo, so, ("max", n, k, enc))
+    assert np.all(fid_close(f, fp))
+    for fld in ("n_cand", "n_jumps", "first_jump_slice", "q_ground"):
+        assert np.array_equal(st[fld], sp[fld]), fld
+
+
 @pytest.mark.parametrize("per_cu,threads", [(1, 0), (2, 256), (4, 128), (8, 64), (32, 64), (3, 128)])
 def test_plain_launch_shapes(lib, orc, per_cu, threads):
     n, k, enc, gamma, nt = 5, 3, QUBIT, 0.03, 700
