@@ -447,15 +447,31 @@ void plain_shape(const qram_ctx *c, int mode, int &threads, int &per_cu, bool &g
   glob = c->plain_glob[m];
 }
 
+// The slabs' share of a workgroup's shared memory.  With depolarizing noise
+// the record capacity counts every stray a trajectory may hold, so slabs
+// are shorter than records and the budget decides how many workgroups a
+// compute unit holds.  Qubit trajectories that draw few faults (their
+// lists stay short) run faster with a smaller budget, which lets five
+// workgroups of the 96-register build share a compute unit, than with
+// longer slabs; many faults lengthen every list, and the larger budget
+// keeps more of them in shared memory.  The qutrit kernel has no build
+// that holds five, and keeps the larger budget.
+constexpr uint32_t PLAIN_SLAB_FEW_FAULTS_BYTES = 26 * 1024;
+constexpr double PLAIN_FEW_FAULTS = 32.0;  // expected faults per trajectory
+uint32_t plain_slab_budget(const qram_ctx *c) {
+  if (c->eps <= 0.0 || c->enc != QUBIT) return PLAIN_SLAB_BYTES;
+  const double faults = c->eps * (double)c->htab.dep_off[c->T];
+  return faults <= PLAIN_FEW_FAULTS ? PLAIN_SLAB_FEW_FAULTS_BYTES : PLAIN_SLAB_BYTES;
+}
+
 // Shared memory of a plain-engine workgroup of `threads`: the slice state,
 // and a record slab per thread (words; 0 when the records stay in device
-// memory: asked for, QRAM_OPT_TIER2_GLOBAL, or a slab within
-// PLAIN_SLAB_BYTES that is shorter than both the record and 32 words).  A
-// slab shorter than the record capacity (which counts every depolarizing
-// stray a trajectory may hold) takes the records that fit it.
+// memory: asked for, QRAM_OPT_TIER2_GLOBAL, or a slab within the budget
+// that is shorter than both the record and 32 words).  A slab shorter than
+// the record capacity takes the records that fit it.
 uint32_t plain_slab(const qram_ctx *c, int threads, bool glob) {
   if (glob || c->tier2_global) return 0;
-  const uint32_t sw = std::min<uint32_t>((uint32_t)c->prec, (PLAIN_SLAB_BYTES / 2u / (uint32_t)threads) & ~7u);
+  const uint32_t sw = std::min<uint32_t>((uint32_t)c->prec, (plain_slab_budget(c) / 2u / (uint32_t)threads) & ~7u);
   return (sw == (uint32_t)c->prec || sw >= 32u) ? sw : 0u;
 }
 uint32_t plain_lds(const qram_ctx *c, int threads, bool glob) {
