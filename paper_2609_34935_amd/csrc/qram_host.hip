@@ -436,13 +436,23 @@ uint32_t pow2ceil(uint32_t x) {
 // engine waits on memory more than it computes), of 256 threads, or of 64 /
 // 128 threads when a trajectory holds at most 256 components (pruned /
 // full), so that small trajectories do not leave most lanes idle.
+// A split pruned run's plain share is few trajectories, and its time is
+// that of its longest ones (a fault near the root leaves nearly the whole
+// tree bad), which one workgroup evolves alone: 256 threads, or 1024 when
+// at most 60% of the trajectories draw a fault and a trajectory holds at
+// least 1024 components (with more faulted trajectories the share fills
+// the device and smaller workgroups keep more of them in flight).
 void plain_shape(const qram_ctx *c, int mode, int &threads, int &per_cu, bool &glob) {
   const int m = mode;
   threads = c->plain_thr[m];
-  // (a split pruned run's plain share is a few trajectories: 256 threads
-  // finish each soonest)
   const bool share = c->dsplit && mode == QRAM_MODE_PRUNED;
-  if (!threads) threads = (c->Emax > 256 || share) ? PLAIN_THREADS : (mode == QRAM_MODE_PRUNED ? 64 : 128);
+  if (!threads) {
+    const double pf = share ? 1.0 - std::pow(1.0 - c->eps, (double)c->htab.dep_off[c->T]) : 1.0;
+    if (share && c->Emax >= 1024 && pf <= 0.6)
+      threads = 1024;
+    else
+      threads = (c->Emax > 256 || share) ? PLAIN_THREADS : (mode == QRAM_MODE_PRUNED ? 64 : 128);
+  }
   per_cu = c->plain_per_cu[m] ? c->plain_per_cu[m] : 32;  // (capped by occupancy)
   glob = c->plain_glob[m];
 }
@@ -471,7 +481,10 @@ uint32_t plain_slab_budget(const qram_ctx *c) {
 // the record capacity takes the records that fit it.
 uint32_t plain_slab(const qram_ctx *c, int threads, bool glob) {
   if (glob || c->tier2_global) return 0;
-  const uint32_t sw = std::min<uint32_t>((uint32_t)c->prec, (plain_slab_budget(c) / 2u / (uint32_t)threads) & ~7u);
+  // (workgroups of more than 256 threads, one or two per compute unit: 40
+  // words a thread)
+  const uint32_t budget = threads > 256 ? (uint32_t)threads * 80u : plain_slab_budget(c);
+  const uint32_t sw = std::min<uint32_t>((uint32_t)c->prec, (budget / 2u / (uint32_t)threads) & ~7u);
   return (sw == (uint32_t)c->prec || sw >= 32u) ? sw : 0u;
 }
 uint32_t plain_lds(const qram_ctx *c, int threads, bool glob) {
@@ -1099,6 +1112,7 @@ qram_status qram_create_ex(const qram_params *p, qram_ctx **out) {
     (void)hipGetLastError();
     c->lds_max = std::min<size_t>(prop.sharedMemPerBlock, 64 * 1024) - 1024;
   }
+  if (plain_prepare((int)prop.sharedMemPerBlock) != hipSuccess) (void)hipGetLastError();  // (large workgroups then fit less)
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return bail(fail(c, QRAM_E_DEVICE, "stream creation failed"));
   for (auto &e : c->ev)
     if (hipEventCreate(&e) != hipSuccess) return bail(fail(c, QRAM_E_DEVICE, "event creation failed"));
@@ -1604,8 +1618,9 @@ qram_status qram_set_launch(qram_ctx *c, qram_mode mode, int slots_per_thread,
     if (slots_per_thread < 0 || slots_per_thread > 32)
       return fail(c, QRAM_E_INVAL, "plain engine: 0..32 workgroups per compute unit");
     const int t = schedule & ~1;
-    if (t != 0 && t != 64 && t != 128 && t != 256)
-      return fail(c, QRAM_E_INVAL, "plain engine: 0, 64, 128 or 256 threads per workgroup (+1: records in device memory)");
+    if (t != 0 && t != 64 && t != 128 && t != 256 && t != 512 && t != 1024)
+      return fail(c, QRAM_E_INVAL,
+                  "plain engine: 0, 64, 128, 256, 512 or 1024 threads per workgroup (+1: records in device memory)");
     c->plain_per_cu[mode] = slots_per_thread;
     c->plain_thr[mode] = t;
     c->plain_glob[mode] = (schedule & 1) != 0;
@@ -1680,7 +1695,8 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
     std::vector<Shape> shapes;
     for (bool g : {false, true}) {
       if (g && c->tier2_global) continue;  // (every shape keeps its records in device memory already)
-      for (int t : {64, 128, 256}) {
+      for (int t : {64, 128, 256, 512, 1024}) {
+        if (t > 256 && !(c->dsplit && mode == QRAM_MODE_PRUNED)) continue;  // (large workgroups: split runs only)
         if (!g && !plain_slab(c, t, false)) continue;  // (no slab fits: the same as in device memory)
         const int occ = plain_occupancy(c->enc, t, plain_lds(c, t, g));
         if (occ < 1) continue;
@@ -1689,7 +1705,7 @@ qram_status qram_autotune(qram_ctx *c, qram_mode mode, uint64_t seed,
             shapes.push_back({t, w, g});
       }
     }
-    const uint32_t ntp = std::min<uint32_t>(nt, 16384u);  // (18 shapes, two runs each)
+    const uint32_t ntp = std::min<uint32_t>(nt, 16384u);  // (18 shapes, 24 for a split run; two runs each)
     for (const auto &sh : shapes) {
       c->plain_thr[m] = sh.t;
       c->plain_per_cu[m] = sh.w;

@@ -198,6 +198,9 @@ int plain_occupancy(int enc, int threads, uint32_t lds_bytes);
 // the register budget for a launch asking for per_cu workgroups per compute
 // unit (occ: how many it holds)
 int plain_variant(int enc, int threads, uint32_t lds_bytes, int per_cu, int &occ);
+// lets the plain kernel's large workgroups take up to lds_max bytes of
+// shared memory
+hipError_t plain_prepare(int lds_max);
 hipError_t launch_plain(const Tables *tb, const Run &rp, int enc, int variant, uint32_t grid, int threads,
                         uint32_t lds_bytes,
                         hipStream_t s);

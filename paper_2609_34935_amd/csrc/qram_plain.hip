@@ -348,11 +348,12 @@ struct PlainSm {
   uint32_t *J;       // [JMAX] joint outcome: site | level << 16
   double *red;       // [16 * 16] reduction buffer
   int *misc;         // [16]
+  int *wv;           // [4 * 16] the pick's per-wave data (up to 16 waves)
   uint16_t *slab;    // [threads * prec] one record per thread (16-byte aligned)
 };
 
 __host__ __device__ inline uint32_t plain_sm_head(int M) {
-  return (uint32_t)((((M + 31) / 32) * 4 + (MAXT + 1) * 4 + JMAX * 4 + 16 * 16 * 8 + 16 * 4 + 64 + 15) & ~15);
+  return (uint32_t)((((M + 31) / 32) * 4 + (MAXT + 1) * 4 + JMAX * 4 + 16 * 16 * 8 + 16 * 4 + 4 * 16 * 4 + 64 + 15) & ~15);
 }
 
 __device__ inline PlainSm plain_carve(unsigned char *base, int M) {
@@ -367,6 +368,8 @@ __device__ inline PlainSm plain_carve(unsigned char *base, int M) {
   s.J = reinterpret_cast<uint32_t *>(base + o);
   o += JMAX * 4;
   s.misc = reinterpret_cast<int *>(base + o);
+  o += 16 * 4;
+  s.wv = reinterpret_cast<int *>(base + o);
   s.slab = reinterpret_cast<uint16_t *>(base + plain_sm_head(M));
   return s;
 }
@@ -461,9 +464,10 @@ __device__ __forceinline__ double2 in_ab(const Tables *__restrict__ tb, uint32_t
 }
 
 // WPE: the register budget, as waves per SIMD the kernel must allow (1:
-// unconstrained; see plain_variant below)
-template <int ENC, int WPE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
+// unconstrained; see plain_variant below); NT: the most threads per
+// workgroup (256, or 1024 for the longest trajectories of a split run)
+template <int ENC, int WPE, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_plain(const Tables *__restrict__ tb, const Run R_) {
   const Run *rp = &R_;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -778,19 +782,19 @@ k_plain(const Tables *__restrict__ tb, const Run R_) {
             int lastm = my >= 0 ? (int)x : -1;
             for (int off = 32; off > 0; off >>= 1) lastm = max(lastm, __shfl_xor(lastm, off, 64));
             if ((tid & 63) == 0) {
-              sm.misc[1 + (tid >> 6)] = lowest;
-              reinterpret_cast<int *>(sm.J)[JMAX - 1 - (tid >> 6)] = lastm;
+              sm.wv[tid >> 6] = lowest;
+              sm.wv[32 + (tid >> 6)] = lastm;
             }
-            if (mine && (int)x == lowest) sm.misc[5 + (tid >> 6)] = my;  // explicit index of the wave's pick
-            if (my >= 0 && (int)x == lastm) reinterpret_cast<int *>(sm.J)[JMAX - 5 - (tid >> 6)] = my;
+            if (mine && (int)x == lowest) sm.wv[16 + (tid >> 6)] = my;  // explicit index of the wave's pick
+            if (my >= 0 && (int)x == lastm) sm.wv[48 + (tid >> 6)] = my;
             __syncthreads();
             int best = 0x7FFFFFFF, bw = -1, lw = -1, lst = -1;
             for (int w8 = 0; w8 < nthr / 64; ++w8) {
-              if (sm.misc[1 + w8] < best) {
-                best = sm.misc[1 + w8];
+              if (sm.wv[w8] < best) {
+                best = sm.wv[w8];
                 bw = w8;
               }
-              const int l8 = reinterpret_cast<int *>(sm.J)[JMAX - 1 - w8];
+              const int l8 = sm.wv[32 + w8];
               if (l8 > lst) {
                 lst = l8;
                 lw = w8;
@@ -798,12 +802,12 @@ k_plain(const Tables *__restrict__ tb, const Run R_) {
             }
             if (lst >= 0 && lst > last) {
               last = lst;
-              last_y = reinterpret_cast<int *>(sm.J)[JMAX - 5 - lw];
+              last_y = sm.wv[48 + lw];
             }
             base += sm.red[64];
             if (best != 0x7FFFFFFF) {
               pick = best;
-              pick_y = sm.misc[5 + bw];
+              pick_y = sm.wv[16 + bw];
             }
             __syncthreads();
           }
@@ -1057,7 +1061,7 @@ k_plain(const Tables *__restrict__ tb, const Run R_) {
     fin[9] = gw;
     double fin2[1] = {ga};
     block_sum<11>(fin, sm.red);
-    block_sum<1>(fin2, sm.red + 160);
+    block_sum<1>(fin2, sm.red + 11 * 16);  // (after the 16 waves' entries of the first)
     if (tid == 0) {
       double ovx = fin[0], ovy = fin[1], wg = fin[2], wx = fin[3];
       if (goods && cref2 > 0.0) {
@@ -1104,23 +1108,49 @@ uint32_t plain_lds_bytes(int M, uint32_t slab_words) { return plain_sm_head(M) +
 // memory, limit the workgroups a compute unit holds (short records in
 // small slabs).  A launch takes the first budget that fits the workgroups
 // per compute unit it asks for, else the one that fits the most.
+// Workgroups of more than 256 threads (up to 1024) take a build of their
+// own, at most 128 registers.
 namespace {
-template <int ENC, int WPE>
+template <int ENC, int WPE, int NT>
 int plain_occ_one(int threads, uint32_t lds_bytes) {
   int blocks = 0;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<ENC, WPE>, threads, lds_bytes) == hipSuccess
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<ENC, WPE, NT>, threads, lds_bytes) ==
+                 hipSuccess
              ? blocks
              : 0;
 }
+constexpr int PLAIN_BIG = 3;  // the variant of the large workgroups
 int plain_occ_variant(int enc, int threads, uint32_t lds_bytes, int v) {
+  if (v == PLAIN_BIG)
+    return enc == QUBIT ? plain_occ_one<QUBIT, 4, 1024>(threads, lds_bytes)
+                        : plain_occ_one<QUTRIT, 4, 1024>(threads, lds_bytes);
   if (enc == QUBIT)
-    return v == 0 ? plain_occ_one<QUBIT, 1>(threads, lds_bytes)
-                  : (v == 1 ? plain_occ_one<QUBIT, 4>(threads, lds_bytes) : plain_occ_one<QUBIT, 5>(threads, lds_bytes));
-  return v == 0 ? plain_occ_one<QUTRIT, 1>(threads, lds_bytes) : plain_occ_one<QUTRIT, 4>(threads, lds_bytes);
+    return v == 0 ? plain_occ_one<QUBIT, 1, 256>(threads, lds_bytes)
+                  : (v == 1 ? plain_occ_one<QUBIT, 4, 256>(threads, lds_bytes)
+                            : plain_occ_one<QUBIT, 5, 256>(threads, lds_bytes));
+  return v == 0 ? plain_occ_one<QUTRIT, 1, 256>(threads, lds_bytes) : plain_occ_one<QUTRIT, 4, 256>(threads, lds_bytes);
 }
 }  // namespace
 
+hipError_t plain_prepare(int lds_max) {
+  hipError_t e = hipSuccess;
+  const void *fns[2] = {reinterpret_cast<const void *>(&k_plain<QUBIT, 4, 1024>),
+                        reinterpret_cast<const void *>(&k_plain<QUTRIT, 4, 1024>)};
+  for (const void *f : fns) {  // the large workgroups' slabs may pass 64 KiB
+    hipFuncAttributes fa;
+    int dyn = lds_max;
+    if (hipFuncGetAttributes(&fa, f) == hipSuccess) dyn = lds_max - (int)fa.sharedSizeBytes;
+    const hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    if (r != hipSuccess) e = r;
+  }
+  return e;
+}
+
 int plain_variant(int enc, int threads, uint32_t lds_bytes, int per_cu, int &occ) {
+  if (threads > 256) {
+    occ = plain_occ_variant(enc, threads, lds_bytes, PLAIN_BIG);
+    return PLAIN_BIG;
+  }
   int var = 0;
   occ = 0;
   for (int v = 0; v < (enc == QUBIT ? 3 : 2); ++v) {
@@ -1149,17 +1179,21 @@ hipError_t launch_plain(const Tables *tb, const Run &rp, int enc, int variant, u
   if (e != hipSuccess) return e;
   const dim3 g(grid), b(threads);
   if (enc == QUBIT) {
-    if (variant == 2)
-      hipLaunchKernelGGL((k_plain<QUBIT, 5>), g, b, lds_bytes, s, tb, rp);
+    if (variant == PLAIN_BIG)
+      hipLaunchKernelGGL((k_plain<QUBIT, 4, 1024>), g, b, lds_bytes, s, tb, rp);
+    else if (variant == 2)
+      hipLaunchKernelGGL((k_plain<QUBIT, 5, 256>), g, b, lds_bytes, s, tb, rp);
     else if (variant == 1)
-      hipLaunchKernelGGL((k_plain<QUBIT, 4>), g, b, lds_bytes, s, tb, rp);
+      hipLaunchKernelGGL((k_plain<QUBIT, 4, 256>), g, b, lds_bytes, s, tb, rp);
     else
-      hipLaunchKernelGGL((k_plain<QUBIT, 1>), g, b, lds_bytes, s, tb, rp);
+      hipLaunchKernelGGL((k_plain<QUBIT, 1, 256>), g, b, lds_bytes, s, tb, rp);
   } else {
-    if (variant == 1)
-      hipLaunchKernelGGL((k_plain<QUTRIT, 4>), g, b, lds_bytes, s, tb, rp);
+    if (variant == PLAIN_BIG)
+      hipLaunchKernelGGL((k_plain<QUTRIT, 4, 1024>), g, b, lds_bytes, s, tb, rp);
+    else if (variant == 1)
+      hipLaunchKernelGGL((k_plain<QUTRIT, 4, 256>), g, b, lds_bytes, s, tb, rp);
     else
-      hipLaunchKernelGGL((k_plain<QUTRIT, 1>), g, b, lds_bytes, s, tb, rp);
+      hipLaunchKernelGGL((k_plain<QUTRIT, 1, 256>), g, b, lds_bytes, s, tb, rp);
   }
   return hipGetLastError();
 }

@@ -272,6 +272,26 @@ def test_split_pruned_run(lib, orc, enc):
     assert seen[0] > 0 and seen[1] > 0  # jumps on both halves
 
 
+@pytest.mark.parametrize("enc,n,k,p", [(QUBIT, 7, 3, 0.0002), (QUTRIT, 10, 1, 0.00005)])
+def test_split_run_large_workgroups(lib, orc, enc, n, k, p):
+    """A split run's plain share in workgroups of 256, 512 and 1024 threads
+    (records in slabs and in device memory), and the automatic shape, which
+    takes 1024 threads here: every shape gives the oracle's results."""
+    nt, no = 600, 96
+    mem = memory_words(n, k, 93)
+    fo, fpo, so, _ = orc.run_many(n, k, enc, p, mem, 29, 0, no, eps=p)
+    with lib.QramContext(n, k, enc, p, mem, eps=p) as ctx:
+        assert ctx.get_launch(PRUNED)[1] == 1024  # (few faulted trajectories, 1024 components or more)
+        first = None
+        for per_cu, sched in ((0, 0), (32, 256), (32, 512), (32, 1024), (32, 513), (32, 1025)):
+            ctx.set_launch(PRUNED, per_cu, sched)
+            f, st = ctx.run_pruned(29, 0, nt)
+            check_stats(f[:no], st[:no], fo, fpo, so, ("large", enc, sched))
+            if first is None:
+                first = f
+            assert np.all(fid_close(f, first)), sched
+
+
 @pytest.mark.parametrize("enc", [QUBIT, QUTRIT])
 def test_split_runs_as_graphs(lib, enc):
     """Graph mode on a depolarizing context: the captured batch holds the
