@@ -272,7 +272,7 @@ qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,
  * 256, 512 or 1024; 0 = automatic: 256, or 64 (pruned) / 128 (full) when a
  * trajectory holds at most 256 components and the run is not split, or 1024
  * for the plain share of a split run where at most 60% of the trajectories
- * draw a fault and a trajectory holds at least 1024 components), plus 1 to work on
+ * draw a fault and a trajectory holds at least 2048 components), plus 1 to work on
  * each component record in device memory instead of staging it in shared
  * memory while a thread applies a slice's gates to it.  The launch stays
  * within 16 GiB of per-trajectory state, and the plain share of a split

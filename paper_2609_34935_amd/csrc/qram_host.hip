@@ -440,15 +440,16 @@ uint32_t pow2ceil(uint32_t x) {
 // that of its longest ones (a fault near the root leaves nearly the whole
 // tree bad), which one workgroup evolves alone: 256 threads, or 1024 when
 // at most 60% of the trajectories draw a fault and a trajectory holds at
-// least 1024 components (with more faulted trajectories the share fills
-// the device and smaller workgroups keep more of them in flight).
+// least 2048 components, two a thread (with more faulted trajectories the
+// share fills the device and smaller workgroups keep more of them in
+// flight; with fewer components most of the threads idle).
 void plain_shape(const qram_ctx *c, int mode, int &threads, int &per_cu, bool &glob) {
   const int m = mode;
   threads = c->plain_thr[m];
   const bool share = c->dsplit && mode == QRAM_MODE_PRUNED;
   if (!threads) {
     const double pf = share ? 1.0 - std::pow(1.0 - c->eps, (double)c->htab.dep_off[c->T]) : 1.0;
-    if (share && c->Emax >= 1024 && pf <= 0.6)
+    if (share && c->Emax >= 2048 && pf <= 0.6)
       threads = 1024;
     else
       threads = (c->Emax > 256 || share) ? PLAIN_THREADS : (mode == QRAM_MODE_PRUNED ? 64 : 128);

@@ -272,7 +272,7 @@ def test_split_pruned_run(lib, orc, enc):
     assert seen[0] > 0 and seen[1] > 0  # jumps on both halves
 
 
-@pytest.mark.parametrize("enc,n,k,p", [(QUBIT, 7, 3, 0.0002), (QUTRIT, 10, 1, 0.00005)])
+@pytest.mark.parametrize("enc,n,k,p", [(QUBIT, 8, 3, 0.0001), (QUTRIT, 11, 1, 0.00002)])
 def test_split_run_large_workgroups(lib, orc, enc, n, k, p):
     """A split run's plain share in workgroups of 256, 512 and 1024 threads
     (records in slabs and in device memory), and the automatic shape, which
@@ -281,7 +281,7 @@ def test_split_run_large_workgroups(lib, orc, enc, n, k, p):
     mem = memory_words(n, k, 93)
     fo, fpo, so, _ = orc.run_many(n, k, enc, p, mem, 29, 0, no, eps=p)
     with lib.QramContext(n, k, enc, p, mem, eps=p) as ctx:
-        assert ctx.get_launch(PRUNED)[1] == 1024  # (few faulted trajectories, 1024 components or more)
+        assert ctx.get_launch(PRUNED)[1] == 1024  # (few faulted trajectories, 2048 components or more)
         first = None
         for per_cu, sched in ((0, 0), (32, 256), (32, 512), (32, 1024), (32, 513), (32, 1025)):
             ctx.set_launch(PRUNED, per_cu, sched)
