@@ -271,8 +271,9 @@ qram_status qram_fidelity(const double *fid, uint32_t ntraj, double *mean,
  * for) and schedule the threads per workgroup (64, 128,
  * 256, 512 or 1024; 0 = automatic: 256, or 64 (pruned) / 128 (full) when a
  * trajectory holds at most 256 components and the run is not split, or 1024
- * for the plain share of a split run where at most 60% of the trajectories
- * draw a fault and a trajectory holds at least 2048 components), plus 1 to work on
+ * for the plain share of a split run whose batch expects at most ten
+ * faulted trajectories per compute unit, a trajectory holding at least 2048
+ * components; qram_get_launch reports the last run's choice), plus 1 to work on
  * each component record in device memory instead of staging it in shared
  * memory while a thread applies a slice's gates to it.  The launch stays
  * within 16 GiB of per-trajectory state, and the plain share of a split

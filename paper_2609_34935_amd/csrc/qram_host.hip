@@ -104,6 +104,7 @@ struct qram_ctx {
   int prec = 0;
   int plain_per_cu[3] = {0, 0, 0};
   int plain_thr[3] = {0, 0, 0};
+  int plain_used_thr[3] = {0, 0, 0};  // threads of the last plain launch planned per mode
   bool plain_glob[3] = {false, false, false};  // records worked on in device memory
   double *pamp = nullptr, *pgrp = nullptr;
   uint8_t *phit = nullptr;
@@ -439,17 +440,22 @@ uint32_t pow2ceil(uint32_t x) {
 // A split pruned run's plain share is few trajectories, and its time is
 // that of its longest ones (a fault near the root leaves nearly the whole
 // tree bad), which one workgroup evolves alone: 256 threads, or 1024 when
-// at most 60% of the trajectories draw a fault and a trajectory holds at
-// least 2048 components, two a thread (with more faulted trajectories the
-// share fills the device and smaller workgroups keep more of them in
-// flight; with fewer components most of the threads idle).
-void plain_shape(const qram_ctx *c, int mode, int &threads, int &per_cu, bool &glob) {
+// the batch's expected faulted trajectories are about as many as the
+// device holds workgroups of 256 threads, at most ten per compute unit
+// (ntraj trajectories, each drawing a fault with the context's
+// probability; for a batch of unknown size, ntraj = 0, at most 60% of the
+// trajectories drawing a fault stands in), and a trajectory holds at least
+// 2048 components, two a thread.  With more faulted trajectories the share
+// fills the device and smaller workgroups keep more of them in flight;
+// with fewer components most of the threads idle.
+void plain_shape(const qram_ctx *c, int mode, int &threads, int &per_cu, bool &glob, uint32_t ntraj) {
   const int m = mode;
   threads = c->plain_thr[m];
   const bool share = c->dsplit && mode == QRAM_MODE_PRUNED;
   if (!threads) {
     const double pf = share ? 1.0 - std::pow(1.0 - c->eps, (double)c->htab.dep_off[c->T]) : 1.0;
-    if (share && c->Emax >= 2048 && pf <= 0.6)
+    const bool few = ntraj ? pf * (double)ntraj <= 10.0 * (double)c->num_cu : pf <= 0.6;
+    if (share && c->Emax >= 2048 && few)
       threads = 1024;
     else
       threads = (c->Emax > 256 || share) ? PLAIN_THREADS : (mode == QRAM_MODE_PRUNED ? 64 : 128);
@@ -500,7 +506,8 @@ uint32_t plain_lds(const qram_ctx *c, int threads, bool glob) {
 qram_status plain_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
   int threads = 0, per_cu = 0;
   bool glob = false;
-  plain_shape(c, mode, threads, per_cu, glob);
+  plain_shape(c, mode, threads, per_cu, glob, ntraj);
+  c->plain_used_thr[mode] = threads;
   pl.plds = plain_lds(c, threads, glob);
   pl.pslab = plain_slab(c, threads, glob);
   int occ = 0;
@@ -1625,6 +1632,7 @@ qram_status qram_set_launch(qram_ctx *c, qram_mode mode, int slots_per_thread,
     c->plain_per_cu[mode] = slots_per_thread;
     c->plain_thr[mode] = t;
     c->plain_glob[mode] = (schedule & 1) != 0;
+    c->plain_used_thr[mode] = 0;
     return QRAM_OK;
   }
   if (slots_per_thread != 0 && slots_per_thread != 4 && slots_per_thread != 8 && slots_per_thread != 16 &&
@@ -1643,7 +1651,8 @@ qram_status qram_get_launch(const qram_ctx *c, qram_mode mode,
   if (mode == QRAM_MODE_PLAIN || c->general) {  // the shape in use: explicit or automatic
     int threads = 0, per_cu = 0;
     bool glob = false;
-    plain_shape(c, mode, threads, per_cu, glob);
+    plain_shape(c, mode, threads, per_cu, glob, 0);
+    if (!c->plain_thr[mode] && c->plain_used_thr[mode]) threads = c->plain_used_thr[mode];  // (the last run's)
     const int occ = plain_occupancy(c->enc, threads, plain_lds(c, threads, glob));
     *slots_per_thread = occ > 0 ? std::min(per_cu, occ) : per_cu;
     *schedule = threads + (plain_slab(c, threads, glob) ? 0 : 1);  // (+1: records in device memory)
