@@ -302,14 +302,15 @@ def table5_leg(P, scale=1.0, points=None):
                 for name, fn in (("pruned", ctx.run_pruned_async), ("full", ctx.run_plain_async)):
                     # plain-engine launch shape: the autotuner's pick where a
                     # trajectory holds at most 4096 components, else the
-                    # automatic one (256 threads, all workgroups that fit)
+                    # library's automatic one (recorded after the runs: a
+                    # split run's choice depends on the batch)
                     mode = P.QRAM_MODE_PRUNED if name == "pruned" else P.QRAM_MODE_PLAIN
                     if (p > 0 or name == "full") and 2 ** (n + k) <= 4096:
                         ctx.autotune(mode, seed + 1, 0, min(nt, 8192))
-                    if p > 0 or name == "full":
-                        row.setdefault("launch", {})[name] = list(ctx.get_launch(mode))
                     reps = 3 if name == "pruned" else 1
                     dt = time_mode(ctx, fn, seed, nt, reps, d_fid, d_st, stream)
+                    if p > 0 or name == "full":
+                        row.setdefault("launch", {})[name] = list(ctx.get_launch(mode))
                     row[f"{name}_traj_per_s"] = round(nt / dt, 1)
                     fids[name] = d_fid.cpu().numpy()
                     if name == "pruned":
