@@ -104,7 +104,7 @@ struct qram_ctx {
   int prec = 0;
   int plain_per_cu[3] = {0, 0, 0};
   int plain_thr[3] = {0, 0, 0};
-  int plain_used_thr[3] = {0, 0, 0};  // threads of the last plain launch planned per mode
+  int plain_used_thr[3] = {0, 0, 0};  // threads of the last plain launch per mode
   bool plain_glob[3] = {false, false, false};  // records worked on in device memory
   double *pamp = nullptr, *pgrp = nullptr;
   uint8_t *phit = nullptr;
@@ -507,7 +507,6 @@ qram_status plain_plan(qram_ctx *c, int mode, uint32_t ntraj, Plan &pl) {
   int threads = 0, per_cu = 0;
   bool glob = false;
   plain_shape(c, mode, threads, per_cu, glob, ntraj);
-  c->plain_used_thr[mode] = threads;
   pl.plds = plain_lds(c, threads, glob);
   pl.pslab = plain_slab(c, threads, glob);
   int occ = 0;
@@ -789,11 +788,14 @@ qram_status enqueue_batch(qram_ctx *c, const Plan &pl, Run r, hipStream_t s,
   if (timed) HIPCHK(c, hipEventRecord(e[2], s));
   if (pl.plain) {
     HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.pvar, pl.pb.grid, pl.pb.threads, pl.plds, s));
+    c->plain_used_thr[r.mode] = pl.pb.threads;
   } else {
     qram_status st = launch_buckets(c, pl, r, s, be);
     if (st) return st;
-    if (pl.split)  // the trajectories that drew a depolarizing fault
+    if (pl.split) {  // the trajectories that drew a depolarizing fault
       HIPCHK(c, launch_plain(c->dtab, r, c->enc, pl.pvar, pl.pb.grid, pl.pb.threads, pl.plds, s));
+      c->plain_used_thr[QRAM_MODE_PRUNED] = pl.pb.threads;
+    }
   }
   if (timed) HIPCHK(c, hipEventRecord(e[3], s));
   return QRAM_OK;
